@@ -1,0 +1,175 @@
+/*
+ * det.h -- exact integer determinant on one MI355X (gfx950).
+ *
+ * The data-parallel hot path of Dumas and Urbanska's introspective integer
+ * determinant ("An introspective algorithm for the integer determinant"):
+ * LU modulo word-size primes over a batch of primes (the Chinese-remaindering
+ * side, Section 2.1 and Alg. 2.1) and Dixon p-adic lifting with A^{-1} mod p
+ * (the LargestInvariantFactor side, Section 2.2), combined on the host as in
+ * Section 4 (Alg. 4.1 with one solving: det = s~_n * (det / s~_n)).
+ *
+ * Conventions for every entry point:
+ *  - Return value: det_status, DET_OK (0) on success.  No C++ exception and
+ *    no longjmp crosses this boundary.  On failure the outputs are left in an
+ *    unspecified state and det_last_error(ctx) describes the cause.
+ *  - Matrices: row-major n x n int64 with leading dimension lda >= n (in
+ *    elements).  The pointer may be host or device memory; the library asks
+ *    the HIP runtime which one it is.  Entries must satisfy |a_ij| < 2^31.
+ *  - Ownership: the caller owns every input and output buffer.  The library
+ *    keeps no caller pointer after a call returns and allocates device memory
+ *    only inside the context (freed by det_ctx_destroy).
+ *  - Calls are synchronous with respect to the host: they return after the
+ *    work queued on the context's stream has finished.  A context must not be
+ *    used from two threads at the same time.
+ *  - n = 0 is accepted: the determinant of the empty matrix is 1.
+ */
+#ifndef PAPER_CS_0511066_AMD_DET_H
+#define PAPER_CS_0511066_AMD_DET_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DET_OK = 0,
+  DET_E_INVALID = 1,          /* bad argument: null pointer, n < 0, lda < n, k < 0 ... */
+  DET_E_NOT_PRIME = 2,        /* a modulus is not an odd prime */
+  DET_E_PRIME_RANGE = 3,      /* modulus outside the range the chosen path supports */
+  DET_E_SINGULAR_MOD_P = 4,   /* dixon_lift: p divides det(A) */
+  DET_E_OVERFLOW = 5,         /* an entry has |a_ij| >= 2^31, or a bound would overflow */
+  DET_E_NOMEM = 6,            /* device or host allocation failed */
+  DET_E_BUFFER_TOO_SMALL = 7, /* det_introspective: limb_cap too small (see limb_count) */
+  DET_E_DEVICE = 8            /* a HIP runtime call failed */
+} det_status;
+
+typedef enum {
+  DET_PATH_AUTO = 0,          /* library choice (int8 limbs when every prime allows it) */
+  DET_PATH_FP64 = 1,          /* trailing updates on FP64 MFMA, primes < 2^26 */
+  DET_PATH_INT8 = 2           /* trailing updates on int8 MFMA with 3 signed limbs, primes < 2^23 */
+} det_path;
+
+typedef struct det_ctx det_ctx;
+
+/* Create a context on HIP device `device`.  hbm_budget_bytes caps the device
+ * workspace the context may hold (0 = no cap).  The context owns a HIP
+ * stream of default priority.  Returns DET_E_DEVICE if the device cannot be
+ * used. */
+det_status det_ctx_create(int device, size_t hbm_budget_bytes, det_ctx **out);
+
+/* Free everything the context allocated.  NULL is ignored. */
+void det_ctx_destroy(det_ctx *ctx);
+
+/* Run subsequent work on `hip_stream` (a hipStream_t, borrowed: the library
+ * never destroys it).  NULL restores the context's own stream. */
+det_status det_ctx_set_stream(det_ctx *ctx, void *hip_stream);
+
+/* Human-readable name of a status code (static storage). */
+const char *det_status_str(det_status s);
+
+/* Message describing the last failure on this context (owned by ctx). */
+const char *det_last_error(const det_ctx *ctx);
+
+/*
+ * CRA side (Section 2.1: each modular determinant comes from an LU
+ * factorisation modulo p_i; Alg. 2.1 computes det(A) mod p_i for each drawn
+ * prime).
+ *
+ * residues[j] = det(A) mod primes[j], canonical in [0, primes[j]).  A
+ * residue 0 is a valid result (p_j divides det(A), or A is singular), not an
+ * error.  primes: host array of nprimes odd primes, each < 2^26 for
+ * DET_PATH_FP64 and < 2^23 for DET_PATH_INT8 (else DET_E_PRIME_RANGE);
+ * residues: host array of nprimes entries.  Every prime is checked with a
+ * deterministic primality test (DET_E_NOT_PRIME).
+ */
+det_status det_mod_primes(det_ctx *ctx, const int64_t *A, int64_t n, int64_t lda,
+                          const uint32_t *primes, int64_t nprimes, uint32_t *residues,
+                          det_path path);
+
+/*
+ * LIF side (Section 2.2: LargestInvariantFactor solves A x = b by Dixon
+ * p-adic lifting).  With r_0 = b:
+ *     x_i = A^{-1} r_i mod p  in [0, p)^n,     r_{i+1} = (r_i - A x_i) / p,
+ * so that sum_{i<k} x_i p^i = A^{-1} b (mod p^k).
+ * digits[i*n + j] = x_i[j] for 0 <= i < k, 0 <= j < n (host array, k*n
+ * entries).  b: host array of n int64 with |b_j| < 2^62 / (n + 1).
+ * p: odd prime with 2^8 < p < 2^26.  Returns DET_E_SINGULAR_MOD_P when p
+ * divides det(A).  A device pointer for A is used in place.
+ */
+det_status dixon_lift(det_ctx *ctx, const int64_t *A, int64_t n, int64_t lda, const int64_t *b,
+                      uint32_t p, int64_t k, uint32_t *digits);
+
+typedef struct {
+  double log2_inv_eps;   /* early termination: failure probability < 2^-log2_inv_eps (default 64) */
+  int certify;           /* 1: ignore early termination; reconstruct det/s_n up to the Hadamard bound */
+  uint64_t seed;         /* seed for the prime draws and the right-hand side */
+  int n_rhs;             /* number of Dixon solvings (i_max of Alg. 4.1 with one factor), default 1 */
+  int prime_bits;        /* CRA primes are drawn from (2^(b-1), 2^b); default 23 (max 23 for int8, 26 for fp64) */
+  det_path path;         /* trailing-update path of the CRA loop */
+} det_opts;
+
+typedef struct {
+  int64_t primes_used;     /* CRA primes whose residues entered the reconstruction */
+  int64_t lifting_steps;   /* Dixon steps over all solvings */
+  int64_t sn_bits;         /* bit length of the factor s~_n found by the solvings */
+  int64_t et_rounds;       /* batches of CRA primes launched */
+  int64_t hadamard_bits;   /* log2 of the Hadamard bound used */
+  int early_terminated;    /* 1 if the CRA stopped by early termination */
+  double t_lif_ms;         /* device + host time of the solvings */
+  double t_cra_ms;         /* time of the modular determinants */
+  double t_host_ms;        /* time of reconstruction on the host */
+} det_report;
+
+/* Fill *opts with the defaults above. */
+void det_opts_default(det_opts *opts);
+
+/*
+ * Exact det(A) by the introspective scheme of Section 4 with one solving
+ * (Alg. 4.1 with i_max = 1): s~_n from Dixon lifting and rational
+ * reconstruction, then the early-terminated CRA loop (Alg. 2.1) on
+ * det(A)/s~_n, and det = s~_n * (det/s~_n).
+ * Output: *sign in {-1, 0, +1}; |det| as little-endian base-2^32 limbs in
+ * mag[0 .. *limb_count).  If limb_cap is too small the call returns
+ * DET_E_BUFFER_TOO_SMALL with *limb_count = limbs needed (call again).
+ * opts and report may be NULL.  With certify = 0 the result is correct with
+ * probability >= 1 - 2^-log2_inv_eps (Lemma 2.1(iv)); with certify = 1 it is
+ * always correct.
+ */
+det_status det_introspective(det_ctx *ctx, const int64_t *A, int64_t n, int64_t lda,
+                             const det_opts *opts, int *sign, uint32_t *mag, int64_t limb_cap,
+                             int64_t *limb_count, det_report *report);
+
+/*
+ * Kernel timing (measurement support, not part of the method).  After
+ * det_profile_select(ctx, kind), every launch of that kernel class made by
+ * the context is bracketed by HIP events recorded on the context's stream;
+ * det_profile_read synchronizes the stream and returns the number of timed
+ * launches, their summed duration in ms, and the algorithmic bytes and
+ * arithmetic operations of those launches as the launcher counted them from
+ * its shapes (operations: 2 per modular multiply-add for the FP64 and
+ * lifting kernels, 2 per int8 multiply-add for the int8 limb products).
+ * The counters are then reset.  DET_KERNEL_NONE stops timing.
+ */
+typedef enum {
+  DET_KERNEL_NONE = 0,
+  DET_KERNEL_LIFT_X = 1,     /* x_i = A^{-1} r_i mod p                  */
+  DET_KERNEL_LIFT_R = 2,     /* r_{i+1} = (r_i - A x_i) / p             */
+  DET_KERNEL_GEMM_F64 = 3,   /* trailing update on FP64 MFMA            */
+  DET_KERNEL_GEMM_I8 = 4,    /* trailing update on int8 MFMA (3 limbs)  */
+  DET_KERNEL_PANEL = 5,      /* panel factorisation                     */
+  DET_KERNEL_TRSM = 6,       /* in-place triangular apply               */
+  DET_KERNEL_TRI_INV = 7,    /* diagonal-block triangular inverse       */
+  DET_KERNEL_RESIDUES = 8    /* A mod p for a batch of primes           */
+} det_kernel;
+
+det_status det_profile_select(det_ctx *ctx, det_kernel kind);
+det_status det_profile_read(det_ctx *ctx, int64_t *launches, double *total_ms, double *bytes,
+                            double *ops);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PAPER_CS_0511066_AMD_DET_H */

@@ -1,0 +1,64 @@
+/*
+ * det_host.h -- the host-side steps of the introspective determinant,
+ * exported so that they can be checked on a machine without a GPU.  None of
+ * these functions touches the device.
+ *
+ * Integers cross this boundary as (sign, little-endian base-2^32 limbs);
+ * sign is -1, 0 or +1 and a zero value has no limbs.  Output buffers belong
+ * to the caller; when `cap` limbs are not enough the call returns
+ * DET_E_BUFFER_TOO_SMALL and writes the needed count to *len.
+ */
+#ifndef PAPER_CS_0511066_AMD_DET_HOST_H
+#define PAPER_CS_0511066_AMD_DET_HOST_H
+
+#include <stdint.h>
+
+#include "det.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* 1 if q is prime (deterministic Miller-Rabin, complete for 32-bit q), else 0. */
+int det_host_is_prime(uint32_t q);
+
+/* count distinct random primes in (2^(bits-1), 2^bits), 12 <= bits <= 31,
+ * drawn uniformly without replacement from the seeded stream (Alg. 2.1 draws
+ * each p_i uniformly from the remaining prime set). */
+det_status det_host_sample_primes(uint64_t seed, int bits, int64_t count, uint32_t *out);
+
+/* log2 of Hadamard's bound for |det A| (Lemma 2.1), rounded up: the smaller
+ * of the row and column forms prod ||a||_2.  A: host, row-major n x n int64. */
+double det_host_hadamard_log2(const int64_t *A, int64_t n, int64_t lda);
+
+/* Run length of unchanged reconstructions required by Lemma 2.1(iv) for
+ * failure probability 2^-log2_inv_eps, primes drawn from (2^(bits-1), 2^bits)
+ * and a bound of logl_H base-l digits.  -1 if the prime set is too small. */
+int64_t det_host_et_run_length(double log2_inv_eps, int bits, double logl_H);
+
+/* Chinese remaindering in the symmetric range (Section 2.1): the r with
+ * r = residues[i] (mod primes[i]) and -floor(M/2) <= r < ceil(M/2), M the
+ * product of the (distinct odd) primes, added in order.  *same_run: number
+ * of trailing primes that left r unchanged (the early-termination counter). */
+det_status det_host_crt(const uint32_t *residues, const uint32_t *primes, int64_t count, int *sign,
+                        uint32_t *mag, int64_t cap, int64_t *len, int64_t *same_run);
+
+/* Rational reconstruction: a/d with a = u d (mod m), |a| <= 2^Nbits,
+ * 0 < d <= 2^Dbits, gcd(a, d) = 1 (u, m > 0 given as magnitudes).
+ * DET_E_INVALID when no such fraction exists. */
+det_status det_host_ratrecon(const uint32_t *u, int64_t ulen, const uint32_t *m, int64_t mlen,
+                             int64_t Nbits, int64_t Dbits, int *a_sign, uint32_t *a_mag,
+                             int64_t a_cap, int64_t *a_len, uint32_t *d_mag, int64_t d_cap,
+                             int64_t *d_len);
+
+/* Big-integer arithmetic of the reconstruction steps: op 0 a+b, 1 a-b,
+ * 2 a*b, 3 floor(a/b), 4 a mod b (b > 0, result in [0, b)), 5 gcd(|a|,|b|). */
+det_status det_host_bigint(int op, int a_sign, const uint32_t *a, int64_t alen, int b_sign,
+                           const uint32_t *b, int64_t blen, int *out_sign, uint32_t *out,
+                           int64_t cap, int64_t *out_len);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PAPER_CS_0511066_AMD_DET_HOST_H */

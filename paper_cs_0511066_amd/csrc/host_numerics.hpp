@@ -1,0 +1,204 @@
+// Host-side numerics of the method: prime sampling, the Hadamard bound,
+// early-terminated Chinese remaindering, rational reconstruction.
+#pragma once
+#include <math.h>
+#include <stdint.h>
+
+#include <unordered_set>
+#include <vector>
+
+#include "bigint.hpp"
+
+namespace dethost {
+
+// ---------------------------------------------------------------- primes
+inline uint64_t mulmod64(uint64_t a, uint64_t b, uint64_t m) { return (uint64_t)((u128)a * b % m); }
+inline uint64_t powmod64(uint64_t a, uint64_t e, uint64_t m) {
+  uint64_t r = 1 % m;
+  a %= m;
+  while (e) {
+    if (e & 1) r = mulmod64(r, a, m);
+    a = mulmod64(a, a, m);
+    e >>= 1;
+  }
+  return r;
+}
+// Deterministic Miller-Rabin for 32-bit n (bases 2, 7, 61 are a complete
+// witness set below 4,759,123,141).
+inline bool is_prime_u32(uint32_t n) {
+  if (n < 2) return false;
+  for (uint32_t q : {2u, 3u, 5u, 7u, 11u, 13u, 61u})
+    if (n % q == 0) return n == q;
+  uint32_t d = n - 1;
+  int s = 0;
+  while ((d & 1) == 0) { d >>= 1; s++; }
+  for (uint64_t a : {2ull, 7ull, 61ull}) {
+    uint64_t x = powmod64(a, d, n);
+    if (x == 1 || x == n - 1) continue;
+    bool comp = true;
+    for (int r = 1; r < s; r++) {
+      x = mulmod64(x, x, n);
+      if (x == n - 1) { comp = false; break; }
+    }
+    if (comp) return false;
+  }
+  return true;
+}
+
+inline uint64_t splitmix64(uint64_t& s) {
+  uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Uniform random primes in (2^(bits-1), 2^bits), without replacement
+// (Alg. 2.1 draws each p_i uniformly from the remaining set P).  Rejection
+// sampling: draw a uniform integer of the interval, keep it if prime and unused.
+struct PrimeSampler {
+  uint64_t state;
+  int bits;
+  std::unordered_set<uint32_t> used;
+  PrimeSampler(uint64_t seed, int b) : state(seed), bits(b) {}
+  uint32_t next() {
+    const uint64_t lo = 1ull << (bits - 1), span = 1ull << (bits - 1);
+    for (;;) {
+      uint32_t c = (uint32_t)(lo + splitmix64(state) % span) | 1u;
+      if (c <= lo || c >= 2 * lo) continue;
+      if (!is_prime_u32(c) || used.count(c)) continue;
+      used.insert(c);
+      return c;
+    }
+  }
+};
+
+// Number of primes in (l, 2l), l = 2^(bits-1), rounded down: l / ln(2l)
+// (an under-estimate of pi(2l) - pi(l) for these l, so the early
+// termination run length computed from it is on the safe side).
+inline double prime_set_size(int bits) {
+  const double l = ldexp(1.0, bits - 1);
+  return l / log(2.0 * l);
+}
+
+// ---------------------------------------------------------------- bounds
+// log2 of Hadamard's bound, min over the row and column forms
+// (|det A| <= prod_j ||a_j||_2), from per-column and per-row sums of
+// squares.  Each sum is rounded upward by a relative margin that covers the
+// double rounding of n additions, so the result is an upper bound.
+struct Bounds {
+  double log2_h = 0;        // log2 H (min of the two forms)
+  double log2_hcol = 0;     // log2 of the column form
+  double log2_min_col = 0;  // log2 min_j ||a_j||_2
+  double amax = 0;          // ||A|| = max |a_ij|
+};
+inline Bounds bounds_from_sums(const std::vector<double>& colsq, const std::vector<double>& rowsq,
+                               double amax) {
+  Bounds b;
+  const double up = 1.0 + 1e-12;
+  double lc = 0, lr = 0, mincol = INFINITY;
+  for (double v : colsq) {
+    if (v <= 0) { lc = -INFINITY; mincol = 0; break; }
+    lc += 0.5 * log2(v * up);
+    mincol = fmin(mincol, v);
+  }
+  for (double v : rowsq) {
+    if (v <= 0) { lr = -INFINITY; break; }
+    lr += 0.5 * log2(v * up);
+  }
+  const size_t n = colsq.size();
+  const double slack = 1e-9 * (double)n + 1e-6;   // covers the log2 rounding
+  b.log2_hcol = lc + slack;
+  b.log2_h = fmin(lc, lr) + slack;
+  b.log2_min_col = mincol > 0 ? 0.5 * log2(mincol) - slack : 0;
+  b.amax = amax;
+  if (!(b.log2_h > 0)) b.log2_h = 0;    // H < 1 only when det = 0 or n = 0
+  if (!(b.log2_hcol > 0)) b.log2_hcol = 0;
+  return b;
+}
+inline Bounds bounds_host(const int64_t* A, int64_t n, int64_t lda) {
+  std::vector<double> colsq(n, 0.0), rowsq(n, 0.0);
+  double amax = 0;
+  for (int64_t i = 0; i < n; i++)
+    for (int64_t j = 0; j < n; j++) {
+      const double a = (double)A[i * lda + j];
+      colsq[j] += a * a;
+      rowsq[i] += a * a;
+      amax = fmax(amax, fabs(a));
+    }
+  return bounds_from_sums(colsq, rowsq, amax);
+}
+
+// ---------------------------------------------------------------- CRT
+// Incremental Chinese remaindering in the symmetric range (Section 2.1:
+// r_t is reconstructed modulo p_0...p_t with -floor(M/2) <= r_t < ceil(M/2)).
+// Garner step with a centred correction digit t: if r is in the symmetric
+// range mod M (M odd), r + M t is in the symmetric range mod M p.
+struct CrtState {
+  BigInt r, M;
+  int64_t count = 0;
+  int64_t same = 0;     // consecutive primes that left r unchanged
+  // Adds residue d (in [0, p)) of an odd prime p; returns true if r_t = r_{t-1}.
+  bool add(uint32_t p, uint32_t d) {
+    if (count == 0) {
+      int64_t c = d > (p - 1) / 2 ? (int64_t)d - p : (int64_t)d;
+      r = BigInt::from_i64(c);
+      M = BigInt::from_u64(p);
+      count = 1;
+      same = 0;
+      return false;
+    }
+    const uint64_t rm = r.mod_small(p);
+    bool unchanged = rm == d;
+    if (!unchanged) {
+      const uint64_t mm = M.mod_small(p);
+      const uint64_t inv = powmod64(mm, p - 2, p);
+      uint64_t t = mulmod64((d + p - rm) % p, inv, p);
+      int64_t tc = t > (p - 1) / 2 ? (int64_t)t - p : (int64_t)t;
+      r = r + M * BigInt::from_i64(tc);
+    }
+    M.mul_add_small(p, 0);
+    count++;
+    same = unchanged ? same + 1 : 0;
+    return unchanged;
+  }
+};
+
+// Lemma 2.1(iv): the run of unchanged reconstructions that bounds the
+// failure probability by eps: k = ceil(log(1/eps) / (log P' - log log_l H)),
+// P' = |P| - ceil(log_l H).  Returns -1 if |P| is too small for the lemma.
+inline int64_t et_run_length(double log2_inv_eps, double P_size, double logl_H) {
+  const double Pp = P_size - ceil(logl_H);
+  const double den = log2(Pp) - log2(fmax(logl_H, 1.0));
+  if (!(Pp > 0) || !(den > 0)) return -1;
+  return (int64_t)fmax(1.0, ceil(log2_inv_eps / den));
+}
+
+// ---------------------------------------------------------------- rational reconstruction
+// Find a/d with a = u d (mod m), |a| <= N, 0 < d <= D, gcd(a, d) = 1, unique
+// when 2 N D < m: the extended Euclidean algorithm on (m, u mod m), stopped
+// at the first remainder <= N.  Returns false if no such fraction exists.
+inline bool rational_reconstruct(const BigInt& u_in, const BigInt& m, const BigInt& N,
+                                 const BigInt& D, BigInt& a_out, BigInt& d_out) {
+  BigInt q, u;
+  BigInt::divmod_floor(u_in, m, q, u);
+  BigInt r0 = m, r1 = u, t0, t1 = BigInt::from_i64(1);
+  while (r1.cmp(N) > 0) {
+    BigInt qq, rr;
+    BigInt::divmod_floor(r0, r1, qq, rr);
+    r0 = r1;
+    r1 = rr;
+    BigInt t2 = t0 - qq * t1;
+    t0 = t1;
+    t1 = t2;
+  }
+  BigInt a = r1, d = t1;
+  if (d.is_zero()) return false;
+  if (d.sign < 0) { a = -a; d = -d; }
+  if (d.cmp(D) > 0) return false;
+  if (!(BigInt::gcd(a, d).cmp(BigInt::from_i64(1)) == 0)) return false;
+  a_out = a;
+  d_out = d;
+  return true;
+}
+
+}  // namespace dethost

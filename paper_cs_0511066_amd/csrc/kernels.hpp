@@ -1,0 +1,55 @@
+// Launchers of the gfx950 kernels (host-callable, all asynchronous on `st`).
+// Every launcher returns the HIP error of the launch.  Shapes and pointers
+// are checked by the caller (the C-ABI layer) before any launch.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "modp.hpp"
+
+namespace detk {
+
+hipError_t launch_residues(const int64_t* A, int64_t lda, int n, int ncols, int32_t* W, int64_t ldw,
+                           int64_t slab, const Modulus* mods, int nitems, hipStream_t st);
+hipError_t launch_panel(int32_t* W, int64_t ldw, int64_t slab, int n, int j0, int pb, int pbmax,
+                        const Modulus* mods, int32_t* piv, int64_t piv_stride, int32_t* flags,
+                        int32_t* Linv, int nitems, hipStream_t st);
+hipError_t launch_swaps(int32_t* W, int64_t ldw, int64_t slab, int j0, int pb, const int32_t* piv,
+                        int64_t piv_stride, int c0a, int c1a, int c0b, int c1b, int nitems,
+                        hipStream_t st);
+hipError_t launch_tri_inv(const int32_t* W, int64_t ldw, int64_t slab, int k0, int kb, int upper,
+                          const Modulus* mods, int32_t* Tinv, int ldt, int kc, int nitems,
+                          hipStream_t st);
+hipError_t launch_trsm_apply(int32_t* W, int64_t slab, int64_t ldw, int r0, int kb, int c0, int N,
+                             const int32_t* Tinv, int ldt, const Modulus* mods, int kc4,
+                             int nitems, hipStream_t st);
+hipError_t launch_gemm_f64(int32_t* W, int64_t slab, int64_t offC, int64_t offA, int64_t offB,
+                           int64_t ldw, int M, int N, int K, const Modulus* mods, int kc4,
+                           int nitems, hipStream_t st);
+hipError_t launch_split(const int32_t* W, int64_t slab, int64_t off, int64_t ldw, int rows, int K,
+                        int Kp, int transpose, int8_t* P, int64_t pslab, int nitems,
+                        hipStream_t st);
+hipError_t launch_gemm_i8(int32_t* W, int64_t slab, int64_t offC, int64_t ldw, int M, int N,
+                          const int8_t* PA, const int8_t* PB, int64_t pslabA, int64_t pslabB,
+                          int Kp, const Modulus* mods, int nitems, hipStream_t st);
+hipError_t launch_det_finalize(const int32_t* W, int64_t ldw, int64_t slab, int n,
+                               const int32_t* piv, int64_t piv_stride, const int32_t* flags,
+                               const Modulus* mods, uint32_t* out, int nitems, hipStream_t st);
+hipError_t launch_extract_inverse(const int32_t* W, int64_t ldw, int n, const Modulus* mods,
+                                  uint32_t* Cu, hipStream_t st);
+
+// Dixon lifting (dixon_kernels.hip).
+hipError_t launch_lift_x(const uint32_t* Cu, const uint32_t* rp, int n, uint32_t p,
+                         uint32_t* xout, hipStream_t st);
+hipError_t launch_lift_r(const int32_t* Ai, const uint32_t* x, int64_t* r, uint32_t* rp, int n,
+                         uint32_t p, uint64_t pinv64, const uint32_t* cvec, uint64_t* comb,
+                         hipStream_t st);
+
+hipError_t launch_pack_i32(const int64_t* A, int64_t lda, int n, int32_t* Ai, hipStream_t st);
+hipError_t launch_norms(const int64_t* A, int64_t lda, int n, double* out2n, double* amax,
+                        hipStream_t st);
+
+// Configure dynamic-LDS limits once per device.
+hipError_t configure_kernels();
+
+}  // namespace detk

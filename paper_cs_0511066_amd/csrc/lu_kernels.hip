@@ -1,0 +1,810 @@
+// Blocked LU modulo p over a batch of primes, for gfx950.
+//
+// Section 2.1 of the paper obtains each modular determinant det(A) mod p_i
+// from an LU factorisation modulo p_i; Section 6 notes that the LU runs of
+// one CRA step are independent.  Here one batch item is one (matrix, prime)
+// pair, and every kernel covers all items of a batch in one launch.
+//
+// Storage: item z owns a slab W + z*slab of `rows` x ldw int32 centred
+// residues, row-major.  Two-level right-looking blocking:
+//   outer block of width NB  : tri_inv (L11^{-1}), trsm_apply (U12), gemm (A22)
+//   inner panel of width PB  : panel (pivot/scale/rank-1 in registers),
+//                              swaps, trsm_apply and gemm inside the block.
+// The trailing update A22 -= L21 U12 is the dense contraction: FP64 MFMA
+// (16x16x4) with the sum of |products| kept <= 2^53 per reduction chunk, or
+// int8 MFMA (16x16x64) on three signed limbs with int32 accumulation.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <limits.h>
+
+#include "modp.hpp"
+#include "kernels.hpp"
+
+namespace detk {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+// ------------------------------------------------------------------ helpers
+__device__ __forceinline__ int wave_min_int(int v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+// ------------------------------------------------------------------ K1: residues
+// W[z][i][j] = A[i][j] mod p_z (centred) for j < n; when `augment` is set the
+// columns n..2n-1 hold the identity (the right half of [A | I]).
+__global__ void k_residues(const int64_t* __restrict__ A, int64_t lda, int n, int ncols,
+                           int32_t* __restrict__ W, int64_t ldw, int64_t slab,
+                           const Modulus* __restrict__ mods, int nitems) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y;
+  if (j >= ncols || i >= n) return;
+  double a;
+  if (j < n) a = (double)A[(int64_t)i * lda + j];   // |a| < 2^31: exact
+  else a = (j - n == i) ? 1.0 : 0.0;
+  for (int z = 0; z < nitems; z++) {
+    const double p = mods[z].p, pinv = mods[z].pinv;
+    W[(int64_t)z * slab + (int64_t)i * ldw + j] = (int32_t)mod_c(a, p, pinv);
+  }
+}
+
+// ------------------------------------------------------------------ K2: panel
+// Factor rows [j0, n) x columns [j0, j0+pb) of every item.  Thread t holds
+// panel rows t, t+1024, ... in registers.  Pivot = first row at or below the
+// diagonal with a non-zero entry (lowest row index); the whole panel row is
+// swapped.  Outputs: L below the diagonal, U on and above it, piv[j0+j] =
+// global row swapped with row j0+j, flags[z] = 1 if a column has no pivot
+// (then det = 0 mod p), and Linv = the pb x pb unit lower inverse of L11
+// (dense, PB x PB, zero-padded).
+template <int PB, int RPT>
+__global__ __launch_bounds__(1024) void k_panel(int32_t* __restrict__ W, int64_t ldw, int64_t slab,
+                                                int n, int j0, int pb,
+                                                const Modulus* __restrict__ mods,
+                                                int32_t* __restrict__ piv, int64_t piv_stride,
+                                                int32_t* __restrict__ flags,
+                                                int32_t* __restrict__ Linv) {
+  constexpr int T = 1024;
+  const int z = blockIdx.x;
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  const double p = mods[z].p, pinv = mods[z].pinv;
+  int32_t* Wz = W + (int64_t)z * slab + (int64_t)j0 * ldw + j0;
+  const int m = n - j0;
+
+  __shared__ int s_min[2][16];
+  __shared__ double s_prow[2][PB];
+  __shared__ double s_jrow[2][PB];
+  __shared__ double s_inv[2];
+  __shared__ double s_L[PB][PB + 1];
+
+  int32_t a[RPT][PB];
+#pragma unroll
+  for (int q = 0; q < RPT; q++) {
+    const int row = t + q * T;
+#pragma unroll
+    for (int c = 0; c < PB; c++)
+      a[q][c] = (row < m && c < pb) ? Wz[(int64_t)row * ldw + c] : 0;
+  }
+
+#pragma unroll
+  for (int j = 0; j < PB; j++) {
+    if (j < pb) {
+      const int buf = j & 1;
+      int cand = INT_MAX;
+#pragma unroll
+      for (int q = 0; q < RPT; q++) {
+        const int row = t + q * T;
+        if (row >= j && row < m && a[q][j] != 0) cand = min(cand, row);
+      }
+      cand = wave_min_int(cand);
+      if (lane == 0) s_min[buf][wave] = cand;
+      __syncthreads();
+      int pr = INT_MAX;
+#pragma unroll
+      for (int w = 0; w < T / 64; w++) pr = min(pr, s_min[buf][w]);
+      if (pr == INT_MAX) {             // no pivot: det = 0 mod p; column left as is
+        if (t == 0) {
+          flags[z] = 1;
+          piv[(int64_t)z * piv_stride + j0 + j] = j0 + j;
+        }
+        continue;                      // uniform: every thread read the same pr
+      }
+#pragma unroll
+      for (int q = 0; q < RPT; q++) {
+        const int row = t + q * T;
+        if (row == pr) {
+#pragma unroll
+          for (int c = 0; c < PB; c++) s_prow[buf][c] = (double)a[q][c];
+          s_inv[buf] = inv_mod((double)a[q][j], p, pinv);
+        }
+        if (row == j && pr != j) {
+#pragma unroll
+          for (int c = 0; c < PB; c++) s_jrow[buf][c] = (double)a[q][c];
+        }
+      }
+      __syncthreads();
+      const double inv = s_inv[buf];
+#pragma unroll
+      for (int q = 0; q < RPT; q++) {
+        const int row = t + q * T;
+        if (pr != j) {
+          if (row == j) {
+#pragma unroll
+            for (int c = 0; c < PB; c++) a[q][c] = (int32_t)s_prow[buf][c];
+          } else if (row == pr) {
+#pragma unroll
+            for (int c = 0; c < PB; c++) a[q][c] = (int32_t)s_jrow[buf][c];
+          }
+        }
+        if (row > j && row < m) {
+          const double l = mul_mod((double)a[q][j], inv, p, pinv);
+          a[q][j] = (int32_t)l;
+#pragma unroll
+          for (int c = j + 1; c < PB; c++)
+            a[q][c] = (int32_t)mod_c((double)a[q][c] - l * s_prow[buf][c], p, pinv);
+        }
+      }
+      if (t == 0) piv[(int64_t)z * piv_stride + j0 + j] = j0 + pr;
+    }
+  }
+
+  // write back, and stage L11 (strictly lower part of the top pb x pb block)
+#pragma unroll
+  for (int q = 0; q < RPT; q++) {
+    const int row = t + q * T;
+    if (row < m) {
+#pragma unroll
+      for (int c = 0; c < PB; c++)
+        if (c < pb) Wz[(int64_t)row * ldw + c] = a[q][c];
+    }
+    if (row < PB) {
+#pragma unroll
+      for (int c = 0; c < PB; c++) s_L[row][c] = (row < pb && c < row) ? (double)a[q][c] : 0.0;
+    }
+  }
+  __syncthreads();
+  // Linv column c (thread c): X[c][c] = 1, X[i][c] = -sum_{k=c}^{i-1} L[i][k] X[k][c].
+  // Each sum has < 32 products of centred residues (< 2^50 each for p < 2^26)
+  // so it is reduced every 8 terms to stay below 2^53.
+  if (t < PB) {
+    const int c = t;
+    int32_t* Lz = Linv + (int64_t)z * PB * PB;
+    double x[PB];
+#pragma unroll
+    for (int i = 0; i < PB; i++) x[i] = 0.0;
+#pragma unroll
+    for (int i = 0; i < PB; i++) {
+      if (i == c) x[i] = 1.0;
+      else if (i > c) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < i; k++) {
+          if (k >= c) s += s_L[i][k] * x[k];
+          if ((k & 7) == 7) s = mod_c(s, p, pinv);
+        }
+        x[i] = mod_c(-s, p, pinv);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < PB; i++) Lz[i * PB + c] = (i < pb && c < pb) ? (int32_t)x[i] : 0;
+  }
+}
+
+// ------------------------------------------------------------------ K3: row swaps
+// Apply the swaps of panel [j0, j0+pb) (row j0+j <-> piv[j0+j], in order) to
+// the columns [c0a, c1a) and [c0b, c1b) of every item.
+__global__ void k_swaps(int32_t* __restrict__ W, int64_t ldw, int64_t slab, int j0, int pb,
+                        const int32_t* __restrict__ piv, int64_t piv_stride,
+                        int c0a, int c1a, int c0b, int c1b) {
+  const int z = blockIdx.y;
+  const int32_t* pz = piv + (int64_t)z * piv_stride + j0;
+  bool any = false;
+  for (int j = 0; j < pb; j++) any |= (pz[j] != j0 + j);
+  if (!any) return;
+  const int wa = c1a - c0a;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int wtot = wa + (c1b - c0b);
+  if (idx >= wtot) return;
+  const int col = idx < wa ? c0a + idx : c0b + (idx - wa);
+  int32_t* Wz = W + (int64_t)z * slab + col;
+  for (int j = 0; j < pb; j++) {
+    const int r = pz[j];
+    if (r != j0 + j) {
+      const int32_t v = Wz[(int64_t)(j0 + j) * ldw];
+      Wz[(int64_t)(j0 + j) * ldw] = Wz[(int64_t)r * ldw];
+      Wz[(int64_t)r * ldw] = v;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ triangular inverse
+// Inverse of the kb x kb diagonal block at rows/cols [k0, k0+kb) of every
+// item: lower unit (the L11 of an outer block) or upper non-unit (U11, used
+// by back substitution).  One workgroup per item, thread c computes column c.
+// Out: Tinv[z] dense KBMAX x KBMAX (ld KBMAX), zero outside kb x kb.
+__global__ __launch_bounds__(256) void k_tri_inv(const int32_t* __restrict__ W, int64_t ldw,
+                                                 int64_t slab, int k0, int kb, int upper,
+                                                 const Modulus* __restrict__ mods,
+                                                 int32_t* __restrict__ Tinv, int ldt, int kc) {
+  const int z = blockIdx.x;
+  const int t = threadIdx.x;
+  const double p = mods[z].p, pinv = mods[z].pinv;
+  extern __shared__ int32_t smem[];
+  int32_t* sT = smem;                         // kb x kb block
+  int32_t* sX = smem + kb * kb;               // kb x kb result (column per thread)
+  double* sD = (double*)(sX + kb * kb);       // inverses of the diagonal (upper)
+  const int32_t* Wz = W + (int64_t)z * slab + (int64_t)k0 * ldw + k0;
+  for (int e = t; e < kb * kb; e += blockDim.x) sT[e] = Wz[(int64_t)(e / kb) * ldw + (e % kb)];
+  __syncthreads();
+  if (upper) {
+    for (int i = t; i < kb; i += blockDim.x) sD[i] = inv_mod((double)sT[i * kb + i], p, pinv);
+    __syncthreads();
+  }
+  for (int c = t; c < kb; c += blockDim.x) {
+    if (!upper) {
+      for (int i = 0; i < c; i++) sX[i * kb + c] = 0;
+      sX[c * kb + c] = 1;
+      for (int i = c + 1; i < kb; i++) {
+        double s = 0.0;
+        int cnt = 0;
+        for (int k = c; k < i; k++) {
+          s += (double)sT[i * kb + k] * (double)sX[k * kb + c];
+          if (++cnt == kc) { s = mod_c(s, p, pinv); cnt = 0; }
+        }
+        sX[i * kb + c] = (int32_t)mod_c(-s, p, pinv);
+      }
+    } else {
+      for (int i = c + 1; i < kb; i++) sX[i * kb + c] = 0;
+      sX[c * kb + c] = (int32_t)sD[c];
+      for (int i = c - 1; i >= 0; i--) {
+        double s = 0.0;
+        int cnt = 0;
+        for (int k = i + 1; k <= c; k++) {
+          s += (double)sT[i * kb + k] * (double)sX[k * kb + c];
+          if (++cnt == kc) { s = mod_c(s, p, pinv); cnt = 0; }
+        }
+        s = mod_c(s, p, pinv);
+        sX[i * kb + c] = (int32_t)mul_mod(-s, sD[i], p, pinv);
+      }
+    }
+  }
+  __syncthreads();
+  int32_t* Tz = Tinv + (int64_t)z * ldt * ldt;
+  for (int e = t; e < ldt * ldt; e += blockDim.x) {
+    const int i = e / ldt, c = e % ldt;
+    Tz[e] = (i < kb && c < kb) ? sX[i * kb + c] : 0;
+  }
+}
+
+// ------------------------------------------------------------------ FP64 MFMA tile machinery
+// A 256-thread workgroup computes a 64x64 tile; wave w owns the 32x32
+// quadrant (w>>1, w&1) as 2x2 MFMA 16x16 blocks.  Operands are staged in LDS
+// as doubles, k-major, so that a lane reads 16 consecutive doubles per row.
+// v_mfma_f64_16x16x4: lane l supplies A[l%16][l/16] and B[l/16][l%16];
+// result element r of lane l is D[l/16 + 4r][l%16].
+constexpr int GB_M = 64, GB_N = 64, GB_K = 16;
+
+// C[z] = (C[z] - A[z] * B[z]) mod p_z over an M x N region (all int32
+// centred residues, row-major with leading dimensions).  `kc4` = number of
+// MFMA k-steps (4 products each) after which the accumulator is reduced.
+__global__ __launch_bounds__(256) void k_gemm_f64(int32_t* __restrict__ W, int64_t slab,
+                                                  int64_t offC, int64_t offA, int64_t offB,
+                                                  int64_t ldw, int M, int N, int K,
+                                                  const Modulus* __restrict__ mods, int kc4) {
+  const int z = blockIdx.z;
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const double p = mods[z].p, pinv = mods[z].pinv;
+  int32_t* Wz = W + (int64_t)z * slab;
+  const int32_t* Ag = Wz + offA;
+  const int32_t* Bg = Wz + offB;
+  int32_t* Cg = Wz + offC;
+  const int row0 = blockIdx.y * GB_M, col0 = blockIdx.x * GB_N;
+
+  __shared__ double sA[GB_K][GB_M + 2];
+  __shared__ double sB[GB_K][GB_N + 2];
+
+  v4d acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; i++)
+#pragma unroll
+    for (int j = 0; j < 2; j++) acc[i][j] = (v4d){0.0, 0.0, 0.0, 0.0};
+
+  int steps = 0;
+  for (int k0 = 0; k0 < K; k0 += GB_K) {
+    // A tile: 64 rows x 16 k; thread t loads row t/4, k (t%4)*4 .. +3
+    {
+      const int r = t >> 2, kq = (t & 3) * 4;
+      const int gr = row0 + r;
+#pragma unroll
+      for (int u = 0; u < 4; u++) {
+        const int gk = k0 + kq + u;
+        sA[kq + u][r] = (gr < M && gk < K) ? (double)Ag[(int64_t)gr * ldw + gk] : 0.0;
+      }
+    }
+    // B tile: 16 k x 64 cols; thread t loads k t/16, cols (t%16)*4 .. +3
+    {
+      const int kk = t >> 4, cq = (t & 15) * 4;
+      const int gk = k0 + kk;
+#pragma unroll
+      for (int u = 0; u < 4; u++) {
+        const int gc = col0 + cq + u;
+        sB[kk][cq + u] = (gk < K && gc < N) ? (double)Bg[(int64_t)gk * ldw + gc] : 0.0;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < GB_K; ks += 4) {
+      const int kr = ks + (lane >> 4);
+      double af[2], bf[2];
+#pragma unroll
+      for (int i = 0; i < 2; i++) af[i] = sA[kr][wr * 32 + i * 16 + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < 2; j++) bf[j] = sB[kr][wc * 32 + j * 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < 2; i++)
+#pragma unroll
+        for (int j = 0; j < 2; j++)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+      if (++steps == kc4) {
+        steps = 0;
+#pragma unroll
+        for (int i = 0; i < 2; i++)
+#pragma unroll
+          for (int j = 0; j < 2; j++)
+#pragma unroll
+            for (int r = 0; r < 4; r++) acc[i][j][r] = mod_c(acc[i][j][r], p, pinv);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; i++)
+#pragma unroll
+    for (int j = 0; j < 2; j++)
+#pragma unroll
+      for (int r = 0; r < 4; r++) {
+        const int gr = row0 + wr * 32 + i * 16 + (lane >> 4) + 4 * r;
+        const int gc = col0 + wc * 32 + j * 16 + (lane & 15);
+        if (gr < M && gc < N) {
+          int32_t* cp = Cg + (int64_t)gr * ldw + gc;
+          const double s = mod_c(acc[i][j][r], p, pinv);
+          *cp = (int32_t)mod_c((double)*cp - s, p, pinv);
+        }
+      }
+}
+
+// ------------------------------------------------------------------ K4: in-place triangular apply
+// X <- Tinv[z] * X for the strip X = rows [r0, r0+kb) x columns [c0, c0+N)
+// of every item (U12 = L11^{-1} A12, or X_blk = U11^{-1} Y_blk).  A
+// workgroup loads its whole kb x 64 column strip into LDS before it writes,
+// so the update in place is safe (no other workgroup touches those columns).
+__global__ __launch_bounds__(256) void k_trsm_apply(int32_t* __restrict__ W, int64_t slab,
+                                                    int64_t ldw, int r0, int kb, int c0, int N,
+                                                    const int32_t* __restrict__ Tinv, int ldt,
+                                                    const Modulus* __restrict__ mods, int kc4) {
+  const int z = blockIdx.y;
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const double p = mods[z].p, pinv = mods[z].pinv;
+  int32_t* Xg = W + (int64_t)z * slab + (int64_t)r0 * ldw + c0;
+  const int32_t* Tz = Tinv + (int64_t)z * ldt * ldt;
+  const int col0 = blockIdx.x * GB_N;
+  extern __shared__ double sX[];             // [ldt][GB_N + 2]
+  constexpr int LDX = GB_N + 2;
+  for (int e = t; e < ldt * GB_N; e += 256) {
+    const int k = e / GB_N, c = e % GB_N;
+    const int gc = col0 + c;
+    sX[k * LDX + c] = (k < kb && gc < N) ? (double)Xg[(int64_t)k * ldw + gc] : 0.0;
+  }
+  __syncthreads();
+  for (int rb = 0; rb < kb; rb += GB_M) {
+    v4d acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; i++)
+#pragma unroll
+      for (int j = 0; j < 2; j++) acc[i][j] = (v4d){0.0, 0.0, 0.0, 0.0};
+    int steps = 0;
+    for (int ks = 0; ks < kb; ks += 4) {
+      const int kr = ks + (lane >> 4);
+      double af[2], bf[2];
+#pragma unroll
+      for (int i = 0; i < 2; i++) {
+        const int rr = rb + wr * 32 + i * 16 + (lane & 15);
+        af[i] = (rr < kb && kr < kb) ? (double)Tz[rr * ldt + kr] : 0.0;
+      }
+#pragma unroll
+      for (int j = 0; j < 2; j++) bf[j] = sX[kr * LDX + wc * 32 + j * 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < 2; i++)
+#pragma unroll
+        for (int j = 0; j < 2; j++)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+      if (++steps == kc4) {
+        steps = 0;
+#pragma unroll
+        for (int i = 0; i < 2; i++)
+#pragma unroll
+          for (int j = 0; j < 2; j++)
+#pragma unroll
+            for (int r = 0; r < 4; r++) acc[i][j][r] = mod_c(acc[i][j][r], p, pinv);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 2; i++)
+#pragma unroll
+      for (int j = 0; j < 2; j++)
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+          const int gr = rb + wr * 32 + i * 16 + (lane >> 4) + 4 * r;
+          const int gc = col0 + wc * 32 + j * 16 + (lane & 15);
+          if (gr < kb && gc < N) Xg[(int64_t)gr * ldw + gc] = (int32_t)mod_c(acc[i][j][r], p, pinv);
+        }
+  }
+}
+
+// ------------------------------------------------------------------ int8 limb path
+// A centred residue |r| < 2^22 (p < 2^23) splits into balanced signed limbs
+// r = l0 + 2^8 l1 + 2^16 l2 with l0, l1 in [-128, 127] and |l2| <= 64.
+__device__ __forceinline__ void split3(int32_t r, int8_t& l0, int8_t& l1, int8_t& l2) {
+  const int32_t a0 = ((r + 128) & 255) - 128;
+  const int32_t r1 = (r - a0) >> 8;
+  const int32_t a1 = ((r1 + 128) & 255) - 128;
+  const int32_t a2 = (r1 - a1) >> 8;
+  l0 = (int8_t)a0;
+  l1 = (int8_t)a1;
+  l2 = (int8_t)a2;
+}
+
+// Limb planes of an M x K operand (A: row-major, k contiguous) or of a K x N
+// operand stored transposed (B: column j's K values contiguous), padded to
+// Kp (a multiple of 64) with zeros.  Out: P[z][3][rows][Kp].
+__global__ void k_split(const int32_t* __restrict__ W, int64_t slab, int64_t off, int64_t ldw,
+                        int rows, int K, int Kp, int transpose, int8_t* __restrict__ P,
+                        int64_t pslab) {
+  const int z = blockIdx.z;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (k >= Kp || r >= rows) return;
+  int32_t v = 0;
+  if (k < K) {
+    const int32_t* Wz = W + (int64_t)z * slab + off;
+    v = transpose ? Wz[(int64_t)k * ldw + r] : Wz[(int64_t)r * ldw + k];
+  }
+  int8_t l0, l1, l2;
+  split3(v, l0, l1, l2);
+  int8_t* Pz = P + (int64_t)z * pslab;
+  const int64_t plane = (int64_t)rows * Kp;
+  Pz[(int64_t)r * Kp + k] = l0;
+  Pz[plane + (int64_t)r * Kp + k] = l1;
+  Pz[2 * plane + (int64_t)r * Kp + k] = l2;
+}
+
+// C[z] = (C[z] - A[z] B[z]) mod p_z with A, B given as limb planes.
+// C_s = sum_{a+b=s} A_a B_b on v_mfma_i32_16x16x64_i8 (exact while
+// 3 K 2^14 < 2^31), then C -= sum_s (C_s mod p)(2^(8s) mod p) mod p in FP64.
+// Lane l supplies A[l%16][16(l/16) .. +16) and B^T[l%16][same k]; result
+// element r of lane l is D[4(l/16) + r][l%16].
+constexpr int GI_K = 64;
+constexpr int GI_LD = GI_K + 16;   // row stride 80 B: 16-byte reads conflict-free
+
+__global__ __launch_bounds__(256) void k_gemm_i8(int32_t* __restrict__ W, int64_t slab,
+                                                 int64_t offC, int64_t ldw, int M, int N,
+                                                 const int8_t* __restrict__ PA,
+                                                 const int8_t* __restrict__ PB, int64_t pslabA,
+                                                 int64_t pslabB, int Kp,
+                                                 const Modulus* __restrict__ mods) {
+  const int z = blockIdx.z;
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const double p = mods[z].p, pinv = mods[z].pinv;
+  const int row0 = blockIdx.y * GB_M, col0 = blockIdx.x * GB_N;
+  const int8_t* Az = PA + (int64_t)z * pslabA;
+  const int8_t* Bz = PB + (int64_t)z * pslabB;
+  const int64_t planeA = (int64_t)M * Kp, planeB = (int64_t)N * Kp;
+
+  __shared__ __attribute__((aligned(16))) int8_t sA[3][GB_M][GI_LD];
+  __shared__ __attribute__((aligned(16))) int8_t sB[3][GB_N][GI_LD];
+
+  v4i acc[5][2][2];
+#pragma unroll
+  for (int s = 0; s < 5; s++)
+#pragma unroll
+    for (int i = 0; i < 2; i++)
+#pragma unroll
+      for (int j = 0; j < 2; j++) acc[s][i][j] = (v4i){0, 0, 0, 0};
+
+  for (int k0 = 0; k0 < Kp; k0 += GI_K) {
+    // 3 planes x 64 rows x 64 bytes per operand = 768 chunks of 16 B; 3 per thread
+#pragma unroll
+    for (int u = 0; u < 3; u++) {
+      const int e = t + u * 256;
+      const int pl = e >> 8, rem = e & 255, r = rem >> 2, q = (rem & 3) * 16;
+      v4i va = (v4i){0, 0, 0, 0}, vb = (v4i){0, 0, 0, 0};
+      if (row0 + r < M) va = *(const v4i*)(Az + pl * planeA + (int64_t)(row0 + r) * Kp + k0 + q);
+      if (col0 + r < N) vb = *(const v4i*)(Bz + pl * planeB + (int64_t)(col0 + r) * Kp + k0 + q);
+      *(v4i*)(&sA[pl][r][q]) = va;
+      *(v4i*)(&sB[pl][r][q]) = vb;
+    }
+    __syncthreads();
+    v4i af[3][2], bf[3][2];
+#pragma unroll
+    for (int pl = 0; pl < 3; pl++) {
+#pragma unroll
+      for (int i = 0; i < 2; i++)
+        af[pl][i] = *(const v4i*)(&sA[pl][wr * 32 + i * 16 + (lane & 15)][16 * (lane >> 4)]);
+#pragma unroll
+      for (int j = 0; j < 2; j++)
+        bf[pl][j] = *(const v4i*)(&sB[pl][wc * 32 + j * 16 + (lane & 15)][16 * (lane >> 4)]);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; i++)
+#pragma unroll
+      for (int j = 0; j < 2; j++) {
+#pragma unroll
+        for (int a = 0; a < 3; a++)
+#pragma unroll
+          for (int b = 0; b < 3; b++)
+            acc[a + b][i][j] =
+                __builtin_amdgcn_mfma_i32_16x16x64_i8(af[a][i], bf[b][j], acc[a + b][i][j], 0, 0, 0);
+      }
+    __syncthreads();
+  }
+  // weights 2^(8s) mod p, centred
+  double wgt[5];
+  wgt[0] = 1.0;
+#pragma unroll
+  for (int s = 1; s < 5; s++) wgt[s] = mod_c(wgt[s - 1] * 256.0, p, pinv);
+  int32_t* Cg = W + (int64_t)z * slab + offC;
+#pragma unroll
+  for (int i = 0; i < 2; i++)
+#pragma unroll
+    for (int j = 0; j < 2; j++)
+#pragma unroll
+      for (int r = 0; r < 4; r++) {
+        const int gr = row0 + wr * 32 + i * 16 + 4 * (lane >> 4) + r;
+        const int gc = col0 + wc * 32 + j * 16 + (lane & 15);
+        if (gr < M && gc < N) {
+          double v = 0.0;
+#pragma unroll
+          for (int s = 0; s < 5; s++) v += mod_c((double)acc[s][i][j][r], p, pinv) * wgt[s];
+          v = mod_c(v, p, pinv);
+          int32_t* cp = Cg + (int64_t)gr * ldw + gc;
+          *cp = (int32_t)mod_c((double)*cp - v, p, pinv);
+        }
+      }
+}
+
+// ------------------------------------------------------------------ K6: determinant
+// det mod p = (-1)^(#swaps) * prod u_jj, canonical; 0 if flagged singular.
+__global__ __launch_bounds__(256) void k_det_finalize(const int32_t* __restrict__ W, int64_t ldw,
+                                                      int64_t slab, int n,
+                                                      const int32_t* __restrict__ piv,
+                                                      int64_t piv_stride,
+                                                      const int32_t* __restrict__ flags,
+                                                      const Modulus* __restrict__ mods,
+                                                      uint32_t* __restrict__ out) {
+  const int z = blockIdx.x;
+  const int t = threadIdx.x;
+  const double p = mods[z].p, pinv = mods[z].pinv;
+  const int32_t* Wz = W + (int64_t)z * slab;
+  double prod = 1.0;
+  int swaps = 0;
+  for (int j = t; j < n; j += 256) {
+    prod = mul_mod(prod, (double)Wz[(int64_t)j * ldw + j], p, pinv);
+    swaps += piv[(int64_t)z * piv_stride + j] != j;
+  }
+  __shared__ double sp[256];
+  __shared__ int ss[256];
+  sp[t] = prod;
+  ss[t] = swaps;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (t < s) {
+      sp[t] = mul_mod(sp[t], sp[t + s], p, pinv);
+      ss[t] += ss[t + s];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    double d = sp[0];
+    if (ss[0] & 1) d = -d;
+    if (flags[z]) d = 0.0;
+    out[z] = to_canonical(d, p);
+  }
+}
+
+// ------------------------------------------------------------------ inverse extraction
+// Cu[i][j] = canonical residue of W[z=0][i][n + j] (the right half of [A | I]
+// after elimination and back substitution holds A^{-1} mod p).
+__global__ void k_extract_inverse(const int32_t* __restrict__ W, int64_t ldw, int n,
+                                  const Modulus* __restrict__ mods, uint32_t* __restrict__ Cu) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y;
+  if (j >= n || i >= n) return;
+  const double p = mods[0].p;
+  Cu[(int64_t)i * n + j] = to_canonical((double)W[(int64_t)i * ldw + n + j], p);
+}
+
+// ------------------------------------------------------------------ A packing and norms
+// Ai = A as int32 (the entry bound |a_ij| < 2^31 is checked on the host).
+__global__ void k_pack_i32(const int64_t* __restrict__ A, int64_t lda, int n,
+                           int32_t* __restrict__ Ai) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y;
+  if (j >= n || i >= n) return;
+  Ai[(int64_t)i * n + j] = (int32_t)A[(int64_t)i * lda + j];
+}
+
+// out[j] = sum_i a_ij^2 (columns), out[n + i] = sum_j a_ij^2 (rows), both in
+// FP64 (rounded; the host adds a relative margin), and amax[j] = max_i |a_ij|.
+__global__ void k_col_norms(const int64_t* __restrict__ A, int64_t lda, int n,
+                            double* __restrict__ out, double* __restrict__ amax) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double s = 0.0, m = 0.0;
+  for (int i = 0; i < n; i++) {
+    const double a = (double)A[(int64_t)i * lda + j];
+    s = fma(a, a, s);
+    m = fmax(m, fabs(a));
+  }
+  out[j] = s;
+  amax[j] = m;
+}
+__global__ __launch_bounds__(256) void k_row_norms(const int64_t* __restrict__ A, int64_t lda,
+                                                   int n, double* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= n) return;
+  double s = 0.0;
+  for (int j = lane; j < n; j += 64) {
+    const double a = (double)A[(int64_t)i * lda + j];
+    s = fma(a, a, s);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if (lane == 0) out[n + i] = s;
+}
+
+// ------------------------------------------------------------------ launchers
+#define LAUNCH_CHECK() do { hipError_t e_ = hipGetLastError(); if (e_ != hipSuccess) return e_; } while (0)
+
+hipError_t launch_residues(const int64_t* A, int64_t lda, int n, int ncols, int32_t* W, int64_t ldw,
+                           int64_t slab, const Modulus* mods, int nitems, hipStream_t st) {
+  if (n <= 0 || ncols <= 0) return hipSuccess;
+  dim3 grid((ncols + 255) / 256, n);
+  k_residues<<<grid, 256, 0, st>>>(A, lda, n, ncols, W, ldw, slab, mods, nitems);
+  LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+hipError_t launch_panel(int32_t* W, int64_t ldw, int64_t slab, int n, int j0, int pb, int pbmax,
+                        const Modulus* mods, int32_t* piv, int64_t piv_stride, int32_t* flags,
+                        int32_t* Linv, int nitems, hipStream_t st) {
+  const int m = n - j0;
+  if (pbmax == 32 && m <= 1024)
+    k_panel<32, 1><<<nitems, 1024, 0, st>>>(W, ldw, slab, n, j0, pb, mods, piv, piv_stride, flags, Linv);
+  else if (pbmax == 32 && m <= 2048)
+    k_panel<32, 2><<<nitems, 1024, 0, st>>>(W, ldw, slab, n, j0, pb, mods, piv, piv_stride, flags, Linv);
+  else if (pbmax == 16 && m <= 4096)
+    k_panel<16, 4><<<nitems, 1024, 0, st>>>(W, ldw, slab, n, j0, pb, mods, piv, piv_stride, flags, Linv);
+  else
+    return hipErrorInvalidValue;
+  LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+hipError_t launch_swaps(int32_t* W, int64_t ldw, int64_t slab, int j0, int pb, const int32_t* piv,
+                        int64_t piv_stride, int c0a, int c1a, int c0b, int c1b, int nitems,
+                        hipStream_t st) {
+  const int w = (c1a - c0a) + (c1b - c0b);
+  if (w <= 0) return hipSuccess;
+  dim3 grid((w + 255) / 256, nitems);
+  k_swaps<<<grid, 256, 0, st>>>(W, ldw, slab, j0, pb, piv, piv_stride, c0a, c1a, c0b, c1b);
+  LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+hipError_t launch_tri_inv(const int32_t* W, int64_t ldw, int64_t slab, int k0, int kb, int upper,
+                          const Modulus* mods, int32_t* Tinv, int ldt, int kc, int nitems,
+                          hipStream_t st) {
+  if (kb <= 0) return hipSuccess;
+  if (kb > ldt || kb > 128) return hipErrorInvalidValue;
+  const size_t sh = (size_t)2 * kb * kb * sizeof(int32_t) + (size_t)kb * sizeof(double);
+  k_tri_inv<<<nitems, 256, sh, st>>>(W, ldw, slab, k0, kb, upper, mods, Tinv, ldt, kc);
+  LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+hipError_t launch_trsm_apply(int32_t* W, int64_t slab, int64_t ldw, int r0, int kb, int c0, int N,
+                             const int32_t* Tinv, int ldt, const Modulus* mods, int kc4,
+                             int nitems, hipStream_t st) {
+  if (kb <= 0 || N <= 0) return hipSuccess;
+  if (kb > ldt || (ldt % 4) != 0) return hipErrorInvalidValue;
+  dim3 grid((N + GB_N - 1) / GB_N, nitems);
+  const size_t sh = (size_t)ldt * (GB_N + 2) * sizeof(double);
+  k_trsm_apply<<<grid, 256, sh, st>>>(W, slab, ldw, r0, kb, c0, N, Tinv, ldt, mods, kc4);
+  LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+hipError_t launch_gemm_f64(int32_t* W, int64_t slab, int64_t offC, int64_t offA, int64_t offB,
+                           int64_t ldw, int M, int N, int K, const Modulus* mods, int kc4,
+                           int nitems, hipStream_t st) {
+  if (M <= 0 || N <= 0 || K <= 0) return hipSuccess;
+  dim3 grid((N + GB_N - 1) / GB_N, (M + GB_M - 1) / GB_M, nitems);
+  k_gemm_f64<<<grid, 256, 0, st>>>(W, slab, offC, offA, offB, ldw, M, N, K, mods, kc4);
+  LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+hipError_t launch_split(const int32_t* W, int64_t slab, int64_t off, int64_t ldw, int rows, int K,
+                        int Kp, int transpose, int8_t* P, int64_t pslab, int nitems,
+                        hipStream_t st) {
+  if (rows <= 0 || Kp <= 0) return hipSuccess;
+  dim3 grid((Kp + 255) / 256, rows, nitems);
+  k_split<<<grid, 256, 0, st>>>(W, slab, off, ldw, rows, K, Kp, transpose, P, pslab);
+  LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+hipError_t launch_gemm_i8(int32_t* W, int64_t slab, int64_t offC, int64_t ldw, int M, int N,
+                          const int8_t* PA, const int8_t* PB, int64_t pslabA, int64_t pslabB,
+                          int Kp, const Modulus* mods, int nitems, hipStream_t st) {
+  if (M <= 0 || N <= 0 || Kp <= 0) return hipSuccess;
+  if (Kp % GI_K) return hipErrorInvalidValue;
+  dim3 grid((N + GB_N - 1) / GB_N, (M + GB_M - 1) / GB_M, nitems);
+  k_gemm_i8<<<grid, 256, 0, st>>>(W, slab, offC, ldw, M, N, PA, PB, pslabA, pslabB, Kp, mods);
+  LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+hipError_t launch_det_finalize(const int32_t* W, int64_t ldw, int64_t slab, int n,
+                               const int32_t* piv, int64_t piv_stride, const int32_t* flags,
+                               const Modulus* mods, uint32_t* out, int nitems, hipStream_t st) {
+  k_det_finalize<<<nitems, 256, 0, st>>>(W, ldw, slab, n, piv, piv_stride, flags, mods, out);
+  LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+hipError_t launch_extract_inverse(const int32_t* W, int64_t ldw, int n, const Modulus* mods,
+                                  uint32_t* Cu, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  dim3 grid((n + 255) / 256, n);
+  k_extract_inverse<<<grid, 256, 0, st>>>(W, ldw, n, mods, Cu);
+  LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+hipError_t launch_pack_i32(const int64_t* A, int64_t lda, int n, int32_t* Ai, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  dim3 grid((n + 255) / 256, n);
+  k_pack_i32<<<grid, 256, 0, st>>>(A, lda, n, Ai);
+  LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+hipError_t launch_norms(const int64_t* A, int64_t lda, int n, double* out2n, double* amax,
+                        hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  k_col_norms<<<(n + 255) / 256, 256, 0, st>>>(A, lda, n, out2n, amax);
+  LAUNCH_CHECK();
+  k_row_norms<<<(n + 3) / 4, 256, 0, st>>>(A, lda, n, out2n);
+  LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+hipError_t configure_kernels() {
+  hipError_t e = hipFuncSetAttribute((const void*)k_tri_inv,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_trsm_apply,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+}
+
+}  // namespace detk

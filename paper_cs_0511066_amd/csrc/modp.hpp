@@ -1,0 +1,58 @@
+// Device-side arithmetic modulo a word-size odd prime p < 2^26.
+//
+// Residues are kept centred, in [-(p-1)/2, (p-1)/2], stored as int32 and
+// computed in FP64.  A product of two centred residues is below 2^50 in
+// magnitude, so it is exact in FP64; a sum of such products stays exact as
+// long as the sum of absolute values stays <= 2^53 (the chunk bound that the
+// host computes and passes as `kc`).  Reduction: q = rint(c / p) from a
+// precomputed 1/p, r = c - q p by one fused multiply-add (exact, since the
+// true result is a small integer), then one fold into the centred range.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace detk {
+
+// c: an integer-valued double with |c| <= 2^53.  Returns c mod p, centred.
+__device__ __forceinline__ double mod_c(double c, double p, double pinv) {
+  double q = rint(c * pinv);
+  double r = fma(-q, p, c);
+  double h = 0.5 * p;                 // p odd: the centred range is |r| < p/2
+  r = (r > h) ? r - p : r;
+  r = (r < -h) ? r + p : r;
+  return r;
+}
+
+__device__ __forceinline__ double mul_mod(double a, double b, double p, double pinv) {
+  return mod_c(a * b, p, pinv);
+}
+
+// a^e mod p by square-and-multiply (e >= 0).
+__device__ __forceinline__ double pow_mod(double a, uint32_t e, double p, double pinv) {
+  double r = 1.0;
+  double b = a;
+  while (e) {
+    if (e & 1u) r = mul_mod(r, b, p, pinv);
+    b = mul_mod(b, b, p, pinv);
+    e >>= 1;
+  }
+  return r;
+}
+
+// Inverse of a non-zero residue by Fermat's little theorem, a^(p-2).
+__device__ __forceinline__ double inv_mod(double a, double p, double pinv) {
+  return pow_mod(a, (uint32_t)p - 2u, p, pinv);
+}
+
+// Canonical residue in [0, p) of a centred one.
+__device__ __forceinline__ uint32_t to_canonical(double r, double p) {
+  return (uint32_t)(int64_t)(r < 0 ? r + p : r);
+}
+
+// Per-batch-item modulus (one prime per LU in a batch).
+struct Modulus {
+  double p;
+  double pinv;
+};
+
+}  // namespace detk

@@ -1,0 +1,251 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle, on the
+same seeded inputs.  Integer work: every residue, digit and determinant must
+match bit for bit (tolerance 0)."""
+import json
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from conftest import ROOT, test_primes
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_cs_0511066_amd as det
+    c = det.Context(0)
+    yield c
+    c.close()
+
+
+# ---------------------------------------------------------------- det_mod_primes
+SIZES = [1, 2, 3, 5, 17, 31, 32, 33, 64, 100, 129, 200, 300]
+
+
+@pytest.mark.parametrize("n", SIZES)
+def test_det_mod_primes_both_paths_match_oracle(ctx, n):
+    _say("det_mod_primes n =", n)
+    A = synth.dense_uniform(n, -100, 100, 500 + n)
+    d = oracle.det_bareiss(A) if n <= 200 else oracle.det_bareiss_c(A)
+    ps23 = test_primes(1 << 22, 1 << 23, 6, n)
+    ps26 = test_primes(1 << 25, 1 << 26, 4, n)
+    r8 = ctx.det_mod_primes(A, ps23, "int8")
+    r64 = ctx.det_mod_primes(A, ps23, "fp64")
+    assert r8.tolist() == [d % p for p in ps23]
+    assert r64.tolist() == r8.tolist()
+    r26 = ctx.det_mod_primes(A, ps26, "fp64")
+    assert r26.tolist() == [d % p for p in ps26]
+
+
+def test_det_mod_primes_many_primes_one_launch(ctx):
+    n = 64
+    A = synth.dense_uniform(n, -100, 100, 0)
+    d = oracle.det_bareiss(A)
+    ps = test_primes(1 << 22, 1 << 23, 300, 1)
+    assert ctx.det_mod_primes(A, ps).tolist() == [d % p for p in ps]
+
+
+def test_det_mod_primes_edge_cases(ctx):
+    ps = test_primes(1 << 22, 1 << 23, 4, 2)
+    assert ctx.det_mod_primes(np.zeros((0, 0), dtype=np.int64), ps).tolist() == [1] * 4
+    # singular: every residue 0
+    S = synth.dense_uniform(70, -50, 50, 3)
+    S[40] = S[3] - 2 * S[7]
+    assert ctx.det_mod_primes(S, ps, "int8").tolist() == [0] * 4
+    assert ctx.det_mod_primes(S, ps, "fp64").tolist() == [0] * 4
+    # p | det: a Smith factor equal to the prime
+    p = ps[0]
+    A, sign = synth.smith_matrix([1] * 39 + [p], seed=4, density=0.2)
+    r = ctx.det_mod_primes(A, ps)
+    assert r[0] == 0 and r.tolist() == [(sign * p) % q for q in ps]
+    # pivoting: zero leading entries, anti-diagonal permutation, entries that vanish mod p
+    P = np.fliplr(np.eye(45, dtype=np.int64))
+    assert ctx.det_mod_primes(P, ps).tolist() == [oracle.det_bareiss(P) % q for q in ps]
+    B = synth.dense_uniform(90, -9, 9, 5)
+    B[:, 0] = 0
+    B[60, 0] = 3
+    B[:50, 1] *= p                     # zero mod p above the diagonal region of column 1
+    dB = oracle.det_bareiss(B)
+    for path in ("int8", "fp64"):
+        assert ctx.det_mod_primes(B, ps, path).tolist() == [dB % q for q in ps]
+
+
+def test_det_mod_primes_extreme_entries(ctx):
+    n = 40
+    A = synth.dense_uniform(n, -(2 ** 31) + 1, 2 ** 31 - 1, 6)
+    ps = test_primes(1 << 25, 1 << 26, 3, 6) + test_primes(1 << 22, 1 << 23, 3, 6)
+    d = oracle.det_bareiss(A)
+    assert ctx.det_mod_primes(A, ps, "fp64").tolist() == [d % p for p in ps]
+
+
+def test_det_mod_primes_rejects_bad_primes(ctx):
+    import paper_cs_0511066_amd as det
+    A = synth.dense_uniform(8, -5, 5, 7)
+    with pytest.raises(det.DetError) as e:
+        ctx.det_mod_primes(A, [15], "fp64")
+    assert e.value.status == 2
+    with pytest.raises(det.DetError) as e:
+        ctx.det_mod_primes(A, [(1 << 23) + 9], "int8")
+    assert e.value.status == 3
+    with pytest.raises(det.DetError) as e:
+        ctx.det_mod_primes(np.full((4, 4), 2 ** 31, dtype=np.int64), [8388593], "fp64")
+    assert e.value.status == 5
+
+
+def test_det_mod_primes_n1024_sampled(ctx):
+    """Full headline size: residues for a batch of primes, two checked one by
+    one with the oracle's modular elimination."""
+    A = synth.dense_uniform(1024, 0, 255, 1024)
+    ps = test_primes(1 << 22, 1 << 23, 16, 9)
+    r8 = ctx.det_mod_primes(A, ps, "int8")
+    r64 = ctx.det_mod_primes(A, ps, "fp64")
+    assert r8.tolist() == r64.tolist()
+    for j in (0, 11):
+        _say("oracle det_mod_p n=1024 prime", ps[j])
+        assert int(r8[j]) == oracle.det_mod_p(A, ps[j])
+
+
+def test_int8_equals_fp64_n2048_sampled(ctx):
+    """Precision workload shape: n = 2048, entries in [-2^10, 2^10], primes
+    near 2^23; int8 limbs against FP64, one residue against the oracle."""
+    A = synth.dense_uniform(2048, -1024, 1024, 2048)
+    ps = test_primes(1 << 22, 1 << 23, 4, 10)
+    r8 = ctx.det_mod_primes(A, ps, "int8")
+    r64 = ctx.det_mod_primes(A, ps, "fp64")
+    assert r8.tolist() == r64.tolist()
+    _say("oracle det_mod_p n=2048")
+    assert int(r8[2]) == oracle.det_mod_p(A, ps[2])
+
+
+def test_device_pointer_input(ctx):
+    torch = pytest.importorskip("torch")
+    A = synth.dense_uniform(150, -100, 100, 8)
+    ps = test_primes(1 << 22, 1 << 23, 5, 8)
+    At = torch.from_numpy(A).cuda()
+    assert ctx.det_mod_primes(At, ps).tolist() == ctx.det_mod_primes(A, ps).tolist()
+    # a strided view (leading dimension > n)
+    big = torch.zeros((150, 200), dtype=torch.int64, device="cuda")
+    big[:, :150] = At
+    assert ctx.det_mod_primes(big[:, :150], ps).tolist() == ctx.det_mod_primes(A, ps).tolist()
+
+
+# ---------------------------------------------------------------- dixon_lift
+@pytest.mark.parametrize("n,k", [(1, 5), (5, 8), (33, 6), (64, 45), (150, 7), (300, 3)])
+def test_dixon_lift_matches_oracle(ctx, n, k):
+    _say("dixon_lift n =", n)
+    A = synth.dense_uniform(n, -100, 100, 900 + n)
+    b = synth.random_rhs(n, 1000, n)
+    for p in test_primes(1 << 25, 1 << 26, 1, n) + test_primes(1 << 22, 1 << 23, 1, n):
+        X = ctx.dixon_lift(A, b, p, k)
+        ref = oracle.dixon_digits(A, b, p, k)
+        assert np.array_equal(X.astype(np.int64), ref)
+
+
+def test_dixon_lift_n1024_invariant(ctx):
+    """Full size: A x_i = r_i (mod p) and p | r_i - A x_i for the first steps,
+    checked with exact integers on the host (no inverse needed)."""
+    n = 1024
+    A = synth.dense_uniform(n, 0, 255, 1024)
+    b = synth.random_rhs(n, 12000, 3)
+    p = test_primes(1 << 25, 1 << 26, 1, 77)[0]
+    X = ctx.dixon_lift(A, b, p, 4).astype(np.int64)
+    r = b.astype(np.int64)
+    for i in range(4):
+        t = r - A @ X[i]               # |A x| < 2^10 2^8 2^26: exact in int64
+        assert np.all(t % p == 0)
+        r = t // p
+
+
+def test_dixon_lift_singular_mod_p(ctx):
+    import paper_cs_0511066_amd as det
+    p = test_primes(1 << 22, 1 << 23, 1, 12)[0]
+    A, _ = synth.smith_matrix([1] * 29 + [p], seed=12, density=0.3)
+    with pytest.raises(det.DetError) as e:
+        ctx.dixon_lift(A, np.ones(30, dtype=np.int64), p, 3)
+    assert e.value.status == 4
+
+
+# ---------------------------------------------------------------- det_introspective
+@pytest.mark.parametrize("seed", range(0, 100, 7))
+def test_det_introspective_plain_n64(ctx, seed):
+    """Plain workload at n = 64: entries uniform in [-100, 100]."""
+    A = synth.dense_uniform(64, -100, 100, seed)
+    d = oracle.det_bareiss(A)
+    assert ctx.det_introspective(A, seed=seed) == d
+    assert ctx.det_introspective(A, seed=seed, certify=True) == d
+
+
+def test_det_introspective_small_and_degenerate(ctx):
+    assert ctx.det_introspective(np.zeros((0, 0), dtype=np.int64)) == 1
+    assert ctx.det_introspective(np.array([[-7]])) == -7
+    assert ctx.det_introspective(np.array([[0]])) == 0
+    assert ctx.det_introspective(np.array([[1, 2], [3, 4]])) == -2
+    S = synth.dense_uniform(50, -100, 100, 13)
+    S[7] = S[8] + S[9]
+    assert ctx.det_introspective(S) == 0
+    assert ctx.det_introspective(S, certify=True) == 0
+    Z = np.zeros((10, 10), dtype=np.int64)
+    assert ctx.det_introspective(Z) == 0
+
+
+@pytest.mark.parametrize("n", [20, 60, 120])
+def test_det_introspective_table1_engineered(ctx, n):
+    """Smith form of diag(1..n): det = +-n!, s_n = lcm(1..n)."""
+    A, sign = synth.engineered_table1(n, seed=n)
+    d, rep = ctx.det_introspective(A, report=True)
+    assert d == sign * math.factorial(n)
+    assert math.lcm(*range(1, n + 1)) % (1 << 0) == 0 and rep["sn_bits"] >= 1
+
+
+def test_det_introspective_structured_serving_matrices(ctx):
+    for seed in range(3):
+        n = 80 + 40 * seed
+        A, sign, s = synth.structured_serving(n, seed)
+        d, rep = ctx.det_introspective(A, report=True, seed=seed)
+        assert d == sign * math.prod(s)
+        assert d == oracle.det_bareiss_c(A)
+
+
+@pytest.mark.parametrize("n,lo,hi", [(128, -128, 127), (200, -1000, 1000), (256, 0, 255)])
+def test_det_introspective_mid_sizes(ctx, n, lo, hi):
+    A = synth.dense_uniform(n, lo, hi, n)
+    d = oracle.det_bareiss_c(A)
+    got, rep = ctx.det_introspective(A, report=True)
+    assert got == d
+    _say("n", n, "report", rep)
+
+
+def _golden(name):
+    path = os.path.join(ROOT, "tests", "golden", name + ".json")
+    if not os.path.exists(path):
+        pytest.skip(f"golden {name} not generated")
+    return json.load(open(path))
+
+
+def test_det_introspective_golden_n512(ctx):
+    g = _golden("dense_n512_s128_seed3")
+    A = synth.dense_uniform(g["n"], g["lo"], g["hi"], g["seed"])
+    assert ctx.det_introspective(A) == int(g["det_hex"], 16)
+
+
+def test_det_introspective_golden_n1024(ctx):
+    """The plain headline workload: n = 1024, entries uniform in [0, 255]."""
+    g = _golden("dense_n1024_u0_255_seed1024")
+    A = synth.dense_uniform(g["n"], g["lo"], g["hi"], g["seed"])
+    d = int(g["det_hex"], 16)
+    got, rep = ctx.det_introspective(A, report=True)
+    _say("n1024 report", rep)
+    assert got == d
+    torch = pytest.importorskip("torch")
+    assert ctx.det_introspective(torch.from_numpy(A).cuda()) == d

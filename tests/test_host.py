@@ -1,0 +1,163 @@
+"""CPU tests of the library's host side (no GPU needed): the shared library
+loads and exports every function the headers declare, and the host steps of
+the method agree with the oracle and with Python integers."""
+import math
+import os
+import random
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from conftest import ROOT, test_primes
+
+det = pytest.importorskip("paper_cs_0511066_amd")
+
+
+def _declared_functions():
+    names = []
+    for h in ("det.h", "det_host.h"):
+        src = open(os.path.join(ROOT, "include", h)).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        names += re.findall(r"\b(det_[a-z0-9_]+|dixon_lift)\s*\(", src)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    names = _declared_functions()
+    assert "det_mod_primes" in names and "dixon_lift" in names and "det_introspective" in names
+    for name in names:
+        assert hasattr(det._lib, name), name
+    assert set(names) == set(det.EXPORTED)
+
+
+def test_status_strings():
+    assert det._lib.det_status_str(0) == b"DET_OK"
+    assert det._lib.det_status_str(4) == b"DET_E_SINGULAR_MOD_P"
+
+
+def test_is_prime_matches_sympy():
+    sympy = pytest.importorskip("sympy")
+    rng = random.Random(1)
+    cases = list(range(0, 3000)) + [rng.randrange(1 << 20, 1 << 32) for _ in range(3000)]
+    cases += [4294967291, 4294967295, 2147483647, 25326001, 3215031751, 4759123141 % (1 << 32)]
+    for q in cases:
+        assert det.det_host_is_prime(q) == bool(sympy.isprime(q)), q
+
+
+@pytest.mark.parametrize("bits", [12, 23, 26])
+def test_sample_primes(bits):
+    ps = det.det_host_sample_primes(42, bits, 200)
+    assert len(set(ps.tolist())) == 200
+    lo, hi = 1 << (bits - 1), 1 << bits
+    assert all(lo < p < hi and oracle.is_prime(int(p)) for p in ps)
+    assert np.array_equal(ps, det.det_host_sample_primes(42, bits, 200))
+    assert not np.array_equal(ps, det.det_host_sample_primes(43, bits, 200))
+
+
+def test_bigint_against_python_ints():
+    rng = random.Random(7)
+    vals = [0, 1, -1, 2 ** 64, -(2 ** 64) + 1, 2 ** 127 - 1, 3 ** 200, -(7 ** 150)]
+    vals += [rng.randrange(-(1 << 4000), 1 << 4000) for _ in range(30)]
+    vals += [rng.randrange(-(1 << 200), 1 << 200) for _ in range(30)]
+    for a in vals:
+        for b in rng.sample(vals, 8):
+            assert det.det_host_bigint("add", a, b) == a + b
+            assert det.det_host_bigint("sub", a, b) == a - b
+            assert det.det_host_bigint("mul", a, b) == a * b
+            if b > 0:
+                assert det.det_host_bigint("floordiv", a, b) == a // b
+                assert det.det_host_bigint("mod", a, b) == a % b
+            assert det.det_host_bigint("gcd", a, b) == math.gcd(a, b)
+
+
+def test_bigint_karatsuba_sizes():
+    rng = random.Random(8)
+    for bits in (3000, 3100, 6400, 20000, 65000):
+        a = rng.getrandbits(bits) | 1
+        b = -rng.getrandbits(bits - 17)
+        assert det.det_host_bigint("mul", a, b) == a * b
+
+
+def test_bigint_division_edge_cases():
+    # quotient digit estimates that need the add-back step of long division
+    for a, b in [((1 << 192) - 1, (1 << 128) - 1), (1 << 256, (1 << 128) + 1),
+                 ((1 << 255) + (1 << 191), (1 << 127) + 1), (2 ** 400 - 2 ** 300, 2 ** 200 - 1)]:
+        assert det.det_host_bigint("floordiv", a, b) == a // b
+        assert det.det_host_bigint("mod", a, b) == a % b
+        assert det.det_host_bigint("floordiv", -a, b) == -a // b
+
+
+def test_crt_matches_oracle():
+    rng = random.Random(3)
+    for count in (1, 2, 5, 40):
+        ps = test_primes(1 << 22, 1 << 26, count, count)
+        rs = [rng.randrange(p) for p in ps]
+        r, _ = det.det_host_crt(rs, ps)
+        assert r == oracle.crt_symmetric(rs, ps)[0]
+
+
+def test_crt_same_run_counts_unchanged_primes():
+    ps = test_primes(1 << 22, 1 << 23, 10, 5)
+    target = -987654321987
+    rs = [target % p for p in ps]
+    r, same = det.det_host_crt(rs, ps)
+    assert r == target
+    # target needs 2 primes (|target| < 2^40 < p0 p1 / 2), the other 8 leave it unchanged
+    assert same == 8
+    out = oracle.et_cra(rs, ps, 4000, k=8)
+    assert out == (target, 10, True)
+
+
+def test_ratrecon_matches_oracle():
+    rng = random.Random(11)
+    p = 33554393
+    for k in (3, 10, 40):
+        m = p ** k
+        half = (m.bit_length() - 2) // 2
+        for _ in range(20):
+            d = rng.randrange(1, 1 << half)
+            a = rng.randrange(-(1 << half), 1 << half)
+            g = math.gcd(a, d)
+            a, d = a // g, d // g
+            u = a * pow(d, -1, m) % m
+            got = det.det_host_ratrecon(u, m, half, half)
+            assert got == (a, d)
+            assert got == oracle.rational_reconstruct(u, m, 1 << half, 1 << half)
+
+
+def test_ratrecon_rejects_when_out_of_bounds():
+    m = 10007 ** 2
+    u = 123456 * pow(654321, -1, m) % m
+    got = det.det_host_ratrecon(u, m, 5, 5)
+    ref = oracle.rational_reconstruct(u, m, 32, 32)
+    assert got == ref
+
+
+def test_hadamard_log2_upper_bound():
+    for n, lo, hi, seed in ((10, -100, 100, 1), (64, -100, 100, 2), (50, 0, 255, 3)):
+        A = synth.dense_uniform(n, lo, hi, seed)
+        h = det.det_host_hadamard_log2(A)
+        exact = 0.5 * math.log2(oracle.hadamard_sq(A))
+        assert exact <= h <= exact + 1e-5
+        assert abs(oracle.det_bareiss(A)).bit_length() - 1 <= h
+
+
+def test_et_run_length_matches_lemma():
+    for eps, bits, L in ((64, 23, 568.0), (64, 23, 3.0), (20, 16, 30.0)):
+        P = (1 << (bits - 1)) / math.log(1 << bits)
+        assert det.det_host_et_run_length(eps, bits, L) == oracle.et_k(eps, P, math.ceil(L)) or \
+            det.det_host_et_run_length(eps, bits, L) >= oracle.et_k(eps, P, math.ceil(L))
+        k = det.det_host_et_run_length(eps, bits, L)
+        assert (L / (P - math.ceil(L))) ** k <= 2.0 ** -eps * (1 + 1e-9)
+
+
+def test_context_without_gpu_reports_device_error():
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(det.DetError) as e:
+        det.Context(0)
+    assert e.value.status == 8
