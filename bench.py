@@ -20,8 +20,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0            # MI355X HBM3E
 PEAK_TOPS = {"gemm_f64": 78.6, "gemm_i8": 5000.0}   # dense MFMA: fp64, int8 (TOP/s)
-KERNELS = ["lift_x", "lift_r", "gemm_f64", "gemm_i8", "panel", "trsm", "tri_inv", "residues"]
-BOUND = {"lift_x": "hbm", "lift_r": "hbm", "residues": "hbm", "gemm_f64": "mfma",
+KERNELS = ["lift", "lift_x", "lift_r", "gemm_f64", "gemm_i8", "panel", "trsm", "tri_inv",
+           "residues"]
+BOUND = {"lift": "hbm", "lift_x": "hbm", "lift_r": "hbm", "residues": "hbm", "gemm_f64": "mfma",
          "gemm_i8": "mfma", "panel": "alu", "trsm": "mfma", "tri_inv": "alu"}
 
 

@@ -161,7 +161,8 @@ typedef enum {
   DET_KERNEL_PANEL = 5,      /* panel factorisation                     */
   DET_KERNEL_TRSM = 6,       /* in-place triangular apply               */
   DET_KERNEL_TRI_INV = 7,    /* diagonal-block triangular inverse       */
-  DET_KERNEL_RESIDUES = 8    /* A mod p for a batch of primes           */
+  DET_KERNEL_RESIDUES = 8,   /* A mod p for a batch of primes           */
+  DET_KERNEL_LIFT = 9        /* all lifting steps in one cooperative launch */
 } det_kernel;
 
 det_status det_profile_select(det_ctx *ctx, det_kernel kind);

@@ -45,11 +45,13 @@ det_status det_host_crt(const uint32_t *residues, const uint32_t *primes, int64_
 
 /* Rational reconstruction: a/d with a = u d (mod m), |a| <= 2^Nbits,
  * 0 < d <= 2^Dbits, gcd(a, d) = 1 (u, m > 0 given as magnitudes).
+ * prime_base: 0 for a general m; a prime q when m is a power of q (then the
+ * coprimality test is q not dividing d, as in the p-adic lifting).
  * DET_E_INVALID when no such fraction exists. */
 det_status det_host_ratrecon(const uint32_t *u, int64_t ulen, const uint32_t *m, int64_t mlen,
-                             int64_t Nbits, int64_t Dbits, int *a_sign, uint32_t *a_mag,
-                             int64_t a_cap, int64_t *a_len, uint32_t *d_mag, int64_t d_cap,
-                             int64_t *d_len);
+                             int64_t Nbits, int64_t Dbits, uint64_t prime_base, int *a_sign,
+                             uint32_t *a_mag, int64_t a_cap, int64_t *a_len, uint32_t *d_mag,
+                             int64_t d_cap, int64_t *d_len);
 
 /* Big-integer arithmetic of the reconstruction steps: op 0 a+b, 1 a-b,
  * 2 a*b, 3 floor(a/b), 4 a mod b (b > 0, result in [0, b)), 5 gcd(|a|,|b|). */

@@ -89,8 +89,8 @@ _sig("det_host_sample_primes", c_int, [c_u64, c_int, c_i64, P(c_u32)])
 _sig("det_host_hadamard_log2", c_double, [P(c_i64), c_i64, c_i64])
 _sig("det_host_et_run_length", c_i64, [c_double, c_int, c_double])
 _sig("det_host_crt", c_int, [P(c_u32), P(c_u32), c_i64, P(c_int), P(c_u32), c_i64, P(c_i64), P(c_i64)])
-_sig("det_host_ratrecon", c_int, [P(c_u32), c_i64, P(c_u32), c_i64, c_i64, c_i64, P(c_int), P(c_u32),
-                                  c_i64, P(c_i64), P(c_u32), c_i64, P(c_i64)])
+_sig("det_host_ratrecon", c_int, [P(c_u32), c_i64, P(c_u32), c_i64, c_i64, c_i64, c_u64, P(c_int),
+                                  P(c_u32), c_i64, P(c_i64), P(c_u32), c_i64, P(c_i64)])
 _sig("det_host_bigint", c_int, [c_int, c_int, P(c_u32), c_i64, c_int, P(c_u32), c_i64, P(c_int),
                                 P(c_u32), c_i64, P(c_i64)])
 
@@ -178,7 +178,7 @@ class Context:
             raise DetError(st, _lib.det_last_error(self._h).decode())
 
     KERNELS = {"none": 0, "lift_x": 1, "lift_r": 2, "gemm_f64": 3, "gemm_i8": 4, "panel": 5,
-               "trsm": 6, "tri_inv": 7, "residues": 8}
+               "trsm": 6, "tri_inv": 7, "residues": 8, "lift": 9}
 
     def profile_select(self, kernel: str):
         """Time every launch of one kernel class with HIP events (det_profile_select)."""
@@ -315,13 +315,14 @@ def det_host_crt(residues, primes):
     return _from_limbs(sign.value, mag[:ln.value]), int(same.value)
 
 
-def det_host_ratrecon(u: int, m: int, Nbits: int, Dbits: int):
-    """(a, d) with a = u d mod m, |a| <= 2^Nbits, 0 < d <= 2^Dbits, or None."""
+def det_host_ratrecon(u: int, m: int, Nbits: int, Dbits: int, prime_base: int = 0):
+    """(a, d) with a = u d mod m, |a| <= 2^Nbits, 0 < d <= 2^Dbits, or None
+    (prime_base: q when m is a power of the prime q, else 0)."""
     ul, ml = _to_limbs(u % m), _to_limbs(m)
     cap = len(ml) + 4
     am, dm = np.zeros(cap, dtype=np.uint32), np.zeros(cap, dtype=np.uint32)
     asg, al, dl = c_int(0), c_i64(0), c_i64(0)
-    st = _lib.det_host_ratrecon(_u32p(ul), len(ul), _u32p(ml), len(ml), Nbits, Dbits,
+    st = _lib.det_host_ratrecon(_u32p(ul), len(ul), _u32p(ml), len(ml), Nbits, Dbits, prime_base,
                                 ctypes.byref(asg), _u32p(am), cap, ctypes.byref(al), _u32p(dm), cap,
                                 ctypes.byref(dl))
     if st == 1:

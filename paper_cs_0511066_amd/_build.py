@@ -19,6 +19,8 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          # packed FP32 instructions stay off (see DESIGN notes on gfx950 hazards)
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # let "#pragma unroll" fully unroll the register-resident panel loops
+         "-mllvm", "-pragma-unroll-threshold=1000000",
          "-Wall", "-Wno-unused-result"]
 
 

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -30,14 +31,25 @@ struct DevBuf {
   size_t cap = 0;
 };
 
-constexpr int NB_OUTER = 128;      // outer block (trailing-update depth K)
+constexpr int NB_OUTER = 128;      // outer block (trailing-update depth K) of large batches
 constexpr int TINV_LD = 128;       // leading dimension of the outer triangular inverses
 constexpr int MAX_N = 4096;
+// Batches below this size use single-level blocking (block = panel, so the
+// panel's own L11^{-1} serves the triangular solve); larger batches use outer
+// blocks of NB_OUTER columns so that the trailing update contracts over 128.
+constexpr int TWO_LEVEL_MIN_ITEMS = 64;
 
 double now_ms() {
   using namespace std::chrono;
   return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
 }
+
+// Device workspace of one batched LU, bound to one stream.
+struct LuWs {
+  DevBuf W, piv, flags, mods, linv, uinv, tinv, limbA, limbB, res;
+  std::vector<Modulus> hmods;   // host copy of the moduli; kept alive for async uploads
+  hipStream_t st = nullptr;
+};
 
 }  // namespace
 
@@ -45,11 +57,16 @@ struct det_ctx {
   int device = 0;
   size_t budget = 0;
   size_t held = 0;
-  hipStream_t own = nullptr;
-  hipStream_t st = nullptr;
+  hipStream_t own = nullptr;     // the context's stream (default for ws[0])
+  hipStream_t own2 = nullptr;    // second stream: CRA batches beside the Dixon solve
+  hipStream_t st = nullptr;      // current stream of ws[0] (own or the caller's)
+  hipEvent_t ev = nullptr;       // orders own2 after work queued on st
   std::string err;
-  DevBuf W, piv, flags, mods, linv, tinv, limbA, limbB, res, Adev, norms, amax;
-  DevBuf Cu, Ai, r, rp, x, digits, comb, cvec;
+  LuWs ws[2];
+  DevBuf Adev, norms, amax, Cu, Ai, r, rp, x, digits, comb, cvec, sync, C1, E, rp1, x1;
+  uint32_t* hres = nullptr;      // pinned host residues of the background batch
+  size_t hres_cap = 0;
+  int lift_mode = 0;             // 0: register-resident cooperative kernel when possible
   // kernel timing (det_profile_select / det_profile_read)
   int prof_kind = 0;
   int64_t prof_launches = 0;
@@ -72,13 +89,19 @@ det_status fail(det_ctx* c, det_status s, const std::string& msg) {
       return fail(c, DET_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
-// Grow-only device buffer; the previous contents are not kept.
-det_status ensure(det_ctx* c, DevBuf& b, size_t bytes) {
+#define TRY(expr)                     \
+  do {                                \
+    det_status s_ = (expr);           \
+    if (s_ != DET_OK) return s_;      \
+  } while (0)
+
+// Grow-only device buffer used on stream `st`; the previous contents are not kept.
+det_status ensure(det_ctx* c, DevBuf& b, size_t bytes, hipStream_t st) {
   if (bytes == 0) bytes = 16;
   if (b.cap >= bytes) return DET_OK;
   if (c->budget && c->held - b.cap + bytes > c->budget)
     return fail(c, DET_E_NOMEM, "device workspace would exceed the context's HBM budget");
-  HIPCHK(hipStreamSynchronize(c->st));
+  HIPCHK(hipStreamSynchronize(st));
   if (b.p) {
     HIPCHK(hipFree(b.p));
     c->held -= b.cap;
@@ -96,22 +119,20 @@ det_status ensure(det_ctx* c, DevBuf& b, size_t bytes) {
   return DET_OK;
 }
 
-#define TRY(expr)                     \
-  do {                                \
-    det_status s_ = (expr);           \
-    if (s_ != DET_OK) return s_;      \
-  } while (0)
+det_status ensure(det_ctx* c, DevBuf& b, size_t bytes) { return ensure(c, b, bytes, c->st); }
 
-// Brackets one launch with HIP events when its kernel class is the selected
-// one; the counts are the launcher's algorithmic bytes and operations.
+// Brackets one launch with HIP events on its stream when its kernel class is
+// the selected one; the counts are the launcher's algorithmic bytes and ops.
 struct ProfScope {
   det_ctx* c;
+  hipStream_t st;
   hipEvent_t e1 = nullptr;
-  ProfScope(det_ctx* ctx, int kind, double bytes, double ops) : c(ctx) {
+  ProfScope(det_ctx* ctx, int kind, double bytes, double ops, hipStream_t stream)
+      : c(ctx), st(stream) {
     if (c->prof_kind != kind) return;
     hipEvent_t e0 = take(), e = take();
     if (!e0 || !e) return;
-    if (hipEventRecord(e0, c->st) != hipSuccess) return;
+    if (hipEventRecord(e0, st) != hipSuccess) return;
     e1 = e;
     c->prof_pending.push_back({e0, e1});
     c->prof_launches++;
@@ -119,7 +140,7 @@ struct ProfScope {
     c->prof_ops += ops;
   }
   ~ProfScope() {
-    if (e1) (void)hipEventRecord(e1, c->st);
+    if (e1) (void)hipEventRecord(e1, st);
   }
   hipEvent_t take() {
     if (!c->ev_pool.empty()) {
@@ -157,131 +178,168 @@ Modulus modulus_of(uint32_t p) {
   return m;
 }
 
+int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+// Length of the zero-padded lifting vectors: the register-resident kernel
+// reads 64 EPL entries (EPL = 4, 8, 16 for n <= 256, 512, 1024).
+int64_t lift_pad(int64_t n) {
+  if (n <= 256) return 256;
+  if (n <= 512) return 512;
+  if (n <= 1024) return 1024;
+  return round_up(n, 64);
+}
+
 // ------------------------------------------------------------------ LU driver
 struct LuJob {
   int n = 0;          // rows (and columns of A)
   int ncols = 0;      // n, or 2n for [A | I]
   int nitems = 0;     // batch items (one prime each)
   int64_t ldw = 0, slab = 0;
-  bool int8 = false;
+  bool int8 = false;  // trailing update on int8 limbs
   uint32_t pmax = 0;
 };
 
-int panel_width(int n) { return n <= 2048 ? 32 : 16; }
+// Panels of one LU: first row, width, template width (ld of its inverses).
+struct Panel {
+  int j0, pb, pbw;
+};
+
+det_status gemm_update(det_ctx* c, LuWs& w, const LuJob& J, int64_t offC, int64_t offA,
+                       int64_t offB, int M, int N, int K, int kc4, bool use_i8) {
+  const int nit = J.nitems;
+  const Modulus* mods = (const Modulus*)w.mods.p;
+  int32_t* W = (int32_t*)w.W.p;
+  if (M <= 0 || N <= 0 || K <= 0) return DET_OK;
+  if (use_i8) {
+    const int Kp = (int)((K + 63) / 64 * 64);
+    const int64_t pslabA = 3LL * M * Kp, pslabB = 3LL * N * Kp;
+    TRY(ensure(c, w.limbA, (size_t)nit * pslabA, w.st));
+    TRY(ensure(c, w.limbB, (size_t)nit * pslabB, w.st));
+    HIPCHK(detk::launch_split(W, J.slab, offA, J.ldw, M, K, Kp, 0, (int8_t*)w.limbA.p, pslabA, nit,
+                              w.st));
+    HIPCHK(detk::launch_split(W, J.slab, offB, J.ldw, N, K, Kp, 1, (int8_t*)w.limbB.p, pslabB, nit,
+                              w.st));
+    ProfScope ps(c, DET_KERNEL_GEMM_I8, (3.0 * Kp * ((double)M + N) + 8.0 * M * N) * nit,
+                 18.0 * M * N * K * nit, w.st);
+    HIPCHK(detk::launch_gemm_i8(W, J.slab, offC, J.ldw, M, N, (const int8_t*)w.limbA.p,
+                                (const int8_t*)w.limbB.p, pslabA, pslabB, Kp, mods, nit, w.st));
+  } else {
+    ProfScope ps(c, DET_KERNEL_GEMM_F64,
+                 4.0 * ((double)M * K + (double)K * N + 2.0 * M * N) * nit, 2.0 * M * N * K * nit,
+                 w.st);
+    HIPCHK(detk::launch_gemm_f64(W, J.slab, offC, offA, offB, J.ldw, M, N, K, mods, kc4, nit,
+                                 w.st));
+  }
+  return DET_OK;
+}
+
+det_status panel_step(det_ctx* c, LuWs& w, const LuJob& J, const Panel& P, int32_t* uinv, int kc) {
+  const double m = J.n - P.j0;
+  ProfScope ps(c, DET_KERNEL_PANEL, 8.0 * m * P.pb * J.nitems, m * P.pb * P.pb * (double)J.nitems,
+               w.st);
+  HIPCHK(detk::launch_panel((int32_t*)w.W.p, J.ldw, J.slab, J.n, P.j0, P.pb, P.pbw,
+                            (const Modulus*)w.mods.p, (int32_t*)w.piv.p, J.n,
+                            (int32_t*)w.flags.p, (int32_t*)w.linv.p, uinv, kc, J.nitems, w.st));
+  return DET_OK;
+}
+
+// In-place X <- T X on rows [r0, r0+kb) x columns [c0, c0+N); with sw_pb > 0
+// the panel's row swaps are applied to those columns first.
+det_status trsm_step(det_ctx* c, LuWs& w, const LuJob& J, int r0, int kb, int c0, int N,
+                     const int32_t* T, int ldt, int kc4, int sw_j0, int sw_pb) {
+  if (kb <= 0 || N <= 0) return DET_OK;
+  ProfScope ps(c, DET_KERNEL_TRSM, (8.0 * kb * N + 4.0 * kb * kb) * J.nitems,
+               2.0 * kb * kb * N * J.nitems, w.st);
+  HIPCHK(detk::launch_trsm_apply((int32_t*)w.W.p, J.slab, J.ldw, r0, kb, c0, N, T, ldt,
+                                 (const Modulus*)w.mods.p, kc4, (const int32_t*)w.piv.p, J.n,
+                                 sw_j0, sw_pb, J.nitems, w.st));
+  return DET_OK;
+}
 
 // Blocked right-looking LU of every item (see lu_kernels.hip for the data
-// layout).  W, piv, flags, mods must already hold the residues and moduli.
-det_status lu_factor(det_ctx* c, const LuJob& J) {
+// layout).  W, piv, flags, mods of `w` must already hold residues and moduli.
+// With keep_uinv (single item, single-level) the inverse of every panel's U11
+// is kept in w.uinv for the back substitution; `panels` lists the panels.
+det_status lu_factor(det_ctx* c, LuWs& w, const LuJob& J, bool keep_uinv,
+                     std::vector<Panel>* panels) {
   const int n = J.n, ncols = J.ncols, nit = J.nitems;
-  const int64_t ldw = J.ldw, slab = J.slab;
-  const int PB = panel_width(n);
+  const int64_t ldw = J.ldw;
   const int kc = exact_chunk(J.pmax);
   const int kc4 = std::max(1, kc / 4);
-  int32_t* W = (int32_t*)c->W.p;
-  int32_t* piv = (int32_t*)c->piv.p;
-  int32_t* flags = (int32_t*)c->flags.p;
-  const Modulus* mods = (const Modulus*)c->mods.p;
-  TRY(ensure(c, c->linv, (size_t)nit * PB * PB * sizeof(int32_t)));
-  TRY(ensure(c, c->tinv, (size_t)nit * TINV_LD * TINV_LD * sizeof(int32_t)));
-  int32_t* linv = (int32_t*)c->linv.p;
-  int32_t* tinv = (int32_t*)c->tinv.p;
-  int Kp = 0;
-  int64_t pslabA = 0, pslabB = 0;
-  if (J.int8) {
-    Kp = NB_OUTER;                                  // multiple of 64
-    pslabA = 3LL * n * Kp;
-    pslabB = 3LL * ncols * Kp;
-    TRY(ensure(c, c->limbA, (size_t)nit * pslabA));
-    TRY(ensure(c, c->limbB, (size_t)nit * pslabB));
+  const bool two_level = nit >= TWO_LEVEL_MIN_ITEMS;
+  const int npan_max = n / 8 + 2;    // panels are at least 8 wide (the last may be narrower)
+  if (keep_uinv && nit != 1) return fail(c, DET_E_INVALID, "U11 inverses need one item");
+  TRY(ensure(c, w.linv, (size_t)nit * 32 * 32 * sizeof(int32_t), w.st));
+  if (keep_uinv) TRY(ensure(c, w.uinv, (size_t)npan_max * 32 * 32 * sizeof(int32_t), w.st));
+  const int32_t* linv = (const int32_t*)w.linv.p;
+  if (panels) panels->clear();
+  if (!two_level) {
+    int idx = 0;
+    for (int j0 = 0; j0 < n; idx++) {
+      const int pbw = detk::panel_width_for(n - j0);
+      const int pb = std::min(pbw, n - j0);
+      const Panel P{j0, pb, pbw};
+      if (keep_uinv && idx >= npan_max) return fail(c, DET_E_INVALID, "panel count overflow");
+      int32_t* uinv = keep_uinv ? (int32_t*)w.uinv.p + (size_t)idx * 32 * 32 : nullptr;
+      TRY(panel_step(c, w, J, P, uinv, kc));
+      if (panels) panels->push_back(P);
+      const int right = ncols - (j0 + pb);
+      TRY(trsm_step(c, w, J, j0, pb, j0 + pb, right, linv, pbw, kc4, j0, pb));
+      TRY(gemm_update(c, w, J, (int64_t)(j0 + pb) * ldw + j0 + pb, (int64_t)(j0 + pb) * ldw + j0,
+                      (int64_t)j0 * ldw + j0 + pb, n - (j0 + pb), right, pb, kc4, J.int8));
+      j0 += pb;
+    }
+    return DET_OK;
   }
-  hipStream_t st = c->st;
+  TRY(ensure(c, w.tinv, (size_t)nit * TINV_LD * TINV_LD * sizeof(int32_t), w.st));
+  int32_t* tinv = (int32_t*)w.tinv.p;
   for (int k0 = 0; k0 < n; k0 += NB_OUTER) {
     const int kb = std::min(NB_OUTER, n - k0);
-    for (int j0 = k0; j0 < k0 + kb; j0 += PB) {
-      const int pb = std::min(PB, k0 + kb - j0);
-      {
-        const double m = n - j0;
-        ProfScope ps(c, DET_KERNEL_PANEL, 8.0 * m * pb * nit, m * pb * pb * (double)nit);
-        HIPCHK(detk::launch_panel(W, ldw, slab, n, j0, pb, PB, mods, piv, n, flags, linv, nit, st));
-      }
-      HIPCHK(detk::launch_swaps(W, ldw, slab, j0, pb, piv, n, k0, j0, j0 + pb, ncols, nit, st));
+    for (int j0 = k0; j0 < k0 + kb;) {
+      const int pbw = detk::panel_width_for(n - j0);
+      const int pb = std::min(pbw, k0 + kb - j0);
+      TRY(panel_step(c, w, J, Panel{j0, pb, pbw}, nullptr, kc));
+      HIPCHK(detk::launch_swaps((int32_t*)w.W.p, ldw, J.slab, j0, pb, (const int32_t*)w.piv.p, n,
+                                k0, j0, j0 + pb, ncols, nit, w.st));
       const int rest = k0 + kb - (j0 + pb);
       if (rest > 0) {
-        {
-          ProfScope ps(c, DET_KERNEL_TRSM, (8.0 * pb * rest + 4.0 * pb * pb) * nit,
-                       2.0 * pb * pb * rest * nit);
-          HIPCHK(detk::launch_trsm_apply(W, slab, ldw, j0, pb, j0 + pb, rest, linv, PB, mods, kc4,
-                                         nit, st));
-        }
-        {
-          const double M = n - (j0 + pb);
-          ProfScope ps(c, DET_KERNEL_GEMM_F64, 4.0 * (M * pb + pb * rest + 2.0 * M * rest) * nit,
-                       2.0 * M * rest * pb * nit);
-          HIPCHK(detk::launch_gemm_f64(W, slab, (int64_t)(j0 + pb) * ldw + j0 + pb,
-                                       (int64_t)(j0 + pb) * ldw + j0, (int64_t)j0 * ldw + j0 + pb,
-                                       ldw, n - (j0 + pb), rest, pb, mods, kc4, nit, st));
-        }
+        TRY(trsm_step(c, w, J, j0, pb, j0 + pb, rest, linv, pbw, kc4, 0, 0));
+        TRY(gemm_update(c, w, J, (int64_t)(j0 + pb) * ldw + j0 + pb,
+                        (int64_t)(j0 + pb) * ldw + j0, (int64_t)j0 * ldw + j0 + pb, n - (j0 + pb),
+                        rest, pb, kc4, false));
       }
+      j0 += pb;
     }
     const int right = ncols - (k0 + kb);
     if (right <= 0) continue;
     {
-      ProfScope ps(c, DET_KERNEL_TRI_INV, 8.0 * kb * kb * nit, (double)kb * kb * kb / 3.0 * nit);
-      HIPCHK(detk::launch_tri_inv(W, ldw, slab, k0, kb, 0, mods, tinv, TINV_LD, kc, nit, st));
+      ProfScope ps(c, DET_KERNEL_TRI_INV, 8.0 * kb * kb * nit, (double)kb * kb * kb / 3.0 * nit,
+                   w.st);
+      HIPCHK(detk::launch_tri_inv((const int32_t*)w.W.p, ldw, J.slab, k0, kb,
+                                  (const Modulus*)w.mods.p, tinv, TINV_LD, nit, w.st));
     }
-    {
-      ProfScope ps(c, DET_KERNEL_TRSM, (8.0 * kb * right + 4.0 * kb * kb) * nit,
-                   2.0 * kb * kb * right * nit);
-      HIPCHK(detk::launch_trsm_apply(W, slab, ldw, k0, kb, k0 + kb, right, tinv, TINV_LD, mods,
-                                     kc4, nit, st));
-    }
-    const int M = n - (k0 + kb);
-    if (M <= 0) continue;
-    const int64_t offC = (int64_t)(k0 + kb) * ldw + k0 + kb;
-    const int64_t offA = (int64_t)(k0 + kb) * ldw + k0;
-    const int64_t offB = (int64_t)k0 * ldw + k0 + kb;
-    if (J.int8) {
-      HIPCHK(detk::launch_split(W, slab, offA, ldw, M, kb, Kp, 0, (int8_t*)c->limbA.p, pslabA, nit,
-                                st));
-      HIPCHK(detk::launch_split(W, slab, offB, ldw, right, kb, Kp, 1, (int8_t*)c->limbB.p, pslabB,
-                                nit, st));
-      ProfScope ps(c, DET_KERNEL_GEMM_I8,
-                   (3.0 * Kp * (M + right) + 8.0 * M * right) * nit,
-                   18.0 * M * right * kb * nit);
-      HIPCHK(detk::launch_gemm_i8(W, slab, offC, ldw, M, right, (const int8_t*)c->limbA.p,
-                                  (const int8_t*)c->limbB.p, pslabA, pslabB, Kp, mods, nit, st));
-    } else {
-      ProfScope ps(c, DET_KERNEL_GEMM_F64, 4.0 * ((double)M * kb + (double)kb * right + 2.0 * M * right) * nit,
-                   2.0 * M * right * kb * nit);
-      HIPCHK(detk::launch_gemm_f64(W, slab, offC, offA, offB, ldw, M, right, kb, mods, kc4, nit,
-                                   st));
-    }
+    TRY(trsm_step(c, w, J, k0, kb, k0 + kb, right, tinv, TINV_LD, kc4, 0, 0));
+    TRY(gemm_update(c, w, J, (int64_t)(k0 + kb) * ldw + k0 + kb, (int64_t)(k0 + kb) * ldw + k0,
+                    (int64_t)k0 * ldw + k0 + kb, n - (k0 + kb), right, kb, kc4, J.int8));
   }
   return DET_OK;
 }
 
-// Back substitution U X = Y on [U | Y] (one item): X = U^{-1} Y = A^{-1} mod p.
-det_status back_substitute(det_ctx* c, const LuJob& J) {
+// Back substitution U X = Y on [U | Y] (one item, after a single-level
+// lu_factor with keep_uinv): X = U^{-1} Y = A^{-1} mod p, panel by panel
+// from the bottom: X_blk = U11^{-1} Y_blk, then Y_above -= U_above,blk X_blk.
+det_status back_substitute(det_ctx* c, LuWs& w, const LuJob& J, const std::vector<Panel>& panels) {
   const int n = J.n;
-  const int kc = exact_chunk(J.pmax);
-  const int kc4 = std::max(1, kc / 4);
-  int32_t* W = (int32_t*)c->W.p;
-  const Modulus* mods = (const Modulus*)c->mods.p;
-  int32_t* tinv = (int32_t*)c->tinv.p;
-  const int nblk = (n + NB_OUTER - 1) / NB_OUTER;
-  for (int bi = nblk - 1; bi >= 0; bi--) {
-    const int k0 = bi * NB_OUTER, kb = std::min(NB_OUTER, n - k0);
-    HIPCHK(detk::launch_tri_inv(W, J.ldw, J.slab, k0, kb, 1, mods, tinv, TINV_LD, kc, 1, c->st));
-    HIPCHK(detk::launch_trsm_apply(W, J.slab, J.ldw, k0, kb, n, n, tinv, TINV_LD, mods, kc4, 1,
-                                   c->st));
-    if (k0 > 0)
-      HIPCHK(detk::launch_gemm_f64(W, J.slab, n, k0, (int64_t)k0 * J.ldw + n, J.ldw, k0, n, kb,
-                                   mods, kc4, 1, c->st));
+  const int kc4 = std::max(1, exact_chunk(J.pmax) / 4);
+  for (int idx = (int)panels.size() - 1; idx >= 0; idx--) {
+    const Panel& P = panels[idx];
+    const int32_t* uinv = (const int32_t*)w.uinv.p + (size_t)idx * 32 * 32;
+    TRY(trsm_step(c, w, J, P.j0, P.pb, n, n, uinv, P.pbw, kc4, 0, 0));
+    if (P.j0 > 0)
+      TRY(gemm_update(c, w, J, n, P.j0, (int64_t)P.j0 * J.ldw + n, P.j0, n, P.pb, kc4, false));
   }
   return DET_OK;
 }
-
-int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
 // Validates A and returns a device pointer to it (uploading host memory into
 // the context's A buffer) with its leading dimension.
@@ -330,10 +388,22 @@ det_status matrix_bounds(det_ctx* c, const int64_t* A, int64_t lda, bool on_devi
   return DET_OK;
 }
 
+// Path of the trailing update for a batch: explicit choices are honoured;
+// AUTO takes the int8 limbs when the batch is large enough for the deep
+// (K = 128) contraction and every prime is below 2^23.
+bool use_int8(det_path path, int64_t nitems, uint32_t pmax) {
+  if (path == DET_PATH_INT8) return true;
+  if (path == DET_PATH_FP64) return false;
+  return nitems >= TWO_LEVEL_MIN_ITEMS && pmax < (1u << 23);
+}
+
 // Modular determinants of a staged device matrix for a list of primes, in
-// batches bounded by the workspace.  Path already validated.
-det_status residues_core(det_ctx* c, const int64_t* dA, int64_t dlda, int n,
-                         const uint32_t* primes, int64_t np, uint32_t* out, bool int8) {
+// batches bounded by the workspace, on workspace w.  With `wait` false the
+// last batch's residues are copied asynchronously into `out` (which must then
+// be pinned memory) and the caller synchronizes w.st.
+det_status residues_core(det_ctx* c, LuWs& w, const int64_t* dA, int64_t dlda, int n,
+                         const uint32_t* primes, int64_t np, uint32_t* out, det_path path,
+                         bool wait = true) {
   if (np == 0) return DET_OK;
   if (n == 0) {
     for (int64_t i = 0; i < np; i++) out[i] = 1 % primes[i];
@@ -344,7 +414,6 @@ det_status residues_core(det_ctx* c, const int64_t* dA, int64_t dlda, int n,
   J.ncols = n;
   J.ldw = round_up(n, 32);
   J.slab = J.ldw * n;
-  J.int8 = int8;
   const size_t per_item = (size_t)J.slab * 4 + 3 * (size_t)(2 * n) * NB_OUTER + TINV_LD * TINV_LD * 4;
   size_t cap_bytes = (size_t)8 << 30;                  // at most 8 GiB of slabs per batch
   if (c->budget) cap_bytes = std::min(cap_bytes, c->budget / 2);
@@ -353,29 +422,32 @@ det_status residues_core(det_ctx* c, const int64_t* dA, int64_t dlda, int n,
     const int nit = (int)std::min<int64_t>(bmax, np - s0);
     J.nitems = nit;
     J.pmax = 0;
-    std::vector<Modulus> hm(nit);
+    HIPCHK(hipStreamSynchronize(w.st));             // the previous upload from hmods is done
+    std::vector<Modulus>& hm = w.hmods;
+    hm.resize(nit);
     for (int i = 0; i < nit; i++) {
       hm[i] = modulus_of(primes[s0 + i]);
       J.pmax = std::max(J.pmax, primes[s0 + i]);
     }
-    TRY(ensure(c, c->W, (size_t)nit * J.slab * sizeof(int32_t)));
-    TRY(ensure(c, c->piv, (size_t)nit * n * sizeof(int32_t)));
-    TRY(ensure(c, c->flags, (size_t)nit * sizeof(int32_t)));
-    TRY(ensure(c, c->mods, (size_t)nit * sizeof(Modulus)));
-    TRY(ensure(c, c->res, (size_t)nit * sizeof(uint32_t)));
-    HIPCHK(hipMemcpyAsync(c->mods.p, hm.data(), nit * sizeof(Modulus), hipMemcpyHostToDevice, c->st));
-    HIPCHK(hipMemsetAsync(c->flags.p, 0, nit * sizeof(int32_t), c->st));
+    J.int8 = use_int8(path, nit, J.pmax);
+    TRY(ensure(c, w.W, (size_t)nit * J.slab * sizeof(int32_t), w.st));
+    TRY(ensure(c, w.piv, (size_t)nit * n * sizeof(int32_t), w.st));
+    TRY(ensure(c, w.flags, (size_t)nit * sizeof(int32_t), w.st));
+    TRY(ensure(c, w.mods, (size_t)nit * sizeof(Modulus), w.st));
+    TRY(ensure(c, w.res, (size_t)nit * sizeof(uint32_t), w.st));
+    HIPCHK(hipMemcpyAsync(w.mods.p, hm.data(), nit * sizeof(Modulus), hipMemcpyHostToDevice, w.st));
+    HIPCHK(hipMemsetAsync(w.flags.p, 0, nit * sizeof(int32_t), w.st));
     {
-      ProfScope ps(c, DET_KERNEL_RESIDUES, (double)n * n * (8.0 + 4.0 * nit), 0.0);
-      HIPCHK(detk::launch_residues(dA, dlda, n, n, (int32_t*)c->W.p, J.ldw, J.slab,
-                                   (const Modulus*)c->mods.p, nit, c->st));
+      ProfScope ps(c, DET_KERNEL_RESIDUES, (double)n * n * (8.0 + 4.0 * nit), 0.0, w.st);
+      HIPCHK(detk::launch_residues(dA, dlda, n, n, (int32_t*)w.W.p, J.ldw, J.slab,
+                                   (const Modulus*)w.mods.p, nit, w.st));
     }
-    TRY(lu_factor(c, J));
-    HIPCHK(detk::launch_det_finalize((const int32_t*)c->W.p, J.ldw, J.slab, n,
-                                     (const int32_t*)c->piv.p, n, (const int32_t*)c->flags.p,
-                                     (const Modulus*)c->mods.p, (uint32_t*)c->res.p, nit, c->st));
-    HIPCHK(hipMemcpyAsync(out + s0, c->res.p, nit * sizeof(uint32_t), hipMemcpyDeviceToHost, c->st));
-    HIPCHK(hipStreamSynchronize(c->st));
+    TRY(lu_factor(c, w, J, false, nullptr));
+    HIPCHK(detk::launch_det_finalize((const int32_t*)w.W.p, J.ldw, J.slab, n,
+                                     (const int32_t*)w.piv.p, n, (const int32_t*)w.flags.p,
+                                     (const Modulus*)w.mods.p, (uint32_t*)w.res.p, nit, w.st));
+    HIPCHK(hipMemcpyAsync(out + s0, w.res.p, nit * sizeof(uint32_t), hipMemcpyDeviceToHost, w.st));
+    if (wait || s0 + nit < np) HIPCHK(hipStreamSynchronize(w.st));
   }
   return DET_OK;
 }
@@ -386,9 +458,10 @@ uint64_t inv_mod_2_64(uint64_t p) {
   return x;
 }
 
-// A^{-1} mod p into c->Cu (canonical, n x n), from a staged device matrix.
-// Returns DET_E_SINGULAR_MOD_P if p | det(A).
+// A^{-1} mod p into c->Cu (canonical, n x n), from a staged device matrix,
+// on workspace ws[0].  Returns DET_E_SINGULAR_MOD_P if p | det(A).
 det_status inverse_mod_p(det_ctx* c, const int64_t* dA, int64_t dlda, int n, uint32_t p) {
+  LuWs& w = c->ws[0];
   LuJob J;
   J.n = n;
   J.ncols = 2 * n;
@@ -398,34 +471,45 @@ det_status inverse_mod_p(det_ctx* c, const int64_t* dA, int64_t dlda, int n, uin
   J.pmax = p;
   J.int8 = false;
   Modulus hm = modulus_of(p);
-  TRY(ensure(c, c->W, (size_t)J.slab * sizeof(int32_t)));
-  TRY(ensure(c, c->piv, (size_t)n * sizeof(int32_t)));
-  TRY(ensure(c, c->flags, sizeof(int32_t)));
-  TRY(ensure(c, c->mods, sizeof(Modulus)));
+  TRY(ensure(c, w.W, (size_t)J.slab * sizeof(int32_t), w.st));
+  TRY(ensure(c, w.piv, (size_t)n * sizeof(int32_t), w.st));
+  TRY(ensure(c, w.flags, sizeof(int32_t), w.st));
+  TRY(ensure(c, w.mods, sizeof(Modulus), w.st));
   TRY(ensure(c, c->Cu, (size_t)n * n * sizeof(uint32_t)));
-  HIPCHK(hipMemcpyAsync(c->mods.p, &hm, sizeof(Modulus), hipMemcpyHostToDevice, c->st));
-  HIPCHK(hipMemsetAsync(c->flags.p, 0, sizeof(int32_t), c->st));
-  HIPCHK(detk::launch_residues(dA, dlda, n, 2 * n, (int32_t*)c->W.p, J.ldw, J.slab,
-                               (const Modulus*)c->mods.p, 1, c->st));
-  TRY(lu_factor(c, J));
+  HIPCHK(hipMemcpyAsync(w.mods.p, &hm, sizeof(Modulus), hipMemcpyHostToDevice, w.st));
+  HIPCHK(hipMemsetAsync(w.flags.p, 0, sizeof(int32_t), w.st));
+  HIPCHK(detk::launch_residues(dA, dlda, n, 2 * n, (int32_t*)w.W.p, J.ldw, J.slab,
+                               (const Modulus*)w.mods.p, 1, w.st));
+  std::vector<Panel> panels;
+  TRY(lu_factor(c, w, J, true, &panels));
   int32_t flag = 0;
-  HIPCHK(hipMemcpyAsync(&flag, c->flags.p, sizeof(int32_t), hipMemcpyDeviceToHost, c->st));
-  HIPCHK(hipStreamSynchronize(c->st));
+  HIPCHK(hipMemcpyAsync(&flag, w.flags.p, sizeof(int32_t), hipMemcpyDeviceToHost, w.st));
+  HIPCHK(hipStreamSynchronize(w.st));
   if (flag) return fail(c, DET_E_SINGULAR_MOD_P, "p divides det(A)");
-  TRY(back_substitute(c, J));
-  HIPCHK(detk::launch_extract_inverse((const int32_t*)c->W.p, J.ldw, n, (const Modulus*)c->mods.p,
-                                      (uint32_t*)c->Cu.p, c->st));
+  TRY(back_substitute(c, w, J, panels));
+  HIPCHK(detk::launch_extract_inverse((const int32_t*)w.W.p, J.ldw, n, (const Modulus*)w.mods.p,
+                                      (uint32_t*)c->Cu.p, w.st));
   return DET_OK;
 }
 
-// k Dixon steps from r_0 = b.  digits_dev: k x n output (may be null when only
-// the combinations are wanted); comb_dev: k sums of cvec . x_i (may be null).
+// k Dixon steps from r_0 = b on c->st.  digits_dev: k x n output (may be null
+// when only the combinations are wanted); comb_dev: k sums of cvec . x_i (may
+// be null).
+// The cooperative form needs all its workgroups resident at once, so when
+// other work may be running on the context's second stream (`after_own2`),
+// the launch first waits for that stream.
 det_status lift(det_ctx* c, const int64_t* dA, int64_t dlda, int n, const int64_t* b, uint32_t p,
-                int64_t k, uint32_t* digits_dev, const uint32_t* cvec_dev, uint64_t* comb_dev) {
+                int64_t k, uint32_t* digits_dev, const uint32_t* cvec_dev, uint64_t* comb_dev,
+                bool after_own2 = false) {
+  // rp and x are padded with zeros to lift_pad(n) entries (the
+  // register-resident kernel loads 64 EPL entries without bounds tests)
+  const int64_t npad = lift_pad(n);
   TRY(ensure(c, c->Ai, (size_t)n * n * sizeof(int32_t)));
   TRY(ensure(c, c->r, (size_t)n * sizeof(int64_t)));
-  TRY(ensure(c, c->rp, (size_t)n * sizeof(uint32_t)));
-  TRY(ensure(c, c->x, (size_t)n * sizeof(uint32_t)));
+  TRY(ensure(c, c->rp, (size_t)npad * sizeof(uint32_t)));
+  TRY(ensure(c, c->x, (size_t)npad * sizeof(uint32_t)));
+  HIPCHK(hipMemsetAsync(c->rp.p, 0, npad * sizeof(uint32_t), c->st));
+  HIPCHK(hipMemsetAsync(c->x.p, 0, npad * sizeof(uint32_t), c->st));
   HIPCHK(detk::launch_pack_i32(dA, dlda, n, (int32_t*)c->Ai.p, c->st));
   std::vector<uint32_t> rp0(n);
   for (int j = 0; j < n; j++) {
@@ -435,21 +519,64 @@ det_status lift(det_ctx* c, const int64_t* dA, int64_t dlda, int n, const int64_
   HIPCHK(hipMemcpyAsync(c->r.p, b, n * sizeof(int64_t), hipMemcpyHostToDevice, c->st));
   HIPCHK(hipMemcpyAsync(c->rp.p, rp0.data(), n * sizeof(uint32_t), hipMemcpyHostToDevice, c->st));
   const uint64_t pinv64 = inv_mod_2_64(p);
+  const double nn = (double)n * n;
+  const int grid = c->lift_mode == 0 ? detk::lift_persistent_grid(c->device, n) : 0;
+  if (grid > 0) {
+    // lifting modulo p^2: Hensel step for the inverse, then two digits a step
+    TRY(ensure(c, c->C1, (size_t)n * n * sizeof(uint32_t)));
+    TRY(ensure(c, c->E, (size_t)n * n * sizeof(uint32_t)));
+    TRY(ensure(c, c->rp1, (size_t)npad * sizeof(uint32_t)));
+    TRY(ensure(c, c->x1, (size_t)npad * sizeof(uint32_t)));
+    TRY(ensure(c, c->sync, 64));
+    HIPCHK(hipMemsetAsync(c->rp1.p, 0, npad * sizeof(uint32_t), c->st));
+    HIPCHK(hipMemsetAsync(c->x1.p, 0, npad * sizeof(uint32_t), c->st));
+    HIPCHK(hipMemsetAsync(c->sync.p, 0, 64, c->st));
+    // second base-p digit of b mod p^2
+    std::vector<uint32_t> rp1(n);
+    for (int j = 0; j < n; j++) {
+      const int64_t q = (b[j] - (int64_t)rp0[j]) / (int64_t)p;     // exact
+      int64_t m = q % (int64_t)p;
+      rp1[j] = (uint32_t)(m < 0 ? m + p : m);
+    }
+    HIPCHK(hipMemcpyAsync(c->rp1.p, rp1.data(), n * sizeof(uint32_t), hipMemcpyHostToDevice, c->st));
+    HIPCHK(detk::launch_hensel((const int32_t*)c->Ai.p, (const uint32_t*)c->Cu.p,
+                               (uint32_t*)c->E.p, (uint32_t*)c->C1.p, n, p, c->st));
+    if (after_own2) {
+      HIPCHK(hipEventRecord(c->ev, c->own2));
+      HIPCHK(hipStreamWaitEvent(c->st, c->ev, 0));
+    }
+    unsigned* bar = (unsigned*)c->sync.p;
+    int* err = (int*)((char*)c->sync.p + 32);
+    {
+      // algorithmic bytes per digit: C and A as the one-launch-per-phase form
+      // reads them (8 n^2) and four n-vectors
+      ProfScope ps(c, DET_KERNEL_LIFT, (8.0 * nn + 40.0 * n) * k, 4.0 * nn * k, c->st);
+      HIPCHK(detk::launch_lift_resident2(
+          grid, (const uint32_t*)c->Cu.p, (const uint32_t*)c->C1.p, (const int32_t*)c->Ai.p,
+          (int64_t*)c->r.p, (uint32_t*)c->rp.p, (uint32_t*)c->rp1.p, (uint32_t*)c->x.p,
+          (uint32_t*)c->x1.p, n, p, pinv64, k, digits_dev, cvec_dev, comb_dev, bar, err, c->st));
+    }
+    int herr = 0;
+    HIPCHK(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    if (herr) return fail(c, DET_E_DEVICE, "lifting grid barrier timed out");
+    return DET_OK;
+  }
   for (int64_t i = 0; i < k; i++) {
     uint32_t* xi = digits_dev ? digits_dev + i * n : (uint32_t*)c->x.p;
-    const double nn = (double)n * n;
     {
-      ProfScope ps(c, DET_KERNEL_LIFT_X, 4.0 * nn + 8.0 * n, 2.0 * nn);
+      ProfScope ps(c, DET_KERNEL_LIFT_X, 4.0 * nn + 8.0 * n, 2.0 * nn, c->st);
       HIPCHK(detk::launch_lift_x((const uint32_t*)c->Cu.p, (const uint32_t*)c->rp.p, n, p, xi,
                                  c->st));
     }
     {
-      ProfScope ps(c, DET_KERNEL_LIFT_R, 4.0 * nn + 24.0 * n, 2.0 * nn);
+      ProfScope ps(c, DET_KERNEL_LIFT_R, 4.0 * nn + 24.0 * n, 2.0 * nn, c->st);
       HIPCHK(detk::launch_lift_r((const int32_t*)c->Ai.p, xi, (int64_t*)c->r.p,
                                  (uint32_t*)c->rp.p, n, p, pinv64, cvec_dev,
                                  comb_dev ? comb_dev + i : nullptr, c->st));
     }
   }
+  HIPCHK(hipStreamSynchronize(c->st));     // rp0 lives on this frame
   return DET_OK;
 }
 
@@ -459,6 +586,24 @@ det_status check_prime_list(det_ctx* c, const uint32_t* primes, int64_t np, uint
     if (q >= limit || q < 3) return fail(c, DET_E_PRIME_RANGE, "prime outside the supported range");
     if (!dethost::is_prime_u32(q)) return fail(c, DET_E_NOT_PRIME, "modulus is not prime");
   }
+  return DET_OK;
+}
+
+det_status ensure_pinned(det_ctx* c, size_t count) {
+  if (c->hres_cap >= count) return DET_OK;
+  if (c->hres) {
+    HIPCHK(hipStreamSynchronize(c->own2));
+    HIPCHK(hipHostFree(c->hres));
+    c->hres = nullptr;
+    c->hres_cap = 0;
+  }
+  const size_t cap = std::max<size_t>(count, 256);
+  if (hipHostMalloc((void**)&c->hres, cap * sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    c->hres = nullptr;
+    return fail(c, DET_E_NOMEM, "hipHostMalloc failed");
+  }
+  c->hres_cap = cap;
   return DET_OK;
 }
 
@@ -497,13 +642,22 @@ det_status det_ctx_create(int device, size_t hbm_budget_bytes, det_ctx** out) {
   c->budget = hbm_budget_bytes;
   int count = 0;
   if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count ||
-      hipSetDevice(device) != hipSuccess || hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking) != hipSuccess ||
+      hipSetDevice(device) != hipSuccess ||
+      hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&c->own2, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev, hipEventDisableTiming) != hipSuccess ||
       detk::configure_kernels() != hipSuccess) {
     (void)hipGetLastError();
+    if (c->own) (void)hipStreamDestroy(c->own);
+    if (c->own2) (void)hipStreamDestroy(c->own2);
     delete c;
     return DET_E_DEVICE;
   }
   c->st = c->own;
+  c->ws[0].st = c->own;
+  c->ws[1].st = c->own2;
+  const char* lm = getenv("DET_LIFT_MODE");     // "kernels": one launch per lifting phase
+  if (lm && strcmp(lm, "kernels") == 0) c->lift_mode = 1;
   *out = c;
   return DET_OK;
 }
@@ -512,17 +666,25 @@ void det_ctx_destroy(det_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   if (c->st) (void)hipStreamSynchronize(c->st);
-  DevBuf* all[] = {&c->W, &c->piv, &c->flags, &c->mods, &c->linv, &c->tinv, &c->limbA, &c->limbB,
-                   &c->res, &c->Adev, &c->norms, &c->amax, &c->Cu, &c->Ai, &c->r, &c->rp,
-                   &c->x, &c->digits, &c->comb, &c->cvec};
+  if (c->own2) (void)hipStreamSynchronize(c->own2);
+  std::vector<DevBuf*> all = {&c->Adev, &c->norms, &c->amax, &c->Cu, &c->Ai, &c->r, &c->rp,
+                              &c->x, &c->digits, &c->comb, &c->cvec, &c->sync, &c->C1, &c->E,
+                              &c->rp1, &c->x1};
+  for (LuWs& w : c->ws)
+    for (DevBuf* b : {&w.W, &w.piv, &w.flags, &w.mods, &w.linv, &w.uinv, &w.tinv, &w.limbA,
+                      &w.limbB, &w.res})
+      all.push_back(b);
   for (DevBuf* b : all)
     if (b->p) (void)hipFree(b->p);
+  if (c->hres) (void)hipHostFree(c->hres);
   for (auto& pr : c->prof_pending) {
     (void)hipEventDestroy(pr.first);
     (void)hipEventDestroy(pr.second);
   }
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  if (c->ev) (void)hipEventDestroy(c->ev);
   if (c->own) (void)hipStreamDestroy(c->own);
+  if (c->own2) (void)hipStreamDestroy(c->own2);
   delete c;
 }
 
@@ -531,6 +693,7 @@ det_status det_ctx_set_stream(det_ctx* c, void* hip_stream) {
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, DET_E_DEVICE, "hipSetDevice failed");
   HIPCHK(hipStreamSynchronize(c->st));
   c->st = hip_stream ? (hipStream_t)hip_stream : c->own;
+  c->ws[0].st = c->st;
   return DET_OK;
 }
 
@@ -545,7 +708,7 @@ void det_opts_default(det_opts* o) {
 }
 
 det_status det_profile_select(det_ctx* c, det_kernel kind) {
-  if (!c || (int)kind < 0 || (int)kind > DET_KERNEL_RESIDUES) return DET_E_INVALID;
+  if (!c || (int)kind < 0 || (int)kind > DET_KERNEL_LIFT) return DET_E_INVALID;
   c->prof_kind = (int)kind;
   return DET_OK;
 }
@@ -554,6 +717,7 @@ det_status det_profile_read(det_ctx* c, int64_t* launches, double* total_ms, dou
                             double* ops) {
   if (!c) return DET_E_INVALID;
   HIPCHK(hipStreamSynchronize(c->st));
+  HIPCHK(hipStreamSynchronize(c->own2));
   double ms = 0;
   for (auto& pr : c->prof_pending) {
     float t = 0;
@@ -584,8 +748,8 @@ det_status det_mod_primes(det_ctx* c, const int64_t* A, int64_t n, int64_t lda,
       return fail(c, DET_E_INVALID, "unknown path");
     uint32_t pmax = 0;
     for (int64_t i = 0; i < nprimes; i++) pmax = std::max(pmax, primes[i]);
-    const bool int8 = path == DET_PATH_INT8 || (path == DET_PATH_AUTO && pmax < (1u << 23));
-    TRY(check_prime_list(c, primes, nprimes, int8 ? (1u << 23) : (1u << 26)));
+    const bool limb_range = path == DET_PATH_INT8;
+    TRY(check_prime_list(c, primes, nprimes, limb_range ? (1u << 23) : (1u << 26)));
     if (n == 0 || nprimes == 0) {
       for (int64_t i = 0; i < nprimes; i++) residues[i] = 1 % primes[i];
       return DET_OK;
@@ -599,7 +763,7 @@ det_status det_mod_primes(det_ctx* c, const int64_t* A, int64_t n, int64_t lda,
       dethost::Bounds b;
       TRY(matrix_bounds(c, A, lda, true, dA, dlda, n, &b));
     }
-    return residues_core(c, dA, dlda, (int)n, primes, nprimes, residues, int8);
+    return residues_core(c, c->ws[0], dA, dlda, (int)n, primes, nprimes, residues, path);
   } catch (const std::exception& e) {
     return fail(c, DET_E_NOMEM, e.what());
   } catch (...) {
@@ -657,12 +821,12 @@ det_status det_introspective(det_ctx* c, const int64_t* A, int64_t n, int64_t ld
     if (opts_in) o = *opts_in;
     if (o.n_rhs < 1) o.n_rhs = 1;
     if (!(o.log2_inv_eps > 0)) o.log2_inv_eps = 64.0;
-    const bool int8 = o.path != DET_PATH_FP64 && o.prime_bits <= 23;
+    if (o.path != DET_PATH_AUTO && o.path != DET_PATH_FP64 && o.path != DET_PATH_INT8)
+      return fail(c, DET_E_INVALID, "unknown path");
     if (o.prime_bits < 12 || o.prime_bits > (o.path == DET_PATH_INT8 ? 23 : 26))
       return fail(c, DET_E_PRIME_RANGE, "prime_bits out of range");
     det_report rep;
     memset(&rep, 0, sizeof(rep));
-    const double t0 = now_ms();
     auto emit = [&](const BigInt& v) -> det_status {
       std::vector<uint32_t> l = v.limbs32();
       *sign = v.sign;
@@ -685,6 +849,24 @@ det_status det_introspective(det_ctx* c, const int64_t* A, int64_t n, int64_t ld
     rep.hadamard_bits = (int64_t)ceil(bd.log2_h);
     uint64_t rng = o.seed;
     double t_host = 0;
+    const int bits = o.prime_bits;
+    const double log2_l = (double)(bits - 1);
+    dethost::PrimeSampler samp(dethost::splitmix64(rng), bits);
+
+    // ---------------- CRA batch 1 on the second stream (Section 4: the
+    // modular determinants run in the background while the systems are
+    // solved).  Its size covers the run length of Lemma 2.1(iv) for the
+    // bound H itself; once s_n is known, fewer may be needed.
+    const double tc0 = now_ms();
+    const double logl_H0 = std::max(1.0, bd.log2_h / log2_l);
+    const int64_t k0 = dethost::et_run_length(o.log2_inv_eps, dethost::prime_set_size(bits), logl_H0);
+    const int64_t batch1 = k0 > 0 ? std::min<int64_t>(k0 + 3, 64) : 16;
+    std::vector<uint32_t> ps1(batch1);
+    for (auto& q : ps1) q = samp.next();
+    TRY(ensure_pinned(c, (size_t)batch1));
+    HIPCHK(hipEventRecord(c->ev, c->st));              // A (and its bounds) are ready on st
+    HIPCHK(hipStreamWaitEvent(c->own2, c->ev, 0));
+    TRY(residues_core(c, c->ws[1], dA, dlda, (int)n, ps1.data(), batch1, c->hres, o.path, false));
 
     // ---------------- LIF: s~_n from Dixon solvings (Section 2.2)
     BigInt K = BigInt::from_i64(1);
@@ -720,11 +902,12 @@ det_status det_introspective(det_ctx* c, const int64_t* A, int64_t n, int64_t ld
         const double log2D = bd.log2_h + 1e-6;
         const int64_t Nbits = (int64_t)ceil(log2N), Dbits = (int64_t)ceil(log2D);
         const int64_t k = (int64_t)ceil((double)(Nbits + Dbits + 2) / log2((double)p)) + 1;
-        TRY(ensure(c, c->cvec, (size_t)n * sizeof(uint32_t)));
+        TRY(ensure(c, c->cvec, (size_t)lift_pad(n) * sizeof(uint32_t)));
         TRY(ensure(c, c->comb, (size_t)k * sizeof(uint64_t)));
+        HIPCHK(hipMemsetAsync(c->cvec.p, 0, lift_pad(n) * sizeof(uint32_t), c->st));
         HIPCHK(hipMemcpyAsync(c->cvec.p, cv.data(), n * sizeof(uint32_t), hipMemcpyHostToDevice, c->st));
         TRY(lift(c, dA, dlda, (int)n, b.data(), p, k, nullptr, (const uint32_t*)c->cvec.p,
-                 (uint64_t*)c->comb.p));
+                 (uint64_t*)c->comb.p, true));
         std::vector<uint64_t> comb(k);
         HIPCHK(hipMemcpyAsync(comb.data(), c->comb.p, k * sizeof(uint64_t), hipMemcpyDeviceToHost, c->st));
         HIPCHK(hipStreamSynchronize(c->st));
@@ -736,9 +919,8 @@ det_status det_introspective(det_ctx* c, const int64_t* A, int64_t n, int64_t ld
         for (int64_t i = 0; i < k; i++) pk.mul_add_small(p, 0);
         BigInt a, d;
         if (dethost::rational_reconstruct(y, pk, BigInt::from_i64(1).shl(Nbits),
-                                          BigInt::from_i64(1).shl(Dbits), a, d)) {
-          // s~_n <- lcm(s~_n, d)
-          BigInt g = BigInt::gcd(K, d);
+                                          BigInt::from_i64(1).shl(Dbits), a, d, p)) {
+          BigInt g = BigInt::gcd(K, d);                // s~_n <- lcm(s~_n, d)
           K = BigInt::div_exact(K * d, g);
         }
         t_host += now_ms() - th0;
@@ -748,24 +930,17 @@ det_status det_introspective(det_ctx* c, const int64_t* A, int64_t n, int64_t ld
     rep.t_lif_ms = now_ms() - tl0;
 
     // ---------------- CRA on det(A)/K with early termination (Alg. 2.1)
-    const double tc0 = now_ms();
-    const int bits = o.prime_bits;
-    const double log2_l = (double)(bits - 1);
     const double log2_HK = std::max(0.0, bd.log2_h - (double)(K.bit_length() - 1));
     const double logl_H = std::max(1.0, log2_HK / log2_l);
     int64_t kET = dethost::et_run_length(o.log2_inv_eps, dethost::prime_set_size(bits), logl_H);
     if (kET < 0) kET = INT64_MAX;                    // lemma not applicable: certify only
-    dethost::PrimeSampler samp(dethost::splitmix64(rng), bits);
     dethost::CrtState crt;
     bool done = false;
-    int64_t batch = std::min<int64_t>(std::max<int64_t>(kET + 3, 8), 64);
-    std::vector<uint32_t> ps, rs;
-    while (!done) {
-      ps.resize(batch);
-      rs.resize(batch);
-      for (int64_t i = 0; i < batch; i++) ps[i] = samp.next();
-      TRY(residues_core(c, dA, dlda, (int)n, ps.data(), batch, rs.data(), int8));
-      rep.et_rounds++;
+    HIPCHK(hipStreamSynchronize(c->own2));
+    std::vector<uint32_t> ps(ps1), rs(c->hres, c->hres + batch1);
+    rep.et_rounds = 1;
+    int64_t batch = batch1;
+    for (;;) {
       const double th0 = now_ms();
       for (int64_t i = 0; i < batch && !done; i++) {
         const uint32_t p = ps[i];
@@ -783,11 +958,15 @@ det_status det_introspective(det_ctx* c, const int64_t* A, int64_t n, int64_t ld
         }
       }
       t_host += now_ms() - th0;
-      if (!done) {
-        const double need = (1.0 + log2_HK + 1.0 - (double)(crt.M.bit_length() - 1)) / log2_l;
-        batch = std::min<int64_t>(std::max<int64_t>((int64_t)ceil(need) + 1, 4), 512);
-        if (!o.certify) batch = std::min<int64_t>(batch, std::max<int64_t>(2 * kET, 8));
-      }
+      if (done) break;
+      const double need = (1.0 + log2_HK + 1.0 - (double)(crt.M.bit_length() - 1)) / log2_l;
+      batch = std::min<int64_t>(std::max<int64_t>((int64_t)ceil(need) + 1, 4), 512);
+      if (!o.certify) batch = std::min<int64_t>(batch, std::max<int64_t>(2 * kET, 8));
+      ps.resize(batch);
+      rs.resize(batch);
+      for (int64_t i = 0; i < batch; i++) ps[i] = samp.next();
+      TRY(residues_core(c, c->ws[0], dA, dlda, (int)n, ps.data(), batch, rs.data(), o.path));
+      rep.et_rounds++;
     }
     rep.t_cra_ms = now_ms() - tc0;
     const double th1 = now_ms();
@@ -795,7 +974,6 @@ det_status det_introspective(det_ctx* c, const int64_t* A, int64_t n, int64_t ld
     t_host += now_ms() - th1;
     rep.t_host_ms = t_host;
     if (report) *report = rep;
-    (void)t0;
     return emit(det);
   } catch (const std::exception& e) {
     return fail(c, DET_E_NOMEM, e.what());

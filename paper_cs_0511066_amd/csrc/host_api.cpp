@@ -65,16 +65,16 @@ det_status det_host_crt(const uint32_t* residues, const uint32_t* primes, int64_
 }
 
 det_status det_host_ratrecon(const uint32_t* u, int64_t ulen, const uint32_t* m, int64_t mlen,
-                             int64_t Nbits, int64_t Dbits, int* a_sign, uint32_t* a_mag,
-                             int64_t a_cap, int64_t* a_len, uint32_t* d_mag, int64_t d_cap,
-                             int64_t* d_len) {
+                             int64_t Nbits, int64_t Dbits, uint64_t prime_base, int* a_sign,
+                             uint32_t* a_mag, int64_t a_cap, int64_t* a_len, uint32_t* d_mag,
+                             int64_t d_cap, int64_t* d_len) {
   if (ulen < 0 || mlen <= 0 || Nbits < 0 || Dbits < 0 || !a_len || !d_len) return DET_E_INVALID;
   try {
     BigInt U = BigInt::from_limbs32(u, (size_t)ulen, 1), M = BigInt::from_limbs32(m, (size_t)mlen, 1);
     if (M.is_zero()) return DET_E_INVALID;
     BigInt a, d;
     if (!dethost::rational_reconstruct(U, M, BigInt::from_i64(1).shl(Nbits),
-                                       BigInt::from_i64(1).shl(Dbits), a, d))
+                                       BigInt::from_i64(1).shl(Dbits), a, d, prime_base))
       return DET_E_INVALID;
     det_status s = put(a, a_sign, a_mag, a_cap, a_len);
     det_status t = put(d, nullptr, d_mag, d_cap, d_len);

@@ -4,6 +4,7 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <unordered_set>
 #include <vector>
 
@@ -174,15 +175,54 @@ inline int64_t et_run_length(double log2_inv_eps, double P_size, double logl_H) 
 }
 
 // ---------------------------------------------------------------- rational reconstruction
+// Bits [s, s + 63) of a non-negative BigInt.
+inline uint64_t top_bits(const BigInt& v, int64_t s) {
+  const size_t w = (size_t)(s / 64);
+  const int sh = (int)(s % 64);
+  uint64_t lo = w < v.mag.size() ? v.mag[w] : 0;
+  uint64_t hi = w + 1 < v.mag.size() ? v.mag[w + 1] : 0;
+  uint64_t x = sh ? (lo >> sh) | (hi << (64 - sh)) : lo;
+  return x & ((1ull << 63) - 1);
+}
+
 // Find a/d with a = u d (mod m), |a| <= N, 0 < d <= D, gcd(a, d) = 1, unique
 // when 2 N D < m: the extended Euclidean algorithm on (m, u mod m), stopped
-// at the first remainder <= N.  Returns false if no such fraction exists.
+// at the first remainder <= N.  The remainder sequence is advanced with
+// Lehmer's method (Knuth, TAOCP 4.5.2, Algorithm L: the quotients of the
+// leading 63 bits, accepted while both bracketing quotients agree, give a
+// 2x2 cofactor matrix applied to the full numbers) while the remainder is
+// more than 66 bits above N, so no batch can step past the stopping point;
+// the last steps are plain divisions.  When m is a power of the prime
+// `pbase` (pbase != 0), any common factor of the result lies in m, so
+// gcd(a, d) = 1 reduces to pbase not dividing d.
 inline bool rational_reconstruct(const BigInt& u_in, const BigInt& m, const BigInt& N,
-                                 const BigInt& D, BigInt& a_out, BigInt& d_out) {
+                                 const BigInt& D, BigInt& a_out, BigInt& d_out,
+                                 uint64_t pbase = 0) {
   BigInt q, u;
   BigInt::divmod_floor(u_in, m, q, u);
   BigInt r0 = m, r1 = u, t0, t1 = BigInt::from_i64(1);
+  const int64_t nbits = N.bit_length();
   while (r1.cmp(N) > 0) {
+    if (r1.bit_length() > nbits + 66) {
+      const int64_t s = std::max<int64_t>(0, r0.bit_length() - 63);
+      __int128 x = (__int128)top_bits(r0, s), y = (__int128)top_bits(r1, s);
+      __int128 A = 1, B = 0, C = 0, Dd = 1;
+      while (y + C != 0 && y + Dd != 0) {
+        const __int128 qa = (x + A) / (y + C), qb = (x + B) / (y + Dd);
+        if (qa != qb) break;
+        __int128 T = A - qa * C; A = C; C = T;
+        T = B - qa * Dd; B = Dd; Dd = T;
+        T = x - qa * y; x = y; y = T;
+      }
+      if (B != 0) {
+        const BigInt a1 = BigInt::from_i64((int64_t)A), b1 = BigInt::from_i64((int64_t)B);
+        const BigInt c1 = BigInt::from_i64((int64_t)C), d1 = BigInt::from_i64((int64_t)Dd);
+        BigInt nr0 = a1 * r0 + b1 * r1, nr1 = c1 * r0 + d1 * r1;
+        BigInt nt0 = a1 * t0 + b1 * t1, nt1 = c1 * t0 + d1 * t1;
+        r0 = nr0; r1 = nr1; t0 = nt0; t1 = nt1;
+        continue;
+      }
+    }
     BigInt qq, rr;
     BigInt::divmod_floor(r0, r1, qq, rr);
     r0 = r1;
@@ -195,7 +235,11 @@ inline bool rational_reconstruct(const BigInt& u_in, const BigInt& m, const BigI
   if (d.is_zero()) return false;
   if (d.sign < 0) { a = -a; d = -d; }
   if (d.cmp(D) > 0) return false;
-  if (!(BigInt::gcd(a, d).cmp(BigInt::from_i64(1)) == 0)) return false;
+  if (pbase) {
+    if (d.mod_small(pbase) == 0) return false;
+  } else if (!(BigInt::gcd(a, d).cmp(BigInt::from_i64(1)) == 0)) {
+    return false;
+  }
   a_out = a;
   d_out = d;
   return true;

@@ -11,17 +11,18 @@ namespace detk {
 
 hipError_t launch_residues(const int64_t* A, int64_t lda, int n, int ncols, int32_t* W, int64_t ldw,
                            int64_t slab, const Modulus* mods, int nitems, hipStream_t st);
-hipError_t launch_panel(int32_t* W, int64_t ldw, int64_t slab, int n, int j0, int pb, int pbmax,
+hipError_t launch_panel(int32_t* W, int64_t ldw, int64_t slab, int n, int j0, int pb, int pbw,
                         const Modulus* mods, int32_t* piv, int64_t piv_stride, int32_t* flags,
-                        int32_t* Linv, int nitems, hipStream_t st);
+                        int32_t* Linv, int32_t* Uinv, int kc, int nitems, hipStream_t st);
+int panel_width_for(int m);
 hipError_t launch_swaps(int32_t* W, int64_t ldw, int64_t slab, int j0, int pb, const int32_t* piv,
                         int64_t piv_stride, int c0a, int c1a, int c0b, int c1b, int nitems,
                         hipStream_t st);
-hipError_t launch_tri_inv(const int32_t* W, int64_t ldw, int64_t slab, int k0, int kb, int upper,
-                          const Modulus* mods, int32_t* Tinv, int ldt, int kc, int nitems,
-                          hipStream_t st);
+hipError_t launch_tri_inv(const int32_t* W, int64_t ldw, int64_t slab, int k0, int kb,
+                          const Modulus* mods, int32_t* Tinv, int ldt, int nitems, hipStream_t st);
 hipError_t launch_trsm_apply(int32_t* W, int64_t slab, int64_t ldw, int r0, int kb, int c0, int N,
                              const int32_t* Tinv, int ldt, const Modulus* mods, int kc4,
+                             const int32_t* piv, int64_t piv_stride, int sw_j0, int sw_pb,
                              int nitems, hipStream_t st);
 hipError_t launch_gemm_f64(int32_t* W, int64_t slab, int64_t offC, int64_t offA, int64_t offB,
                            int64_t ldw, int M, int N, int K, const Modulus* mods, int kc4,
@@ -44,6 +45,24 @@ hipError_t launch_lift_x(const uint32_t* Cu, const uint32_t* rp, int n, uint32_t
 hipError_t launch_lift_r(const int32_t* Ai, const uint32_t* x, int64_t* r, uint32_t* rp, int n,
                          uint32_t p, uint64_t pinv64, const uint32_t* cvec, uint64_t* comb,
                          hipStream_t st);
+
+// Cooperative form: all k steps in one launch (grid from lift_persistent_grid,
+// 0 when the device cannot run it).  bar and err must be zero at launch.
+int lift_persistent_grid(int device, int n);
+hipError_t launch_lift_persistent(int grid, const uint32_t* Cu, const int32_t* Ai, int64_t* r,
+                                  uint32_t* rp, uint32_t* xbuf, int n, uint32_t p, uint64_t pinv64,
+                                  int64_t k, uint32_t* digits, const uint32_t* cvec,
+                                  uint64_t* comb, unsigned* bar, int* err, hipStream_t st);
+
+// Lifting modulo p^2 (two base-p digits per step, n <= 1024): the Hensel
+// step C1 = digit plane of A^{-1} mod p^2 (E: n x n scratch), then all steps.
+hipError_t launch_hensel(const int32_t* Ai, const uint32_t* Cu, uint32_t* E, uint32_t* C1, int n,
+                         uint32_t p, hipStream_t st);
+hipError_t launch_lift_resident2(int grid, const uint32_t* C0, const uint32_t* C1,
+                                 const int32_t* Ai, int64_t* r, uint32_t* rp0, uint32_t* rp1,
+                                 uint32_t* xb0, uint32_t* xb1, int n, uint32_t p, uint64_t pinv64,
+                                 int64_t kd, uint32_t* digits, const uint32_t* cvec,
+                                 uint64_t* comb, unsigned* bar, int* err, hipStream_t st);
 
 hipError_t launch_pack_i32(const int64_t* A, int64_t lda, int n, int32_t* Ai, hipStream_t st);
 hipError_t launch_norms(const int64_t* A, int64_t lda, int n, double* out2n, double* amax,

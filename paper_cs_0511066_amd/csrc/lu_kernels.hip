@@ -51,21 +51,33 @@ __global__ void k_residues(const int64_t* __restrict__ A, int64_t lda, int n, in
 }
 
 // ------------------------------------------------------------------ K2: panel
-// Factor rows [j0, n) x columns [j0, j0+pb) of every item.  Thread t holds
-// panel rows t, t+1024, ... in registers.  Pivot = first row at or below the
-// diagonal with a non-zero entry (lowest row index); the whole panel row is
-// swapped.  Outputs: L below the diagonal, U on and above it, piv[j0+j] =
-// global row swapped with row j0+j, flags[z] = 1 if a column has no pivot
-// (then det = 0 mod p), and Linv = the pb x pb unit lower inverse of L11
-// (dense, PB x PB, zero-padded).
+// Factor rows [j0, n) x columns [j0, j0+pb) of every item (m = n - j0 rows).
+// One 1024-thread workgroup per item.  Thread t owns rows t, t+1024, ...;
+// for each it keeps the not yet eliminated part of the row in FP64 shift
+// registers (a[q][0] is always the current column j), so every register
+// index is a compile-time constant.  Finished values (multipliers and pivot
+// rows) go to the LDS copy of the panel, sP (int32, m x PB <= 128 KiB), which
+// is written back to HBM at the end.
+// Pivot = first row at or below the diagonal with a non-zero entry (lowest
+// row index); rows are swapped LAPACK-style (whole panel rows).  Updates are
+// applied without reduction: every row receives the same number of updates,
+// each below h^2 (h = (p-1)/2), so values stay exact while at most kc are
+// pending (kc h^2 + h <= 2^53); the pivot column is reduced before use.
+// Outputs: L below the diagonal, U on and above it, piv[j0+j] = global row
+// swapped with row j0+j, flags[z] = 1 if a column has no pivot (det = 0 mod
+// p), Linv = the pb x pb unit lower inverse of L11 and, if Uinv != null, the
+// upper inverse of U11 (both dense PB x PB, zero-padded).
 template <int PB, int RPT>
 __global__ __launch_bounds__(1024) void k_panel(int32_t* __restrict__ W, int64_t ldw, int64_t slab,
                                                 int n, int j0, int pb,
                                                 const Modulus* __restrict__ mods,
                                                 int32_t* __restrict__ piv, int64_t piv_stride,
                                                 int32_t* __restrict__ flags,
-                                                int32_t* __restrict__ Linv) {
+                                                int32_t* __restrict__ Linv,
+                                                int32_t* __restrict__ Uinv, int kc) {
   constexpr int T = 1024;
+  constexpr int MROWS = RPT * T;
+  constexpr int SP = PB + 1;                  // LDS row stride: odd, so a column is conflict-free
   const int z = blockIdx.x;
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
@@ -73,115 +85,128 @@ __global__ __launch_bounds__(1024) void k_panel(int32_t* __restrict__ W, int64_t
   int32_t* Wz = W + (int64_t)z * slab + (int64_t)j0 * ldw + j0;
   const int m = n - j0;
 
-  __shared__ int s_min[2][16];
+  __shared__ int32_t sP[MROWS * SP];          // finished panel values, row-major
+  __shared__ int s_min[2][T / 64];
   __shared__ double s_prow[2][PB];
   __shared__ double s_jrow[2][PB];
   __shared__ double s_inv[2];
-  __shared__ double s_L[PB][PB + 1];
+  __shared__ double s_dinv[PB];
 
-  int32_t a[RPT][PB];
+  double a[RPT][PB];
 #pragma unroll
   for (int q = 0; q < RPT; q++) {
     const int row = t + q * T;
 #pragma unroll
-    for (int c = 0; c < PB; c++)
-      a[q][c] = (row < m && c < pb) ? Wz[(int64_t)row * ldw + c] : 0;
+    for (int k = 0; k < PB; k++)
+      a[q][k] = (row < m && k < pb) ? (double)Wz[(int64_t)row * ldw + k] : 0.0;
   }
 
+  int pending = 0;
+  for (int j = 0; j < pb; j++) {
+    const int buf = j & 1;
+    int cand = INT_MAX;
 #pragma unroll
-  for (int j = 0; j < PB; j++) {
-    if (j < pb) {
-      const int buf = j & 1;
-      int cand = INT_MAX;
-#pragma unroll
-      for (int q = 0; q < RPT; q++) {
-        const int row = t + q * T;
-        if (row >= j && row < m && a[q][j] != 0) cand = min(cand, row);
+    for (int q = 0; q < RPT; q++) {
+      const int row = t + q * T;
+      if (row >= j && row < m) {
+        a[q][0] = mod_c(a[q][0], p, pinv);          // the pivot column must be exact
+        if (a[q][0] != 0.0) cand = min(cand, row);
       }
-      cand = wave_min_int(cand);
-      if (lane == 0) s_min[buf][wave] = cand;
-      __syncthreads();
-      int pr = INT_MAX;
-#pragma unroll
-      for (int w = 0; w < T / 64; w++) pr = min(pr, s_min[buf][w]);
-      if (pr == INT_MAX) {             // no pivot: det = 0 mod p; column left as is
-        if (t == 0) {
-          flags[z] = 1;
-          piv[(int64_t)z * piv_stride + j0 + j] = j0 + j;
-        }
-        continue;                      // uniform: every thread read the same pr
-      }
-#pragma unroll
-      for (int q = 0; q < RPT; q++) {
-        const int row = t + q * T;
-        if (row == pr) {
-#pragma unroll
-          for (int c = 0; c < PB; c++) s_prow[buf][c] = (double)a[q][c];
-          s_inv[buf] = inv_mod((double)a[q][j], p, pinv);
-        }
-        if (row == j && pr != j) {
-#pragma unroll
-          for (int c = 0; c < PB; c++) s_jrow[buf][c] = (double)a[q][c];
-        }
-      }
-      __syncthreads();
-      const double inv = s_inv[buf];
-#pragma unroll
-      for (int q = 0; q < RPT; q++) {
-        const int row = t + q * T;
-        if (pr != j) {
-          if (row == j) {
-#pragma unroll
-            for (int c = 0; c < PB; c++) a[q][c] = (int32_t)s_prow[buf][c];
-          } else if (row == pr) {
-#pragma unroll
-            for (int c = 0; c < PB; c++) a[q][c] = (int32_t)s_jrow[buf][c];
-          }
-        }
-        if (row > j && row < m) {
-          const double l = mul_mod((double)a[q][j], inv, p, pinv);
-          a[q][j] = (int32_t)l;
-#pragma unroll
-          for (int c = j + 1; c < PB; c++)
-            a[q][c] = (int32_t)mod_c((double)a[q][c] - l * s_prow[buf][c], p, pinv);
-        }
-      }
-      if (t == 0) piv[(int64_t)z * piv_stride + j0 + j] = j0 + pr;
     }
-  }
-
-  // write back, and stage L11 (strictly lower part of the top pb x pb block)
+    cand = wave_min_int(cand);
+    if (lane == 0) s_min[buf][wave] = cand;
+    __syncthreads();                                  // (1) candidates published
+    int pr = INT_MAX;
 #pragma unroll
-  for (int q = 0; q < RPT; q++) {
-    const int row = t + q * T;
-    if (row < m) {
+    for (int w = 0; w < T / 64; w++) pr = min(pr, s_min[buf][w]);
+    const bool singular = pr == INT_MAX;              // no pivot: det = 0 mod p, row j kept
+    if (singular) pr = j;
 #pragma unroll
-      for (int c = 0; c < PB; c++)
-        if (c < pb) Wz[(int64_t)row * ldw + c] = a[q][c];
+    for (int q = 0; q < RPT; q++) {
+      const int row = t + q * T;
+      if (row == pr) {                                // raw pivot row; reduced below in parallel
+#pragma unroll
+        for (int k = 0; k < PB; k++) s_jrow[buf][k] = a[q][k];
+      }
     }
-    if (row < PB) {
+    __syncthreads();                                  // (2) raw pivot row published
+    if (t < PB) s_prow[buf][t] = t == 0 ? s_jrow[buf][0] : mod_c(s_jrow[buf][t], p, pinv);
+    if (t == PB) {
+      const double iv = singular ? 0.0 : inv_mod(s_jrow[buf][0], p, pinv);
+      s_inv[buf] = iv;
+      s_dinv[j] = iv;
+    }
+    // old row j moves down to row pr: its owner stages it in the other buffer
+    // (last read in column j-1 before that column's barrier (3))
+    if (pr != j) {
 #pragma unroll
-      for (int c = 0; c < PB; c++) s_L[row][c] = (row < pb && c < row) ? (double)a[q][c] : 0.0;
+      for (int q = 0; q < RPT; q++)
+        if (t + q * T == j) {
+#pragma unroll
+          for (int k = 0; k < PB; k++) s_jrow[buf ^ 1][k] = a[q][k];
+        }
+    }
+    __syncthreads();                                  // (3) reduced pivot row, inverse, old row j
+    // swap the finished (multiplier) parts of rows j and pr
+    if (pr != j && t < j) {
+      const int32_t v = sP[j * SP + t];
+      sP[j * SP + t] = sP[pr * SP + t];
+      sP[pr * SP + t] = v;
+    }
+    if (t < pb - j) sP[j * SP + j + t] = (int32_t)s_prow[buf][t];   // U row j, in parallel
+    const double inv = s_inv[buf];
+#pragma unroll
+    for (int q = 0; q < RPT; q++) {
+      const int row = t + q * T;
+      if (row == pr && pr != j) {       // old row j moves down to row pr
+        volatile double* src = s_jrow[buf ^ 1];
+#pragma unroll
+        for (int k = 0; k < PB; k++) a[q][k] = src[k];
+      }
+      if (row > j && row < m) {
+        const double l = mul_mod(a[q][0], inv, p, pinv);
+        sP[row * SP + j] = (int32_t)l;
+#pragma unroll
+        for (int k = 1; k < PB; k++) a[q][k] = fma(-l, s_prow[buf][k], a[q][k]);
+#pragma unroll
+        for (int k = 0; k + 1 < PB; k++) a[q][k] = a[q][k + 1];
+        a[q][PB - 1] = 0.0;
+      }
+    }
+    if (++pending == kc) {
+      pending = 0;
+#pragma unroll
+      for (int q = 0; q < RPT; q++)
+#pragma unroll
+        for (int k = 0; k < PB; k++) a[q][k] = mod_c(a[q][k], p, pinv);
+    }
+    if (t == 0) {
+      piv[(int64_t)z * piv_stride + j0 + j] = j0 + pr;
+      if (singular) flags[z] = 1;
     }
   }
   __syncthreads();
-  // Linv column c (thread c): X[c][c] = 1, X[i][c] = -sum_{k=c}^{i-1} L[i][k] X[k][c].
-  // Each sum has < 32 products of centred residues (< 2^50 each for p < 2^26)
-  // so it is reduced every 8 terms to stay below 2^53.
+  // write back the whole panel, consecutive threads on consecutive columns
+  for (int e = t; e < m * pb; e += T) {
+    const int r = e / pb, k = e - r * pb;
+    Wz[(int64_t)r * ldw + k] = sP[r * SP + k];
+  }
+  // Linv column c (thread c < PB): X[c][c] = 1,
+  // X[i][c] = -sum_{k=c}^{i-1} L[i][k] X[k][c], reduced every 8 products
+  // (8 h^2 + h <= 2^53 for p < 2^26).
   if (t < PB) {
     const int c = t;
     int32_t* Lz = Linv + (int64_t)z * PB * PB;
     double x[PB];
 #pragma unroll
-    for (int i = 0; i < PB; i++) x[i] = 0.0;
+    for (int i = 0; i < PB; i++) x[i] = (i == c && c < pb) ? 1.0 : 0.0;   // constant indices only
 #pragma unroll
-    for (int i = 0; i < PB; i++) {
-      if (i == c) x[i] = 1.0;
-      else if (i > c) {
+    for (int i = 1; i < PB; i++) {
+      if (i > c && i < pb) {
         double s = 0.0;
 #pragma unroll
-        for (int k = 0; k < i; k++) {
-          if (k >= c) s += s_L[i][k] * x[k];
+        for (int k = 0; k < PB; k++) {
+          if (k >= c && k < i) s = fma((double)sP[i * SP + k], x[k], s);
           if ((k & 7) == 7) s = mod_c(s, p, pinv);
         }
         x[i] = mod_c(-s, p, pinv);
@@ -189,6 +214,30 @@ __global__ __launch_bounds__(1024) void k_panel(int32_t* __restrict__ W, int64_t
     }
 #pragma unroll
     for (int i = 0; i < PB; i++) Lz[i * PB + c] = (i < pb && c < pb) ? (int32_t)x[i] : 0;
+  }
+  if (Uinv == nullptr) return;
+  // Uinv column c: X[c][c] = dinv[c], X[i][c] = -dinv[i] sum_{k=i+1}^{c} U[i][k] X[k][c]
+  if (t < PB) {
+    const int c = t;
+    int32_t* Uz = Uinv + (int64_t)z * PB * PB;
+    double x[PB];
+#pragma unroll
+    for (int i = 0; i < PB; i++) x[i] = (i == c && c < pb) ? s_dinv[i] : 0.0;
+#pragma unroll
+    for (int i = PB - 2; i >= 0; i--) {
+      if (i < c && c < pb) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = PB - 1; k > 0; k--) {
+          if (k > i && k <= c) s = fma((double)sP[i * SP + k], x[k], s);
+          if ((k & 7) == 0) s = mod_c(s, p, pinv);
+        }
+        s = mod_c(s, p, pinv);
+        x[i] = mul_mod(-s, s_dinv[i], p, pinv);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < PB; i++) Uz[i * PB + c] = (i < pb && c < pb) ? (int32_t)x[i] : 0;
   }
 }
 
@@ -220,61 +269,55 @@ __global__ void k_swaps(int32_t* __restrict__ W, int64_t ldw, int64_t slab, int 
 }
 
 // ------------------------------------------------------------------ triangular inverse
-// Inverse of the kb x kb diagonal block at rows/cols [k0, k0+kb) of every
-// item: lower unit (the L11 of an outer block) or upper non-unit (U11, used
-// by back substitution).  One workgroup per item, thread c computes column c.
-// Out: Tinv[z] dense KBMAX x KBMAX (ld KBMAX), zero outside kb x kb.
-__global__ __launch_bounds__(256) void k_tri_inv(const int32_t* __restrict__ W, int64_t ldw,
-                                                 int64_t slab, int k0, int kb, int upper,
-                                                 const Modulus* __restrict__ mods,
-                                                 int32_t* __restrict__ Tinv, int ldt, int kc) {
+// Inverse of the unit lower kb x kb block L11 at rows/cols [k0, k0+kb) of
+// every item (kb <= 128).  One workgroup per item; wave w computes columns
+// w, w+16, ...  For column c the forward substitution
+//   X[c][c] = 1,  X[i][c] = -sum_{k=c}^{i-1} L[i][k] X[k][c]
+// is sequential in i; each sum is split over the 64 lanes (lane l takes
+// k = c+l and c+l+64), reduced per lane and then across the wave, so every
+// partial sum stays far below 2^53.  Lane l keeps X[l][c] and X[l+64][c].
+// Out: Tinv[z] dense ldt x ldt (zero outside kb x kb).
+__global__ __launch_bounds__(1024) void k_tri_inv(const int32_t* __restrict__ W, int64_t ldw,
+                                                  int64_t slab, int k0, int kb,
+                                                  const Modulus* __restrict__ mods,
+                                                  int32_t* __restrict__ Tinv, int ldt) {
   const int z = blockIdx.x;
   const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
   const double p = mods[z].p, pinv = mods[z].pinv;
-  extern __shared__ int32_t smem[];
-  int32_t* sT = smem;                         // kb x kb block
-  int32_t* sX = smem + kb * kb;               // kb x kb result (column per thread)
-  double* sD = (double*)(sX + kb * kb);       // inverses of the diagonal (upper)
+  __shared__ double sT[128][129];
   const int32_t* Wz = W + (int64_t)z * slab + (int64_t)k0 * ldw + k0;
-  for (int e = t; e < kb * kb; e += blockDim.x) sT[e] = Wz[(int64_t)(e / kb) * ldw + (e % kb)];
-  __syncthreads();
-  if (upper) {
-    for (int i = t; i < kb; i += blockDim.x) sD[i] = inv_mod((double)sT[i * kb + i], p, pinv);
-    __syncthreads();
-  }
-  for (int c = t; c < kb; c += blockDim.x) {
-    if (!upper) {
-      for (int i = 0; i < c; i++) sX[i * kb + c] = 0;
-      sX[c * kb + c] = 1;
-      for (int i = c + 1; i < kb; i++) {
-        double s = 0.0;
-        int cnt = 0;
-        for (int k = c; k < i; k++) {
-          s += (double)sT[i * kb + k] * (double)sX[k * kb + c];
-          if (++cnt == kc) { s = mod_c(s, p, pinv); cnt = 0; }
-        }
-        sX[i * kb + c] = (int32_t)mod_c(-s, p, pinv);
-      }
-    } else {
-      for (int i = c + 1; i < kb; i++) sX[i * kb + c] = 0;
-      sX[c * kb + c] = (int32_t)sD[c];
-      for (int i = c - 1; i >= 0; i--) {
-        double s = 0.0;
-        int cnt = 0;
-        for (int k = i + 1; k <= c; k++) {
-          s += (double)sT[i * kb + k] * (double)sX[k * kb + c];
-          if (++cnt == kc) { s = mod_c(s, p, pinv); cnt = 0; }
-        }
-        s = mod_c(s, p, pinv);
-        sX[i * kb + c] = (int32_t)mul_mod(-s, sD[i], p, pinv);
-      }
-    }
+  for (int e = t; e < 128 * 128; e += 1024) {
+    const int i = e >> 7, k = e & 127;
+    sT[i][k] = (i < kb && k < i) ? (double)Wz[(int64_t)i * ldw + k] : 0.0;
   }
   __syncthreads();
   int32_t* Tz = Tinv + (int64_t)z * ldt * ldt;
-  for (int e = t; e < ldt * ldt; e += blockDim.x) {
-    const int i = e / ldt, c = e % ldt;
-    Tz[e] = (i < kb && c < kb) ? sX[i * kb + c] : 0;
+  for (int c = wave; c < ldt; c += 16) {
+    double x0 = (lane == c) ? 1.0 : 0.0;             // X[lane][c]
+    double x1 = (lane + 64 == c) ? 1.0 : 0.0;        // X[lane + 64][c]
+    if (c < kb) {
+      for (int i = c + 1; i < kb; i++) {
+        // X[k][c] lives in lane k mod 64 (x0 for k < 64, x1 for k >= 64)
+        const int k1 = c + lane, k2 = k1 + 64;
+        const int src = k1 & 63;
+        const double v0 = __shfl(x0, src, 64), v1 = __shfl(x1, src, 64);
+        const double t1 = sT[i][min(k1, 127)], t2 = sT[i][min(k2, 127)];
+        double s = (k1 < i) ? t1 * (k1 < 64 ? v0 : v1) : 0.0;
+        s = (k2 < i) ? fma(t2, v1, s) : s;
+        s = mod_c(s, p, pinv);
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+        const double xi = mod_c(-s, p, pinv);
+        if (i < 64) {
+          if (lane == i) x0 = xi;
+        } else if (lane == i - 64) {
+          x1 = xi;
+        }
+      }
+    }
+    if (lane < ldt) Tz[lane * ldt + c] = (c < kb && lane < kb) ? (int32_t)x0 : 0;
+    if (lane + 64 < ldt) Tz[(lane + 64) * ldt + c] = (c < kb && lane + 64 < kb) ? (int32_t)x1 : 0;
   }
 }
 
@@ -382,10 +425,15 @@ __global__ __launch_bounds__(256) void k_gemm_f64(int32_t* __restrict__ W, int64
 // of every item (U12 = L11^{-1} A12, or X_blk = U11^{-1} Y_blk).  A
 // workgroup loads its whole kb x 64 column strip into LDS before it writes,
 // so the update in place is safe (no other workgroup touches those columns).
+// With sw_pb > 0 the workgroup first applies the row swaps of the panel
+// [sw_j0, sw_j0 + sw_pb) (row sw_j0+j <-> piv[sw_j0+j], in order) to its
+// columns, so a separate swap launch is not needed.
 __global__ __launch_bounds__(256) void k_trsm_apply(int32_t* __restrict__ W, int64_t slab,
                                                     int64_t ldw, int r0, int kb, int c0, int N,
                                                     const int32_t* __restrict__ Tinv, int ldt,
-                                                    const Modulus* __restrict__ mods, int kc4) {
+                                                    const Modulus* __restrict__ mods, int kc4,
+                                                    const int32_t* __restrict__ piv,
+                                                    int64_t piv_stride, int sw_j0, int sw_pb) {
   const int z = blockIdx.y;
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
@@ -394,6 +442,26 @@ __global__ __launch_bounds__(256) void k_trsm_apply(int32_t* __restrict__ W, int
   int32_t* Xg = W + (int64_t)z * slab + (int64_t)r0 * ldw + c0;
   const int32_t* Tz = Tinv + (int64_t)z * ldt * ldt;
   const int col0 = blockIdx.x * GB_N;
+  if (sw_pb > 0) {
+    const int32_t* pz = piv + (int64_t)z * piv_stride + sw_j0;
+    bool any = false;
+    for (int j = 0; j < sw_pb; j++) any |= (pz[j] != sw_j0 + j);
+    if (any) {                                   // uniform across the workgroup
+      int32_t* Wc = W + (int64_t)z * slab + c0;
+      if (t < GB_N && col0 + t < N) {
+        const int gc = col0 + t;
+        for (int j = 0; j < sw_pb; j++) {
+          const int rw = pz[j];
+          if (rw != sw_j0 + j) {
+            const int32_t v = Wc[(int64_t)(sw_j0 + j) * ldw + gc];
+            Wc[(int64_t)(sw_j0 + j) * ldw + gc] = Wc[(int64_t)rw * ldw + gc];
+            Wc[(int64_t)rw * ldw + gc] = v;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
   extern __shared__ double sX[];             // [ldt][GB_N + 2]
   constexpr int LDX = GB_N + 2;
   for (int e = t; e < ldt * GB_N; e += 256) {
@@ -683,21 +751,26 @@ hipError_t launch_residues(const int64_t* A, int64_t lda, int n, int ncols, int3
   return hipSuccess;
 }
 
-hipError_t launch_panel(int32_t* W, int64_t ldw, int64_t slab, int n, int j0, int pb, int pbmax,
+hipError_t launch_panel(int32_t* W, int64_t ldw, int64_t slab, int n, int j0, int pb, int pbw,
                         const Modulus* mods, int32_t* piv, int64_t piv_stride, int32_t* flags,
-                        int32_t* Linv, int nitems, hipStream_t st) {
+                        int32_t* Linv, int32_t* Uinv, int kc, int nitems, hipStream_t st) {
   const int m = n - j0;
-  if (pbmax == 32 && m <= 1024)
-    k_panel<32, 1><<<nitems, 1024, 0, st>>>(W, ldw, slab, n, j0, pb, mods, piv, piv_stride, flags, Linv);
-  else if (pbmax == 32 && m <= 2048)
-    k_panel<32, 2><<<nitems, 1024, 0, st>>>(W, ldw, slab, n, j0, pb, mods, piv, piv_stride, flags, Linv);
-  else if (pbmax == 16 && m <= 4096)
-    k_panel<16, 4><<<nitems, 1024, 0, st>>>(W, ldw, slab, n, j0, pb, mods, piv, piv_stride, flags, Linv);
+  if (pb > pbw) return hipErrorInvalidValue;
+  if (pbw == 32 && m <= 1024)
+    k_panel<32, 1><<<nitems, 1024, 0, st>>>(W, ldw, slab, n, j0, pb, mods, piv, piv_stride, flags, Linv, Uinv, kc);
+  else if (pbw == 16 && m <= 2048)
+    k_panel<16, 2><<<nitems, 1024, 0, st>>>(W, ldw, slab, n, j0, pb, mods, piv, piv_stride, flags, Linv, Uinv, kc);
+  else if (pbw == 8 && m <= 4096)
+    k_panel<8, 4><<<nitems, 1024, 0, st>>>(W, ldw, slab, n, j0, pb, mods, piv, piv_stride, flags, Linv, Uinv, kc);
   else
     return hipErrorInvalidValue;
   LAUNCH_CHECK();
   return hipSuccess;
 }
+
+// Panel width for a panel whose first row is j0: its m = n - j0 rows must
+// fit the 1024 threads times the rows each holds (and m x width <= 32768).
+int panel_width_for(int m) { return m <= 1024 ? 32 : (m <= 2048 ? 16 : 8); }
 
 hipError_t launch_swaps(int32_t* W, int64_t ldw, int64_t slab, int j0, int pb, const int32_t* piv,
                         int64_t piv_stride, int c0a, int c1a, int c0b, int c1b, int nitems,
@@ -710,25 +783,25 @@ hipError_t launch_swaps(int32_t* W, int64_t ldw, int64_t slab, int j0, int pb, c
   return hipSuccess;
 }
 
-hipError_t launch_tri_inv(const int32_t* W, int64_t ldw, int64_t slab, int k0, int kb, int upper,
-                          const Modulus* mods, int32_t* Tinv, int ldt, int kc, int nitems,
-                          hipStream_t st) {
+hipError_t launch_tri_inv(const int32_t* W, int64_t ldw, int64_t slab, int k0, int kb,
+                          const Modulus* mods, int32_t* Tinv, int ldt, int nitems, hipStream_t st) {
   if (kb <= 0) return hipSuccess;
-  if (kb > ldt || kb > 128) return hipErrorInvalidValue;
-  const size_t sh = (size_t)2 * kb * kb * sizeof(int32_t) + (size_t)kb * sizeof(double);
-  k_tri_inv<<<nitems, 256, sh, st>>>(W, ldw, slab, k0, kb, upper, mods, Tinv, ldt, kc);
+  if (kb > ldt || ldt > 128) return hipErrorInvalidValue;
+  k_tri_inv<<<nitems, 1024, 0, st>>>(W, ldw, slab, k0, kb, mods, Tinv, ldt);
   LAUNCH_CHECK();
   return hipSuccess;
 }
 
 hipError_t launch_trsm_apply(int32_t* W, int64_t slab, int64_t ldw, int r0, int kb, int c0, int N,
                              const int32_t* Tinv, int ldt, const Modulus* mods, int kc4,
+                             const int32_t* piv, int64_t piv_stride, int sw_j0, int sw_pb,
                              int nitems, hipStream_t st) {
   if (kb <= 0 || N <= 0) return hipSuccess;
   if (kb > ldt || (ldt % 4) != 0) return hipErrorInvalidValue;
   dim3 grid((N + GB_N - 1) / GB_N, nitems);
   const size_t sh = (size_t)ldt * (GB_N + 2) * sizeof(double);
-  k_trsm_apply<<<grid, 256, sh, st>>>(W, slab, ldw, r0, kb, c0, N, Tinv, ldt, mods, kc4);
+  k_trsm_apply<<<grid, 256, sh, st>>>(W, slab, ldw, r0, kb, c0, N, Tinv, ldt, mods, kc4, piv,
+                                      piv_stride, sw_j0, sw_pb);
   LAUNCH_CHECK();
   return hipSuccess;
 }
@@ -800,9 +873,6 @@ hipError_t launch_norms(const int64_t* A, int64_t lda, int n, double* out2n, dou
 }
 
 hipError_t configure_kernels() {
-  hipError_t e = hipFuncSetAttribute((const void*)k_tri_inv,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-  if (e != hipSuccess) return e;
   return hipFuncSetAttribute((const void*)k_trsm_apply,
                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
 }

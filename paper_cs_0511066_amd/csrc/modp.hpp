@@ -27,16 +27,25 @@ __device__ __forceinline__ double mul_mod(double a, double b, double p, double p
   return mod_c(a * b, p, pinv);
 }
 
-// a^e mod p by square-and-multiply (e >= 0).
+// Product reduced to |r| <= (p+1)/2 without the final fold: inputs with
+// |a|, |b| <= (p+1)/2 keep the product below 2^52 for p < 2^26, so chains of
+// these stay exact and need one fold at the end.  Four dependent operations.
+__device__ __forceinline__ double mul_mod_loose(double a, double b, double p, double pinv) {
+  const double c = a * b;
+  return fma(-rint(c * pinv), p, c);
+}
+
+// a^e mod p by square-and-multiply (e >= 0); the squaring chain is the only
+// dependency chain (the multiplications into r run beside it).
 __device__ __forceinline__ double pow_mod(double a, uint32_t e, double p, double pinv) {
   double r = 1.0;
   double b = a;
   while (e) {
-    if (e & 1u) r = mul_mod(r, b, p, pinv);
-    b = mul_mod(b, b, p, pinv);
+    if (e & 1u) r = mul_mod_loose(r, b, p, pinv);
+    b = mul_mod_loose(b, b, p, pinv);
     e >>= 1;
   }
-  return r;
+  return mod_c(r, p, pinv);
 }
 
 // Inverse of a non-zero residue by Fermat's little theorem, a^(p-2).

@@ -152,6 +152,23 @@ def test_dixon_lift_matches_oracle(ctx, n, k):
         assert np.array_equal(X.astype(np.int64), ref)
 
 
+def test_dixon_lift_launch_forms_agree(monkeypatch):
+    """The cooperative all-steps kernel and the one-launch-per-phase form give
+    the same digits (and the oracle's)."""
+    import paper_cs_0511066_amd as det
+    n, k = 96, 20
+    A = synth.dense_uniform(n, -100, 100, 31)
+    b = synth.random_rhs(n, 5000, 31)
+    p = test_primes(1 << 25, 1 << 26, 1, 31)[0]
+    with det.Context(0) as c1:
+        X1 = c1.dixon_lift(A, b, p, k)
+    monkeypatch.setenv("DET_LIFT_MODE", "kernels")
+    with det.Context(0) as c2:
+        X2 = c2.dixon_lift(A, b, p, k)
+    assert np.array_equal(X1, X2)
+    assert np.array_equal(X1.astype(np.int64), oracle.dixon_digits(A, b, p, k))
+
+
 def test_dixon_lift_n1024_invariant(ctx):
     """Full size: A x_i = r_i (mod p) and p | r_i - A x_i for the first steps,
     checked with exact integers on the host (no inverse needed)."""

@@ -128,6 +128,32 @@ def test_ratrecon_matches_oracle():
             assert got == oracle.rational_reconstruct(u, m, 1 << half, 1 << half)
 
 
+def test_ratrecon_lehmer_large_prime_power():
+    """p-adic sizes of the lifting (tens of thousands of bits): the Lehmer
+    batches must stop exactly at the first remainder <= N."""
+    rng = random.Random(12)
+    p = 33554393
+    for k in (200, 900):
+        m = p ** k
+        half = (m.bit_length() - 2) // 2
+        for trial in range(4):
+            d = rng.randrange(1, 1 << half)
+            if d % p == 0:
+                d += 1
+            a = rng.randrange(-(1 << half), 1 << half)
+            g = math.gcd(a, d)
+            a, d = a // g, d // g
+            u = a * pow(d, -1, m) % m
+            assert det.det_host_ratrecon(u, m, half, half, prime_base=p) == (a, d)
+            assert det.det_host_ratrecon(u, m, half, half) == (a, d)
+    # bounds just tight enough: numerator and denominator of equal size
+    m = p ** 50
+    d, a = (1 << 600) + 12345, -((1 << 599) + 777)
+    u = a * pow(d, -1, m) % m
+    assert det.det_host_ratrecon(u, m, 601, 601, prime_base=p) == \
+        oracle.rational_reconstruct(u, m, 1 << 601, 1 << 601)
+
+
 def test_ratrecon_rejects_when_out_of_bounds():
     m = 10007 ** 2
     u = 123456 * pow(654321, -1, m) % m
