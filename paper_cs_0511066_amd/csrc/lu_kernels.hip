@@ -26,6 +26,15 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 typedef int v4i __attribute__((ext_vector_type(4)));
 
 // ------------------------------------------------------------------ helpers
+// A value that is the same in every lane, moved to scalar registers (an FP64
+// VALU operation can take one scalar operand, which saves vector registers).
+__device__ __forceinline__ double uniform_d(double x) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, x);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
 __device__ __forceinline__ int wave_min_int(int v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
@@ -52,192 +61,248 @@ __global__ void k_residues(const int64_t* __restrict__ A, int64_t lda, int n, in
 
 // ------------------------------------------------------------------ K2: panel
 // Factor rows [j0, n) x columns [j0, j0+pb) of every item (m = n - j0 rows).
-// One 1024-thread workgroup per item.  Thread t owns rows t, t+1024, ...;
-// for each it keeps the not yet eliminated part of the row in FP64 shift
-// registers (a[q][0] is always the current column j), so every register
-// index is a compile-time constant.  Finished values (multipliers and pivot
-// rows) go to the LDS copy of the panel, sP (int32, m x PB <= 128 KiB), which
-// is written back to HBM at the end.
+// One 512-thread workgroup per item.  Thread t owns rows t, t+512, ...;
+// for each it keeps a window of PB entries of the row in FP64 registers.
+// Columns are taken in groups of 8: the group's columns are unrolled (so
+// register indices are compile-time constants), and at the end of a group
+// the window moves on by 8 columns, which keeps the code small enough for
+// the instruction cache.  Finished values (multipliers and pivot rows) go to
+// the LDS copy of the panel, sP (int32, m x (PB+1)), written back at the end.
 // Pivot = first row at or below the diagonal with a non-zero entry (lowest
-// row index); rows are swapped LAPACK-style (whole panel rows).  Updates are
-// applied without reduction: every row receives the same number of updates,
-// each below h^2 (h = (p-1)/2), so values stay exact while at most kc are
-// pending (kc h^2 + h <= 2^53); the pivot column is reduced before use.
+// row index); rows are swapped LAPACK-style (whole panel rows).  Row j is
+// the pivot unless its entry is 0 mod p, so its owner (thread j) reduces it
+// and inverts its entry before the column's barrier; only when row j's entry
+// vanishes does a second round fetch the pivot row from below.
+// Updates are applied without reduction and every row receives the same
+// number of them, each below h^2 (h = (p-1)/2); the window is reduced every
+// 8 columns (to |v| <= h + 5 by mod_loose), which keeps every value exact
+// (8 h^2 + h + 5 < 2^53 for p < 2^26); the pivot column is reduced before
+// use, multipliers and pivot rows fully (|v| <= h).
 // Outputs: L below the diagonal, U on and above it, piv[j0+j] = global row
 // swapped with row j0+j, flags[z] = 1 if a column has no pivot (det = 0 mod
 // p), Linv = the pb x pb unit lower inverse of L11 and, if Uinv != null, the
 // upper inverse of U11 (both dense PB x PB, zero-padded).
 template <int PB, int RPT>
-__global__ __launch_bounds__(1024) void k_panel(int32_t* __restrict__ W, int64_t ldw, int64_t slab,
+__global__ __launch_bounds__(512) void k_panel(int32_t* __restrict__ W, int64_t ldw, int64_t slab,
                                                 int n, int j0, int pb,
                                                 const Modulus* __restrict__ mods,
                                                 int32_t* __restrict__ piv, int64_t piv_stride,
                                                 int32_t* __restrict__ flags,
                                                 int32_t* __restrict__ Linv,
-                                                int32_t* __restrict__ Uinv, int kc) {
-  constexpr int T = 1024;
+                                                int32_t* __restrict__ Uinv) {
+  constexpr int T = 512;
+  constexpr int NW = T / 64;
   constexpr int MROWS = RPT * T;
   constexpr int SP = PB + 1;                  // LDS row stride: odd, so a column is conflict-free
+  constexpr int GJ = 8;                       // columns per group (and reduction interval)
+  static_assert(PB % GJ == 0 && PB <= 32, "panel width");
   const int z = blockIdx.x;
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
   const double p = mods[z].p, pinv = mods[z].pinv;
+  const uint32_t e_inv = (uint32_t)__builtin_amdgcn_readfirstlane((int)((uint32_t)p - 2u));
   int32_t* Wz = W + (int64_t)z * slab + (int64_t)j0 * ldw + j0;
   const int m = n - j0;
 
-  __shared__ int32_t sP[MROWS * SP];          // finished panel values, row-major
-  __shared__ int s_min[2][T / 64];
-  __shared__ double s_prow[2][PB];
-  __shared__ double s_jrow[2][PB];
+  __shared__ int32_t sP[MROWS * SP];          // the panel; finished values replace the input
+  __shared__ double s_prow[2][PB];            // pivot row, reduced (window columns)
+  __shared__ double s_old[2][PB];             // row j as it was (moves down when swapped)
   __shared__ double s_inv[2];
+  __shared__ int s_min[2][NW];                // each wave's lowest candidate row
   __shared__ double s_dinv[PB];
+  __shared__ int s_piv[PB];
+  __shared__ int s_sing;
 
+  // coalesced load of the panel into LDS (all loads in flight at once), then
+  // each thread takes its rows
+  if (t == 0) s_sing = 0;
+  if (t < 2 * PB) s_prow[t / PB][t % PB] = 0.0;   // finite even where it is not written
+  if (t < PB) s_dinv[t] = 0.0;
+  {
+    constexpr int RS = T / PB;                  // rows per pass of the workgroup
+    const int k = t % PB;
+    constexpr int NL = RPT * PB / 2 < 32 ? RPT * PB / 2 : 32;   // loads in flight per thread
+    static_assert((RPT * PB) % NL == 0, "load batches");
+#pragma unroll 1
+    for (int r0 = t / PB; r0 < MROWS; r0 += NL * RS) {
+      int32_t v[NL];
+#pragma unroll
+      for (int i = 0; i < NL; i++) {
+        const int r = r0 + i * RS;
+        v[i] = (r < m && k < pb) ? Wz[(int64_t)r * ldw + k] : 0;
+      }
+#pragma unroll
+      for (int i = 0; i < NL; i++) sP[(r0 + i * RS) * SP + k] = v[i];
+    }
+  }
+  __syncthreads();
   double a[RPT][PB];
 #pragma unroll
   for (int q = 0; q < RPT; q++) {
     const int row = t + q * T;
 #pragma unroll
-    for (int k = 0; k < PB; k++)
-      a[q][k] = (row < m && k < pb) ? (double)Wz[(int64_t)row * ldw + k] : 0.0;
+    for (int k = 0; k < PB; k++) a[q][k] = row < m ? (double)sP[row * SP + k] : 0.0;
   }
 
-  int pending = 0;
-  for (int j = 0; j < pb; j++) {
-    const int buf = j & 1;
-    int cand = INT_MAX;
+  for (int g = 0; g < pb; g += GJ) {
 #pragma unroll
-    for (int q = 0; q < RPT; q++) {
-      const int row = t + q * T;
-      if (row >= j && row < m) {
-        a[q][0] = mod_c(a[q][0], p, pinv);          // the pivot column must be exact
-        if (a[q][0] != 0.0) cand = min(cand, row);
-      }
-    }
-    cand = wave_min_int(cand);
-    if (lane == 0) s_min[buf][wave] = cand;
-    __syncthreads();                                  // (1) candidates published
-    int pr = INT_MAX;
+    for (int jj = 0; jj < GJ; jj++) {
+      const int j = g + jj;
+      if (j < pb) {
+        const int buf = jj & 1;
+        // lowest row of this wave at or below j with a non-zero entry (the
+        // reduction runs on every row: finished rows are never read again)
+        int wc = INT_MAX;
 #pragma unroll
-    for (int w = 0; w < T / 64; w++) pr = min(pr, s_min[buf][w]);
-    const bool singular = pr == INT_MAX;              // no pivot: det = 0 mod p, row j kept
-    if (singular) pr = j;
-#pragma unroll
-    for (int q = 0; q < RPT; q++) {
-      const int row = t + q * T;
-      if (row == pr) {                                // raw pivot row; reduced below in parallel
-#pragma unroll
-        for (int k = 0; k < PB; k++) s_jrow[buf][k] = a[q][k];
-      }
-    }
-    __syncthreads();                                  // (2) raw pivot row published
-    if (t < PB) s_prow[buf][t] = t == 0 ? s_jrow[buf][0] : mod_c(s_jrow[buf][t], p, pinv);
-    if (t == PB) {
-      const double iv = singular ? 0.0 : inv_mod(s_jrow[buf][0], p, pinv);
-      s_inv[buf] = iv;
-      s_dinv[j] = iv;
-    }
-    // old row j moves down to row pr: its owner stages it in the other buffer
-    // (last read in column j-1 before that column's barrier (3))
-    if (pr != j) {
-#pragma unroll
-      for (int q = 0; q < RPT; q++)
-        if (t + q * T == j) {
-#pragma unroll
-          for (int k = 0; k < PB; k++) s_jrow[buf ^ 1][k] = a[q][k];
+        for (int q = RPT - 1; q >= 0; q--) {
+          const int row = t + q * T;
+          a[q][jj] = mod_loose(a[q][jj], p, pinv);    // exact zero test (|r| < p)
+          const uint64_t bal = __ballot(row >= j && row < m && a[q][jj] != 0.0);
+          if (bal) wc = q * T + wave * 64 + (__ffsll((unsigned long long)bal) - 1);
         }
-    }
-    __syncthreads();                                  // (3) reduced pivot row, inverse, old row j
-    // swap the finished (multiplier) parts of rows j and pr
-    if (pr != j && t < j) {
-      const int32_t v = sP[j * SP + t];
-      sP[j * SP + t] = sP[pr * SP + t];
-      sP[pr * SP + t] = v;
-    }
-    if (t < pb - j) sP[j * SP + j + t] = (int32_t)s_prow[buf][t];   // U row j, in parallel
-    const double inv = s_inv[buf];
+        // row j (thread j, since j < PB <= 64): publish it as it is; if its
+        // entry is non-zero it is the pivot, so reduce it and invert the entry
+        if (wave == 0) {
+          if (t == j) {
 #pragma unroll
-    for (int q = 0; q < RPT; q++) {
-      const int row = t + q * T;
-      if (row == pr && pr != j) {       // old row j moves down to row pr
-        volatile double* src = s_jrow[buf ^ 1];
+            for (int k = 0; k < PB; k++)
+              if (k >= jj) s_old[buf][k] = a[0][k];
+            if (wc == j) s_inv[buf] = pow_mod_fixed(a[0][jj], e_inv, p, pinv);
+          }
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+          if (wc == j && lane >= jj && lane < PB)
+            s_prow[buf][lane] = mod_c(s_old[buf][lane], p, pinv);
+        }
+        if (lane == 0) s_min[buf][wave] = wc;
+        __syncthreads();
+        int pr = INT_MAX;
 #pragma unroll
-        for (int k = 0; k < PB; k++) a[q][k] = src[k];
+        for (int w = 0; w < NW; w++) pr = min(pr, s_min[buf][w]);
+        pr = __builtin_amdgcn_readfirstlane(pr);      // the same in every lane
+        const bool singular = pr == INT_MAX;          // no pivot: det = 0 mod p, row j kept
+        if (singular) pr = j;
+        if (pr != j) {                                // pivot below row j: second round
+          if (wave == ((pr % T) >> 6)) {
+            const int qp = pr / T;
+#pragma unroll
+            for (int q = 0; q < RPT; q++)
+              if (q == qp && t + q * T == pr) {
+#pragma unroll
+                for (int k = 0; k < PB; k++)
+                  if (k >= jj) s_prow[buf][k] = a[q][k];
+                s_inv[buf] = inv_mod_call(a[q][jj], e_inv, p, pinv);
+              }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (lane > jj && lane < PB) s_prow[buf][lane] = mod_c(s_prow[buf][lane], p, pinv);
+            // old row j moves down to row pr (its entry j is 0 mod p)
+#pragma unroll
+            for (int q = 0; q < RPT; q++)
+              if (q == qp && t + q * T == pr) {
+                a[q][jj] = 0.0;
+#pragma unroll
+                for (int k = 1; k < PB; k++)
+                  if (k > jj) a[q][k] = s_old[buf][k];
+              }
+          }
+          __syncthreads();
+          // swap the finished (multiplier) parts of rows j and pr
+          if (t < j) {
+            const int32_t v = sP[j * SP + t];
+            sP[j * SP + t] = sP[pr * SP + t];
+            sP[pr * SP + t] = v;
+          }
+        }
+        // with no pivot, row j stays (U row j = row j) and nothing is eliminated
+        const double inv = uniform_d(singular ? 0.0 : s_inv[buf]);
+        if (t < pb - j)                                                            // U row j
+          sP[j * SP + j + t] = (int32_t)mod_c(singular ? s_old[buf][jj + t] : s_prow[buf][jj + t], p, pinv);
+        double pv[PB];                                // pivot row (same in all lanes)
+#pragma unroll
+        for (int k = 1; k < PB; k++)
+          if (k > jj) pv[k] = s_prow[buf][k];   // any finite values when singular
+        // elimination on every row (rows at or above j, and absent rows, are
+        // never read again); only the multipliers of live rows are stored
+#pragma unroll
+        for (int q = 0; q < RPT; q++) {
+          const int row = t + q * T;
+          const double l = mul_mod(a[q][jj], inv, p, pinv);
+          if (row > j && row < m) sP[row * SP + j] = (int32_t)l;
+#pragma unroll
+          for (int k = 1; k < PB; k++)
+            if (k > jj) a[q][k] = fma(-l, pv[k], a[q][k]);
+        }
+        if (t == 0) {                   // results stay in LDS until the end (no global
+          s_dinv[j] = inv;              // stores inside the loop)
+          s_piv[j] = pr;
+          if (singular) s_sing = 1;
+        }
       }
-      if (row > j && row < m) {
-        const double l = mul_mod(a[q][0], inv, p, pinv);
-        sP[row * SP + j] = (int32_t)l;
-#pragma unroll
-        for (int k = 1; k < PB; k++) a[q][k] = fma(-l, s_prow[buf][k], a[q][k]);
-#pragma unroll
-        for (int k = 0; k + 1 < PB; k++) a[q][k] = a[q][k + 1];
-        a[q][PB - 1] = 0.0;
-      }
     }
-    if (++pending == kc) {
-      pending = 0;
+    // next window: columns g+8 .. g+8+PB-1, reduced (at most 8 updates pending)
 #pragma unroll
-      for (int q = 0; q < RPT; q++)
+    for (int q = 0; q < RPT; q++)
 #pragma unroll
-        for (int k = 0; k < PB; k++) a[q][k] = mod_c(a[q][k], p, pinv);
-    }
-    if (t == 0) {
-      piv[(int64_t)z * piv_stride + j0 + j] = j0 + pr;
-      if (singular) flags[z] = 1;
-    }
+      for (int k = 0; k < PB; k++)
+        a[q][k] = (k + GJ < PB) ? mod_loose(a[q][k + GJ], p, pinv) : 0.0;
   }
   __syncthreads();
-  // write back the whole panel, consecutive threads on consecutive columns
-  for (int e = t; e < m * pb; e += T) {
-    const int r = e / pb, k = e - r * pb;
-    Wz[(int64_t)r * ldw + k] = sP[r * SP + k];
+  // write back the panel, consecutive threads on consecutive columns
+  for (int e = t; e < m * PB; e += T) {
+    const int r = e / PB, k = e % PB;
+    if (k < pb) Wz[(int64_t)r * ldw + k] = sP[r * SP + k];
   }
-  // Linv column c (thread c < PB): X[c][c] = 1,
-  // X[i][c] = -sum_{k=c}^{i-1} L[i][k] X[k][c], reduced every 8 products
-  // (8 h^2 + h <= 2^53 for p < 2^26).
-  if (t < PB) {
-    const int c = t;
-    int32_t* Lz = Linv + (int64_t)z * PB * PB;
+  if (t < pb) piv[(int64_t)z * piv_stride + j0 + t] = j0 + s_piv[t];
+  if (t == 0 && s_sing) flags[z] = 1;
+  // Triangular inverses, lane c of wave 0 (Linv) or wave 1 (Uinv) solving
+  // for one column with the column in registers.  Wave 0 solves L X = I;
+  // wave 1 solves U^T Y = I (U^T is lower triangular with the pivots on its
+  // diagonal), whose column c is row c of U^{-1}:
+  //   x = e_c; for k = 0..pb-1: x[k] = x[k] / diag[k] (final);
+  //            x[i] -= M[i][k] x[k] for i > k
+  // Entries are reduced every 8 steps (8 h^2 + h + 5 < 2^53).
+  if (wave < 2 && lane < PB && (wave == 0 || Uinv != nullptr)) {
+    const bool up = wave == 1;
+    const int cc = lane;
     double x[PB];
 #pragma unroll
-    for (int i = 0; i < PB; i++) x[i] = (i == c && c < pb) ? 1.0 : 0.0;   // constant indices only
+    for (int i = 0; i < PB; i++) x[i] = (i == cc) ? 1.0 : 0.0;
+    // no masks needed: for L, rows i >= pb never feed rows below pb (and are
+    // not written out); for U^T, columns >= pb of sP are 0 and so is dinv
+    if (!up) {
 #pragma unroll
-    for (int i = 1; i < PB; i++) {
-      if (i > c && i < pb) {
-        double s = 0.0;
+      for (int k = 0; k < PB; k++) {
+        x[k] = mod_c(x[k], p, pinv);
 #pragma unroll
-        for (int k = 0; k < PB; k++) {
-          if (k >= c && k < i) s = fma((double)sP[i * SP + k], x[k], s);
-          if ((k & 7) == 7) s = mod_c(s, p, pinv);
+        for (int i = 1; i < PB; i++)
+          if (i > k) x[i] = fma(-(double)sP[i * SP + k], x[k], x[i]);
+        if ((k & 7) == 7) {
+#pragma unroll
+          for (int i = 1; i < PB; i++)
+            if (i > k) x[i] = mod_loose(x[i], p, pinv);
         }
-        x[i] = mod_c(-s, p, pinv);
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < PB; k++) {
+        x[k] = mul_mod(mod_c(x[k], p, pinv), s_dinv[k], p, pinv);
+#pragma unroll
+        for (int i = 1; i < PB; i++)
+          if (i > k) x[i] = fma(-(double)sP[k * SP + i], x[k], x[i]);
+        if ((k & 7) == 7) {
+#pragma unroll
+          for (int i = 1; i < PB; i++)
+            if (i > k) x[i] = mod_loose(x[i], p, pinv);
+        }
       }
     }
+    int32_t* out = (up ? Uinv : Linv) + (int64_t)z * PB * PB;
 #pragma unroll
-    for (int i = 0; i < PB; i++) Lz[i * PB + c] = (i < pb && c < pb) ? (int32_t)x[i] : 0;
-  }
-  if (Uinv == nullptr) return;
-  // Uinv column c: X[c][c] = dinv[c], X[i][c] = -dinv[i] sum_{k=i+1}^{c} U[i][k] X[k][c]
-  if (t < PB) {
-    const int c = t;
-    int32_t* Uz = Uinv + (int64_t)z * PB * PB;
-    double x[PB];
-#pragma unroll
-    for (int i = 0; i < PB; i++) x[i] = (i == c && c < pb) ? s_dinv[i] : 0.0;
-#pragma unroll
-    for (int i = PB - 2; i >= 0; i--) {
-      if (i < c && c < pb) {
-        double s = 0.0;
-#pragma unroll
-        for (int k = PB - 1; k > 0; k--) {
-          if (k > i && k <= c) s = fma((double)sP[i * SP + k], x[k], s);
-          if ((k & 7) == 0) s = mod_c(s, p, pinv);
-        }
-        s = mod_c(s, p, pinv);
-        x[i] = mul_mod(-s, s_dinv[i], p, pinv);
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < PB; i++) Uz[i * PB + c] = (i < pb && c < pb) ? (int32_t)x[i] : 0;
+    for (int i = 0; i < PB; i++)
+      out[up ? cc * PB + i : i * PB + cc] = (i < pb && cc < pb) ? (int32_t)x[i] : 0;
   }
 }
 
@@ -711,18 +776,34 @@ __global__ void k_pack_i32(const int64_t* __restrict__ A, int64_t lda, int n,
 
 // out[j] = sum_i a_ij^2 (columns), out[n + i] = sum_j a_ij^2 (rows), both in
 // FP64 (rounded; the host adds a relative margin), and amax[j] = max_i |a_ij|.
-__global__ void k_col_norms(const int64_t* __restrict__ A, int64_t lda, int n,
-                            double* __restrict__ out, double* __restrict__ amax) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
+// Squared column norms and column maxima: 64 columns per workgroup, the 16
+// waves take interleaved rows and combine through LDS.
+__global__ __launch_bounds__(1024) void k_col_norms(const int64_t* __restrict__ A, int64_t lda,
+                                                    int n, double* __restrict__ out,
+                                                    double* __restrict__ amax) {
+  __shared__ double s_s[16][65];
+  __shared__ double s_m[16][65];
+  const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int j = blockIdx.x * 64 + lane;
   double s = 0.0, m = 0.0;
-  for (int i = 0; i < n; i++) {
-    const double a = (double)A[(int64_t)i * lda + j];
-    s = fma(a, a, s);
-    m = fmax(m, fabs(a));
+  if (j < n) {
+    for (int i = g; i < n; i += 16) {
+      const double a = (double)A[(int64_t)i * lda + j];
+      s = fma(a, a, s);
+      m = fmax(m, fabs(a));
+    }
   }
-  out[j] = s;
-  amax[j] = m;
+  s_s[g][lane] = s;
+  s_m[g][lane] = m;
+  __syncthreads();
+  if (g == 0 && j < n) {
+    for (int w = 1; w < 16; w++) {
+      s += s_s[w][lane];
+      m = fmax(m, s_m[w][lane]);
+    }
+    out[j] = s;
+    amax[j] = m;
+  }
 }
 __global__ __launch_bounds__(256) void k_row_norms(const int64_t* __restrict__ A, int64_t lda,
                                                    int n, double* __restrict__ out) {
@@ -755,13 +836,14 @@ hipError_t launch_panel(int32_t* W, int64_t ldw, int64_t slab, int n, int j0, in
                         const Modulus* mods, int32_t* piv, int64_t piv_stride, int32_t* flags,
                         int32_t* Linv, int32_t* Uinv, int kc, int nitems, hipStream_t st) {
   const int m = n - j0;
-  if (pb > pbw) return hipErrorInvalidValue;
+  // the kernel reduces every 8 columns: exact when kc >= 8 (all p < 2^26)
+  if (pb > pbw || pb > m || kc < 8) return hipErrorInvalidValue;
   if (pbw == 32 && m <= 1024)
-    k_panel<32, 1><<<nitems, 1024, 0, st>>>(W, ldw, slab, n, j0, pb, mods, piv, piv_stride, flags, Linv, Uinv, kc);
+    k_panel<32, 2><<<nitems, 512, 0, st>>>(W, ldw, slab, n, j0, pb, mods, piv, piv_stride, flags, Linv, Uinv);
   else if (pbw == 16 && m <= 2048)
-    k_panel<16, 2><<<nitems, 1024, 0, st>>>(W, ldw, slab, n, j0, pb, mods, piv, piv_stride, flags, Linv, Uinv, kc);
+    k_panel<16, 4><<<nitems, 512, 0, st>>>(W, ldw, slab, n, j0, pb, mods, piv, piv_stride, flags, Linv, Uinv);
   else if (pbw == 8 && m <= 4096)
-    k_panel<8, 4><<<nitems, 1024, 0, st>>>(W, ldw, slab, n, j0, pb, mods, piv, piv_stride, flags, Linv, Uinv, kc);
+    k_panel<8, 8><<<nitems, 512, 0, st>>>(W, ldw, slab, n, j0, pb, mods, piv, piv_stride, flags, Linv, Uinv);
   else
     return hipErrorInvalidValue;
   LAUNCH_CHECK();
@@ -865,7 +947,7 @@ hipError_t launch_pack_i32(const int64_t* A, int64_t lda, int n, int32_t* Ai, hi
 hipError_t launch_norms(const int64_t* A, int64_t lda, int n, double* out2n, double* amax,
                         hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  k_col_norms<<<(n + 255) / 256, 256, 0, st>>>(A, lda, n, out2n, amax);
+  k_col_norms<<<(n + 63) / 64, 1024, 0, st>>>(A, lda, n, out2n, amax);
   LAUNCH_CHECK();
   k_row_norms<<<(n + 3) / 4, 256, 0, st>>>(A, lda, n, out2n);
   LAUNCH_CHECK();

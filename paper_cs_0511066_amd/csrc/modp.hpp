@@ -23,6 +23,12 @@ __device__ __forceinline__ double mod_c(double c, double p, double pinv) {
   return r;
 }
 
+// c mod p without the final fold: |c| <= 2^53 gives a result congruent to c
+// with |r| <= h + 5 (h = (p-1)/2), so r == 0 exactly when p divides c.
+__device__ __forceinline__ double mod_loose(double c, double p, double pinv) {
+  return fma(-rint(c * pinv), p, c);
+}
+
 __device__ __forceinline__ double mul_mod(double a, double b, double p, double pinv) {
   return mod_c(a * b, p, pinv);
 }
@@ -51,6 +57,28 @@ __device__ __forceinline__ double pow_mod(double a, uint32_t e, double p, double
 // Inverse of a non-zero residue by Fermat's little theorem, a^(p-2).
 __device__ __forceinline__ double inv_mod(double a, double p, double pinv) {
   return pow_mod(a, (uint32_t)p - 2u, p, pinv);
+}
+
+// a^e mod p for e < 2^26: a fixed 26-step ladder with selects instead of
+// branches (the exponent is wave-uniform).  Fully unrolled: a taken branch
+// costs more than a step of the dependent chain.
+__device__ __forceinline__ double pow_mod_fixed(double a, uint32_t e, double p, double pinv) {
+  double r = 1.0;
+  double b = a;
+#pragma unroll
+  for (int i = 0; i < 26; i++) {
+    const double rb = mul_mod_loose(r, b, p, pinv);
+    r = ((e >> i) & 1u) ? rb : r;
+    b = mul_mod_loose(b, b, p, pinv);
+  }
+  return mod_c(r, p, pinv);
+}
+
+// Out-of-line inverse of a non-zero residue (a^(p-2)), so that call sites in
+// unrolled code share one copy of the ladder.
+__device__ __attribute__((noinline)) double inv_mod_call(double a, uint32_t e, double p,
+                                                         double pinv) {
+  return pow_mod_fixed(a, e, p, pinv);
 }
 
 // Canonical residue in [0, p) of a centred one.
