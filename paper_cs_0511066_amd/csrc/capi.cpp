@@ -63,10 +63,12 @@ struct det_ctx {
   hipEvent_t ev = nullptr;       // orders own2 after work queued on st
   std::string err;
   LuWs ws[2];
-  DevBuf Adev, norms, amax, Cu, Ai, r, rp, x, digits, comb, cvec, sync, C1, E, rp1, x1;
+  DevBuf Adev, norms, amax, Cu, Ai, r, rp, x, digits, comb, cvec, sync, C1, E, rp1, x1, C2, Ed,
+      rp2, x2;
   uint32_t* hres = nullptr;      // pinned host residues of the background batch
   size_t hres_cap = 0;
-  int lift_mode = 0;             // 0: register-resident cooperative kernel when possible
+  int lift_mode = 0;             // 0: fastest cooperative form that applies; 1: one launch per
+                                 // phase; 2: the 64-bit integer form modulo p^2
   // kernel timing (det_profile_select / det_profile_read)
   int prof_kind = 0;
   int64_t prof_launches = 0;
@@ -492,15 +494,20 @@ det_status inverse_mod_p(det_ctx* c, const int64_t* dA, int64_t dlda, int n, uin
   return DET_OK;
 }
 
+// The FP64 three-digit lifting is exact for p < 2^25 and n ||A|| p < 2^53.
+bool lift3_applies(int n, double amax, uint32_t p) {
+  return p < (1u << 25) && (double)n * std::max(amax, 1.0) * (double)p < ldexp(1.0, 53);
+}
+
 // k Dixon steps from r_0 = b on c->st.  digits_dev: k x n output (may be null
 // when only the combinations are wanted); comb_dev: k sums of cvec . x_i (may
 // be null).
 // The cooperative form needs all its workgroups resident at once, so when
 // other work may be running on the context's second stream (`after_own2`),
 // the launch first waits for that stream.
-det_status lift(det_ctx* c, const int64_t* dA, int64_t dlda, int n, const int64_t* b, uint32_t p,
-                int64_t k, uint32_t* digits_dev, const uint32_t* cvec_dev, uint64_t* comb_dev,
-                bool after_own2 = false) {
+det_status lift(det_ctx* c, const int64_t* dA, int64_t dlda, int n, double amax, const int64_t* b,
+                uint32_t p, int64_t k, uint32_t* digits_dev, const uint32_t* cvec_dev,
+                uint64_t* comb_dev, bool after_own2 = false) {
   // rp and x are padded with zeros to lift_pad(n) entries (the
   // register-resident kernel loads 64 EPL entries without bounds tests)
   const int64_t npad = lift_pad(n);
@@ -520,7 +527,62 @@ det_status lift(det_ctx* c, const int64_t* dA, int64_t dlda, int n, const int64_
   HIPCHK(hipMemcpyAsync(c->rp.p, rp0.data(), n * sizeof(uint32_t), hipMemcpyHostToDevice, c->st));
   const uint64_t pinv64 = inv_mod_2_64(p);
   const double nn = (double)n * n;
-  const int grid = c->lift_mode == 0 ? detk::lift_persistent_grid(c->device, n) : 0;
+  const int grid3 = c->lift_mode == 0 && lift3_applies(n, amax, p) ? detk::lift3_grid(c->device, n) : 0;
+  if (grid3 > 0) {
+    // lifting modulo p^3 in FP64: Hensel planes, then three digits a step
+    TRY(ensure(c, c->C1, (size_t)n * n * sizeof(uint32_t)));
+    TRY(ensure(c, c->C2, (size_t)n * n * sizeof(uint32_t)));
+    TRY(ensure(c, c->Ed, (size_t)n * n * sizeof(double)));
+    TRY(ensure(c, c->rp1, (size_t)npad * sizeof(uint32_t)));
+    TRY(ensure(c, c->rp2, (size_t)npad * sizeof(uint32_t)));
+    TRY(ensure(c, c->x1, (size_t)npad * sizeof(uint32_t)));
+    TRY(ensure(c, c->x2, (size_t)npad * sizeof(uint32_t)));
+    TRY(ensure(c, c->sync, 64));
+    for (DevBuf* v : {&c->rp1, &c->rp2, &c->x1, &c->x2})
+      HIPCHK(hipMemsetAsync(v->p, 0, npad * sizeof(uint32_t), c->st));
+    HIPCHK(hipMemsetAsync(c->sync.p, 0, 64, c->st));
+    // balanced digits of b mod p^3 (each centring carried into the next digit)
+    std::vector<int32_t> d3(3 * (size_t)n);
+    for (int j = 0; j < n; j++) {
+      int64_t v = b[j];
+      for (int q = 0; q < 3; q++) {
+        int64_t m = v % (int64_t)p;
+        if (m < 0) m += p;
+        if (m > (int64_t)(p - 1) / 2) m -= p;
+        d3[(size_t)q * n + j] = (int32_t)m;
+        v = (v - m) / (int64_t)p;                  // exact
+      }
+    }
+    HIPCHK(hipMemcpyAsync(c->rp.p, d3.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, c->st));
+    HIPCHK(hipMemcpyAsync(c->rp1.p, d3.data() + n, n * sizeof(int32_t), hipMemcpyHostToDevice, c->st));
+    HIPCHK(hipMemcpyAsync(c->rp2.p, d3.data() + 2 * (size_t)n, n * sizeof(int32_t),
+                          hipMemcpyHostToDevice, c->st));
+    HIPCHK(detk::launch_hensel_f64((const int32_t*)c->Ai.p, (const uint32_t*)c->Cu.p,
+                                   (double*)c->Ed.p, (uint32_t*)c->C1.p, (uint32_t*)c->C2.p, n, p,
+                                   c->st));
+    if (after_own2) {
+      HIPCHK(hipEventRecord(c->ev, c->own2));
+      HIPCHK(hipStreamWaitEvent(c->st, c->ev, 0));
+    }
+    unsigned* bar = (unsigned*)c->sync.p;
+    int* err = (int*)((char*)c->sync.p + 32);
+    {
+      // algorithmic bytes per digit: C and A as the one-launch-per-phase form
+      // reads them (8 n^2) and four n-vectors
+      ProfScope ps(c, DET_KERNEL_LIFT, (8.0 * nn + 40.0 * n) * k, 4.0 * nn * k, c->st);
+      HIPCHK(detk::launch_lift_resident3(
+          grid3, (const uint32_t*)c->Cu.p, (const uint32_t*)c->C1.p, (const uint32_t*)c->C2.p,
+          (const int32_t*)c->Ai.p, (int64_t*)c->r.p, (uint32_t*)c->rp.p, (uint32_t*)c->rp1.p,
+          (uint32_t*)c->rp2.p, (uint32_t*)c->x.p, (uint32_t*)c->x1.p, (uint32_t*)c->x2.p, n, p,
+          pinv64, k, digits_dev, cvec_dev, comb_dev, bar, err, c->st));
+    }
+    int herr = 0;
+    HIPCHK(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    if (herr) return fail(c, DET_E_DEVICE, "lifting grid barrier timed out");
+    return DET_OK;
+  }
+  const int grid = c->lift_mode != 1 ? detk::lift_persistent_grid(c->device, n) : 0;
   if (grid > 0) {
     // lifting modulo p^2: Hensel step for the inverse, then two digits a step
     TRY(ensure(c, c->C1, (size_t)n * n * sizeof(uint32_t)));
@@ -658,6 +720,7 @@ det_status det_ctx_create(int device, size_t hbm_budget_bytes, det_ctx** out) {
   c->ws[1].st = c->own2;
   const char* lm = getenv("DET_LIFT_MODE");     // "kernels": one launch per lifting phase
   if (lm && strcmp(lm, "kernels") == 0) c->lift_mode = 1;
+  if (lm && strcmp(lm, "p2") == 0) c->lift_mode = 2;
   *out = c;
   return DET_OK;
 }
@@ -669,7 +732,7 @@ void det_ctx_destroy(det_ctx* c) {
   if (c->own2) (void)hipStreamSynchronize(c->own2);
   std::vector<DevBuf*> all = {&c->Adev, &c->norms, &c->amax, &c->Cu, &c->Ai, &c->r, &c->rp,
                               &c->x, &c->digits, &c->comb, &c->cvec, &c->sync, &c->C1, &c->E,
-                              &c->rp1, &c->x1};
+                              &c->rp1, &c->x1, &c->C2, &c->Ed, &c->rp2, &c->x2};
   for (LuWs& w : c->ws)
     for (DevBuf* b : {&w.W, &w.piv, &w.flags, &w.mods, &w.linv, &w.uinv, &w.tinv, &w.limbA,
                       &w.limbB, &w.res})
@@ -795,7 +858,7 @@ det_status dixon_lift(det_ctx* c, const int64_t* A, int64_t n, int64_t lda, cons
       return fail(c, DET_E_OVERFLOW, "n ||A|| p >= 2^62");
     TRY(inverse_mod_p(c, dA, dlda, (int)n, p));
     TRY(ensure(c, c->digits, (size_t)k * n * sizeof(uint32_t)));
-    TRY(lift(c, dA, dlda, (int)n, b, p, k, (uint32_t*)c->digits.p, nullptr, nullptr));
+    TRY(lift(c, dA, dlda, (int)n, bd.amax, b, p, k, (uint32_t*)c->digits.p, nullptr, nullptr));
     HIPCHK(hipMemcpyAsync(digits, c->digits.p, (size_t)k * n * sizeof(uint32_t),
                           hipMemcpyDeviceToHost, c->st));
     HIPCHK(hipStreamSynchronize(c->st));
@@ -871,7 +934,12 @@ det_status det_introspective(det_ctx* c, const int64_t* A, int64_t n, int64_t ld
     // ---------------- LIF: s~_n from Dixon solvings (Section 2.2)
     BigInt K = BigInt::from_i64(1);
     const double tl0 = now_ms();
+    // 25-bit primes when the FP64 three-digit lifting applies, else the
+    // largest below 2^26 with n ||A|| p < 2^62 (64-bit integer lifting)
     int dixon_bits = 26;
+    if (c->lift_mode == 0 && lift3_applies((int)n, bd.amax, (1u << 25) - 1) &&
+        detk::lift3_grid(c->device, (int)n) > 0)
+      dixon_bits = 25;
     while (dixon_bits > 12 && (double)n * bd.amax * ldexp(1.0, dixon_bits) >= ldexp(1.0, 62))
       dixon_bits--;
     const int64_t beta = std::max<int64_t>(2, (int64_t)ceil(bd.log2_h));
@@ -906,7 +974,7 @@ det_status det_introspective(det_ctx* c, const int64_t* A, int64_t n, int64_t ld
         TRY(ensure(c, c->comb, (size_t)k * sizeof(uint64_t)));
         HIPCHK(hipMemsetAsync(c->cvec.p, 0, lift_pad(n) * sizeof(uint32_t), c->st));
         HIPCHK(hipMemcpyAsync(c->cvec.p, cv.data(), n * sizeof(uint32_t), hipMemcpyHostToDevice, c->st));
-        TRY(lift(c, dA, dlda, (int)n, b.data(), p, k, nullptr, (const uint32_t*)c->cvec.p,
+        TRY(lift(c, dA, dlda, (int)n, bd.amax, b.data(), p, k, nullptr, (const uint32_t*)c->cvec.p,
                  (uint64_t*)c->comb.p, true));
         std::vector<uint64_t> comb(k);
         HIPCHK(hipMemcpyAsync(comb.data(), c->comb.p, k * sizeof(uint64_t), hipMemcpyDeviceToHost, c->st));

@@ -14,6 +14,7 @@
 #include <stdint.h>
 
 #include "kernels.hpp"
+#include "modp.hpp"
 
 namespace detk {
 
@@ -536,6 +537,408 @@ hipError_t launch_lift_resident2(int grid, const uint32_t* C0, const uint32_t* C
   else if (epl == 8) f = (const void*)k_lift_resident2<8, 4>;
   else if (epl == 16) f = (const void*)k_lift_resident2<16, 2>;
   if (!f || grid != (n + 8 * rpw - 1) / (8 * rpw)) return hipErrorInvalidValue;
+  return hipLaunchCooperativeKernel(f, dim3(grid), dim3(512), args, 0, st);
+}
+
+// Shape of the three-plane kernel: 8 waves per workgroup, 2 rows per wave.
+static int lift3_grid_size(int n) { return (n + 15) / 16; }
+
+int lift3_grid(int device, int n) {
+  int cus = 0, coop = 0;
+  if (n > 1024) return 0;
+  if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, device) != hipSuccess ||
+      !coop)
+    return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
+    return 0;
+  const int grid = lift3_grid_size(n);
+  return grid <= cus ? grid : 0;
+}
+
+// ------------------------------------------------------------------ lifting modulo p^3 in FP64
+// For p < 2^25 and n ||A|| p < 2^53 every product and partial sum below is an
+// integer of magnitude < 2^53, so FP64 arithmetic is exact and runs at the
+// full vector rate (64-bit integer multiplies run at a quarter of it).
+//
+// Hensel planes of C = A^{-1} mod p^3, C = c0 + p c1 + p^2 c2, by the
+// linear Hensel recursion with full integer error matrices:
+//   E_1 = (A c0 - I) / p,  C_k = -c0 E_k mod p,  E_{k+1} = (E_k + A c_k) / p,
+// where c_k is the centred representative of the stored plane C_k in [0, p)
+// (A C^{(k)} = I + p^k E_k exactly, and E_k + A c_k = 0 mod p).  The lifting
+// kernel uses the same centred representatives.
+//
+// k_hensel_f64<MODE>: 64x64 output tile per 256-thread workgroup, 4x4
+// outputs per thread, K in chunks of 16 through LDS.
+//   MODE 0: Eout = (Ein + A Ck) / p   (Ein = -I when Ein == null; |E| <= n ||A||)
+//   MODE 1: Cout = (-C0 E) mod p in [0, p)  (E reduced to centred residues
+//           first; products < 2^48, reduced every 32 k-steps)
+template <int MODE>
+__global__ __launch_bounds__(256) void k_hensel_f64(const void* __restrict__ Lv,
+                                                    const void* __restrict__ Rv,
+                                                    const double* __restrict__ Ein, int n,
+                                                    uint32_t p, double pinv, void* __restrict__ out) {
+  const int t = threadIdx.x;
+  const int ty = t >> 4, tx = t & 15;
+  const int row0 = blockIdx.y * 64, col0 = blockIdx.x * 64;
+  const double pd = (double)p, h = 0.5 * pd;
+  __shared__ double sL[16][65];
+  __shared__ double sR[16][65];
+  double acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; i++)
+#pragma unroll
+    for (int j = 0; j < 4; j++) acc[i][j] = 0.0;
+  int since = 0;
+  for (int k0 = 0; k0 < n; k0 += 16) {
+    for (int e = t; e < 64 * 16; e += 256) {
+      const int r = e >> 4, kk = e & 15;
+      const int gr = row0 + r, gk = k0 + kk;
+      double v = 0.0;
+      if (gr < n && gk < n) {
+        if (MODE == 0) {
+          v = (double)((const int32_t*)Lv)[(int64_t)gr * n + gk];
+        } else {
+          const double u = (double)((const uint32_t*)Lv)[(int64_t)gr * n + gk];
+          v = u > h ? u - pd : u;
+        }
+      }
+      sL[kk][r] = v;
+      const int kr = e >> 6, cc = e & 63;
+      const int gk2 = k0 + kr, gc = col0 + cc;
+      double w = 0.0;
+      if (gk2 < n && gc < n) {
+        if (MODE == 0) {
+          const double u = (double)((const uint32_t*)Rv)[(int64_t)gk2 * n + gc];
+          w = u > h ? u - pd : u;
+        } else {
+          w = mod_c(((const double*)Rv)[(int64_t)gk2 * n + gc], pd, pinv);
+        }
+      }
+      sR[kr][cc] = w;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; kk++) {
+      double a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; i++) a[i] = sL[kk][ty * 4 + i];
+#pragma unroll
+      for (int j = 0; j < 4; j++) b[j] = sR[kk][tx * 4 + j];
+#pragma unroll
+      for (int i = 0; i < 4; i++)
+#pragma unroll
+        for (int j = 0; j < 4; j++) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+    }
+    if (MODE == 1 && (since += 16) == 32) {
+      since = 0;
+#pragma unroll
+      for (int i = 0; i < 4; i++)
+#pragma unroll
+        for (int j = 0; j < 4; j++) acc[i][j] = mod_loose(acc[i][j], pd, pinv);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; i++)
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      const int gr = row0 + ty * 4 + i, gc = col0 + tx * 4 + j;
+      if (gr >= n || gc >= n) continue;
+      const int64_t o = (int64_t)gr * n + gc;
+      if (MODE == 0) {
+        // E + A C_k is an exact multiple of p: rint of the scaled value is
+        // the exact quotient
+        const double ein = Ein ? Ein[o] : (gr == gc ? -1.0 : 0.0);
+        ((double*)out)[o] = rint((ein + acc[i][j]) * pinv);
+      } else {
+        double v = mod_c(-acc[i][j], pd, pinv);
+        ((uint32_t*)out)[o] = (uint32_t)(v < 0 ? v + pd : v);
+      }
+    }
+}
+
+__device__ __forceinline__ int wave_sum_i32(int v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__device__ __forceinline__ double wave_sum_f64(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Wave sums through DPP row operations (quad permutes, row rotations, row
+// broadcasts): six VALU steps instead of six LDS round trips; the total is
+// read from lane 63 and is the same in every lane afterwards.
+__device__ __forceinline__ int dpp_sum_i32(int x) {
+  x += __builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false);    // quad_perm [1,0,3,2]
+  x += __builtin_amdgcn_update_dpp(0, x, 0x4E, 0xF, 0xF, false);    // quad_perm [2,3,0,1]
+  x += __builtin_amdgcn_update_dpp(0, x, 0x124, 0xF, 0xF, false);   // row_ror:4
+  x += __builtin_amdgcn_update_dpp(0, x, 0x128, 0xF, 0xF, false);   // row_ror:8
+  x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xA, 0xF, false);   // row_bcast:15
+  x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xC, 0xF, false);   // row_bcast:31
+  return __builtin_amdgcn_readlane(x, 63);
+}
+
+template <int CTRL, int RMASK>
+__device__ __forceinline__ double dpp_mov_f64(double x) {
+  const long long b = __builtin_bit_cast(long long, x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, RMASK, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, RMASK, 0xF, false);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+
+// Exact when every partial sum is an integer below 2^53 in magnitude.
+__device__ __forceinline__ double dpp_sum_f64(double x) {
+  x += dpp_mov_f64<0xB1, 0xF>(x);
+  x += dpp_mov_f64<0x4E, 0xF>(x);
+  x += dpp_mov_f64<0x124, 0xF>(x);
+  x += dpp_mov_f64<0x128, 0xF>(x);
+  x += dpp_mov_f64<0x142, 0xA>(x);
+  x += dpp_mov_f64<0x143, 0xC>(x);
+  const long long b = __builtin_bit_cast(long long, x);
+  const int lo = __builtin_amdgcn_readlane((int)b, 63);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+
+__device__ __forceinline__ int32_t centred_i32(uint32_t u, uint32_t p) {
+  return u > (p - 1) / 2 ? (int32_t)u - (int32_t)p : (int32_t)u;
+}
+
+// All lifting steps modulo p^3 in FP64, three base-p digits per step, with
+// the centred planes c0, c1, c2 of A^{-1} mod p^3 and the rows of A in
+// registers: wave w of workgroup g (NWAVE waves) owns rows
+// (NWAVE g + w) RPW + i, lane l columns l + 64 e (e < EPL).  Vectors crossing
+// the barriers: the three digit planes of r mod p^3, balanced (|digit| <=
+// (p-1)/2, stored as int32 bits, r = w0 + p w1 + p^2 w2 mod p^3), and the
+// three digit planes of x in [0, p).
+// Phase X, per lane over its EPL columns (w_q = centred digit q of r):
+//   S0 = sum c0 w0, S1 = sum c0 w1 + c1 w0, S2 = sum c0 w2 + c1 w1 + c2 w0,
+// each partial sum of 16 products below 2^52; carries are taken lane by lane
+// (S0 = q0 p + m0, ...), so the three lane digits m0, m1, m2 are small and
+// their wave sums fit in int32; digits of x follow with a carry pass.
+// Phase R: D_q = A x_q (|D_q| <= n ||A|| p < 2^53) and
+//   r' = (((r - D0)/p - D1)/p - D2)/p   in exact int64 arithmetic.
+template <int EPL, int RPW, int NWAVE>
+__global__ __launch_bounds__(64 * NWAVE) void k_lift_resident3(
+    const uint32_t* __restrict__ C0, const uint32_t* __restrict__ C1,
+    const uint32_t* __restrict__ C2, const int32_t* __restrict__ Ai, int64_t* __restrict__ r,
+    uint32_t* rp0, uint32_t* rp1, uint32_t* rp2, uint32_t* xb0, uint32_t* xb1, uint32_t* xb2,
+    int n, uint32_t p, double pinv, uint64_t pinv64, int64_t kd,
+    uint32_t* __restrict__ digits, const uint32_t* __restrict__ cvec,
+    uint64_t* __restrict__ comb, unsigned* bar, int* err, unsigned spin_limit) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int G = gridDim.x;
+  const double pd = (double)p;
+  // the three planes of the vector a phase reads, staged once per workgroup
+  // (64 EPL entries each; the workgroup's threads load them together)
+  __shared__ uint32_t sV[3][64 * EPL];
+  auto stage3 = [&](uint32_t (*s)[64 * EPL], const uint32_t* v0, const uint32_t* v1,
+                    const uint32_t* v2) {
+    for (int j = threadIdx.x; j < 64 * EPL; j += 64 * NWAVE) {
+      const uint32_t a0 = v0[j], a1 = v1[j], a2 = v2[j];
+      s[0][j] = a0;
+      s[1][j] = a1;
+      s[2][j] = a2;
+    }
+    __syncthreads();
+  };
+  // the workgroup's rows of A live in LDS (only phase R reads them), the
+  // three planes in registers (only phase X reads them)
+  __shared__ int32_t sA[NWAVE * RPW][64 * EPL];
+  int32_t c0[RPW][EPL], c1[RPW][EPL], c2[RPW][EPL];
+  int64_t rr[RPW];
+  int rows[RPW];
+#pragma unroll
+  for (int i = 0; i < RPW; i++) {
+    const int row = (blockIdx.x * NWAVE + wave) * RPW + i;
+    rows[i] = row;
+    rr[i] = 0;
+#pragma unroll
+    for (int e = 0; e < EPL; e++) {
+      const int j = lane + 64 * e;
+      const bool in = row < n && j < n;
+      const int64_t o = (int64_t)row * n + j;
+      c0[i][e] = in ? centred_i32(C0[o], p) : 0;
+      c1[i][e] = in ? centred_i32(C1[o], p) : 0;
+      c2[i][e] = in ? centred_i32(C2[o], p) : 0;
+      sA[wave * RPW + i][j] = in ? Ai[o] : 0;
+    }
+    if (row < n && lane == 0) rr[i] = r[row];
+  }
+  unsigned target = 0;
+  const int64_t steps = (kd + 2) / 3;
+  for (int64_t step = 0; step < steps; step++) {
+    const int z = (int)(step >> 62);               // 0: step < 2^62
+    // ---- phase X
+    double S0[RPW], S1a[RPW], S1b[RPW], S2a[RPW], S2b[RPW], S2c[RPW];
+#pragma unroll
+    for (int i = 0; i < RPW; i++) S0[i] = S1a[i] = S1b[i] = S2a[i] = S2b[i] = S2c[i] = 0.0;
+    stage3(sV, rp0, rp1, rp2);
+#pragma unroll
+    for (int e = 0; e < EPL; e++) {
+      const double w0 = (double)(int32_t)sV[0][lane + 64 * e];     // balanced digits
+      const double w1 = (double)(int32_t)sV[1][lane + 64 * e];
+      const double w2 = (double)(int32_t)sV[2][lane + 64 * e];
+#pragma unroll
+      for (int i = 0; i < RPW; i++) {
+        // the planes stay int32 in registers and are converted at each use;
+        // z (always 0, not known to the compiler) keeps FP64 copies of them
+        // (twice the registers) from being hoisted out of the step loop
+        const double x0 = (double)(c0[i][e] ^ z), x1 = (double)(c1[i][e] ^ z),
+                     x2 = (double)(c2[i][e] ^ z);
+        S0[i] = fma(x0, w0, S0[i]);
+        S1a[i] = fma(x0, w1, S1a[i]);
+        S1b[i] = fma(x1, w0, S1b[i]);
+        S2a[i] = fma(x0, w2, S2a[i]);
+        S2b[i] = fma(x1, w1, S2b[i]);
+        S2c[i] = fma(x2, w0, S2c[i]);
+      }
+      // one column at a time: otherwise every conversion of the phase is
+      // scheduled up front and the planes spill
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    // (absent rows, whose planes are 0, run through as well: a conditional
+    // here would let the compiler sink the row's products into it, out of
+    // the column-by-column schedule above)
+#pragma unroll
+    for (int i = 0; i < RPW; i++) {
+      {
+        const double q0 = rint(S0[i] * pinv), m0 = fma(-q0, pd, S0[i]);
+        const double qa = rint(S1a[i] * pinv), ma = fma(-qa, pd, S1a[i]);
+        const double T1 = ma + S1b[i] + q0;
+        const double q1 = rint(T1 * pinv), m1 = fma(-q1, pd, T1);
+        const double T2 = mod_loose(S2a[i], pd, pinv) + mod_loose(S2b[i], pd, pinv) +
+                          mod_loose(S2c[i], pd, pinv) + qa + q1;
+        const double m2 = mod_loose(T2, pd, pinv);
+        const int64_t M0 = dpp_sum_i32((int)m0);
+        const int64_t M1 = dpp_sum_i32((int)m1);
+        const int64_t M2 = dpp_sum_i32((int)m2);
+        if (rows[i] < n && lane == 0) {
+          // carries by exact division (multiplication by p^{-1} mod 2^64)
+          const uint32_t x0 = smod64(M0, p, pinv);
+          const int64_t t1 = M1 + (int64_t)((uint64_t)(M0 - (int64_t)x0) * pinv64);
+          const uint32_t x1 = smod64(t1, p, pinv);
+          const int64_t t2 = M2 + (int64_t)((uint64_t)(t1 - (int64_t)x1) * pinv64);
+          const uint32_t x2 = smod64(t2, p, pinv);
+          xb0[rows[i]] = x0;
+          xb1[rows[i]] = x1;
+          xb2[rows[i]] = x2;
+          if (digits) {
+            digits[(3 * step) * n + rows[i]] = x0;
+            if (3 * step + 1 < kd) digits[(3 * step + 1) * n + rows[i]] = x1;
+            if (3 * step + 2 < kd) digits[(3 * step + 2) * n + rows[i]] = x2;
+          }
+        }
+      }
+    }
+    target += G;
+    grid_barrier(bar, target, err, spin_limit);
+    // ---- phase R
+    double D0[RPW], D1[RPW], D2[RPW];
+#pragma unroll
+    for (int i = 0; i < RPW; i++) D0[i] = D1[i] = D2[i] = 0.0;
+    double cs0 = 0.0, cs1 = 0.0, cs2 = 0.0;
+    const bool do_comb = comb != nullptr && blockIdx.x == 0 && wave == 0;
+    stage3(sV, xb0, xb1, xb2);
+#pragma unroll
+    for (int e = 0; e < EPL; e++) {
+      const double x0 = (double)sV[0][lane + 64 * e];
+      const double x1 = (double)sV[1][lane + 64 * e];
+      const double x2 = (double)sV[2][lane + 64 * e];
+      if (do_comb) {
+        const double cv = (double)cvec[lane + 64 * e];
+        cs0 = fma(cv, x0, cs0);
+        cs1 = fma(cv, x1, cs1);
+        cs2 = fma(cv, x2, cs2);
+      }
+#pragma unroll
+      for (int i = 0; i < RPW; i++) {
+        const double av = (double)sA[wave * RPW + i][lane + 64 * e];
+        D0[i] = fma(av, x0, D0[i]);
+        D1[i] = fma(av, x1, D1[i]);
+        D2[i] = fma(av, x2, D2[i]);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if (do_comb) {                       // cvec < 2^16, x < 2^25: sums < 2^51
+      cs0 = dpp_sum_f64(cs0);
+      cs1 = dpp_sum_f64(cs1);
+      cs2 = dpp_sum_f64(cs2);
+      if (lane == 0) {
+        comb[3 * step] = (uint64_t)cs0;
+        if (3 * step + 1 < kd) comb[3 * step + 1] = (uint64_t)cs1;
+        if (3 * step + 2 < kd) comb[3 * step + 2] = (uint64_t)cs2;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < RPW; i++) {
+      {
+        const double d0 = dpp_sum_f64(D0[i]);
+        const double d1 = dpp_sum_f64(D1[i]);
+        const double d2 = dpp_sum_f64(D2[i]);
+        if (rows[i] < n && lane == 0) {
+          // exact divisions by p through p^{-1} mod 2^64
+          int64_t q = (int64_t)((uint64_t)(rr[i] - (int64_t)d0) * pinv64);
+          q = (int64_t)((uint64_t)(q - (int64_t)d1) * pinv64);
+          q = (int64_t)((uint64_t)(q - (int64_t)d2) * pinv64);
+          rr[i] = q;
+          // balanced digits of r' mod p^3, the carry of each centring taken
+          // into the next digit, so that m0 + p m1 + p^2 m2 = r' (mod p^3)
+          const int32_t m0 = centred_i32(smod64(q, p, pinv), p);
+          const int64_t u1 = (int64_t)((uint64_t)(q - (int64_t)m0) * pinv64);
+          const int32_t m1 = centred_i32(smod64(u1, p, pinv), p);
+          const int64_t u2 = (int64_t)((uint64_t)(u1 - (int64_t)m1) * pinv64);
+          rp0[rows[i]] = (uint32_t)m0;
+          rp1[rows[i]] = (uint32_t)m1;
+          rp2[rows[i]] = (uint32_t)centred_i32(smod64(u2, p, pinv), p);
+        }
+      }
+    }
+    target += G;
+    grid_barrier(bar, target, err, spin_limit);
+  }
+#pragma unroll
+  for (int i = 0; i < RPW; i++)
+    if (rows[i] < n && lane == 0) r[rows[i]] = rr[i];
+}
+
+hipError_t launch_hensel_f64(const int32_t* Ai, const uint32_t* C0, double* E, uint32_t* C1,
+                             uint32_t* C2, int n, uint32_t p, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  dim3 grid((n + 63) / 64, (n + 63) / 64);
+  const double pinv = 1.0 / (double)p;
+  k_hensel_f64<0><<<grid, 256, 0, st>>>((const void*)Ai, (const void*)C0, nullptr, n, p, pinv, E);
+  k_hensel_f64<1><<<grid, 256, 0, st>>>((const void*)C0, (const void*)E, nullptr, n, p, pinv, C1);
+  k_hensel_f64<0><<<grid, 256, 0, st>>>((const void*)Ai, (const void*)C1, E, n, p, pinv, E);
+  k_hensel_f64<1><<<grid, 256, 0, st>>>((const void*)C0, (const void*)E, nullptr, n, p, pinv, C2);
+  return hipGetLastError();
+}
+
+hipError_t launch_lift_resident3(int grid, const uint32_t* C0, const uint32_t* C1,
+                                 const uint32_t* C2, const int32_t* Ai, int64_t* r,
+                                 uint32_t* rp0, uint32_t* rp1, uint32_t* rp2, uint32_t* xb0,
+                                 uint32_t* xb1, uint32_t* xb2, int n, uint32_t p,
+                                 uint64_t pinv64, int64_t kd, uint32_t* digits,
+                                 const uint32_t* cvec, uint64_t* comb, unsigned* bar, int* err,
+                                 hipStream_t st) {
+  if (n <= 0 || kd <= 0) return hipSuccess;
+  if (p >= (1u << 25)) return hipErrorInvalidValue;
+  double pinv = 1.0 / (double)p;
+  unsigned spin_limit = 1u << 22;     // ~0.1 s of polling per barrier at most
+  void* args[] = {(void*)&C0, (void*)&C1, (void*)&C2, (void*)&Ai, (void*)&r, (void*)&rp0,
+                  (void*)&rp1, (void*)&rp2, (void*)&xb0, (void*)&xb1, (void*)&xb2, (void*)&n,
+                  (void*)&p, (void*)&pinv, (void*)&pinv64, (void*)&kd, (void*)&digits,
+                  (void*)&cvec, (void*)&comb, (void*)&bar, (void*)&err, (void*)&spin_limit};
+  const void* f = nullptr;
+  if (n <= 256) f = (const void*)k_lift_resident3<4, 2, 8>;
+  else if (n <= 512) f = (const void*)k_lift_resident3<8, 2, 8>;
+  else if (n <= 1024) f = (const void*)k_lift_resident3<16, 2, 8>;
+  if (!f || grid != lift3_grid_size(n)) return hipErrorInvalidValue;
   return hipLaunchCooperativeKernel(f, dim3(grid), dim3(512), args, 0, st);
 }
 

@@ -153,32 +153,40 @@ def test_dixon_lift_matches_oracle(ctx, n, k):
 
 
 def test_dixon_lift_launch_forms_agree(monkeypatch):
-    """The cooperative all-steps kernel and the one-launch-per-phase form give
-    the same digits (and the oracle's)."""
+    """The cooperative all-steps kernels (FP64 modulo p^3, 64-bit integer
+    modulo p^2) and the one-launch-per-phase form give the same digits (and
+    the oracle's); k = 20 is not a multiple of 2 or 3 digits per step."""
     import paper_cs_0511066_amd as det
     n, k = 96, 20
     A = synth.dense_uniform(n, -100, 100, 31)
     b = synth.random_rhs(n, 5000, 31)
-    p = test_primes(1 << 25, 1 << 26, 1, 31)[0]
-    with det.Context(0) as c1:
-        X1 = c1.dixon_lift(A, b, p, k)
-    monkeypatch.setenv("DET_LIFT_MODE", "kernels")
-    with det.Context(0) as c2:
-        X2 = c2.dixon_lift(A, b, p, k)
-    assert np.array_equal(X1, X2)
-    assert np.array_equal(X1.astype(np.int64), oracle.dixon_digits(A, b, p, k))
+    p = test_primes(1 << 23, 1 << 24, 1, 31)[0]
+    ref = oracle.dixon_digits(A, b, p, k)
+    outs = []
+    for mode in (None, "p2", "kernels"):
+        if mode is None:
+            monkeypatch.delenv("DET_LIFT_MODE", raising=False)
+        else:
+            monkeypatch.setenv("DET_LIFT_MODE", mode)
+        with det.Context(0) as cx:
+            outs.append(cx.dixon_lift(A, b, p, k))
+    for X in outs:
+        assert np.array_equal(X.astype(np.int64), ref)
 
 
-def test_dixon_lift_n1024_invariant(ctx):
-    """Full size: A x_i = r_i (mod p) and p | r_i - A x_i for the first steps,
+@pytest.mark.parametrize("bits", [26, 24])
+def test_dixon_lift_n1024_invariant(ctx, bits):
+    """Full size (the 64-bit integer form for 26-bit p, the FP64 form for
+    24-bit p): A x_i = r_i (mod p) and p | r_i - A x_i for the first steps,
     checked with exact integers on the host (no inverse needed)."""
-    n = 1024
+    n, k = 1024, 7
     A = synth.dense_uniform(n, 0, 255, 1024)
     b = synth.random_rhs(n, 12000, 3)
-    p = test_primes(1 << 25, 1 << 26, 1, 77)[0]
-    X = ctx.dixon_lift(A, b, p, 4).astype(np.int64)
+    p = test_primes(1 << (bits - 1), 1 << bits, 1, 77)[0]
+    X = ctx.dixon_lift(A, b, p, k).astype(np.int64)
     r = b.astype(np.int64)
-    for i in range(4):
+    for i in range(k):
+        assert np.all((X[i] >= 0) & (X[i] < p))
         t = r - A @ X[i]               # |A x| < 2^10 2^8 2^26: exact in int64
         assert np.all(t % p == 0)
         r = t // p
