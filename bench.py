@@ -7,8 +7,13 @@ trailing updates on MFMA), the inverse mod p and the Dixon lifting steps,
 then early-terminated Chinese remaindering on the host.  Prints one JSON line.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-mfma]
+                    [--copy-probe MIB]
+
+--copy-probe MIB ends the run with three plain device-to-device copies of MIB
+MiB each (the reference kernel that scales the HBM byte counters).
 """
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -30,6 +35,38 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# HBM traffic of the dominant kernel, measured with rocprofv3 counters
+# (FETCH_SIZE and WRITE_SIZE, each scaled by the reading of a plain copy of
+# known size) and recorded with a hash of the kernel source it was taken on.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "lift_resident3_n1024_traffic.txt")
+KERNEL_SOURCES = {"lift": "paper_cs_0511066_amd/csrc/dixon_kernels.hip"}
+
+
+def source_hash(kernel):
+    src = KERNEL_SOURCES.get(kernel)
+    if src is None:
+        return None
+    with open(os.path.join(ROOT, src), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """Bytes per launch from the committed counter summary, or None when the
+    summary is missing or was taken on another version of the kernel."""
+    try:
+        fields = dict(line.split(":", 1) for line in open(TRAFFIC_FILE) if ":" in line)
+    except OSError:
+        return None
+    if fields.get("kernel", "").strip() != kernel:
+        return None
+    if fields.get("source_sha256_16", "").strip() != source_hash(kernel):
+        return None
+    try:
+        return float(fields["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def roofline_entry(kernel, prof):
     """Achieved rate of one kernel class from its HIP-event timings."""
     if prof["launches"] == 0 or prof["ms"] <= 0:
@@ -46,7 +83,7 @@ def roofline_entry(kernel, prof):
         achieved = prof["ops"] / secs / 1e12
         peak, unit = 78.6, "TFLOP/s"
     return {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
-            "frac": round(achieved / peak, 5), "traffic": None,
+            "frac": round(achieved / peak, 5), "traffic": measured_traffic(kernel),
             "kernel": kernel, "launches": prof["launches"],
             "avg_launch_us": round(prof["ms"] * 1e3 / prof["launches"], 3),
             "bytes_per_launch": prof["bytes"] / prof["launches"],
@@ -80,6 +117,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mfma", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the primes of the "
@@ -180,7 +218,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "int8+fp64 (exact integer)",
+        "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "plain dense n=1024, entries uniform [0,255], seed 1024, "
                                "det_introspective (one Dixon solve + early-terminated CRA, eps 2^-64)",
@@ -194,6 +232,16 @@ def main():
     }
     print(json.dumps(out), flush=True)
     ctx.close()
+
+    if args.copy_probe > 0:
+        nbytes = args.copy_probe << 20
+        src = torch.empty(nbytes, dtype=torch.uint8, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: 3 device copies of {nbytes} bytes")
 
 
 if __name__ == "__main__":
