@@ -142,6 +142,32 @@ det_status det_introspective(det_ctx *ctx, const int64_t *A, int64_t n, int64_t 
                              int64_t *limb_count, det_report *report);
 
 /*
+ * Many exact determinants in one call: a set of independent dense matrices
+ * of any sizes (the batched workload; the paper's Section 4 algorithm run on
+ * each).  Matrix i is computed as det_introspective computes it with `opts`
+ * (NULL = defaults) and seed opts->seed + i, so results do not depend on the
+ * schedule.  A pool of `workers` contexts on ctx's device (workers <= 0: up to
+ * 8), each with its own streams and host thread, takes the matrices in
+ * order, so that small determinants share the GPU.  Worker contexts are
+ * created on first use and kept (and destroyed) by ctx.
+ *   A[i]        row-major n[i] x n[i] int64, leading dimension lda[i], host or
+ *               device pointer, owned by the caller and only read.
+ *   sign[i]     -1, 0 or +1.
+ *   mag         count x limb_stride uint32: |det A[i]| as little-endian limbs
+ *               from mag + i * limb_stride; limb_count[i] limbs are used.
+ *   status[i]   per-matrix status; DET_E_BUFFER_TOO_SMALL with the needed
+ *               limb count in limb_count[i] when limb_stride is too small.
+ *   t_done_ms   optional: completion time of matrix i, in ms since the call
+ *               started.
+ * Returns DET_OK when every matrix succeeded, else the status of the first
+ * failing matrix (see det_last_error).  Calls that overlap on one ctx race.
+ */
+det_status det_batch(det_ctx *ctx, int64_t count, const int64_t *const *A, const int64_t *n,
+                     const int64_t *lda, const det_opts *opts, int workers, int *sign,
+                     uint32_t *mag, int64_t limb_stride, int64_t *limb_count,
+                     det_status *status, double *t_done_ms);
+
+/*
  * Kernel timing (measurement support, not part of the method).  After
  * det_profile_select(ctx, kind), every launch of that kernel class made by
  * the context is bracketed by HIP events recorded on the context's stream;

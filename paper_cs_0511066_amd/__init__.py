@@ -82,6 +82,9 @@ _sig("dixon_lift", c_int, [ctypes.c_void_p, ctypes.c_void_p, c_i64, c_i64, P(c_i
                            P(c_u32)])
 _sig("det_introspective", c_int, [ctypes.c_void_p, ctypes.c_void_p, c_i64, c_i64, P(det_opts),
                                   P(c_int), P(c_u32), c_i64, P(c_i64), P(det_report)])
+_sig("det_batch", c_int, [ctypes.c_void_p, c_i64, P(ctypes.c_void_p), P(c_i64), P(c_i64),
+                          P(det_opts), c_int, P(c_int), P(c_u32), c_i64, P(c_i64), P(c_int),
+                          P(c_double)])
 _sig("det_profile_select", c_int, [ctypes.c_void_p, c_int])
 _sig("det_profile_read", c_int, [ctypes.c_void_p, P(c_i64), P(c_double), P(c_double), P(c_double)])
 _sig("det_host_is_prime", c_int, [c_u32])
@@ -96,7 +99,7 @@ _sig("det_host_bigint", c_int, [c_int, c_int, P(c_u32), c_i64, c_int, P(c_u32), 
 
 EXPORTED = ["det_ctx_create", "det_ctx_destroy", "det_ctx_set_stream", "det_status_str",
             "det_last_error", "det_opts_default", "det_mod_primes", "dixon_lift",
-            "det_introspective", "det_profile_select", "det_profile_read", "det_host_is_prime", "det_host_sample_primes",
+            "det_introspective", "det_batch", "det_profile_select", "det_profile_read", "det_host_is_prime", "det_host_sample_primes",
             "det_host_hadamard_log2", "det_host_et_run_length", "det_host_crt",
             "det_host_ratrecon", "det_host_bigint"]
 
@@ -251,6 +254,50 @@ class Context:
         if report:
             return det, {f: getattr(rep, f) for f, _ in det_report._fields_}
         return det
+
+
+    def det_batch(self, matrices, workers: int = 0, certify: bool = False,
+                  seed: int | None = None, log2_inv_eps: float | None = None,
+                  prime_bits: int | None = None, timings: bool = False):
+        """Exact determinants of a list of square int64 matrices (numpy or
+        torch CUDA tensors of any sizes) in one det_batch call.  Returns the
+        list of determinants, and with timings=True also the completion time
+        of each matrix in ms since the call started."""
+        args = [_matrix_arg(A) for A in matrices]
+        m = len(args)
+        o = det_opts()
+        _lib.det_opts_default(ctypes.byref(o))
+        o.certify = int(bool(certify))
+        if seed is not None:
+            o.seed = seed
+        if log2_inv_eps is not None:
+            o.log2_inv_eps = log2_inv_eps
+        if prime_bits is not None:
+            o.prime_bits = prime_bits
+        ptrs = (ctypes.c_void_p * max(m, 1))(*[a[0] for a in args])
+        ns = np.asarray([a[1] for a in args] or [0], dtype=np.int64)
+        ldas = np.asarray([a[2] for a in args] or [0], dtype=np.int64)
+        stride = max(8, 2 * int(ns.max()) + 8) if m else 8
+        while True:
+            sign = np.zeros(max(m, 1), dtype=np.int32)
+            mag = np.zeros(max(m, 1) * stride, dtype=np.uint32)
+            cnt = np.zeros(max(m, 1), dtype=np.int64)
+            stat = np.zeros(max(m, 1), dtype=np.int32)
+            tdone = np.zeros(max(m, 1), dtype=np.float64)
+            st = _lib.det_batch(self._h, m, ptrs, _i64p(ns), _i64p(ldas), ctypes.byref(o),
+                                int(workers), sign.ctypes.data_as(P(c_int)), _u32p(mag), stride,
+                                _i64p(cnt), stat.ctypes.data_as(P(c_int)),
+                                tdone.ctypes.data_as(P(c_double)))
+            if st == 7 and np.any(stat[:m] == 7):
+                stride = int(cnt[:m].max())
+                continue
+            self._check(st)
+            break
+        del args
+        dets = [_from_limbs(int(sign[i]), mag[i * stride:i * stride + int(cnt[i])]) for i in range(m)]
+        if timings:
+            return dets, tdone[:m].tolist()
+        return dets
 
 
 _default_ctx: Context | None = None

@@ -10,9 +10,11 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <exception>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/det.h"
@@ -75,6 +77,7 @@ struct det_ctx {
   double prof_bytes = 0, prof_ops = 0;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_pending;
   std::vector<hipEvent_t> ev_pool;
+  std::vector<det_ctx*> pool;    // worker contexts of det_batch (created on first use)
 };
 
 namespace {
@@ -727,6 +730,7 @@ det_status det_ctx_create(int device, size_t hbm_budget_bytes, det_ctx** out) {
 
 void det_ctx_destroy(det_ctx* c) {
   if (!c) return;
+  for (det_ctx* w : c->pool) det_ctx_destroy(w);
   (void)hipSetDevice(c->device);
   if (c->st) (void)hipStreamSynchronize(c->st);
   if (c->own2) (void)hipStreamSynchronize(c->own2);
@@ -758,6 +762,59 @@ det_status det_ctx_set_stream(det_ctx* c, void* hip_stream) {
   c->st = hip_stream ? (hipStream_t)hip_stream : c->own;
   c->ws[0].st = c->st;
   return DET_OK;
+}
+
+det_status det_batch(det_ctx* c, int64_t count, const int64_t* const* A, const int64_t* n,
+                     const int64_t* lda, const det_opts* opts, int workers, int* sign,
+                     uint32_t* mag, int64_t limb_stride, int64_t* limb_count, det_status* status,
+                     double* t_done_ms) {
+  if (!c) return DET_E_INVALID;
+  if (count < 0 || limb_stride < 0 || (limb_stride > 0 && count > 0 && !mag))
+    return fail(c, DET_E_INVALID, "invalid argument");
+  if (count == 0) return DET_OK;
+  if (!A || !n || !lda || !sign || !limb_count || !status)
+    return fail(c, DET_E_INVALID, "invalid argument");
+  try {
+    const int W = (int)std::max<int64_t>(1, std::min<int64_t>(count, workers > 0 ? workers : 8));
+    while ((int)c->pool.size() < W) {
+      det_ctx* w = nullptr;
+      const det_status s = det_ctx_create(c->device, c->budget, &w);
+      if (s != DET_OK) return fail(c, s, "cannot create a worker context");
+      c->pool.push_back(w);
+    }
+    det_opts o;
+    det_opts_default(&o);
+    if (opts) o = *opts;
+    std::atomic<int64_t> next{0};
+    const auto t0 = std::chrono::steady_clock::now();
+    auto work = [&](det_ctx* w) {
+      (void)hipSetDevice(w->device);
+      for (;;) {
+        const int64_t i = next.fetch_add(1);
+        if (i >= count) break;
+        det_opts oi = o;
+        oi.seed = o.seed + (uint64_t)i;
+        status[i] = det_introspective(w, A[i], n[i], lda[i], &oi, &sign[i],
+                                      limb_stride > 0 ? mag + i * limb_stride : nullptr,
+                                      limb_stride, &limb_count[i], nullptr);
+        if (t_done_ms)
+          t_done_ms[i] = std::chrono::duration<double, std::milli>(
+                             std::chrono::steady_clock::now() - t0).count();
+      }
+    };
+    std::vector<std::thread> threads;
+    for (int k = 1; k < W; k++) threads.emplace_back(work, c->pool[k]);
+    work(c->pool[0]);
+    for (auto& t : threads) t.join();
+    for (int64_t i = 0; i < count; i++)
+      if (status[i] != DET_OK)
+        return fail(c, status[i], "matrix " + std::to_string(i) + ": " + det_status_str(status[i]));
+    return DET_OK;
+  } catch (const std::exception& e) {
+    return fail(c, DET_E_NOMEM, e.what());
+  } catch (...) {
+    return fail(c, DET_E_INVALID, "unexpected error");
+  }
 }
 
 void det_opts_default(det_opts* o) {
