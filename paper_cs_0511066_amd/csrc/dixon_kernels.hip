@@ -567,94 +567,114 @@ int lift3_grid(int device, int n) {
 // (A C^{(k)} = I + p^k E_k exactly, and E_k + A c_k = 0 mod p).  The lifting
 // kernel uses the same centred representatives.
 //
-// k_hensel_f64<MODE>: 64x64 output tile per 256-thread workgroup, 4x4
-// outputs per thread, K in chunks of 16 through LDS.
-//   MODE 0: Eout = (Ein + A Ck) / p   (Ein = -I when Ein == null; |E| <= n ||A||)
-//   MODE 1: Cout = (-C0 E) mod p in [0, p)  (E reduced to centred residues
-//           first; products < 2^48, reduced every 32 k-steps)
+// k_hensel_f64<MODE>: a 64x64 output tile per 256-thread workgroup on FP64
+// MFMA (v_mfma_f64_16x16x4f64; each wave a 32x32 quarter as 2x2 blocks),
+// K in chunks of 16 through LDS.
+//   MODE 0: Eout = (Ein + A c_k) / p   (Ein = -I when Ein == null).  Every
+//           partial sum is below n ||A|| p / 2 < 2^53: exact without reduction;
+//           the quotient is exact, so rint of the scaled sum is it.
+//   MODE 1: Cout = (-c0 E) mod p in [0, p), E reduced to centred residues on
+//           load; products < 2^48 (p < 2^25), reduced every 16 k-steps.
+typedef double v4d_h __attribute__((ext_vector_type(4)));
 template <int MODE>
 __global__ __launch_bounds__(256) void k_hensel_f64(const void* __restrict__ Lv,
                                                     const void* __restrict__ Rv,
                                                     const double* __restrict__ Ein, int n,
                                                     uint32_t p, double pinv, void* __restrict__ out) {
+  constexpr int BM = 64, BN = 64, BK = 16;
   const int t = threadIdx.x;
-  const int ty = t >> 4, tx = t & 15;
-  const int row0 = blockIdx.y * 64, col0 = blockIdx.x * 64;
+  const int lane = t & 63, wave = t >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int row0 = blockIdx.y * BM, col0 = blockIdx.x * BN;
   const double pd = (double)p, h = 0.5 * pd;
-  __shared__ double sL[16][65];
-  __shared__ double sR[16][65];
-  double acc[4][4];
+  __shared__ double sL[BK][BM + 2];
+  __shared__ double sR[BK][BN + 2];
+  v4d_h acc[2][2];
 #pragma unroll
-  for (int i = 0; i < 4; i++)
+  for (int i = 0; i < 2; i++)
 #pragma unroll
-    for (int j = 0; j < 4; j++) acc[i][j] = 0.0;
-  int since = 0;
-  for (int k0 = 0; k0 < n; k0 += 16) {
-    for (int e = t; e < 64 * 16; e += 256) {
-      const int r = e >> 4, kk = e & 15;
-      const int gr = row0 + r, gk = k0 + kk;
-      double v = 0.0;
-      if (gr < n && gk < n) {
-        if (MODE == 0) {
-          v = (double)((const int32_t*)Lv)[(int64_t)gr * n + gk];
-        } else {
-          const double u = (double)((const uint32_t*)Lv)[(int64_t)gr * n + gk];
-          v = u > h ? u - pd : u;
+    for (int j = 0; j < 2; j++) acc[i][j] = (v4d_h){0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < n; k0 += BK) {
+    {   // left tile: 64 rows x 16 k; thread t: row t/4, k (t%4)*4 .. +3
+      const int r = t >> 2, kq = (t & 3) * 4;
+      const int gr = row0 + r;
+#pragma unroll
+      for (int u = 0; u < 4; u++) {
+        const int gk = k0 + kq + u;
+        double v = 0.0;
+        if (gr < n && gk < n) {
+          if (MODE == 0) {
+            v = (double)((const int32_t*)Lv)[(int64_t)gr * n + gk];
+          } else {
+            const double w = (double)((const uint32_t*)Lv)[(int64_t)gr * n + gk];
+            v = w > h ? w - pd : w;
+          }
         }
+        sL[kq + u][r] = v;
       }
-      sL[kk][r] = v;
-      const int kr = e >> 6, cc = e & 63;
-      const int gk2 = k0 + kr, gc = col0 + cc;
-      double w = 0.0;
-      if (gk2 < n && gc < n) {
-        if (MODE == 0) {
-          const double u = (double)((const uint32_t*)Rv)[(int64_t)gk2 * n + gc];
-          w = u > h ? u - pd : u;
-        } else {
-          w = mod_c(((const double*)Rv)[(int64_t)gk2 * n + gc], pd, pinv);
+    }
+    {   // right tile: 16 k x 64 cols; thread t: k t/16, cols (t%16)*4 .. +3
+      const int kk = t >> 4, cq = (t & 15) * 4;
+      const int gk = k0 + kk;
+#pragma unroll
+      for (int u = 0; u < 4; u++) {
+        const int gc = col0 + cq + u;
+        double v = 0.0;
+        if (gk < n && gc < n) {
+          if (MODE == 0) {
+            const double w = (double)((const uint32_t*)Rv)[(int64_t)gk * n + gc];
+            v = w > h ? w - pd : w;
+          } else {
+            v = mod_c(((const double*)Rv)[(int64_t)gk * n + gc], pd, pinv);
+          }
         }
+        sR[kk][cq + u] = v;
       }
-      sR[kr][cc] = w;
     }
     __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < 16; kk++) {
-      double a[4], b[4];
+    for (int ks = 0; ks < BK; ks += 4) {
+      const int kr = ks + (lane >> 4);
+      double af[2], bf[2];
 #pragma unroll
-      for (int i = 0; i < 4; i++) a[i] = sL[kk][ty * 4 + i];
+      for (int i = 0; i < 2; i++) af[i] = sL[kr][wr * 32 + i * 16 + (lane & 15)];
 #pragma unroll
-      for (int j = 0; j < 4; j++) b[j] = sR[kk][tx * 4 + j];
+      for (int j = 0; j < 2; j++) bf[j] = sR[kr][wc * 32 + j * 16 + (lane & 15)];
 #pragma unroll
-      for (int i = 0; i < 4; i++)
+      for (int i = 0; i < 2; i++)
 #pragma unroll
-        for (int j = 0; j < 4; j++) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+        for (int j = 0; j < 2; j++)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
     }
-    if (MODE == 1 && (since += 16) == 32) {
-      since = 0;
+    if (MODE == 1) {
 #pragma unroll
-      for (int i = 0; i < 4; i++)
+      for (int i = 0; i < 2; i++)
 #pragma unroll
-        for (int j = 0; j < 4; j++) acc[i][j] = mod_loose(acc[i][j], pd, pinv);
+        for (int j = 0; j < 2; j++)
+#pragma unroll
+          for (int r = 0; r < 4; r++) acc[i][j][r] = mod_loose(acc[i][j][r], pd, pinv);
     }
     __syncthreads();
   }
+  // output element (row wr*32 + i*16 + lane/16 + 4 r, col wc*32 + j*16 + lane%16)
 #pragma unroll
-  for (int i = 0; i < 4; i++)
+  for (int i = 0; i < 2; i++)
 #pragma unroll
-    for (int j = 0; j < 4; j++) {
-      const int gr = row0 + ty * 4 + i, gc = col0 + tx * 4 + j;
-      if (gr >= n || gc >= n) continue;
-      const int64_t o = (int64_t)gr * n + gc;
-      if (MODE == 0) {
-        // E + A C_k is an exact multiple of p: rint of the scaled value is
-        // the exact quotient
-        const double ein = Ein ? Ein[o] : (gr == gc ? -1.0 : 0.0);
-        ((double*)out)[o] = rint((ein + acc[i][j]) * pinv);
-      } else {
-        double v = mod_c(-acc[i][j], pd, pinv);
-        ((uint32_t*)out)[o] = (uint32_t)(v < 0 ? v + pd : v);
+    for (int j = 0; j < 2; j++)
+#pragma unroll
+      for (int r = 0; r < 4; r++) {
+        const int gr = row0 + wr * 32 + i * 16 + (lane >> 4) + 4 * r;
+        const int gc = col0 + wc * 32 + j * 16 + (lane & 15);
+        if (gr >= n || gc >= n) continue;
+        const int64_t o = (int64_t)gr * n + gc;
+        if (MODE == 0) {
+          const double ein = Ein ? Ein[o] : (gr == gc ? -1.0 : 0.0);
+          ((double*)out)[o] = rint((ein + acc[i][j][r]) * pinv);
+        } else {
+          const double v = mod_c(-acc[i][j][r], pd, pinv);
+          ((uint32_t*)out)[o] = (uint32_t)(v < 0 ? v + pd : v);
+        }
       }
-    }
 }
 
 __device__ __forceinline__ int wave_sum_i32(int v) {
