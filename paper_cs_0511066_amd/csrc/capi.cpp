@@ -5,6 +5,7 @@
 // integer conversion, rational reconstruction and the final product.
 #include <hip/hip_runtime.h>
 #include <math.h>
+#include <stdio.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -47,9 +48,17 @@ double now_ms() {
 }
 
 // Device workspace of one batched LU, bound to one stream.
+// Pinned host memory for the small transfers of the path: an asynchronous
+// copy from pageable memory can hold the host until earlier work drains,
+// which would serialize the two streams of a context.
+struct PinBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+};
+
 struct LuWs {
   DevBuf W, piv, flags, mods, linv, uinv, tinv, limbA, limbB, res;
-  std::vector<Modulus> hmods;   // host copy of the moduli; kept alive for async uploads
+  PinBuf hmods;                 // pinned host copy of the moduli (async uploads)
   hipStream_t st = nullptr;
 };
 
@@ -69,6 +78,8 @@ struct det_ctx {
       rp2, x2;
   uint32_t* hres = nullptr;      // pinned host residues of the background batch
   size_t hres_cap = 0;
+  PinBuf hstage;                 // pinned staging of the lifting's vectors and results
+  PinBuf hsmall;                 // pinned flags and error words read back on st
   int lift_mode = 0;             // 0: fastest cooperative form that applies; 1: one launch per
                                  // phase; 2: the 64-bit integer form modulo p^2
   // kernel timing (det_profile_select / det_profile_read)
@@ -125,6 +136,25 @@ det_status ensure(det_ctx* c, DevBuf& b, size_t bytes, hipStream_t st) {
 }
 
 det_status ensure(det_ctx* c, DevBuf& b, size_t bytes) { return ensure(c, b, bytes, c->st); }
+
+// Grow a pinned host buffer; `st` is the stream whose copies may still read it.
+det_status ensure_pin(det_ctx* c, PinBuf& b, size_t bytes, hipStream_t st) {
+  if (b.cap >= bytes) return DET_OK;
+  if (b.p) {
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipHostFree(b.p));
+    b.p = nullptr;
+    b.cap = 0;
+  }
+  const size_t cap = std::max<size_t>(bytes, 4096);
+  if (hipHostMalloc(&b.p, cap, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    b.p = nullptr;
+    return fail(c, DET_E_NOMEM, "hipHostMalloc failed");
+  }
+  b.cap = cap;
+  return DET_OK;
+}
 
 // Brackets one launch with HIP events on its stream when its kernel class is
 // the selected one; the counts are the launcher's algorithmic bytes and ops.
@@ -273,9 +303,11 @@ det_status lu_factor(det_ctx* c, LuWs& w, const LuJob& J, bool keep_uinv,
   const int kc4 = std::max(1, kc / 4);
   const bool two_level = nit >= TWO_LEVEL_MIN_ITEMS;
   const int npan_max = n / 8 + 2;    // panels are at least 8 wide (the last may be narrower)
-  if (keep_uinv && nit != 1) return fail(c, DET_E_INVALID, "U11 inverses need one item");
   TRY(ensure(c, w.linv, (size_t)nit * 32 * 32 * sizeof(int32_t), w.st));
-  if (keep_uinv) TRY(ensure(c, w.uinv, (size_t)npan_max * 32 * 32 * sizeof(int32_t), w.st));
+  // U11 inverses: panel-major, one 32 x 32 slot per item (back_substitute
+  // reads item 0's)
+  if (keep_uinv)
+    TRY(ensure(c, w.uinv, (size_t)npan_max * nit * 32 * 32 * sizeof(int32_t), w.st));
   const int32_t* linv = (const int32_t*)w.linv.p;
   if (panels) panels->clear();
   if (!two_level) {
@@ -285,7 +317,7 @@ det_status lu_factor(det_ctx* c, LuWs& w, const LuJob& J, bool keep_uinv,
       const int pb = std::min(pbw, n - j0);
       const Panel P{j0, pb, pbw};
       if (keep_uinv && idx >= npan_max) return fail(c, DET_E_INVALID, "panel count overflow");
-      int32_t* uinv = keep_uinv ? (int32_t*)w.uinv.p + (size_t)idx * 32 * 32 : nullptr;
+      int32_t* uinv = keep_uinv ? (int32_t*)w.uinv.p + (size_t)idx * nit * 32 * 32 : nullptr;
       TRY(panel_step(c, w, J, P, uinv, kc));
       if (panels) panels->push_back(P);
       const int right = ncols - (j0 + pb);
@@ -333,12 +365,13 @@ det_status lu_factor(det_ctx* c, LuWs& w, const LuJob& J, bool keep_uinv,
 // Back substitution U X = Y on [U | Y] (one item, after a single-level
 // lu_factor with keep_uinv): X = U^{-1} Y = A^{-1} mod p, panel by panel
 // from the bottom: X_blk = U11^{-1} Y_blk, then Y_above -= U_above,blk X_blk.
-det_status back_substitute(det_ctx* c, LuWs& w, const LuJob& J, const std::vector<Panel>& panels) {
+det_status back_substitute(det_ctx* c, LuWs& w, const LuJob& J, const std::vector<Panel>& panels,
+                           int lu_items) {
   const int n = J.n;
   const int kc4 = std::max(1, exact_chunk(J.pmax) / 4);
   for (int idx = (int)panels.size() - 1; idx >= 0; idx--) {
     const Panel& P = panels[idx];
-    const int32_t* uinv = (const int32_t*)w.uinv.p + (size_t)idx * 32 * 32;
+    const int32_t* uinv = (const int32_t*)w.uinv.p + (size_t)idx * lu_items * 32 * 32;
     TRY(trsm_step(c, w, J, P.j0, P.pb, n, n, uinv, P.pbw, kc4, 0, 0));
     if (P.j0 > 0)
       TRY(gemm_update(c, w, J, n, P.j0, (int64_t)P.j0 * J.ldw + n, P.j0, n, P.pb, kc4, false));
@@ -428,8 +461,8 @@ det_status residues_core(det_ctx* c, LuWs& w, const int64_t* dA, int64_t dlda, i
     J.nitems = nit;
     J.pmax = 0;
     HIPCHK(hipStreamSynchronize(w.st));             // the previous upload from hmods is done
-    std::vector<Modulus>& hm = w.hmods;
-    hm.resize(nit);
+    TRY(ensure_pin(c, w.hmods, (size_t)nit * sizeof(Modulus), w.st));
+    Modulus* hm = (Modulus*)w.hmods.p;
     for (int i = 0; i < nit; i++) {
       hm[i] = modulus_of(primes[s0 + i]);
       J.pmax = std::max(J.pmax, primes[s0 + i]);
@@ -440,7 +473,7 @@ det_status residues_core(det_ctx* c, LuWs& w, const int64_t* dA, int64_t dlda, i
     TRY(ensure(c, w.flags, (size_t)nit * sizeof(int32_t), w.st));
     TRY(ensure(c, w.mods, (size_t)nit * sizeof(Modulus), w.st));
     TRY(ensure(c, w.res, (size_t)nit * sizeof(uint32_t), w.st));
-    HIPCHK(hipMemcpyAsync(w.mods.p, hm.data(), nit * sizeof(Modulus), hipMemcpyHostToDevice, w.st));
+    HIPCHK(hipMemcpyAsync(w.mods.p, hm, nit * sizeof(Modulus), hipMemcpyHostToDevice, w.st));
     HIPCHK(hipMemsetAsync(w.flags.p, 0, nit * sizeof(int32_t), w.st));
     {
       ProfScope ps(c, DET_KERNEL_RESIDUES, (double)n * n * (8.0 + 4.0 * nit), 0.0, w.st);
@@ -465,6 +498,9 @@ uint64_t inv_mod_2_64(uint64_t p) {
 
 // A^{-1} mod p into c->Cu (canonical, n x n), from a staged device matrix,
 // on workspace ws[0].  Returns DET_E_SINGULAR_MOD_P if p | det(A).
+det_status ensure_pinned(det_ctx* c, size_t count);
+
+// A^{-1} mod p into c->Cu by LU of [A | I] and back substitution.
 det_status inverse_mod_p(det_ctx* c, const int64_t* dA, int64_t dlda, int n, uint32_t p) {
   LuWs& w = c->ws[0];
   LuJob J;
@@ -475,26 +511,47 @@ det_status inverse_mod_p(det_ctx* c, const int64_t* dA, int64_t dlda, int n, uin
   J.nitems = 1;
   J.pmax = p;
   J.int8 = false;
-  Modulus hm = modulus_of(p);
+  TRY(ensure_pin(c, w.hmods, sizeof(Modulus), w.st));
+  TRY(ensure_pinned(c, 64));                       // c->hres[0..63]; a background CRA batch
+  Modulus* hm = (Modulus*)w.hmods.p;               // writes from c->hres + 64
+  *hm = modulus_of(p);
   TRY(ensure(c, w.W, (size_t)J.slab * sizeof(int32_t), w.st));
   TRY(ensure(c, w.piv, (size_t)n * sizeof(int32_t), w.st));
   TRY(ensure(c, w.flags, sizeof(int32_t), w.st));
   TRY(ensure(c, w.mods, sizeof(Modulus), w.st));
   TRY(ensure(c, c->Cu, (size_t)n * n * sizeof(uint32_t)));
-  HIPCHK(hipMemcpyAsync(w.mods.p, &hm, sizeof(Modulus), hipMemcpyHostToDevice, w.st));
+  HIPCHK(hipMemcpyAsync(w.mods.p, hm, sizeof(Modulus), hipMemcpyHostToDevice, w.st));
   HIPCHK(hipMemsetAsync(w.flags.p, 0, sizeof(int32_t), w.st));
   HIPCHK(detk::launch_residues(dA, dlda, n, 2 * n, (int32_t*)w.W.p, J.ldw, J.slab,
                                (const Modulus*)w.mods.p, 1, w.st));
   std::vector<Panel> panels;
   TRY(lu_factor(c, w, J, true, &panels));
-  int32_t flag = 0;
-  HIPCHK(hipMemcpyAsync(&flag, w.flags.p, sizeof(int32_t), hipMemcpyDeviceToHost, w.st));
+  int32_t* flag = (int32_t*)c->hres;
+  HIPCHK(hipMemcpyAsync(flag, w.flags.p, sizeof(int32_t), hipMemcpyDeviceToHost, w.st));
   HIPCHK(hipStreamSynchronize(w.st));
-  if (flag) return fail(c, DET_E_SINGULAR_MOD_P, "p divides det(A)");
-  TRY(back_substitute(c, w, J, panels));
+  if (*flag) return fail(c, DET_E_SINGULAR_MOD_P, "p divides det(A)");
+  TRY(back_substitute(c, w, J, panels, 1));
   HIPCHK(detk::launch_extract_inverse((const int32_t*)w.W.p, J.ldw, n, (const Modulus*)w.mods.p,
                                       (uint32_t*)c->Cu.p, w.st));
   return DET_OK;
+}
+
+// Layout of the pinned staging buffer c->hstage for a lifting of order n
+// with k digits: r (int64), digit 0 of r, three balanced digits, digit 1 of
+// r, the combination vector, then k combination sums read back.
+struct Stage {
+  size_t r, rp0, d3, rp1, cvec, comb, total;
+};
+Stage stage_layout(int64_t n, int64_t k) {
+  Stage s;
+  s.r = 0;
+  s.rp0 = s.r + 8 * (size_t)n;
+  s.d3 = s.rp0 + 4 * (size_t)n;
+  s.rp1 = s.d3 + 12 * (size_t)n;
+  s.cvec = s.rp1 + 4 * (size_t)n;
+  s.comb = (s.cvec + 4 * (size_t)n + 63) & ~(size_t)63;
+  s.total = s.comb + 8 * (size_t)k;
+  return s;
 }
 
 // The FP64 three-digit lifting is exact for p < 2^25 and n ||A|| p < 2^53.
@@ -521,13 +578,19 @@ det_status lift(det_ctx* c, const int64_t* dA, int64_t dlda, int n, double amax,
   HIPCHK(hipMemsetAsync(c->rp.p, 0, npad * sizeof(uint32_t), c->st));
   HIPCHK(hipMemsetAsync(c->x.p, 0, npad * sizeof(uint32_t), c->st));
   HIPCHK(detk::launch_pack_i32(dA, dlda, n, (int32_t*)c->Ai.p, c->st));
-  std::vector<uint32_t> rp0(n);
+  const Stage sl = stage_layout(n, 0);
+  TRY(ensure_pin(c, c->hstage, sl.total, c->st));
+  TRY(ensure_pin(c, c->hsmall, 64, c->st));
+  char* hs = (char*)c->hstage.p;
+  int64_t* hb = (int64_t*)(hs + sl.r);
+  uint32_t* rp0 = (uint32_t*)(hs + sl.rp0);
   for (int j = 0; j < n; j++) {
+    hb[j] = b[j];
     int64_t m = b[j] % (int64_t)p;
     rp0[j] = (uint32_t)(m < 0 ? m + p : m);
   }
-  HIPCHK(hipMemcpyAsync(c->r.p, b, n * sizeof(int64_t), hipMemcpyHostToDevice, c->st));
-  HIPCHK(hipMemcpyAsync(c->rp.p, rp0.data(), n * sizeof(uint32_t), hipMemcpyHostToDevice, c->st));
+  HIPCHK(hipMemcpyAsync(c->r.p, hb, n * sizeof(int64_t), hipMemcpyHostToDevice, c->st));
+  HIPCHK(hipMemcpyAsync(c->rp.p, rp0, n * sizeof(uint32_t), hipMemcpyHostToDevice, c->st));
   const uint64_t pinv64 = inv_mod_2_64(p);
   const double nn = (double)n * n;
   const int grid3 = c->lift_mode == 0 && lift3_applies(n, amax, p) ? detk::lift3_grid(c->device, n) : 0;
@@ -545,7 +608,7 @@ det_status lift(det_ctx* c, const int64_t* dA, int64_t dlda, int n, double amax,
       HIPCHK(hipMemsetAsync(v->p, 0, npad * sizeof(uint32_t), c->st));
     HIPCHK(hipMemsetAsync(c->sync.p, 0, 64, c->st));
     // balanced digits of b mod p^3 (each centring carried into the next digit)
-    std::vector<int32_t> d3(3 * (size_t)n);
+    int32_t* d3 = (int32_t*)(hs + sl.d3);
     for (int j = 0; j < n; j++) {
       int64_t v = b[j];
       for (int q = 0; q < 3; q++) {
@@ -556,9 +619,9 @@ det_status lift(det_ctx* c, const int64_t* dA, int64_t dlda, int n, double amax,
         v = (v - m) / (int64_t)p;                  // exact
       }
     }
-    HIPCHK(hipMemcpyAsync(c->rp.p, d3.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, c->st));
-    HIPCHK(hipMemcpyAsync(c->rp1.p, d3.data() + n, n * sizeof(int32_t), hipMemcpyHostToDevice, c->st));
-    HIPCHK(hipMemcpyAsync(c->rp2.p, d3.data() + 2 * (size_t)n, n * sizeof(int32_t),
+    HIPCHK(hipMemcpyAsync(c->rp.p, d3, n * sizeof(int32_t), hipMemcpyHostToDevice, c->st));
+    HIPCHK(hipMemcpyAsync(c->rp1.p, d3 + n, n * sizeof(int32_t), hipMemcpyHostToDevice, c->st));
+    HIPCHK(hipMemcpyAsync(c->rp2.p, d3 + 2 * (size_t)n, n * sizeof(int32_t),
                           hipMemcpyHostToDevice, c->st));
     HIPCHK(detk::launch_hensel_f64((const int32_t*)c->Ai.p, (const uint32_t*)c->Cu.p,
                                    (double*)c->Ed.p, (uint32_t*)c->C1.p, (uint32_t*)c->C2.p, n, p,
@@ -579,10 +642,10 @@ det_status lift(det_ctx* c, const int64_t* dA, int64_t dlda, int n, double amax,
           (uint32_t*)c->rp2.p, (uint32_t*)c->x.p, (uint32_t*)c->x1.p, (uint32_t*)c->x2.p, n, p,
           pinv64, k, digits_dev, cvec_dev, comb_dev, bar, err, c->st));
     }
-    int herr = 0;
-    HIPCHK(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, c->st));
+    int* herr = (int*)c->hsmall.p;
+    HIPCHK(hipMemcpyAsync(herr, err, sizeof(int), hipMemcpyDeviceToHost, c->st));
     HIPCHK(hipStreamSynchronize(c->st));
-    if (herr) return fail(c, DET_E_DEVICE, "lifting grid barrier timed out");
+    if (*herr) return fail(c, DET_E_DEVICE, "lifting grid barrier timed out");
     return DET_OK;
   }
   const int grid = c->lift_mode != 1 ? detk::lift_persistent_grid(c->device, n) : 0;
@@ -597,13 +660,13 @@ det_status lift(det_ctx* c, const int64_t* dA, int64_t dlda, int n, double amax,
     HIPCHK(hipMemsetAsync(c->x1.p, 0, npad * sizeof(uint32_t), c->st));
     HIPCHK(hipMemsetAsync(c->sync.p, 0, 64, c->st));
     // second base-p digit of b mod p^2
-    std::vector<uint32_t> rp1(n);
+    uint32_t* rp1 = (uint32_t*)(hs + sl.rp1);
     for (int j = 0; j < n; j++) {
       const int64_t q = (b[j] - (int64_t)rp0[j]) / (int64_t)p;     // exact
       int64_t m = q % (int64_t)p;
       rp1[j] = (uint32_t)(m < 0 ? m + p : m);
     }
-    HIPCHK(hipMemcpyAsync(c->rp1.p, rp1.data(), n * sizeof(uint32_t), hipMemcpyHostToDevice, c->st));
+    HIPCHK(hipMemcpyAsync(c->rp1.p, rp1, n * sizeof(uint32_t), hipMemcpyHostToDevice, c->st));
     HIPCHK(detk::launch_hensel((const int32_t*)c->Ai.p, (const uint32_t*)c->Cu.p,
                                (uint32_t*)c->E.p, (uint32_t*)c->C1.p, n, p, c->st));
     if (after_own2) {
@@ -621,10 +684,10 @@ det_status lift(det_ctx* c, const int64_t* dA, int64_t dlda, int n, double amax,
           (int64_t*)c->r.p, (uint32_t*)c->rp.p, (uint32_t*)c->rp1.p, (uint32_t*)c->x.p,
           (uint32_t*)c->x1.p, n, p, pinv64, k, digits_dev, cvec_dev, comb_dev, bar, err, c->st));
     }
-    int herr = 0;
-    HIPCHK(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, c->st));
+    int* herr = (int*)c->hsmall.p;
+    HIPCHK(hipMemcpyAsync(herr, err, sizeof(int), hipMemcpyDeviceToHost, c->st));
     HIPCHK(hipStreamSynchronize(c->st));
-    if (herr) return fail(c, DET_E_DEVICE, "lifting grid barrier timed out");
+    if (*herr) return fail(c, DET_E_DEVICE, "lifting grid barrier timed out");
     return DET_OK;
   }
   for (int64_t i = 0; i < k; i++) {
@@ -744,6 +807,8 @@ void det_ctx_destroy(det_ctx* c) {
   for (DevBuf* b : all)
     if (b->p) (void)hipFree(b->p);
   if (c->hres) (void)hipHostFree(c->hres);
+  for (PinBuf* pb : {&c->hstage, &c->hsmall, &c->ws[0].hmods, &c->ws[1].hmods})
+    if (pb->p) (void)hipHostFree(pb->p);
   for (auto& pr : c->prof_pending) {
     (void)hipEventDestroy(pr.first);
     (void)hipEventDestroy(pr.second);
@@ -983,10 +1048,11 @@ det_status det_introspective(det_ctx* c, const int64_t* A, int64_t n, int64_t ld
     const int64_t batch1 = k0 > 0 ? std::min<int64_t>(k0 + 3, 64) : 16;
     std::vector<uint32_t> ps1(batch1);
     for (auto& q : ps1) q = samp.next();
-    TRY(ensure_pinned(c, (size_t)batch1));
+    TRY(ensure_pinned(c, (size_t)batch1 + 64));
+    uint32_t* hres1 = c->hres + 64;                  // (c->hres[0..63]: the inverse's read-backs)
     HIPCHK(hipEventRecord(c->ev, c->st));              // A (and its bounds) are ready on st
     HIPCHK(hipStreamWaitEvent(c->own2, c->ev, 0));
-    TRY(residues_core(c, c->ws[1], dA, dlda, (int)n, ps1.data(), batch1, c->hres, o.path, false));
+    TRY(residues_core(c, c->ws[1], dA, dlda, (int)n, ps1.data(), batch1, hres1, o.path, false));
 
     // ---------------- LIF: s~_n from Dixon solvings (Section 2.2)
     BigInt K = BigInt::from_i64(1);
@@ -1029,12 +1095,17 @@ det_status det_introspective(det_ctx* c, const int64_t* A, int64_t n, int64_t ld
         const int64_t k = (int64_t)ceil((double)(Nbits + Dbits + 2) / log2((double)p)) + 1;
         TRY(ensure(c, c->cvec, (size_t)lift_pad(n) * sizeof(uint32_t)));
         TRY(ensure(c, c->comb, (size_t)k * sizeof(uint64_t)));
+        const Stage sl = stage_layout(n, k);
+        TRY(ensure_pin(c, c->hstage, sl.total, c->st));
+        uint32_t* hcv = (uint32_t*)((char*)c->hstage.p + sl.cvec);
+        memcpy(hcv, cv.data(), n * sizeof(uint32_t));
         HIPCHK(hipMemsetAsync(c->cvec.p, 0, lift_pad(n) * sizeof(uint32_t), c->st));
-        HIPCHK(hipMemcpyAsync(c->cvec.p, cv.data(), n * sizeof(uint32_t), hipMemcpyHostToDevice, c->st));
+        HIPCHK(hipMemcpyAsync(c->cvec.p, hcv, n * sizeof(uint32_t), hipMemcpyHostToDevice, c->st));
         TRY(lift(c, dA, dlda, (int)n, bd.amax, b.data(), p, k, nullptr, (const uint32_t*)c->cvec.p,
                  (uint64_t*)c->comb.p, true));
-        std::vector<uint64_t> comb(k);
-        HIPCHK(hipMemcpyAsync(comb.data(), c->comb.p, k * sizeof(uint64_t), hipMemcpyDeviceToHost, c->st));
+        const uint64_t* comb = (const uint64_t*)((char*)c->hstage.p + sl.comb);
+        HIPCHK(hipMemcpyAsync((void*)comb, c->comb.p, k * sizeof(uint64_t), hipMemcpyDeviceToHost,
+                              c->st));
         HIPCHK(hipStreamSynchronize(c->st));
         rep.lifting_steps += k;
         const double th0 = now_ms();
@@ -1062,7 +1133,7 @@ det_status det_introspective(det_ctx* c, const int64_t* A, int64_t n, int64_t ld
     dethost::CrtState crt;
     bool done = false;
     HIPCHK(hipStreamSynchronize(c->own2));
-    std::vector<uint32_t> ps(ps1), rs(c->hres, c->hres + batch1);
+    std::vector<uint32_t> ps(ps1), rs(hres1, hres1 + batch1);
     rep.et_rounds = 1;
     int64_t batch = batch1;
     for (;;) {
