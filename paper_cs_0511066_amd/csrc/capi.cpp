@@ -632,6 +632,12 @@ det_status lift(det_ctx* c, const int64_t* dA, int64_t dlda, int n, double amax,
     }
     unsigned* bar = (unsigned*)c->sync.p;
     int* err = (int*)((char*)c->sync.p + 32);
+    // the combinations are formed after the lifting, from its digits
+    uint32_t* dig = digits_dev;
+    if (!dig && comb_dev) {
+      TRY(ensure(c, c->digits, (size_t)k * n * sizeof(uint32_t)));
+      dig = (uint32_t*)c->digits.p;
+    }
     {
       // algorithmic bytes per digit: C and A as the one-launch-per-phase form
       // reads them (8 n^2) and four n-vectors
@@ -640,8 +646,9 @@ det_status lift(det_ctx* c, const int64_t* dA, int64_t dlda, int n, double amax,
           grid3, (const uint32_t*)c->Cu.p, (const uint32_t*)c->C1.p, (const uint32_t*)c->C2.p,
           (const int32_t*)c->Ai.p, (int64_t*)c->r.p, (uint32_t*)c->rp.p, (uint32_t*)c->rp1.p,
           (uint32_t*)c->rp2.p, (uint32_t*)c->x.p, (uint32_t*)c->x1.p, (uint32_t*)c->x2.p, n, p,
-          pinv64, k, digits_dev, cvec_dev, comb_dev, bar, err, c->st));
+          pinv64, k, dig, bar, err, c->st));
     }
+    if (comb_dev) HIPCHK(detk::launch_comb_digits(dig, k, n, cvec_dev, comb_dev, c->st));
     int* herr = (int*)c->hsmall.p;
     HIPCHK(hipMemcpyAsync(herr, err, sizeof(int), hipMemcpyDeviceToHost, c->st));
     HIPCHK(hipStreamSynchronize(c->st));

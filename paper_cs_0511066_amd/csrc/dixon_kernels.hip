@@ -748,8 +748,7 @@ __global__ __launch_bounds__(64 * NWAVE) void k_lift_resident3(
     const uint32_t* __restrict__ C2, const int32_t* __restrict__ Ai, int64_t* __restrict__ r,
     uint32_t* rp0, uint32_t* rp1, uint32_t* rp2, uint32_t* xb0, uint32_t* xb1, uint32_t* xb2,
     int n, uint32_t p, double pinv, uint64_t pinv64, int64_t kd,
-    uint32_t* __restrict__ digits, const uint32_t* __restrict__ cvec,
-    uint64_t* __restrict__ comb, unsigned* bar, int* err, unsigned spin_limit) {
+    uint32_t* __restrict__ digits, unsigned* bar, int* err, unsigned spin_limit) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int G = gridDim.x;
@@ -770,7 +769,10 @@ __global__ __launch_bounds__(64 * NWAVE) void k_lift_resident3(
   // the workgroup's rows of A live in LDS (only phase R reads them), the
   // three planes in registers (only phase X reads them)
   __shared__ int32_t sA[NWAVE * RPW][64 * EPL];
-  int32_t c0[RPW][EPL], c1[RPW][EPL], c2[RPW][EPL];
+  // centred planes: c0, c1 (three and two uses per entry) as FP64, c2 (one
+  // use) as int32, converted at its use
+  double c0[RPW][EPL], c1[RPW][EPL];
+  int32_t c2[RPW][EPL];
   int64_t rr[RPW];
   int rows[RPW];
 #pragma unroll
@@ -783,8 +785,8 @@ __global__ __launch_bounds__(64 * NWAVE) void k_lift_resident3(
       const int j = lane + 64 * e;
       const bool in = row < n && j < n;
       const int64_t o = (int64_t)row * n + j;
-      c0[i][e] = in ? centred_i32(C0[o], p) : 0;
-      c1[i][e] = in ? centred_i32(C1[o], p) : 0;
+      c0[i][e] = in ? (double)centred_i32(C0[o], p) : 0.0;
+      c1[i][e] = in ? (double)centred_i32(C1[o], p) : 0.0;
       c2[i][e] = in ? centred_i32(C2[o], p) : 0;
       sA[wave * RPW + i][j] = in ? Ai[o] : 0;
     }
@@ -806,11 +808,9 @@ __global__ __launch_bounds__(64 * NWAVE) void k_lift_resident3(
       const double w2 = (double)(int32_t)sV[2][lane + 64 * e];
 #pragma unroll
       for (int i = 0; i < RPW; i++) {
-        // the planes stay int32 in registers and are converted at each use;
-        // z (always 0, not known to the compiler) keeps FP64 copies of them
-        // (twice the registers) from being hoisted out of the step loop
-        const double x0 = (double)(c0[i][e] ^ z), x1 = (double)(c1[i][e] ^ z),
-                     x2 = (double)(c2[i][e] ^ z);
+        // z (always 0, unknown to the compiler) keeps an FP64 copy of c2
+        // from being hoisted out of the step loop
+        const double x0 = c0[i][e], x1 = c1[i][e], x2 = (double)(c2[i][e] ^ z);
         S0[i] = fma(x0, w0, S0[i]);
         S1a[i] = fma(x0, w1, S1a[i]);
         S1b[i] = fma(x1, w0, S1b[i]);
@@ -818,9 +818,13 @@ __global__ __launch_bounds__(64 * NWAVE) void k_lift_resident3(
         S2b[i] = fma(x1, w1, S2b[i]);
         S2c[i] = fma(x2, w0, S2c[i]);
       }
-      // one column at a time: otherwise every conversion of the phase is
-      // scheduled up front and the planes spill
-      __builtin_amdgcn_sched_barrier(0);
+      // one column at a time for every row: the empty asm consumes the
+      // accumulators, so no row's products are sunk below the column loop
+      // (which would keep every staged value of the phase live)
+#pragma unroll
+      for (int i = 0; i < RPW; i++)
+        asm volatile("" : "+v"(S0[i]), "+v"(S1a[i]), "+v"(S1b[i]), "+v"(S2a[i]), "+v"(S2b[i]),
+                     "+v"(S2c[i]));
     }
     // (absent rows, whose planes are 0, run through as well: a conditional
     // here would let the compiler sink the row's products into it, out of
@@ -862,20 +866,12 @@ __global__ __launch_bounds__(64 * NWAVE) void k_lift_resident3(
     double D0[RPW], D1[RPW], D2[RPW];
 #pragma unroll
     for (int i = 0; i < RPW; i++) D0[i] = D1[i] = D2[i] = 0.0;
-    double cs0 = 0.0, cs1 = 0.0, cs2 = 0.0;
-    const bool do_comb = comb != nullptr && blockIdx.x == 0 && wave == 0;
     stage3(sV, xb0, xb1, xb2);
 #pragma unroll
     for (int e = 0; e < EPL; e++) {
       const double x0 = (double)sV[0][lane + 64 * e];
       const double x1 = (double)sV[1][lane + 64 * e];
       const double x2 = (double)sV[2][lane + 64 * e];
-      if (do_comb) {
-        const double cv = (double)cvec[lane + 64 * e];
-        cs0 = fma(cv, x0, cs0);
-        cs1 = fma(cv, x1, cs1);
-        cs2 = fma(cv, x2, cs2);
-      }
 #pragma unroll
       for (int i = 0; i < RPW; i++) {
         const double av = (double)sA[wave * RPW + i][lane + 64 * e];
@@ -883,17 +879,8 @@ __global__ __launch_bounds__(64 * NWAVE) void k_lift_resident3(
         D1[i] = fma(av, x1, D1[i]);
         D2[i] = fma(av, x2, D2[i]);
       }
-      __builtin_amdgcn_sched_barrier(0);
-    }
-    if (do_comb) {                       // cvec < 2^16, x < 2^25: sums < 2^51
-      cs0 = dpp_sum_f64(cs0);
-      cs1 = dpp_sum_f64(cs1);
-      cs2 = dpp_sum_f64(cs2);
-      if (lane == 0) {
-        comb[3 * step] = (uint64_t)cs0;
-        if (3 * step + 1 < kd) comb[3 * step + 1] = (uint64_t)cs1;
-        if (3 * step + 2 < kd) comb[3 * step + 2] = (uint64_t)cs2;
-      }
+#pragma unroll
+      for (int i = 0; i < RPW; i++) asm volatile("" : "+v"(D0[i]), "+v"(D1[i]), "+v"(D2[i]));
     }
 #pragma unroll
     for (int i = 0; i < RPW; i++) {
@@ -927,6 +914,31 @@ __global__ __launch_bounds__(64 * NWAVE) void k_lift_resident3(
     if (rows[i] < n && lane == 0) r[rows[i]] = rr[i];
 }
 
+// comb[i] = sum_j c_j x_i[j] for every lifted digit vector x_i (the random
+// combination whose rational reconstruction gives a divisor of s_n): one
+// wave per digit, after the lifting, so the lifting loop carries no extra
+// work.  c_j < 2^16, digits < 2^26: the 64-bit sums are exact.
+__global__ __launch_bounds__(256) void k_comb_digits(const uint32_t* __restrict__ digits,
+                                                     int64_t k, int n,
+                                                     const uint32_t* __restrict__ cvec,
+                                                     uint64_t* __restrict__ comb) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= k) return;
+  const uint32_t* x = digits + i * n;
+  uint64_t s = 0;
+  for (int j = lane; j < n; j += 64) s += (uint64_t)cvec[j] * x[j];
+  s = wave_sum_u64(s);
+  if (lane == 0) comb[i] = s;
+}
+
+hipError_t launch_comb_digits(const uint32_t* digits, int64_t k, int n, const uint32_t* cvec,
+                              uint64_t* comb, hipStream_t st) {
+  if (k <= 0 || n <= 0) return hipSuccess;
+  k_comb_digits<<<(unsigned)((k + 3) / 4), 256, 0, st>>>(digits, k, n, cvec, comb);
+  return hipGetLastError();
+}
+
 hipError_t launch_hensel_f64(const int32_t* Ai, const uint32_t* C0, double* E, uint32_t* C1,
                              uint32_t* C2, int n, uint32_t p, hipStream_t st) {
   if (n <= 0) return hipSuccess;
@@ -943,9 +955,8 @@ hipError_t launch_lift_resident3(int grid, const uint32_t* C0, const uint32_t* C
                                  const uint32_t* C2, const int32_t* Ai, int64_t* r,
                                  uint32_t* rp0, uint32_t* rp1, uint32_t* rp2, uint32_t* xb0,
                                  uint32_t* xb1, uint32_t* xb2, int n, uint32_t p,
-                                 uint64_t pinv64, int64_t kd, uint32_t* digits,
-                                 const uint32_t* cvec, uint64_t* comb, unsigned* bar, int* err,
-                                 hipStream_t st) {
+                                 uint64_t pinv64, int64_t kd, uint32_t* digits, unsigned* bar,
+                                 int* err, hipStream_t st) {
   if (n <= 0 || kd <= 0) return hipSuccess;
   if (p >= (1u << 25)) return hipErrorInvalidValue;
   double pinv = 1.0 / (double)p;
@@ -953,7 +964,7 @@ hipError_t launch_lift_resident3(int grid, const uint32_t* C0, const uint32_t* C
   void* args[] = {(void*)&C0, (void*)&C1, (void*)&C2, (void*)&Ai, (void*)&r, (void*)&rp0,
                   (void*)&rp1, (void*)&rp2, (void*)&xb0, (void*)&xb1, (void*)&xb2, (void*)&n,
                   (void*)&p, (void*)&pinv, (void*)&pinv64, (void*)&kd, (void*)&digits,
-                  (void*)&cvec, (void*)&comb, (void*)&bar, (void*)&err, (void*)&spin_limit};
+                  (void*)&bar, (void*)&err, (void*)&spin_limit};
   const void* f = nullptr;
   if (n <= 256) f = (const void*)k_lift_resident3<4, 2, 8>;
   else if (n <= 512) f = (const void*)k_lift_resident3<8, 2, 8>;

@@ -61,16 +61,18 @@ hipError_t launch_hensel(const int32_t* Ai, const uint32_t* Cu, uint32_t* E, uin
 // Lifting modulo p^3 in FP64 (p < 2^25, n ||A|| p < 2^53): Hensel planes
 // C1, C2 of A^{-1} mod p^3 from C0 = A^{-1} mod p (E: n x n FP64 scratch),
 // then all steps in one cooperative launch, three digits per step.
-int lift3_grid(int device, int n);    // 0: the three-plane form does not apply
+int lift3_grid(int device, int n);
+// comb[i] = cvec . digits[i] for k digit vectors of length n (after a lifting)
+hipError_t launch_comb_digits(const uint32_t* digits, int64_t k, int n, const uint32_t* cvec,
+                              uint64_t* comb, hipStream_t st);    // 0: the three-plane form does not apply
 hipError_t launch_hensel_f64(const int32_t* Ai, const uint32_t* C0, double* E, uint32_t* C1,
                              uint32_t* C2, int n, uint32_t p, hipStream_t st);
 hipError_t launch_lift_resident3(int grid, const uint32_t* C0, const uint32_t* C1,
                                  const uint32_t* C2, const int32_t* Ai, int64_t* r,
                                  uint32_t* rp0, uint32_t* rp1, uint32_t* rp2, uint32_t* xb0,
                                  uint32_t* xb1, uint32_t* xb2, int n, uint32_t p,
-                                 uint64_t pinv64, int64_t kd, uint32_t* digits,
-                                 const uint32_t* cvec, uint64_t* comb, unsigned* bar, int* err,
-                                 hipStream_t st);
+                                 uint64_t pinv64, int64_t kd, uint32_t* digits, unsigned* bar,
+                                 int* err, hipStream_t st);
 hipError_t launch_lift_resident2(int grid, const uint32_t* C0, const uint32_t* C1,
                                  const int32_t* Ai, int64_t* r, uint32_t* rp0, uint32_t* rp1,
                                  uint32_t* xb0, uint32_t* xb1, int n, uint32_t p, uint64_t pinv64,
