@@ -604,18 +604,20 @@ det_status lift(det_ctx* c, const int64_t* dA, int64_t dlda, int n, double amax,
     TRY(ensure(c, c->x1, (size_t)npad * sizeof(uint32_t)));
     TRY(ensure(c, c->x2, (size_t)npad * sizeof(uint32_t)));
     TRY(ensure(c, c->sync, 64));
-    for (DevBuf* v : {&c->rp1, &c->rp2, &c->x1, &c->x2})
-      HIPCHK(hipMemsetAsync(v->p, 0, npad * sizeof(uint32_t), c->st));
+    // x: all-ones words (tag 127, not yet written by any step)
+    for (DevBuf* v : {&c->x, &c->x1, &c->x2})
+      HIPCHK(hipMemsetAsync(v->p, 0xFF, npad * sizeof(uint32_t), c->st));
     HIPCHK(hipMemsetAsync(c->sync.p, 0, 64, c->st));
-    // balanced digits of b mod p^3 (each centring carried into the next digit)
-    int32_t* d3 = (int32_t*)(hs + sl.d3);
+    // balanced digits of b mod p^3 (each centring carried into the next
+    // digit), as 25-bit fields under tag 0 (step 0)
+    uint32_t* d3 = (uint32_t*)(hs + sl.d3);
     for (int j = 0; j < n; j++) {
       int64_t v = b[j];
       for (int q = 0; q < 3; q++) {
         int64_t m = v % (int64_t)p;
         if (m < 0) m += p;
         if (m > (int64_t)(p - 1) / 2) m -= p;
-        d3[(size_t)q * n + j] = (int32_t)m;
+        d3[(size_t)q * n + j] = (uint32_t)(int32_t)m & detk::LIFT3_DIGIT_MASK;
         v = (v - m) / (int64_t)p;                  // exact
       }
     }
@@ -630,7 +632,6 @@ det_status lift(det_ctx* c, const int64_t* dA, int64_t dlda, int n, double amax,
       HIPCHK(hipEventRecord(c->ev, c->own2));
       HIPCHK(hipStreamWaitEvent(c->st, c->ev, 0));
     }
-    unsigned* bar = (unsigned*)c->sync.p;
     int* err = (int*)((char*)c->sync.p + 32);
     // the combinations are formed after the lifting, from its digits
     uint32_t* dig = digits_dev;
@@ -646,13 +647,13 @@ det_status lift(det_ctx* c, const int64_t* dA, int64_t dlda, int n, double amax,
           grid3, (const uint32_t*)c->Cu.p, (const uint32_t*)c->C1.p, (const uint32_t*)c->C2.p,
           (const int32_t*)c->Ai.p, (int64_t*)c->r.p, (uint32_t*)c->rp.p, (uint32_t*)c->rp1.p,
           (uint32_t*)c->rp2.p, (uint32_t*)c->x.p, (uint32_t*)c->x1.p, (uint32_t*)c->x2.p, n, p,
-          pinv64, k, dig, bar, err, c->st));
+          pinv64, k, dig, err, c->st));
     }
     if (comb_dev) HIPCHK(detk::launch_comb_digits(dig, k, n, cvec_dev, comb_dev, c->st));
     int* herr = (int*)c->hsmall.p;
     HIPCHK(hipMemcpyAsync(herr, err, sizeof(int), hipMemcpyDeviceToHost, c->st));
     HIPCHK(hipStreamSynchronize(c->st));
-    if (*herr) return fail(c, DET_E_DEVICE, "lifting grid barrier timed out");
+    if (*herr) return fail(c, DET_E_DEVICE, "lifting: a wait for another workgroup's digits timed out");
     return DET_OK;
   }
   const int grid = c->lift_mode != 1 ? detk::lift_persistent_grid(c->device, n) : 0;

@@ -161,6 +161,17 @@ __device__ __forceinline__ void grid_barrier(unsigned* bar, unsigned target, int
   __syncthreads();
 }
 
+// Loads and stores of the vectors that the three-plane lifting kernel passes
+// between workgroups: device-scope relaxed atomics, served at the
+// device-coherent level past the per-XCD L2 caches, so that the exchange
+// needs no L2 writeback or invalidation.
+__device__ __forceinline__ uint32_t ld_dev(const uint32_t* a) {
+  return __hip_atomic_load(a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_dev(uint32_t* a, uint32_t v) {
+  __hip_atomic_store(a, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // All k lifting steps with the rows of C and A held in registers for the
 // whole loop.  Workgroups of 512 threads (8 waves, so up to 256 VGPRs per
 // lane); wave w of workgroup g owns rows (8 g + w) RPW + i (i < RPW); lane l
@@ -731,10 +742,10 @@ __device__ __forceinline__ int32_t centred_i32(uint32_t u, uint32_t p) {
 // All lifting steps modulo p^3 in FP64, three base-p digits per step, with
 // the centred planes c0, c1, c2 of A^{-1} mod p^3 and the rows of A in
 // registers: wave w of workgroup g (NWAVE waves) owns rows
-// (NWAVE g + w) RPW + i, lane l columns l + 64 e (e < EPL).  Vectors crossing
-// the barriers: the three digit planes of r mod p^3, balanced (|digit| <=
-// (p-1)/2, stored as int32 bits, r = w0 + p w1 + p^2 w2 mod p^3), and the
-// three digit planes of x in [0, p).
+// (NWAVE g + w) RPW + i, lane l columns l + 64 e (e < EPL).  Vectors passed
+// between workgroups: the three digit planes of r mod p^3, balanced (|digit|
+// <= (p-1)/2, r = w0 + p w1 + p^2 w2 mod p^3), and the three digit planes of
+// x in [0, p).
 // Phase X, per lane over its EPL columns (w_q = centred digit q of r):
 //   S0 = sum c0 w0, S1 = sum c0 w1 + c1 w0, S2 = sum c0 w2 + c1 w1 + c2 w0,
 // each partial sum of 16 products below 2^52; carries are taken lane by lane
@@ -742,27 +753,65 @@ __device__ __forceinline__ int32_t centred_i32(uint32_t u, uint32_t p) {
 // their wave sums fit in int32; digits of x follow with a carry pass.
 // Phase R: D_q = A x_q (|D_q| <= n ||A|| p < 2^53) and
 //   r' = (((r - D0)/p - D1)/p - D2)/p   in exact int64 arithmetic.
+//
+// No grid barrier: every exchanged 32-bit word holds a 25-bit digit (two's
+// complement for r, plain for x) under a 7-bit tag, the step number mod 127,
+// and is written and read with device-coherent atomics; a reader polls each
+// word until its tag is the step it wants.  The words of x of step s are
+// written only after their writer has read all of r of step s, and each word
+// of r of step s+1 only after its writer has read all of x of step s, so a
+// word is never overwritten before every workgroup has read it, and a reader
+// finds in it either the value it waits for or the one before it (another
+// tag).  Tags run over 0..126: the caller fills x with all-ones words (tag
+// 127) before the launch and writes r of step 0 with tag 0.  A wait that
+// exceeds spin_limit polls sets *err; after that every wait gives up within
+// 64 polls, so all waves exit.
 template <int EPL, int RPW, int NWAVE>
 __global__ __launch_bounds__(64 * NWAVE) void k_lift_resident3(
     const uint32_t* __restrict__ C0, const uint32_t* __restrict__ C1,
     const uint32_t* __restrict__ C2, const int32_t* __restrict__ Ai, int64_t* __restrict__ r,
     uint32_t* rp0, uint32_t* rp1, uint32_t* rp2, uint32_t* xb0, uint32_t* xb1, uint32_t* xb2,
     int n, uint32_t p, double pinv, uint64_t pinv64, int64_t kd,
-    uint32_t* __restrict__ digits, unsigned* bar, int* err, unsigned spin_limit) {
+    uint32_t* __restrict__ digits, int* err, unsigned spin_limit) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int G = gridDim.x;
   const double pd = (double)p;
+  constexpr uint32_t DIG = LIFT3_DIGIT_MASK;
   // the three planes of the vector a phase reads, staged once per workgroup
-  // (64 EPL entries each; the workgroup's threads load them together)
-  __shared__ uint32_t sV[3][64 * EPL];
+  // (64 EPL entries each, decoded; the workgroup's threads load them
+  // together), one buffer per phase so that a phase may stage while slower
+  // waves still read the other phase's buffer
+  __shared__ uint32_t sV[2][3][64 * EPL];
+  bool gave_up = false;
   auto stage3 = [&](uint32_t (*s)[64 * EPL], const uint32_t* v0, const uint32_t* v1,
-                    const uint32_t* v2) {
+                    const uint32_t* v2, uint32_t tag, bool sgn) {
     for (int j = threadIdx.x; j < 64 * EPL; j += 64 * NWAVE) {
-      const uint32_t a0 = v0[j], a1 = v1[j], a2 = v2[j];
-      s[0][j] = a0;
-      s[1][j] = a1;
-      s[2][j] = a2;
+      uint32_t a0 = 0, a1 = 0, a2 = 0;
+      if (j < n) {
+        unsigned spins = 0;
+        for (;;) {
+          a0 = ld_dev(v0 + j);
+          a1 = ld_dev(v1 + j);
+          a2 = ld_dev(v2 + j);
+          if (((a0 >> 25) == tag && (a1 >> 25) == tag && (a2 >> 25) == tag) || gave_up) break;
+          if ((++spins & 63) == 0) {
+            if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+              gave_up = true;
+              break;
+            }
+            if (spins > spin_limit) {
+              __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              gave_up = true;
+              break;
+            }
+          }
+          __builtin_amdgcn_s_sleep(1);
+        }
+      }
+      // r digits: sign-extend the 25-bit field; x digits: the field itself
+      s[0][j] = sgn ? (uint32_t)((int32_t)(a0 << 7) >> 7) : (a0 & DIG);
+      s[1][j] = sgn ? (uint32_t)((int32_t)(a1 << 7) >> 7) : (a1 & DIG);
+      s[2][j] = sgn ? (uint32_t)((int32_t)(a2 << 7) >> 7) : (a2 & DIG);
     }
     __syncthreads();
   };
@@ -792,20 +841,21 @@ __global__ __launch_bounds__(64 * NWAVE) void k_lift_resident3(
     }
     if (row < n && lane == 0) rr[i] = r[row];
   }
-  unsigned target = 0;
   const int64_t steps = (kd + 2) / 3;
+  uint32_t tag = 0;                                // step mod 127
   for (int64_t step = 0; step < steps; step++) {
     const int z = (int)(step >> 62);               // 0: step < 2^62
+    const uint32_t tag1 = tag == 126 ? 0 : tag + 1;
     // ---- phase X
     double S0[RPW], S1a[RPW], S1b[RPW], S2a[RPW], S2b[RPW], S2c[RPW];
 #pragma unroll
     for (int i = 0; i < RPW; i++) S0[i] = S1a[i] = S1b[i] = S2a[i] = S2b[i] = S2c[i] = 0.0;
-    stage3(sV, rp0, rp1, rp2);
+    stage3(sV[0], rp0, rp1, rp2, tag, true);
 #pragma unroll
     for (int e = 0; e < EPL; e++) {
-      const double w0 = (double)(int32_t)sV[0][lane + 64 * e];     // balanced digits
-      const double w1 = (double)(int32_t)sV[1][lane + 64 * e];
-      const double w2 = (double)(int32_t)sV[2][lane + 64 * e];
+      const double w0 = (double)(int32_t)sV[0][0][lane + 64 * e];  // balanced digits
+      const double w1 = (double)(int32_t)sV[0][1][lane + 64 * e];
+      const double w2 = (double)(int32_t)sV[0][2][lane + 64 * e];
 #pragma unroll
       for (int i = 0; i < RPW; i++) {
         // z (always 0, unknown to the compiler) keeps an FP64 copy of c2
@@ -849,9 +899,9 @@ __global__ __launch_bounds__(64 * NWAVE) void k_lift_resident3(
           const uint32_t x1 = smod64(t1, p, pinv);
           const int64_t t2 = M2 + (int64_t)((uint64_t)(t1 - (int64_t)x1) * pinv64);
           const uint32_t x2 = smod64(t2, p, pinv);
-          xb0[rows[i]] = x0;
-          xb1[rows[i]] = x1;
-          xb2[rows[i]] = x2;
+          st_dev(xb0 + rows[i], tag << 25 | x0);
+          st_dev(xb1 + rows[i], tag << 25 | x1);
+          st_dev(xb2 + rows[i], tag << 25 | x2);
           if (digits) {
             digits[(3 * step) * n + rows[i]] = x0;
             if (3 * step + 1 < kd) digits[(3 * step + 1) * n + rows[i]] = x1;
@@ -860,18 +910,16 @@ __global__ __launch_bounds__(64 * NWAVE) void k_lift_resident3(
         }
       }
     }
-    target += G;
-    grid_barrier(bar, target, err, spin_limit);
     // ---- phase R
     double D0[RPW], D1[RPW], D2[RPW];
 #pragma unroll
     for (int i = 0; i < RPW; i++) D0[i] = D1[i] = D2[i] = 0.0;
-    stage3(sV, xb0, xb1, xb2);
+    stage3(sV[1], xb0, xb1, xb2, tag, false);
 #pragma unroll
     for (int e = 0; e < EPL; e++) {
-      const double x0 = (double)sV[0][lane + 64 * e];
-      const double x1 = (double)sV[1][lane + 64 * e];
-      const double x2 = (double)sV[2][lane + 64 * e];
+      const double x0 = (double)sV[1][0][lane + 64 * e];
+      const double x1 = (double)sV[1][1][lane + 64 * e];
+      const double x2 = (double)sV[1][2][lane + 64 * e];
 #pragma unroll
       for (int i = 0; i < RPW; i++) {
         const double av = (double)sA[wave * RPW + i][lane + 64 * e];
@@ -900,14 +948,14 @@ __global__ __launch_bounds__(64 * NWAVE) void k_lift_resident3(
           const int64_t u1 = (int64_t)((uint64_t)(q - (int64_t)m0) * pinv64);
           const int32_t m1 = centred_i32(smod64(u1, p, pinv), p);
           const int64_t u2 = (int64_t)((uint64_t)(u1 - (int64_t)m1) * pinv64);
-          rp0[rows[i]] = (uint32_t)m0;
-          rp1[rows[i]] = (uint32_t)m1;
-          rp2[rows[i]] = (uint32_t)centred_i32(smod64(u2, p, pinv), p);
+          const int32_t m2 = centred_i32(smod64(u2, p, pinv), p);
+          st_dev(rp0 + rows[i], tag1 << 25 | ((uint32_t)m0 & DIG));
+          st_dev(rp1 + rows[i], tag1 << 25 | ((uint32_t)m1 & DIG));
+          st_dev(rp2 + rows[i], tag1 << 25 | ((uint32_t)m2 & DIG));
         }
       }
     }
-    target += G;
-    grid_barrier(bar, target, err, spin_limit);
+    tag = tag1;
   }
 #pragma unroll
   for (int i = 0; i < RPW; i++)
@@ -955,16 +1003,16 @@ hipError_t launch_lift_resident3(int grid, const uint32_t* C0, const uint32_t* C
                                  const uint32_t* C2, const int32_t* Ai, int64_t* r,
                                  uint32_t* rp0, uint32_t* rp1, uint32_t* rp2, uint32_t* xb0,
                                  uint32_t* xb1, uint32_t* xb2, int n, uint32_t p,
-                                 uint64_t pinv64, int64_t kd, uint32_t* digits, unsigned* bar,
-                                 int* err, hipStream_t st) {
+                                 uint64_t pinv64, int64_t kd, uint32_t* digits, int* err,
+                                 hipStream_t st) {
   if (n <= 0 || kd <= 0) return hipSuccess;
   if (p >= (1u << 25)) return hipErrorInvalidValue;
   double pinv = 1.0 / (double)p;
-  unsigned spin_limit = 1u << 22;     // ~0.1 s of polling per barrier at most
+  unsigned spin_limit = 1u << 18;     // polls of about 1 us each: ~0.3 s per wait at most
   void* args[] = {(void*)&C0, (void*)&C1, (void*)&C2, (void*)&Ai, (void*)&r, (void*)&rp0,
                   (void*)&rp1, (void*)&rp2, (void*)&xb0, (void*)&xb1, (void*)&xb2, (void*)&n,
                   (void*)&p, (void*)&pinv, (void*)&pinv64, (void*)&kd, (void*)&digits,
-                  (void*)&bar, (void*)&err, (void*)&spin_limit};
+                  (void*)&err, (void*)&spin_limit};
   const void* f = nullptr;
   if (n <= 256) f = (const void*)k_lift_resident3<4, 2, 8>;
   else if (n <= 512) f = (const void*)k_lift_resident3<8, 2, 8>;

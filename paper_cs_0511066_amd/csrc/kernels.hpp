@@ -61,18 +61,23 @@ hipError_t launch_hensel(const int32_t* Ai, const uint32_t* Cu, uint32_t* E, uin
 // Lifting modulo p^3 in FP64 (p < 2^25, n ||A|| p < 2^53): Hensel planes
 // C1, C2 of A^{-1} mod p^3 from C0 = A^{-1} mod p (E: n x n FP64 scratch),
 // then all steps in one cooperative launch, three digits per step.
-int lift3_grid(int device, int n);
+int lift3_grid(int device, int n);    // 0: the three-plane form does not apply
 // comb[i] = cvec . digits[i] for k digit vectors of length n (after a lifting)
 hipError_t launch_comb_digits(const uint32_t* digits, int64_t k, int n, const uint32_t* cvec,
-                              uint64_t* comb, hipStream_t st);    // 0: the three-plane form does not apply
+                              uint64_t* comb, hipStream_t st);
+// Words of the vectors that the three-plane lifting passes between its
+// workgroups: a 25-bit digit field (two's complement for the balanced digits
+// of r) under a 7-bit tag, the step number mod 127; tag 127 (an all-ones
+// word) marks a word not yet written.  r of step 0 goes in with tag 0.
+constexpr uint32_t LIFT3_DIGIT_MASK = 0x1FFFFFFu;
 hipError_t launch_hensel_f64(const int32_t* Ai, const uint32_t* C0, double* E, uint32_t* C1,
                              uint32_t* C2, int n, uint32_t p, hipStream_t st);
 hipError_t launch_lift_resident3(int grid, const uint32_t* C0, const uint32_t* C1,
                                  const uint32_t* C2, const int32_t* Ai, int64_t* r,
                                  uint32_t* rp0, uint32_t* rp1, uint32_t* rp2, uint32_t* xb0,
                                  uint32_t* xb1, uint32_t* xb2, int n, uint32_t p,
-                                 uint64_t pinv64, int64_t kd, uint32_t* digits, unsigned* bar,
-                                 int* err, hipStream_t st);
+                                 uint64_t pinv64, int64_t kd, uint32_t* digits, int* err,
+                                 hipStream_t st);
 hipError_t launch_lift_resident2(int grid, const uint32_t* C0, const uint32_t* C1,
                                  const int32_t* Ai, int64_t* r, uint32_t* rp0, uint32_t* rp1,
                                  uint32_t* xb0, uint32_t* xb1, int n, uint32_t p, uint64_t pinv64,
