@@ -75,7 +75,7 @@ struct det_ctx {
   std::string err;
   LuWs ws[2];
   DevBuf Adev, norms, amax, Cu, Ai, r, rp, x, digits, comb, cvec, sync, C1, E, rp1, x1, C2, Ed,
-      rp2, x2;
+      rv, xv;
   uint32_t* hres = nullptr;      // pinned host residues of the background batch
   size_t hres_cap = 0;
   PinBuf hstage;                 // pinned staging of the lifting's vectors and results
@@ -537,8 +537,9 @@ det_status inverse_mod_p(det_ctx* c, const int64_t* dA, int64_t dlda, int n, uin
 }
 
 // Layout of the pinned staging buffer c->hstage for a lifting of order n
-// with k digits: r (int64), digit 0 of r, three balanced digits, digit 1 of
-// r, the combination vector, then k combination sums read back.
+// with k digits: r (int64), digit 0 of r, three balanced digits a row (four
+// words), digit 1 of r, the combination vector, then k combination sums read
+// back.
 struct Stage {
   size_t r, rp0, d3, rp1, cvec, comb, total;
 };
@@ -547,7 +548,7 @@ Stage stage_layout(int64_t n, int64_t k) {
   s.r = 0;
   s.rp0 = s.r + 8 * (size_t)n;
   s.d3 = s.rp0 + 4 * (size_t)n;
-  s.rp1 = s.d3 + 12 * (size_t)n;
+  s.rp1 = s.d3 + 16 * (size_t)n;
   s.cvec = s.rp1 + 4 * (size_t)n;
   s.comb = (s.cvec + 4 * (size_t)n + 63) & ~(size_t)63;
   s.total = s.comb + 8 * (size_t)k;
@@ -599,17 +600,14 @@ det_status lift(det_ctx* c, const int64_t* dA, int64_t dlda, int n, double amax,
     TRY(ensure(c, c->C1, (size_t)n * n * sizeof(uint32_t)));
     TRY(ensure(c, c->C2, (size_t)n * n * sizeof(uint32_t)));
     TRY(ensure(c, c->Ed, (size_t)n * n * sizeof(double)));
-    TRY(ensure(c, c->rp1, (size_t)npad * sizeof(uint32_t)));
-    TRY(ensure(c, c->rp2, (size_t)npad * sizeof(uint32_t)));
-    TRY(ensure(c, c->x1, (size_t)npad * sizeof(uint32_t)));
-    TRY(ensure(c, c->x2, (size_t)npad * sizeof(uint32_t)));
+    TRY(ensure(c, c->rv, (size_t)n * 4 * sizeof(uint32_t)));
+    TRY(ensure(c, c->xv, (size_t)n * 4 * sizeof(uint32_t)));
     TRY(ensure(c, c->sync, 64));
-    // x: all-ones words (tag 127, not yet written by any step)
-    for (DevBuf* v : {&c->x, &c->x1, &c->x2})
-      HIPCHK(hipMemsetAsync(v->p, 0xFF, npad * sizeof(uint32_t), c->st));
+    // xv: all-ones words (tag 127, not yet written by any step)
+    HIPCHK(hipMemsetAsync(c->xv.p, 0xFF, (size_t)n * 4 * sizeof(uint32_t), c->st));
     HIPCHK(hipMemsetAsync(c->sync.p, 0, 64, c->st));
     // balanced digits of b mod p^3 (each centring carried into the next
-    // digit), as 25-bit fields under tag 0 (step 0)
+    // digit), row by row as 25-bit fields under tag 0 (step 0)
     uint32_t* d3 = (uint32_t*)(hs + sl.d3);
     for (int j = 0; j < n; j++) {
       int64_t v = b[j];
@@ -617,14 +615,13 @@ det_status lift(det_ctx* c, const int64_t* dA, int64_t dlda, int n, double amax,
         int64_t m = v % (int64_t)p;
         if (m < 0) m += p;
         if (m > (int64_t)(p - 1) / 2) m -= p;
-        d3[(size_t)q * n + j] = (uint32_t)(int32_t)m & detk::LIFT3_DIGIT_MASK;
+        d3[(size_t)4 * j + q] = (uint32_t)(int32_t)m & detk::LIFT3_DIGIT_MASK;
         v = (v - m) / (int64_t)p;                  // exact
       }
+      d3[(size_t)4 * j + 3] = 0;
     }
-    HIPCHK(hipMemcpyAsync(c->rp.p, d3, n * sizeof(int32_t), hipMemcpyHostToDevice, c->st));
-    HIPCHK(hipMemcpyAsync(c->rp1.p, d3 + n, n * sizeof(int32_t), hipMemcpyHostToDevice, c->st));
-    HIPCHK(hipMemcpyAsync(c->rp2.p, d3 + 2 * (size_t)n, n * sizeof(int32_t),
-                          hipMemcpyHostToDevice, c->st));
+    HIPCHK(hipMemcpyAsync(c->rv.p, d3, (size_t)n * 4 * sizeof(uint32_t), hipMemcpyHostToDevice,
+                          c->st));
     HIPCHK(detk::launch_hensel_f64((const int32_t*)c->Ai.p, (const uint32_t*)c->Cu.p,
                                    (double*)c->Ed.p, (uint32_t*)c->C1.p, (uint32_t*)c->C2.p, n, p,
                                    c->st));
@@ -645,9 +642,8 @@ det_status lift(det_ctx* c, const int64_t* dA, int64_t dlda, int n, double amax,
       ProfScope ps(c, DET_KERNEL_LIFT, (8.0 * nn + 40.0 * n) * k, 4.0 * nn * k, c->st);
       HIPCHK(detk::launch_lift_resident3(
           grid3, (const uint32_t*)c->Cu.p, (const uint32_t*)c->C1.p, (const uint32_t*)c->C2.p,
-          (const int32_t*)c->Ai.p, (int64_t*)c->r.p, (uint32_t*)c->rp.p, (uint32_t*)c->rp1.p,
-          (uint32_t*)c->rp2.p, (uint32_t*)c->x.p, (uint32_t*)c->x1.p, (uint32_t*)c->x2.p, n, p,
-          pinv64, k, dig, err, c->st));
+          (const int32_t*)c->Ai.p, (int64_t*)c->r.p, (uint32_t*)c->rv.p, (uint32_t*)c->xv.p, n,
+          p, pinv64, k, dig, err, c->st));
     }
     if (comb_dev) HIPCHK(detk::launch_comb_digits(dig, k, n, cvec_dev, comb_dev, c->st));
     int* herr = (int*)c->hsmall.p;
@@ -807,7 +803,7 @@ void det_ctx_destroy(det_ctx* c) {
   if (c->own2) (void)hipStreamSynchronize(c->own2);
   std::vector<DevBuf*> all = {&c->Adev, &c->norms, &c->amax, &c->Cu, &c->Ai, &c->r, &c->rp,
                               &c->x, &c->digits, &c->comb, &c->cvec, &c->sync, &c->C1, &c->E,
-                              &c->rp1, &c->x1, &c->C2, &c->Ed, &c->rp2, &c->x2};
+                              &c->rp1, &c->x1, &c->C2, &c->Ed, &c->rv, &c->xv};
   for (LuWs& w : c->ws)
     for (DevBuf* b : {&w.W, &w.piv, &w.flags, &w.mods, &w.linv, &w.uinv, &w.tinv, &w.limbA,
                       &w.limbB, &w.res})

@@ -171,6 +171,10 @@ __device__ __forceinline__ uint32_t ld_dev(const uint32_t* a) {
 __device__ __forceinline__ void st_dev(uint32_t* a, uint32_t v) {
   __hip_atomic_store(a, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+// Buffer resource word 3 for raw (untyped) buffer accesses on CDNA, and the
+// sc1 cache-policy bit of the buffer-load builtins (device-coherent access).
+constexpr int BUF_RSRC_WORD3 = 0x00020000;
+constexpr int BUF_SC1 = 16;
 
 // All k lifting steps with the rows of C and A held in registers for the
 // whole loop.  Workgroups of 512 threads (8 waves, so up to 256 VGPRs per
@@ -552,7 +556,12 @@ hipError_t launch_lift_resident2(int grid, const uint32_t* C0, const uint32_t* C
 }
 
 // Shape of the three-plane kernel: 8 waves per workgroup, 2 rows per wave.
-static int lift3_grid_size(int n) { return (n + 15) / 16; }
+// Shape of the three-plane lifting: LIFT3_NWAVE waves of LIFT3_RPW rows per
+// workgroup, one workgroup per LIFT3_RPW * LIFT3_NWAVE rows.
+constexpr int LIFT3_RPW = 1, LIFT3_NWAVE = 8;
+static int lift3_grid_size(int n) {
+  return (n + LIFT3_RPW * LIFT3_NWAVE - 1) / (LIFT3_RPW * LIFT3_NWAVE);
+}
 
 int lift3_grid(int device, int n) {
   int cus = 0, coop = 0;
@@ -740,12 +749,15 @@ __device__ __forceinline__ int32_t centred_i32(uint32_t u, uint32_t p) {
 }
 
 // All lifting steps modulo p^3 in FP64, three base-p digits per step, with
-// the centred planes c0, c1, c2 of A^{-1} mod p^3 and the rows of A in
-// registers: wave w of workgroup g (NWAVE waves) owns rows
-// (NWAVE g + w) RPW + i, lane l columns l + 64 e (e < EPL).  Vectors passed
-// between workgroups: the three digit planes of r mod p^3, balanced (|digit|
-// <= (p-1)/2, r = w0 + p w1 + p^2 w2 mod p^3), and the three digit planes of
-// x in [0, p).
+// the centred planes c0, c1, c2 of A^{-1} mod p^3 in registers and the rows
+// of A in LDS.  Each row is split over CS waves: wave w of workgroup g
+// (NWAVE waves, RG = RPW NWAVE / CS rows) owns rows g RG + (w / CS) RPW + i
+// (i < RPW) in the column part w mod CS, lane l holding columns
+// 64 EPL (w mod CS) + l + 64 e (e < EPL); the parts' sums meet in LDS.  Vectors passed
+// between workgroups: the three digits of r mod p^3, balanced (|digit| <=
+// (p-1)/2, r = w0 + p w1 + p^2 w2 mod p^3), and the three digits of x in
+// [0, p), row by row in 16 bytes (rv, xv: n x 4 words, the fourth word
+// holding only the tag).
 // Phase X, per lane over its EPL columns (w_q = centred digit q of r):
 //   S0 = sum c0 w0, S1 = sum c0 w1 + c1 w0, S2 = sum c0 w2 + c1 w1 + c2 w0,
 // each partial sum of 16 products below 2^52; carries are taken lane by lane
@@ -756,68 +768,135 @@ __device__ __forceinline__ int32_t centred_i32(uint32_t u, uint32_t p) {
 //
 // No grid barrier: every exchanged 32-bit word holds a 25-bit digit (two's
 // complement for r, plain for x) under a 7-bit tag, the step number mod 127,
-// and is written and read with device-coherent atomics; a reader polls each
-// word until its tag is the step it wants.  The words of x of step s are
+// and is written and read at the device-coherent level; a reader polls until
+// the words it wants carry the tag of its step.  The words of x of step s are
 // written only after their writer has read all of r of step s, and each word
 // of r of step s+1 only after its writer has read all of x of step s, so a
 // word is never overwritten before every workgroup has read it, and a reader
 // finds in it either the value it waits for or the one before it (another
-// tag).  Tags run over 0..126: the caller fills x with all-ones words (tag
-// 127) before the launch and writes r of step 0 with tag 0.  A wait that
-// exceeds spin_limit polls sets *err; after that every wait gives up within
-// 64 polls, so all waves exit.
-template <int EPL, int RPW, int NWAVE>
+// tag).  Tags run over 0..126: the caller fills xv with all-ones words (tag
+// 127) before the launch and writes r of step 0 with tag 0.  Each workgroup
+// gathers its rows in LDS and writes them with one store instruction: many
+// small writes into one segment, one per digit and row, take several times
+// longer to become visible than one contiguous write.  A wait that exceeds spin_limit polls sets *err; after that
+// every wait gives up within 64 polls, so all waves exit.
+template <int EPL, int RPW, int NWAVE, int CS>
 __global__ __launch_bounds__(64 * NWAVE) void k_lift_resident3(
     const uint32_t* __restrict__ C0, const uint32_t* __restrict__ C1,
     const uint32_t* __restrict__ C2, const int32_t* __restrict__ Ai, int64_t* __restrict__ r,
-    uint32_t* rp0, uint32_t* rp1, uint32_t* rp2, uint32_t* xb0, uint32_t* xb1, uint32_t* xb2,
-    int n, uint32_t p, double pinv, uint64_t pinv64, int64_t kd,
+    uint32_t* rv, uint32_t* xv, int n, uint32_t p, double pinv, uint64_t pinv64, int64_t kd,
     uint32_t* __restrict__ digits, int* err, unsigned spin_limit) {
+  typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const double pd = (double)p;
   constexpr uint32_t DIG = LIFT3_DIGIT_MASK;
-  // the three planes of the vector a phase reads, staged once per workgroup
-  // (64 EPL entries each, decoded; the workgroup's threads load them
-  // together), one buffer per phase so that a phase may stage while slower
-  // waves still read the other phase's buffer
-  __shared__ uint32_t sV[2][3][64 * EPL];
+  static_assert(NWAVE % CS == 0, "whole rows per workgroup");
+  constexpr int RG = RPW * NWAVE / CS;                  // rows per workgroup
+  constexpr int NC = 64 * EPL * CS;                     // columns (at least n)
+  constexpr int NJ = (EPL * CS + NWAVE - 1) / NWAVE;    // rows staged per thread
+  const int ngroups = gridDim.x;
+  const int row0 = blockIdx.x * RG;
+  const int slot = wave / CS;                           // row slot of this wave
+  const int c0l = 64 * EPL * (wave % CS) + lane;        // its first column
+  // the vector a phase reads, staged once per workgroup and decoded (digit
+  // plane t of row j at [t][j]), one buffer per phase so that a phase may
+  // stage while slower waves still read the other phase's buffer
+  __shared__ uint32_t sV[2][3][NC];
+  // the workgroup's rows of the vector a phase writes, gathered for one store,
+  // and the column parts' wave sums of each row
+  __shared__ uint32_t sOut[RG * 4];
+  __shared__ int64_t sPart[CS > 1 ? RG * RPW * CS * 3 : 1];
+  // 16-byte loads at the device-coherent level: buffer loads with the sc1
+  // cache policy (offsets past 16 n bytes read as zero)
+  const __amdgpu_buffer_rsrc_t rsr = __builtin_amdgcn_make_buffer_rsrc(rv, 0, 16 * n, BUF_RSRC_WORD3);
+  const __amdgpu_buffer_rsrc_t rsx = __builtin_amdgcn_make_buffer_rsrc(xv, 0, 16 * n, BUF_RSRC_WORD3);
   bool gave_up = false;
-  auto stage3 = [&](uint32_t (*s)[64 * EPL], const uint32_t* v0, const uint32_t* v1,
-                    const uint32_t* v2, uint32_t tag, bool sgn) {
-    for (int j = threadIdx.x; j < 64 * EPL; j += 64 * NWAVE) {
-      uint32_t a0 = 0, a1 = 0, a2 = 0;
-      if (j < n) {
-        unsigned spins = 0;
-        for (;;) {
-          a0 = ld_dev(v0 + j);
-          a1 = ld_dev(v1 + j);
-          a2 = ld_dev(v2 + j);
-          if (((a0 >> 25) == tag && (a1 >> 25) == tag && (a2 >> 25) == tag) || gave_up) break;
-          if ((++spins & 63) == 0) {
-            if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-              gave_up = true;
-              break;
-            }
-            if (spins > spin_limit) {
-              __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-              gave_up = true;
-              break;
-            }
-          }
-          __builtin_amdgcn_s_sleep(1);
-        }
+  // counts polls and gives up (setting *err, or on seeing it set) past the limit
+  auto keep_waiting = [&](unsigned& spins) {
+    if ((++spins & 63) == 0) {
+      if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+        gave_up = true;
+        return false;
       }
-      // r digits: sign-extend the 25-bit field; x digits: the field itself
-      s[0][j] = sgn ? (uint32_t)((int32_t)(a0 << 7) >> 7) : (a0 & DIG);
-      s[1][j] = sgn ? (uint32_t)((int32_t)(a1 << 7) >> 7) : (a1 & DIG);
-      s[2][j] = sgn ? (uint32_t)((int32_t)(a2 << 7) >> 7) : (a2 & DIG);
+      if (spins > spin_limit) {
+        __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        gave_up = true;
+        return false;
+      }
+    }
+    __builtin_amdgcn_s_sleep(1);
+    return true;
+  };
+  // Staging of one vector in two parts, to keep the polling traffic small:
+  // wave 0 first polls one proxy word per workgroup (the tag word of its last
+  // row) until each carries the wanted tag; then every thread reads its NJ
+  // rows once, and polls again only those whose tag is still old (a proxy
+  // may become visible before other words of its workgroup).
+  auto stage3 = [&](uint32_t (*s)[NC], const uint32_t* v, __amdgpu_buffer_rsrc_t src,
+                    uint32_t tag, bool sgn) {
+    if (wave == 0) {
+      unsigned spins = 0;
+      for (;;) {
+        uint32_t w[MAX_LIFT3_GROUPS / 64];
+#pragma unroll
+        for (int q = 0; q < MAX_LIFT3_GROUPS / 64; q++) {
+          const int g = lane + 64 * q;
+          w[q] = g < ngroups ? ld_dev(v + 4 * min(g * RG + RG - 1, n - 1) + 3) : tag << 25;
+        }
+        bool ok = true;
+#pragma unroll
+        for (int q = 0; q < MAX_LIFT3_GROUPS / 64; q++) ok &= (w[q] >> 25) == tag;
+        if (__all(ok) || gave_up || !keep_waiting(spins)) break;
+      }
+    }
+    __syncthreads();
+    u32x4 a[NJ];
+    bool want[NJ];
+#pragma unroll
+    for (int q = 0; q < NJ; q++) {
+      const int j = threadIdx.x + 64 * NWAVE * q;
+      want[q] = j < n && j < NC;
+      a[q] = u32x4{0, 0, 0, 0};
+    }
+    unsigned spins = 0;
+    for (;;) {
+#pragma unroll
+      for (int q = 0; q < NJ; q++) {
+        int off = 16 * (threadIdx.x + 64 * NWAVE * q);
+        asm volatile("" : "+v"(off));        // a fresh load on every poll
+        if (want[q]) a[q] = __builtin_amdgcn_raw_buffer_load_b128(src, off, 0, BUF_SC1);
+      }
+      bool pending = false;
+#pragma unroll
+      for (int q = 0; q < NJ; q++) {
+        if (want[q] && (a[q].x >> 25) == tag && (a[q].y >> 25) == tag && (a[q].z >> 25) == tag)
+          want[q] = false;
+        pending |= want[q];
+      }
+      if (!pending || gave_up || !keep_waiting(spins)) break;
+    }
+#pragma unroll
+    for (int q = 0; q < NJ; q++) {
+      const int j = threadIdx.x + 64 * NWAVE * q;
+      if (j < NC) {
+        // r digits: sign-extend the 25-bit field; x digits: the field itself
+        s[0][j] = sgn ? (uint32_t)((int32_t)(a[q].x << 7) >> 7) : (a[q].x & DIG);
+        s[1][j] = sgn ? (uint32_t)((int32_t)(a[q].y << 7) >> 7) : (a[q].y & DIG);
+        s[2][j] = sgn ? (uint32_t)((int32_t)(a[q].z << 7) >> 7) : (a[q].z & DIG);
+      }
     }
     __syncthreads();
   };
+  // the workgroup writes its gathered rows: one word per thread
+  auto publish = [&](uint32_t* v) {
+    __syncthreads();
+    if (threadIdx.x < 4 * RG && row0 + (int)threadIdx.x / 4 < n)
+      st_dev(v + (size_t)row0 * 4 + threadIdx.x, sOut[threadIdx.x]);
+  };
   // the workgroup's rows of A live in LDS (only phase R reads them), the
   // three planes in registers (only phase X reads them)
-  __shared__ int32_t sA[NWAVE * RPW][64 * EPL];
+  __shared__ int32_t sA[RG][NC];
   // centred planes: c0, c1 (three and two uses per entry) as FP64, c2 (one
   // use) as int32, converted at its use
   double c0[RPW][EPL], c1[RPW][EPL];
@@ -826,18 +905,18 @@ __global__ __launch_bounds__(64 * NWAVE) void k_lift_resident3(
   int rows[RPW];
 #pragma unroll
   for (int i = 0; i < RPW; i++) {
-    const int row = (blockIdx.x * NWAVE + wave) * RPW + i;
+    const int row = row0 + slot * RPW + i;
     rows[i] = row;
     rr[i] = 0;
 #pragma unroll
     for (int e = 0; e < EPL; e++) {
-      const int j = lane + 64 * e;
+      const int j = c0l + 64 * e;
       const bool in = row < n && j < n;
       const int64_t o = (int64_t)row * n + j;
       c0[i][e] = in ? (double)centred_i32(C0[o], p) : 0.0;
       c1[i][e] = in ? (double)centred_i32(C1[o], p) : 0.0;
       c2[i][e] = in ? centred_i32(C2[o], p) : 0;
-      sA[wave * RPW + i][j] = in ? Ai[o] : 0;
+      sA[slot * RPW + i][j] = in ? Ai[o] : 0;
     }
     if (row < n && lane == 0) rr[i] = r[row];
   }
@@ -850,12 +929,12 @@ __global__ __launch_bounds__(64 * NWAVE) void k_lift_resident3(
     double S0[RPW], S1a[RPW], S1b[RPW], S2a[RPW], S2b[RPW], S2c[RPW];
 #pragma unroll
     for (int i = 0; i < RPW; i++) S0[i] = S1a[i] = S1b[i] = S2a[i] = S2b[i] = S2c[i] = 0.0;
-    stage3(sV[0], rp0, rp1, rp2, tag, true);
+    stage3(sV[0], rv, rsr, tag, true);
 #pragma unroll
     for (int e = 0; e < EPL; e++) {
-      const double w0 = (double)(int32_t)sV[0][0][lane + 64 * e];  // balanced digits
-      const double w1 = (double)(int32_t)sV[0][1][lane + 64 * e];
-      const double w2 = (double)(int32_t)sV[0][2][lane + 64 * e];
+      const double w0 = (double)(int32_t)sV[0][0][c0l + 64 * e];  // balanced digits
+      const double w1 = (double)(int32_t)sV[0][1][c0l + 64 * e];
+      const double w2 = (double)(int32_t)sV[0][2][c0l + 64 * e];
 #pragma unroll
       for (int i = 0; i < RPW; i++) {
         // z (always 0, unknown to the compiler) keeps an FP64 copy of c2
@@ -889,19 +968,39 @@ __global__ __launch_bounds__(64 * NWAVE) void k_lift_resident3(
         const double T2 = mod_loose(S2a[i], pd, pinv) + mod_loose(S2b[i], pd, pinv) +
                           mod_loose(S2c[i], pd, pinv) + qa + q1;
         const double m2 = mod_loose(T2, pd, pinv);
-        const int64_t M0 = dpp_sum_i32((int)m0);
-        const int64_t M1 = dpp_sum_i32((int)m1);
-        const int64_t M2 = dpp_sum_i32((int)m2);
-        if (rows[i] < n && lane == 0) {
+        int64_t M0 = dpp_sum_i32((int)m0);
+        int64_t M1 = dpp_sum_i32((int)m1);
+        int64_t M2 = dpp_sum_i32((int)m2);
+        if (CS > 1) {
+          // the parts' sums meet in LDS; part 0 carries on
+          if (lane == 0) {
+            int64_t* q = sPart + ((slot * RPW + i) * CS + wave % CS) * 3;
+            q[0] = M0;
+            q[1] = M1;
+            q[2] = M2;
+          }
+          __syncthreads();
+          M0 = M1 = M2 = 0;
+#pragma unroll
+          for (int t = 0; t < CS; t++) {
+            const int64_t* q = sPart + ((slot * RPW + i) * CS + t) * 3;
+            M0 += q[0];
+            M1 += q[1];
+            M2 += q[2];
+          }
+        }
+        if (rows[i] < n && lane == 0 && wave % CS == 0) {
           // carries by exact division (multiplication by p^{-1} mod 2^64)
           const uint32_t x0 = smod64(M0, p, pinv);
           const int64_t t1 = M1 + (int64_t)((uint64_t)(M0 - (int64_t)x0) * pinv64);
           const uint32_t x1 = smod64(t1, p, pinv);
           const int64_t t2 = M2 + (int64_t)((uint64_t)(t1 - (int64_t)x1) * pinv64);
           const uint32_t x2 = smod64(t2, p, pinv);
-          st_dev(xb0 + rows[i], tag << 25 | x0);
-          st_dev(xb1 + rows[i], tag << 25 | x1);
-          st_dev(xb2 + rows[i], tag << 25 | x2);
+          uint32_t* o = sOut + (slot * RPW + i) * 4;
+          o[0] = tag << 25 | x0;
+          o[1] = tag << 25 | x1;
+          o[2] = tag << 25 | x2;
+          o[3] = tag << 25;
           if (digits) {
             digits[(3 * step) * n + rows[i]] = x0;
             if (3 * step + 1 < kd) digits[(3 * step + 1) * n + rows[i]] = x1;
@@ -910,19 +1009,20 @@ __global__ __launch_bounds__(64 * NWAVE) void k_lift_resident3(
         }
       }
     }
+    publish(xv);
     // ---- phase R
     double D0[RPW], D1[RPW], D2[RPW];
 #pragma unroll
     for (int i = 0; i < RPW; i++) D0[i] = D1[i] = D2[i] = 0.0;
-    stage3(sV[1], xb0, xb1, xb2, tag, false);
+    stage3(sV[1], xv, rsx, tag, false);
 #pragma unroll
     for (int e = 0; e < EPL; e++) {
-      const double x0 = (double)sV[1][0][lane + 64 * e];
-      const double x1 = (double)sV[1][1][lane + 64 * e];
-      const double x2 = (double)sV[1][2][lane + 64 * e];
+      const double x0 = (double)sV[1][0][c0l + 64 * e];
+      const double x1 = (double)sV[1][1][c0l + 64 * e];
+      const double x2 = (double)sV[1][2][c0l + 64 * e];
 #pragma unroll
       for (int i = 0; i < RPW; i++) {
-        const double av = (double)sA[wave * RPW + i][lane + 64 * e];
+        const double av = (double)sA[slot * RPW + i][c0l + 64 * e];
         D0[i] = fma(av, x0, D0[i]);
         D1[i] = fma(av, x1, D1[i]);
         D2[i] = fma(av, x2, D2[i]);
@@ -933,10 +1033,31 @@ __global__ __launch_bounds__(64 * NWAVE) void k_lift_resident3(
 #pragma unroll
     for (int i = 0; i < RPW; i++) {
       {
-        const double d0 = dpp_sum_f64(D0[i]);
-        const double d1 = dpp_sum_f64(D1[i]);
-        const double d2 = dpp_sum_f64(D2[i]);
-        if (rows[i] < n && lane == 0) {
+        double d0 = dpp_sum_f64(D0[i]);
+        double d1 = dpp_sum_f64(D1[i]);
+        double d2 = dpp_sum_f64(D2[i]);
+        if (CS > 1) {
+          // the parts' sums (integers: the total is below 2^53 as well)
+          if (lane == 0) {
+            int64_t* q = sPart + ((slot * RPW + i) * CS + wave % CS) * 3;
+            q[0] = (int64_t)d0;
+            q[1] = (int64_t)d1;
+            q[2] = (int64_t)d2;
+          }
+          __syncthreads();
+          int64_t e0 = 0, e1 = 0, e2 = 0;
+#pragma unroll
+          for (int t = 0; t < CS; t++) {
+            const int64_t* q = sPart + ((slot * RPW + i) * CS + t) * 3;
+            e0 += q[0];
+            e1 += q[1];
+            e2 += q[2];
+          }
+          d0 = (double)e0;
+          d1 = (double)e1;
+          d2 = (double)e2;
+        }
+        if (rows[i] < n && lane == 0 && wave % CS == 0) {
           // exact divisions by p through p^{-1} mod 2^64
           int64_t q = (int64_t)((uint64_t)(rr[i] - (int64_t)d0) * pinv64);
           q = (int64_t)((uint64_t)(q - (int64_t)d1) * pinv64);
@@ -949,17 +1070,20 @@ __global__ __launch_bounds__(64 * NWAVE) void k_lift_resident3(
           const int32_t m1 = centred_i32(smod64(u1, p, pinv), p);
           const int64_t u2 = (int64_t)((uint64_t)(u1 - (int64_t)m1) * pinv64);
           const int32_t m2 = centred_i32(smod64(u2, p, pinv), p);
-          st_dev(rp0 + rows[i], tag1 << 25 | ((uint32_t)m0 & DIG));
-          st_dev(rp1 + rows[i], tag1 << 25 | ((uint32_t)m1 & DIG));
-          st_dev(rp2 + rows[i], tag1 << 25 | ((uint32_t)m2 & DIG));
+          uint32_t* o = sOut + (slot * RPW + i) * 4;
+          o[0] = tag1 << 25 | ((uint32_t)m0 & DIG);
+          o[1] = tag1 << 25 | ((uint32_t)m1 & DIG);
+          o[2] = tag1 << 25 | ((uint32_t)m2 & DIG);
+          o[3] = tag1 << 25;
         }
       }
     }
+    publish(rv);
     tag = tag1;
   }
 #pragma unroll
   for (int i = 0; i < RPW; i++)
-    if (rows[i] < n && lane == 0) r[rows[i]] = rr[i];
+    if (rows[i] < n && lane == 0 && wave % CS == 0) r[rows[i]] = rr[i];
 }
 
 // comb[i] = sum_j c_j x_i[j] for every lifted digit vector x_i (the random
@@ -1000,25 +1124,22 @@ hipError_t launch_hensel_f64(const int32_t* Ai, const uint32_t* C0, double* E, u
 }
 
 hipError_t launch_lift_resident3(int grid, const uint32_t* C0, const uint32_t* C1,
-                                 const uint32_t* C2, const int32_t* Ai, int64_t* r,
-                                 uint32_t* rp0, uint32_t* rp1, uint32_t* rp2, uint32_t* xb0,
-                                 uint32_t* xb1, uint32_t* xb2, int n, uint32_t p,
-                                 uint64_t pinv64, int64_t kd, uint32_t* digits, int* err,
-                                 hipStream_t st) {
+                                 const uint32_t* C2, const int32_t* Ai, int64_t* r, uint32_t* rv,
+                                 uint32_t* xv, int n, uint32_t p, uint64_t pinv64, int64_t kd,
+                                 uint32_t* digits, int* err, hipStream_t st) {
   if (n <= 0 || kd <= 0) return hipSuccess;
   if (p >= (1u << 25)) return hipErrorInvalidValue;
   double pinv = 1.0 / (double)p;
   unsigned spin_limit = 1u << 18;     // polls of about 1 us each: ~0.3 s per wait at most
-  void* args[] = {(void*)&C0, (void*)&C1, (void*)&C2, (void*)&Ai, (void*)&r, (void*)&rp0,
-                  (void*)&rp1, (void*)&rp2, (void*)&xb0, (void*)&xb1, (void*)&xb2, (void*)&n,
-                  (void*)&p, (void*)&pinv, (void*)&pinv64, (void*)&kd, (void*)&digits,
-                  (void*)&err, (void*)&spin_limit};
+  void* args[] = {(void*)&C0, (void*)&C1, (void*)&C2, (void*)&Ai, (void*)&r, (void*)&rv,
+                  (void*)&xv, (void*)&n, (void*)&p, (void*)&pinv, (void*)&pinv64, (void*)&kd,
+                  (void*)&digits, (void*)&err, (void*)&spin_limit};
   const void* f = nullptr;
-  if (n <= 256) f = (const void*)k_lift_resident3<4, 2, 8>;
-  else if (n <= 512) f = (const void*)k_lift_resident3<8, 2, 8>;
-  else if (n <= 1024) f = (const void*)k_lift_resident3<16, 2, 8>;
-  if (!f || grid != lift3_grid_size(n)) return hipErrorInvalidValue;
-  return hipLaunchCooperativeKernel(f, dim3(grid), dim3(512), args, 0, st);
+  if (n <= 256) f = (const void*)k_lift_resident3<4, LIFT3_RPW, LIFT3_NWAVE, 1>;
+  else if (n <= 512) f = (const void*)k_lift_resident3<8, LIFT3_RPW, LIFT3_NWAVE, 1>;
+  else if (n <= 1024) f = (const void*)k_lift_resident3<16, LIFT3_RPW, LIFT3_NWAVE, 1>;
+  if (!f || grid != lift3_grid_size(n) || grid > MAX_LIFT3_GROUPS) return hipErrorInvalidValue;
+  return hipLaunchCooperativeKernel(f, dim3(grid), dim3(64 * LIFT3_NWAVE), args, 0, st);
 }
 
 hipError_t launch_lift_persistent(int grid, const uint32_t* Cu, const int32_t* Ai, int64_t* r,
