@@ -749,15 +749,13 @@ __device__ __forceinline__ int32_t centred_i32(uint32_t u, uint32_t p) {
 }
 
 // All lifting steps modulo p^3 in FP64, three base-p digits per step, with
-// the centred planes c0, c1, c2 of A^{-1} mod p^3 in registers and the rows
-// of A in LDS.  Each row is split over CS waves: wave w of workgroup g
-// (NWAVE waves, RG = RPW NWAVE / CS rows) owns rows g RG + (w / CS) RPW + i
-// (i < RPW) in the column part w mod CS, lane l holding columns
-// 64 EPL (w mod CS) + l + 64 e (e < EPL); the parts' sums meet in LDS.  Vectors passed
-// between workgroups: the three digits of r mod p^3, balanced (|digit| <=
-// (p-1)/2, r = w0 + p w1 + p^2 w2 mod p^3), and the three digits of x in
-// [0, p), row by row in 16 bytes (rv, xv: n x 4 words, the fourth word
-// holding only the tag).
+// the centred planes c0, c1, c2 of A^{-1} mod p^3 and the rows of A in
+// registers as FP64: wave w of workgroup g (NWAVE waves, RG = RPW NWAVE
+// rows) owns rows g RG + w RPW + i (i < RPW), lane l columns l + 64 e
+// (e < EPL).  Vectors passed between workgroups: the three digits of r mod
+// p^3, balanced (|digit| <= (p-1)/2, r = w0 + p w1 + p^2 w2 mod p^3), and the
+// three digits of x in [0, p), row by row in 16 bytes (rv, xv: n x 4 words,
+// the fourth word holding only the tag).
 // Phase X, per lane over its EPL columns (w_q = centred digit q of r):
 //   S0 = sum c0 w0, S1 = sum c0 w1 + c1 w0, S2 = sum c0 w2 + c1 w1 + c2 w0,
 // each partial sum of 16 products below 2^52; carries are taken lane by lane
@@ -778,9 +776,10 @@ __device__ __forceinline__ int32_t centred_i32(uint32_t u, uint32_t p) {
 // 127) before the launch and writes r of step 0 with tag 0.  Each workgroup
 // gathers its rows in LDS and writes them with one store instruction: many
 // small writes into one segment, one per digit and row, take several times
-// longer to become visible than one contiguous write.  A wait that exceeds spin_limit polls sets *err; after that
-// every wait gives up within 64 polls, so all waves exit.
-template <int EPL, int RPW, int NWAVE, int CS>
+// longer to become visible than one contiguous write.  A wait that exceeds
+// spin_limit polls sets *err; after that every wait gives up within 64
+// polls, so all waves exit.
+template <int EPL, int RPW, int NWAVE>
 __global__ __launch_bounds__(64 * NWAVE) void k_lift_resident3(
     const uint32_t* __restrict__ C0, const uint32_t* __restrict__ C1,
     const uint32_t* __restrict__ C2, const int32_t* __restrict__ Ai, int64_t* __restrict__ r,
@@ -791,66 +790,25 @@ __global__ __launch_bounds__(64 * NWAVE) void k_lift_resident3(
   const int wave = threadIdx.x >> 6;
   const double pd = (double)p;
   constexpr uint32_t DIG = LIFT3_DIGIT_MASK;
-  static_assert(NWAVE % CS == 0, "whole rows per workgroup");
-  constexpr int RG = RPW * NWAVE / CS;                  // rows per workgroup
-  constexpr int NC = 64 * EPL * CS;                     // columns (at least n)
-  constexpr int NJ = (EPL * CS + NWAVE - 1) / NWAVE;    // rows staged per thread
-  const int ngroups = gridDim.x;
+  constexpr int RG = RPW * NWAVE;                       // rows per workgroup
+  constexpr int NC = 64 * EPL;                          // columns (at least n)
+  constexpr int NJ = (EPL + NWAVE - 1) / NWAVE;         // rows staged per thread
   const int row0 = blockIdx.x * RG;
-  const int slot = wave / CS;                           // row slot of this wave
-  const int c0l = 64 * EPL * (wave % CS) + lane;        // its first column
-  // the vector a phase reads, staged once per workgroup and decoded (digit
-  // plane t of row j at [t][j]), one buffer per phase so that a phase may
-  // stage while slower waves still read the other phase's buffer
-  __shared__ uint32_t sV[2][3][NC];
-  // the workgroup's rows of the vector a phase writes, gathered for one store,
-  // and the column parts' wave sums of each row
+  // the vector a phase reads, staged once per workgroup as FP64 (digit t of
+  // row j at [t][j]), one buffer per phase so that a phase may stage while
+  // slower waves still read the other phase's buffer
+  __shared__ double sV[2][3][NC];
+  // the workgroup's rows of the vector a phase writes, gathered for one store
   __shared__ uint32_t sOut[RG * 4];
-  __shared__ int64_t sPart[CS > 1 ? RG * RPW * CS * 3 : 1];
   // 16-byte loads at the device-coherent level: buffer loads with the sc1
   // cache policy (offsets past 16 n bytes read as zero)
   const __amdgpu_buffer_rsrc_t rsr = __builtin_amdgcn_make_buffer_rsrc(rv, 0, 16 * n, BUF_RSRC_WORD3);
   const __amdgpu_buffer_rsrc_t rsx = __builtin_amdgcn_make_buffer_rsrc(xv, 0, 16 * n, BUF_RSRC_WORD3);
   bool gave_up = false;
-  // counts polls and gives up (setting *err, or on seeing it set) past the limit
-  auto keep_waiting = [&](unsigned& spins) {
-    if ((++spins & 63) == 0) {
-      if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-        gave_up = true;
-        return false;
-      }
-      if (spins > spin_limit) {
-        __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        gave_up = true;
-        return false;
-      }
-    }
-    __builtin_amdgcn_s_sleep(1);
-    return true;
-  };
-  // Staging of one vector in two parts, to keep the polling traffic small:
-  // wave 0 first polls one proxy word per workgroup (the tag word of its last
-  // row) until each carries the wanted tag; then every thread reads its NJ
-  // rows once, and polls again only those whose tag is still old (a proxy
-  // may become visible before other words of its workgroup).
-  auto stage3 = [&](uint32_t (*s)[NC], const uint32_t* v, __amdgpu_buffer_rsrc_t src,
-                    uint32_t tag, bool sgn) {
-    if (wave == 0) {
-      unsigned spins = 0;
-      for (;;) {
-        uint32_t w[MAX_LIFT3_GROUPS / 64];
-#pragma unroll
-        for (int q = 0; q < MAX_LIFT3_GROUPS / 64; q++) {
-          const int g = lane + 64 * q;
-          w[q] = g < ngroups ? ld_dev(v + 4 * min(g * RG + RG - 1, n - 1) + 3) : tag << 25;
-        }
-        bool ok = true;
-#pragma unroll
-        for (int q = 0; q < MAX_LIFT3_GROUPS / 64; q++) ok &= (w[q] >> 25) == tag;
-        if (__all(ok) || gave_up || !keep_waiting(spins)) break;
-      }
-    }
-    __syncthreads();
+  // Staging of one vector: every thread reads its NJ rows and polls again
+  // those whose tag is still old; after spin_limit polls it sets *err (or
+  // gives up on finding it set).
+  auto stage3 = [&](double (*s)[NC], __amdgpu_buffer_rsrc_t src, uint32_t tag, bool sgn) {
     u32x4 a[NJ];
     bool want[NJ];
 #pragma unroll
@@ -874,16 +832,28 @@ __global__ __launch_bounds__(64 * NWAVE) void k_lift_resident3(
           want[q] = false;
         pending |= want[q];
       }
-      if (!pending || gave_up || !keep_waiting(spins)) break;
+      if (!pending || gave_up) break;
+      if ((++spins & 63) == 0) {
+        if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+          gave_up = true;
+          break;
+        }
+        if (spins > spin_limit) {
+          __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          gave_up = true;
+          break;
+        }
+      }
+      __builtin_amdgcn_s_sleep(1);
     }
 #pragma unroll
     for (int q = 0; q < NJ; q++) {
       const int j = threadIdx.x + 64 * NWAVE * q;
       if (j < NC) {
         // r digits: sign-extend the 25-bit field; x digits: the field itself
-        s[0][j] = sgn ? (uint32_t)((int32_t)(a[q].x << 7) >> 7) : (a[q].x & DIG);
-        s[1][j] = sgn ? (uint32_t)((int32_t)(a[q].y << 7) >> 7) : (a[q].y & DIG);
-        s[2][j] = sgn ? (uint32_t)((int32_t)(a[q].z << 7) >> 7) : (a[q].z & DIG);
+        s[0][j] = sgn ? (double)((int32_t)(a[q].x << 7) >> 7) : (double)(a[q].x & DIG);
+        s[1][j] = sgn ? (double)((int32_t)(a[q].y << 7) >> 7) : (double)(a[q].y & DIG);
+        s[2][j] = sgn ? (double)((int32_t)(a[q].z << 7) >> 7) : (double)(a[q].z & DIG);
       }
     }
     __syncthreads();
@@ -894,118 +864,80 @@ __global__ __launch_bounds__(64 * NWAVE) void k_lift_resident3(
     if (threadIdx.x < 4 * RG && row0 + (int)threadIdx.x / 4 < n)
       st_dev(v + (size_t)row0 * 4 + threadIdx.x, sOut[threadIdx.x]);
   };
-  // the workgroup's rows of A live in LDS (only phase R reads them), the
-  // three planes in registers (only phase X reads them)
-  __shared__ int32_t sA[RG][NC];
-  // centred planes: c0, c1 (three and two uses per entry) as FP64, c2 (one
-  // use) as int32, converted at its use
-  double c0[RPW][EPL], c1[RPW][EPL];
-  int32_t c2[RPW][EPL];
+  // centred planes and the rows of A, FP64 in registers
+  double c0[RPW][EPL], c1[RPW][EPL], c2[RPW][EPL], av[RPW][EPL];
   int64_t rr[RPW];
   int rows[RPW];
 #pragma unroll
   for (int i = 0; i < RPW; i++) {
-    const int row = row0 + slot * RPW + i;
+    const int row = row0 + wave * RPW + i;
     rows[i] = row;
     rr[i] = 0;
 #pragma unroll
     for (int e = 0; e < EPL; e++) {
-      const int j = c0l + 64 * e;
+      const int j = lane + 64 * e;
       const bool in = row < n && j < n;
       const int64_t o = (int64_t)row * n + j;
       c0[i][e] = in ? (double)centred_i32(C0[o], p) : 0.0;
       c1[i][e] = in ? (double)centred_i32(C1[o], p) : 0.0;
-      c2[i][e] = in ? centred_i32(C2[o], p) : 0;
-      sA[slot * RPW + i][j] = in ? Ai[o] : 0;
+      c2[i][e] = in ? (double)centred_i32(C2[o], p) : 0.0;
+      av[i][e] = in ? (double)Ai[o] : 0.0;
     }
     if (row < n && lane == 0) rr[i] = r[row];
   }
   const int64_t steps = (kd + 2) / 3;
   uint32_t tag = 0;                                // step mod 127
   for (int64_t step = 0; step < steps; step++) {
-    const int z = (int)(step >> 62);               // 0: step < 2^62
     const uint32_t tag1 = tag == 126 ? 0 : tag + 1;
     // ---- phase X
     double S0[RPW], S1a[RPW], S1b[RPW], S2a[RPW], S2b[RPW], S2c[RPW];
 #pragma unroll
     for (int i = 0; i < RPW; i++) S0[i] = S1a[i] = S1b[i] = S2a[i] = S2b[i] = S2c[i] = 0.0;
-    stage3(sV[0], rv, rsr, tag, true);
+    stage3(sV[0], rsr, tag, true);
 #pragma unroll
     for (int e = 0; e < EPL; e++) {
-      const double w0 = (double)(int32_t)sV[0][0][c0l + 64 * e];  // balanced digits
-      const double w1 = (double)(int32_t)sV[0][1][c0l + 64 * e];
-      const double w2 = (double)(int32_t)sV[0][2][c0l + 64 * e];
+      const double w0 = sV[0][0][lane + 64 * e];    // balanced digits
+      const double w1 = sV[0][1][lane + 64 * e];
+      const double w2 = sV[0][2][lane + 64 * e];
 #pragma unroll
       for (int i = 0; i < RPW; i++) {
-        // z (always 0, unknown to the compiler) keeps an FP64 copy of c2
-        // from being hoisted out of the step loop
-        const double x0 = c0[i][e], x1 = c1[i][e], x2 = (double)(c2[i][e] ^ z);
-        S0[i] = fma(x0, w0, S0[i]);
-        S1a[i] = fma(x0, w1, S1a[i]);
-        S1b[i] = fma(x1, w0, S1b[i]);
-        S2a[i] = fma(x0, w2, S2a[i]);
-        S2b[i] = fma(x1, w1, S2b[i]);
-        S2c[i] = fma(x2, w0, S2c[i]);
+        S0[i] = fma(c0[i][e], w0, S0[i]);
+        S1a[i] = fma(c0[i][e], w1, S1a[i]);
+        S1b[i] = fma(c1[i][e], w0, S1b[i]);
+        S2a[i] = fma(c0[i][e], w2, S2a[i]);
+        S2b[i] = fma(c1[i][e], w1, S2b[i]);
+        S2c[i] = fma(c2[i][e], w0, S2c[i]);
       }
-      // one column at a time for every row: the empty asm consumes the
-      // accumulators, so no row's products are sunk below the column loop
-      // (which would keep every staged value of the phase live)
-#pragma unroll
-      for (int i = 0; i < RPW; i++)
-        asm volatile("" : "+v"(S0[i]), "+v"(S1a[i]), "+v"(S1b[i]), "+v"(S2a[i]), "+v"(S2b[i]),
-                     "+v"(S2c[i]));
     }
-    // (absent rows, whose planes are 0, run through as well: a conditional
-    // here would let the compiler sink the row's products into it, out of
-    // the column-by-column schedule above)
+    // (absent rows, whose planes are 0, run through as well)
 #pragma unroll
     for (int i = 0; i < RPW; i++) {
-      {
-        const double q0 = rint(S0[i] * pinv), m0 = fma(-q0, pd, S0[i]);
-        const double qa = rint(S1a[i] * pinv), ma = fma(-qa, pd, S1a[i]);
-        const double T1 = ma + S1b[i] + q0;
-        const double q1 = rint(T1 * pinv), m1 = fma(-q1, pd, T1);
-        const double T2 = mod_loose(S2a[i], pd, pinv) + mod_loose(S2b[i], pd, pinv) +
-                          mod_loose(S2c[i], pd, pinv) + qa + q1;
-        const double m2 = mod_loose(T2, pd, pinv);
-        int64_t M0 = dpp_sum_i32((int)m0);
-        int64_t M1 = dpp_sum_i32((int)m1);
-        int64_t M2 = dpp_sum_i32((int)m2);
-        if (CS > 1) {
-          // the parts' sums meet in LDS; part 0 carries on
-          if (lane == 0) {
-            int64_t* q = sPart + ((slot * RPW + i) * CS + wave % CS) * 3;
-            q[0] = M0;
-            q[1] = M1;
-            q[2] = M2;
-          }
-          __syncthreads();
-          M0 = M1 = M2 = 0;
-#pragma unroll
-          for (int t = 0; t < CS; t++) {
-            const int64_t* q = sPart + ((slot * RPW + i) * CS + t) * 3;
-            M0 += q[0];
-            M1 += q[1];
-            M2 += q[2];
-          }
-        }
-        if (rows[i] < n && lane == 0 && wave % CS == 0) {
-          // carries by exact division (multiplication by p^{-1} mod 2^64)
-          const uint32_t x0 = smod64(M0, p, pinv);
-          const int64_t t1 = M1 + (int64_t)((uint64_t)(M0 - (int64_t)x0) * pinv64);
-          const uint32_t x1 = smod64(t1, p, pinv);
-          const int64_t t2 = M2 + (int64_t)((uint64_t)(t1 - (int64_t)x1) * pinv64);
-          const uint32_t x2 = smod64(t2, p, pinv);
-          uint32_t* o = sOut + (slot * RPW + i) * 4;
-          o[0] = tag << 25 | x0;
-          o[1] = tag << 25 | x1;
-          o[2] = tag << 25 | x2;
-          o[3] = tag << 25;
-          if (digits) {
-            digits[(3 * step) * n + rows[i]] = x0;
-            if (3 * step + 1 < kd) digits[(3 * step + 1) * n + rows[i]] = x1;
-            if (3 * step + 2 < kd) digits[(3 * step + 2) * n + rows[i]] = x2;
-          }
+      const double q0 = rint(S0[i] * pinv), m0 = fma(-q0, pd, S0[i]);
+      const double qa = rint(S1a[i] * pinv), ma = fma(-qa, pd, S1a[i]);
+      const double T1 = ma + S1b[i] + q0;
+      const double q1 = rint(T1 * pinv), m1 = fma(-q1, pd, T1);
+      const double T2 = mod_loose(S2a[i], pd, pinv) + mod_loose(S2b[i], pd, pinv) +
+                        mod_loose(S2c[i], pd, pinv) + qa + q1;
+      const double m2 = mod_loose(T2, pd, pinv);
+      const int64_t M0 = dpp_sum_i32((int)m0);
+      const int64_t M1 = dpp_sum_i32((int)m1);
+      const int64_t M2 = dpp_sum_i32((int)m2);
+      if (rows[i] < n && lane == 0) {
+        // carries by exact division (multiplication by p^{-1} mod 2^64)
+        const uint32_t x0 = smod64(M0, p, pinv);
+        const int64_t t1 = M1 + (int64_t)((uint64_t)(M0 - (int64_t)x0) * pinv64);
+        const uint32_t x1 = smod64(t1, p, pinv);
+        const int64_t t2 = M2 + (int64_t)((uint64_t)(t1 - (int64_t)x1) * pinv64);
+        const uint32_t x2 = smod64(t2, p, pinv);
+        uint32_t* o = sOut + (wave * RPW + i) * 4;
+        o[0] = tag << 25 | x0;
+        o[1] = tag << 25 | x1;
+        o[2] = tag << 25 | x2;
+        o[3] = tag << 25;
+        if (digits) {
+          digits[(3 * step) * n + rows[i]] = x0;
+          if (3 * step + 1 < kd) digits[(3 * step + 1) * n + rows[i]] = x1;
+          if (3 * step + 2 < kd) digits[(3 * step + 2) * n + rows[i]] = x2;
         }
       }
     }
@@ -1014,68 +946,42 @@ __global__ __launch_bounds__(64 * NWAVE) void k_lift_resident3(
     double D0[RPW], D1[RPW], D2[RPW];
 #pragma unroll
     for (int i = 0; i < RPW; i++) D0[i] = D1[i] = D2[i] = 0.0;
-    stage3(sV[1], xv, rsx, tag, false);
+    stage3(sV[1], rsx, tag, false);
 #pragma unroll
     for (int e = 0; e < EPL; e++) {
-      const double x0 = (double)sV[1][0][c0l + 64 * e];
-      const double x1 = (double)sV[1][1][c0l + 64 * e];
-      const double x2 = (double)sV[1][2][c0l + 64 * e];
+      const double x0 = sV[1][0][lane + 64 * e];
+      const double x1 = sV[1][1][lane + 64 * e];
+      const double x2 = sV[1][2][lane + 64 * e];
 #pragma unroll
       for (int i = 0; i < RPW; i++) {
-        const double av = (double)sA[slot * RPW + i][c0l + 64 * e];
-        D0[i] = fma(av, x0, D0[i]);
-        D1[i] = fma(av, x1, D1[i]);
-        D2[i] = fma(av, x2, D2[i]);
+        D0[i] = fma(av[i][e], x0, D0[i]);
+        D1[i] = fma(av[i][e], x1, D1[i]);
+        D2[i] = fma(av[i][e], x2, D2[i]);
       }
-#pragma unroll
-      for (int i = 0; i < RPW; i++) asm volatile("" : "+v"(D0[i]), "+v"(D1[i]), "+v"(D2[i]));
     }
 #pragma unroll
     for (int i = 0; i < RPW; i++) {
-      {
-        double d0 = dpp_sum_f64(D0[i]);
-        double d1 = dpp_sum_f64(D1[i]);
-        double d2 = dpp_sum_f64(D2[i]);
-        if (CS > 1) {
-          // the parts' sums (integers: the total is below 2^53 as well)
-          if (lane == 0) {
-            int64_t* q = sPart + ((slot * RPW + i) * CS + wave % CS) * 3;
-            q[0] = (int64_t)d0;
-            q[1] = (int64_t)d1;
-            q[2] = (int64_t)d2;
-          }
-          __syncthreads();
-          int64_t e0 = 0, e1 = 0, e2 = 0;
-#pragma unroll
-          for (int t = 0; t < CS; t++) {
-            const int64_t* q = sPart + ((slot * RPW + i) * CS + t) * 3;
-            e0 += q[0];
-            e1 += q[1];
-            e2 += q[2];
-          }
-          d0 = (double)e0;
-          d1 = (double)e1;
-          d2 = (double)e2;
-        }
-        if (rows[i] < n && lane == 0 && wave % CS == 0) {
-          // exact divisions by p through p^{-1} mod 2^64
-          int64_t q = (int64_t)((uint64_t)(rr[i] - (int64_t)d0) * pinv64);
-          q = (int64_t)((uint64_t)(q - (int64_t)d1) * pinv64);
-          q = (int64_t)((uint64_t)(q - (int64_t)d2) * pinv64);
-          rr[i] = q;
-          // balanced digits of r' mod p^3, the carry of each centring taken
-          // into the next digit, so that m0 + p m1 + p^2 m2 = r' (mod p^3)
-          const int32_t m0 = centred_i32(smod64(q, p, pinv), p);
-          const int64_t u1 = (int64_t)((uint64_t)(q - (int64_t)m0) * pinv64);
-          const int32_t m1 = centred_i32(smod64(u1, p, pinv), p);
-          const int64_t u2 = (int64_t)((uint64_t)(u1 - (int64_t)m1) * pinv64);
-          const int32_t m2 = centred_i32(smod64(u2, p, pinv), p);
-          uint32_t* o = sOut + (slot * RPW + i) * 4;
-          o[0] = tag1 << 25 | ((uint32_t)m0 & DIG);
-          o[1] = tag1 << 25 | ((uint32_t)m1 & DIG);
-          o[2] = tag1 << 25 | ((uint32_t)m2 & DIG);
-          o[3] = tag1 << 25;
-        }
+      const double d0 = dpp_sum_f64(D0[i]);
+      const double d1 = dpp_sum_f64(D1[i]);
+      const double d2 = dpp_sum_f64(D2[i]);
+      if (rows[i] < n && lane == 0) {
+        // exact divisions by p through p^{-1} mod 2^64
+        int64_t q = (int64_t)((uint64_t)(rr[i] - (int64_t)d0) * pinv64);
+        q = (int64_t)((uint64_t)(q - (int64_t)d1) * pinv64);
+        q = (int64_t)((uint64_t)(q - (int64_t)d2) * pinv64);
+        rr[i] = q;
+        // balanced digits of r' mod p^3, the carry of each centring taken
+        // into the next digit, so that m0 + p m1 + p^2 m2 = r' (mod p^3)
+        const int32_t m0 = centred_i32(smod64(q, p, pinv), p);
+        const int64_t u1 = (int64_t)((uint64_t)(q - (int64_t)m0) * pinv64);
+        const int32_t m1 = centred_i32(smod64(u1, p, pinv), p);
+        const int64_t u2 = (int64_t)((uint64_t)(u1 - (int64_t)m1) * pinv64);
+        const int32_t m2 = centred_i32(smod64(u2, p, pinv), p);
+        uint32_t* o = sOut + (wave * RPW + i) * 4;
+        o[0] = tag1 << 25 | ((uint32_t)m0 & DIG);
+        o[1] = tag1 << 25 | ((uint32_t)m1 & DIG);
+        o[2] = tag1 << 25 | ((uint32_t)m2 & DIG);
+        o[3] = tag1 << 25;
       }
     }
     publish(rv);
@@ -1083,7 +989,7 @@ __global__ __launch_bounds__(64 * NWAVE) void k_lift_resident3(
   }
 #pragma unroll
   for (int i = 0; i < RPW; i++)
-    if (rows[i] < n && lane == 0 && wave % CS == 0) r[rows[i]] = rr[i];
+    if (rows[i] < n && lane == 0) r[rows[i]] = rr[i];
 }
 
 // comb[i] = sum_j c_j x_i[j] for every lifted digit vector x_i (the random
@@ -1135,10 +1041,10 @@ hipError_t launch_lift_resident3(int grid, const uint32_t* C0, const uint32_t* C
                   (void*)&xv, (void*)&n, (void*)&p, (void*)&pinv, (void*)&pinv64, (void*)&kd,
                   (void*)&digits, (void*)&err, (void*)&spin_limit};
   const void* f = nullptr;
-  if (n <= 256) f = (const void*)k_lift_resident3<4, LIFT3_RPW, LIFT3_NWAVE, 1>;
-  else if (n <= 512) f = (const void*)k_lift_resident3<8, LIFT3_RPW, LIFT3_NWAVE, 1>;
-  else if (n <= 1024) f = (const void*)k_lift_resident3<16, LIFT3_RPW, LIFT3_NWAVE, 1>;
-  if (!f || grid != lift3_grid_size(n) || grid > MAX_LIFT3_GROUPS) return hipErrorInvalidValue;
+  if (n <= 256) f = (const void*)k_lift_resident3<4, LIFT3_RPW, LIFT3_NWAVE>;
+  else if (n <= 512) f = (const void*)k_lift_resident3<8, LIFT3_RPW, LIFT3_NWAVE>;
+  else if (n <= 1024) f = (const void*)k_lift_resident3<16, LIFT3_RPW, LIFT3_NWAVE>;
+  if (!f || grid != lift3_grid_size(n)) return hipErrorInvalidValue;
   return hipLaunchCooperativeKernel(f, dim3(grid), dim3(64 * LIFT3_NWAVE), args, 0, st);
 }
 

@@ -70,8 +70,6 @@ hipError_t launch_comb_digits(const uint32_t* digits, int64_t k, int n, const ui
 // of r) under a 7-bit tag, the step number mod 127; tag 127 (an all-ones
 // word) marks a word not yet written.  r of step 0 goes in with tag 0.
 constexpr uint32_t LIFT3_DIGIT_MASK = 0x1FFFFFFu;
-// Most workgroups of one three-plane lifting launch.
-constexpr int MAX_LIFT3_GROUPS = 256;
 hipError_t launch_hensel_f64(const int32_t* Ai, const uint32_t* C0, double* E, uint32_t* C1,
                              uint32_t* C2, int n, uint32_t p, hipStream_t st);
 // rv, xv: n x 4 words, the digit vectors passed between workgroups (r of
