@@ -35,6 +35,14 @@ __device__ __forceinline__ double uniform_d(double x) {
   return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
+// The value of one lane (a wave-uniform index) in every lane.
+__device__ __forceinline__ double readlane_d(double x, int lane) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, x);
+  const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)u, lane);
+  const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(u >> 32), lane);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
 __device__ __forceinline__ int wave_min_int(int v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
@@ -121,7 +129,7 @@ __global__ __launch_bounds__(512) void k_panel(int32_t* __restrict__ W, int64_t 
   {
     constexpr int RS = T / PB;                  // rows per pass of the workgroup
     const int k = t % PB;
-    constexpr int NL = RPT * PB / 2 < 32 ? RPT * PB / 2 : 32;   // loads in flight per thread
+    constexpr int NL = RPT * PB;                // loads in flight per thread: all of them
     static_assert((RPT * PB) % NL == 0, "load batches");
 #pragma unroll 1
     for (int r0 = t / PB; r0 < MROWS; r0 += NL * RS) {
@@ -145,6 +153,46 @@ __global__ __launch_bounds__(512) void k_panel(int32_t* __restrict__ W, int64_t 
   }
 
   for (int g = 0; g < pb; g += GJ) {
+    // Pivot inverses of the group ahead of time.  While rows g..g+7 are the
+    // group's pivots (no zero pivot, so no swap), a fraction-free
+    // elimination of the 8 x 8 diagonal block in lanes g..g+7 of wave 0
+    // gives b_k = sigma_k a_kk with sigma_0 = 1, sigma_{k+1} = sigma_k b_k, so
+    // the eight inverses 1/a_kk = sigma_k / b_k come from one ladder run in
+    // eight lanes at once instead of eight ladders in a row.  gvalid: the
+    // number of leading columns for which this holds (the first b_k = 0 ends
+    // it, and so does a swap); lane g+k keeps 1/a_kk in ginv.
+    int gvalid = 0;
+    double ginv = 0.0;
+    if (wave == 0) {
+      double B[GJ], bk[GJ];
+#pragma unroll
+      for (int c = 0; c < GJ; c++) B[c] = mod_c(a[0][c], p, pinv);
+      gvalid = GJ;
+#pragma unroll
+      for (int k = 0; k < GJ; k++) {
+        const int src = g + k;                        // the pivot row's lane
+        bk[k] = readlane_d(B[k], src);
+        if (bk[k] == 0.0 && gvalid == GJ) gvalid = k;
+        double rk[GJ];
+#pragma unroll
+        for (int c = k + 1; c < GJ; c++) rk[c] = readlane_d(B[c], src);
+        // rows below: b_k B - B[k] row_k (each product below 2^50: exact)
+#pragma unroll
+        for (int c = k + 1; c < GJ; c++) {
+          const double v = mod_c(fma(bk[k], B[c], -B[k] * rk[c]), p, pinv);
+          B[c] = t > src ? v : B[c];
+        }
+      }
+      const int kk = t - g;                           // 0..7 in the block's lanes
+      double bsel = 1.0, sig = 1.0;
+#pragma unroll
+      for (int k = 0; k < GJ; k++) {
+        bsel = kk == k ? bk[k] : bsel;
+        sig = k < kk ? mul_mod(sig, bk[k], p, pinv) : sig;
+      }
+      bsel = bsel == 0.0 ? 1.0 : bsel;                // (columns past gvalid: unused)
+      ginv = mul_mod(sig, pow_mod_fixed(bsel, e_inv, p, pinv), p, pinv);
+    }
 #pragma unroll
     for (int jj = 0; jj < GJ; jj++) {
       const int j = g + jj;
@@ -167,7 +215,7 @@ __global__ __launch_bounds__(512) void k_panel(int32_t* __restrict__ W, int64_t 
 #pragma unroll
             for (int k = 0; k < PB; k++)
               if (k >= jj) s_old[buf][k] = a[0][k];
-            if (wc == j) s_inv[buf] = pow_mod_fixed(a[0][jj], e_inv, p, pinv);
+            if (wc == j) s_inv[buf] = jj < gvalid ? ginv : pow_mod_fixed(a[0][jj], e_inv, p, pinv);
           }
           __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
           __builtin_amdgcn_wave_barrier();
@@ -183,6 +231,7 @@ __global__ __launch_bounds__(512) void k_panel(int32_t* __restrict__ W, int64_t 
         pr = __builtin_amdgcn_readfirstlane(pr);      // the same in every lane
         const bool singular = pr == INT_MAX;          // no pivot: det = 0 mod p, row j kept
         if (singular) pr = j;
+        if (pr != j || singular) gvalid = 0;          // the group's later pivots change
         if (pr != j) {                                // pivot below row j: second round
           if (wave == ((pr % T) >> 6)) {
             const int qp = pr / T;
@@ -250,10 +299,23 @@ __global__ __launch_bounds__(512) void k_panel(int32_t* __restrict__ W, int64_t 
         a[q][k] = (k + GJ < PB) ? mod_loose(a[q][k + GJ], p, pinv) : 0.0;
   }
   __syncthreads();
-  // write back the panel, consecutive threads on consecutive columns
-  for (int e = t; e < m * PB; e += T) {
-    const int r = e / PB, k = e % PB;
-    if (k < pb) Wz[(int64_t)r * ldw + k] = sP[r * SP + k];
+  // Waves 2.. write the panel back (four consecutive columns a thread, 16-byte
+  // stores: j0, ldw and slab are multiples of 4) while waves 0 and 1 compute
+  // the triangular inverses below.
+  if (wave >= 2) {
+    constexpr int PB4 = PB / 4;
+    for (int e = t - 128; e < m * PB4; e += T - 128) {
+      const int r = e / PB4, k = (e % PB4) * 4;
+      int32_t* dst = Wz + (int64_t)r * ldw + k;
+      const int32_t* src = sP + r * SP + k;
+      if (k + 3 < pb) {
+        *(v4i*)dst = v4i{src[0], src[1], src[2], src[3]};
+      } else {
+#pragma unroll
+        for (int u = 0; u < 4; u++)
+          if (k + u < pb) dst[u] = src[u];
+      }
+    }
   }
   if (t < pb) piv[(int64_t)z * piv_stride + j0 + t] = j0 + s_piv[t];
   if (t == 0 && s_sing) flags[z] = 1;
