@@ -13,6 +13,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "kernels.hpp"
 #include "modp.hpp"
 
@@ -559,6 +561,7 @@ hipError_t launch_lift_resident2(int grid, const uint32_t* C0, const uint32_t* C
 // Shape of the three-plane lifting: LIFT3_NWAVE waves of LIFT3_RPW rows per
 // workgroup, one workgroup per LIFT3_RPW * LIFT3_NWAVE rows.
 constexpr int LIFT3_RPW = 1, LIFT3_NWAVE = 8;
+constexpr bool LIFT3_NARROW = false, LIFT3_SV64 = false;
 static int lift3_grid_size(int n) {
   return (n + LIFT3_RPW * LIFT3_NWAVE - 1) / (LIFT3_RPW * LIFT3_NWAVE);
 }
@@ -589,7 +592,8 @@ int lift3_grid(int device, int n) {
 //
 // k_hensel_f64<MODE>: a 64x64 output tile per 256-thread workgroup on FP64
 // MFMA (v_mfma_f64_16x16x4f64; each wave a 32x32 quarter as 2x2 blocks),
-// K in chunks of 16 through LDS.
+// K in chunks of 64 through LDS; the next chunk's global loads are issued
+// before the current chunk's 64 MFMAs a wave, so their latency is hidden.
 //   MODE 0: Eout = (Ein + A c_k) / p   (Ein = -I when Ein == null).  Every
 //           partial sum is below n ||A|| p / 2 < 2^53: exact without reduction;
 //           the quotient is exact, so rint of the scaled sum is it.
@@ -601,7 +605,9 @@ __global__ __launch_bounds__(256) void k_hensel_f64(const void* __restrict__ Lv,
                                                     const void* __restrict__ Rv,
                                                     const double* __restrict__ Ein, int n,
                                                     uint32_t p, double pinv, void* __restrict__ out) {
-  constexpr int BM = 64, BN = 64, BK = 16;
+  constexpr int BM = 64, BN = 64, BK = 64;
+  constexpr int NL = BM * BK / 256, NR = BK * BN / 256;     // values a thread loads per chunk
+  typedef typename std::conditional<MODE == 0, uint32_t, double>::type rv_t;
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
   const int wr = wave >> 1, wc = wave & 1;
@@ -609,49 +615,61 @@ __global__ __launch_bounds__(256) void k_hensel_f64(const void* __restrict__ Lv,
   const double pd = (double)p, h = 0.5 * pd;
   __shared__ double sL[BK][BM + 2];
   __shared__ double sR[BK][BN + 2];
+  // chunk loads, consecutive threads on consecutive addresses: value u of
+  // thread t is element u * 256 + t of the tile in row-major order
+  uint32_t lreg[NL];
+  rv_t rreg[NR];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < NL; u++) {
+      const int f = u * 256 + t, r = f / BK, k = f % BK;
+      const int gr = row0 + r, gk = k0 + k;
+      lreg[u] = (gr < n && gk < n) ? ((const uint32_t*)Lv)[(int64_t)gr * n + gk] : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < NR; u++) {
+      const int f = u * 256 + t, k = f / BN, c = f % BN;
+      const int gk = k0 + k, gc = col0 + c;
+      rreg[u] = (gk < n && gc < n) ? ((const rv_t*)Rv)[(int64_t)gk * n + gc] : (rv_t)0;
+    }
+  };
+  // to LDS as FP64: A as int32; planes centred; E reduced
+  auto lstore = [&]() {
+#pragma unroll
+    for (int u = 0; u < NL; u++) {
+      const int f = u * 256 + t, r = f / BK, k = f % BK;
+      double v;
+      if (MODE == 0) {
+        v = (double)(int32_t)lreg[u];
+      } else {
+        const double w = (double)lreg[u];
+        v = w > h ? w - pd : w;
+      }
+      sL[k][r] = v;
+    }
+#pragma unroll
+    for (int u = 0; u < NR; u++) {
+      const int f = u * 256 + t, k = f / BN, c = f % BN;
+      double v;
+      if (MODE == 0) {
+        const double w = (double)rreg[u];
+        v = w > h ? w - pd : w;
+      } else {
+        v = mod_c((double)rreg[u], pd, pinv);
+      }
+      sR[k][c] = v;
+    }
+  };
   v4d_h acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; i++)
 #pragma unroll
     for (int j = 0; j < 2; j++) acc[i][j] = (v4d_h){0.0, 0.0, 0.0, 0.0};
+  gload(0);
   for (int k0 = 0; k0 < n; k0 += BK) {
-    {   // left tile: 64 rows x 16 k; thread t: row t/4, k (t%4)*4 .. +3
-      const int r = t >> 2, kq = (t & 3) * 4;
-      const int gr = row0 + r;
-#pragma unroll
-      for (int u = 0; u < 4; u++) {
-        const int gk = k0 + kq + u;
-        double v = 0.0;
-        if (gr < n && gk < n) {
-          if (MODE == 0) {
-            v = (double)((const int32_t*)Lv)[(int64_t)gr * n + gk];
-          } else {
-            const double w = (double)((const uint32_t*)Lv)[(int64_t)gr * n + gk];
-            v = w > h ? w - pd : w;
-          }
-        }
-        sL[kq + u][r] = v;
-      }
-    }
-    {   // right tile: 16 k x 64 cols; thread t: k t/16, cols (t%16)*4 .. +3
-      const int kk = t >> 4, cq = (t & 15) * 4;
-      const int gk = k0 + kk;
-#pragma unroll
-      for (int u = 0; u < 4; u++) {
-        const int gc = col0 + cq + u;
-        double v = 0.0;
-        if (gk < n && gc < n) {
-          if (MODE == 0) {
-            const double w = (double)((const uint32_t*)Rv)[(int64_t)gk * n + gc];
-            v = w > h ? w - pd : w;
-          } else {
-            v = mod_c(((const double*)Rv)[(int64_t)gk * n + gc], pd, pinv);
-          }
-        }
-        sR[kk][cq + u] = v;
-      }
-    }
+    lstore();
     __syncthreads();
+    if (k0 + BK < n) gload(k0 + BK);
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 4) {
       const int kr = ks + (lane >> 4);
@@ -665,14 +683,14 @@ __global__ __launch_bounds__(256) void k_hensel_f64(const void* __restrict__ Lv,
 #pragma unroll
         for (int j = 0; j < 2; j++)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
-    }
-    if (MODE == 1) {
+      if (MODE == 1 && (ks & 15) == 12) {
 #pragma unroll
-      for (int i = 0; i < 2; i++)
+        for (int i = 0; i < 2; i++)
 #pragma unroll
-        for (int j = 0; j < 2; j++)
+          for (int j = 0; j < 2; j++)
 #pragma unroll
-          for (int r = 0; r < 4; r++) acc[i][j][r] = mod_loose(acc[i][j][r], pd, pinv);
+            for (int r = 0; r < 4; r++) acc[i][j][r] = mod_loose(acc[i][j][r], pd, pinv);
+      }
     }
     __syncthreads();
   }
@@ -750,7 +768,8 @@ __device__ __forceinline__ int32_t centred_i32(uint32_t u, uint32_t p) {
 
 // All lifting steps modulo p^3 in FP64, three base-p digits per step, with
 // the centred planes c0, c1, c2 of A^{-1} mod p^3 and the rows of A in
-// registers as FP64: wave w of workgroup g (NWAVE waves, RG = RPW NWAVE
+// registers (c0, c1 as FP64; c2 and A as FP64, or as int32 converted at their
+// use when NARROW): wave w of workgroup g (NWAVE waves, RG = RPW NWAVE
 // rows) owns rows g RG + w RPW + i (i < RPW), lane l columns l + 64 e
 // (e < EPL).  Vectors passed between workgroups: the three digits of r mod
 // p^3, balanced (|digit| <= (p-1)/2, r = w0 + p w1 + p^2 w2 mod p^3), and the
@@ -779,7 +798,7 @@ __device__ __forceinline__ int32_t centred_i32(uint32_t u, uint32_t p) {
 // longer to become visible than one contiguous write.  A wait that exceeds
 // spin_limit polls sets *err; after that every wait gives up within 64
 // polls, so all waves exit.
-template <int EPL, int RPW, int NWAVE>
+template <int EPL, int RPW, int NWAVE, bool NARROW, bool SV64>
 __global__ __launch_bounds__(64 * NWAVE) void k_lift_resident3(
     const uint32_t* __restrict__ C0, const uint32_t* __restrict__ C1,
     const uint32_t* __restrict__ C2, const int32_t* __restrict__ Ai, int64_t* __restrict__ r,
@@ -794,10 +813,12 @@ __global__ __launch_bounds__(64 * NWAVE) void k_lift_resident3(
   constexpr int NC = 64 * EPL;                          // columns (at least n)
   constexpr int NJ = (EPL + NWAVE - 1) / NWAVE;         // rows staged per thread
   const int row0 = blockIdx.x * RG;
-  // the vector a phase reads, staged once per workgroup as FP64 (digit t of
-  // row j at [t][j]), one buffer per phase so that a phase may stage while
-  // slower waves still read the other phase's buffer
-  __shared__ double sV[2][3][NC];
+  // the vector a phase reads, staged once per workgroup (digit t of row j at
+  // [t][j], FP64 or int32: every wave reads all of it, so its width sets the
+  // LDS traffic), one buffer per phase so that a phase may stage while slower
+  // waves still read the other phase's buffer
+  typedef typename std::conditional<SV64, double, int32_t>::type sv_t;
+  __shared__ sv_t sV[2][3][NC];
   // the workgroup's rows of the vector a phase writes, gathered for one store
   __shared__ uint32_t sOut[RG * 4];
   // 16-byte loads at the device-coherent level: buffer loads with the sc1
@@ -808,7 +829,7 @@ __global__ __launch_bounds__(64 * NWAVE) void k_lift_resident3(
   // Staging of one vector: every thread reads its NJ rows and polls again
   // those whose tag is still old; after spin_limit polls it sets *err (or
   // gives up on finding it set).
-  auto stage3 = [&](double (*s)[NC], __amdgpu_buffer_rsrc_t src, uint32_t tag, bool sgn) {
+  auto stage3 = [&](sv_t (*s)[NC], __amdgpu_buffer_rsrc_t src, uint32_t tag, bool sgn) {
     u32x4 a[NJ];
     bool want[NJ];
 #pragma unroll
@@ -851,9 +872,9 @@ __global__ __launch_bounds__(64 * NWAVE) void k_lift_resident3(
       const int j = threadIdx.x + 64 * NWAVE * q;
       if (j < NC) {
         // r digits: sign-extend the 25-bit field; x digits: the field itself
-        s[0][j] = sgn ? (double)((int32_t)(a[q].x << 7) >> 7) : (double)(a[q].x & DIG);
-        s[1][j] = sgn ? (double)((int32_t)(a[q].y << 7) >> 7) : (double)(a[q].y & DIG);
-        s[2][j] = sgn ? (double)((int32_t)(a[q].z << 7) >> 7) : (double)(a[q].z & DIG);
+        s[0][j] = (sv_t)(sgn ? (int32_t)(a[q].x << 7) >> 7 : (int32_t)(a[q].x & DIG));
+        s[1][j] = (sv_t)(sgn ? (int32_t)(a[q].y << 7) >> 7 : (int32_t)(a[q].y & DIG));
+        s[2][j] = (sv_t)(sgn ? (int32_t)(a[q].z << 7) >> 7 : (int32_t)(a[q].z & DIG));
       }
     }
     __syncthreads();
@@ -864,8 +885,10 @@ __global__ __launch_bounds__(64 * NWAVE) void k_lift_resident3(
     if (threadIdx.x < 4 * RG && row0 + (int)threadIdx.x / 4 < n)
       st_dev(v + (size_t)row0 * 4 + threadIdx.x, sOut[threadIdx.x]);
   };
-  // centred planes and the rows of A, FP64 in registers
-  double c0[RPW][EPL], c1[RPW][EPL], c2[RPW][EPL], av[RPW][EPL];
+  // centred planes and the rows of A in registers
+  typedef typename std::conditional<NARROW, int32_t, double>::type nv_t;
+  double c0[RPW][EPL], c1[RPW][EPL];
+  nv_t c2[RPW][EPL], av[RPW][EPL];
   int64_t rr[RPW];
   int rows[RPW];
 #pragma unroll
@@ -880,8 +903,8 @@ __global__ __launch_bounds__(64 * NWAVE) void k_lift_resident3(
       const int64_t o = (int64_t)row * n + j;
       c0[i][e] = in ? (double)centred_i32(C0[o], p) : 0.0;
       c1[i][e] = in ? (double)centred_i32(C1[o], p) : 0.0;
-      c2[i][e] = in ? (double)centred_i32(C2[o], p) : 0.0;
-      av[i][e] = in ? (double)Ai[o] : 0.0;
+      c2[i][e] = (nv_t)(in ? centred_i32(C2[o], p) : 0);
+      av[i][e] = (nv_t)(in ? Ai[o] : 0);
     }
     if (row < n && lane == 0) rr[i] = r[row];
   }
@@ -889,6 +912,9 @@ __global__ __launch_bounds__(64 * NWAVE) void k_lift_resident3(
   uint32_t tag = 0;                                // step mod 127
   for (int64_t step = 0; step < steps; step++) {
     const uint32_t tag1 = tag == 126 ? 0 : tag + 1;
+    // z: always 0, unknown to the compiler, keeps FP64 copies of the int32
+    // registers from being hoisted out of the step loop
+    const int z = (int)(step >> 62);
     // ---- phase X
     double S0[RPW], S1a[RPW], S1b[RPW], S2a[RPW], S2b[RPW], S2c[RPW];
 #pragma unroll
@@ -896,17 +922,18 @@ __global__ __launch_bounds__(64 * NWAVE) void k_lift_resident3(
     stage3(sV[0], rsr, tag, true);
 #pragma unroll
     for (int e = 0; e < EPL; e++) {
-      const double w0 = sV[0][0][lane + 64 * e];    // balanced digits
-      const double w1 = sV[0][1][lane + 64 * e];
-      const double w2 = sV[0][2][lane + 64 * e];
+      const double w0 = (double)sV[0][0][lane + 64 * e];    // balanced digits
+      const double w1 = (double)sV[0][1][lane + 64 * e];
+      const double w2 = (double)sV[0][2][lane + 64 * e];
 #pragma unroll
       for (int i = 0; i < RPW; i++) {
+        const double x2 = NARROW ? (double)((int32_t)c2[i][e] ^ z) : (double)c2[i][e];
         S0[i] = fma(c0[i][e], w0, S0[i]);
         S1a[i] = fma(c0[i][e], w1, S1a[i]);
         S1b[i] = fma(c1[i][e], w0, S1b[i]);
         S2a[i] = fma(c0[i][e], w2, S2a[i]);
         S2b[i] = fma(c1[i][e], w1, S2b[i]);
-        S2c[i] = fma(c2[i][e], w0, S2c[i]);
+        S2c[i] = fma(x2, w0, S2c[i]);
       }
     }
     // (absent rows, whose planes are 0, run through as well)
@@ -949,14 +976,15 @@ __global__ __launch_bounds__(64 * NWAVE) void k_lift_resident3(
     stage3(sV[1], rsx, tag, false);
 #pragma unroll
     for (int e = 0; e < EPL; e++) {
-      const double x0 = sV[1][0][lane + 64 * e];
-      const double x1 = sV[1][1][lane + 64 * e];
-      const double x2 = sV[1][2][lane + 64 * e];
+      const double x0 = (double)sV[1][0][lane + 64 * e];
+      const double x1 = (double)sV[1][1][lane + 64 * e];
+      const double x2 = (double)sV[1][2][lane + 64 * e];
 #pragma unroll
       for (int i = 0; i < RPW; i++) {
-        D0[i] = fma(av[i][e], x0, D0[i]);
-        D1[i] = fma(av[i][e], x1, D1[i]);
-        D2[i] = fma(av[i][e], x2, D2[i]);
+        const double ae = NARROW ? (double)((int32_t)av[i][e] ^ z) : (double)av[i][e];
+        D0[i] = fma(ae, x0, D0[i]);
+        D1[i] = fma(ae, x1, D1[i]);
+        D2[i] = fma(ae, x2, D2[i]);
       }
     }
 #pragma unroll
@@ -1041,9 +1069,9 @@ hipError_t launch_lift_resident3(int grid, const uint32_t* C0, const uint32_t* C
                   (void*)&xv, (void*)&n, (void*)&p, (void*)&pinv, (void*)&pinv64, (void*)&kd,
                   (void*)&digits, (void*)&err, (void*)&spin_limit};
   const void* f = nullptr;
-  if (n <= 256) f = (const void*)k_lift_resident3<4, LIFT3_RPW, LIFT3_NWAVE>;
-  else if (n <= 512) f = (const void*)k_lift_resident3<8, LIFT3_RPW, LIFT3_NWAVE>;
-  else if (n <= 1024) f = (const void*)k_lift_resident3<16, LIFT3_RPW, LIFT3_NWAVE>;
+  if (n <= 256) f = (const void*)k_lift_resident3<4, LIFT3_RPW, LIFT3_NWAVE, LIFT3_NARROW, LIFT3_SV64>;
+  else if (n <= 512) f = (const void*)k_lift_resident3<8, LIFT3_RPW, LIFT3_NWAVE, LIFT3_NARROW, LIFT3_SV64>;
+  else if (n <= 1024) f = (const void*)k_lift_resident3<16, LIFT3_RPW, LIFT3_NWAVE, LIFT3_NARROW, LIFT3_SV64>;
   if (!f || grid != lift3_grid_size(n)) return hipErrorInvalidValue;
   return hipLaunchCooperativeKernel(f, dim3(grid), dim3(64 * LIFT3_NWAVE), args, 0, st);
 }

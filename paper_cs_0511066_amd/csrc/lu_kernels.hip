@@ -120,6 +120,11 @@ __global__ __launch_bounds__(512) void k_panel(int32_t* __restrict__ W, int64_t 
   __shared__ double s_dinv[PB];
   __shared__ int s_piv[PB];
   __shared__ int s_sing;
+  __shared__ double sBlk[8][PB];              // a group's pivot rows, on their way to lane-per-column
+  __shared__ double sU[2][8][PB];             // U rows of a group (window columns), per group parity
+  __shared__ double s_gi[2][8];               // pivot inverses of a group
+  __shared__ double sRik[8][8];               // a group's pivot-column entries (fraction-free)
+  __shared__ int s_gfast[2];
 
   // coalesced load of the panel into LDS (all loads in flight at once), then
   // each thread takes its rows
@@ -153,46 +158,142 @@ __global__ __launch_bounds__(512) void k_panel(int32_t* __restrict__ W, int64_t 
   }
 
   for (int g = 0; g < pb; g += GJ) {
-    // Pivot inverses of the group ahead of time.  While rows g..g+7 are the
-    // group's pivots (no zero pivot, so no swap), a fraction-free
-    // elimination of the 8 x 8 diagonal block in lanes g..g+7 of wave 0
-    // gives b_k = sigma_k a_kk with sigma_0 = 1, sigma_{k+1} = sigma_k b_k, so
-    // the eight inverses 1/a_kk = sigma_k / b_k come from one ladder run in
-    // eight lanes at once instead of eight ladders in a row.  gvalid: the
-    // number of leading columns for which this holds (the first b_k = 0 ends
-    // it, and so does a swap); lane g+k keeps 1/a_kk in ginv.
+    const int gb = (g / GJ) & 1;
+    // ---- The group's pivot rows g..g+7, in wave 0.  Their window entries go
+    // through LDS to a lane-per-column layout (lane c: window column c of the
+    // eight rows), so that an elimination step needs only the pivot column's
+    // entries from other lanes.  A fraction-free elimination of the eight
+    // rows (row i <- b_k row_i - r_ik row_k for i > k, b_k and r_ik the pivot
+    // column's entries of rows k and i) leaves every row scaled by
+    // sigma_k = b_0 ... b_{k-1} at its pivot step, so with one ladder for the
+    // eight inverses 1/b_k:
+    //   U row k = (row k after step k-1) / sigma_k,  l_ik = r_ik / b_k,
+    //   1/a_kk = sigma_k / b_k.
+    // This holds while rows g..g+7 are the group's pivots, that is while no
+    // b_k is 0 mod p (no swap); gvalid = the number of leading columns for
+    // which it holds.  When all eight hold (the fast path) the U rows and the
+    // multipliers are stored here, and every other row then takes its eight
+    // multipliers and the rank-8 update of its window on its own, after a
+    // single barrier.  Values stay |v| <= h + 5 < p through the steps (loose
+    // reductions), so v == 0 exactly when p divides v, and products stay
+    // below 2^51.
     int gvalid = 0;
-    double ginv = 0.0;
     if (wave == 0) {
-      double B[GJ], bk[GJ];
+      if (t >= g && t < g + GJ) {
 #pragma unroll
-      for (int c = 0; c < GJ; c++) B[c] = mod_c(a[0][c], p, pinv);
-      gvalid = GJ;
+        for (int c = 0; c < PB; c++) sBlk[t - g][c] = a[0][c];
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      const int cl = lane < PB ? lane : PB - 1;
+      double F[GJ], bk[GJ];
+#pragma unroll
+      for (int i = 0; i < GJ; i++) F[i] = sBlk[i][cl];
+      int gv = GJ;
 #pragma unroll
       for (int k = 0; k < GJ; k++) {
-        const int src = g + k;                        // the pivot row's lane
-        bk[k] = readlane_d(B[k], src);
-        if (bk[k] == 0.0 && gvalid == GJ) gvalid = k;
-        double rk[GJ];
+        bk[k] = readlane_d(F[k], k);
+        if (bk[k] == 0.0 && gv == GJ) gv = k;
+        // the pivot column's entries r_ik (lane k) are kept for the multipliers
+        if (lane == k) {
 #pragma unroll
-        for (int c = k + 1; c < GJ; c++) rk[c] = readlane_d(B[c], src);
-        // rows below: b_k B - B[k] row_k (each product below 2^50: exact)
+          for (int i = k + 1; i < GJ; i++) sRik[i][k] = F[i];
+        }
 #pragma unroll
-        for (int c = k + 1; c < GJ; c++) {
-          const double v = mod_c(fma(bk[k], B[c], -B[k] * rk[c]), p, pinv);
-          B[c] = t > src ? v : B[c];
+        for (int i = k + 1; i < GJ; i++) {
+          const double r = readlane_d(F[i], k);
+          F[i] = mod_loose(fma(bk[k], F[i], -r * F[k]), p, pinv);
         }
       }
-      const int kk = t - g;                           // 0..7 in the block's lanes
-      double bsel = 1.0, sig = 1.0;
+      // 1/b_k in lane k (one ladder for all eight); sigma_k and 1/sigma_k
+      double bsel = 1.0;
+#pragma unroll
+      for (int k = 0; k < GJ; k++) bsel = lane == k ? bk[k] : bsel;
+      bsel = bsel == 0.0 ? 1.0 : bsel;                // (columns past gvalid: unused)
+      const double ib = pow_mod_fixed(bsel, e_inv, p, pinv);
+      double ibk[GJ], sg[GJ], isg[GJ];
+#pragma unroll
+      for (int k = 0; k < GJ; k++) ibk[k] = readlane_d(ib, k);
+      sg[0] = isg[0] = 1.0;
+#pragma unroll
+      for (int k = 1; k < GJ; k++) {
+        sg[k] = mul_mod_loose(sg[k - 1], bk[k - 1], p, pinv);
+        isg[k] = mul_mod_loose(isg[k - 1], ibk[k - 1], p, pinv);
+      }
+      double gi = 0.0;                                // lane k: 1/a_kk
+#pragma unroll
+      for (int k = 0; k < GJ; k++) gi = lane == k ? mul_mod(sg[k], ibk[k], p, pinv) : gi;
+      if (lane < GJ) s_gi[gb][lane] = gi;
+      gvalid = gv;
+      const bool fastg = gv == GJ && g + GJ <= pb;
+      if (fastg) {
+#pragma unroll
+        for (int k = 0; k < GJ; k++) {
+          const double u = mul_mod(F[k], isg[k], p, pinv);             // U row g+k (lanes >= k)
+          if (lane < PB) sU[gb][k][lane] = u;
+          if (lane >= k && lane < PB && g + lane < pb) sP[(g + k) * SP + g + lane] = (int32_t)u;
+        }
+        // multipliers of the block: lane i*8+k stores l_ik = r_ik / b_k (i > k)
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        {
+          const int i = lane / GJ, k = lane % GJ;
+          const double ibl = __shfl(ib, k);
+          if (i > k) sP[(g + i) * SP + g + k] = (int32_t)mul_mod(sRik[i][k], ibl, p, pinv);
+        }
+        if (lane < GJ) {
+          s_piv[g + lane] = g + lane;
+          s_dinv[g + lane] = gi;
+        }
+      }
+      if (lane == 0) s_gfast[gb] = fastg ? 1 : 0;
+    }
+    __syncthreads();
+    if (s_gfast[gb]) {
+      // every row: multipliers l_k = (a_k - sum_{m<k} l_m U_mk) / U_kk, then
+      // a_c -= sum_k l_k U_kc for the window columns past the group (eight
+      // pending products, below 2^51, reduced at the window shift); rows at
+      // or above g+7 and absent rows run through and store nothing
+      double inv[GJ];
+#pragma unroll
+      for (int k = 0; k < GJ; k++) inv[k] = s_gi[gb][k];
+      double l[RPT][GJ];
 #pragma unroll
       for (int k = 0; k < GJ; k++) {
-        bsel = kk == k ? bk[k] : bsel;
-        sig = k < kk ? mul_mod(sig, bk[k], p, pinv) : sig;
+#pragma unroll
+        for (int q = 0; q < RPT; q++) {
+          double v = a[q][k];
+#pragma unroll
+          for (int mm = 0; mm < k; mm++) v = fma(-l[q][mm], sU[gb][mm][k], v);
+          l[q][k] = mul_mod_loose(mod_loose(v, p, pinv), inv[k], p, pinv);   // |l| <= h + 5
+        }
       }
-      bsel = bsel == 0.0 ? 1.0 : bsel;                // (columns past gvalid: unused)
-      ginv = mul_mod(sig, pow_mod_fixed(bsel, e_inv, p, pinv), p, pinv);
-    }
+      // canonical multipliers for the store and the update (eight products
+      // of |l| <= h stay below 2^53 for p < 2^26)
+#pragma unroll
+      for (int k = 0; k < GJ; k++)
+#pragma unroll
+        for (int q = 0; q < RPT; q++) l[q][k] = mod_c(l[q][k], p, pinv);
+#pragma unroll
+      for (int q = 0; q < RPT; q++) {
+        const int row = t + q * T;
+        if (row >= g + GJ && row < m) {
+#pragma unroll
+          for (int k = 0; k < GJ; k++) sP[row * SP + g + k] = (int32_t)l[q][k];
+        }
+      }
+#pragma unroll
+      for (int c = GJ; c < PB; c++) {
+#pragma unroll
+        for (int k = 0; k < GJ; k++) {
+          const double u = sU[gb][k][c];
+#pragma unroll
+          for (int q = 0; q < RPT; q++) a[q][c] = fma(-l[q][k], u, a[q][c]);
+        }
+      }
+    } else {
 #pragma unroll
     for (int jj = 0; jj < GJ; jj++) {
       const int j = g + jj;
@@ -215,7 +316,7 @@ __global__ __launch_bounds__(512) void k_panel(int32_t* __restrict__ W, int64_t 
 #pragma unroll
             for (int k = 0; k < PB; k++)
               if (k >= jj) s_old[buf][k] = a[0][k];
-            if (wc == j) s_inv[buf] = jj < gvalid ? ginv : pow_mod_fixed(a[0][jj], e_inv, p, pinv);
+            if (wc == j) s_inv[buf] = jj < gvalid ? s_gi[gb][jj] : pow_mod_fixed(a[0][jj], e_inv, p, pinv);
           }
           __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
           __builtin_amdgcn_wave_barrier();
@@ -290,6 +391,7 @@ __global__ __launch_bounds__(512) void k_panel(int32_t* __restrict__ W, int64_t 
           if (singular) s_sing = 1;
         }
       }
+    }
     }
     // next window: columns g+8 .. g+8+PB-1, reduced (at most 8 updates pending)
 #pragma unroll

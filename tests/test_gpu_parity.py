@@ -81,6 +81,35 @@ def test_det_mod_primes_edge_cases(ctx):
         assert ctx.det_mod_primes(B, ps, path).tolist() == [dB % q for q in ps]
 
 
+def _vanishing_minors(n, sizes, seed):
+    """A nonsingular matrix whose leading k x k minors vanish for k in `sizes`
+    (row k-1 restricted to the first k columns is the sum of rows 0 and 1),
+    so elimination meets a zero pivot in the middle of a column group."""
+    A = synth.dense_uniform(n, -30, 30, seed)
+    for k in sizes:
+        A[k - 1, :k] = A[0, :k] + A[1, :k]
+    return A
+
+
+@pytest.mark.gpu
+def test_det_mod_primes_zero_pivots_mid_group(ctx):
+    ps23 = test_primes(1 << 22, 1 << 23, 3, 9)
+    ps25 = test_primes(1 << 24, 1 << 25, 2, 9)
+    for n, sizes, seed in ((100, (4, 12, 29, 41), 11), (300, (7, 36, 70, 131, 260), 12)):
+        A = _vanishing_minors(n, sizes, seed)
+        d = oracle.det_bareiss(A) if n <= 200 else oracle.det_bareiss_c(A)
+        assert d != 0
+        assert ctx.det_mod_primes(A, ps23, "int8").tolist() == [d % q for q in ps23]
+        ps = ps23 + ps25
+        assert ctx.det_mod_primes(A, ps, "fp64").tolist() == [d % q for q in ps]
+
+
+@pytest.mark.gpu
+def test_det_introspective_zero_pivots_mid_group(ctx):
+    A = _vanishing_minors(100, (4, 12, 29, 41), 13)
+    assert ctx.det_introspective(A) == oracle.det_bareiss(A)
+
+
 def test_det_mod_primes_extreme_entries(ctx):
     n = 40
     A = synth.dense_uniform(n, -(2 ** 31) + 1, 2 ** 31 - 1, 6)
