@@ -184,6 +184,81 @@ class BigInt {
     sign = mag.empty() ? 0 : 1;
     trim();
   }
+  // this = this * m + c for this >= 0, m < 2^63 and c < 2^127 (two base-p
+  // digits a pass in a radix conversion); every partial sum is below 2^128.
+  void mul_add_u128(uint64_t m, u128 c) {
+    u128 carry = c;
+    for (size_t i = 0; i < mag.size(); i++) {
+      const u128 t = (u128)mag[i] * m + carry;
+      mag[i] = (uint64_t)t;
+      carry = t >> 64;
+    }
+    while (carry) {
+      mag.push_back((uint64_t)carry);
+      carry >>= 64;
+    }
+    sign = mag.empty() ? 0 : 1;
+    trim();
+  }
+  // Sign-magnitude linear combination in place:
+  //   (x, y) <- (A x + B y, C x + D y)
+  // for 64-bit signed cofactors (|A|, |B|, |C|, |D| < 2^63), one pass over the
+  // words per result with 128-bit accumulation: terms of equal sign add as
+  // magnitudes (below 2^128 with the carry), terms of opposite sign subtract
+  // (below 2^127 in magnitude); a negative result is negated at the end.
+  static void lincomb2(BigInt& x, BigInt& y, int64_t A, int64_t B, int64_t C, int64_t D) {
+    BigInt nx = combine(x, A, y, B), ny = combine(x, C, y, D);
+    x.mag.swap(nx.mag);
+    x.sign = nx.sign;
+    y.mag.swap(ny.mag);
+    y.sign = ny.sign;
+  }
+  static BigInt combine(const BigInt& x, int64_t a, const BigInt& y, int64_t b) {
+    const int sa = x.sign * (a < 0 ? -1 : a > 0 ? 1 : 0);
+    const int sb = y.sign * (b < 0 ? -1 : b > 0 ? 1 : 0);
+    const uint64_t ma = a < 0 ? (uint64_t)0 - (uint64_t)a : (uint64_t)a;
+    const uint64_t mb = b < 0 ? (uint64_t)0 - (uint64_t)b : (uint64_t)b;
+    BigInt r;
+    if (sa == 0 && sb == 0) return r;
+    const size_t n = std::max(x.mag.size(), y.mag.size());
+    r.mag.assign(n + 2, 0);
+    if (sa == 0 || sb == 0 || sa == sb) {
+      const uint64_t mx = sa ? ma : 0, my = sb ? mb : 0;
+      u128 carry = 0;
+      for (size_t i = 0; i < n; i++) {
+        const u128 t = (u128)(i < x.mag.size() ? x.mag[i] : 0) * mx +
+                       (u128)(i < y.mag.size() ? y.mag[i] : 0) * my + carry;
+        r.mag[i] = (uint64_t)t;
+        carry = t >> 64;
+      }
+      r.mag[n] = (uint64_t)carry;
+      r.mag[n + 1] = (uint64_t)(carry >> 64);
+      r.sign = sa ? sa : sb;
+    } else {
+      // |a| |x| - |b| |y| in two's complement, then the sign of sa applied
+      __int128 carry = 0;
+      for (size_t i = 0; i < n; i++) {
+        const __int128 t = (__int128)((u128)(i < x.mag.size() ? x.mag[i] : 0) * ma) -
+                           (__int128)((u128)(i < y.mag.size() ? y.mag[i] : 0) * mb) + carry;
+        r.mag[i] = (uint64_t)t;
+        carry = t >> 64;                            // arithmetic shift
+      }
+      r.mag[n] = (uint64_t)carry;
+      const bool neg = carry < 0;
+      r.mag[n + 1] = neg ? ~(uint64_t)0 : 0;
+      if (neg) {                                    // magnitude of a negative value
+        uint64_t c = 1;
+        for (size_t i = 0; i < n + 2; i++) {
+          const u128 t = (u128)(~r.mag[i]) + c;
+          r.mag[i] = (uint64_t)t;
+          c = (uint64_t)(t >> 64);
+        }
+      }
+      r.sign = neg ? -sa : sa;
+    }
+    r.trim();
+    return r;
+  }
   // |this| mod m (m > 0), result in [0, m)
   uint64_t mod_small_mag(uint64_t m) const {
     u128 r = 0;

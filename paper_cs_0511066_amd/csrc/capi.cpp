@@ -1113,10 +1113,9 @@ det_status det_introspective(det_ctx* c, const int64_t* A, int64_t n, int64_t ld
         HIPCHK(hipStreamSynchronize(c->st));
         rep.lifting_steps += k;
         const double th0 = now_ms();
-        // y mod p^k from the per-step combinations (Horner, high digit first)
-        BigInt y, pk = BigInt::from_i64(1);
-        for (int64_t i = k - 1; i >= 0; i--) y.mul_add_small(p, comb[i]);
-        for (int64_t i = 0; i < k; i++) pk.mul_add_small(p, 0);
+        // y = sum_i comb[i] p^i (y mod p^k is c.x mod p^k) and p^k
+        BigInt y, pk;
+        dethost::radix_value(comb, k, p, y, pk);
         BigInt a, d;
         if (dethost::rational_reconstruct(y, pk, BigInt::from_i64(1).shl(Nbits),
                                           BigInt::from_i64(1).shl(Dbits), a, d, p)) {

@@ -185,14 +185,51 @@ inline uint64_t top_bits(const BigInt& v, int64_t s) {
   return x & ((1ull << 63) - 1);
 }
 
+// Bits [s, s + 126) of |v|.
+inline u128 top_bits126(const BigInt& v, int64_t s) {
+  const u128 lo = top_bits(v, s), hi = top_bits(v, s + 63);
+  return lo | (hi << 63);
+}
+
+// Quotient floor(a / b) for 0 <= a, 0 < b (128-bit), by subtraction when it
+// is small (most quotients of the Euclidean algorithm are 1, 2 or 3).
+inline __int128 small_quot(__int128 a, __int128 b) {
+  if (a < b) return 0;
+  if (a < 2 * b) return 1;
+  if (a < 3 * b) return 2;
+  if (a < 4 * b) return 3;
+  return a / b;
+}
+
+// The integer sum_i c[i] p^i (c[i] < 2^64, p < 2^25) and p^k, for the
+// rational reconstruction of a p-adic expansion: Horner's rule two digits a
+// pass (multiplier p^2, a 128-bit addend), p^k by squaring.
+inline void radix_value(const uint64_t* c, int64_t k, uint64_t p, BigInt& y, BigInt& pk) {
+  y = BigInt();
+  int64_t i = k - 1;
+  if (k & 1) {
+    y = BigInt::from_u64(c[k - 1]);
+    i = k - 2;
+  }
+  const uint64_t p2 = p * p;
+  for (; i >= 1; i -= 2) y.mul_add_u128(p2, (u128)c[i] * p + c[i - 1]);
+  pk = BigInt::from_i64(1);
+  BigInt b = BigInt::from_u64(p);
+  for (int64_t e = k; e > 0; e >>= 1) {
+    if (e & 1) pk = pk * b;
+    if (e > 1) b = b * b;
+  }
+}
+
 // Find a/d with a = u d (mod m), |a| <= N, 0 < d <= D, gcd(a, d) = 1, unique
 // when 2 N D < m: the extended Euclidean algorithm on (m, u mod m), stopped
 // at the first remainder <= N.  The remainder sequence is advanced with
-// Lehmer's method (Knuth, TAOCP 4.5.2, Algorithm L: the quotients of the
-// leading 63 bits, accepted while both bracketing quotients agree, give a
-// 2x2 cofactor matrix applied to the full numbers) while the remainder is
-// more than 66 bits above N, so no batch can step past the stopping point;
-// the last steps are plain divisions.  When m is a power of the prime
+// Lehmer's method (Knuth, TAOCP 4.5.2, Algorithm L, on two words: the
+// quotients of the leading 126 bits, accepted while both bracketing quotients
+// agree and the cofactors stay below 2^62, give a 2x2 cofactor matrix applied
+// to the full numbers in one pass) while the remainder is more than 130 bits
+// above N, so no batch can step past the stopping point; the last steps are
+// plain divisions.  When m is a power of the prime
 // `pbase` (pbase != 0), any common factor of the result lies in m, so
 // gcd(a, d) = 1 reduces to pbase not dividing d.
 inline bool rational_reconstruct(const BigInt& u_in, const BigInt& m, const BigInt& N,
@@ -203,23 +240,26 @@ inline bool rational_reconstruct(const BigInt& u_in, const BigInt& m, const BigI
   BigInt r0 = m, r1 = u, t0, t1 = BigInt::from_i64(1);
   const int64_t nbits = N.bit_length();
   while (r1.cmp(N) > 0) {
-    if (r1.bit_length() > nbits + 66) {
-      const int64_t s = std::max<int64_t>(0, r0.bit_length() - 63);
-      __int128 x = (__int128)top_bits(r0, s), y = (__int128)top_bits(r1, s);
+    if (r1.bit_length() > nbits + 130) {
+      // Lehmer (double-word): the quotients of the leading 126 bits, as long
+      // as both bracketing quotients agree and the cofactors stay below
+      // 2^62, taken as one 2 x 2 cofactor matrix
+      const int64_t s = std::max<int64_t>(0, r0.bit_length() - 126);
+      __int128 x = (__int128)top_bits126(r0, s), y = (__int128)top_bits126(r1, s);
       __int128 A = 1, B = 0, C = 0, Dd = 1;
-      while (y + C != 0 && y + Dd != 0) {
-        const __int128 qa = (x + A) / (y + C), qb = (x + B) / (y + Dd);
+      const __int128 lim = (__int128)1 << 62;
+      while (y + C > 0 && y + Dd > 0 && x + A >= 0 && x + B >= 0) {
+        const __int128 qa = small_quot(x + A, y + C), qb = small_quot(x + B, y + Dd);
         if (qa != qb) break;
-        __int128 T = A - qa * C; A = C; C = T;
-        T = B - qa * Dd; B = Dd; Dd = T;
-        T = x - qa * y; x = y; y = T;
+        const __int128 nC = A - qa * C, nD = B - qa * Dd;
+        if (nC >= lim || nC <= -lim || nD >= lim || nD <= -lim) break;
+        A = C; C = nC;
+        B = Dd; Dd = nD;
+        const __int128 T = x - qa * y; x = y; y = T;
       }
       if (B != 0) {
-        const BigInt a1 = BigInt::from_i64((int64_t)A), b1 = BigInt::from_i64((int64_t)B);
-        const BigInt c1 = BigInt::from_i64((int64_t)C), d1 = BigInt::from_i64((int64_t)Dd);
-        BigInt nr0 = a1 * r0 + b1 * r1, nr1 = c1 * r0 + d1 * r1;
-        BigInt nt0 = a1 * t0 + b1 * t1, nt1 = c1 * t0 + d1 * t1;
-        r0 = nr0; r1 = nr1; t0 = nt0; t1 = nt1;
+        BigInt::lincomb2(r0, r1, (int64_t)A, (int64_t)B, (int64_t)C, (int64_t)Dd);
+        BigInt::lincomb2(t0, t1, (int64_t)A, (int64_t)B, (int64_t)C, (int64_t)Dd);
         continue;
       }
     }
