@@ -57,7 +57,7 @@ struct PinBuf {
 };
 
 struct LuWs {
-  DevBuf W, piv, flags, mods, linv, uinv, tinv, limbA, limbB, res;
+  DevBuf W, piv, flags, mods, linv, uinv, tinv, limbA, limbB, res, modsr;
   PinBuf hmods;                 // pinned host copy of the moduli (async uploads)
   hipStream_t st = nullptr;
 };
@@ -379,6 +379,56 @@ det_status back_substitute(det_ctx* c, LuWs& w, const LuJob& J, const std::vecto
   return DET_OK;
 }
 
+// A^{-1} = U^{-1} (L^{-1} P) from the factored [A | I] when every panel is 32
+// wide, in a few launches: V = U^{-1} by recursive doubling over the diagonal
+// blocks (for a pair of blocks of size b, V12 = -V1 U12 V2, batched over the
+// pairs of a level: the pairs lie a fixed stride 2b (ldw + 1) apart), then
+// one product V (L^{-1} P).  Regions of W (ldw >= 4n): [0, n) L\U,
+// [n, 2n) L^{-1} P, [2n, 3n) V, [3n, 4n) scratch, then the inverse.
+// w.hmods must hold (n + 63) / 64 copies of the modulus.
+det_status inverse_from_lu(det_ctx* c, LuWs& w, const LuJob& J, int64_t* col_out) {
+  const int n = J.n;
+  const int64_t ldw = J.ldw;
+  const int kc4 = std::max(1, exact_chunk(J.pmax) / 4);
+  const int64_t offV = 2 * (int64_t)n, offS = 3 * (int64_t)n;
+  int32_t* W = (int32_t*)w.W.p;
+  const int nrep = (n + 63) / 64;
+  TRY(ensure(c, w.modsr, (size_t)nrep * sizeof(Modulus), w.st));
+  HIPCHK(hipMemcpyAsync(w.modsr.p, w.hmods.p, (size_t)nrep * sizeof(Modulus),
+                        hipMemcpyHostToDevice, w.st));
+  const Modulus* mr = (const Modulus*)w.modsr.p;
+  HIPCHK(hipMemset2DAsync(W + offV, ldw * sizeof(int32_t), 0, (size_t)n * sizeof(int32_t), n,
+                          w.st));
+  HIPCHK(detk::launch_place_diag(W, ldw, offV, n, (const int32_t*)w.uinv.p, w.st));
+  for (int64_t b = 32; b < n; b *= 2) {
+    const int64_t npairs = ((n + b - 1) / b) / 2;
+    int64_t nfull = 0;
+    while (nfull < npairs && (2 * nfull + 2) * b <= n) nfull++;
+    // pairs i0 .. i0+cnt-1, right blocks of size r
+    auto level = [&](int64_t i0, int64_t cnt, int64_t r) -> det_status {
+      const int64_t rowL = 2 * i0 * b, rowR = rowL + b, stride = 2 * b * (ldw + 1);
+      ProfScope ps(c, DET_KERNEL_GEMM_F64, 12.0 * b * (b + 2.0 * r) * cnt,
+                   2.0 * b * r * (r + b) * cnt, w.st);
+      HIPCHK(detk::launch_gemm_mod(W, stride, rowL * ldw + offS + rowR, rowL * ldw + rowR,
+                                   rowR * ldw + offV + rowR, ldw, (int)b, (int)r, (int)r, mr, kc4,
+                                   2, false, (int)cnt, w.st));           // S = U12 V2
+      HIPCHK(detk::launch_gemm_mod(W, stride, rowL * ldw + offV + rowR, rowL * ldw + offV + rowL,
+                                   rowL * ldw + offS + rowR, ldw, (int)b, (int)r, (int)b, mr, kc4,
+                                   3, true, (int)cnt, w.st));            // V12 = -V1 S
+      return DET_OK;
+    };
+    if (nfull > 0) TRY(level(0, nfull, b));
+    if (npairs > nfull) TRY(level(nfull, 1, n - (2 * nfull + 1) * b));
+  }
+  {
+    ProfScope ps(c, DET_KERNEL_GEMM_F64, 12.0 * (double)n * n, (double)n * n * n, w.st);
+    HIPCHK(detk::launch_gemm_mod(W, J.slab, offS, offV, n, ldw, n, n, n,
+                                 (const Modulus*)w.mods.p, kc4, 2, true, 1, w.st));
+  }
+  *col_out = offS;
+  return DET_OK;
+}
+
 // Validates A and returns a device pointer to it (uploading host memory into
 // the context's A buffer) with its leading dimension.
 det_status stage_matrix(det_ctx* c, const int64_t* A, int64_t n, int64_t lda,
@@ -503,18 +553,23 @@ det_status ensure_pinned(det_ctx* c, size_t count);
 // A^{-1} mod p into c->Cu by LU of [A | I] and back substitution.
 det_status inverse_mod_p(det_ctx* c, const int64_t* dA, int64_t dlda, int n, uint32_t p) {
   LuWs& w = c->ws[0];
+  // with every panel 32 wide the inverse is formed from the factors in a few
+  // launches (inverse_from_lu, four n-wide regions), else by the blocked back
+  // substitution (two)
+  const bool fast = detk::panel_width_for(n) == 32;
   LuJob J;
   J.n = n;
   J.ncols = 2 * n;
-  J.ldw = round_up(2 * n, 32);
+  J.ldw = round_up((fast ? 4 : 2) * (int64_t)n, 32);
   J.slab = J.ldw * n;
   J.nitems = 1;
   J.pmax = p;
   J.int8 = false;
-  TRY(ensure_pin(c, w.hmods, sizeof(Modulus), w.st));
+  const int nrep = (n + 63) / 64;
+  TRY(ensure_pin(c, w.hmods, (size_t)nrep * sizeof(Modulus), w.st));
   TRY(ensure_pinned(c, 64));                       // c->hres[0..63]; a background CRA batch
   Modulus* hm = (Modulus*)w.hmods.p;               // writes from c->hres + 64
-  *hm = modulus_of(p);
+  for (int i = 0; i < nrep; i++) hm[i] = modulus_of(p);
   TRY(ensure(c, w.W, (size_t)J.slab * sizeof(int32_t), w.st));
   TRY(ensure(c, w.piv, (size_t)n * sizeof(int32_t), w.st));
   TRY(ensure(c, w.flags, sizeof(int32_t), w.st));
@@ -530,9 +585,11 @@ det_status inverse_mod_p(det_ctx* c, const int64_t* dA, int64_t dlda, int n, uin
   HIPCHK(hipMemcpyAsync(flag, w.flags.p, sizeof(int32_t), hipMemcpyDeviceToHost, w.st));
   HIPCHK(hipStreamSynchronize(w.st));
   if (*flag) return fail(c, DET_E_SINGULAR_MOD_P, "p divides det(A)");
-  TRY(back_substitute(c, w, J, panels, 1));
-  HIPCHK(detk::launch_extract_inverse((const int32_t*)w.W.p, J.ldw, n, (const Modulus*)w.mods.p,
-                                      (uint32_t*)c->Cu.p, w.st));
+  int64_t col = n;
+  if (fast) TRY(inverse_from_lu(c, w, J, &col));
+  else TRY(back_substitute(c, w, J, panels, 1));
+  HIPCHK(detk::launch_extract_inverse((const int32_t*)w.W.p, J.ldw, col, n,
+                                      (const Modulus*)w.mods.p, (uint32_t*)c->Cu.p, w.st));
   return DET_OK;
 }
 
@@ -806,7 +863,7 @@ void det_ctx_destroy(det_ctx* c) {
                               &c->rp1, &c->x1, &c->C2, &c->Ed, &c->rv, &c->xv};
   for (LuWs& w : c->ws)
     for (DevBuf* b : {&w.W, &w.piv, &w.flags, &w.mods, &w.linv, &w.uinv, &w.tinv, &w.limbA,
-                      &w.limbB, &w.res})
+                      &w.limbB, &w.res, &w.modsr})
       all.push_back(b);
   for (DevBuf* b : all)
     if (b->p) (void)hipFree(b->p);

@@ -36,8 +36,18 @@ hipError_t launch_gemm_i8(int32_t* W, int64_t slab, int64_t offC, int64_t ldw, i
 hipError_t launch_det_finalize(const int32_t* W, int64_t ldw, int64_t slab, int n,
                                const int32_t* piv, int64_t piv_stride, const int32_t* flags,
                                const Modulus* mods, uint32_t* out, int nitems, hipStream_t st);
-hipError_t launch_extract_inverse(const int32_t* W, int64_t ldw, int n, const Modulus* mods,
-                                  uint32_t* Cu, hipStream_t st);
+hipError_t launch_extract_inverse(const int32_t* W, int64_t ldw, int64_t col0, int n,
+                                  const Modulus* mods, uint32_t* Cu, hipStream_t st);
+// C <op> A B (mod p) on int32 centred residues within one slab per item
+// (op 0: C -= AB, 1: C += AB, 2: C = AB, 3: C = -AB); upper_a: A is upper
+// triangular (a row tile starts K at its row).
+hipError_t launch_gemm_mod(int32_t* W, int64_t slab, int64_t offC, int64_t offA, int64_t offB,
+                           int64_t ldw, int M, int N, int K, const Modulus* mods, int kc4, int op,
+                           bool upper_a, int nitems, hipStream_t st);
+// The 32 x 32 diagonal-block inverses (panel-major) onto the diagonal of the
+// n x n region at offV.
+hipError_t launch_place_diag(int32_t* W, int64_t ldw, int64_t offV, int n, const int32_t* uinv,
+                             hipStream_t st);
 
 // Dixon lifting (dixon_kernels.hip).
 hipError_t launch_lift_x(const uint32_t* Cu, const uint32_t* rp, int n, uint32_t p,

@@ -649,6 +649,127 @@ __global__ __launch_bounds__(256) void k_gemm_f64(int32_t* __restrict__ W, int64
       }
 }
 
+// ------------------------------------------------------------------ general modular product
+// C <op> A B (mod p) on int32 centred residues of one slab per item, FP64
+// MFMA on 64x64 tiles, K in chunks of 32 with the next chunk's global loads
+// issued before the current chunk's MFMAs (latency hidden for long K).
+// Sums are reduced every kc4 MFMA k-steps (exact chunking as k_gemm_f64).
+// op: 0 C -= AB, 1 C += AB, 2 C = AB, 3 C = -AB.  upper_a: A is upper
+// triangular (zero below the diagonal), so a row tile starts K at its row.
+// Items: z = blockIdx.z at W + z * slab with modulus mods[z].
+constexpr int GM_K = 32;
+__global__ __launch_bounds__(256) void k_gemm_mod(int32_t* __restrict__ W, int64_t slab,
+                                                  int64_t offC, int64_t offA, int64_t offB,
+                                                  int64_t ldw, int M, int N, int K,
+                                                  const Modulus* __restrict__ mods, int kc4, int op,
+                                                  int upper_a) {
+  constexpr int NL = GB_M * GM_K / 256, NR = GM_K * GB_N / 256;
+  const int z = blockIdx.z;
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const double p = mods[z].p, pinv = mods[z].pinv;
+  int32_t* Wz = W + (int64_t)z * slab;
+  const int32_t* Ag = Wz + offA;
+  const int32_t* Bg = Wz + offB;
+  int32_t* Cg = Wz + offC;
+  const int row0 = blockIdx.y * GB_M, col0 = blockIdx.x * GB_N;
+  __shared__ double sA[GM_K][GB_M + 2];
+  __shared__ double sB[GM_K][GB_N + 2];
+  int32_t areg[NL], breg[NR];
+  // value u of thread t: element u * 256 + t of the tile, row-major
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < NL; u++) {
+      const int f = u * 256 + t, r = f / GM_K, k = f % GM_K;
+      const int gr = row0 + r, gk = k0 + k;
+      areg[u] = (gr < M && gk < K) ? Ag[(int64_t)gr * ldw + gk] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < NR; u++) {
+      const int f = u * 256 + t, k = f / GB_N, c = f % GB_N;
+      const int gk = k0 + k, gc = col0 + c;
+      breg[u] = (gk < K && gc < N) ? Bg[(int64_t)gk * ldw + gc] : 0;
+    }
+  };
+  v4d acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; i++)
+#pragma unroll
+    for (int j = 0; j < 2; j++) acc[i][j] = (v4d){0.0, 0.0, 0.0, 0.0};
+  const int kbeg = upper_a ? (row0 / GM_K) * GM_K : 0;
+  int steps = 0;
+  if (kbeg < K) gload(kbeg);
+  for (int k0 = kbeg; k0 < K; k0 += GM_K) {
+#pragma unroll
+    for (int u = 0; u < NL; u++) {
+      const int f = u * 256 + t;
+      sA[f % GM_K][f / GM_K] = (double)areg[u];
+    }
+#pragma unroll
+    for (int u = 0; u < NR; u++) {
+      const int f = u * 256 + t;
+      sB[f / GB_N][f % GB_N] = (double)breg[u];
+    }
+    __syncthreads();
+    if (k0 + GM_K < K) gload(k0 + GM_K);
+#pragma unroll
+    for (int ks = 0; ks < GM_K; ks += 4) {
+      const int kr = ks + (lane >> 4);
+      double af[2], bf[2];
+#pragma unroll
+      for (int i = 0; i < 2; i++) af[i] = sA[kr][wr * 32 + i * 16 + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < 2; j++) bf[j] = sB[kr][wc * 32 + j * 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < 2; i++)
+#pragma unroll
+        for (int j = 0; j < 2; j++)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+      if (++steps == kc4) {
+        steps = 0;
+#pragma unroll
+        for (int i = 0; i < 2; i++)
+#pragma unroll
+          for (int j = 0; j < 2; j++)
+#pragma unroll
+            for (int r = 0; r < 4; r++) acc[i][j][r] = mod_c(acc[i][j][r], p, pinv);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; i++)
+#pragma unroll
+    for (int j = 0; j < 2; j++)
+#pragma unroll
+      for (int r = 0; r < 4; r++) {
+        const int gr = row0 + wr * 32 + i * 16 + (lane >> 4) + 4 * r;
+        const int gc = col0 + wc * 32 + j * 16 + (lane & 15);
+        if (gr < M && gc < N) {
+          int32_t* cp = Cg + (int64_t)gr * ldw + gc;
+          const double s = mod_c(acc[i][j][r], p, pinv);
+          double v;
+          if (op == 0) v = (double)*cp - s;
+          else if (op == 1) v = (double)*cp + s;
+          else if (op == 2) v = s;
+          else v = -s;
+          *cp = (int32_t)mod_c(v, p, pinv);
+        }
+      }
+}
+
+// The 32 x 32 inverses of the diagonal blocks of U (panel-major, panel q at
+// rows and columns [32 q, 32 q + pb)) into the diagonal of an n x n region.
+__global__ void k_place_diag(int32_t* __restrict__ W, int64_t ldw, int64_t offV, int n,
+                             const int32_t* __restrict__ uinv) {
+  const int q = blockIdx.x, r = threadIdx.x >> 5, cc = threadIdx.x & 31;
+  for (int rr = r; rr < 32; rr += blockDim.x >> 5) {
+    const int gr = 32 * q + rr, gc = 32 * q + cc;
+    if (gr < n && gc < n) W[offV + (int64_t)gr * ldw + gc] = uinv[(int64_t)q * 1024 + rr * 32 + cc];
+  }
+}
+
 // ------------------------------------------------------------------ K4: in-place triangular apply
 // X <- Tinv[z] * X for the strip X = rows [r0, r0+kb) x columns [c0, c0+N)
 // of every item (U12 = L11^{-1} A12, or X_blk = U11^{-1} Y_blk).  A
@@ -919,13 +1040,14 @@ __global__ __launch_bounds__(256) void k_det_finalize(const int32_t* __restrict_
 // ------------------------------------------------------------------ inverse extraction
 // Cu[i][j] = canonical residue of W[z=0][i][n + j] (the right half of [A | I]
 // after elimination and back substitution holds A^{-1} mod p).
-__global__ void k_extract_inverse(const int32_t* __restrict__ W, int64_t ldw, int n,
-                                  const Modulus* __restrict__ mods, uint32_t* __restrict__ Cu) {
+__global__ void k_extract_inverse(const int32_t* __restrict__ W, int64_t ldw, int64_t col0,
+                                  int n, const Modulus* __restrict__ mods,
+                                  uint32_t* __restrict__ Cu) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   const int i = blockIdx.y;
   if (j >= n || i >= n) return;
   const double p = mods[0].p;
-  Cu[(int64_t)i * n + j] = to_canonical((double)W[(int64_t)i * ldw + n + j], p);
+  Cu[(int64_t)i * n + j] = to_canonical((double)W[(int64_t)i * ldw + col0 + j], p);
 }
 
 // ------------------------------------------------------------------ A packing and norms
@@ -1062,6 +1184,26 @@ hipError_t launch_gemm_f64(int32_t* W, int64_t slab, int64_t offC, int64_t offA,
   return hipSuccess;
 }
 
+hipError_t launch_gemm_mod(int32_t* W, int64_t slab, int64_t offC, int64_t offA, int64_t offB,
+                           int64_t ldw, int M, int N, int K, const Modulus* mods, int kc4, int op,
+                           bool upper_a, int nitems, hipStream_t st) {
+  if (M <= 0 || N <= 0 || nitems <= 0) return hipSuccess;
+  if (op < 0 || op > 3 || kc4 < 1) return hipErrorInvalidValue;
+  dim3 grid((N + GB_N - 1) / GB_N, (M + GB_M - 1) / GB_M, nitems);
+  k_gemm_mod<<<grid, 256, 0, st>>>(W, slab, offC, offA, offB, ldw, M, N, K, mods, kc4, op,
+                                   upper_a ? 1 : 0);
+  LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+hipError_t launch_place_diag(int32_t* W, int64_t ldw, int64_t offV, int n, const int32_t* uinv,
+                             hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  k_place_diag<<<(n + 31) / 32, 256, 0, st>>>(W, ldw, offV, n, uinv);
+  LAUNCH_CHECK();
+  return hipSuccess;
+}
+
 hipError_t launch_split(const int32_t* W, int64_t slab, int64_t off, int64_t ldw, int rows, int K,
                         int Kp, int transpose, int8_t* P, int64_t pslab, int nitems,
                         hipStream_t st) {
@@ -1091,11 +1233,11 @@ hipError_t launch_det_finalize(const int32_t* W, int64_t ldw, int64_t slab, int 
   return hipSuccess;
 }
 
-hipError_t launch_extract_inverse(const int32_t* W, int64_t ldw, int n, const Modulus* mods,
-                                  uint32_t* Cu, hipStream_t st) {
+hipError_t launch_extract_inverse(const int32_t* W, int64_t ldw, int64_t col0, int n,
+                                  const Modulus* mods, uint32_t* Cu, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   dim3 grid((n + 255) / 256, n);
-  k_extract_inverse<<<grid, 256, 0, st>>>(W, ldw, n, mods, Cu);
+  k_extract_inverse<<<grid, 256, 0, st>>>(W, ldw, col0, n, mods, Cu);
   LAUNCH_CHECK();
   return hipSuccess;
 }
