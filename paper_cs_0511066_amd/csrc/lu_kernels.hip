@@ -126,36 +126,33 @@ __global__ __launch_bounds__(512) void k_panel(int32_t* __restrict__ W, int64_t 
   __shared__ double sRik[8][8];               // a group's pivot-column entries (fraction-free)
   __shared__ int s_gfast[2];
 
-  // coalesced load of the panel into LDS (all loads in flight at once), then
-  // each thread takes its rows
+  // each thread loads its own rows straight into registers (16-byte loads of
+  // the row's PB entries when the panel is full width: j0, ldw and slab are
+  // multiples of 4); the LDS copy of the panel, sP, only ever receives
+  // finished values, and every entry of it is written before the write-back
   if (t == 0) s_sing = 0;
   if (t < 2 * PB) s_prow[t / PB][t % PB] = 0.0;   // finite even where it is not written
   if (t < PB) s_dinv[t] = 0.0;
-  {
-    constexpr int RS = T / PB;                  // rows per pass of the workgroup
-    const int k = t % PB;
-    constexpr int NL = RPT * PB;                // loads in flight per thread: all of them
-    static_assert((RPT * PB) % NL == 0, "load batches");
-#pragma unroll 1
-    for (int r0 = t / PB; r0 < MROWS; r0 += NL * RS) {
-      int32_t v[NL];
-#pragma unroll
-      for (int i = 0; i < NL; i++) {
-        const int r = r0 + i * RS;
-        v[i] = (r < m && k < pb) ? Wz[(int64_t)r * ldw + k] : 0;
-      }
-#pragma unroll
-      for (int i = 0; i < NL; i++) sP[(r0 + i * RS) * SP + k] = v[i];
-    }
-  }
-  __syncthreads();
   double a[RPT][PB];
 #pragma unroll
   for (int q = 0; q < RPT; q++) {
     const int row = t + q * T;
+    const int32_t* src = Wz + (int64_t)(row < m ? row : 0) * ldw;
+    if (pb == PB) {
 #pragma unroll
-    for (int k = 0; k < PB; k++) a[q][k] = row < m ? (double)sP[row * SP + k] : 0.0;
+      for (int k4 = 0; k4 < PB / 4; k4++) {
+        const v4i v = row < m ? ((const v4i*)src)[k4] : v4i{0, 0, 0, 0};
+        a[q][4 * k4] = (double)v.x;
+        a[q][4 * k4 + 1] = (double)v.y;
+        a[q][4 * k4 + 2] = (double)v.z;
+        a[q][4 * k4 + 3] = (double)v.w;
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < PB; k++) a[q][k] = (row < m && k < pb) ? (double)src[k] : 0.0;
+    }
   }
+  __syncthreads();
 
   for (int g = 0; g < pb; g += GJ) {
     const int gb = (g / GJ) & 1;
@@ -478,9 +475,9 @@ __global__ void k_swaps(int32_t* __restrict__ W, int64_t ldw, int64_t slab, int 
                         int c0a, int c1a, int c0b, int c1b) {
   const int z = blockIdx.y;
   const int32_t* pz = piv + (int64_t)z * piv_stride + j0;
-  bool any = false;
-  for (int j = 0; j < pb; j++) any |= (pz[j] != j0 + j);
-  if (!any) return;
+  // one pivot a thread (pb <= 32 <= blockDim.x)
+  const int tt = threadIdx.x;
+  if (!__syncthreads_or(tt < pb && pz[tt] != j0 + tt)) return;
   const int wa = c1a - c0a;
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   const int wtot = wa + (c1b - c0b);
@@ -556,7 +553,7 @@ __global__ __launch_bounds__(1024) void k_tri_inv(const int32_t* __restrict__ W,
 // as doubles, k-major, so that a lane reads 16 consecutive doubles per row.
 // v_mfma_f64_16x16x4: lane l supplies A[l%16][l/16] and B[l/16][l%16];
 // result element r of lane l is D[l/16 + 4r][l%16].
-constexpr int GB_M = 64, GB_N = 64, GB_K = 16;
+constexpr int GB_M = 64, GB_N = 64, GB_K = 32;
 
 // C[z] = (C[z] - A[z] * B[z]) mod p_z over an M x N region (all int32
 // centred residues, row-major with leading dimensions).  `kc4` = number of
@@ -587,24 +584,32 @@ __global__ __launch_bounds__(256) void k_gemm_f64(int32_t* __restrict__ W, int64
 
   int steps = 0;
   for (int k0 = 0; k0 < K; k0 += GB_K) {
-    // A tile: 64 rows x 16 k; thread t loads row t/4, k (t%4)*4 .. +3
+    // A tile 64 rows x 32 k and B tile 32 k x 64 cols (a trailing update of
+    // a 32-wide panel in one chunk): value u of thread t is element u * 256 + t
+    // of the tile, row-major, so consecutive threads read consecutive words
     {
-      const int r = t >> 2, kq = (t & 3) * 4;
-      const int gr = row0 + r;
+      int32_t va[GB_M * GB_K / 256], vb[GB_K * GB_N / 256];
 #pragma unroll
-      for (int u = 0; u < 4; u++) {
-        const int gk = k0 + kq + u;
-        sA[kq + u][r] = (gr < M && gk < K) ? (double)Ag[(int64_t)gr * ldw + gk] : 0.0;
+      for (int u = 0; u < GB_M * GB_K / 256; u++) {
+        const int f = u * 256 + t, r = f / GB_K, k = f % GB_K;
+        const int gr = row0 + r, gk = k0 + k;
+        va[u] = (gr < M && gk < K) ? Ag[(int64_t)gr * ldw + gk] : 0;
       }
-    }
-    // B tile: 16 k x 64 cols; thread t loads k t/16, cols (t%16)*4 .. +3
-    {
-      const int kk = t >> 4, cq = (t & 15) * 4;
-      const int gk = k0 + kk;
 #pragma unroll
-      for (int u = 0; u < 4; u++) {
-        const int gc = col0 + cq + u;
-        sB[kk][cq + u] = (gk < K && gc < N) ? (double)Bg[(int64_t)gk * ldw + gc] : 0.0;
+      for (int u = 0; u < GB_K * GB_N / 256; u++) {
+        const int f = u * 256 + t, k = f / GB_N, c = f % GB_N;
+        const int gk = k0 + k, gc = col0 + c;
+        vb[u] = (gk < K && gc < N) ? Bg[(int64_t)gk * ldw + gc] : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < GB_M * GB_K / 256; u++) {
+        const int f = u * 256 + t;
+        sA[f % GB_K][f / GB_K] = (double)va[u];
+      }
+#pragma unroll
+      for (int u = 0; u < GB_K * GB_N / 256; u++) {
+        const int f = u * 256 + t;
+        sB[f / GB_N][f % GB_N] = (double)vb[u];
       }
     }
     __syncthreads();
@@ -658,36 +663,41 @@ __global__ __launch_bounds__(256) void k_gemm_f64(int32_t* __restrict__ W, int64
 // triangular (zero below the diagonal), so a row tile starts K at its row.
 // Items: z = blockIdx.z at W + z * slab with modulus mods[z].
 constexpr int GM_K = 32;
-__global__ __launch_bounds__(256) void k_gemm_mod(int32_t* __restrict__ W, int64_t slab,
-                                                  int64_t offC, int64_t offA, int64_t offB,
-                                                  int64_t ldw, int M, int N, int K,
-                                                  const Modulus* __restrict__ mods, int kc4, int op,
-                                                  int upper_a) {
-  constexpr int NL = GB_M * GM_K / 256, NR = GM_K * GB_N / 256;
+// WR x WC waves, each a 32 x 32 quarter (2 x 2 MFMA blocks): tiles of
+// 32 WR x 32 WC (launched as 64 x 64 with four waves).
+template <int WR, int WC>
+__global__ __launch_bounds__(64 * WR * WC) void k_gemm_mod(int32_t* __restrict__ W, int64_t slab,
+                                                           int64_t offC, int64_t offA,
+                                                           int64_t offB, int64_t ldw, int M,
+                                                           int N, int K,
+                                                           const Modulus* __restrict__ mods,
+                                                           int kc4, int op, int upper_a) {
+  constexpr int T = 64 * WR * WC, TM = 32 * WR, TN = 32 * WC;
+  constexpr int NL = TM * GM_K / T, NR = GM_K * TN / T;
   const int z = blockIdx.z;
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
-  const int wr = wave >> 1, wc = wave & 1;
+  const int wr = wave / WC, wc = wave % WC;
   const double p = mods[z].p, pinv = mods[z].pinv;
   int32_t* Wz = W + (int64_t)z * slab;
   const int32_t* Ag = Wz + offA;
   const int32_t* Bg = Wz + offB;
   int32_t* Cg = Wz + offC;
-  const int row0 = blockIdx.y * GB_M, col0 = blockIdx.x * GB_N;
-  __shared__ double sA[GM_K][GB_M + 2];
-  __shared__ double sB[GM_K][GB_N + 2];
+  const int row0 = blockIdx.y * TM, col0 = blockIdx.x * TN;
+  __shared__ double sA[GM_K][TM + 2];
+  __shared__ double sB[GM_K][TN + 2];
   int32_t areg[NL], breg[NR];
-  // value u of thread t: element u * 256 + t of the tile, row-major
+  // value u of thread t: element u * T + t of the tile, row-major
   auto gload = [&](int k0) {
 #pragma unroll
     for (int u = 0; u < NL; u++) {
-      const int f = u * 256 + t, r = f / GM_K, k = f % GM_K;
+      const int f = u * T + t, r = f / GM_K, k = f % GM_K;
       const int gr = row0 + r, gk = k0 + k;
       areg[u] = (gr < M && gk < K) ? Ag[(int64_t)gr * ldw + gk] : 0;
     }
 #pragma unroll
     for (int u = 0; u < NR; u++) {
-      const int f = u * 256 + t, k = f / GB_N, c = f % GB_N;
+      const int f = u * T + t, k = f / TN, c = f % TN;
       const int gk = k0 + k, gc = col0 + c;
       breg[u] = (gk < K && gc < N) ? Bg[(int64_t)gk * ldw + gc] : 0;
     }
@@ -703,13 +713,13 @@ __global__ __launch_bounds__(256) void k_gemm_mod(int32_t* __restrict__ W, int64
   for (int k0 = kbeg; k0 < K; k0 += GM_K) {
 #pragma unroll
     for (int u = 0; u < NL; u++) {
-      const int f = u * 256 + t;
+      const int f = u * T + t;
       sA[f % GM_K][f / GM_K] = (double)areg[u];
     }
 #pragma unroll
     for (int u = 0; u < NR; u++) {
-      const int f = u * 256 + t;
-      sB[f / GB_N][f % GB_N] = (double)breg[u];
+      const int f = u * T + t;
+      sB[f / TN][f % TN] = (double)breg[u];
     }
     __syncthreads();
     if (k0 + GM_K < K) gload(k0 + GM_K);
@@ -794,8 +804,8 @@ __global__ __launch_bounds__(256) void k_trsm_apply(int32_t* __restrict__ W, int
   const int col0 = blockIdx.x * GB_N;
   if (sw_pb > 0) {
     const int32_t* pz = piv + (int64_t)z * piv_stride + sw_j0;
-    bool any = false;
-    for (int j = 0; j < sw_pb; j++) any |= (pz[j] != sw_j0 + j);
+    // one pivot a thread (a loop over them would wait for each load in turn)
+    const bool any = __syncthreads_or(t < sw_pb && pz[t] != sw_j0 + t);
     if (any) {                                   // uniform across the workgroup
       int32_t* Wc = W + (int64_t)z * slab + c0;
       if (t < GB_N && col0 + t < N) {
@@ -812,13 +822,17 @@ __global__ __launch_bounds__(256) void k_trsm_apply(int32_t* __restrict__ W, int
       __syncthreads();
     }
   }
-  extern __shared__ double sX[];             // [ldt][GB_N + 2]
+  extern __shared__ double sX[];             // [ldt][GB_N + 2], then Tinv when ldt <= 32
   constexpr int LDX = GB_N + 2;
+  const bool stage_t = ldt <= 32;              // the inverse in LDS, not read per k-step
+  double* sT = sX + ldt * LDX;
   for (int e = t; e < ldt * GB_N; e += 256) {
     const int k = e / GB_N, c = e % GB_N;
     const int gc = col0 + c;
     sX[k * LDX + c] = (k < kb && gc < N) ? (double)Xg[(int64_t)k * ldw + gc] : 0.0;
   }
+  if (stage_t)
+    for (int e = t; e < ldt * ldt; e += 256) sT[e] = (double)Tz[e];
   __syncthreads();
   for (int rb = 0; rb < kb; rb += GB_M) {
     v4d acc[2][2];
@@ -833,7 +847,8 @@ __global__ __launch_bounds__(256) void k_trsm_apply(int32_t* __restrict__ W, int
 #pragma unroll
       for (int i = 0; i < 2; i++) {
         const int rr = rb + wr * 32 + i * 16 + (lane & 15);
-        af[i] = (rr < kb && kr < kb) ? (double)Tz[rr * ldt + kr] : 0.0;
+        af[i] = (rr < kb && kr < kb) ? (stage_t ? sT[rr * ldt + kr] : (double)Tz[rr * ldt + kr])
+                                     : 0.0;
       }
 #pragma unroll
       for (int j = 0; j < 2; j++) bf[j] = sX[kr * LDX + wc * 32 + j * 16 + (lane & 15)];
@@ -1167,7 +1182,7 @@ hipError_t launch_trsm_apply(int32_t* W, int64_t slab, int64_t ldw, int r0, int 
   if (kb <= 0 || N <= 0) return hipSuccess;
   if (kb > ldt || (ldt % 4) != 0) return hipErrorInvalidValue;
   dim3 grid((N + GB_N - 1) / GB_N, nitems);
-  const size_t sh = (size_t)ldt * (GB_N + 2) * sizeof(double);
+  const size_t sh = ((size_t)ldt * (GB_N + 2) + (ldt <= 32 ? (size_t)ldt * ldt : 0)) * sizeof(double);
   k_trsm_apply<<<grid, 256, sh, st>>>(W, slab, ldw, r0, kb, c0, N, Tinv, ldt, mods, kc4, piv,
                                       piv_stride, sw_j0, sw_pb);
   LAUNCH_CHECK();
@@ -1189,9 +1204,9 @@ hipError_t launch_gemm_mod(int32_t* W, int64_t slab, int64_t offC, int64_t offA,
                            bool upper_a, int nitems, hipStream_t st) {
   if (M <= 0 || N <= 0 || nitems <= 0) return hipSuccess;
   if (op < 0 || op > 3 || kc4 < 1) return hipErrorInvalidValue;
-  dim3 grid((N + GB_N - 1) / GB_N, (M + GB_M - 1) / GB_M, nitems);
-  k_gemm_mod<<<grid, 256, 0, st>>>(W, slab, offC, offA, offB, ldw, M, N, K, mods, kc4, op,
-                                   upper_a ? 1 : 0);
+  dim3 grid((N + 63) / 64, (M + 63) / 64, nitems);
+  k_gemm_mod<2, 2><<<grid, 256, 0, st>>>(W, slab, offC, offA, offB, ldw, M, N, K, mods, kc4, op,
+                                         upper_a ? 1 : 0);
   LAUNCH_CHECK();
   return hipSuccess;
 }
@@ -1260,9 +1275,12 @@ hipError_t launch_norms(const int64_t* A, int64_t lda, int n, double* out2n, dou
   return hipSuccess;
 }
 
+// k_trsm_apply takes its strip (and a small inverse) as dynamic LDS: at most
+// 128 x 66 doubles for the 128-wide outer inverses; its own static LDS (the
+// workgroup vote) must fit beside it in the 160 KB of a CU.
 hipError_t configure_kernels() {
   return hipFuncSetAttribute((const void*)k_trsm_apply,
-                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+                             hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
 }
 
 }  // namespace detk
