@@ -35,31 +35,33 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-# HBM traffic of the dominant kernel, measured with rocprofv3 counters
+# HBM traffic per launch of a kernel class, measured with rocprofv3 counters
 # (FETCH_SIZE and WRITE_SIZE, each scaled by the reading of a plain copy of
 # known size) and recorded with a hash of the kernel source it was taken on.
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "lift_resident3_n1024_traffic.txt")
-KERNEL_SOURCES = {"lift": "paper_cs_0511066_amd/csrc/dixon_kernels.hip"}
+TRAFFIC = {
+    "lift": ("profiles/lift_resident3_n1024_traffic.txt", "paper_cs_0511066_amd/csrc/dixon_kernels.hip"),
+    "panel": ("profiles/panel_n1024_traffic.txt", "paper_cs_0511066_amd/csrc/lu_kernels.hip"),
+}
 
 
-def source_hash(kernel):
-    src = KERNEL_SOURCES.get(kernel)
-    if src is None:
-        return None
-    with open(os.path.join(ROOT, src), "rb") as f:
+def source_hash(path):
+    with open(os.path.join(ROOT, path), "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
 def measured_traffic(kernel):
-    """Bytes per launch from the committed counter summary, or None when the
-    summary is missing or was taken on another version of the kernel."""
+    """Bytes per launch from the committed counter summary, or None when there
+    is none for this kernel class or it was taken on another version of it."""
+    if kernel not in TRAFFIC:
+        return None
+    summary, src = TRAFFIC[kernel]
     try:
-        fields = dict(line.split(":", 1) for line in open(TRAFFIC_FILE) if ":" in line)
+        fields = dict(line.split(":", 1) for line in open(os.path.join(ROOT, summary)) if ":" in line)
     except OSError:
         return None
     if fields.get("kernel", "").strip() != kernel:
         return None
-    if fields.get("source_sha256_16", "").strip() != source_hash(kernel):
+    if fields.get("source_sha256_16", "").strip() != source_hash(src):
         return None
     try:
         return float(fields["hbm_bytes_per_launch"])
