@@ -44,6 +44,12 @@ __device__ __forceinline__ uint32_t umod64(uint64_t v, uint32_t p, double pinv) 
   return (uint32_t)r;
 }
 
+// v mod p in [0, p) for an integer-valued double with |v| < 2^52.
+__device__ __forceinline__ double canon_p(double v, double pd, double pinv) {
+  const double r = fma(-rint(v * pinv), pd, v);
+  return r < 0.0 ? r + pd : r;
+}
+
 // v mod p in [0, p) for signed 64-bit v with |v| < 2^62.
 __device__ __forceinline__ uint32_t smod64(int64_t v, uint32_t p, double pinv) {
   const int64_t q = (int64_t)floor((double)v * pinv);
@@ -781,7 +787,11 @@ __device__ __forceinline__ int32_t centred_i32(uint32_t u, uint32_t p) {
 // (S0 = q0 p + m0, ...), so the three lane digits m0, m1, m2 are small and
 // their wave sums fit in int32; digits of x follow with a carry pass.
 // Phase R: D_q = A x_q (|D_q| <= n ||A|| p < 2^53) and
-//   r' = (((r - D0)/p - D1)/p - D2)/p   in exact int64 arithmetic.
+//   r' = (((r - D0)/p - D1)/p - D2)/p,
+// every partial value an integer below 2^53 (|r| stays below n ||A|| + ||b||),
+// so the per-row steps run in FP64 too: an exact quotient by p is
+// rint(v * (1/p)), as |v / p| < 2^28 keeps the error of the reciprocal far
+// below 1/2.
 //
 // No grid barrier: every exchanged 32-bit word holds a 25-bit digit (two's
 // complement for r, plain for x) under a 7-bit tag, the step number mod 127,
@@ -889,13 +899,13 @@ __global__ __launch_bounds__(64 * NWAVE) void k_lift_resident3(
   typedef typename std::conditional<NARROW, int32_t, double>::type nv_t;
   double c0[RPW][EPL], c1[RPW][EPL];
   nv_t c2[RPW][EPL], av[RPW][EPL];
-  int64_t rr[RPW];
+  double rr[RPW];                                  // r of the row (lane 0), an integer
   int rows[RPW];
 #pragma unroll
   for (int i = 0; i < RPW; i++) {
     const int row = row0 + wave * RPW + i;
     rows[i] = row;
-    rr[i] = 0;
+    rr[i] = 0.0;
 #pragma unroll
     for (int e = 0; e < EPL; e++) {
       const int j = lane + 64 * e;
@@ -906,7 +916,7 @@ __global__ __launch_bounds__(64 * NWAVE) void k_lift_resident3(
       c2[i][e] = (nv_t)(in ? centred_i32(C2[o], p) : 0);
       av[i][e] = (nv_t)(in ? Ai[o] : 0);
     }
-    if (row < n && lane == 0) rr[i] = r[row];
+    if (row < n && lane == 0) rr[i] = (double)r[row];
   }
   const int64_t steps = (kd + 2) / 3;
   uint32_t tag = 0;                                // step mod 127
@@ -950,12 +960,13 @@ __global__ __launch_bounds__(64 * NWAVE) void k_lift_resident3(
       const int64_t M1 = dpp_sum_i32((int)m1);
       const int64_t M2 = dpp_sum_i32((int)m2);
       if (rows[i] < n && lane == 0) {
-        // carries by exact division (multiplication by p^{-1} mod 2^64)
-        const uint32_t x0 = smod64(M0, p, pinv);
-        const int64_t t1 = M1 + (int64_t)((uint64_t)(M0 - (int64_t)x0) * pinv64);
-        const uint32_t x1 = smod64(t1, p, pinv);
-        const int64_t t2 = M2 + (int64_t)((uint64_t)(t1 - (int64_t)x1) * pinv64);
-        const uint32_t x2 = smod64(t2, p, pinv);
+        // carries (|M| < 2^31): exact quotients by p in FP64
+        const double x0d = canon_p((double)M0, pd, pinv);
+        const double t1 = (double)M1 + rint(((double)M0 - x0d) * pinv);
+        const double x1d = canon_p(t1, pd, pinv);
+        const double t2 = (double)M2 + rint((t1 - x1d) * pinv);
+        const uint32_t x0 = (uint32_t)x0d, x1 = (uint32_t)x1d;
+        const uint32_t x2 = (uint32_t)canon_p(t2, pd, pinv);
         uint32_t* o = sOut + (wave * RPW + i) * 4;
         o[0] = tag << 25 | x0;
         o[1] = tag << 25 | x1;
@@ -993,18 +1004,19 @@ __global__ __launch_bounds__(64 * NWAVE) void k_lift_resident3(
       const double d1 = dpp_sum_f64(D1[i]);
       const double d2 = dpp_sum_f64(D2[i]);
       if (rows[i] < n && lane == 0) {
-        // exact divisions by p through p^{-1} mod 2^64
-        int64_t q = (int64_t)((uint64_t)(rr[i] - (int64_t)d0) * pinv64);
-        q = (int64_t)((uint64_t)(q - (int64_t)d1) * pinv64);
-        q = (int64_t)((uint64_t)(q - (int64_t)d2) * pinv64);
+        // exact divisions by p
+        double q = rint((rr[i] - d0) * pinv);
+        q = rint((q - d1) * pinv);
+        q = rint((q - d2) * pinv);
         rr[i] = q;
         // balanced digits of r' mod p^3, the carry of each centring taken
         // into the next digit, so that m0 + p m1 + p^2 m2 = r' (mod p^3)
-        const int32_t m0 = centred_i32(smod64(q, p, pinv), p);
-        const int64_t u1 = (int64_t)((uint64_t)(q - (int64_t)m0) * pinv64);
-        const int32_t m1 = centred_i32(smod64(u1, p, pinv), p);
-        const int64_t u2 = (int64_t)((uint64_t)(u1 - (int64_t)m1) * pinv64);
-        const int32_t m2 = centred_i32(smod64(u2, p, pinv), p);
+        const double m0d = mod_c(q, pd, pinv);
+        const double u1 = rint((q - m0d) * pinv);
+        const double m1d = mod_c(u1, pd, pinv);
+        const double u2 = rint((u1 - m1d) * pinv);
+        const int32_t m0 = (int32_t)m0d, m1 = (int32_t)m1d;
+        const int32_t m2 = (int32_t)mod_c(u2, pd, pinv);
         uint32_t* o = sOut + (wave * RPW + i) * 4;
         o[0] = tag1 << 25 | ((uint32_t)m0 & DIG);
         o[1] = tag1 << 25 | ((uint32_t)m1 & DIG);
@@ -1017,7 +1029,7 @@ __global__ __launch_bounds__(64 * NWAVE) void k_lift_resident3(
   }
 #pragma unroll
   for (int i = 0; i < RPW; i++)
-    if (rows[i] < n && lane == 0) r[rows[i]] = rr[i];
+    if (rows[i] < n && lane == 0) r[rows[i]] = (int64_t)rr[i];
 }
 
 // comb[i] = sum_j c_j x_i[j] for every lifted digit vector x_i (the random
