@@ -57,7 +57,7 @@ struct PinBuf {
 };
 
 struct LuWs {
-  DevBuf W, piv, flags, mods, linv, uinv, tinv, limbA, limbB, res, modsr;
+  DevBuf W, piv, flags, mods, linv, uinv, tinv, limbA, limbB, res, modsr, cnt;
   PinBuf hmods;                 // pinned host copy of the moduli (async uploads)
   hipStream_t st = nullptr;
 };
@@ -268,13 +268,17 @@ det_status gemm_update(det_ctx* c, LuWs& w, const LuJob& J, int64_t offC, int64_
   return DET_OK;
 }
 
-det_status panel_step(det_ctx* c, LuWs& w, const LuJob& J, const Panel& P, int32_t* uinv, int kc) {
+// ncols_sw > 0: the panel also applies its row swaps to the columns
+// [j0 + pb, ncols_sw) right of it.
+det_status panel_step(det_ctx* c, LuWs& w, const LuJob& J, const Panel& P, int32_t* uinv, int kc,
+                      int ncols_sw = 0) {
   const double m = J.n - P.j0;
   ProfScope ps(c, DET_KERNEL_PANEL, 8.0 * m * P.pb * J.nitems, m * P.pb * P.pb * (double)J.nitems,
                w.st);
   HIPCHK(detk::launch_panel((int32_t*)w.W.p, J.ldw, J.slab, J.n, P.j0, P.pb, P.pbw,
                             (const Modulus*)w.mods.p, (int32_t*)w.piv.p, J.n,
-                            (int32_t*)w.flags.p, (int32_t*)w.linv.p, uinv, kc, J.nitems, w.st));
+                            (int32_t*)w.flags.p, (int32_t*)w.linv.p, uinv, kc, J.nitems,
+                            ncols_sw, w.st));
   return DET_OK;
 }
 
@@ -311,19 +315,44 @@ det_status lu_factor(det_ctx* c, LuWs& w, const LuJob& J, bool keep_uinv,
   const int32_t* linv = (const int32_t*)w.linv.p;
   if (panels) panels->clear();
   if (!two_level) {
+    // FP64 trailing updates: the panel applies its swaps to the columns right
+    // of it and one launch forms U12 and updates A22 (U12 kept, by the last
+    // workgroup of each column tile to read A12, when the factors are needed:
+    // per-step counters); int8: triangular apply, then the product
+    const bool fused = !J.int8;
+    const int cstride = (ncols + 63) / 64;
+    unsigned* cnt = nullptr;
+    if (fused && keep_uinv) {
+      const size_t nc = (size_t)npan_max * nit * cstride;
+      TRY(ensure(c, w.cnt, nc * sizeof(unsigned), w.st));
+      HIPCHK(hipMemsetAsync(w.cnt.p, 0, nc * sizeof(unsigned), w.st));
+      cnt = (unsigned*)w.cnt.p;
+    }
     int idx = 0;
     for (int j0 = 0; j0 < n; idx++) {
       const int pbw = detk::panel_width_for(n - j0);
       const int pb = std::min(pbw, n - j0);
       const Panel P{j0, pb, pbw};
-      if (keep_uinv && idx >= npan_max) return fail(c, DET_E_INVALID, "panel count overflow");
+      if (idx >= npan_max) return fail(c, DET_E_INVALID, "panel count overflow");
       int32_t* uinv = keep_uinv ? (int32_t*)w.uinv.p + (size_t)idx * nit * 32 * 32 : nullptr;
-      TRY(panel_step(c, w, J, P, uinv, kc));
+      TRY(panel_step(c, w, J, P, uinv, kc, fused ? ncols : 0));
       if (panels) panels->push_back(P);
       const int right = ncols - (j0 + pb);
-      TRY(trsm_step(c, w, J, j0, pb, j0 + pb, right, linv, pbw, kc4, j0, pb));
-      TRY(gemm_update(c, w, J, (int64_t)(j0 + pb) * ldw + j0 + pb, (int64_t)(j0 + pb) * ldw + j0,
-                      (int64_t)j0 * ldw + j0 + pb, n - (j0 + pb), right, pb, kc4, J.int8));
+      if (fused) {
+        const int M = n - (j0 + pb);
+        ProfScope ps(c, DET_KERNEL_GEMM_F64,
+                     4.0 * ((double)M * pb + (double)pb * right + 2.0 * (double)M * right) * nit,
+                     2.0 * ((double)M + pb) * right * pb * nit, w.st);
+        HIPCHK(detk::launch_lu_update((int32_t*)w.W.p, J.slab, ldw, j0, pb, M, right, linv, pbw,
+                                      (const Modulus*)w.mods.p, kc4,
+                                      cnt ? cnt + (size_t)idx * nit * cstride : nullptr, cstride,
+                                      nit, w.st));
+      } else {
+        TRY(trsm_step(c, w, J, j0, pb, j0 + pb, right, linv, pbw, kc4, j0, pb));
+        TRY(gemm_update(c, w, J, (int64_t)(j0 + pb) * ldw + j0 + pb,
+                        (int64_t)(j0 + pb) * ldw + j0, (int64_t)j0 * ldw + j0 + pb,
+                        n - (j0 + pb), right, pb, kc4, J.int8));
+      }
       j0 += pb;
     }
     return DET_OK;
@@ -863,7 +892,7 @@ void det_ctx_destroy(det_ctx* c) {
                               &c->rp1, &c->x1, &c->C2, &c->Ed, &c->rv, &c->xv};
   for (LuWs& w : c->ws)
     for (DevBuf* b : {&w.W, &w.piv, &w.flags, &w.mods, &w.linv, &w.uinv, &w.tinv, &w.limbA,
-                      &w.limbB, &w.res, &w.modsr})
+                      &w.limbB, &w.res, &w.modsr, &w.cnt})
       all.push_back(b);
   for (DevBuf* b : all)
     if (b->p) (void)hipFree(b->p);

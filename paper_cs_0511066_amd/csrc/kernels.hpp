@@ -13,7 +13,14 @@ hipError_t launch_residues(const int64_t* A, int64_t lda, int n, int ncols, int3
                            int64_t slab, const Modulus* mods, int nitems, hipStream_t st);
 hipError_t launch_panel(int32_t* W, int64_t ldw, int64_t slab, int n, int j0, int pb, int pbw,
                         const Modulus* mods, int32_t* piv, int64_t piv_stride, int32_t* flags,
-                        int32_t* Linv, int32_t* Uinv, int kc, int nitems, hipStream_t st);
+                        int32_t* Linv, int32_t* Uinv, int kc, int nitems, int ncols_sw,
+                        hipStream_t st);
+// One LU step's update of the trailing block in one launch (U12 from L11^{-1}
+// A12 per column tile, stored by the last reader when cnt != null; A22 -=
+// L21 U12); the panel's swaps already applied (launch_panel with ncols_sw).
+hipError_t launch_lu_update(int32_t* W, int64_t slab, int64_t ldw, int j0, int pb, int M, int N,
+                            const int32_t* Linv, int ldt, const Modulus* mods, int kc4,
+                            unsigned* cnt, int cnt_stride, int nitems, hipStream_t st);
 int panel_width_for(int m);
 hipError_t launch_swaps(int32_t* W, int64_t ldw, int64_t slab, int j0, int pb, const int32_t* piv,
                         int64_t piv_stride, int c0a, int c1a, int c0b, int c1b, int nitems,

@@ -14,6 +14,8 @@
 // (16x16x4) with the sum of |products| kept <= 2^53 per reduction chunk, or
 // int8 MFMA (16x16x64) on three signed limbs with int32 accumulation.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 #include <stdint.h>
 #include <limits.h>
 
@@ -97,7 +99,7 @@ __global__ __launch_bounds__(512) void k_panel(int32_t* __restrict__ W, int64_t 
                                                 int32_t* __restrict__ piv, int64_t piv_stride,
                                                 int32_t* __restrict__ flags,
                                                 int32_t* __restrict__ Linv,
-                                                int32_t* __restrict__ Uinv) {
+                                                int32_t* __restrict__ Uinv, int ncols_sw) {
   constexpr int T = 512;
   constexpr int NW = T / 64;
   constexpr int MROWS = RPT * T;
@@ -465,6 +467,29 @@ __global__ __launch_bounds__(512) void k_panel(int32_t* __restrict__ W, int64_t 
     for (int i = 0; i < PB; i++)
       out[up ? cc * PB + i : i * PB + cc] = (i < pb && cc < pb) ? (int32_t)x[i] : 0;
   }
+  // The panel's row swaps on the columns [j0 + pb, ncols_sw) right of it,
+  // when the caller asks for them (ncols_sw > 0) and a pivot came from below
+  // (random inputs almost never need it): one column a thread, the swaps in
+  // order.
+  if (ncols_sw > j0 + pb) {
+    __syncthreads();
+    bool any = false;
+    for (int i = 0; i < pb; i++) any |= s_piv[i] != i;
+    if (any) {
+      int32_t* Wr = W + (int64_t)z * slab;
+      for (int c = j0 + pb + t; c < ncols_sw; c += T)
+        for (int i = 0; i < pb; i++) {
+          const int r = s_piv[i];
+          if (r != i) {
+            int32_t* a0 = Wr + (int64_t)(j0 + i) * ldw + c;
+            int32_t* a1 = Wr + (int64_t)(j0 + r) * ldw + c;
+            const int32_t v = *a0;
+            *a0 = *a1;
+            *a1 = v;
+          }
+        }
+    }
+  }
 }
 
 // ------------------------------------------------------------------ K3: row swaps
@@ -778,6 +803,158 @@ __global__ void k_place_diag(int32_t* __restrict__ W, int64_t ldw, int64_t offV,
     const int gr = 32 * q + rr, gc = 32 * q + cc;
     if (gr < n && gc < n) W[offV + (int64_t)gr * ldw + gc] = uinv[(int64_t)q * 1024 + rr * 32 + cc];
   }
+}
+
+// ------------------------------------------------------------------ fused LU step update
+// One step of the right-looking LU after the panel [j0, j0 + pb) (pb <= 32),
+// on the trailing block A22 = rows [j0 + pb, j0 + pb + M) x columns
+// [j0 + pb, j0 + pb + N) of every item, in one launch:
+//   U12 = L11^{-1} A12 for the workgroup's 64 columns (every workgroup of a
+//   column tile computes it from A12), then A22 -= L21 U12 on its 64 x 64
+//   tile.
+// A12 stays in place until every workgroup of its column tile has read it:
+// with cnt != null each workgroup counts its read (after the loads have
+// completed) and the last one stores U12 over A12; without it U12 is not
+// kept (a determinant needs only the diagonal).  The panel's row swaps must
+// already be applied to these columns.  Sums are reduced every kc4 MFMA
+// k-steps (exact chunking).
+__global__ __launch_bounds__(256) void k_lu_update(int32_t* __restrict__ W, int64_t slab,
+                                                   int64_t ldw, int j0, int pb, int M, int N,
+                                                   const int32_t* __restrict__ Linv, int ldt,
+                                                   const Modulus* __restrict__ mods, int kc4,
+                                                   unsigned* __restrict__ cnt, int cnt_stride) {
+  const int z = blockIdx.z;
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const double p = mods[z].p, pinv = mods[z].pinv;
+  int32_t* Wz = W + (int64_t)z * slab;
+  const int r0 = j0 + pb;                               // first row and column of A22
+  const int row0 = blockIdx.y * GB_M, col0 = blockIdx.x * GB_N;
+  __shared__ double sA[GB_K][GB_M + 2];                 // L21 tile, k-major
+  __shared__ double sB[GB_K][GB_N + 2];                 // A12 tile, then U12
+  __shared__ double sT[32][33];                         // L11^{-1}
+  __shared__ int s_last;
+  // all loads at once: L11^{-1}, A12, L21 and the old values of the tile
+  const int32_t* Tz = Linv + (int64_t)z * ldt * ldt;
+  for (int e = t; e < 32 * 32; e += 256) {
+    const int r = e >> 5, c = e & 31;
+    sT[r][c] = (r < pb && c < pb) ? (double)Tz[r * ldt + c] : 0.0;
+  }
+  int32_t va[GB_M * GB_K / 256], vb[GB_K * GB_N / 256], vc[2][2][4];
+#pragma unroll
+  for (int u = 0; u < GB_M * GB_K / 256; u++) {
+    const int f = u * 256 + t, r = f / GB_K, k = f % GB_K;
+    va[u] = (row0 + r < M && k < pb) ? Wz[(int64_t)(r0 + row0 + r) * ldw + j0 + k] : 0;
+  }
+#pragma unroll
+  for (int u = 0; u < GB_K * GB_N / 256; u++) {
+    const int f = u * 256 + t, k = f / GB_N, c = f % GB_N;
+    vb[u] = (k < pb && col0 + c < N) ? Wz[(int64_t)(j0 + k) * ldw + r0 + col0 + c] : 0;
+  }
+#pragma unroll
+  for (int i = 0; i < 2; i++)
+#pragma unroll
+    for (int j = 0; j < 2; j++)
+#pragma unroll
+      for (int r = 0; r < 4; r++) {
+        const int gr = row0 + wr * 32 + i * 16 + (lane >> 4) + 4 * r;
+        const int gc = col0 + wc * 32 + j * 16 + (lane & 15);
+        vc[i][j][r] = (gr < M && gc < N) ? Wz[(int64_t)(r0 + gr) * ldw + r0 + gc] : 0;
+      }
+#pragma unroll
+  for (int u = 0; u < GB_M * GB_K / 256; u++) {
+    const int f = u * 256 + t;
+    sA[f % GB_K][f / GB_K] = (double)va[u];
+  }
+#pragma unroll
+  for (int u = 0; u < GB_K * GB_N / 256; u++) {
+    const int f = u * 256 + t;
+    sB[f / GB_N][f % GB_N] = (double)vb[u];
+  }
+  __syncthreads();
+  // U12 = L11^{-1} A12 (32 x 64): wave w the 16 x 32 block (rows 16 (w >> 1),
+  // columns 32 (w & 1)), two 16 x 16 MFMA blocks
+  v4d u2[2];
+  u2[0] = u2[1] = (v4d){0.0, 0.0, 0.0, 0.0};
+  {
+    int steps = 0;
+#pragma unroll
+    for (int ks = 0; ks < 32; ks += 4) {
+      const int kr = ks + (lane >> 4);
+      const double af = sT[wr * 16 + (lane & 15)][kr];
+#pragma unroll
+      for (int j = 0; j < 2; j++)
+        u2[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af, sB[kr][wc * 32 + j * 16 + (lane & 15)],
+                                                     u2[j], 0, 0, 0);
+      if (++steps == kc4) {
+        steps = 0;
+#pragma unroll
+        for (int j = 0; j < 2; j++)
+#pragma unroll
+          for (int r = 0; r < 4; r++) u2[j][r] = mod_c(u2[j][r], p, pinv);
+      }
+    }
+  }
+  __syncthreads();                                      // every wave is done with A12
+#pragma unroll
+  for (int j = 0; j < 2; j++)
+#pragma unroll
+    for (int r = 0; r < 4; r++)
+      sB[wr * 16 + (lane >> 4) + 4 * r][wc * 32 + j * 16 + (lane & 15)] = mod_c(u2[j][r], p, pinv);
+  if (cnt != nullptr && t == 0) {
+    const unsigned prev = atomicAdd(cnt + (int64_t)z * cnt_stride + blockIdx.x, 1u);
+    s_last = prev + 1 == gridDim.y;
+  }
+  __syncthreads();
+  if (cnt != nullptr && s_last) {                       // the last reader stores U12
+    for (int e = t; e < 32 * GB_N; e += 256) {
+      const int k = e / GB_N, c = e % GB_N;
+      if (k < pb && col0 + c < N) Wz[(int64_t)(j0 + k) * ldw + r0 + col0 + c] = (int32_t)sB[k][c];
+    }
+  }
+  // A22 -= L21 U12
+  v4d acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; i++)
+#pragma unroll
+    for (int j = 0; j < 2; j++) acc[i][j] = (v4d){0.0, 0.0, 0.0, 0.0};
+  int steps = 0;
+#pragma unroll
+  for (int ks = 0; ks < GB_K; ks += 4) {
+    const int kr = ks + (lane >> 4);
+    double af[2], bf[2];
+#pragma unroll
+    for (int i = 0; i < 2; i++) af[i] = sA[kr][wr * 32 + i * 16 + (lane & 15)];
+#pragma unroll
+    for (int j = 0; j < 2; j++) bf[j] = sB[kr][wc * 32 + j * 16 + (lane & 15)];
+#pragma unroll
+    for (int i = 0; i < 2; i++)
+#pragma unroll
+      for (int j = 0; j < 2; j++)
+        acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+    if (++steps == kc4) {
+      steps = 0;
+#pragma unroll
+      for (int i = 0; i < 2; i++)
+#pragma unroll
+        for (int j = 0; j < 2; j++)
+#pragma unroll
+          for (int r = 0; r < 4; r++) acc[i][j][r] = mod_c(acc[i][j][r], p, pinv);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 2; i++)
+#pragma unroll
+    for (int j = 0; j < 2; j++)
+#pragma unroll
+      for (int r = 0; r < 4; r++) {
+        const int gr = row0 + wr * 32 + i * 16 + (lane >> 4) + 4 * r;
+        const int gc = col0 + wc * 32 + j * 16 + (lane & 15);
+        if (gr < M && gc < N)
+          Wz[(int64_t)(r0 + gr) * ldw + r0 + gc] =
+              (int32_t)mod_c((double)vc[i][j][r] - mod_c(acc[i][j][r], p, pinv), p, pinv);
+      }
 }
 
 // ------------------------------------------------------------------ K4: in-place triangular apply
@@ -1135,16 +1312,17 @@ hipError_t launch_residues(const int64_t* A, int64_t lda, int n, int ncols, int3
 
 hipError_t launch_panel(int32_t* W, int64_t ldw, int64_t slab, int n, int j0, int pb, int pbw,
                         const Modulus* mods, int32_t* piv, int64_t piv_stride, int32_t* flags,
-                        int32_t* Linv, int32_t* Uinv, int kc, int nitems, hipStream_t st) {
+                        int32_t* Linv, int32_t* Uinv, int kc, int nitems, int ncols_sw,
+                        hipStream_t st) {
   const int m = n - j0;
   // the kernel reduces every 8 columns: exact when kc >= 8 (all p < 2^26)
   if (pb > pbw || pb > m || kc < 8) return hipErrorInvalidValue;
   if (pbw == 32 && m <= 1024)
-    k_panel<32, 2><<<nitems, 512, 0, st>>>(W, ldw, slab, n, j0, pb, mods, piv, piv_stride, flags, Linv, Uinv);
+    k_panel<32, 2><<<nitems, 512, 0, st>>>(W, ldw, slab, n, j0, pb, mods, piv, piv_stride, flags, Linv, Uinv, ncols_sw);
   else if (pbw == 16 && m <= 2048)
-    k_panel<16, 4><<<nitems, 512, 0, st>>>(W, ldw, slab, n, j0, pb, mods, piv, piv_stride, flags, Linv, Uinv);
+    k_panel<16, 4><<<nitems, 512, 0, st>>>(W, ldw, slab, n, j0, pb, mods, piv, piv_stride, flags, Linv, Uinv, ncols_sw);
   else if (pbw == 8 && m <= 4096)
-    k_panel<8, 8><<<nitems, 512, 0, st>>>(W, ldw, slab, n, j0, pb, mods, piv, piv_stride, flags, Linv, Uinv);
+    k_panel<8, 8><<<nitems, 512, 0, st>>>(W, ldw, slab, n, j0, pb, mods, piv, piv_stride, flags, Linv, Uinv, ncols_sw);
   else
     return hipErrorInvalidValue;
   LAUNCH_CHECK();
@@ -1195,6 +1373,19 @@ hipError_t launch_gemm_f64(int32_t* W, int64_t slab, int64_t offC, int64_t offA,
   if (M <= 0 || N <= 0 || K <= 0) return hipSuccess;
   dim3 grid((N + GB_N - 1) / GB_N, (M + GB_M - 1) / GB_M, nitems);
   k_gemm_f64<<<grid, 256, 0, st>>>(W, slab, offC, offA, offB, ldw, M, N, K, mods, kc4);
+  LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+hipError_t launch_lu_update(int32_t* W, int64_t slab, int64_t ldw, int j0, int pb, int M, int N,
+                            const int32_t* Linv, int ldt, const Modulus* mods, int kc4,
+                            unsigned* cnt, int cnt_stride, int nitems, hipStream_t st) {
+  if (M < 0 || N <= 0 || nitems <= 0) return hipSuccess;
+  if (pb < 1 || pb > 32 || pb > ldt || kc4 < 1) return hipErrorInvalidValue;
+  dim3 grid((N + GB_N - 1) / GB_N, std::max(1, (M + GB_M - 1) / GB_M), nitems);
+  if (cnt != nullptr && (int)grid.x > cnt_stride) return hipErrorInvalidValue;
+  k_lu_update<<<grid, 256, 0, st>>>(W, slab, ldw, j0, pb, M, N, Linv, ldt, mods, kc4, cnt,
+                                    cnt_stride);
   LAUNCH_CHECK();
   return hipSuccess;
 }
