@@ -215,6 +215,11 @@ Modulus modulus_of(uint32_t p) {
 
 int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
+// Row stride of an LU workspace for rows of `w` entries: a multiple of 32
+// entries plus 32, so that it is an odd multiple of 128 bytes (power-of-two
+// strides put the rows of a tile on few memory channels).
+int64_t lu_stride(int64_t w) { return round_up(w, 64) + 32; }
+
 // Length of the zero-padded lifting vectors: the register-resident kernel
 // reads 64 EPL entries (EPL = 4, 8, 16 for n <= 256, 512, 1024).
 int64_t lift_pad(int64_t n) {
@@ -529,7 +534,7 @@ det_status residues_core(det_ctx* c, LuWs& w, const int64_t* dA, int64_t dlda, i
   LuJob J;
   J.n = n;
   J.ncols = n;
-  J.ldw = round_up(n, 32);
+  J.ldw = lu_stride(n);
   J.slab = J.ldw * n;
   const size_t per_item = (size_t)J.slab * 4 + 3 * (size_t)(2 * n) * NB_OUTER + TINV_LD * TINV_LD * 4;
   size_t cap_bytes = (size_t)8 << 30;                  // at most 8 GiB of slabs per batch
@@ -589,7 +594,7 @@ det_status inverse_mod_p(det_ctx* c, const int64_t* dA, int64_t dlda, int n, uin
   LuJob J;
   J.n = n;
   J.ncols = 2 * n;
-  J.ldw = round_up((fast ? 4 : 2) * (int64_t)n, 32);
+  J.ldw = lu_stride((fast ? 4 : 2) * (int64_t)n);
   J.slab = J.ldw * n;
   J.nitems = 1;
   J.pmax = p;
