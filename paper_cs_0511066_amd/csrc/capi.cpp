@@ -734,7 +734,7 @@ det_status lift(det_ctx* c, const int64_t* dA, int64_t dlda, int n, double amax,
       HIPCHK(detk::launch_lift_resident3(
           grid3, (const uint32_t*)c->Cu.p, (const uint32_t*)c->C1.p, (const uint32_t*)c->C2.p,
           (const int32_t*)c->Ai.p, (int64_t*)c->r.p, (uint32_t*)c->rv.p, (uint32_t*)c->xv.p, n,
-          p, pinv64, k, dig, err, c->st));
+          p, k, dig, err, c->st));
     }
     if (comb_dev) HIPCHK(detk::launch_comb_digits(dig, k, n, cvec_dev, comb_dev, c->st));
     int* herr = (int*)c->hsmall.p;

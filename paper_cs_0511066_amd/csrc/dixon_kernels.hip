@@ -812,7 +812,7 @@ template <int EPL, int RPW, int NWAVE, bool NARROW, bool SV64>
 __global__ __launch_bounds__(64 * NWAVE) void k_lift_resident3(
     const uint32_t* __restrict__ C0, const uint32_t* __restrict__ C1,
     const uint32_t* __restrict__ C2, const int32_t* __restrict__ Ai, int64_t* __restrict__ r,
-    uint32_t* rv, uint32_t* xv, int n, uint32_t p, double pinv, uint64_t pinv64, int64_t kd,
+    uint32_t* rv, uint32_t* xv, int n, uint32_t p, double pinv, int64_t kd,
     uint32_t* __restrict__ digits, int* err, unsigned spin_limit) {
   typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
   const int lane = threadIdx.x & 63;
@@ -1071,14 +1071,14 @@ hipError_t launch_hensel_f64(const int32_t* Ai, const uint32_t* C0, double* E, u
 
 hipError_t launch_lift_resident3(int grid, const uint32_t* C0, const uint32_t* C1,
                                  const uint32_t* C2, const int32_t* Ai, int64_t* r, uint32_t* rv,
-                                 uint32_t* xv, int n, uint32_t p, uint64_t pinv64, int64_t kd,
+                                 uint32_t* xv, int n, uint32_t p, int64_t kd,
                                  uint32_t* digits, int* err, hipStream_t st) {
   if (n <= 0 || kd <= 0) return hipSuccess;
   if (p >= (1u << 25)) return hipErrorInvalidValue;
   double pinv = 1.0 / (double)p;
   unsigned spin_limit = 1u << 18;     // polls of about 1 us each: ~0.3 s per wait at most
   void* args[] = {(void*)&C0, (void*)&C1, (void*)&C2, (void*)&Ai, (void*)&r, (void*)&rv,
-                  (void*)&xv, (void*)&n, (void*)&p, (void*)&pinv, (void*)&pinv64, (void*)&kd,
+                  (void*)&xv, (void*)&n, (void*)&p, (void*)&pinv, (void*)&kd,
                   (void*)&digits, (void*)&err, (void*)&spin_limit};
   const void* f = nullptr;
   if (n <= 256) f = (const void*)k_lift_resident3<4, LIFT3_RPW, LIFT3_NWAVE, LIFT3_NARROW, LIFT3_SV64>;

@@ -93,7 +93,7 @@ hipError_t launch_hensel_f64(const int32_t* Ai, const uint32_t* C0, double* E, u
 // step 0 in rv under tag 0, xv filled with all-ones words before the launch)
 hipError_t launch_lift_resident3(int grid, const uint32_t* C0, const uint32_t* C1,
                                  const uint32_t* C2, const int32_t* Ai, int64_t* r, uint32_t* rv,
-                                 uint32_t* xv, int n, uint32_t p, uint64_t pinv64, int64_t kd,
+                                 uint32_t* xv, int n, uint32_t p, int64_t kd,
                                  uint32_t* digits, int* err, hipStream_t st);
 hipError_t launch_lift_resident2(int grid, const uint32_t* C0, const uint32_t* C1,
                                  const int32_t* Ai, int64_t* r, uint32_t* rp0, uint32_t* rp1,
