@@ -14,6 +14,7 @@
 #include <atomic>
 #include <chrono>
 #include <exception>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -72,6 +73,8 @@ struct det_ctx {
   hipStream_t own2 = nullptr;    // second stream: CRA batches beside the Dixon solve
   hipStream_t st = nullptr;      // current stream of ws[0] (own or the caller's)
   hipEvent_t ev = nullptr;       // orders own2 after work queued on st
+  hipEvent_t ev_cra = nullptr;   // the same for the first CRA batch (enqueued by a second thread)
+  std::mutex mu;                 // the error text, the budget count, the kernel timing state
   std::string err;
   LuWs ws[2];
   DevBuf Adev, norms, amax, Cu, Ai, r, rp, x, digits, comb, cvec, sync, C1, E, rp1, x1, C2, Ed,
@@ -94,7 +97,10 @@ struct det_ctx {
 namespace {
 
 det_status fail(det_ctx* c, det_status s, const std::string& msg) {
-  if (c) c->err = msg;
+  if (c) {
+    std::lock_guard<std::mutex> lk(c->mu);
+    c->err = msg;
+  }
   return s;
 }
 
@@ -115,12 +121,20 @@ det_status fail(det_ctx* c, det_status s, const std::string& msg) {
 det_status ensure(det_ctx* c, DevBuf& b, size_t bytes, hipStream_t st) {
   if (bytes == 0) bytes = 16;
   if (b.cap >= bytes) return DET_OK;
-  if (c->budget && c->held - b.cap + bytes > c->budget)
-    return fail(c, DET_E_NOMEM, "device workspace would exceed the context's HBM budget");
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (c->budget && c->held - b.cap + bytes > c->budget) {
+      c->err = "device workspace would exceed the context's HBM budget";
+      return DET_E_NOMEM;
+    }
+  }
   HIPCHK(hipStreamSynchronize(st));
   if (b.p) {
     HIPCHK(hipFree(b.p));
-    c->held -= b.cap;
+    {
+      std::lock_guard<std::mutex> lk(c->mu);
+      c->held -= b.cap;
+    }
     b.p = nullptr;
     b.cap = 0;
   }
@@ -131,6 +145,7 @@ det_status ensure(det_ctx* c, DevBuf& b, size_t bytes, hipStream_t st) {
     return fail(c, DET_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
   }
   b.cap = bytes;
+  std::lock_guard<std::mutex> lk(c->mu);
   c->held += bytes;
   return DET_OK;
 }
@@ -164,6 +179,7 @@ struct ProfScope {
   hipEvent_t e1 = nullptr;
   ProfScope(det_ctx* ctx, int kind, double bytes, double ops, hipStream_t stream)
       : c(ctx), st(stream) {
+    std::lock_guard<std::mutex> lk(c->mu);
     if (c->prof_kind != kind) return;
     hipEvent_t e0 = take(), e = take();
     if (!e0 || !e) return;
@@ -869,6 +885,7 @@ det_status det_ctx_create(int device, size_t hbm_budget_bytes, det_ctx** out) {
       hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking) != hipSuccess ||
       hipStreamCreateWithFlags(&c->own2, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_cra, hipEventDisableTiming) != hipSuccess ||
       detk::configure_kernels() != hipSuccess) {
     (void)hipGetLastError();
     if (c->own) (void)hipStreamDestroy(c->own);
@@ -910,6 +927,7 @@ void det_ctx_destroy(det_ctx* c) {
   }
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   if (c->ev) (void)hipEventDestroy(c->ev);
+  if (c->ev_cra) (void)hipEventDestroy(c->ev_cra);
   if (c->own) (void)hipStreamDestroy(c->own);
   if (c->own2) (void)hipStreamDestroy(c->own2);
   delete c;
@@ -998,6 +1016,7 @@ det_status det_profile_read(det_ctx* c, int64_t* launches, double* total_ms, dou
   if (!c) return DET_E_INVALID;
   HIPCHK(hipStreamSynchronize(c->st));
   HIPCHK(hipStreamSynchronize(c->own2));
+  std::lock_guard<std::mutex> lk(c->mu);
   double ms = 0;
   for (auto& pr : c->prof_pending) {
     float t = 0;
@@ -1145,9 +1164,28 @@ det_status det_introspective(det_ctx* c, const int64_t* A, int64_t n, int64_t ld
     for (auto& q : ps1) q = samp.next();
     TRY(ensure_pinned(c, (size_t)batch1 + 64));
     uint32_t* hres1 = c->hres + 64;                  // (c->hres[0..63]: the inverse's read-backs)
-    HIPCHK(hipEventRecord(c->ev, c->st));              // A (and its bounds) are ready on st
-    HIPCHK(hipStreamWaitEvent(c->own2, c->ev, 0));
-    TRY(residues_core(c, c->ws[1], dA, dlda, (int)n, ps1.data(), batch1, hres1, o.path, false));
+    HIPCHK(hipEventRecord(c->ev_cra, c->st));          // A (and its bounds) are ready on st
+    HIPCHK(hipStreamWaitEvent(c->own2, c->ev_cra, 0));
+    // A second host thread enqueues the batch (some seventy launches), so that
+    // the Dixon solve's launches start at once.  It uses only ws[1], own2 and
+    // hres1; it is joined before anything waits for own2.
+    det_status cra_st = DET_OK;
+    std::thread cra_thread([&] {
+      try {
+        (void)hipSetDevice(c->device);
+        cra_st = residues_core(c, c->ws[1], dA, dlda, (int)n, ps1.data(), batch1, hres1, o.path,
+                               false);
+      } catch (...) {
+        cra_st = DET_E_NOMEM;
+      }
+    });
+    struct Joiner {
+      std::thread& t;
+      void join() {
+        if (t.joinable()) t.join();
+      }
+      ~Joiner() { join(); }
+    } cra_join{cra_thread};
 
     // ---------------- LIF: s~_n from Dixon solvings (Section 2.2)
     BigInt K = BigInt::from_i64(1);
@@ -1196,6 +1234,8 @@ det_status det_introspective(det_ctx* c, const int64_t* A, int64_t n, int64_t ld
         memcpy(hcv, cv.data(), n * sizeof(uint32_t));
         HIPCHK(hipMemsetAsync(c->cvec.p, 0, lift_pad(n) * sizeof(uint32_t), c->st));
         HIPCHK(hipMemcpyAsync(c->cvec.p, hcv, n * sizeof(uint32_t), hipMemcpyHostToDevice, c->st));
+        cra_join.join();                               // all of the batch is on own2
+        TRY(cra_st);
         TRY(lift(c, dA, dlda, (int)n, bd.amax, b.data(), p, k, nullptr, (const uint32_t*)c->cvec.p,
                  (uint64_t*)c->comb.p, true));
         const uint64_t* comb = (const uint64_t*)((char*)c->hstage.p + sl.comb);
@@ -1226,6 +1266,8 @@ det_status det_introspective(det_ctx* c, const int64_t* A, int64_t n, int64_t ld
     if (kET < 0) kET = INT64_MAX;                    // lemma not applicable: certify only
     dethost::CrtState crt;
     bool done = false;
+    cra_join.join();
+    TRY(cra_st);
     HIPCHK(hipStreamSynchronize(c->own2));
     std::vector<uint32_t> ps(ps1), rs(hres1, hres1 + batch1);
     rep.et_rounds = 1;
