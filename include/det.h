@@ -101,6 +101,21 @@ det_status det_mod_primes(det_ctx *ctx, const int64_t *A, int64_t n, int64_t lda
 det_status dixon_lift(det_ctx *ctx, const int64_t *A, int64_t n, int64_t lda, const int64_t *b,
                       uint32_t p, int64_t k, uint32_t *digits);
 
+/*
+ * Dixon lifting of m right-hand sides at once (the system A X = B with
+ * several right-hand sides, Section 3.2: the lifting step becomes a product
+ * with an n x m matrix):  digits[(h*k + i)*n + j] = x_{h,i}[j], the i-th
+ * base-p digit of A^{-1} b_h, for h < m, i < k, j < n -- exactly what
+ * dixon_lift returns for b_h alone.  B: host array, n x m int64 row-major
+ * (B[j*m + h]), each |B_jh| < 2^62 / (n + 1); digits: host array of m*k*n
+ * entries, owned by the caller.  In the FP64 three-digit form two right-hand
+ * sides share one launch (the planes of A^{-1}, the rows of A and every
+ * exchange between workgroups); other forms lift them one after the other.
+ * Errors as dixon_lift; m = 0 returns DET_OK.
+ */
+det_status dixon_lift_multi(det_ctx *ctx, const int64_t *A, int64_t n, int64_t lda,
+                            const int64_t *B, int64_t m, uint32_t p, int64_t k, uint32_t *digits);
+
 typedef struct {
   double log2_inv_eps;   /* early termination: failure probability < 2^-log2_inv_eps (default 64) */
   int certify;           /* 1: ignore early termination; reconstruct det/s_n up to the Hadamard bound */

@@ -80,6 +80,8 @@ _sig("det_mod_primes", c_int, [ctypes.c_void_p, ctypes.c_void_p, c_i64, c_i64, P
                                P(c_u32), c_int])
 _sig("dixon_lift", c_int, [ctypes.c_void_p, ctypes.c_void_p, c_i64, c_i64, P(c_i64), c_u32, c_i64,
                            P(c_u32)])
+_sig("dixon_lift_multi", c_int, [ctypes.c_void_p, ctypes.c_void_p, c_i64, c_i64, P(c_i64), c_i64,
+                                 c_u32, c_i64, P(c_u32)])
 _sig("det_introspective", c_int, [ctypes.c_void_p, ctypes.c_void_p, c_i64, c_i64, P(det_opts),
                                   P(c_int), P(c_u32), c_i64, P(c_i64), P(det_report)])
 _sig("det_batch", c_int, [ctypes.c_void_p, c_i64, P(ctypes.c_void_p), P(c_i64), P(c_i64),
@@ -98,7 +100,7 @@ _sig("det_host_bigint", c_int, [c_int, c_int, P(c_u32), c_i64, c_int, P(c_u32), 
                                 P(c_u32), c_i64, P(c_i64)])
 
 EXPORTED = ["det_ctx_create", "det_ctx_destroy", "det_ctx_set_stream", "det_status_str",
-            "det_last_error", "det_opts_default", "det_mod_primes", "dixon_lift",
+            "det_last_error", "det_opts_default", "det_mod_primes", "dixon_lift", "dixon_lift_multi",
             "det_introspective", "det_batch", "det_profile_select", "det_profile_read", "det_host_is_prime", "det_host_sample_primes",
             "det_host_hadamard_log2", "det_host_et_run_length", "det_host_crt",
             "det_host_ratrecon", "det_host_bigint"]
@@ -215,6 +217,19 @@ class Context:
             raise ValueError("b must have n entries")
         out = np.zeros((k, n), dtype=np.uint32)
         self._check(_lib.dixon_lift(self._h, ptr, n, lda, _i64p(bb), p, k, _u32p(out)))
+        del keep
+        return out
+
+    def dixon_lift_multi(self, A, B, p: int, k: int) -> np.ndarray:
+        """Digits of A^{-1} b_h mod p^k for every column b_h of the n x m
+        matrix B (dixon_lift_multi): an m x k x n array."""
+        ptr, n, lda, keep = _matrix_arg(A)
+        BB = np.ascontiguousarray(np.asarray(B, dtype=np.int64))
+        if BB.ndim != 2 or BB.shape[0] != n:
+            raise ValueError("B must be n x m")
+        m = BB.shape[1]
+        out = np.zeros((m, k, n), dtype=np.uint32)
+        self._check(_lib.dixon_lift_multi(self._h, ptr, n, lda, _i64p(BB), m, p, k, _u32p(out)))
         del keep
         return out
 

@@ -644,8 +644,9 @@ det_status inverse_mod_p(det_ctx* c, const int64_t* dA, int64_t dlda, int n, uin
 }
 
 // Layout of the pinned staging buffer c->hstage for a lifting of order n
-// with k digits: r (int64), digit 0 of r, three balanced digits a row (four
-// words), digit 1 of r, the combination vector, then k combination sums read
+// with k digits: r (int64, up to LIFT3_MAX_RHS right-hand sides), digit 0 of
+// r, three balanced digits a record (four words, up to LIFT3_MAX_RHS records
+// a row), digit 1 of r, the combination vector, then k combination sums read
 // back.
 struct Stage {
   size_t r, rp0, d3, rp1, cvec, comb, total;
@@ -653,9 +654,9 @@ struct Stage {
 Stage stage_layout(int64_t n, int64_t k) {
   Stage s;
   s.r = 0;
-  s.rp0 = s.r + 8 * (size_t)n;
+  s.rp0 = s.r + 8 * (size_t)n * detk::LIFT3_MAX_RHS;
   s.d3 = s.rp0 + 4 * (size_t)n;
-  s.rp1 = s.d3 + 16 * (size_t)n;
+  s.rp1 = s.d3 + 16 * (size_t)n * detk::LIFT3_MAX_RHS;
   s.cvec = s.rp1 + 4 * (size_t)n;
   s.comb = (s.cvec + 4 * (size_t)n + 63) & ~(size_t)63;
   s.total = s.comb + 8 * (size_t)k;
@@ -667,6 +668,92 @@ bool lift3_applies(int n, double amax, uint32_t p) {
   return p < (1u << 25) && (double)n * std::max(amax, 1.0) * (double)p < ldexp(1.0, 53);
 }
 
+// The three-digit FP64 lifting (modulo p^3) of m right-hand sides B (n x m,
+// row-major) from C0 = A^{-1} mod p in c->Cu and A packed in c->Ai, on c->st:
+// the Hensel planes once, then one cooperative launch per LIFT3_MAX_RHS
+// right-hand sides (they share the planes, the rows of A and every exchange).
+// digits_dev: m x k x n (may be null); comb_dev: m x k sums of cvec . x_i
+// (may be null).  With after_own2 the launches first wait for own2.
+det_status lift3_multi(det_ctx* c, int grid3, int n, const int64_t* B, int m, uint32_t p,
+                       int64_t k, uint32_t* digits_dev, const uint32_t* cvec_dev,
+                       uint64_t* comb_dev, bool after_own2) {
+  constexpr int MR = detk::LIFT3_MAX_RHS;
+  const double nn = (double)n * n;
+  TRY(ensure(c, c->C1, (size_t)n * n * sizeof(uint32_t)));
+  TRY(ensure(c, c->C2, (size_t)n * n * sizeof(uint32_t)));
+  TRY(ensure(c, c->Ed, (size_t)n * n * sizeof(double)));
+  TRY(ensure(c, c->r, (size_t)n * MR * sizeof(int64_t)));
+  TRY(ensure(c, c->rv, (size_t)n * MR * 4 * sizeof(uint32_t)));
+  TRY(ensure(c, c->xv, (size_t)n * MR * 4 * sizeof(uint32_t)));
+  TRY(ensure(c, c->sync, 64));
+  const Stage sl = stage_layout(n, 0);
+  TRY(ensure_pin(c, c->hstage, sl.total, c->st));
+  TRY(ensure_pin(c, c->hsmall, 64, c->st));
+  HIPCHK(detk::launch_hensel_f64((const int32_t*)c->Ai.p, (const uint32_t*)c->Cu.p,
+                                 (double*)c->Ed.p, (uint32_t*)c->C1.p, (uint32_t*)c->C2.p, n, p,
+                                 c->st));
+  if (after_own2) {
+    HIPCHK(hipEventRecord(c->ev, c->own2));
+    HIPCHK(hipStreamWaitEvent(c->st, c->ev, 0));
+  }
+  // the combinations are formed after the lifting, from its digits
+  uint32_t* dig = digits_dev;
+  if (!dig && comb_dev) {
+    TRY(ensure(c, c->digits, (size_t)m * k * n * sizeof(uint32_t)));
+    dig = (uint32_t*)c->digits.p;
+  }
+  int* err = (int*)((char*)c->sync.p + 32);
+  int* herr = (int*)c->hsmall.p;
+  char* hs = (char*)c->hstage.p;
+  for (int h0 = 0; h0 < m; h0 += MR) {
+    const int mm = std::min(MR, m - h0);
+    if (h0 > 0) HIPCHK(hipStreamSynchronize(c->st));    // the staging of the last chunk is read
+    // r_0 = b and its balanced digits mod p^3 (each centring carried into the
+    // next digit), one record of 25-bit fields under tag 0 (step 0) per row
+    // and right-hand side
+    int64_t* hb = (int64_t*)(hs + sl.r);
+    uint32_t* d3 = (uint32_t*)(hs + sl.d3);
+    for (int j = 0; j < n; j++)
+      for (int hh = 0; hh < mm; hh++) {
+        int64_t v = B[(size_t)j * m + h0 + hh];
+        hb[(size_t)j * mm + hh] = v;
+        uint32_t* rec = d3 + ((size_t)j * mm + hh) * 4;
+        for (int q = 0; q < 3; q++) {
+          int64_t md = v % (int64_t)p;
+          if (md < 0) md += p;
+          if (md > (int64_t)(p - 1) / 2) md -= p;
+          rec[q] = (uint32_t)(int32_t)md & detk::LIFT3_DIGIT_MASK;
+          v = (v - md) / (int64_t)p;                   // exact
+        }
+        rec[3] = 0;
+      }
+    const size_t recs = (size_t)n * mm;
+    HIPCHK(hipMemcpyAsync(c->r.p, hb, recs * sizeof(int64_t), hipMemcpyHostToDevice, c->st));
+    HIPCHK(hipMemcpyAsync(c->rv.p, d3, recs * 4 * sizeof(uint32_t), hipMemcpyHostToDevice,
+                          c->st));
+    // xv: all-ones words (tag 127, not yet written by any step)
+    HIPCHK(hipMemsetAsync(c->xv.p, 0xFF, recs * 4 * sizeof(uint32_t), c->st));
+    HIPCHK(hipMemsetAsync(c->sync.p, 0, 64, c->st));
+    {
+      // algorithmic bytes per digit and right-hand side: C and A as the
+      // one-launch-per-phase form reads them (8 n^2) and four n-vectors
+      ProfScope ps(c, DET_KERNEL_LIFT, (8.0 * nn + 40.0 * n) * k * mm, 4.0 * nn * k * mm, c->st);
+      HIPCHK(detk::launch_lift_resident3(
+          grid3, (const uint32_t*)c->Cu.p, (const uint32_t*)c->C1.p, (const uint32_t*)c->C2.p,
+          (const int32_t*)c->Ai.p, (int64_t*)c->r.p, (uint32_t*)c->rv.p, (uint32_t*)c->xv.p, n,
+          mm, p, k, dig ? dig + (size_t)h0 * k * n : nullptr, err, c->st));
+    }
+    if (comb_dev)
+      for (int hh = 0; hh < mm; hh++)
+        HIPCHK(detk::launch_comb_digits(dig + (size_t)(h0 + hh) * k * n, k, n, cvec_dev,
+                                        comb_dev + (size_t)(h0 + hh) * k, c->st));
+    HIPCHK(hipMemcpyAsync(herr, err, sizeof(int), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    if (*herr) return fail(c, DET_E_DEVICE, "lifting: a wait for another workgroup's digits timed out");
+  }
+  return DET_OK;
+}
+
 // k Dixon steps from r_0 = b on c->st.  digits_dev: k x n output (may be null
 // when only the combinations are wanted); comb_dev: k sums of cvec . x_i (may
 // be null).
@@ -676,16 +763,19 @@ bool lift3_applies(int n, double amax, uint32_t p) {
 det_status lift(det_ctx* c, const int64_t* dA, int64_t dlda, int n, double amax, const int64_t* b,
                 uint32_t p, int64_t k, uint32_t* digits_dev, const uint32_t* cvec_dev,
                 uint64_t* comb_dev, bool after_own2 = false) {
+  TRY(ensure(c, c->Ai, (size_t)n * n * sizeof(int32_t)));
+  HIPCHK(detk::launch_pack_i32(dA, dlda, n, (int32_t*)c->Ai.p, c->st));
+  const int grid3 = c->lift_mode == 0 && lift3_applies(n, amax, p) ? detk::lift3_grid(c->device, n) : 0;
+  if (grid3 > 0)      // lifting modulo p^3 in FP64: Hensel planes, then three digits a step
+    return lift3_multi(c, grid3, n, b, 1, p, k, digits_dev, cvec_dev, comb_dev, after_own2);
   // rp and x are padded with zeros to lift_pad(n) entries (the
   // register-resident kernel loads 64 EPL entries without bounds tests)
   const int64_t npad = lift_pad(n);
-  TRY(ensure(c, c->Ai, (size_t)n * n * sizeof(int32_t)));
   TRY(ensure(c, c->r, (size_t)n * sizeof(int64_t)));
   TRY(ensure(c, c->rp, (size_t)npad * sizeof(uint32_t)));
   TRY(ensure(c, c->x, (size_t)npad * sizeof(uint32_t)));
   HIPCHK(hipMemsetAsync(c->rp.p, 0, npad * sizeof(uint32_t), c->st));
   HIPCHK(hipMemsetAsync(c->x.p, 0, npad * sizeof(uint32_t), c->st));
-  HIPCHK(detk::launch_pack_i32(dA, dlda, n, (int32_t*)c->Ai.p, c->st));
   const Stage sl = stage_layout(n, 0);
   TRY(ensure_pin(c, c->hstage, sl.total, c->st));
   TRY(ensure_pin(c, c->hsmall, 64, c->st));
@@ -701,64 +791,6 @@ det_status lift(det_ctx* c, const int64_t* dA, int64_t dlda, int n, double amax,
   HIPCHK(hipMemcpyAsync(c->rp.p, rp0, n * sizeof(uint32_t), hipMemcpyHostToDevice, c->st));
   const uint64_t pinv64 = inv_mod_2_64(p);
   const double nn = (double)n * n;
-  const int grid3 = c->lift_mode == 0 && lift3_applies(n, amax, p) ? detk::lift3_grid(c->device, n) : 0;
-  if (grid3 > 0) {
-    // lifting modulo p^3 in FP64: Hensel planes, then three digits a step
-    TRY(ensure(c, c->C1, (size_t)n * n * sizeof(uint32_t)));
-    TRY(ensure(c, c->C2, (size_t)n * n * sizeof(uint32_t)));
-    TRY(ensure(c, c->Ed, (size_t)n * n * sizeof(double)));
-    TRY(ensure(c, c->rv, (size_t)n * 4 * sizeof(uint32_t)));
-    TRY(ensure(c, c->xv, (size_t)n * 4 * sizeof(uint32_t)));
-    TRY(ensure(c, c->sync, 64));
-    // xv: all-ones words (tag 127, not yet written by any step)
-    HIPCHK(hipMemsetAsync(c->xv.p, 0xFF, (size_t)n * 4 * sizeof(uint32_t), c->st));
-    HIPCHK(hipMemsetAsync(c->sync.p, 0, 64, c->st));
-    // balanced digits of b mod p^3 (each centring carried into the next
-    // digit), row by row as 25-bit fields under tag 0 (step 0)
-    uint32_t* d3 = (uint32_t*)(hs + sl.d3);
-    for (int j = 0; j < n; j++) {
-      int64_t v = b[j];
-      for (int q = 0; q < 3; q++) {
-        int64_t m = v % (int64_t)p;
-        if (m < 0) m += p;
-        if (m > (int64_t)(p - 1) / 2) m -= p;
-        d3[(size_t)4 * j + q] = (uint32_t)(int32_t)m & detk::LIFT3_DIGIT_MASK;
-        v = (v - m) / (int64_t)p;                  // exact
-      }
-      d3[(size_t)4 * j + 3] = 0;
-    }
-    HIPCHK(hipMemcpyAsync(c->rv.p, d3, (size_t)n * 4 * sizeof(uint32_t), hipMemcpyHostToDevice,
-                          c->st));
-    HIPCHK(detk::launch_hensel_f64((const int32_t*)c->Ai.p, (const uint32_t*)c->Cu.p,
-                                   (double*)c->Ed.p, (uint32_t*)c->C1.p, (uint32_t*)c->C2.p, n, p,
-                                   c->st));
-    if (after_own2) {
-      HIPCHK(hipEventRecord(c->ev, c->own2));
-      HIPCHK(hipStreamWaitEvent(c->st, c->ev, 0));
-    }
-    int* err = (int*)((char*)c->sync.p + 32);
-    // the combinations are formed after the lifting, from its digits
-    uint32_t* dig = digits_dev;
-    if (!dig && comb_dev) {
-      TRY(ensure(c, c->digits, (size_t)k * n * sizeof(uint32_t)));
-      dig = (uint32_t*)c->digits.p;
-    }
-    {
-      // algorithmic bytes per digit: C and A as the one-launch-per-phase form
-      // reads them (8 n^2) and four n-vectors
-      ProfScope ps(c, DET_KERNEL_LIFT, (8.0 * nn + 40.0 * n) * k, 4.0 * nn * k, c->st);
-      HIPCHK(detk::launch_lift_resident3(
-          grid3, (const uint32_t*)c->Cu.p, (const uint32_t*)c->C1.p, (const uint32_t*)c->C2.p,
-          (const int32_t*)c->Ai.p, (int64_t*)c->r.p, (uint32_t*)c->rv.p, (uint32_t*)c->xv.p, n,
-          p, k, dig, err, c->st));
-    }
-    if (comb_dev) HIPCHK(detk::launch_comb_digits(dig, k, n, cvec_dev, comb_dev, c->st));
-    int* herr = (int*)c->hsmall.p;
-    HIPCHK(hipMemcpyAsync(herr, err, sizeof(int), hipMemcpyDeviceToHost, c->st));
-    HIPCHK(hipStreamSynchronize(c->st));
-    if (*herr) return fail(c, DET_E_DEVICE, "lifting: a wait for another workgroup's digits timed out");
-    return DET_OK;
-  }
   const int grid = c->lift_mode != 1 ? detk::lift_persistent_grid(c->device, n) : 0;
   if (grid > 0) {
     // lifting modulo p^2: Hensel step for the inverse, then two digits a step
@@ -1097,6 +1129,58 @@ det_status dixon_lift(det_ctx* c, const int64_t* A, int64_t n, int64_t lda, cons
     TRY(lift(c, dA, dlda, (int)n, bd.amax, b, p, k, (uint32_t*)c->digits.p, nullptr, nullptr));
     HIPCHK(hipMemcpyAsync(digits, c->digits.p, (size_t)k * n * sizeof(uint32_t),
                           hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    return DET_OK;
+  } catch (const std::exception& e) {
+    return fail(c, DET_E_NOMEM, e.what());
+  } catch (...) {
+    return fail(c, DET_E_INVALID, "unexpected error");
+  }
+}
+
+det_status dixon_lift_multi(det_ctx* c, const int64_t* A, int64_t n, int64_t lda,
+                            const int64_t* B, int64_t m, uint32_t p, int64_t k, uint32_t* digits) {
+  if (!c) return DET_E_INVALID;
+  try {
+    if (n < 0 || k < 0 || m < 0 || (n > 0 && (!A || lda < n)) || (n > 0 && m > 0 && !B) ||
+        (n > 0 && k > 0 && m > 0 && !digits))
+      return fail(c, DET_E_INVALID, "invalid argument");
+    if (n > MAX_N) return fail(c, DET_E_INVALID, "n exceeds 4096");
+    if (m > (1 << 20)) return fail(c, DET_E_INVALID, "m too large");
+    if (p <= 256 || p >= (1u << 26)) return fail(c, DET_E_PRIME_RANGE, "p must lie in (2^8, 2^26)");
+    if (!dethost::is_prime_u32(p)) return fail(c, DET_E_NOT_PRIME, "p is not prime");
+    if (n == 0 || k == 0 || m == 0) return DET_OK;
+    const double blim = ldexp(1.0, 62) / (double)(n + 1);
+    for (int64_t e = 0; e < n * m; e++)
+      if (fabs((double)B[e]) >= blim) return fail(c, DET_E_OVERFLOW, "|B_jh| too large");
+    HIPCHK(hipSetDevice(c->device));
+    const int64_t* dA;
+    int64_t dlda;
+    bool on_dev;
+    TRY(stage_matrix(c, A, n, lda, &dA, &dlda, &on_dev));
+    dethost::Bounds bd;
+    TRY(matrix_bounds(c, A, lda, on_dev, dA, dlda, n, &bd));
+    if ((double)n * bd.amax * (double)p >= ldexp(1.0, 62))
+      return fail(c, DET_E_OVERFLOW, "n ||A|| p >= 2^62");
+    TRY(inverse_mod_p(c, dA, dlda, (int)n, p));
+    TRY(ensure(c, c->digits, (size_t)m * k * n * sizeof(uint32_t)));
+    uint32_t* dig = (uint32_t*)c->digits.p;
+    const int grid3 =
+        c->lift_mode == 0 && lift3_applies((int)n, bd.amax, p) ? detk::lift3_grid(c->device, (int)n) : 0;
+    if (grid3 > 0) {
+      TRY(ensure(c, c->Ai, (size_t)n * n * sizeof(int32_t)));
+      HIPCHK(detk::launch_pack_i32(dA, dlda, (int)n, (int32_t*)c->Ai.p, c->st));
+      TRY(lift3_multi(c, grid3, (int)n, B, (int)m, p, k, dig, nullptr, nullptr, false));
+    } else {
+      std::vector<int64_t> bh(n);
+      for (int64_t h = 0; h < m; h++) {
+        for (int64_t j = 0; j < n; j++) bh[j] = B[j * m + h];
+        TRY(lift(c, dA, dlda, (int)n, bd.amax, bh.data(), p, k, dig + (size_t)h * k * n,
+                 nullptr, nullptr));
+      }
+    }
+    HIPCHK(hipMemcpyAsync(digits, dig, (size_t)m * k * n * sizeof(uint32_t), hipMemcpyDeviceToHost,
+                          c->st));
     HIPCHK(hipStreamSynchronize(c->st));
     return DET_OK;
   } catch (const std::exception& e) {

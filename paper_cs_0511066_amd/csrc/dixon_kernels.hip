@@ -567,7 +567,6 @@ hipError_t launch_lift_resident2(int grid, const uint32_t* C0, const uint32_t* C
 // Shape of the three-plane lifting: LIFT3_NWAVE waves of LIFT3_RPW rows per
 // workgroup, one workgroup per LIFT3_RPW * LIFT3_NWAVE rows.
 constexpr int LIFT3_RPW = 1, LIFT3_NWAVE = 8;
-constexpr bool LIFT3_NARROW = false, LIFT3_SV64 = false;
 static int lift3_grid_size(int n) {
   return (n + LIFT3_RPW * LIFT3_NWAVE - 1) / (LIFT3_RPW * LIFT3_NWAVE);
 }
@@ -779,8 +778,9 @@ __device__ __forceinline__ int32_t centred_i32(uint32_t u, uint32_t p) {
 // rows) owns rows g RG + w RPW + i (i < RPW), lane l columns l + 64 e
 // (e < EPL).  Vectors passed between workgroups: the three digits of r mod
 // p^3, balanced (|digit| <= (p-1)/2, r = w0 + p w1 + p^2 w2 mod p^3), and the
-// three digits of x in [0, p), row by row in 16 bytes (rv, xv: n x 4 words,
-// the fourth word holding only the tag).
+// three digits of x in [0, p), row by row in 16 bytes per right-hand side
+// (rv, xv: n x NRHS x 4 words, the fourth word holding only the tag; NRHS
+// right-hand sides share the planes, the rows of A and the exchanges).
 // Phase X, per lane over its EPL columns (w_q = centred digit q of r):
 //   S0 = sum c0 w0, S1 = sum c0 w1 + c1 w0, S2 = sum c0 w2 + c1 w1 + c2 w0,
 // each partial sum of 16 products below 2^52; carries are taken lane by lane
@@ -808,7 +808,7 @@ __device__ __forceinline__ int32_t centred_i32(uint32_t u, uint32_t p) {
 // longer to become visible than one contiguous write.  A wait that exceeds
 // spin_limit polls sets *err; after that every wait gives up within 64
 // polls, so all waves exit.
-template <int EPL, int RPW, int NWAVE, bool NARROW, bool SV64>
+template <int EPL, int RPW, int NWAVE, int NRHS>
 __global__ __launch_bounds__(64 * NWAVE) void k_lift_resident3(
     const uint32_t* __restrict__ C0, const uint32_t* __restrict__ C1,
     const uint32_t* __restrict__ C2, const int32_t* __restrict__ Ai, int64_t* __restrict__ r,
@@ -823,46 +823,54 @@ __global__ __launch_bounds__(64 * NWAVE) void k_lift_resident3(
   constexpr int NC = 64 * EPL;                          // columns (at least n)
   constexpr int NJ = (EPL + NWAVE - 1) / NWAVE;         // rows staged per thread
   const int row0 = blockIdx.x * RG;
-  // the vector a phase reads, staged once per workgroup (digit t of row j at
-  // [t][j], FP64 or int32: every wave reads all of it, so its width sets the
-  // LDS traffic), one buffer per phase so that a phase may stage while slower
-  // waves still read the other phase's buffer
-  typedef typename std::conditional<SV64, double, int32_t>::type sv_t;
-  __shared__ sv_t sV[2][3][NC];
-  // the workgroup's rows of the vector a phase writes, gathered for one store
-  __shared__ uint32_t sOut[RG * 4];
+  // the vectors a phase reads, staged once per workgroup as int32 (digit t of
+  // row j for right-hand side h at [h][t][j]: every wave reads all of it), one
+  // buffer per phase so that a phase may stage while slower waves still read
+  // the other phase's buffer
+  __shared__ int32_t sV[2][NRHS][3][NC];
+  // the workgroup's records of the vectors a phase writes, gathered for one store
+  __shared__ uint32_t sOut[RG * NRHS * 4];
   // 16-byte loads at the device-coherent level: buffer loads with the sc1
-  // cache policy (offsets past 16 n bytes read as zero)
-  const __amdgpu_buffer_rsrc_t rsr = __builtin_amdgcn_make_buffer_rsrc(rv, 0, 16 * n, BUF_RSRC_WORD3);
-  const __amdgpu_buffer_rsrc_t rsx = __builtin_amdgcn_make_buffer_rsrc(xv, 0, 16 * n, BUF_RSRC_WORD3);
+  // cache policy (offsets past the vectors read as zero)
+  const int nbytes = 16 * n * NRHS;
+  const __amdgpu_buffer_rsrc_t rsr = __builtin_amdgcn_make_buffer_rsrc(rv, 0, nbytes, BUF_RSRC_WORD3);
+  const __amdgpu_buffer_rsrc_t rsx = __builtin_amdgcn_make_buffer_rsrc(xv, 0, nbytes, BUF_RSRC_WORD3);
   bool gave_up = false;
-  // Staging of one vector: every thread reads its NJ rows and polls again
-  // those whose tag is still old; after spin_limit polls it sets *err (or
-  // gives up on finding it set).
-  auto stage3 = [&](sv_t (*s)[NC], __amdgpu_buffer_rsrc_t src, uint32_t tag, bool sgn) {
-    u32x4 a[NJ];
-    bool want[NJ];
+  // Staging of one set of vectors: every thread reads the records of its NJ
+  // rows and polls again those whose tag is still old; after spin_limit polls
+  // it sets *err (or gives up on finding it set).
+  auto stage3 = [&](int32_t (*s)[3][NC], __amdgpu_buffer_rsrc_t src, uint32_t tag, bool sgn) {
+    u32x4 a[NJ][NRHS];
+    bool want[NJ][NRHS];
 #pragma unroll
     for (int q = 0; q < NJ; q++) {
       const int j = threadIdx.x + 64 * NWAVE * q;
-      want[q] = j < n && j < NC;
-      a[q] = u32x4{0, 0, 0, 0};
+#pragma unroll
+      for (int h = 0; h < NRHS; h++) {
+        want[q][h] = j < n && j < NC;
+        a[q][h] = u32x4{0, 0, 0, 0};
+      }
     }
     unsigned spins = 0;
     for (;;) {
 #pragma unroll
-      for (int q = 0; q < NJ; q++) {
-        int off = 16 * (threadIdx.x + 64 * NWAVE * q);
-        asm volatile("" : "+v"(off));        // a fresh load on every poll
-        if (want[q]) a[q] = __builtin_amdgcn_raw_buffer_load_b128(src, off, 0, BUF_SC1);
-      }
+      for (int q = 0; q < NJ; q++)
+#pragma unroll
+        for (int h = 0; h < NRHS; h++) {
+          int off = 16 * ((threadIdx.x + 64 * NWAVE * q) * NRHS + h);
+          asm volatile("" : "+v"(off));      // a fresh load on every poll
+          if (want[q][h]) a[q][h] = __builtin_amdgcn_raw_buffer_load_b128(src, off, 0, BUF_SC1);
+        }
       bool pending = false;
 #pragma unroll
-      for (int q = 0; q < NJ; q++) {
-        if (want[q] && (a[q].x >> 25) == tag && (a[q].y >> 25) == tag && (a[q].z >> 25) == tag)
-          want[q] = false;
-        pending |= want[q];
-      }
+      for (int q = 0; q < NJ; q++)
+#pragma unroll
+        for (int h = 0; h < NRHS; h++) {
+          if (want[q][h] && (a[q][h].x >> 25) == tag && (a[q][h].y >> 25) == tag &&
+              (a[q][h].z >> 25) == tag)
+            want[q][h] = false;
+          pending |= want[q][h];
+        }
       if (!pending || gave_up) break;
       if ((++spins & 63) == 0) {
         if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
@@ -881,31 +889,31 @@ __global__ __launch_bounds__(64 * NWAVE) void k_lift_resident3(
     for (int q = 0; q < NJ; q++) {
       const int j = threadIdx.x + 64 * NWAVE * q;
       if (j < NC) {
-        // r digits: sign-extend the 25-bit field; x digits: the field itself
-        s[0][j] = (sv_t)(sgn ? (int32_t)(a[q].x << 7) >> 7 : (int32_t)(a[q].x & DIG));
-        s[1][j] = (sv_t)(sgn ? (int32_t)(a[q].y << 7) >> 7 : (int32_t)(a[q].y & DIG));
-        s[2][j] = (sv_t)(sgn ? (int32_t)(a[q].z << 7) >> 7 : (int32_t)(a[q].z & DIG));
+#pragma unroll
+        for (int h = 0; h < NRHS; h++) {
+          // r digits: sign-extend the 25-bit field; x digits: the field itself
+          s[h][0][j] = sgn ? (int32_t)(a[q][h].x << 7) >> 7 : (int32_t)(a[q][h].x & DIG);
+          s[h][1][j] = sgn ? (int32_t)(a[q][h].y << 7) >> 7 : (int32_t)(a[q][h].y & DIG);
+          s[h][2][j] = sgn ? (int32_t)(a[q][h].z << 7) >> 7 : (int32_t)(a[q][h].z & DIG);
+        }
       }
     }
     __syncthreads();
   };
-  // the workgroup writes its gathered rows: one word per thread
+  // the workgroup writes its gathered records: one word per thread
   auto publish = [&](uint32_t* v) {
     __syncthreads();
-    if (threadIdx.x < 4 * RG && row0 + (int)threadIdx.x / 4 < n)
-      st_dev(v + (size_t)row0 * 4 + threadIdx.x, sOut[threadIdx.x]);
+    if (threadIdx.x < 4 * RG * NRHS && row0 + (int)threadIdx.x / (4 * NRHS) < n)
+      st_dev(v + (size_t)row0 * NRHS * 4 + threadIdx.x, sOut[threadIdx.x]);
   };
-  // centred planes and the rows of A in registers
-  typedef typename std::conditional<NARROW, int32_t, double>::type nv_t;
-  double c0[RPW][EPL], c1[RPW][EPL];
-  nv_t c2[RPW][EPL], av[RPW][EPL];
-  double rr[RPW];                                  // r of the row (lane 0), an integer
+  // centred planes and the rows of A, FP64 in registers
+  double c0[RPW][EPL], c1[RPW][EPL], c2[RPW][EPL], av[RPW][EPL];
+  double rr[RPW][NRHS];                            // r of the row (lane 0), integers
   int rows[RPW];
 #pragma unroll
   for (int i = 0; i < RPW; i++) {
     const int row = row0 + wave * RPW + i;
     rows[i] = row;
-    rr[i] = 0.0;
 #pragma unroll
     for (int e = 0; e < EPL; e++) {
       const int j = lane + 64 * e;
@@ -913,123 +921,139 @@ __global__ __launch_bounds__(64 * NWAVE) void k_lift_resident3(
       const int64_t o = (int64_t)row * n + j;
       c0[i][e] = in ? (double)centred_i32(C0[o], p) : 0.0;
       c1[i][e] = in ? (double)centred_i32(C1[o], p) : 0.0;
-      c2[i][e] = (nv_t)(in ? centred_i32(C2[o], p) : 0);
-      av[i][e] = (nv_t)(in ? Ai[o] : 0);
+      c2[i][e] = in ? (double)centred_i32(C2[o], p) : 0.0;
+      av[i][e] = in ? (double)Ai[o] : 0.0;
     }
-    if (row < n && lane == 0) rr[i] = (double)r[row];
+#pragma unroll
+    for (int h = 0; h < NRHS; h++)
+      rr[i][h] = (row < n && lane == 0) ? (double)r[(int64_t)row * NRHS + h] : 0.0;
   }
   const int64_t steps = (kd + 2) / 3;
   uint32_t tag = 0;                                // step mod 127
   for (int64_t step = 0; step < steps; step++) {
     const uint32_t tag1 = tag == 126 ? 0 : tag + 1;
-    // z: always 0, unknown to the compiler, keeps FP64 copies of the int32
-    // registers from being hoisted out of the step loop
-    const int z = (int)(step >> 62);
     // ---- phase X
-    double S0[RPW], S1a[RPW], S1b[RPW], S2a[RPW], S2b[RPW], S2c[RPW];
+    double S0[RPW][NRHS], S1a[RPW][NRHS], S1b[RPW][NRHS], S2a[RPW][NRHS], S2b[RPW][NRHS],
+        S2c[RPW][NRHS];
 #pragma unroll
-    for (int i = 0; i < RPW; i++) S0[i] = S1a[i] = S1b[i] = S2a[i] = S2b[i] = S2c[i] = 0.0;
+    for (int i = 0; i < RPW; i++)
+#pragma unroll
+      for (int h = 0; h < NRHS; h++)
+        S0[i][h] = S1a[i][h] = S1b[i][h] = S2a[i][h] = S2b[i][h] = S2c[i][h] = 0.0;
     stage3(sV[0], rsr, tag, true);
 #pragma unroll
     for (int e = 0; e < EPL; e++) {
-      const double w0 = (double)sV[0][0][lane + 64 * e];    // balanced digits
-      const double w1 = (double)sV[0][1][lane + 64 * e];
-      const double w2 = (double)sV[0][2][lane + 64 * e];
 #pragma unroll
-      for (int i = 0; i < RPW; i++) {
-        const double x2 = NARROW ? (double)((int32_t)c2[i][e] ^ z) : (double)c2[i][e];
-        S0[i] = fma(c0[i][e], w0, S0[i]);
-        S1a[i] = fma(c0[i][e], w1, S1a[i]);
-        S1b[i] = fma(c1[i][e], w0, S1b[i]);
-        S2a[i] = fma(c0[i][e], w2, S2a[i]);
-        S2b[i] = fma(c1[i][e], w1, S2b[i]);
-        S2c[i] = fma(x2, w0, S2c[i]);
+      for (int h = 0; h < NRHS; h++) {
+        const double w0 = (double)sV[0][h][0][lane + 64 * e];    // balanced digits
+        const double w1 = (double)sV[0][h][1][lane + 64 * e];
+        const double w2 = (double)sV[0][h][2][lane + 64 * e];
+#pragma unroll
+        for (int i = 0; i < RPW; i++) {
+          S0[i][h] = fma(c0[i][e], w0, S0[i][h]);
+          S1a[i][h] = fma(c0[i][e], w1, S1a[i][h]);
+          S1b[i][h] = fma(c1[i][e], w0, S1b[i][h]);
+          S2a[i][h] = fma(c0[i][e], w2, S2a[i][h]);
+          S2b[i][h] = fma(c1[i][e], w1, S2b[i][h]);
+          S2c[i][h] = fma(c2[i][e], w0, S2c[i][h]);
+        }
       }
     }
     // (absent rows, whose planes are 0, run through as well)
 #pragma unroll
-    for (int i = 0; i < RPW; i++) {
-      const double q0 = rint(S0[i] * pinv), m0 = fma(-q0, pd, S0[i]);
-      const double qa = rint(S1a[i] * pinv), ma = fma(-qa, pd, S1a[i]);
-      const double T1 = ma + S1b[i] + q0;
-      const double q1 = rint(T1 * pinv), m1 = fma(-q1, pd, T1);
-      const double T2 = mod_loose(S2a[i], pd, pinv) + mod_loose(S2b[i], pd, pinv) +
-                        mod_loose(S2c[i], pd, pinv) + qa + q1;
-      const double m2 = mod_loose(T2, pd, pinv);
-      const int64_t M0 = dpp_sum_i32((int)m0);
-      const int64_t M1 = dpp_sum_i32((int)m1);
-      const int64_t M2 = dpp_sum_i32((int)m2);
-      if (rows[i] < n && lane == 0) {
-        // carries (|M| < 2^31): exact quotients by p in FP64
-        const double x0d = canon_p((double)M0, pd, pinv);
-        const double t1 = (double)M1 + rint(((double)M0 - x0d) * pinv);
-        const double x1d = canon_p(t1, pd, pinv);
-        const double t2 = (double)M2 + rint((t1 - x1d) * pinv);
-        const uint32_t x0 = (uint32_t)x0d, x1 = (uint32_t)x1d;
-        const uint32_t x2 = (uint32_t)canon_p(t2, pd, pinv);
-        uint32_t* o = sOut + (wave * RPW + i) * 4;
-        o[0] = tag << 25 | x0;
-        o[1] = tag << 25 | x1;
-        o[2] = tag << 25 | x2;
-        o[3] = tag << 25;
-        if (digits) {
-          digits[(3 * step) * n + rows[i]] = x0;
-          if (3 * step + 1 < kd) digits[(3 * step + 1) * n + rows[i]] = x1;
-          if (3 * step + 2 < kd) digits[(3 * step + 2) * n + rows[i]] = x2;
+    for (int i = 0; i < RPW; i++)
+#pragma unroll
+      for (int h = 0; h < NRHS; h++) {
+        const double q0 = rint(S0[i][h] * pinv), m0 = fma(-q0, pd, S0[i][h]);
+        const double qa = rint(S1a[i][h] * pinv), ma = fma(-qa, pd, S1a[i][h]);
+        const double T1 = ma + S1b[i][h] + q0;
+        const double q1 = rint(T1 * pinv), m1 = fma(-q1, pd, T1);
+        const double T2 = mod_loose(S2a[i][h], pd, pinv) + mod_loose(S2b[i][h], pd, pinv) +
+                          mod_loose(S2c[i][h], pd, pinv) + qa + q1;
+        const double m2 = mod_loose(T2, pd, pinv);
+        const int64_t M0 = dpp_sum_i32((int)m0);
+        const int64_t M1 = dpp_sum_i32((int)m1);
+        const int64_t M2 = dpp_sum_i32((int)m2);
+        if (rows[i] < n && lane == 0) {
+          // carries (|M| < 2^31): exact quotients by p in FP64
+          const double x0d = canon_p((double)M0, pd, pinv);
+          const double t1 = (double)M1 + rint(((double)M0 - x0d) * pinv);
+          const double x1d = canon_p(t1, pd, pinv);
+          const double t2 = (double)M2 + rint((t1 - x1d) * pinv);
+          const uint32_t x0 = (uint32_t)x0d, x1 = (uint32_t)x1d;
+          const uint32_t x2 = (uint32_t)canon_p(t2, pd, pinv);
+          uint32_t* o = sOut + ((wave * RPW + i) * NRHS + h) * 4;
+          o[0] = tag << 25 | x0;
+          o[1] = tag << 25 | x1;
+          o[2] = tag << 25 | x2;
+          o[3] = tag << 25;
+          if (digits) {
+            uint32_t* dg = digits + (int64_t)h * kd * n;
+            dg[(3 * step) * n + rows[i]] = x0;
+            if (3 * step + 1 < kd) dg[(3 * step + 1) * n + rows[i]] = x1;
+            if (3 * step + 2 < kd) dg[(3 * step + 2) * n + rows[i]] = x2;
+          }
         }
       }
-    }
     publish(xv);
     // ---- phase R
-    double D0[RPW], D1[RPW], D2[RPW];
+    double D0[RPW][NRHS], D1[RPW][NRHS], D2[RPW][NRHS];
 #pragma unroll
-    for (int i = 0; i < RPW; i++) D0[i] = D1[i] = D2[i] = 0.0;
+    for (int i = 0; i < RPW; i++)
+#pragma unroll
+      for (int h = 0; h < NRHS; h++) D0[i][h] = D1[i][h] = D2[i][h] = 0.0;
     stage3(sV[1], rsx, tag, false);
 #pragma unroll
     for (int e = 0; e < EPL; e++) {
-      const double x0 = (double)sV[1][0][lane + 64 * e];
-      const double x1 = (double)sV[1][1][lane + 64 * e];
-      const double x2 = (double)sV[1][2][lane + 64 * e];
 #pragma unroll
-      for (int i = 0; i < RPW; i++) {
-        const double ae = NARROW ? (double)((int32_t)av[i][e] ^ z) : (double)av[i][e];
-        D0[i] = fma(ae, x0, D0[i]);
-        D1[i] = fma(ae, x1, D1[i]);
-        D2[i] = fma(ae, x2, D2[i]);
+      for (int h = 0; h < NRHS; h++) {
+        const double x0 = (double)sV[1][h][0][lane + 64 * e];
+        const double x1 = (double)sV[1][h][1][lane + 64 * e];
+        const double x2 = (double)sV[1][h][2][lane + 64 * e];
+#pragma unroll
+        for (int i = 0; i < RPW; i++) {
+          D0[i][h] = fma(av[i][e], x0, D0[i][h]);
+          D1[i][h] = fma(av[i][e], x1, D1[i][h]);
+          D2[i][h] = fma(av[i][e], x2, D2[i][h]);
+        }
       }
     }
 #pragma unroll
-    for (int i = 0; i < RPW; i++) {
-      const double d0 = dpp_sum_f64(D0[i]);
-      const double d1 = dpp_sum_f64(D1[i]);
-      const double d2 = dpp_sum_f64(D2[i]);
-      if (rows[i] < n && lane == 0) {
-        // exact divisions by p
-        double q = rint((rr[i] - d0) * pinv);
-        q = rint((q - d1) * pinv);
-        q = rint((q - d2) * pinv);
-        rr[i] = q;
-        // balanced digits of r' mod p^3, the carry of each centring taken
-        // into the next digit, so that m0 + p m1 + p^2 m2 = r' (mod p^3)
-        const double m0d = mod_c(q, pd, pinv);
-        const double u1 = rint((q - m0d) * pinv);
-        const double m1d = mod_c(u1, pd, pinv);
-        const double u2 = rint((u1 - m1d) * pinv);
-        const int32_t m0 = (int32_t)m0d, m1 = (int32_t)m1d;
-        const int32_t m2 = (int32_t)mod_c(u2, pd, pinv);
-        uint32_t* o = sOut + (wave * RPW + i) * 4;
-        o[0] = tag1 << 25 | ((uint32_t)m0 & DIG);
-        o[1] = tag1 << 25 | ((uint32_t)m1 & DIG);
-        o[2] = tag1 << 25 | ((uint32_t)m2 & DIG);
-        o[3] = tag1 << 25;
+    for (int i = 0; i < RPW; i++)
+#pragma unroll
+      for (int h = 0; h < NRHS; h++) {
+        const double d0 = dpp_sum_f64(D0[i][h]);
+        const double d1 = dpp_sum_f64(D1[i][h]);
+        const double d2 = dpp_sum_f64(D2[i][h]);
+        if (rows[i] < n && lane == 0) {
+          // exact divisions by p
+          double q = rint((rr[i][h] - d0) * pinv);
+          q = rint((q - d1) * pinv);
+          q = rint((q - d2) * pinv);
+          rr[i][h] = q;
+          // balanced digits of r' mod p^3, the carry of each centring taken
+          // into the next digit, so that m0 + p m1 + p^2 m2 = r' (mod p^3)
+          const double m0d = mod_c(q, pd, pinv);
+          const double u1 = rint((q - m0d) * pinv);
+          const double m1d = mod_c(u1, pd, pinv);
+          const double u2 = rint((u1 - m1d) * pinv);
+          const int32_t m0 = (int32_t)m0d, m1 = (int32_t)m1d;
+          const int32_t m2 = (int32_t)mod_c(u2, pd, pinv);
+          uint32_t* o = sOut + ((wave * RPW + i) * NRHS + h) * 4;
+          o[0] = tag1 << 25 | ((uint32_t)m0 & DIG);
+          o[1] = tag1 << 25 | ((uint32_t)m1 & DIG);
+          o[2] = tag1 << 25 | ((uint32_t)m2 & DIG);
+          o[3] = tag1 << 25;
+        }
       }
-    }
     publish(rv);
     tag = tag1;
   }
 #pragma unroll
   for (int i = 0; i < RPW; i++)
-    if (rows[i] < n && lane == 0) r[rows[i]] = (int64_t)rr[i];
+#pragma unroll
+    for (int h = 0; h < NRHS; h++)
+      if (rows[i] < n && lane == 0) r[(int64_t)rows[i] * NRHS + h] = (int64_t)rr[i][h];
 }
 
 // comb[i] = sum_j c_j x_i[j] for every lifted digit vector x_i (the random
@@ -1071,19 +1095,23 @@ hipError_t launch_hensel_f64(const int32_t* Ai, const uint32_t* C0, double* E, u
 
 hipError_t launch_lift_resident3(int grid, const uint32_t* C0, const uint32_t* C1,
                                  const uint32_t* C2, const int32_t* Ai, int64_t* r, uint32_t* rv,
-                                 uint32_t* xv, int n, uint32_t p, int64_t kd,
+                                 uint32_t* xv, int n, int nrhs, uint32_t p, int64_t kd,
                                  uint32_t* digits, int* err, hipStream_t st) {
   if (n <= 0 || kd <= 0) return hipSuccess;
-  if (p >= (1u << 25)) return hipErrorInvalidValue;
+  if (p >= (1u << 25) || nrhs < 1 || nrhs > LIFT3_MAX_RHS) return hipErrorInvalidValue;
   double pinv = 1.0 / (double)p;
   unsigned spin_limit = 1u << 18;     // polls of about 1 us each: ~0.3 s per wait at most
   void* args[] = {(void*)&C0, (void*)&C1, (void*)&C2, (void*)&Ai, (void*)&r, (void*)&rv,
                   (void*)&xv, (void*)&n, (void*)&p, (void*)&pinv, (void*)&kd,
                   (void*)&digits, (void*)&err, (void*)&spin_limit};
   const void* f = nullptr;
-  if (n <= 256) f = (const void*)k_lift_resident3<4, LIFT3_RPW, LIFT3_NWAVE, LIFT3_NARROW, LIFT3_SV64>;
-  else if (n <= 512) f = (const void*)k_lift_resident3<8, LIFT3_RPW, LIFT3_NWAVE, LIFT3_NARROW, LIFT3_SV64>;
-  else if (n <= 1024) f = (const void*)k_lift_resident3<16, LIFT3_RPW, LIFT3_NWAVE, LIFT3_NARROW, LIFT3_SV64>;
+#define LIFT3_PICK(E)                                                                        \
+  f = nrhs == 1 ? (const void*)k_lift_resident3<E, LIFT3_RPW, LIFT3_NWAVE, 1>                 \
+                : (const void*)k_lift_resident3<E, LIFT3_RPW, LIFT3_NWAVE, 2>
+  if (n <= 256) LIFT3_PICK(4);
+  else if (n <= 512) LIFT3_PICK(8);
+  else if (n <= 1024) LIFT3_PICK(16);
+#undef LIFT3_PICK
   if (!f || grid != lift3_grid_size(n)) return hipErrorInvalidValue;
   return hipLaunchCooperativeKernel(f, dim3(grid), dim3(64 * LIFT3_NWAVE), args, 0, st);
 }

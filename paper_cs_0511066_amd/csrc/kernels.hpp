@@ -89,11 +89,14 @@ hipError_t launch_comb_digits(const uint32_t* digits, int64_t k, int n, const ui
 constexpr uint32_t LIFT3_DIGIT_MASK = 0x1FFFFFFu;
 hipError_t launch_hensel_f64(const int32_t* Ai, const uint32_t* C0, double* E, uint32_t* C1,
                              uint32_t* C2, int n, uint32_t p, hipStream_t st);
-// rv, xv: n x 4 words, the digit vectors passed between workgroups (r of
-// step 0 in rv under tag 0, xv filled with all-ones words before the launch)
+// rv, xv: n x nrhs x 4 words, the digit vectors passed between workgroups (r
+// of step 0 in rv under tag 0, xv filled with all-ones words before the
+// launch); r: n x nrhs (row-major); digits: nrhs x kd x n.  nrhs <= LIFT3_MAX_RHS
+// right-hand sides share one launch.
+constexpr int LIFT3_MAX_RHS = 2;
 hipError_t launch_lift_resident3(int grid, const uint32_t* C0, const uint32_t* C1,
                                  const uint32_t* C2, const int32_t* Ai, int64_t* r, uint32_t* rv,
-                                 uint32_t* xv, int n, uint32_t p, int64_t kd,
+                                 uint32_t* xv, int n, int nrhs, uint32_t p, int64_t kd,
                                  uint32_t* digits, int* err, hipStream_t st);
 hipError_t launch_lift_resident2(int grid, const uint32_t* C0, const uint32_t* C1,
                                  const int32_t* Ai, int64_t* r, uint32_t* rp0, uint32_t* rp1,

@@ -221,6 +221,38 @@ def test_dixon_lift_n1024_invariant(ctx, bits):
         r = t // p
 
 
+@pytest.mark.gpu
+@pytest.mark.parametrize("n,m,k", [(1, 2, 5), (5, 3, 8), (33, 2, 6), (64, 2, 30), (150, 3, 7),
+                                   (300, 2, 3)])
+def test_dixon_lift_multi_matches_oracle(ctx, n, m, k):
+    """Several right-hand sides in one call: the digits of every column are
+    those of the one-right-hand-side oracle (25-bit p: the FP64 three-digit
+    form, two right-hand sides a launch; 26-bit p: one after the other)."""
+    _say("dixon_lift_multi n =", n, "m =", m)
+    A = synth.dense_uniform(n, -100, 100, 910 + n)
+    B = np.stack([synth.random_rhs(n, 1000, n + 17 * h) for h in range(m)], axis=1)
+    for p in test_primes(1 << 24, 1 << 25, 1, n) + test_primes(1 << 25, 1 << 26, 1, n):
+        X = ctx.dixon_lift_multi(A, B, p, k)
+        assert X.shape == (m, k, n)
+        for h in range(m):
+            assert np.array_equal(X[h].astype(np.int64), oracle.dixon_digits(A, B[:, h], p, k))
+
+
+@pytest.mark.gpu
+def test_dixon_lift_multi_n1024_equals_single(ctx):
+    """Full size, two right-hand sides in one launch: the same digits as two
+    one-right-hand-side calls (whose digits are pinned against the exact
+    residual invariant above)."""
+    n, k = 1024, 9
+    A = synth.dense_uniform(n, 0, 255, 1024)
+    B = np.stack([synth.random_rhs(n, 12000, 5), synth.random_rhs(n, 12000, 6)], axis=1)
+    p = test_primes(1 << 24, 1 << 25, 1, 78)[0]
+    X = ctx.dixon_lift_multi(A, B, p, k)
+    for h in range(2):
+        assert np.array_equal(X[h], ctx.dixon_lift(A, B[:, h], p, k))
+    assert ctx.dixon_lift_multi(A, B[:, :0], p, k).shape == (0, k, n)
+
+
 def test_dixon_lift_singular_mod_p(ctx):
     import paper_cs_0511066_amd as det
     p = test_primes(1 << 22, 1 << 23, 1, 12)[0]

@@ -21,7 +21,7 @@ def _declared_functions():
     for h in ("det.h", "det_host.h"):
         src = open(os.path.join(ROOT, "include", h)).read()
         src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-        names += re.findall(r"\b(det_[a-z0-9_]+|dixon_lift)\s*\(", src)
+        names += re.findall(r"\b(det_[a-z0-9_]+|dixon_lift[a-z_]*)\s*\(", src)
     return sorted(set(names))
 
 
