@@ -7,7 +7,7 @@ trailing updates on MFMA), the inverse mod p and the Dixon lifting steps,
 then early-terminated Chinese remaindering on the host.  Prints one JSON line.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-mfma]
-                    [--copy-probe MIB]
+                    [--no-multi] [--copy-probe MIB]
 
 --copy-probe MIB ends the run with three plain device-to-device copies of MIB
 MiB each (the reference kernel that scales the HBM byte counters).
@@ -119,6 +119,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mfma", action="store_true")
+    ap.add_argument("--no-multi", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -127,6 +128,7 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    import numpy as np
     import torch
 
     import paper_cs_0511066_amd as det
@@ -204,6 +206,25 @@ def main():
         del mfma["residues"]
         log("mfma:", mfma)
 
+    multi = None
+    if not args.no_multi:
+        # several right-hand sides in one lifting launch (dixon_lift_multi)
+        # against one: lifting-kernel time at the headline size and length
+        k = int(rep["lifting_steps"])
+        p25 = int(det.det_host_sample_primes(11, 25, 1)[0])
+        B = np.stack([synth.random_rhs(n, 12000, 21), synth.random_rhs(n, 12000, 22)], axis=1)
+        ctx.dixon_lift(At, B[:, 0], p25, 8)
+        ctx.profile_select("lift")
+        ctx.dixon_lift(At, B[:, 0], p25, k)
+        one = ctx.profile_read()
+        ctx.profile_select("lift")
+        ctx.dixon_lift_multi(At, B, p25, k)
+        two = ctx.profile_read()
+        ctx.profile_select("none")
+        multi = {"k": k, "one_rhs_lift_ms": round(one["ms"], 3), "two_rhs_lift_ms": round(two["ms"], 3),
+                 "lift_ms_per_rhs_ratio": round(two["ms"] / 2.0 / one["ms"], 3)}
+        log("multi-rhs lifting:", multi)
+
     cpu = None
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
@@ -230,6 +251,7 @@ def main():
                    "kernel_ms_per_det": {k: round(v["ms"], 3) for k, v in breakdown.items()}},
         "roofline": roof,
         "mfma_trailing_update": mfma,
+        "multi_rhs_lift": multi,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
