@@ -16,6 +16,7 @@ out when the method reaches that definition exactly.
   inverse_mod_p        --  A^{-1} mod p by Gauss-Jordan over Z_p
   dixon_digits         O3  p-adic digits of A^{-1} b (Section 2.2)
   solve_rational       O4  exact x = A^{-1} b over Q, its common denominator
+  extended_bonus       O4  pi~ = s~^i / gcd(det(R N), s~^i) (Section 3.2)
   crt_symmetric        O5  Chinese remaindering into the symmetric range
   et_cra               O5  early-terminated CRA (Alg. 2.1, Lemma 2.1)
   rational_reconstruct O6  rational number reconstruction (extended Euclid)
@@ -28,6 +29,7 @@ from .det_oracle import (  # noqa: F401
     dixon_digits,
     dixon_length,
     solve_rational,
+    extended_bonus,
     largest_invariant_factor,
     crt_symmetric,
     et_cra,

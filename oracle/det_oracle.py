@@ -234,6 +234,29 @@ def largest_invariant_factor(A, bs) -> int:
     return s
 
 
+def extended_bonus(A, B, R):
+    """pi~ of the extended bonus (Section 3.2, "the last k invariant factors";
+    Alg. 4.1 with i right-hand sides): the columns b_1..b_i of B solved over
+    Q, s~ = lcm of their common denominators (Section 2.2), N = s~ X with
+    X = [x_1..x_i], and for the random i x n matrix R
+        pi~ = s~^i / gcd(det(R N), s~^i),
+    a factor of s_n s_{n-1} ... s_{n-i+1} (equal to it with high probability).
+    Returns (s~, pi~)."""
+    B = [[int(v) for v in row] for row in np.asarray(B, dtype=object).tolist()]
+    i = len(B[0])
+    sols = [solve_rational(A, [row[h] for row in B]) for h in range(i)]
+    s = 1
+    for _, d in sols:
+        s = s * d // math.gcd(s, d)
+    # N = s~ X: column h is num_h * (s~ / d_h)
+    N = [[num[j] * (s // d) for num, d in sols] for j in range(len(A))]
+    R = [[int(v) for v in row] for row in np.asarray(R, dtype=object).tolist()]
+    RN = [[sum(R[a][j] * N[j][h] for j in range(len(A))) for h in range(i)] for a in range(i)]
+    dRN = det_bareiss(RN) if i > 0 else 1
+    si = s ** i
+    return s, si // math.gcd(dRN, si)
+
+
 def dixon_length(A, b, p: int) -> int:
     """Smallest k with p^k > 2 N D, where D = H (Hadamard) bounds the common
     denominator and N = H ||b|| / min_j ||a_j|| bounds every Cramer numerator

@@ -413,3 +413,39 @@ def test_pins_catch_a_planted_sign_error(monkeypatch):
 
     src_bad = lambda B: abs(m.det_bareiss(B))     # noqa: E731  (drops the sign)
     assert src_bad(A) != det_cofactor(A)
+
+
+def test_extended_bonus_recovers_the_last_invariant_factors():
+    """Section 3.2: with i right-hand sides, pi~ = s~^i / gcd(det(R N), s~^i)
+    (N = s~ X) is the product of the i largest invariant factors for random B
+    and R (with high probability: a prime q dividing them is lost with
+    probability about 1/q, so the factors here are large primes; these
+    seeds), checked against the Smith form the matrices are built with, and
+    it divides det(A)."""
+    import math
+
+    for n, tail, seed in ((12, [101, 101 * 103, 101 * 103 * 107], 1),
+                          (16, [113, 113 * 127, 113 * 127 * 131, 113 * 127 * 131 * 137], 2)):
+        s_list = [1] * (n - len(tail)) + tail
+        A, _ = synth.smith_matrix(s_list, seed, 0.3)
+        d = oracle.det_bareiss(A)
+        rng = np.random.default_rng(seed)
+        for i in (1, 2, 3):
+            B = rng.integers(0, 100, size=(n, i))
+            R = rng.integers(1, 1 << 16, size=(i, n))
+            s, pi = oracle.extended_bonus(A, B, R)
+            assert s == s_list[-1]
+            assert pi == math.prod(s_list[-i:])
+            assert d % pi == 0
+
+
+def test_extended_bonus_with_one_right_hand_side_is_s_n():
+    """i = 1: pi~ = s~ / gcd(r . N, s~), which is s~ itself for a random
+    combination r (Alg. 4.1 sets pi~_1 = s~_n)."""
+    A = synth.dense_uniform(10, -20, 20, 44)
+    rng = np.random.default_rng(44)
+    B = rng.integers(0, 50, size=(10, 1))
+    R = rng.integers(1, 1 << 16, size=(1, 10))
+    s, pi = oracle.extended_bonus(A, B, R)
+    _, den = oracle.solve_rational(A, B[:, 0])
+    assert s == den and pi == s
