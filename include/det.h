@@ -120,7 +120,10 @@ typedef struct {
   double log2_inv_eps;   /* early termination: failure probability < 2^-log2_inv_eps (default 64) */
   int certify;           /* 1: ignore early termination; reconstruct det/s_n up to the Hadamard bound */
   uint64_t seed;         /* seed for the prime draws and the right-hand side */
-  int n_rhs;             /* number of Dixon solvings (i_max of Alg. 4.1 with one factor), default 1 */
+  int n_rhs;             /* number of Dixon solvings, default 1.  With n_rhs = i >= 2 (at most 8)
+                            and the FP64 three-digit lifting, the i solvings share one prime and
+                            one launch, and the extended bonus (Section 3.2) contributes
+                            pi~ = s~^i / gcd(det(R N), s~^i), a factor of s_n ... s_{n-i+1} */
   int prime_bits;        /* CRA primes are drawn from (2^(b-1), 2^b); default 23 (max 23 for int8, 26 for fp64) */
   det_path path;         /* trailing-update path of the CRA loop */
 } det_opts;
@@ -128,10 +131,11 @@ typedef struct {
 typedef struct {
   int64_t primes_used;     /* CRA primes whose residues entered the reconstruction */
   int64_t lifting_steps;   /* Dixon steps over all solvings */
-  int64_t sn_bits;         /* bit length of the factor s~_n found by the solvings */
+  int64_t sn_bits;         /* bit length of the divisor K of det(A) found by the solvings */
   int64_t et_rounds;       /* batches of CRA primes launched */
   int64_t hadamard_bits;   /* log2 of the Hadamard bound used */
   int early_terminated;    /* 1 if the CRA stopped by early termination */
+  int bonus_factors;       /* i when the extended bonus pi~ (i solvings) entered the divisor */
   double t_lif_ms;         /* device + host time of the solvings */
   double t_cra_ms;         /* time of the modular determinants */
   double t_host_ms;        /* time of reconstruction on the host */

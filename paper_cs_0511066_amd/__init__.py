@@ -60,7 +60,8 @@ class det_opts(ctypes.Structure):
 class det_report(ctypes.Structure):
     _fields_ = [("primes_used", c_i64), ("lifting_steps", c_i64), ("sn_bits", c_i64),
                 ("et_rounds", c_i64), ("hadamard_bits", c_i64), ("early_terminated", c_int),
-                ("t_lif_ms", c_double), ("t_cra_ms", c_double), ("t_host_ms", c_double)]
+                ("bonus_factors", c_int), ("t_lif_ms", c_double), ("t_cra_ms", c_double),
+                ("t_host_ms", c_double)]
 
 
 def _sig(name, res, args):

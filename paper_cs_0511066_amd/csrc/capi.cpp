@@ -672,11 +672,12 @@ bool lift3_applies(int n, double amax, uint32_t p) {
 // row-major) from C0 = A^{-1} mod p in c->Cu and A packed in c->Ai, on c->st:
 // the Hensel planes once, then one cooperative launch per LIFT3_MAX_RHS
 // right-hand sides (they share the planes, the rows of A and every exchange).
-// digits_dev: m x k x n (may be null); comb_dev: m x k sums of cvec . x_i
-// (may be null).  With after_own2 the launches first wait for own2.
+// digits_dev: m x k x n (may be null); cvec_dev: ncv combination vectors
+// (stride lift_pad(n)); comb_dev: m x ncv x k sums cvec_a . x_i (may be null).
+// With after_own2 the launches first wait for own2.
 det_status lift3_multi(det_ctx* c, int grid3, int n, const int64_t* B, int m, uint32_t p,
                        int64_t k, uint32_t* digits_dev, const uint32_t* cvec_dev,
-                       uint64_t* comb_dev, bool after_own2) {
+                       uint64_t* comb_dev, bool after_own2, int ncv = 1) {
   constexpr int MR = detk::LIFT3_MAX_RHS;
   const double nn = (double)n * n;
   TRY(ensure(c, c->C1, (size_t)n * n * sizeof(uint32_t)));
@@ -745,8 +746,10 @@ det_status lift3_multi(det_ctx* c, int grid3, int n, const int64_t* B, int m, ui
     }
     if (comb_dev)
       for (int hh = 0; hh < mm; hh++)
-        HIPCHK(detk::launch_comb_digits(dig + (size_t)(h0 + hh) * k * n, k, n, cvec_dev,
-                                        comb_dev + (size_t)(h0 + hh) * k, c->st));
+        for (int a = 0; a < ncv; a++)
+          HIPCHK(detk::launch_comb_digits(dig + (size_t)(h0 + hh) * k * n, k, n,
+                                          cvec_dev + (size_t)a * lift_pad(n),
+                                          comb_dev + ((size_t)(h0 + hh) * ncv + a) * k, c->st));
     HIPCHK(hipMemcpyAsync(herr, err, sizeof(int), hipMemcpyDeviceToHost, c->st));
     HIPCHK(hipStreamSynchronize(c->st));
     if (*herr) return fail(c, DET_E_DEVICE, "lifting: a wait for another workgroup's digits timed out");
@@ -1138,6 +1141,104 @@ det_status dixon_lift(det_ctx* c, const int64_t* A, int64_t n, int64_t lda, cons
   }
 }
 
+// The extended bonus (Section 3.2; Alg. 4.1 with i = m >= 2 solvings) on the
+// FP64 three-digit lifting: one inverse mod p, m random right-hand sides
+// lifted together, and m random combination vectors R_0..R_{m-1} formed on
+// the GPU with every solution digit by digit.  s~ = lcm of the denominators
+// that rational reconstruction finds in the R_0 . x_h; R N = s~ (R X) from
+// the symmetric residues mod p^k (each must stay within the numerator bound
+// 2^Nbits, which it does when s~ X is integral; otherwise only s~ is kept);
+// pi~ = s~^m / gcd(det(R N), s~^m) (Section 3.2's exponent: R N is m x m).
+// K becomes lcm(K, s~, pi~).  *done is false when p divided det(A) twice.
+det_status extended_bonus(det_ctx* c, const int64_t* dA, int64_t dlda, int n,
+                          const dethost::Bounds& bd, int m, int grid3,
+                          dethost::PrimeSampler& dsamp, uint64_t& rng, int64_t beta, BigInt& K,
+                          det_report& rep, double& t_host, bool& done) {
+  done = false;
+  uint32_t p = 0;
+  det_status st = DET_E_SINGULAR_MOD_P;
+  for (int tries = 0; tries < 2 && st == DET_E_SINGULAR_MOD_P; tries++) {
+    p = dsamp.next();
+    st = inverse_mod_p(c, dA, dlda, n, p);
+  }
+  if (st == DET_E_SINGULAR_MOD_P) return DET_OK;     // det is probably 0: CRA alone
+  TRY(st);
+  // right-hand sides in [0, beta) (B[j*m + h]) and combination vectors in [1, 2^16)
+  const int64_t npad = lift_pad(n);
+  std::vector<int64_t> B((size_t)n * m);
+  std::vector<uint32_t> R((size_t)m * npad, 0);
+  double csum = 0, b2 = 0;
+  for (int64_t j = 0; j < n; j++)
+    for (int h = 0; h < m; h++) B[(size_t)j * m + h] = (int64_t)(dethost::splitmix64(rng) % (uint64_t)beta);
+  for (int a = 0; a < m; a++) {
+    double cs = 0;
+    for (int64_t j = 0; j < n; j++) {
+      R[(size_t)a * npad + j] = 1 + (uint32_t)(dethost::splitmix64(rng) % 65535u);
+      cs += R[(size_t)a * npad + j];
+    }
+    csum = std::max(csum, cs);
+  }
+  for (int h = 0; h < m; h++) {
+    double t = 0;
+    for (int64_t j = 0; j < n; j++) t += (double)B[(size_t)j * m + h] * (double)B[(size_t)j * m + h];
+    b2 = std::max(b2, t);
+  }
+  // numerators of R_a . x_h (and entries of R N): |.| <= max_a sum(R_a) H_col
+  // max_h ||b_h|| / min_j ||a_j||; denominators d <= H
+  const double log2N = log2(csum) + bd.log2_hcol + 0.5 * log2(std::max(b2, 1.0)) -
+                       bd.log2_min_col + 1e-6;
+  const int64_t Nbits = (int64_t)ceil(log2N), Dbits = (int64_t)ceil(bd.log2_h + 1e-6);
+  const int64_t k = (int64_t)ceil((double)(Nbits + Dbits + 2) / log2((double)p)) + 1;
+  TRY(ensure(c, c->cvec, (size_t)m * npad * sizeof(uint32_t)));
+  TRY(ensure(c, c->comb, (size_t)m * m * k * sizeof(uint64_t)));
+  HIPCHK(hipMemcpy(c->cvec.p, R.data(), R.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+  TRY(lift3_multi(c, grid3, n, B.data(), m, p, k, nullptr, (const uint32_t*)c->cvec.p,
+                  (uint64_t*)c->comb.p, true, m));
+  std::vector<uint64_t> comb((size_t)m * m * k);
+  HIPCHK(hipMemcpy(comb.data(), c->comb.p, comb.size() * sizeof(uint64_t), hipMemcpyDeviceToHost));
+  rep.lifting_steps += k * m;
+  const double th0 = now_ms();
+  // y[h][a] = R_a . x_h mod p^k
+  std::vector<std::vector<BigInt>> y(m, std::vector<BigInt>(m));
+  BigInt pk;
+  for (int h = 0; h < m; h++)
+    for (int a = 0; a < m; a++) dethost::radix_value(&comb[((size_t)h * m + a) * k], k, p, y[h][a], pk);
+  BigInt s = BigInt::from_i64(1);
+  for (int h = 0; h < m; h++) {
+    BigInt num, d;
+    if (dethost::rational_reconstruct(y[h][0], pk, BigInt::from_i64(1).shl(Nbits),
+                                      BigInt::from_i64(1).shl(Dbits), num, d, p))
+      s = BigInt::div_exact(s * d, BigInt::gcd(s, d));
+  }
+  K = BigInt::div_exact(K * s, BigInt::gcd(K, s));
+  // R N = s~ (R X): symmetric residues of s~ y mod p^k, within 2^Nbits
+  const BigInt lim = BigInt::from_i64(1).shl(Nbits);
+  BigInt half, rem;
+  BigInt::divmod_floor(pk, BigInt::from_i64(2), half, rem);
+  std::vector<std::vector<BigInt>> RN(m, std::vector<BigInt>(m));
+  bool ok = true;
+  for (int a = 0; a < m && ok; a++)
+    for (int h = 0; h < m && ok; h++) {
+      BigInt q, t;
+      BigInt::divmod_floor(s * y[h][a], pk, q, t);
+      if (t.cmp(half) > 0) t = t - pk;
+      ok = t.cmp_abs(lim) <= 0;
+      RN[a][h] = t;
+    }
+  if (ok) {
+    BigInt sm = BigInt::from_i64(1);
+    for (int i = 0; i < m; i++) sm = sm * s;
+    BigInt dRN = dethost::bareiss_det(RN);
+    if (dRN.sign < 0) dRN = -dRN;
+    const BigInt pi = BigInt::div_exact(sm, BigInt::gcd(dRN, sm));
+    K = BigInt::div_exact(K * pi, BigInt::gcd(K, pi));
+    rep.bonus_factors = m;
+  }
+  t_host += now_ms() - th0;
+  done = true;
+  return DET_OK;
+}
+
 det_status dixon_lift_multi(det_ctx* c, const int64_t* A, int64_t n, int64_t lda,
                             const int64_t* B, int64_t m, uint32_t p, int64_t k, uint32_t* digits) {
   if (!c) return DET_E_INVALID;
@@ -1283,7 +1384,16 @@ det_status det_introspective(det_ctx* c, const int64_t* A, int64_t n, int64_t ld
     while (dixon_bits > 12 && (double)n * bd.amax * ldexp(1.0, dixon_bits) >= ldexp(1.0, 62))
       dixon_bits--;
     const int64_t beta = std::max<int64_t>(2, (int64_t)ceil(bd.log2_h));
-    if (bd.log2_h > 0 && dixon_bits > 12) {
+    const int grid3 = dixon_bits == 25 ? detk::lift3_grid(c->device, (int)n) : 0;
+    if (bd.log2_h > 0 && dixon_bits > 12 && o.n_rhs >= 2 && grid3 > 0) {
+      // several solvings at once, with the extended bonus (Section 3.2)
+      dethost::PrimeSampler dsamp(dethost::splitmix64(rng), dixon_bits);
+      cra_join.join();                               // all of the batch is on own2
+      TRY(cra_st);
+      bool done = false;
+      TRY(extended_bonus(c, dA, dlda, (int)n, bd, std::min(o.n_rhs, 8), grid3, dsamp, rng, beta,
+                         K, rep, t_host, done));
+    } else if (bd.log2_h > 0 && dixon_bits > 12) {
       dethost::PrimeSampler dsamp(dethost::splitmix64(rng), dixon_bits);
       for (int solve = 0; solve < o.n_rhs; solve++) {
         uint32_t p = 0;

@@ -201,6 +201,32 @@ inline __int128 small_quot(__int128 a, __int128 b) {
   return a / b;
 }
 
+// det(M) of a small square BigInt matrix by fraction-free (Bareiss)
+// elimination: every division is exact; a zero pivot is replaced by a row
+// below it (changing the sign).
+inline BigInt bareiss_det(std::vector<std::vector<BigInt>> M) {
+  const size_t n = M.size();
+  if (n == 0) return BigInt::from_i64(1);
+  int sign = 1;
+  BigInt prev = BigInt::from_i64(1);
+  for (size_t k = 0; k < n; k++) {
+    if (M[k][k].is_zero()) {
+      size_t r = k + 1;
+      while (r < n && M[r][k].is_zero()) r++;
+      if (r == n) return BigInt();
+      std::swap(M[k], M[r]);
+      sign = -sign;
+    }
+    for (size_t i = k + 1; i < n; i++)
+      for (size_t j = k + 1; j < n; j++)
+        M[i][j] = BigInt::div_exact(M[i][j] * M[k][k] - M[i][k] * M[k][j], prev);
+    prev = M[k][k];
+  }
+  BigInt d = M[n - 1][n - 1];
+  if (sign < 0) d = -d;
+  return d;
+}
+
 // The integer sum_i c[i] p^i (c[i] < 2^64, p < 2^25) and p^k, for the
 // rational reconstruction of a p-adic expansion: Horner's rule two digits a
 // pass (multiplier p^2, a 128-bit addend), p^k by squaring.

@@ -253,6 +253,36 @@ def test_dixon_lift_multi_n1024_equals_single(ctx):
     assert ctx.dixon_lift_multi(A, B[:, :0], p, k).shape == (0, k, n)
 
 
+@pytest.mark.gpu
+@pytest.mark.parametrize("n,tail,seed,i", [(60, [101, 101 * 103], 31, 2),
+                                           (96, [107, 107 * 109, 107 * 109 * 113], 32, 3),
+                                           (150, [103, 103 * 127], 33, 2)])
+def test_det_introspective_extended_bonus(ctx, n, tail, seed, i):
+    """Section 3.2 on the GPU: i solvings share one prime and one lifting
+    launch, and the divisor found is the product of the i largest invariant
+    factors (large primes here, which the random choices keep with high
+    probability), while det(A) stays exact."""
+    import math
+
+    _say("extended bonus n =", n, "i =", i)
+    s = [1] * (n - len(tail)) + tail
+    A, sign = synth.smith_matrix(s, seed, None)
+    d, rep = ctx.det_introspective(A, n_rhs=i, report=True)
+    assert d == sign * math.prod(s)
+    assert d == oracle.det_bareiss(A)
+    assert rep["bonus_factors"] == i, rep
+    assert rep["sn_bits"] == math.prod(tail[-i:]).bit_length()
+
+
+@pytest.mark.gpu
+def test_det_introspective_two_solvings_dense(ctx):
+    """n_rhs = 2 on a plain dense matrix: the same exact determinant."""
+    A = synth.dense_uniform(128, -100, 100, 128)
+    d, rep = ctx.det_introspective(A, n_rhs=2, report=True)
+    assert d == oracle.det_bareiss(A)
+    assert rep["bonus_factors"] == 2
+
+
 def test_dixon_lift_singular_mod_p(ctx):
     import paper_cs_0511066_amd as det
     p = test_primes(1 << 22, 1 << 23, 1, 12)[0]
