@@ -169,6 +169,11 @@ def main():
     ctx.profile_select("none")
     if d != d0:
         raise SystemExit("determinant changed between runs")
+    golden = int(json.load(open(os.path.join(ROOT, "tests", "golden",
+                                             "dense_n1024_u0_255_seed1024.json")))["det_hex"], 16)
+    if d != golden:
+        raise SystemExit("determinant differs from the oracle's stored value: the metric is invalid")
+    log("det equals the oracle's stored determinant (", abs(golden).bit_length(), "bits )")
     secs = t1 - t0
     value = args.steps / secs
     roof = roofline_entry(dominant, prof)
@@ -201,9 +206,9 @@ def main():
                 "peak_tops": PEAK_TOPS[kern],
                 "frac_of_peak": round(pr["ops"] / (pr["ms"] / 1e3) / 1e12 / PEAK_TOPS[kern], 4),
             }
-            mfma.setdefault("residues", []).append(int(res.sum()) & 0xFFFFFFFF)
-        mfma["paths_agree"] = mfma["residues"][0] == mfma["residues"][1]
-        del mfma["residues"]
+            mfma[path]["residues_equal_oracle"] = res.tolist() == [golden % int(q) for q in primes]
+            if not mfma[path]["residues_equal_oracle"]:
+                raise SystemExit(f"{path} residues differ from the oracle's determinant mod p")
         log("mfma:", mfma)
 
     multi = None

@@ -135,7 +135,9 @@ typedef struct {
   int64_t et_rounds;       /* batches of CRA primes launched */
   int64_t hadamard_bits;   /* log2 of the Hadamard bound used */
   int early_terminated;    /* 1 if the CRA stopped by early termination */
-  int bonus_factors;       /* i when the extended bonus pi~ (i solvings) entered the divisor */
+  int bonus_factors;       /* i when the extended bonus pi~ (i solvings) entered the divisor;
+                              -i when a rational reconstruction of the bonus failed (only the
+                              denominators found entered it); 0 when the bonus did not run */
   double t_lif_ms;         /* device + host time of the solvings */
   double t_cra_ms;         /* time of the modular determinants */
   double t_host_ms;        /* time of reconstruction on the host */

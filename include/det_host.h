@@ -59,6 +59,23 @@ det_status det_host_bigint(int op, int a_sign, const uint32_t *a, int64_t alen, 
                            const uint32_t *b, int64_t blen, int *out_sign, uint32_t *out,
                            int64_t cap, int64_t *out_len);
 
+/* The extended bonus of Section 3.2 (Alg. 4.1 with m solvings) from the
+ * p-adic expansions of the m x m combinations y[h][a] = R_a . x_h, with
+ * x_h = A^{-1} b_h:  comb[(h*m + a)*k + i] = R_a . (digit i of x_h), so
+ * y[h][a] = sum_{i<k} comb[..+i] p^i mod p^k (host array, m*m*k entries,
+ * each < 2^64).  Every y[h][a] is rebuilt by rational reconstruction
+ * (|numerator| <= 2^Nbits, 0 < denominator <= 2^Dbits; needs
+ * Nbits + Dbits + 1 < k log2 p).  Outputs, as magnitudes:
+ *   s~  = lcm of the denominators found (a divisor of s_n),
+ *   pi~ = s~^m / gcd(det(R N), s~^m) with R N = s~ (R_a . x_h), a divisor of
+ *         s_n s_{n-1} ... s_{n-m+1};
+ * *failed = number of combinations whose reconstruction failed (then pi~ = 1
+ * and s~ covers only the others).  1 <= m <= 64. */
+det_status det_host_extended_bonus(const uint64_t* comb, int64_t m, int64_t k, uint32_t p,
+                                   int64_t Nbits, int64_t Dbits, uint32_t* s_mag, int64_t s_cap,
+                                   int64_t* s_len, uint32_t* pi_mag, int64_t pi_cap,
+                                   int64_t* pi_len, int64_t* failed);
+
 #ifdef __cplusplus
 }
 #endif

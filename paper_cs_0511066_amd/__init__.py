@@ -11,8 +11,11 @@ Matrices may be numpy int64 arrays (host memory) or torch int64 CUDA tensors
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import sys
+import weakref
 from dataclasses import dataclass
 
 import numpy as np
@@ -99,12 +102,14 @@ _sig("det_host_ratrecon", c_int, [P(c_u32), c_i64, P(c_u32), c_i64, c_i64, c_i64
                                   P(c_u32), c_i64, P(c_i64), P(c_u32), c_i64, P(c_i64)])
 _sig("det_host_bigint", c_int, [c_int, c_int, P(c_u32), c_i64, c_int, P(c_u32), c_i64, P(c_int),
                                 P(c_u32), c_i64, P(c_i64)])
+_sig("det_host_extended_bonus", c_int, [P(c_u64), c_i64, c_i64, c_u32, c_i64, c_i64, P(c_u32), c_i64,
+                                        P(c_i64), P(c_u32), c_i64, P(c_i64), P(c_i64)])
 
 EXPORTED = ["det_ctx_create", "det_ctx_destroy", "det_ctx_set_stream", "det_status_str",
             "det_last_error", "det_opts_default", "det_mod_primes", "dixon_lift", "dixon_lift_multi",
             "det_introspective", "det_batch", "det_profile_select", "det_profile_read", "det_host_is_prime", "det_host_sample_primes",
             "det_host_hadamard_log2", "det_host_et_run_length", "det_host_crt",
-            "det_host_ratrecon", "det_host_bigint"]
+            "det_host_ratrecon", "det_host_bigint", "det_host_extended_bonus"]
 
 
 # ------------------------------------------------------------------ helpers
@@ -152,6 +157,23 @@ def _matrix_arg(A):
     return ctypes.c_void_p(M.ctypes.data if n else 0), n, max(n, 1), M
 
 
+# Contexts still open when the interpreter exits are closed by an atexit
+# handler, which runs before any module or runtime teardown; a context found
+# by the garbage collector during finalisation is left alone (its memory goes
+# with the process), so no HIP call is made after the runtime has started to
+# shut down.
+_live: "weakref.WeakSet[Context]" = weakref.WeakSet()
+
+
+@atexit.register
+def _close_live_contexts():
+    for c in list(_live):
+        try:
+            c.close()
+        except Exception:
+            pass
+
+
 class Context:
     """A det_ctx: device workspace and stream of the library."""
 
@@ -161,13 +183,16 @@ class Context:
         if st != DET_OK:
             raise DetError(st, "det_ctx_create failed (no usable HIP device?)")
         self._h = h
+        _live.add(self)
 
     def close(self):
         if getattr(self, "_h", None):
-            _lib.det_ctx_destroy(self._h)
-            self._h = None
+            h, self._h = self._h, None
+            _lib.det_ctx_destroy(h)
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -408,3 +433,21 @@ def det_host_bigint(op: str, a: int, b: int) -> int:
     if st != DET_OK:
         raise DetError(st)
     return _from_limbs(so.value, out[:ln.value])
+
+
+def det_host_extended_bonus(comb, p: int, Nbits: int, Dbits: int):
+    """(s~, pi~, failed) of the extended bonus from an m x m x k array of
+    combination digits comb[h, a, i] = R_a . (digit i of x_h)."""
+    cb = np.ascontiguousarray(np.asarray(comb, dtype=np.uint64))
+    if cb.ndim != 3 or cb.shape[0] != cb.shape[1]:
+        raise ValueError("comb must be m x m x k")
+    m, _, k = cb.shape
+    cap = int((Nbits + Dbits) * m // 32 + 8)
+    sm, pm = np.zeros(cap, dtype=np.uint32), np.zeros(cap, dtype=np.uint32)
+    sl, pl, failed = c_i64(0), c_i64(0), c_i64(0)
+    st = _lib.det_host_extended_bonus(cb.ctypes.data_as(P(c_u64)), m, k, p, Nbits, Dbits,
+                                      _u32p(sm), cap, ctypes.byref(sl), _u32p(pm), cap,
+                                      ctypes.byref(pl), ctypes.byref(failed))
+    if st != DET_OK:
+        raise DetError(st)
+    return _from_limbs(1, sm[:sl.value]), _from_limbs(1, pm[:pl.value]), int(failed.value)

@@ -668,18 +668,28 @@ bool lift3_applies(int n, double amax, uint32_t p) {
   return p < (1u << 25) && (double)n * std::max(amax, 1.0) * (double)p < ldexp(1.0, 53);
 }
 
+// A as int32 (row-major, n x n) in c->Ai, for the Hensel planes and the
+// lifting kernels (the entry bound |a_ij| < 2^31 is checked beforehand).
+det_status pack_matrix(det_ctx* c, const int64_t* dA, int64_t dlda, int n) {
+  TRY(ensure(c, c->Ai, (size_t)n * n * sizeof(int32_t)));
+  HIPCHK(detk::launch_pack_i32(dA, dlda, n, (int32_t*)c->Ai.p, c->st));
+  return DET_OK;
+}
+
 // The three-digit FP64 lifting (modulo p^3) of m right-hand sides B (n x m,
-// row-major) from C0 = A^{-1} mod p in c->Cu and A packed in c->Ai, on c->st:
+// row-major) from C0 = A^{-1} mod p in c->Cu, on c->st: A packed into c->Ai,
 // the Hensel planes once, then one cooperative launch per LIFT3_MAX_RHS
 // right-hand sides (they share the planes, the rows of A and every exchange).
 // digits_dev: m x k x n (may be null); cvec_dev: ncv combination vectors
 // (stride lift_pad(n)); comb_dev: m x ncv x k sums cvec_a . x_i (may be null).
 // With after_own2 the launches first wait for own2.
-det_status lift3_multi(det_ctx* c, int grid3, int n, const int64_t* B, int m, uint32_t p,
-                       int64_t k, uint32_t* digits_dev, const uint32_t* cvec_dev,
-                       uint64_t* comb_dev, bool after_own2, int ncv = 1) {
+det_status lift3_multi(det_ctx* c, int grid3, const int64_t* dA, int64_t dlda, int n,
+                       const int64_t* B, int m, uint32_t p, int64_t k, uint32_t* digits_dev,
+                       const uint32_t* cvec_dev, uint64_t* comb_dev, bool after_own2,
+                       int ncv = 1) {
   constexpr int MR = detk::LIFT3_MAX_RHS;
   const double nn = (double)n * n;
+  TRY(pack_matrix(c, dA, dlda, n));
   TRY(ensure(c, c->C1, (size_t)n * n * sizeof(uint32_t)));
   TRY(ensure(c, c->C2, (size_t)n * n * sizeof(uint32_t)));
   TRY(ensure(c, c->Ed, (size_t)n * n * sizeof(double)));
@@ -766,11 +776,11 @@ det_status lift3_multi(det_ctx* c, int grid3, int n, const int64_t* B, int m, ui
 det_status lift(det_ctx* c, const int64_t* dA, int64_t dlda, int n, double amax, const int64_t* b,
                 uint32_t p, int64_t k, uint32_t* digits_dev, const uint32_t* cvec_dev,
                 uint64_t* comb_dev, bool after_own2 = false) {
-  TRY(ensure(c, c->Ai, (size_t)n * n * sizeof(int32_t)));
-  HIPCHK(detk::launch_pack_i32(dA, dlda, n, (int32_t*)c->Ai.p, c->st));
   const int grid3 = c->lift_mode == 0 && lift3_applies(n, amax, p) ? detk::lift3_grid(c->device, n) : 0;
   if (grid3 > 0)      // lifting modulo p^3 in FP64: Hensel planes, then three digits a step
-    return lift3_multi(c, grid3, n, b, 1, p, k, digits_dev, cvec_dev, comb_dev, after_own2);
+    return lift3_multi(c, grid3, dA, dlda, n, b, 1, p, k, digits_dev, cvec_dev, comb_dev,
+                       after_own2);
+  TRY(pack_matrix(c, dA, dlda, n));
   // rp and x are padded with zeros to lift_pad(n) entries (the
   // register-resident kernel loads 64 EPL entries without bounds tests)
   const int64_t npad = lift_pad(n);
@@ -1144,12 +1154,14 @@ det_status dixon_lift(det_ctx* c, const int64_t* A, int64_t n, int64_t lda, cons
 // The extended bonus (Section 3.2; Alg. 4.1 with i = m >= 2 solvings) on the
 // FP64 three-digit lifting: one inverse mod p, m random right-hand sides
 // lifted together, and m random combination vectors R_0..R_{m-1} formed on
-// the GPU with every solution digit by digit.  s~ = lcm of the denominators
-// that rational reconstruction finds in the R_0 . x_h; R N = s~ (R X) from
-// the symmetric residues mod p^k (each must stay within the numerator bound
-// 2^Nbits, which it does when s~ X is integral; otherwise only s~ is kept);
-// pi~ = s~^m / gcd(det(R N), s~^m) (Section 3.2's exponent: R N is m x m).
-// K becomes lcm(K, s~, pi~).  *done is false when p divided det(A) twice.
+// the GPU with every solution digit by digit.  The host step
+// (extended_bonus_host) rebuilds every R_a . x_h by rational reconstruction,
+// takes s~ = lcm of all their denominators (so that R N = s~ R X is an
+// integer matrix), and pi~ = s~^m / gcd(det(R N), s~^m) (Section 3.2's
+// exponent: R N is m x m).  K becomes lcm(K, s~, pi~), a divisor of det(A).
+// rep.bonus_factors = m on success; -m when a reconstruction failed (then
+// only the denominators that were found enter K).  *done is false when p
+// divided det(A) twice.
 det_status extended_bonus(det_ctx* c, const int64_t* dA, int64_t dlda, int n,
                           const dethost::Bounds& bd, int m, int grid3,
                           dethost::PrimeSampler& dsamp, uint64_t& rng, int64_t beta, BigInt& K,
@@ -1183,57 +1195,29 @@ det_status extended_bonus(det_ctx* c, const int64_t* dA, int64_t dlda, int n,
     for (int64_t j = 0; j < n; j++) t += (double)B[(size_t)j * m + h] * (double)B[(size_t)j * m + h];
     b2 = std::max(b2, t);
   }
-  // numerators of R_a . x_h (and entries of R N): |.| <= max_a sum(R_a) H_col
-  // max_h ||b_h|| / min_j ||a_j||; denominators d <= H
+  // numerators of R_a . x_h: |.| <= max_a sum(R_a) H_col max_h ||b_h|| /
+  // min_j ||a_j|| (Cramer); denominators d <= H
   const double log2N = log2(csum) + bd.log2_hcol + 0.5 * log2(std::max(b2, 1.0)) -
                        bd.log2_min_col + 1e-6;
   const int64_t Nbits = (int64_t)ceil(log2N), Dbits = (int64_t)ceil(bd.log2_h + 1e-6);
   const int64_t k = (int64_t)ceil((double)(Nbits + Dbits + 2) / log2((double)p)) + 1;
   TRY(ensure(c, c->cvec, (size_t)m * npad * sizeof(uint32_t)));
   TRY(ensure(c, c->comb, (size_t)m * m * k * sizeof(uint64_t)));
-  HIPCHK(hipMemcpy(c->cvec.p, R.data(), R.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
-  TRY(lift3_multi(c, grid3, n, B.data(), m, p, k, nullptr, (const uint32_t*)c->cvec.p,
+  HIPCHK(hipMemcpyAsync(c->cvec.p, R.data(), R.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
+                        c->st));
+  TRY(lift3_multi(c, grid3, dA, dlda, n, B.data(), m, p, k, nullptr, (const uint32_t*)c->cvec.p,
                   (uint64_t*)c->comb.p, true, m));
   std::vector<uint64_t> comb((size_t)m * m * k);
-  HIPCHK(hipMemcpy(comb.data(), c->comb.p, comb.size() * sizeof(uint64_t), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpyAsync(comb.data(), c->comb.p, comb.size() * sizeof(uint64_t),
+                        hipMemcpyDeviceToHost, c->st));
+  HIPCHK(hipStreamSynchronize(c->st));
   rep.lifting_steps += k * m;
   const double th0 = now_ms();
-  // y[h][a] = R_a . x_h mod p^k
-  std::vector<std::vector<BigInt>> y(m, std::vector<BigInt>(m));
-  BigInt pk;
-  for (int h = 0; h < m; h++)
-    for (int a = 0; a < m; a++) dethost::radix_value(&comb[((size_t)h * m + a) * k], k, p, y[h][a], pk);
-  BigInt s = BigInt::from_i64(1);
-  for (int h = 0; h < m; h++) {
-    BigInt num, d;
-    if (dethost::rational_reconstruct(y[h][0], pk, BigInt::from_i64(1).shl(Nbits),
-                                      BigInt::from_i64(1).shl(Dbits), num, d, p))
-      s = BigInt::div_exact(s * d, BigInt::gcd(s, d));
-  }
+  BigInt s, pi;
+  const int64_t failed = dethost::extended_bonus_host(comb.data(), m, k, p, Nbits, Dbits, s, pi);
   K = BigInt::div_exact(K * s, BigInt::gcd(K, s));
-  // R N = s~ (R X): symmetric residues of s~ y mod p^k, within 2^Nbits
-  const BigInt lim = BigInt::from_i64(1).shl(Nbits);
-  BigInt half, rem;
-  BigInt::divmod_floor(pk, BigInt::from_i64(2), half, rem);
-  std::vector<std::vector<BigInt>> RN(m, std::vector<BigInt>(m));
-  bool ok = true;
-  for (int a = 0; a < m && ok; a++)
-    for (int h = 0; h < m && ok; h++) {
-      BigInt q, t;
-      BigInt::divmod_floor(s * y[h][a], pk, q, t);
-      if (t.cmp(half) > 0) t = t - pk;
-      ok = t.cmp_abs(lim) <= 0;
-      RN[a][h] = t;
-    }
-  if (ok) {
-    BigInt sm = BigInt::from_i64(1);
-    for (int i = 0; i < m; i++) sm = sm * s;
-    BigInt dRN = dethost::bareiss_det(RN);
-    if (dRN.sign < 0) dRN = -dRN;
-    const BigInt pi = BigInt::div_exact(sm, BigInt::gcd(dRN, sm));
-    K = BigInt::div_exact(K * pi, BigInt::gcd(K, pi));
-    rep.bonus_factors = m;
-  }
+  K = BigInt::div_exact(K * pi, BigInt::gcd(K, pi));
+  rep.bonus_factors = failed ? -m : m;
   t_host += now_ms() - th0;
   done = true;
   return DET_OK;
@@ -1269,9 +1253,7 @@ det_status dixon_lift_multi(det_ctx* c, const int64_t* A, int64_t n, int64_t lda
     const int grid3 =
         c->lift_mode == 0 && lift3_applies((int)n, bd.amax, p) ? detk::lift3_grid(c->device, (int)n) : 0;
     if (grid3 > 0) {
-      TRY(ensure(c, c->Ai, (size_t)n * n * sizeof(int32_t)));
-      HIPCHK(detk::launch_pack_i32(dA, dlda, (int)n, (int32_t*)c->Ai.p, c->st));
-      TRY(lift3_multi(c, grid3, (int)n, B, (int)m, p, k, dig, nullptr, nullptr, false));
+      TRY(lift3_multi(c, grid3, dA, dlda, (int)n, B, (int)m, p, k, dig, nullptr, nullptr, false));
     } else {
       std::vector<int64_t> bh(n);
       for (int64_t h = 0; h < m; h++) {

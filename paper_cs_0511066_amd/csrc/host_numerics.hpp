@@ -311,4 +311,56 @@ inline bool rational_reconstruct(const BigInt& u_in, const BigInt& m, const BigI
   return true;
 }
 
+// ---------------------------------------------------------------- extended bonus
+// The extended bonus of Section 3.2 (Alg. 4.1 with m >= 2 solvings), from
+// the p-adic expansions of the m x m combinations y[h][a] = R_a . x_h,
+// x_h = A^{-1} b_h:  comb[(h m + a) k + i] = R_a . (digit i of x_h), so that
+// y[h][a] = sum_i comb[..i] p^i (mod p^k).  Each y[h][a] is rebuilt by
+// rational reconstruction (numerator <= 2^Nbits, denominator <= 2^Dbits,
+// unique when Nbits + Dbits + 1 < k log2 p).
+//   s~  = lcm of the denominators of all y[h][a]; every one divides the
+//         common denominator of X = [x_0 .. x_{m-1}] and so s_n;
+//   R N = s~ R X, the integer m x m matrix with entries num * (s~ / den);
+//   pi~ = s~^m / gcd(det(R N), s~^m).
+// Since det(R X) P_m is an integer for P_m = s_n s_{n-1} ... s_{n-m+1}
+// (Cauchy-Binet over the Smith form of A), s~^m divides det(R N) P_m, so pi~
+// divides P_m for any s~ that makes R N integral; and s~ | s_n | P_m, so
+// lcm(s~, pi~) divides det(A).  Returns the number of combinations whose
+// reconstruction failed (0 on success; then pi~ is set, else pi~ = 1 and s~
+// is the lcm of the denominators that were found).
+inline int64_t extended_bonus_host(const uint64_t* comb, int m, int64_t k, uint64_t p,
+                                   int64_t Nbits, int64_t Dbits, BigInt& s, BigInt& pi) {
+  s = BigInt::from_i64(1);
+  pi = BigInt::from_i64(1);
+  if (m <= 0) return 0;
+  const BigInt Nb = BigInt::from_i64(1).shl(Nbits), Db = BigInt::from_i64(1).shl(Dbits);
+  std::vector<std::vector<BigInt>> num(m, std::vector<BigInt>(m)), den(m, std::vector<BigInt>(m));
+  int64_t failed = 0;
+  BigInt pk;
+  for (int h = 0; h < m; h++)
+    for (int a = 0; a < m; a++) {
+      BigInt y;
+      radix_value(comb + ((size_t)h * m + a) * k, k, p, y, pk);
+      BigInt nu, d;
+      if (!rational_reconstruct(y, pk, Nb, Db, nu, d, p)) {
+        failed++;
+        continue;
+      }
+      num[h][a] = nu;
+      den[h][a] = d;
+      s = BigInt::div_exact(s * d, BigInt::gcd(s, d));
+    }
+  if (failed) return failed;
+  // R N (rows a, columns h): exact, as every den divides s~
+  std::vector<std::vector<BigInt>> RN(m, std::vector<BigInt>(m));
+  for (int a = 0; a < m; a++)
+    for (int h = 0; h < m; h++) RN[a][h] = num[h][a] * BigInt::div_exact(s, den[h][a]);
+  BigInt sm = BigInt::from_i64(1);
+  for (int i = 0; i < m; i++) sm = sm * s;
+  BigInt dRN = bareiss_det(RN);
+  if (dRN.sign < 0) dRN = -dRN;
+  pi = BigInt::div_exact(sm, BigInt::gcd(dRN, sm));
+  return 0;
+}
+
 }  // namespace dethost

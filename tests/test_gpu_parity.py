@@ -132,17 +132,49 @@ def test_det_mod_primes_rejects_bad_primes(ctx):
     assert e.value.status == 5
 
 
-def test_det_mod_primes_n1024_sampled(ctx):
-    """Full headline size: residues for a batch of primes, two checked one by
-    one with the oracle's modular elimination."""
-    A = synth.dense_uniform(1024, 0, 255, 1024)
+def test_det_mod_primes_n1024_golden_every_residue(ctx):
+    """Full headline size: every residue of a 16-prime batch (single-level
+    blocking) and of a 96-prime batch (two-level blocking: 128-wide outer
+    blocks, outer triangular inverses, int8 outer updates) on both paths
+    equals the oracle's exact determinant mod p; two residues are also
+    checked against the oracle's modular elimination."""
+    g = _golden("dense_n1024_u0_255_seed1024")
+    A = synth.dense_uniform(g["n"], g["lo"], g["hi"], g["seed"])
+    d = int(g["det_hex"], 16)
+    for count, seed in ((16, 9), (96, 10)):
+        ps = test_primes(1 << 22, 1 << 23, count, seed)
+        _say("n=1024 golden residues, primes", count)
+        for path in ("int8", "fp64"):
+            assert ctx.det_mod_primes(A, ps, path).tolist() == [d % q for q in ps], path
     ps = test_primes(1 << 22, 1 << 23, 16, 9)
     r8 = ctx.det_mod_primes(A, ps, "int8")
-    r64 = ctx.det_mod_primes(A, ps, "fp64")
-    assert r8.tolist() == r64.tolist()
     for j in (0, 11):
         _say("oracle det_mod_p n=1024 prime", ps[j])
         assert int(r8[j]) == oracle.det_mod_p(A, ps[j])
+
+
+@pytest.mark.parametrize("path", ["int8", "fp64"])
+def test_det_mod_primes_two_level_pivoting_n300(ctx, path):
+    """The two-level blocking (64 or more primes in one batch) at n = 300,
+    three 128-wide outer blocks: zero pivots inside and across the outer
+    blocks force row swaps (the swap kernel moves rows between blocks), the
+    outer triangular inverses and updates run, and every residue of every
+    prime equals the oracle's determinant mod p."""
+    ps = test_primes(1 << 22, 1 << 23, 72, 41)
+    cases = []
+    A = _vanishing_minors(300, (7, 36, 70, 131, 200, 260), 14)
+    cases.append((A, oracle.det_bareiss_c(A)))
+    Z = synth.dense_uniform(300, -40, 40, 15)
+    Z[:, 0] = 0
+    Z[271, 0] = 5                      # column 0's only pivot lies in the third outer block
+    Z[:140, 130] = 0                   # a zero pivot at the start of the second outer block
+    cases.append((Z, oracle.det_bareiss_c(Z)))
+    S, sign = synth.smith_matrix([1] * 296 + [3, 3 * 7, 3 * 7 * 11, 3 * 7 * 11 * 13], 16, None)
+    cases.append((S, sign * 3 ** 4 * 7 ** 3 * 11 ** 2 * 13))
+    for M, d in cases:
+        assert d != 0
+        _say("two-level n=300", path)
+        assert ctx.det_mod_primes(M, ps, path).tolist() == [d % q for q in ps]
 
 
 def test_int8_equals_fp64_n2048_sampled(ctx):
@@ -203,12 +235,25 @@ def test_dixon_lift_launch_forms_agree(monkeypatch):
         assert np.array_equal(X.astype(np.int64), ref)
 
 
-@pytest.mark.parametrize("bits", [26, 24])
-def test_dixon_lift_n1024_invariant(ctx, bits):
-    """Full size (the 64-bit integer form for 26-bit p, the FP64 form for
-    24-bit p): A x_i = r_i (mod p) and p | r_i - A x_i for the first steps,
-    checked with exact integers on the host (no inverse needed)."""
-    n, k = 1024, 7
+def test_dixon_lift_past_the_tag_wrap_matches_oracle(ctx):
+    """A long lifting in the FP64 three-digit form: 450 digits are 150 steps,
+    past the 127 values of the step tag that the kernel's workgroups exchange
+    with their digits; every digit equals the oracle's."""
+    n, k = 64, 450
+    A = synth.dense_uniform(n, -100, 100, 977)
+    b = synth.random_rhs(n, 1000, 977)
+    p = test_primes(1 << 24, 1 << 25, 1, 977)[0]
+    X = ctx.dixon_lift(A, b, p, k)
+    assert np.array_equal(X.astype(np.int64), oracle.dixon_digits(A, b, p, k))
+
+
+@pytest.mark.parametrize("bits,k", [(26, 7), (24, 420)])
+def test_dixon_lift_n1024_invariant(ctx, bits, k):
+    """Full size (the 64-bit integer form for 26-bit p, the FP64 three-digit
+    form for 24-bit p, there over 140 steps, past the step-tag wrap):
+    A x_i = r_i (mod p) and p | r_i - A x_i for every step, checked with
+    exact integers on the host (no inverse needed)."""
+    n = 1024
     A = synth.dense_uniform(n, 0, 255, 1024)
     b = synth.random_rhs(n, 12000, 3)
     p = test_primes(1 << (bits - 1), 1 << bits, 1, 77)[0]
@@ -267,6 +312,15 @@ def test_det_introspective_extended_bonus(ctx, n, tail, seed, i):
     _say("extended bonus n =", n, "i =", i)
     s = [1] * (n - len(tail)) + tail
     A, sign = synth.smith_matrix(s, seed, None)
+    import paper_cs_0511066_amd as det
+
+    # a fresh context (no earlier matrix in its buffers), then the shared one
+    # after a call on a matrix of another size
+    with det.Context(0) as fresh:
+        d, rep = fresh.det_introspective(A, n_rhs=i, report=True)
+    assert d == sign * math.prod(s)
+    assert rep["bonus_factors"] == i, rep
+    ctx.det_introspective(synth.dense_uniform(n + 37, -9, 9, seed), n_rhs=i)
     d, rep = ctx.det_introspective(A, n_rhs=i, report=True)
     assert d == sign * math.prod(s)
     assert d == oracle.det_bareiss(A)
@@ -363,6 +417,10 @@ def test_det_introspective_golden_n1024(ctx):
     got, rep = ctx.det_introspective(A, report=True)
     _say("n1024 report", rep)
     assert got == d
+    # the divisor from the lifting (335 three-digit steps, past the step-tag
+    # wrap) carries nearly all of det: the CRA on det / K needed few primes
+    assert rep["sn_bits"] >= abs(d).bit_length() - 64, rep
+    assert rep["primes_used"] <= 16, rep
     torch = pytest.importorskip("torch")
     assert ctx.det_introspective(torch.from_numpy(A).cuda()) == d
 

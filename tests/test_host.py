@@ -187,3 +187,57 @@ def test_context_without_gpu_reports_device_error():
     with pytest.raises(det.DetError) as e:
         det.Context(0)
     assert e.value.status == 8
+
+
+def _bonus_inputs(n, tail, seed, m, p):
+    """A Smith-form matrix with the given last invariant factors, m seeded
+    right-hand sides and combination vectors, and the m x m x k combination
+    digits R_a . x_{h,i} formed from the oracle's Dixon digits."""
+    s = [1] * (n - len(tail)) + list(tail)
+    A, _ = synth.smith_matrix(s, seed, None)
+    rng = np.random.default_rng(seed)
+    B = rng.integers(0, 64, size=(n, m), dtype=np.int64)
+    R = rng.integers(1, 1 << 16, size=(m, n), dtype=np.int64)
+    hb = oracle.hadamard_bits(A)
+    bmax = max(math.isqrt(int(sum(int(v) ** 2 for v in B[:, h]))) + 1 for h in range(m))
+    Nbits = int(R.sum(axis=1).max()).bit_length() + hb + bmax.bit_length() + 1
+    Dbits = hb
+    k = -(-(Nbits + Dbits + 2) // (p.bit_length() - 1)) + 1
+    comb = np.zeros((m, m, k), dtype=np.uint64)
+    for h in range(m):
+        X = oracle.dixon_digits(A, B[:, h], p, k)          # k x n, in [0, p)
+        for a in range(m):
+            comb[h, a] = (X @ R[a]).astype(np.uint64)      # < 2^16 * 2^25 * n: exact
+    return A, B, R, comb, Nbits, Dbits, s
+
+
+@pytest.mark.parametrize("n,tail,seed,m", [(60, [101, 101 * 103], 31, 2),
+                                           (96, [107, 107 * 109, 107 * 109 * 113], 32, 3),
+                                           (40, [1, 1], 33, 2)])
+def test_extended_bonus_host_matches_oracle(n, tail, seed, m):
+    """The host step of the extended bonus (Section 3.2) on combination
+    digits built from the oracle's Dixon digits: s~ and pi~ equal those the
+    oracle computes from the exact rational solutions, and lcm(s~, pi~)
+    divides det(A)."""
+    p = test_primes(1 << 24, 1 << 25, 1, seed)[0]
+    A, B, R, comb, Nbits, Dbits, s = _bonus_inputs(n, tail, seed, m, p)
+    got_s, got_pi, failed = det.det_host_extended_bonus(comb, p, Nbits, Dbits)
+    ref_s, ref_pi = oracle.extended_bonus(A, B, R)
+    assert failed == 0
+    assert (got_s, got_pi) == (ref_s, ref_pi)
+    d = math.prod(s)
+    assert d % math.lcm(got_s, got_pi) == 0
+    if tail[-1] > 1:                    # the m largest invariant factors, found exactly
+        assert got_pi == math.prod(s[-m:])
+
+
+def test_extended_bonus_host_reports_a_corrupted_lifting():
+    """A wrong digit in one combination's expansion makes its reconstruction
+    fail (the bounds leave no room for a spurious fraction), and the failure
+    is reported instead of entering pi~."""
+    p = test_primes(1 << 24, 1 << 25, 1, 5)[0]
+    A, B, R, comb, Nbits, Dbits, s = _bonus_inputs(60, [101, 101 * 103], 31, 2, p)
+    bad = comb.copy()
+    bad[1, 0, bad.shape[2] // 2] ^= np.uint64(1 << 7)
+    _, got_pi, failed = det.det_host_extended_bonus(bad, p, Nbits, Dbits)
+    assert failed >= 1 and got_pi == 1
