@@ -89,6 +89,30 @@ det_status det_mod_primes(det_ctx *ctx, const int64_t *A, int64_t n, int64_t lda
                           det_path path);
 
 /*
+ * det_mod_primes without device allocation, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same result as det_mod_primes(..., DET_PATH_FP64), from the
+ * same kernels, but every device buffer comes from one static 64 MiB array
+ * per device that the library holds until the process ends; no context is
+ * used and nothing is allocated.
+ *   device      HIP device to run on (made current for the call, then the
+ *               caller's current device is restored).
+ *   hip_stream  hipStream_t on that device (NULL: its null stream), borrowed.
+ *   A           DEVICE pointer, row-major n x n int64, leading dimension lda,
+ *               |a_ij| < 2^31 (checked: DET_E_OVERFLOW).
+ *   primes      host array of nprimes odd primes < 2^26.
+ *   residues    host array of nprimes outputs, det(A) mod primes[j].
+ * Returns DET_E_INVALID when A is not device memory or when the workspace of
+ * one prime at this n does not fit the array (n above about 4000); primes are
+ * processed in batches that fit.  The array keeps the last call's contents;
+ * calls that overlap on one device (other threads, other streams) race on it.
+ * The call returns after its work on hip_stream has finished.
+ */
+det_status det_mod_primes_noalloc(int device, void *hip_stream, const int64_t *A, int64_t n,
+                                  int64_t lda, const uint32_t *primes, int64_t nprimes,
+                                  uint32_t *residues);
+
+/*
  * LIF side (Section 2.2: LargestInvariantFactor solves A x = b by Dixon
  * p-adic lifting).  With r_0 = b:
  *     x_i = A^{-1} r_i mod p  in [0, p)^n,     r_{i+1} = (r_i - A x_i) / p,

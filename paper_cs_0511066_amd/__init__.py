@@ -91,6 +91,8 @@ _sig("det_introspective", c_int, [ctypes.c_void_p, ctypes.c_void_p, c_i64, c_i64
 _sig("det_batch", c_int, [ctypes.c_void_p, c_i64, P(ctypes.c_void_p), P(c_i64), P(c_i64),
                           P(det_opts), c_int, P(c_int), P(c_u32), c_i64, P(c_i64), P(c_int),
                           P(c_double)])
+_sig("det_mod_primes_noalloc", c_int, [c_int, ctypes.c_void_p, ctypes.c_void_p, c_i64, c_i64,
+                                       P(c_u32), c_i64, P(c_u32)])
 _sig("det_profile_select", c_int, [ctypes.c_void_p, c_int])
 _sig("det_profile_read", c_int, [ctypes.c_void_p, P(c_i64), P(c_double), P(c_double), P(c_double)])
 _sig("det_host_is_prime", c_int, [c_u32])
@@ -107,7 +109,7 @@ _sig("det_host_extended_bonus", c_int, [P(c_u64), c_i64, c_i64, c_u32, c_i64, c_
 
 EXPORTED = ["det_ctx_create", "det_ctx_destroy", "det_ctx_set_stream", "det_status_str",
             "det_last_error", "det_opts_default", "det_mod_primes", "dixon_lift", "dixon_lift_multi",
-            "det_introspective", "det_batch", "det_profile_select", "det_profile_read", "det_host_is_prime", "det_host_sample_primes",
+            "det_introspective", "det_batch", "det_mod_primes_noalloc", "det_profile_select", "det_profile_read", "det_host_is_prime", "det_host_sample_primes",
             "det_host_hadamard_log2", "det_host_et_run_length", "det_host_crt",
             "det_host_ratrecon", "det_host_bigint", "det_host_extended_bonus"]
 
@@ -339,6 +341,20 @@ class Context:
         if timings:
             return dets, tdone[:m].tolist()
         return dets
+
+
+def det_mod_primes_noalloc(A, primes, device: int = 0, hip_stream: int | None = None) -> np.ndarray:
+    """det(A) mod p for each prime with no device allocation by the library
+    (det_mod_primes_noalloc): A must be a torch int64 CUDA tensor."""
+    ptr, n, lda, keep = _matrix_arg(A)
+    ps = np.ascontiguousarray(np.asarray(primes, dtype=np.uint32))
+    out = np.zeros(len(ps), dtype=np.uint32)
+    st = _lib.det_mod_primes_noalloc(device, ctypes.c_void_p(hip_stream or 0), ptr, n, lda,
+                                     _u32p(ps), len(ps), _u32p(out))
+    del keep
+    if st != DET_OK:
+        raise DetError(st, "det_mod_primes_noalloc")
+    return out
 
 
 _default_ctx: Context | None = None
