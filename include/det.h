@@ -187,30 +187,57 @@ det_status det_introspective(det_ctx *ctx, const int64_t *A, int64_t n, int64_t 
                              int64_t *limb_count, det_report *report);
 
 /*
- * Many exact determinants in one call: a set of independent dense matrices
- * of any sizes (the batched workload; the paper's Section 4 algorithm run on
- * each).  Matrix i is computed as det_introspective computes it with `opts`
- * (NULL = defaults) and seed opts->seed + i, so results do not depend on the
- * schedule.  A pool of `workers` contexts on ctx's device (workers <= 0: up to
- * 8), each with its own streams and host thread, takes the matrices in
- * order, so that small determinants share the GPU.  Worker contexts are
- * created on first use and kept (and destroyed) by ctx.
+ * Many exact determinants in one call (the batched workload): a set of
+ * independent dense matrices of any orders.  Each matrix follows the
+ * early-terminated Chinese remaindering of Section 2.1 (Alg. 2.1, run length
+ * of Lemma 2.1(iv); certify = 1: up to the Hadamard bound) with its own primes,
+ * drawn from the stream seeded by opts->seed + i, so its result does not
+ * depend on the rest of the batch.  The rounds of all matrices run together:
+ * every (matrix, prime) LU item of order <= 512 of a round is one entry of a
+ * device work queue, sorted by decreasing order and run by one persistent
+ * launch (HIP graph: queue reset, launch and copies), in the launch shape
+ * that det_autotune chose for the orders present; larger matrices take the
+ * blocked batched LU of det_mod_primes beside it.  Section 6 observes that
+ * the LU runs of one CRA step are independent; so are those of different
+ * matrices.
  *   A[i]        row-major n[i] x n[i] int64, leading dimension lda[i], host or
- *               device pointer, owned by the caller and only read.
+ *               device pointer, owned by the caller and only read; |a| < 2^31.
+ *   opts        NULL = defaults; log2_inv_eps, certify, seed and prime_bits are
+ *               used (path applies to the matrices above 512).
  *   sign[i]     -1, 0 or +1.
  *   mag         count x limb_stride uint32: |det A[i]| as little-endian limbs
  *               from mag + i * limb_stride; limb_count[i] limbs are used.
  *   status[i]   per-matrix status; DET_E_BUFFER_TOO_SMALL with the needed
  *               limb count in limb_count[i] when limb_stride is too small.
- *   t_done_ms   optional: completion time of matrix i, in ms since the call
- *               started.
- * Returns DET_OK when every matrix succeeded, else the status of the first
- * failing matrix (see det_last_error).  Calls that overlap on one ctx race.
+ *   t_done_ms   optional: time at which matrix i's result was ready, in ms
+ *               since the call started.
+ * The first call on a context without a launch-shape table runs det_autotune
+ * (with the cache file named by the environment variable DET_AUTOTUNE_CACHE,
+ * if set).  Returns DET_OK when every matrix succeeded, else the status of the
+ * first failing matrix (see det_last_error).
  */
 det_status det_batch(det_ctx *ctx, int64_t count, const int64_t *const *A, const int64_t *n,
-                     const int64_t *lda, const det_opts *opts, int workers, int *sign,
-                     uint32_t *mag, int64_t limb_stride, int64_t *limb_count,
-                     det_status *status, double *t_done_ms);
+                     const int64_t *lda, const det_opts *opts, int *sign, uint32_t *mag,
+                     int64_t limb_stride, int64_t *limb_count, det_status *status,
+                     double *t_done_ms);
+
+/*
+ * Autotuner of the persistent LU kernel: for each order bucket (<= 64, 128,
+ * 256, 512) it times every launch shape (panel width 32 with one workgroup per
+ * CU, panel width 16 with one, or two with registers capped) on a seeded batch
+ * of 4 items per CU, checks that all shapes give the same residues, and keeps
+ * the fastest.
+ * cache_path (may be NULL): a JSON file read instead of measuring when it
+ * matches this device (architecture name and CU count), and written after
+ * measuring.
+ */
+det_status det_autotune(det_ctx *ctx, const char *cache_path);
+
+/* The context's launch-shape table: up to cap entries (bucket order limit,
+ * kernel variant 1 = panel width 32, 2 = width 16, 3 = width 16 two per CU;
+ * workgroups per CU; measured items per ms); *count = number of entries. */
+det_status det_autotune_read(const det_ctx *ctx, int64_t cap, int32_t *nmax, int32_t *variant,
+                             int32_t *blocks_per_cu, double *items_per_ms, int64_t *count);
 
 /*
  * Kernel timing (measurement support, not part of the method).  After

@@ -89,8 +89,11 @@ _sig("dixon_lift_multi", c_int, [ctypes.c_void_p, ctypes.c_void_p, c_i64, c_i64,
 _sig("det_introspective", c_int, [ctypes.c_void_p, ctypes.c_void_p, c_i64, c_i64, P(det_opts),
                                   P(c_int), P(c_u32), c_i64, P(c_i64), P(det_report)])
 _sig("det_batch", c_int, [ctypes.c_void_p, c_i64, P(ctypes.c_void_p), P(c_i64), P(c_i64),
-                          P(det_opts), c_int, P(c_int), P(c_u32), c_i64, P(c_i64), P(c_int),
+                          P(det_opts), P(c_int), P(c_u32), c_i64, P(c_i64), P(c_int),
                           P(c_double)])
+_sig("det_autotune", c_int, [ctypes.c_void_p, ctypes.c_char_p])
+_sig("det_autotune_read", c_int, [ctypes.c_void_p, c_i64, P(ctypes.c_int32), P(ctypes.c_int32),
+                                  P(ctypes.c_int32), P(c_double), P(c_i64)])
 _sig("det_mod_primes_noalloc", c_int, [c_int, ctypes.c_void_p, ctypes.c_void_p, c_i64, c_i64,
                                        P(c_u32), c_i64, P(c_u32)])
 _sig("det_profile_select", c_int, [ctypes.c_void_p, c_int])
@@ -109,7 +112,8 @@ _sig("det_host_extended_bonus", c_int, [P(c_u64), c_i64, c_i64, c_u32, c_i64, c_
 
 EXPORTED = ["det_ctx_create", "det_ctx_destroy", "det_ctx_set_stream", "det_status_str",
             "det_last_error", "det_opts_default", "det_mod_primes", "dixon_lift", "dixon_lift_multi",
-            "det_introspective", "det_batch", "det_mod_primes_noalloc", "det_profile_select", "det_profile_read", "det_host_is_prime", "det_host_sample_primes",
+            "det_introspective", "det_batch", "det_autotune", "det_autotune_read",
+            "det_mod_primes_noalloc", "det_profile_select", "det_profile_read", "det_host_is_prime", "det_host_sample_primes",
             "det_host_hadamard_log2", "det_host_et_run_length", "det_host_crt",
             "det_host_ratrecon", "det_host_bigint", "det_host_extended_bonus"]
 
@@ -192,8 +196,8 @@ class Context:
             h, self._h = self._h, None
             _lib.det_ctx_destroy(h)
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if _finalizing():
             return
         try:
             self.close()
@@ -299,13 +303,13 @@ class Context:
         return det
 
 
-    def det_batch(self, matrices, workers: int = 0, certify: bool = False,
-                  seed: int | None = None, log2_inv_eps: float | None = None,
-                  prime_bits: int | None = None, timings: bool = False):
+    def det_batch(self, matrices, certify: bool = False, seed: int | None = None,
+                  log2_inv_eps: float | None = None, prime_bits: int | None = None,
+                  timings: bool = False):
         """Exact determinants of a list of square int64 matrices (numpy or
         torch CUDA tensors of any sizes) in one det_batch call.  Returns the
-        list of determinants, and with timings=True also the completion time
-        of each matrix in ms since the call started."""
+        list of determinants, and with timings=True also the time at which
+        each result was ready, in ms since the call started."""
         args = [_matrix_arg(A) for A in matrices]
         m = len(args)
         o = det_opts()
@@ -328,9 +332,8 @@ class Context:
             stat = np.zeros(max(m, 1), dtype=np.int32)
             tdone = np.zeros(max(m, 1), dtype=np.float64)
             st = _lib.det_batch(self._h, m, ptrs, _i64p(ns), _i64p(ldas), ctypes.byref(o),
-                                int(workers), sign.ctypes.data_as(P(c_int)), _u32p(mag), stride,
-                                _i64p(cnt), stat.ctypes.data_as(P(c_int)),
-                                tdone.ctypes.data_as(P(c_double)))
+                                sign.ctypes.data_as(P(c_int)), _u32p(mag), stride, _i64p(cnt),
+                                stat.ctypes.data_as(P(c_int)), tdone.ctypes.data_as(P(c_double)))
             if st == 7 and np.any(stat[:m] == 7):
                 stride = int(cnt[:m].max())
                 continue
@@ -341,6 +344,26 @@ class Context:
         if timings:
             return dets, tdone[:m].tolist()
         return dets
+
+    def autotune(self, cache_path: str | None = None) -> list[dict]:
+        """Run (or load from cache_path) the launch-shape autotuner of the
+        persistent LU kernel (det_autotune); returns the table."""
+        self._check(_lib.det_autotune(self._h, cache_path.encode() if cache_path else None))
+        return self.autotune_table()
+
+    def autotune_table(self) -> list[dict]:
+        cap = 16
+        nm = np.zeros(cap, dtype=np.int32)
+        va = np.zeros(cap, dtype=np.int32)
+        bp = np.zeros(cap, dtype=np.int32)
+        ip = np.zeros(cap, dtype=np.float64)
+        cnt = c_i64(0)
+        i32 = P(ctypes.c_int32)
+        self._check(_lib.det_autotune_read(self._h, cap, nm.ctypes.data_as(i32), va.ctypes.data_as(i32),
+                                           bp.ctypes.data_as(i32), ip.ctypes.data_as(P(c_double)),
+                                           ctypes.byref(cnt)))
+        return [{"nmax": int(nm[i]), "variant": int(va[i]), "blocks_per_cu": int(bp[i]),
+                 "items_per_ms": float(ip[i])} for i in range(min(cap, cnt.value))]
 
 
 def det_mod_primes_noalloc(A, primes, device: int = 0, hip_stream: int | None = None) -> np.ndarray:

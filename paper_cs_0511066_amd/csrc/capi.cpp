@@ -24,16 +24,12 @@
 #include "bigint.hpp"
 #include "host_numerics.hpp"
 #include "kernels.hpp"
+#include "ctx.hpp"
 
 using dethost::BigInt;
 using detk::Modulus;
 
 namespace {
-
-struct DevBuf {
-  void* p = nullptr;
-  size_t cap = 0;
-};
 
 constexpr int NB_OUTER = 128;      // outer block (trailing-update depth K) of large batches
 constexpr int TINV_LD = 128;       // leading dimension of the outer triangular inverses
@@ -42,177 +38,6 @@ constexpr int MAX_N = 4096;
 // panel's own L11^{-1} serves the triangular solve); larger batches use outer
 // blocks of NB_OUTER columns so that the trailing update contracts over 128.
 constexpr int TWO_LEVEL_MIN_ITEMS = 64;
-
-double now_ms() {
-  using namespace std::chrono;
-  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
-}
-
-// Device workspace of one batched LU, bound to one stream.
-// Pinned host memory for the small transfers of the path: an asynchronous
-// copy from pageable memory can hold the host until earlier work drains,
-// which would serialize the two streams of a context.
-struct PinBuf {
-  void* p = nullptr;
-  size_t cap = 0;
-};
-
-struct LuWs {
-  DevBuf W, piv, flags, mods, linv, uinv, tinv, limbA, limbB, res, modsr, cnt;
-  PinBuf hmods;                 // pinned host copy of the moduli (async uploads)
-  hipStream_t st = nullptr;
-};
-
-}  // namespace
-
-struct det_ctx {
-  int device = 0;
-  size_t budget = 0;
-  size_t held = 0;
-  hipStream_t own = nullptr;     // the context's stream (default for ws[0])
-  hipStream_t own2 = nullptr;    // second stream: CRA batches beside the Dixon solve
-  hipStream_t st = nullptr;      // current stream of ws[0] (own or the caller's)
-  hipEvent_t ev = nullptr;       // orders own2 after work queued on st
-  hipEvent_t ev_cra = nullptr;   // the same for the first CRA batch (enqueued by a second thread)
-  std::mutex mu;                 // the error text, the budget count, the kernel timing state
-  std::string err;
-  LuWs ws[2];
-  DevBuf Adev, norms, amax, Cu, Ai, r, rp, x, digits, comb, cvec, sync, C1, E, rp1, x1, C2, Ed,
-      rv, xv;
-  uint32_t* hres = nullptr;      // pinned host residues of the background batch
-  size_t hres_cap = 0;
-  PinBuf hstage;                 // pinned staging of the lifting's vectors and results
-  PinBuf hsmall;                 // pinned flags and error words read back on st
-  int lift_mode = 0;             // 0: fastest cooperative form that applies; 1: one launch per
-                                 // phase; 2: the 64-bit integer form modulo p^2
-  // kernel timing (det_profile_select / det_profile_read)
-  int prof_kind = 0;
-  int64_t prof_launches = 0;
-  double prof_bytes = 0, prof_ops = 0;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_pending;
-  std::vector<hipEvent_t> ev_pool;
-  std::vector<det_ctx*> pool;    // worker contexts of det_batch (created on first use)
-};
-
-namespace {
-
-det_status fail(det_ctx* c, det_status s, const std::string& msg) {
-  if (c) {
-    std::lock_guard<std::mutex> lk(c->mu);
-    c->err = msg;
-  }
-  return s;
-}
-
-#define HIPCHK(expr)                                                                    \
-  do {                                                                                  \
-    hipError_t e_ = (expr);                                                             \
-    if (e_ != hipSuccess)                                                               \
-      return fail(c, DET_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
-  } while (0)
-
-#define TRY(expr)                     \
-  do {                                \
-    det_status s_ = (expr);           \
-    if (s_ != DET_OK) return s_;      \
-  } while (0)
-
-// Grow-only device buffer used on stream `st`; the previous contents are not kept.
-det_status ensure(det_ctx* c, DevBuf& b, size_t bytes, hipStream_t st) {
-  if (bytes == 0) bytes = 16;
-  if (b.cap >= bytes) return DET_OK;
-  {
-    std::lock_guard<std::mutex> lk(c->mu);
-    if (c->budget && c->held - b.cap + bytes > c->budget) {
-      c->err = "device workspace would exceed the context's HBM budget";
-      return DET_E_NOMEM;
-    }
-  }
-  HIPCHK(hipStreamSynchronize(st));
-  if (b.p) {
-    HIPCHK(hipFree(b.p));
-    {
-      std::lock_guard<std::mutex> lk(c->mu);
-      c->held -= b.cap;
-    }
-    b.p = nullptr;
-    b.cap = 0;
-  }
-  hipError_t e = hipMalloc(&b.p, bytes);
-  if (e != hipSuccess) {
-    b.p = nullptr;
-    (void)hipGetLastError();
-    return fail(c, DET_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
-  }
-  b.cap = bytes;
-  std::lock_guard<std::mutex> lk(c->mu);
-  c->held += bytes;
-  return DET_OK;
-}
-
-det_status ensure(det_ctx* c, DevBuf& b, size_t bytes) { return ensure(c, b, bytes, c->st); }
-
-// Grow a pinned host buffer; `st` is the stream whose copies may still read it.
-det_status ensure_pin(det_ctx* c, PinBuf& b, size_t bytes, hipStream_t st) {
-  if (b.cap >= bytes) return DET_OK;
-  if (b.p) {
-    HIPCHK(hipStreamSynchronize(st));
-    HIPCHK(hipHostFree(b.p));
-    b.p = nullptr;
-    b.cap = 0;
-  }
-  const size_t cap = std::max<size_t>(bytes, 4096);
-  if (hipHostMalloc(&b.p, cap, hipHostMallocDefault) != hipSuccess) {
-    (void)hipGetLastError();
-    b.p = nullptr;
-    return fail(c, DET_E_NOMEM, "hipHostMalloc failed");
-  }
-  b.cap = cap;
-  return DET_OK;
-}
-
-// Brackets one launch with HIP events on its stream when its kernel class is
-// the selected one; the counts are the launcher's algorithmic bytes and ops.
-struct ProfScope {
-  det_ctx* c;
-  hipStream_t st;
-  hipEvent_t e1 = nullptr;
-  ProfScope(det_ctx* ctx, int kind, double bytes, double ops, hipStream_t stream)
-      : c(ctx), st(stream) {
-    std::lock_guard<std::mutex> lk(c->mu);
-    if (c->prof_kind != kind) return;
-    hipEvent_t e0 = take(), e = take();
-    if (!e0 || !e) return;
-    if (hipEventRecord(e0, st) != hipSuccess) return;
-    e1 = e;
-    c->prof_pending.push_back({e0, e1});
-    c->prof_launches++;
-    c->prof_bytes += bytes;
-    c->prof_ops += ops;
-  }
-  ~ProfScope() {
-    if (e1) (void)hipEventRecord(e1, st);
-  }
-  hipEvent_t take() {
-    if (!c->ev_pool.empty()) {
-      hipEvent_t e = c->ev_pool.back();
-      c->ev_pool.pop_back();
-      return e;
-    }
-    hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
-    return e;
-  }
-};
-
-bool is_device_ptr(const void* p) {
-  hipPointerAttribute_t attr;
-  if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
-    (void)hipGetLastError();
-    return false;
-  }
-  return attr.type == hipMemoryTypeDevice;
-}
 
 // Largest K such that K h^2 + h <= 2^53 with h = (pmax - 1)/2: FP64 sums of
 // that many products of centred residues are exact.
@@ -291,12 +116,15 @@ det_status gemm_update(det_ctx* c, LuWs& w, const LuJob& J, int64_t offC, int64_
 
 // ncols_sw > 0: the panel also applies its row swaps to the columns
 // [j0 + pb, ncols_sw) right of it.
+// rows_end > 0: the panel searches its pivots only in rows [j0, rows_end)
+// (the diagonal block when the update forms L21 itself).
 det_status panel_step(det_ctx* c, LuWs& w, const LuJob& J, const Panel& P, int32_t* uinv, int kc,
-                      int ncols_sw = 0) {
-  const double m = J.n - P.j0;
+                      int ncols_sw = 0, int rows_end = 0) {
+  const int nr = rows_end > 0 ? rows_end : J.n;
+  const double m = nr - P.j0;
   ProfScope ps(c, DET_KERNEL_PANEL, 8.0 * m * P.pb * J.nitems, m * P.pb * P.pb * (double)J.nitems,
                w.st);
-  HIPCHK(detk::launch_panel((int32_t*)w.W.p, J.ldw, J.slab, J.n, P.j0, P.pb, P.pbw,
+  HIPCHK(detk::launch_panel((int32_t*)w.W.p, J.ldw, J.slab, nr, P.j0, P.pb, P.pbw,
                             (const Modulus*)w.mods.p, (int32_t*)w.piv.p, J.n,
                             (int32_t*)w.flags.p, (int32_t*)w.linv.p, uinv, kc, J.nitems,
                             ncols_sw, w.st));
@@ -320,8 +148,14 @@ det_status trsm_step(det_ctx* c, LuWs& w, const LuJob& J, int r0, int kb, int c0
 // layout).  W, piv, flags, mods of `w` must already hold residues and moduli.
 // With keep_uinv (single item, single-level) the inverse of every panel's U11
 // is kept in w.uinv for the back substitution; `panels` lists the panels.
+// block_pivots (with keep_uinv, FP64): each panel looks for its pivots only in
+// its diagonal block and the update forms L21 = A21 U11^{-1}; a column whose
+// block has no non-zero entry raises the item's flag (the caller then runs
+// the full pivot search).  Whenever no flag is raised the factors are those
+// of an LU with the same row order, so the inverse and the determinant are
+// unchanged: both are unique.
 det_status lu_factor(det_ctx* c, LuWs& w, const LuJob& J, bool keep_uinv,
-                     std::vector<Panel>* panels) {
+                     std::vector<Panel>* panels, bool block_pivots = false) {
   const int n = J.n, ncols = J.ncols, nit = J.nitems;
   const int64_t ldw = J.ldw;
   const int kc = exact_chunk(J.pmax);
@@ -356,7 +190,8 @@ det_status lu_factor(det_ctx* c, LuWs& w, const LuJob& J, bool keep_uinv,
       const Panel P{j0, pb, pbw};
       if (idx >= npan_max) return fail(c, DET_E_INVALID, "panel count overflow");
       int32_t* uinv = keep_uinv ? (int32_t*)w.uinv.p + (size_t)idx * nit * 32 * 32 : nullptr;
-      TRY(panel_step(c, w, J, P, uinv, kc, fused ? ncols : 0));
+      const bool bp = block_pivots && fused && uinv != nullptr;
+      TRY(panel_step(c, w, J, P, uinv, kc, fused ? ncols : 0, bp ? j0 + pb : 0));
       if (panels) panels->push_back(P);
       const int right = ncols - (j0 + pb);
       if (fused) {
@@ -365,7 +200,7 @@ det_status lu_factor(det_ctx* c, LuWs& w, const LuJob& J, bool keep_uinv,
                      4.0 * ((double)M * pb + (double)pb * right + 2.0 * (double)M * right) * nit,
                      2.0 * ((double)M + pb) * right * pb * nit, w.st);
         HIPCHK(detk::launch_lu_update((int32_t*)w.W.p, J.slab, ldw, j0, pb, M, right, linv, pbw,
-                                      (const Modulus*)w.mods.p, kc4,
+                                      bp ? uinv : nullptr, (const Modulus*)w.mods.p, kc4,
                                       cnt ? cnt + (size_t)idx * nit * cstride : nullptr, cstride,
                                       nit, w.st));
       } else {
@@ -626,15 +461,25 @@ det_status inverse_mod_p(det_ctx* c, const int64_t* dA, int64_t dlda, int n, uin
   TRY(ensure(c, w.mods, sizeof(Modulus), w.st));
   TRY(ensure(c, c->Cu, (size_t)n * n * sizeof(uint32_t)));
   HIPCHK(hipMemcpyAsync(w.mods.p, hm, sizeof(Modulus), hipMemcpyHostToDevice, w.st));
-  HIPCHK(hipMemsetAsync(w.flags.p, 0, sizeof(int32_t), w.st));
-  HIPCHK(detk::launch_residues(dA, dlda, n, 2 * n, (int32_t*)w.W.p, J.ldw, J.slab,
-                               (const Modulus*)w.mods.p, 1, w.st));
   std::vector<Panel> panels;
-  TRY(lu_factor(c, w, J, true, &panels));
   int32_t* flag = (int32_t*)c->hres;
-  HIPCHK(hipMemcpyAsync(flag, w.flags.p, sizeof(int32_t), hipMemcpyDeviceToHost, w.st));
-  HIPCHK(hipStreamSynchronize(w.st));
-  if (*flag) return fail(c, DET_E_SINGULAR_MOD_P, "p divides det(A)");
+  // first with pivots searched inside each diagonal block only (the panels
+  // then take a few rows instead of all of them); if some block column has
+  // no non-zero entry, again with the full pivot search, whose flag means
+  // that p divides det(A)
+  for (int attempt = 0; attempt < 2; attempt++) {
+    const bool block_pivots = attempt == 0 && c->block_pivots;
+    if (attempt == 1 && !c->block_pivots) break;
+    HIPCHK(hipMemsetAsync(w.flags.p, 0, sizeof(int32_t), w.st));
+    HIPCHK(detk::launch_residues(dA, dlda, n, 2 * n, (int32_t*)w.W.p, J.ldw, J.slab,
+                                 (const Modulus*)w.mods.p, 1, w.st));
+    TRY(lu_factor(c, w, J, true, &panels, block_pivots));
+    HIPCHK(hipMemcpyAsync(flag, w.flags.p, sizeof(int32_t), hipMemcpyDeviceToHost, w.st));
+    HIPCHK(hipStreamSynchronize(w.st));
+    if (!*flag) break;
+    if (!block_pivots) return fail(c, DET_E_SINGULAR_MOD_P, "p divides det(A)");
+    c->block_pivot_retries++;
+  }
   int64_t col = n;
   if (fast) TRY(inverse_from_lu(c, w, J, &col));
   else TRY(back_substitute(c, w, J, panels, 1));
@@ -893,6 +738,16 @@ det_status ensure_pinned(det_ctx* c, size_t count) {
 
 }  // namespace
 
+// Entry points of the driver used by the batched and serving sources.
+det_status drv_residues(det_ctx* c, LuWs& w, const int64_t* dA, int64_t dlda, int n,
+                        const uint32_t* primes, int64_t np, uint32_t* out, det_path path) {
+  return residues_core(c, w, dA, dlda, n, primes, np, out, path, true);
+}
+
+det_status drv_check_primes(det_ctx* c, const uint32_t* primes, int64_t np, uint32_t limit) {
+  return check_prime_list(c, primes, np, limit);
+}
+
 // ====================================================================== C ABI
 extern "C" {
 
@@ -941,22 +796,30 @@ det_status det_ctx_create(int device, size_t hbm_budget_bytes, det_ctx** out) {
   c->st = c->own;
   c->ws[0].st = c->own;
   c->ws[1].st = c->own2;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+    c->cus = prop.multiProcessorCount;
+    snprintf(c->arch, sizeof(c->arch), "%s", prop.gcnArchName);
+  }
+  if (c->cus <= 0) c->cus = 1;
   const char* lm = getenv("DET_LIFT_MODE");     // "kernels": one launch per lifting phase
   if (lm && strcmp(lm, "kernels") == 0) c->lift_mode = 1;
   if (lm && strcmp(lm, "p2") == 0) c->lift_mode = 2;
+  const char* bpv = getenv("DET_BLOCK_PIVOTS");   // "0": the inverse always searches whole columns
+  c->block_pivots = !(bpv && strcmp(bpv, "0") == 0);
   *out = c;
   return DET_OK;
 }
 
 void det_ctx_destroy(det_ctx* c) {
   if (!c) return;
-  for (det_ctx* w : c->pool) det_ctx_destroy(w);
   (void)hipSetDevice(c->device);
   if (c->st) (void)hipStreamSynchronize(c->st);
   if (c->own2) (void)hipStreamSynchronize(c->own2);
   std::vector<DevBuf*> all = {&c->Adev, &c->norms, &c->amax, &c->Cu, &c->Ai, &c->r, &c->rp,
                               &c->x, &c->digits, &c->comb, &c->cvec, &c->sync, &c->C1, &c->E,
-                              &c->rp1, &c->x1, &c->C2, &c->Ed, &c->rv, &c->xv};
+                              &c->rp1, &c->x1, &c->C2, &c->Ed, &c->rv, &c->xv, &c->q_items,
+                              &c->q_next, &c->q_ws, &c->q_aux, &c->q_out, &c->q_mats};
   for (LuWs& w : c->ws)
     for (DevBuf* b : {&w.W, &w.piv, &w.flags, &w.mods, &w.linv, &w.uinv, &w.tinv, &w.limbA,
                       &w.limbB, &w.res, &w.modsr, &w.cnt})
@@ -964,13 +827,15 @@ void det_ctx_destroy(det_ctx* c) {
   for (DevBuf* b : all)
     if (b->p) (void)hipFree(b->p);
   if (c->hres) (void)hipHostFree(c->hres);
-  for (PinBuf* pb : {&c->hstage, &c->hsmall, &c->ws[0].hmods, &c->ws[1].hmods})
+  for (PinBuf* pb : {&c->hstage, &c->hsmall, &c->ws[0].hmods, &c->ws[1].hmods, &c->q_hitems,
+                     &c->q_hout})
     if (pb->p) (void)hipHostFree(pb->p);
   for (auto& pr : c->prof_pending) {
     (void)hipEventDestroy(pr.first);
     (void)hipEventDestroy(pr.second);
   }
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  if (c->q_exec) (void)hipGraphExecDestroy(c->q_exec);
   if (c->ev) (void)hipEventDestroy(c->ev);
   if (c->ev_cra) (void)hipEventDestroy(c->ev_cra);
   if (c->own) (void)hipStreamDestroy(c->own);
@@ -985,59 +850,6 @@ det_status det_ctx_set_stream(det_ctx* c, void* hip_stream) {
   c->st = hip_stream ? (hipStream_t)hip_stream : c->own;
   c->ws[0].st = c->st;
   return DET_OK;
-}
-
-det_status det_batch(det_ctx* c, int64_t count, const int64_t* const* A, const int64_t* n,
-                     const int64_t* lda, const det_opts* opts, int workers, int* sign,
-                     uint32_t* mag, int64_t limb_stride, int64_t* limb_count, det_status* status,
-                     double* t_done_ms) {
-  if (!c) return DET_E_INVALID;
-  if (count < 0 || limb_stride < 0 || (limb_stride > 0 && count > 0 && !mag))
-    return fail(c, DET_E_INVALID, "invalid argument");
-  if (count == 0) return DET_OK;
-  if (!A || !n || !lda || !sign || !limb_count || !status)
-    return fail(c, DET_E_INVALID, "invalid argument");
-  try {
-    const int W = (int)std::max<int64_t>(1, std::min<int64_t>(count, workers > 0 ? workers : 8));
-    while ((int)c->pool.size() < W) {
-      det_ctx* w = nullptr;
-      const det_status s = det_ctx_create(c->device, c->budget, &w);
-      if (s != DET_OK) return fail(c, s, "cannot create a worker context");
-      c->pool.push_back(w);
-    }
-    det_opts o;
-    det_opts_default(&o);
-    if (opts) o = *opts;
-    std::atomic<int64_t> next{0};
-    const auto t0 = std::chrono::steady_clock::now();
-    auto work = [&](det_ctx* w) {
-      (void)hipSetDevice(w->device);
-      for (;;) {
-        const int64_t i = next.fetch_add(1);
-        if (i >= count) break;
-        det_opts oi = o;
-        oi.seed = o.seed + (uint64_t)i;
-        status[i] = det_introspective(w, A[i], n[i], lda[i], &oi, &sign[i],
-                                      limb_stride > 0 ? mag + i * limb_stride : nullptr,
-                                      limb_stride, &limb_count[i], nullptr);
-        if (t_done_ms)
-          t_done_ms[i] = std::chrono::duration<double, std::milli>(
-                             std::chrono::steady_clock::now() - t0).count();
-      }
-    };
-    std::vector<std::thread> threads;
-    for (int k = 1; k < W; k++) threads.emplace_back(work, c->pool[k]);
-    work(c->pool[0]);
-    for (auto& t : threads) t.join();
-    for (int64_t i = 0; i < count; i++)
-      if (status[i] != DET_OK)
-        return fail(c, status[i], "matrix " + std::to_string(i) + ": " + det_status_str(status[i]));
-    return DET_OK;
-  } catch (const std::exception& e) {
-    return fail(c, DET_E_NOMEM, e.what());
-  } catch (...) {
-    return fail(c, DET_E_INVALID, "unexpected error");
-  }
 }
 
 void det_opts_default(det_opts* o) {

@@ -18,9 +18,12 @@ hipError_t launch_panel(int32_t* W, int64_t ldw, int64_t slab, int n, int j0, in
 // One LU step's update of the trailing block in one launch (U12 from L11^{-1}
 // A12 per column tile, stored by the last reader when cnt != null; A22 -=
 // L21 U12); the panel's swaps already applied (launch_panel with ncols_sw).
+// Uinv != null: the panel factored only its diagonal block, and L21 is formed
+// as A21 U11^{-1} inside the update (U11^{-1} from the panel, ldt x ldt).
 hipError_t launch_lu_update(int32_t* W, int64_t slab, int64_t ldw, int j0, int pb, int M, int N,
-                            const int32_t* Linv, int ldt, const Modulus* mods, int kc4,
-                            unsigned* cnt, int cnt_stride, int nitems, hipStream_t st);
+                            const int32_t* Linv, int ldt, const int32_t* Uinv,
+                            const Modulus* mods, int kc4, unsigned* cnt, int cnt_stride,
+                            int nitems, hipStream_t st);
 int panel_width_for(int m);
 hipError_t launch_swaps(int32_t* W, int64_t ldw, int64_t slab, int j0, int pb, const int32_t* piv,
                         int64_t piv_stride, int c0a, int c1a, int c0b, int c1b, int nitems,
@@ -103,6 +106,37 @@ hipError_t launch_lift_resident2(int grid, const uint32_t* C0, const uint32_t* C
                                  uint32_t* xb0, uint32_t* xb1, int n, uint32_t p, uint64_t pinv64,
                                  int64_t kd, uint32_t* digits, const uint32_t* cvec,
                                  uint64_t* comb, unsigned* bar, int* err, hipStream_t st);
+
+// Persistent LU over a work queue (batch_kernels.hip).  One item is one
+// (matrix, prime) pair: A device row-major int64 with leading dimension lda,
+// order n <= lu_queue_max_n(variant), odd prime p < 2^26; the result
+// det(A) mod p goes to out[out_index].
+struct LuItem {
+  const int64_t* A;
+  int64_t lda;
+  int32_t n;
+  uint32_t p;
+  int32_t out_index;
+  int32_t pad;
+};
+// Kernel variants, all for orders up to 512: panel width 32 (one workgroup
+// per CU), panel width 16 (one per CU), panel width 16 compiled for two
+// workgroups per CU (registers capped at 256 a lane).
+enum { LU_QUEUE_PB32 = 1, LU_QUEUE_PB16 = 2, LU_QUEUE_PB16X2 = 3 };
+int lu_queue_max_n(int variant);
+int lu_queue_blocks_per_cu(int variant);          // resident workgroups per CU at most
+int64_t lu_queue_aux_stride();                    // int32 per workgroup in `aux`
+// Slab stride (int32) per workgroup for orders up to nmax.
+inline int64_t lu_queue_ws_stride(int nmax) {
+  return ((int64_t)(nmax + 63) / 64 * 64 + 4) * nmax;
+}
+// next[0 .. count) = 0 (a kernel, so that it can be captured in a graph).
+hipError_t launch_queue_reset(unsigned* next, int count, hipStream_t st);
+// `grid` workgroups take items[next[0]++] until the queue is empty; ws: grid
+// slabs of ws_stride int32; aux: grid x lu_queue_aux_stride() int32.
+hipError_t launch_lu_queue(int variant, int grid, const LuItem* items, int nitems, unsigned* next,
+                           int32_t* ws, int64_t ws_stride, int32_t* aux, uint32_t* out,
+                           hipStream_t st);
 
 hipError_t launch_pack_i32(const int64_t* A, int64_t lda, int n, int32_t* Ai, hipStream_t st);
 hipError_t launch_norms(const int64_t* A, int64_t lda, int n, double* out2n, double* amax,

@@ -389,9 +389,15 @@ __global__ void k_place_diag(int32_t* __restrict__ W, int64_t ldw, int64_t offV,
 // kept (a determinant needs only the diagonal).  The panel's row swaps must
 // already be applied to these columns.  Sums are reduced every kc4 MFMA
 // k-steps (exact chunking).
+// With Uinv != null the panel factored only the pb x pb diagonal block (no
+// pivot search below it) and the rows below still hold A21: every workgroup
+// forms its rows' multipliers L21 = A21 U11^{-1} first (U11^{-1} from the
+// panel, dense ldt x ldt per item); they are not stored (neither a
+// determinant nor the inverse from [A | I] reads L).
 __global__ __launch_bounds__(256) void k_lu_update(int32_t* __restrict__ W, int64_t slab,
                                                    int64_t ldw, int j0, int pb, int M, int N,
                                                    const int32_t* __restrict__ Linv, int ldt,
+                                                   const int32_t* __restrict__ Uinv,
                                                    const Modulus* __restrict__ mods, int kc4,
                                                    unsigned* __restrict__ cnt, int cnt_stride) {
   const int z = blockIdx.z;
@@ -405,12 +411,20 @@ __global__ __launch_bounds__(256) void k_lu_update(int32_t* __restrict__ W, int6
   __shared__ double sA[GB_K][GB_M + 2];                 // L21 tile, k-major
   __shared__ double sB[GB_K][GB_N + 2];                 // A12 tile, then U12
   __shared__ double sT[32][33];                         // L11^{-1}
+  __shared__ double sU[32][33];                         // U11^{-1} (no-pivot mode)
   __shared__ int s_last;
   // all loads at once: L11^{-1}, A12, L21 and the old values of the tile
   const int32_t* Tz = Linv + (int64_t)z * ldt * ldt;
   for (int e = t; e < 32 * 32; e += 256) {
     const int r = e >> 5, c = e & 31;
     sT[r][c] = (r < pb && c < pb) ? (double)Tz[r * ldt + c] : 0.0;
+  }
+  if (Uinv != nullptr) {
+    const int32_t* Uz = Uinv + (int64_t)z * ldt * ldt;
+    for (int e = t; e < 32 * 32; e += 256) {
+      const int r = e >> 5, c = e & 31;
+      sU[r][c] = (r < pb && c < pb) ? (double)Uz[r * ldt + c] : 0.0;
+    }
   }
   int32_t va[GB_M * GB_K / 256], vb[GB_K * GB_N / 256], vc[2][2][4];
 #pragma unroll
@@ -444,6 +458,36 @@ __global__ __launch_bounds__(256) void k_lu_update(int32_t* __restrict__ W, int6
     sB[f / GB_N][f % GB_N] = (double)vb[u];
   }
   __syncthreads();
+  if (Uinv != nullptr) {
+    // L21 = A21 U11^{-1} (64 x 32): wave w the rows 16 w .. 16 w + 15, two
+    // 16 x 16 MFMA blocks; written back into sA (k-major) after every wave
+    // has read A21
+    v4d l2[2];
+    l2[0] = l2[1] = (v4d){0.0, 0.0, 0.0, 0.0};
+    int steps = 0;
+#pragma unroll
+    for (int ks = 0; ks < 32; ks += 4) {
+      const int kr = ks + (lane >> 4);
+      const double af = sA[kr][wave * 16 + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < 2; j++)
+        l2[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af, sU[kr][j * 16 + (lane & 15)], l2[j], 0, 0, 0);
+      if (++steps == kc4) {
+        steps = 0;
+#pragma unroll
+        for (int j = 0; j < 2; j++)
+#pragma unroll
+          for (int r = 0; r < 4; r++) l2[j][r] = mod_c(l2[j][r], p, pinv);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 2; j++)
+#pragma unroll
+      for (int r = 0; r < 4; r++)
+        sA[j * 16 + (lane & 15)][wave * 16 + (lane >> 4) + 4 * r] = mod_c(l2[j][r], p, pinv);
+    __syncthreads();
+  }
   // U12 = L11^{-1} A12 (32 x 64): wave w the 16 x 32 block (rows 16 (w >> 1),
   // columns 32 (w & 1)), two 16 x 16 MFMA blocks
   v4d u2[2];
@@ -949,13 +993,14 @@ hipError_t launch_gemm_f64(int32_t* W, int64_t slab, int64_t offC, int64_t offA,
 }
 
 hipError_t launch_lu_update(int32_t* W, int64_t slab, int64_t ldw, int j0, int pb, int M, int N,
-                            const int32_t* Linv, int ldt, const Modulus* mods, int kc4,
-                            unsigned* cnt, int cnt_stride, int nitems, hipStream_t st) {
+                            const int32_t* Linv, int ldt, const int32_t* Uinv,
+                            const Modulus* mods, int kc4, unsigned* cnt, int cnt_stride,
+                            int nitems, hipStream_t st) {
   if (M < 0 || N <= 0 || nitems <= 0) return hipSuccess;
   if (pb < 1 || pb > 32 || pb > ldt || kc4 < 1) return hipErrorInvalidValue;
   dim3 grid((N + GB_N - 1) / GB_N, std::max(1, (M + GB_M - 1) / GB_M), nitems);
   if (cnt != nullptr && (int)grid.x > cnt_stride) return hipErrorInvalidValue;
-  k_lu_update<<<grid, 256, 0, st>>>(W, slab, ldw, j0, pb, M, N, Linv, ldt, mods, kc4, cnt,
+  k_lu_update<<<grid, 256, 0, st>>>(W, slab, ldw, j0, pb, M, N, Linv, ldt, Uinv, mods, kc4, cnt,
                                     cnt_stride);
   LAUNCH_CHECK();
   return hipSuccess;

@@ -174,8 +174,8 @@ extern "C" det_status det_mod_primes_noalloc(int device, void* hip_stream, const
                              nullptr, kc, nit, nn, st) != hipSuccess)
         return DET_E_DEVICE;
       const int rest = nn - (j0 + pb);
-      if (detk::launch_lu_update(W, L.slab, L.ldw, j0, pb, rest, rest, linv, pbw, mods, kc4,
-                                 nullptr, 0, nit, st) != hipSuccess)
+      if (detk::launch_lu_update(W, L.slab, L.ldw, j0, pb, rest, rest, linv, pbw, nullptr, mods,
+                                 kc4, nullptr, 0, nit, st) != hipSuccess)
         return DET_E_DEVICE;
       j0 += pb;
     }

@@ -404,15 +404,66 @@ def test_is_prime_trial_division():
 
 
 # ---------------------------------------------------------------- planted mistakes
-def test_pins_catch_a_planted_sign_error(monkeypatch):
-    """A row-swap sign slip planted into the oracle must fail the pins."""
-    A = np.array([[0, 1, 2], [3, 4, 5], [6, 7, 9]])
-    good = oracle.det_bareiss(A)
-    assert good == det_cofactor(A)
+def _pins_hold(det) -> bool:
+    """The determinant pins of this file, run against a candidate `det`:
+    cofactor expansion (matrices with zero leading entries, so row swaps
+    happen), triangular products, det(AB) = det(A) det(B), a row swap flips
+    the sign, and Smith-form constructions with a known determinant."""
+    try:
+        rng = np.random.default_rng(2024)
+        for n in (3, 4, 5, 6):
+            for _ in range(4):
+                A = rng.integers(-9, 10, size=(n, n))
+                A[0, 0] = 0
+                if det(A) != det_cofactor(A):
+                    return False
+        T = np.triu(rng.integers(-9, 10, size=(7, 7)))
+        if det(T) != int(np.prod([int(v) for v in np.diag(T)])):
+            return False
+        A = rng.integers(-5, 6, size=(6, 6))
+        B = rng.integers(-5, 6, size=(6, 6))
+        if det(A @ B) != det(A) * det(B):
+            return False
+        S = A.copy()
+        S[[1, 4]] = S[[4, 1]]
+        if det(S) != -det(A):
+            return False
+        M, sign = synth.smith_matrix([1, 1, 2, 6, 30], 5, 0.5)
+        if det(M) != sign * 360:
+            return False
+    except Exception:          # a planted slip may also break the exact division
+        return False
+    return True
+
+
+# each mutation is one plausible slip in the elimination: a dropped sign
+# flip, a transposed operand, a wrong pivot divisor, an off-by-one index, a
+# lost pivot search
+_MUTATIONS = [
+    ("sign = -sign", "sign = sign"),
+    ("akk * rowi[j] - aik * rowk[j]", "aik * rowk[j] - akk * rowi[j]"),
+    ("prev = akk", "prev = 1"),
+    ("aik * rowk[j]", "aik * rowk[j - 1]"),
+    ("return sign * M[n - 1][n - 1]", "return sign * M[n - 1][n - 2]"),
+    ("if M[k][k] == 0:", "if False:"),
+]
+
+
+@pytest.mark.parametrize("old,new", _MUTATIONS)
+def test_pins_catch_a_planted_mistake(old, new):
+    """A slip planted into a copy of the oracle's Bareiss elimination fails
+    the pins, while the oracle itself passes them."""
+    import inspect
+    import textwrap
+
     from oracle import det_oracle as m
 
-    src_bad = lambda B: abs(m.det_bareiss(B))     # noqa: E731  (drops the sign)
-    assert src_bad(A) != det_cofactor(A)
+    assert _pins_hold(m.det_bareiss)
+    src = textwrap.dedent(inspect.getsource(m.det_bareiss))
+    assert old in src
+    ns = {"np": np}
+    exec(compile(src.replace(old, new), "<mutant>", "exec"), ns)
+    assert not _pins_hold(ns["det_bareiss"])
 
 
 def test_extended_bonus_recovers_the_last_invariant_factors():
