@@ -7,7 +7,12 @@ trailing updates on MFMA), the inverse mod p and the Dixon lifting steps,
 then early-terminated Chinese remaindering on the host.  Prints one JSON line.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-mfma]
-                    [--no-multi] [--copy-probe MIB]
+                    [--no-multi] [--no-batch] [--no-precision] [--copy-probe MIB]
+
+Besides the headline line it reports, in the same JSON object, the batched
+workload (256 matrices in one det_batch call against one at a time), the
+precision workload (n = 2048, int8 limbs against FP64 on the same primes) and
+the trailing-update throughput of the full Hadamard-bound CRA at n = 1024.
 
 --copy-probe MIB ends the run with three plain device-to-device copies of MIB
 MiB each (the reference kernel that scales the HBM byte counters).
@@ -92,24 +97,124 @@ def roofline_entry(kernel, prof):
             "ops_per_launch": prof["ops"] / prof["launches"]}
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(A, n_full):
-    """The oracle (plain C Bareiss over big integers) on the leading n_s x n_s
-    block of the same matrix, scaled to n_full by the n^5 bit-cost of
-    schoolbook Bareiss (n^3 updates on numbers of O(n) words)."""
+    """The oracle (plain C Bareiss over big integers, OpenMP over the rows of
+    each step) on two leading blocks of the same matrix; the growth exponent
+    e of its time is fitted from the two and the larger block's time is
+    scaled by (n_full / n_2)^e."""
     import oracle
 
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    threads = max(1, min(threads, os.cpu_count() or 1, 16))
-    n_s = 448
-    sub = A[:n_s, :n_s].copy()
+    threads = max(1, min(threads, os.cpu_count() or 1))
     oracle.build_bareiss_c(force=False)
-    t0 = time.perf_counter()
-    oracle.det_bareiss_c(sub, threads=threads)
-    t = time.perf_counter() - t0
-    est = t * (n_full / n_s) ** 5
+    times = {}
+    for n_s in (320, 448):
+        sub = A[:n_s, :n_s].copy()
+        t0 = time.perf_counter()
+        oracle.det_bareiss_c(sub, threads=threads)
+        times[n_s] = time.perf_counter() - t0
+    e = math.log(times[448] / times[320]) / math.log(448 / 320)
+    est = times[448] * (n_full / 448) ** e
     return {"value": 1.0 / est, "unit": "dets/s", "cores": threads, "kind": "oracle",
-            "sample": f"C Bareiss on the leading {n_s}x{n_s} block of the n={n_full} matrix took "
-                      f"{t:.2f} s; scaled by (n/{n_s})^5 to {est:.0f} s per n={n_full} det"}
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+            "sample": f"C Bareiss on the leading 320x320 and 448x448 blocks of the n={n_full} "
+                      f"matrix took {times[320]:.2f} s and {times[448]:.2f} s; fitted exponent "
+                      f"{e:.2f}; scaled to {est:.0f} s per n={n_full} det"}
+
+
+def batched_leg(det, ctx, torch, synth, oracle, np):
+    """The batched workload: 256 matrices, orders log-uniform in [32, 512],
+    entries uniform in [-128, 127], resident in HBM; one det_batch call
+    against the same matrices run one at a time with det_introspective."""
+    sizes = synth.batched_sizes(256, 32, 512, 3)
+    mats = [torch.from_numpy(synth.dense_uniform(n, -128, 127, 3000 + i)).cuda()
+            for i, n in enumerate(sizes)]
+    tune_path = os.path.join("/tmp", "det_autotune_%d.json" % os.getpid())
+    table = ctx.autotune(tune_path)
+    ctx.det_batch(mats[:16])                     # warm-up
+    runs = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        dets, tdone = ctx.det_batch(mats, timings=True)
+        runs.append((time.perf_counter() - t0, dets, tdone))
+    runs.sort(key=lambda r: r[0])
+    mk, dets, tdone = runs[1]
+    svc = []
+    plain = []
+    for A in mats:
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        plain.append(ctx.det_introspective(A))
+        svc.append(1e3 * (time.perf_counter() - a))
+    if plain != dets:
+        raise SystemExit("batched determinants differ from one-at-a-time determinants")
+    small = [i for i, n in enumerate(sizes) if n <= 40][:8]
+    for i in small:
+        if dets[i] != oracle.det_bareiss(mats[i].cpu().numpy()):
+            raise SystemExit("batched determinant differs from the oracle")
+    fifo = np.cumsum(svc)
+    return {"workload": "256 dense matrices, n log-uniform in [32,512], entries uniform [-128,127], "
+                        "seed 3, HBM-resident",
+            "batched": {"makespan_ms": round(1e3 * mk, 3), "dets_per_s": round(256 / mk, 1),
+                        "latency_p50_ms": round(float(np.percentile(tdone, 50)), 3),
+                        "latency_p99_ms": round(float(np.percentile(tdone, 99)), 3)},
+            "plain_one_at_a_time": {"total_ms": round(float(fifo[-1]), 3),
+                                    "dets_per_s": round(256e3 / float(fifo[-1]), 1),
+                                    "service_p50_ms": round(float(np.percentile(svc, 50)), 3),
+                                    "service_p99_ms": round(float(np.percentile(svc, 99)), 3),
+                                    "fifo_latency_p50_ms": round(float(np.percentile(fifo, 50)), 3),
+                                    "fifo_latency_p99_ms": round(float(np.percentile(fifo, 99)), 3)},
+            "equal_to_plain": True, "checked_against_oracle": len(small),
+            "autotune": table}
+
+
+def precision_leg(det, ctx, torch, synth, np):
+    """The precision workload: n = 2048, entries uniform in [-1024, 1024],
+    the primes near 2^23 of a deterministic Hadamard-bound CRT; every residue
+    on the int8-limb path and on the FP64 path, compared bit for bit."""
+    n = 2048
+    A = synth.dense_uniform(n, -1024, 1024, 2048)
+    At = torch.from_numpy(A).cuda()
+    hb = det.det_host_hadamard_log2(A)
+    count = int(math.ceil((hb + 1) / 22.0)) + 1
+    primes = det.det_host_sample_primes(2048, 23, count)
+    out = {"workload": f"dense n={n}, entries uniform [-1024,1024], seed 2048, {count} primes "
+                       "in (2^22, 2^23) (Hadamard bound)", "primes": count}
+    res = {}
+    for path, kern in (("int8", "gemm_i8"), ("fp64", "gemm_f64")):
+        ctx.det_mod_primes(At, primes[:4], path)
+        ctx.profile_select(kern)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        res[path] = ctx.det_mod_primes(At, primes, path)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        pr = ctx.profile_read()
+        ctx.profile_select("none")
+        mod_macs = (pr["ops"] / 18.0) if kern == "gemm_i8" else pr["ops"] / 2.0
+        out[path] = {"wall_ms": round(1e3 * (tb - ta), 2),
+                     "residues_per_s": round(count / (tb - ta), 1),
+                     "trailing_update_ms": round(pr["ms"], 3),
+                     "modular_tops": round(2.0 * mod_macs / (pr["ms"] / 1e3) / 1e12, 3),
+                     "mfma_tops": round(pr["ops"] / (pr["ms"] / 1e3) / 1e12, 3),
+                     "peak_tops": PEAK_TOPS[kern],
+                     "frac_of_peak": round(pr["ops"] / (pr["ms"] / 1e3) / 1e12 / PEAK_TOPS[kern], 4)}
+    out["paths_bit_identical"] = res["int8"].tolist() == res["fp64"].tolist()
+    if not out["paths_bit_identical"]:
+        raise SystemExit("int8 and FP64 residues differ at n=2048")
+    out["int8_over_fp64_wall"] = round(out["fp64"]["wall_ms"] / out["int8"]["wall_ms"], 3)
+    return out
 
 
 def main():
@@ -120,6 +225,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mfma", action="store_true")
     ap.add_argument("--no-multi", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -230,6 +337,19 @@ def main():
                  "lift_ms_per_rhs_ratio": round(two["ms"] / 2.0 / one["ms"], 3)}
         log("multi-rhs lifting:", multi)
 
+    batched = None
+    if not args.no_batch:
+        import oracle
+        log("batched workload ...")
+        batched = batched_leg(det, ctx, torch, synth, oracle, np)
+        log("batched:", batched)
+
+    precision = None
+    if not args.no_precision:
+        log("precision workload ...")
+        precision = precision_leg(det, ctx, torch, synth, np)
+        log("precision:", precision)
+
     cpu = None
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
@@ -256,6 +376,8 @@ def main():
                    "kernel_ms_per_det": {k: round(v["ms"], 3) for k, v in breakdown.items()}},
         "roofline": roof,
         "mfma_trailing_update": mfma,
+        "batched": batched,
+        "precision": precision,
         "multi_rhs_lift": multi,
         "cpu_baseline": cpu,
     }

@@ -255,7 +255,7 @@ typedef enum {
   DET_KERNEL_LIFT_X = 1,     /* x_i = A^{-1} r_i mod p                  */
   DET_KERNEL_LIFT_R = 2,     /* r_{i+1} = (r_i - A x_i) / p             */
   DET_KERNEL_GEMM_F64 = 3,   /* trailing update on FP64 MFMA            */
-  DET_KERNEL_GEMM_I8 = 4,    /* trailing update on int8 MFMA (3 limbs)  */
+  DET_KERNEL_GEMM_I8 = 4,    /* trailing update on int8 MFMA (3 limbs; the limb splits included) */
   DET_KERNEL_PANEL = 5,      /* panel factorisation                     */
   DET_KERNEL_TRSM = 6,       /* in-place triangular apply               */
   DET_KERNEL_TRI_INV = 7,    /* diagonal-block triangular inverse       */

@@ -28,13 +28,12 @@
 
 #include "../../include/det.h"
 #include "bigint.hpp"
+#include "cra.hpp"
 #include "ctx.hpp"
 #include "host_numerics.hpp"
 #include "kernels.hpp"
 
 using dethost::BigInt;
-
-namespace {
 
 constexpr int QUEUE_BUCKETS[] = {64, 128, 256, 512};
 
@@ -121,7 +120,7 @@ det_status queue_start(det_ctx* c, std::vector<detk::LuItem>& items, std::vector
 }
 
 // Residue of the item at queue position q, or 0xFFFFFFFF while it runs.
-inline uint32_t queue_result(const det_ctx* c, int32_t q) {
+uint32_t queue_result(const det_ctx* c, int32_t q) {
   return __atomic_load_n((const uint32_t*)c->q_hout.p + q, __ATOMIC_ACQUIRE);
 }
 
@@ -140,25 +139,21 @@ det_status run_queue(det_ctx* c, std::vector<detk::LuItem>& items, uint32_t* out
   return DET_OK;
 }
 
+namespace {
+
 bool graphs_enabled() {
   const char* g = getenv("DET_BATCH_GRAPH");
   return !(g && strcmp(g, "0") == 0);
 }
 
-// One matrix of a batch and its Chinese remaindering state.
+// One matrix of a batch: its staged copy and its Chinese remaindering.
 struct Mat {
   const int64_t* dA = nullptr;
   int64_t dlda = 0;
   int n = 0;
   dethost::Bounds bd;
-  std::unique_ptr<dethost::PrimeSampler> samp;
-  dethost::CrtState crt;
-  int64_t kET = 0;
-  int64_t cert = 0;          // primes that reach the deterministic bound 2H
-  int64_t drawn = 0;
+  dethost::CraJob job;
   bool done = false;
-  std::vector<uint32_t> ps;  // this round's primes, in draw order
-  int64_t res0 = 0;          // their residues at res[res0 ..)
 };
 
 // ---- the autotuner's cache file: one line a bucket after a header line
@@ -371,8 +366,6 @@ det_status det_batch(det_ctx* c, int64_t count, const int64_t* const* A, const i
     }
     // ---- per-matrix Chinese remaindering set-up (Alg. 2.1, Lemma 2.1(iv))
     const int bits = o.prime_bits;
-    const double log2_l = (double)(bits - 1);
-    const double psize = dethost::prime_set_size(bits);
     int64_t left = 0;
     auto emit = [&](int64_t i, const BigInt& v) {
       std::vector<uint32_t> l = v.limbs32();
@@ -389,12 +382,7 @@ det_status det_batch(det_ctx* c, int64_t count, const int64_t* const* A, const i
         m.done = true;
         continue;
       }
-      uint64_t seed = o.seed + (uint64_t)i;
-      m.samp.reset(new dethost::PrimeSampler(dethost::splitmix64(seed), bits));
-      const double logl_H = std::max(1.0, m.bd.log2_h / log2_l);
-      m.kET = dethost::et_run_length(o.log2_inv_eps, psize, logl_H);
-      if (m.kET < 0) m.kET = INT64_MAX;
-      m.cert = (int64_t)ceil((m.bd.log2_h + 2.0) / log2_l) + 1;
+      m.job.init(m.bd, m.n, o.seed + (uint64_t)i, bits, o.log2_inv_eps, o.certify != 0);
       left++;
     }
     // ---- rounds
@@ -408,31 +396,15 @@ det_status det_batch(det_ctx* c, int64_t count, const int64_t* const* A, const i
       for (int64_t i = 0; i < count; i++) {
         Mat& m = M[i];
         if (m.done) continue;
-        int64_t want;
-        if (round == 0) {
-          // first round: the primes that reach the expected size of |det|
-          // for dense matrices (log2 H minus n log2(e) / 2) plus the run
-          // length; certify: the deterministic bound
-          const double est = std::max(1.0, m.bd.log2_h - 0.5 * m.n * 1.4426950408889634 + 32.0);
-          want = o.certify ? m.cert
-                           : std::min<int64_t>(m.cert, (int64_t)ceil(est / log2_l) + std::min<int64_t>(m.kET, 64) + 1);
-        } else {
-          const double need = (m.bd.log2_h + 2.0 - (double)(m.crt.M.bit_length() - 1)) / log2_l;
-          want = std::min<int64_t>(std::max<int64_t>((int64_t)ceil(need) + 1, 4), 4096);
-          if (!o.certify) want = std::min<int64_t>(want, std::max<int64_t>(2 * std::min<int64_t>(m.kET, 64), 8));
-        }
-        want = std::max<int64_t>(want, 1);
-        m.ps.resize(want);
-        for (auto& q : m.ps) q = m.samp->next();
-        m.drawn += want;
-        m.res0 = nres;
+        const int64_t want = m.job.next_count();
+        m.job.draw(want, nres);
         nres += want;
         if (m.n > qmax) {
           big.push_back(i);
           continue;
         }
         for (int64_t k = 0; k < want; k++)
-          items.push_back(detk::LuItem{m.dA, m.dlda, m.n, m.ps[k], (int32_t)(m.res0 + k), 0});
+          items.push_back(detk::LuItem{m.dA, m.dlda, m.n, m.job.ps[k], (int32_t)(m.job.res0 + k), 0});
       }
       res.assign(nres, 0);
       // smallest orders first: their matrices complete early, and with many
@@ -453,8 +425,9 @@ det_status det_batch(det_ctx* c, int64_t count, const int64_t* const* A, const i
           (void)hipSetDevice(c->device);
           for (int64_t i : big) {
             Mat& m = M[i];
-            const det_status s = drv_residues(c, c->ws[1], m.dA, m.dlda, m.n, m.ps.data(),
-                                              (int64_t)m.ps.size(), res.data() + m.res0, o.path);
+            const det_status s = drv_residues(c, c->ws[1], m.dA, m.dlda, m.n, m.job.ps.data(),
+                                              (int64_t)m.job.ps.size(), res.data() + m.job.res0,
+                                              o.path);
             if (s != DET_OK) {
               big_st = s;
               return;
@@ -469,29 +442,24 @@ det_status det_batch(det_ctx* c, int64_t count, const int64_t* const* A, const i
       // keeps running
       auto finish = [&](int64_t i) {
         Mat& m = M[i];
-        for (size_t k = 0; k < m.ps.size() && !m.done; k++) {
-          m.crt.add(m.ps[k], res[m.res0 + k]);
-          if ((double)(m.crt.M.bit_length() - 1) >= m.bd.log2_h + 2.0) m.done = true;
-          else if (!o.certify && m.crt.same >= m.kET) m.done = true;
-        }
-        m.ps.clear();
-        if (m.done) {
-          emit(i, m.crt.r);
+        if (m.job.absorb(res.data())) {
+          m.done = true;
+          emit(i, m.job.crt.r);
           left--;
         }
       };
       std::vector<int64_t> pend;
       for (int64_t i = 0; i < count; i++)
-        if (!M[i].done && !M[i].ps.empty() && M[i].n <= qmax) pend.push_back(i);
+        if (!M[i].done && !M[i].job.ps.empty() && M[i].n <= qmax) pend.push_back(i);
       while (qs == DET_OK && !pend.empty()) {
         size_t keep = 0;
         for (size_t u = 0; u < pend.size(); u++) {
           Mat& m = M[pend[u]];
           bool all = true;
-          for (size_t k = 0; k < m.ps.size() && all; k++) {
-            const uint32_t v = queue_result(c, qpos[m.res0 + k]);
+          for (size_t k = 0; k < m.job.ps.size() && all; k++) {
+            const uint32_t v = queue_result(c, qpos[m.job.res0 + k]);
             if (v == 0xFFFFFFFFu) all = false;
-            else res[m.res0 + k] = v;
+            else res[m.job.res0 + k] = v;
           }
           if (all) finish(pend[u]);
           else pend[keep++] = pend[u];
@@ -505,7 +473,8 @@ det_status det_batch(det_ctx* c, int64_t count, const int64_t* const* A, const i
             // the queue is done: every slot is written
             for (int64_t i : pend) {
               Mat& m = M[i];
-              for (size_t k = 0; k < m.ps.size(); k++) res[m.res0 + k] = queue_result(c, qpos[m.res0 + k]);
+              for (size_t k = 0; k < m.job.ps.size(); k++)
+                res[m.job.res0 + k] = queue_result(c, qpos[m.job.res0 + k]);
               finish(i);
             }
             pend.clear();

@@ -96,12 +96,13 @@ det_status gemm_update(det_ctx* c, LuWs& w, const LuJob& J, int64_t offC, int64_
     const int64_t pslabA = 3LL * M * Kp, pslabB = 3LL * N * Kp;
     TRY(ensure(c, w.limbA, (size_t)nit * pslabA, w.st));
     TRY(ensure(c, w.limbB, (size_t)nit * pslabB, w.st));
+    // the timed interval covers the limb splits as well as the products
+    ProfScope ps(c, DET_KERNEL_GEMM_I8, (3.0 * Kp * ((double)M + N) + 8.0 * M * N) * nit,
+                 18.0 * M * N * K * nit, w.st);
     HIPCHK(detk::launch_split(W, J.slab, offA, J.ldw, M, K, Kp, 0, (int8_t*)w.limbA.p, pslabA, nit,
                               w.st));
     HIPCHK(detk::launch_split(W, J.slab, offB, J.ldw, N, K, Kp, 1, (int8_t*)w.limbB.p, pslabB, nit,
                               w.st));
-    ProfScope ps(c, DET_KERNEL_GEMM_I8, (3.0 * Kp * ((double)M + N) + 8.0 * M * N) * nit,
-                 18.0 * M * N * K * nit, w.st);
     HIPCHK(detk::launch_gemm_i8(W, J.slab, offC, J.ldw, M, N, (const int8_t*)w.limbA.p,
                                 (const int8_t*)w.limbB.p, pslabA, pslabB, Kp, mods, nit, w.st));
   } else {
@@ -167,6 +168,8 @@ det_status lu_factor(det_ctx* c, LuWs& w, const LuJob& J, bool keep_uinv,
   // reads item 0's)
   if (keep_uinv)
     TRY(ensure(c, w.uinv, (size_t)npan_max * nit * 32 * 32 * sizeof(int32_t), w.st));
+  else if (block_pivots)
+    TRY(ensure(c, w.uinv, (size_t)nit * 32 * 32 * sizeof(int32_t), w.st));
   const int32_t* linv = (const int32_t*)w.linv.p;
   if (panels) panels->clear();
   if (!two_level) {
@@ -189,9 +192,20 @@ det_status lu_factor(det_ctx* c, LuWs& w, const LuJob& J, bool keep_uinv,
       const int pb = std::min(pbw, n - j0);
       const Panel P{j0, pb, pbw};
       if (idx >= npan_max) return fail(c, DET_E_INVALID, "panel count overflow");
-      int32_t* uinv = keep_uinv ? (int32_t*)w.uinv.p + (size_t)idx * nit * 32 * 32 : nullptr;
+      // U11^{-1}: kept per panel for the inverse, else (block pivots) one
+      // slot per item reused by every step
+      int32_t* uinv = keep_uinv ? (int32_t*)w.uinv.p + (size_t)idx * nit * 32 * 32
+                                : (block_pivots ? (int32_t*)w.uinv.p : nullptr);
       const bool bp = block_pivots && fused && uinv != nullptr;
-      TRY(panel_step(c, w, J, P, uinv, kc, fused ? ncols : 0, bp ? j0 + pb : 0));
+      if (bp && pbw == 32) {
+        // the diagonal block alone, one wave per item (no row swaps)
+        ProfScope ps(c, DET_KERNEL_PANEL, 8.0 * pb * pb * nit, (double)pb * pb * pb * nit, w.st);
+        HIPCHK(detk::launch_diag_block((int32_t*)w.W.p, ldw, J.slab, j0, pb,
+                                       (const Modulus*)w.mods.p, (int32_t*)w.piv.p, n,
+                                       (int32_t*)w.flags.p, (int32_t*)w.linv.p, uinv, nit, w.st));
+      } else {
+        TRY(panel_step(c, w, J, P, uinv, kc, fused ? ncols : 0, bp ? j0 + pb : 0));
+      }
       if (panels) panels->push_back(P);
       const int right = ncols - (j0 + pb);
       if (fused) {
@@ -370,13 +384,28 @@ bool use_int8(det_path path, int64_t nitems, uint32_t pmax) {
   return nitems >= TWO_LEVEL_MIN_ITEMS && pmax < (1u << 23);
 }
 
+// Flags of a batch whose block-pivot check is left to the caller: primes
+// [s0, s0 + count) of the call; flags (pinned host memory, valid after the
+// workspace's stream is synchronized) non-zero where the block-pivot LU met a
+// block column without a non-zero entry, so that the residue must be
+// recomputed with the full pivot search.
+struct Deferred {
+  const int32_t* flags = nullptr;
+  int64_t s0 = 0, count = 0;
+};
+
 // Modular determinants of a staged device matrix for a list of primes, in
-// batches bounded by the workspace, on workspace w.  With `wait` false the
-// last batch's residues are copied asynchronously into `out` (which must then
-// be pinned memory) and the caller synchronizes w.st.
+// batches bounded by the workspace, on workspace w.  Single-level FP64
+// batches first search pivots in each diagonal block (as the inverse does);
+// a batch that meets a block column without a non-zero entry is computed
+// again with the full search (allow_block false forces the full search).
+// With `wait` false the last batch's residues are copied asynchronously into
+// `out` (which must then be pinned memory), the caller synchronizes w.st and,
+// when *deferred has a count, checks its flags and recomputes flagged primes.
 det_status residues_core(det_ctx* c, LuWs& w, const int64_t* dA, int64_t dlda, int n,
                          const uint32_t* primes, int64_t np, uint32_t* out, det_path path,
-                         bool wait = true) {
+                         bool wait = true, Deferred* deferred = nullptr, bool allow_block = true) {
+  if (deferred) *deferred = Deferred();
   if (np == 0) return DET_OK;
   if (n == 0) {
     for (int64_t i = 0; i < np; i++) out[i] = 1 % primes[i];
@@ -397,12 +426,14 @@ det_status residues_core(det_ctx* c, LuWs& w, const int64_t* dA, int64_t dlda, i
     J.pmax = 0;
     HIPCHK(hipStreamSynchronize(w.st));             // the previous upload from hmods is done
     TRY(ensure_pin(c, w.hmods, (size_t)nit * sizeof(Modulus), w.st));
+    TRY(ensure_pin(c, w.hflags, (size_t)nit * sizeof(int32_t), w.st));
     Modulus* hm = (Modulus*)w.hmods.p;
     for (int i = 0; i < nit; i++) {
       hm[i] = modulus_of(primes[s0 + i]);
       J.pmax = std::max(J.pmax, primes[s0 + i]);
     }
     J.int8 = use_int8(path, nit, J.pmax);
+    const bool block = allow_block && c->block_pivots && !J.int8 && nit < TWO_LEVEL_MIN_ITEMS;
     TRY(ensure(c, w.W, (size_t)nit * J.slab * sizeof(int32_t), w.st));
     TRY(ensure(c, w.piv, (size_t)nit * n * sizeof(int32_t), w.st));
     TRY(ensure(c, w.flags, (size_t)nit * sizeof(int32_t), w.st));
@@ -415,12 +446,37 @@ det_status residues_core(det_ctx* c, LuWs& w, const int64_t* dA, int64_t dlda, i
       HIPCHK(detk::launch_residues(dA, dlda, n, n, (int32_t*)w.W.p, J.ldw, J.slab,
                                    (const Modulus*)w.mods.p, nit, w.st));
     }
-    TRY(lu_factor(c, w, J, false, nullptr));
+    TRY(lu_factor(c, w, J, false, nullptr, block));
     HIPCHK(detk::launch_det_finalize((const int32_t*)w.W.p, J.ldw, J.slab, n,
                                      (const int32_t*)w.piv.p, n, (const int32_t*)w.flags.p,
                                      (const Modulus*)w.mods.p, (uint32_t*)w.res.p, nit, w.st));
     HIPCHK(hipMemcpyAsync(out + s0, w.res.p, nit * sizeof(uint32_t), hipMemcpyDeviceToHost, w.st));
-    if (wait || s0 + nit < np) HIPCHK(hipStreamSynchronize(w.st));
+    if (block)
+      HIPCHK(hipMemcpyAsync(w.hflags.p, w.flags.p, nit * sizeof(int32_t), hipMemcpyDeviceToHost,
+                            w.st));
+    const bool last = s0 + nit >= np;
+    if (!wait && last) {
+      if (block && deferred) {
+        deferred->flags = (const int32_t*)w.hflags.p;
+        deferred->s0 = s0;
+        deferred->count = nit;
+      } else if (block) {
+        HIPCHK(hipStreamSynchronize(w.st));     // no caller check: check here
+      } else {
+        continue;
+      }
+      if (deferred) continue;
+    } else {
+      HIPCHK(hipStreamSynchronize(w.st));
+    }
+    if (block) {
+      bool any = false;
+      for (int i = 0; i < nit; i++) any |= ((const int32_t*)w.hflags.p)[i] != 0;
+      if (any) {
+        c->block_pivot_retries++;
+        TRY(residues_core(c, w, dA, dlda, n, primes + s0, nit, out + s0, path, true, nullptr, false));
+      }
+    }
   }
   return DET_OK;
 }
@@ -741,7 +797,7 @@ det_status ensure_pinned(det_ctx* c, size_t count) {
 // Entry points of the driver used by the batched and serving sources.
 det_status drv_residues(det_ctx* c, LuWs& w, const int64_t* dA, int64_t dlda, int n,
                         const uint32_t* primes, int64_t np, uint32_t* out, det_path path) {
-  return residues_core(c, w, dA, dlda, n, primes, np, out, path, true);
+  return residues_core(c, w, dA, dlda, n, primes, np, out, path, true, nullptr, true);
 }
 
 det_status drv_check_primes(det_ctx* c, const uint32_t* primes, int64_t np, uint32_t limit) {
@@ -827,8 +883,8 @@ void det_ctx_destroy(det_ctx* c) {
   for (DevBuf* b : all)
     if (b->p) (void)hipFree(b->p);
   if (c->hres) (void)hipHostFree(c->hres);
-  for (PinBuf* pb : {&c->hstage, &c->hsmall, &c->ws[0].hmods, &c->ws[1].hmods, &c->q_hitems,
-                     &c->q_hout})
+  for (PinBuf* pb : {&c->hstage, &c->hsmall, &c->ws[0].hmods, &c->ws[1].hmods, &c->ws[0].hflags,
+                     &c->ws[1].hflags, &c->q_hitems, &c->q_hout})
     if (pb->p) (void)hipHostFree(pb->p);
   for (auto& pr : c->prof_pending) {
     (void)hipEventDestroy(pr.first);
@@ -1149,11 +1205,12 @@ det_status det_introspective(det_ctx* c, const int64_t* A, int64_t n, int64_t ld
     // the Dixon solve's launches start at once.  It uses only ws[1], own2 and
     // hres1; it is joined before anything waits for own2.
     det_status cra_st = DET_OK;
+    Deferred cra_def;
     std::thread cra_thread([&] {
       try {
         (void)hipSetDevice(c->device);
         cra_st = residues_core(c, c->ws[1], dA, dlda, (int)n, ps1.data(), batch1, hres1, o.path,
-                               false);
+                               false, &cra_def);
       } catch (...) {
         cra_st = DET_E_NOMEM;
       }
@@ -1257,6 +1314,17 @@ det_status det_introspective(det_ctx* c, const int64_t* A, int64_t n, int64_t ld
     cra_join.join();
     TRY(cra_st);
     HIPCHK(hipStreamSynchronize(c->own2));
+    if (cra_def.count) {
+      // a prime whose block-pivot LU met an all-zero block column: again
+      // with the full pivot search
+      bool any = false;
+      for (int64_t i = 0; i < cra_def.count; i++) any |= cra_def.flags[i] != 0;
+      if (any) {
+        c->block_pivot_retries++;
+        TRY(residues_core(c, c->ws[1], dA, dlda, (int)n, ps1.data() + cra_def.s0, cra_def.count,
+                          hres1 + cra_def.s0, o.path, true, nullptr, false));
+      }
+    }
     std::vector<uint32_t> ps(ps1), rs(hres1, hres1 + batch1);
     rep.et_rounds = 1;
     int64_t batch = batch1;

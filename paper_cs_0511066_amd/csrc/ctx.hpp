@@ -37,6 +37,7 @@ struct PinBuf {
 struct LuWs {
   DevBuf W, piv, flags, mods, linv, uinv, tinv, limbA, limbB, res, modsr, cnt;
   PinBuf hmods;                 // pinned host copy of the moduli (async uploads)
+  PinBuf hflags;                // pinned copy of the batch's flags (block-pivot check)
   hipStream_t st = nullptr;
 };
 
@@ -231,3 +232,13 @@ inline bool is_device_ptr(const void* p) {
 det_status drv_residues(det_ctx* c, LuWs& w, const int64_t* dA, int64_t dlda, int n,
                         const uint32_t* primes, int64_t np, uint32_t* out, det_path path);
 det_status drv_check_primes(det_ctx* c, const uint32_t* primes, int64_t np, uint32_t limit);
+
+// The persistent LU queue (batch.cpp): its autotuned launch shape for items
+// of orders up to nmax; starting a set of items on stream st (each residue
+// then appears in mapped host memory at the item's queue position, which
+// qpos maps from the items' out_index); and reading one residue (0xFFFFFFFF
+// while it runs).
+void queue_shape(const det_ctx* c, int nmax, int* variant, int* grid_per_cu);
+det_status queue_start(det_ctx* c, std::vector<detk::LuItem>& items, std::vector<int32_t>* qpos,
+                       hipStream_t st, bool graph, int variant, int grid_per_cu);
+uint32_t queue_result(const det_ctx* c, int32_t q);

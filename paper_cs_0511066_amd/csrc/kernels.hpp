@@ -25,6 +25,13 @@ hipError_t launch_lu_update(int32_t* W, int64_t slab, int64_t ldw, int j0, int p
                             const Modulus* mods, int kc4, unsigned* cnt, int cnt_stride,
                             int nitems, hipStream_t st);
 int panel_width_for(int m);
+// The pb x pb diagonal block at (j0, j0) of every item (pb <= 32) factored
+// without pivot search below it: U11 into W, L11^{-1} and U11^{-1} dense
+// 32 x 32 (Linv, Uinv + z * 1024), piv = identity on the block, flags[z] = 1
+// when a pivot is 0 mod p.
+hipError_t launch_diag_block(int32_t* W, int64_t ldw, int64_t slab, int j0, int pb,
+                             const Modulus* mods, int32_t* piv, int64_t piv_stride, int32_t* flags,
+                             int32_t* Linv, int32_t* Uinv, int nitems, hipStream_t st);
 hipError_t launch_swaps(int32_t* W, int64_t ldw, int64_t slab, int j0, int pb, const int32_t* piv,
                         int64_t piv_stride, int c0a, int c1a, int c0b, int c1b, int nitems,
                         hipStream_t st);
