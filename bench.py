@@ -7,11 +7,13 @@ trailing updates on MFMA), the inverse mod p and the Dixon lifting steps,
 then early-terminated Chinese remaindering on the host.  Prints one JSON line.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-mfma]
-                    [--no-multi] [--no-batch] [--no-precision] [--copy-probe MIB]
+                    [--no-multi] [--no-batch] [--no-precision] [--no-serve]
+                    [--copy-probe MIB]
 
 Besides the headline line it reports, in the same JSON object, the batched
 workload (256 matrices in one det_batch call against one at a time), the
-precision workload (n = 2048, int8 limbs against FP64 on the same primes) and
+serving workload (a Poisson request stream at three loads against a plain
+one-at-a-time server), the precision workload (n = 2048, int8 limbs against FP64 on the same primes) and
 the trailing-update throughput of the full Hadamard-bound CRA at n = 1024.
 
 --copy-probe MIB ends the run with three plain device-to-device copies of MIB
@@ -179,6 +181,84 @@ def batched_leg(det, ctx, torch, synth, oracle, np):
             "autotune": table}
 
 
+def serving_requests(synth, np, count, seed):
+    """The serving stream's matrices: n uniform in [64, 1536]; 70% dense with
+    entries uniform in [-1000, 1000], 30% U diag(s) V with a few non-trivial
+    invariant factors (host arrays: requests come from clients)."""
+    rng = np.random.default_rng(seed)
+    mats = []
+    for i in range(count):
+        n = int(rng.integers(64, 1537))
+        if rng.random() < 0.3:
+            A, _, _ = synth.structured_serving(n, seed * 1000 + i)
+        else:
+            A = synth.dense_uniform(n, -1000, 1000, seed * 1000 + i)
+        mats.append(A)
+    return mats
+
+
+def serving_leg(det, ctx, synth, np, count=96):
+    """The serving workload: a Poisson stream of requests at 0.5, 0.8 and 0.95
+    of the server's measured sustained rate, against a plain server that runs
+    det_introspective one request at a time in arrival order (simulated from
+    each request's measured service time on the same arrival times)."""
+    import threading
+    mats = serving_requests(synth, np, count, 5)
+    svc, plain = [], []
+    for A in mats:
+        a = time.perf_counter()
+        plain.append(ctx.det_introspective(A))
+        svc.append(1e3 * (time.perf_counter() - a))
+    budget = 256 << 20                       # admission binds: about 16 large matrices resident
+
+    def serve(arrivals):
+        with det.Server(ctx, hbm_budget_bytes=budget) as srv:
+            ids = [None] * count
+            t0 = time.perf_counter()
+
+            def feed():
+                for i, ta in enumerate(arrivals):
+                    dt = ta - (time.perf_counter() - t0)
+                    if dt > 0:
+                        time.sleep(dt)
+                    ids[i] = srv.submit(mats[i])
+            th = threading.Thread(target=feed)
+            th.start()
+            th.join()
+            out = [srv.poll(i, -1) for i in ids]
+            wall = time.perf_counter() - t0
+            stats = srv.stats()
+        dets = [o[1] for o in out]
+        if dets != plain:
+            raise SystemExit("served determinants differ from one-at-a-time determinants")
+        return [o[2] for o in out], wall, stats
+
+    lat0, wall0, _ = serve([0.0] * count)
+    rate = count / wall0
+    out = {"workload": f"{count} requests, n uniform in [64,1536], 70% dense entries uniform "
+                       "[-1000,1000], 30% U diag(s) V, seed 5, host inputs",
+           "hbm_budget_bytes": budget, "sustained_req_per_s": round(rate, 2),
+           "plain_req_per_s": round(count / (sum(svc) / 1e3), 2), "loads": []}
+    for f in (0.5, 0.8, 0.95):
+        arr = synth.poisson_arrivals(count, f * rate, 55)
+        lat, wall, st = serve(list(arr))
+        end, pl = 0.0, []
+        for ta, sv in zip(arr * 1e3, svc):
+            start = max(ta, end)
+            end = start + sv
+            pl.append(end - ta)
+        out["loads"].append({
+            "offered_fraction": f, "offered_req_per_s": round(f * rate, 2),
+            "served": {"p50_ms": round(float(np.percentile(lat, 50)), 2),
+                       "p99_ms": round(float(np.percentile(lat, 99)), 2),
+                       "req_per_s": round(count / wall, 2), "max_admitted": st["max_admitted"],
+                       "hbm_peak_bytes": st["hbm_peak"]},
+            "plain_fifo": {"p50_ms": round(float(np.percentile(pl, 50)), 2),
+                           "p99_ms": round(float(np.percentile(pl, 99)), 2)}})
+    out["equal_to_plain"] = True
+    return out
+
+
 def precision_leg(det, ctx, torch, synth, np):
     """The precision workload: n = 2048, entries uniform in [-1024, 1024],
     the primes near 2^23 of a deterministic Hadamard-bound CRT; every residue
@@ -227,6 +307,7 @@ def main():
     ap.add_argument("--no-multi", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -350,6 +431,12 @@ def main():
         precision = precision_leg(det, ctx, torch, synth, np)
         log("precision:", precision)
 
+    serving = None
+    if not args.no_serve:
+        log("serving workload ...")
+        serving = serving_leg(det, ctx, synth, np)
+        log("serving:", serving)
+
     cpu = None
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
@@ -378,6 +465,7 @@ def main():
         "mfma_trailing_update": mfma,
         "batched": batched,
         "precision": precision,
+        "serving": serving,
         "multi_rhs_lift": multi,
         "cpu_baseline": cpu,
     }

@@ -143,13 +143,20 @@ det_status dixon_lift_multi(det_ctx *ctx, const int64_t *A, int64_t n, int64_t l
 typedef struct {
   double log2_inv_eps;   /* early termination: failure probability < 2^-log2_inv_eps (default 64) */
   int certify;           /* 1: ignore early termination; reconstruct det/s_n up to the Hadamard bound */
-  uint64_t seed;         /* seed for the prime draws and the right-hand side */
-  int n_rhs;             /* number of Dixon solvings, default 1.  With n_rhs = i >= 2 (at most 8)
-                            and the FP64 three-digit lifting, the i solvings share one prime and
-                            one launch, and the extended bonus (Section 3.2) contributes
-                            pi~ = s~^i / gcd(det(R N), s~^i), a factor of s_n ... s_{n-i+1} */
+  uint64_t seed;         /* seed for the prime draws and the right-hand sides */
+  int n_rhs;             /* i_max, the most Dixon solvings (Alg. 4.1), default 1, at most 8.  All
+                            solvings share one prime and one inverse; from the second on, the
+                            extended bonus (Section 3.2) turns i solutions into
+                            pi~_i = s~^i / gcd(det(R N), s~^i), a factor of s_n ... s_{n-i+1},
+                            and K = lcm of everything found */
   int prime_bits;        /* CRA primes are drawn from (2^(b-1), 2^b); default 23 (max 23 for int8, 26 for fp64) */
   det_path path;         /* trailing-update path of the CRA loop */
+  int adaptive;          /* 1 (default): Alg. 4.1's loop -- after each solving the CRA on det/K
+                            resumes for at most that solving's time and returns on early
+                            termination; from the second solving on, the loop turns to the CRA
+                            when pi~_i = pi~_{i-1} or, by Section 5.3's rule, when
+                            log2(pi~_i / pi~_{i-1}) <= (time(solving) / time(LU)) log2(l).
+                            0: exactly n_rhs solvings, then the CRA on det/K */
 } det_opts;
 
 typedef struct {
@@ -165,16 +172,21 @@ typedef struct {
   double t_lif_ms;         /* device + host time of the solvings */
   double t_cra_ms;         /* time of the modular determinants */
   double t_host_ms;        /* time of reconstruction on the host */
+  int64_t solvings;        /* Dixon solvings done (Alg. 4.1's i) */
+  int timing_switch;       /* 1 when Section 5.3's time rule ended the solvings */
+  double t_solve_ms;       /* time of the last solving (lifting + reconstruction) */
+  double t_lu_ms;          /* measured device time per modular determinant (batched) */
 } det_report;
 
 /* Fill *opts with the defaults above. */
 void det_opts_default(det_opts *opts);
 
 /*
- * Exact det(A) by the introspective scheme of Section 4 with one solving
- * (Alg. 4.1 with i_max = 1): s~_n from Dixon lifting and rational
- * reconstruction, then the early-terminated CRA loop (Alg. 2.1) on
- * det(A)/s~_n, and det = s~_n * (det/s~_n).
+ * Exact det(A) by the introspective scheme of Section 4 (Alg. 4.1 with
+ * i_max = opts->n_rhs, default 1): s~_n from Dixon lifting and rational
+ * reconstruction (and, from the second solving on, the extended bonus), then
+ * the early-terminated CRA loop (Alg. 2.1) on det(A)/K, and
+ * det = K * (det/K).  See det_opts.adaptive for the loop's stopping rules.
  * Output: *sign in {-1, 0, +1}; |det| as little-endian base-2^32 limbs in
  * mag[0 .. *limb_count).  If limb_cap is too small the call returns
  * DET_E_BUFFER_TOO_SMALL with *limb_count = limbs needed (call again).
@@ -238,6 +250,50 @@ det_status det_autotune(det_ctx *ctx, const char *cache_path);
  * workgroups per CU; measured items per ms); *count = number of entries. */
 det_status det_autotune_read(const det_ctx *ctx, int64_t cap, int32_t *nmax, int32_t *variant,
                              int32_t *blocks_per_cu, double *items_per_ms, int64_t *count);
+
+/*
+ * Serving: a stream of determinant requests on one context, admitted by HBM
+ * footprint and served with continuous batching.  An engine thread owns the
+ * context from det_server_create to det_server_destroy (the caller must not
+ * use ctx meanwhile, and must destroy the server before the context).  Each
+ * turn it (1) admits waiting requests in arrival order while the sum of their
+ * resident footprints (the matrix copied into HBM, 8 n^2 bytes plus 4 KiB)
+ * stays within hbm_budget_bytes (0: 16 GiB; a request larger than the budget
+ * is admitted alone); (2) runs one round of the early-terminated CRA loop
+ * (Section 2.1, Alg. 2.1; rounds as in det_batch) for every admitted request
+ * of order <= 512, all their LU items in one persistent launch, each request
+ * taking its residues as they arrive and completing when it early-terminates
+ * or reaches the Hadamard bound; (3) runs one admitted request of larger order
+ * by the introspective scheme of det_introspective (Section 4).  Requests that
+ * arrive meanwhile join the next turn.  Request i's primes come from the
+ * stream seeded by opts->seed + i, so its result is the same alone and in any
+ * mix.  Budget and occupancy are reported by det_server_stats.
+ */
+typedef struct det_server det_server;
+typedef struct {
+  int64_t submitted, completed, waiting, admitted, max_admitted;
+  int64_t rounds;          /* engine turns */
+  int64_t queue_items;     /* (matrix, prime) LU items run through the queue */
+  int64_t hbm_budget, hbm_in_use, hbm_peak;   /* bytes of admitted resident data */
+} det_server_report;
+
+det_status det_server_create(det_ctx *ctx, size_t hbm_budget_bytes, const det_opts *opts,
+                             det_server **out);
+/* Copies A (host or device, row-major n x n, leading dimension lda, |a| < 2^31)
+ * and queues it; *request_id identifies it.  Returns at once. */
+det_status det_server_submit(det_server *s, const int64_t *A, int64_t n, int64_t lda,
+                             int64_t *request_id);
+/* *done = 1 when the request has finished (waits up to timeout_ms for it; -1:
+ * without limit, 0: no wait); then sign, |det| as little-endian limbs in
+ * mag[0 .. *limb_count) (DET_E_BUFFER_TOO_SMALL with *limb_count set when
+ * limb_cap is too small) and the latency from submission to completion in ms.
+ * A request that failed returns its status. */
+det_status det_server_poll(det_server *s, int64_t request_id, int timeout_ms, int *done,
+                           int *sign, uint32_t *mag, int64_t limb_cap, int64_t *limb_count,
+                           double *latency_ms);
+det_status det_server_stats(det_server *s, det_server_report *out);
+/* Finishes every submitted request, stops the engine and frees the server. */
+void det_server_destroy(det_server *s);
 
 /*
  * Kernel timing (measurement support, not part of the method).  After

@@ -57,14 +57,15 @@ class DetError(RuntimeError):
 
 class det_opts(ctypes.Structure):
     _fields_ = [("log2_inv_eps", c_double), ("certify", c_int), ("seed", c_u64),
-                ("n_rhs", c_int), ("prime_bits", c_int), ("path", c_int)]
+                ("n_rhs", c_int), ("prime_bits", c_int), ("path", c_int), ("adaptive", c_int)]
 
 
 class det_report(ctypes.Structure):
     _fields_ = [("primes_used", c_i64), ("lifting_steps", c_i64), ("sn_bits", c_i64),
                 ("et_rounds", c_i64), ("hadamard_bits", c_i64), ("early_terminated", c_int),
                 ("bonus_factors", c_int), ("t_lif_ms", c_double), ("t_cra_ms", c_double),
-                ("t_host_ms", c_double)]
+                ("t_host_ms", c_double), ("solvings", c_i64), ("timing_switch", c_int),
+                ("t_solve_ms", c_double), ("t_lu_ms", c_double)]
 
 
 def _sig(name, res, args):
@@ -96,6 +97,18 @@ _sig("det_autotune_read", c_int, [ctypes.c_void_p, c_i64, P(ctypes.c_int32), P(c
                                   P(ctypes.c_int32), P(c_double), P(c_i64)])
 _sig("det_mod_primes_noalloc", c_int, [c_int, ctypes.c_void_p, ctypes.c_void_p, c_i64, c_i64,
                                        P(c_u32), c_i64, P(c_u32)])
+class det_server_report(ctypes.Structure):
+    _fields_ = [("submitted", c_i64), ("completed", c_i64), ("waiting", c_i64), ("admitted", c_i64),
+                ("max_admitted", c_i64), ("rounds", c_i64), ("queue_items", c_i64),
+                ("hbm_budget", c_i64), ("hbm_in_use", c_i64), ("hbm_peak", c_i64)]
+
+
+_sig("det_server_create", c_int, [ctypes.c_void_p, ctypes.c_size_t, P(det_opts), P(ctypes.c_void_p)])
+_sig("det_server_submit", c_int, [ctypes.c_void_p, ctypes.c_void_p, c_i64, c_i64, P(c_i64)])
+_sig("det_server_poll", c_int, [ctypes.c_void_p, c_i64, c_int, P(c_int), P(c_int), P(c_u32), c_i64,
+                                P(c_i64), P(c_double)])
+_sig("det_server_stats", c_int, [ctypes.c_void_p, P(det_server_report)])
+_sig("det_server_destroy", None, [ctypes.c_void_p])
 _sig("det_profile_select", c_int, [ctypes.c_void_p, c_int])
 _sig("det_profile_read", c_int, [ctypes.c_void_p, P(c_i64), P(c_double), P(c_double), P(c_double)])
 _sig("det_host_is_prime", c_int, [c_u32])
@@ -113,7 +126,8 @@ _sig("det_host_extended_bonus", c_int, [P(c_u64), c_i64, c_i64, c_u32, c_i64, c_
 EXPORTED = ["det_ctx_create", "det_ctx_destroy", "det_ctx_set_stream", "det_status_str",
             "det_last_error", "det_opts_default", "det_mod_primes", "dixon_lift", "dixon_lift_multi",
             "det_introspective", "det_batch", "det_autotune", "det_autotune_read",
-            "det_mod_primes_noalloc", "det_profile_select", "det_profile_read", "det_host_is_prime", "det_host_sample_primes",
+            "det_mod_primes_noalloc", "det_server_create", "det_server_submit", "det_server_poll",
+            "det_server_stats", "det_server_destroy", "det_profile_select", "det_profile_read", "det_host_is_prime", "det_host_sample_primes",
             "det_host_hadamard_log2", "det_host_et_run_length", "det_host_crt",
             "det_host_ratrecon", "det_host_bigint", "det_host_extended_bonus"]
 
@@ -268,7 +282,7 @@ class Context:
     def det_introspective(self, A, certify: bool = False, seed: int | None = None,
                           log2_inv_eps: float | None = None, n_rhs: int | None = None,
                           prime_bits: int | None = None, path: str | None = None,
-                          report: bool = False):
+                          adaptive: bool | None = None, report: bool = False):
         ptr, n, lda, keep = _matrix_arg(A)
         o = det_opts()
         _lib.det_opts_default(ctypes.byref(o))
@@ -283,6 +297,8 @@ class Context:
             o.prime_bits = prime_bits
         if path is not None:
             o.path = PATHS[path]
+        if adaptive is not None:
+            o.adaptive = int(bool(adaptive))
         cap = max(8, 2 * n + 8)
         rep = det_report()
         while True:
@@ -378,6 +394,75 @@ def det_mod_primes_noalloc(A, primes, device: int = 0, hip_stream: int | None = 
     if st != DET_OK:
         raise DetError(st, "det_mod_primes_noalloc")
     return out
+
+
+class Server:
+    """A det_server on a context (det_server_*): submit matrices, poll for
+    their determinants.  The context must not be used while the server runs."""
+
+    def __init__(self, ctx: Context, hbm_budget_bytes: int = 0, seed: int | None = None,
+                 certify: bool = False, log2_inv_eps: float | None = None,
+                 prime_bits: int | None = None):
+        o = det_opts()
+        _lib.det_opts_default(ctypes.byref(o))
+        o.certify = int(bool(certify))
+        if seed is not None:
+            o.seed = seed
+        if log2_inv_eps is not None:
+            o.log2_inv_eps = log2_inv_eps
+        if prime_bits is not None:
+            o.prime_bits = prime_bits
+        h = ctypes.c_void_p()
+        ctx._check(_lib.det_server_create(ctx._h, hbm_budget_bytes, ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        self._ctx = ctx
+        self._keep = {}
+
+    def submit(self, A) -> int:
+        ptr, n, lda, keep = _matrix_arg(A)
+        rid = c_i64(0)
+        st = _lib.det_server_submit(self._h, ptr, n, lda, ctypes.byref(rid))
+        if st != DET_OK:
+            raise DetError(st, "det_server_submit")
+        self._keep[rid.value] = n
+        return int(rid.value)
+
+    def poll(self, request_id: int, timeout_ms: int = -1):
+        """(done, det or None, latency_ms or None)."""
+        n = self._keep.get(request_id, 0)
+        cap = max(8, 2 * n + 8)
+        while True:
+            done, sign, cnt, lat = c_int(0), c_int(0), c_i64(0), c_double(0)
+            mag = np.zeros(cap, dtype=np.uint32)
+            st = _lib.det_server_poll(self._h, request_id, timeout_ms, ctypes.byref(done),
+                                      ctypes.byref(sign), _u32p(mag), cap, ctypes.byref(cnt),
+                                      ctypes.byref(lat))
+            if st == 7:
+                cap = int(cnt.value)
+                continue
+            if st != DET_OK:
+                raise DetError(st, "det_server_poll")
+            if not done.value:
+                return False, None, None
+            return True, _from_limbs(sign.value, mag[:cnt.value]), float(lat.value)
+
+    def stats(self) -> dict:
+        r = det_server_report()
+        st = _lib.det_server_stats(self._h, ctypes.byref(r))
+        if st != DET_OK:
+            raise DetError(st, "det_server_stats")
+        return {f: int(getattr(r, f)) for f, _ in det_server_report._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            h, self._h = self._h, None
+            _lib.det_server_destroy(h)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 _default_ctx: Context | None = None

@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdet.so")
 SOURCES = ["lu_kernels.hip", "dixon_kernels.hip", "batch_kernels.hip", "capi.cpp", "batch.cpp",
-           "host_api.cpp", "noalloc.hip"]
+           "serve.cpp", "host_api.cpp", "noalloc.hip"]
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -163,13 +163,15 @@ det_status lu_factor(det_ctx* c, LuWs& w, const LuJob& J, bool keep_uinv,
   const int kc4 = std::max(1, kc / 4);
   const bool two_level = nit >= TWO_LEVEL_MIN_ITEMS;
   const int npan_max = n / 8 + 2;    // panels are at least 8 wide (the last may be narrower)
-  TRY(ensure(c, w.linv, (size_t)nit * 32 * 32 * sizeof(int32_t), w.st));
+  // L11 inverses: two sets of nit x 32 x 32, used alternately by the steps
+  // (a step's update may factor the next diagonal block while it reads its own)
+  TRY(ensure(c, w.linv, (size_t)2 * nit * 32 * 32 * sizeof(int32_t), w.st));
   // U11 inverses: panel-major, one 32 x 32 slot per item (back_substitute
-  // reads item 0's)
+  // reads item 0's); with block pivots and no factors kept, two alternating sets
   if (keep_uinv)
     TRY(ensure(c, w.uinv, (size_t)npan_max * nit * 32 * 32 * sizeof(int32_t), w.st));
   else if (block_pivots)
-    TRY(ensure(c, w.uinv, (size_t)nit * 32 * 32 * sizeof(int32_t), w.st));
+    TRY(ensure(c, w.uinv, (size_t)2 * nit * 32 * 32 * sizeof(int32_t), w.st));
   const int32_t* linv = (const int32_t*)w.linv.p;
   if (panels) panels->clear();
   if (!two_level) {
@@ -186,37 +188,53 @@ det_status lu_factor(det_ctx* c, LuWs& w, const LuJob& J, bool keep_uinv,
       HIPCHK(hipMemsetAsync(w.cnt.p, 0, nc * sizeof(unsigned), w.st));
       cnt = (unsigned*)w.cnt.p;
     }
+    // U11^{-1} and L11^{-1} slots of step idx
+    auto uinv_of = [&](int idx) -> int32_t* {
+      if (keep_uinv) return (int32_t*)w.uinv.p + (size_t)idx * nit * 32 * 32;
+      return block_pivots ? (int32_t*)w.uinv.p + (size_t)(idx & 1) * nit * 32 * 32 : nullptr;
+    };
+    auto linv_of = [&](int idx) { return (int32_t*)w.linv.p + (size_t)(idx & 1) * nit * 32 * 32; };
+    bool diag_done = false;          // the previous step's update factored this diagonal block
     int idx = 0;
     for (int j0 = 0; j0 < n; idx++) {
       const int pbw = detk::panel_width_for(n - j0);
       const int pb = std::min(pbw, n - j0);
       const Panel P{j0, pb, pbw};
       if (idx >= npan_max) return fail(c, DET_E_INVALID, "panel count overflow");
-      // U11^{-1}: kept per panel for the inverse, else (block pivots) one
-      // slot per item reused by every step
-      int32_t* uinv = keep_uinv ? (int32_t*)w.uinv.p + (size_t)idx * nit * 32 * 32
-                                : (block_pivots ? (int32_t*)w.uinv.p : nullptr);
+      int32_t* uinv = uinv_of(idx);
+      int32_t* lz = linv_of(idx);
       const bool bp = block_pivots && fused && uinv != nullptr;
       if (bp && pbw == 32) {
-        // the diagonal block alone, one wave per item (no row swaps)
-        ProfScope ps(c, DET_KERNEL_PANEL, 8.0 * pb * pb * nit, (double)pb * pb * pb * nit, w.st);
-        HIPCHK(detk::launch_diag_block((int32_t*)w.W.p, ldw, J.slab, j0, pb,
-                                       (const Modulus*)w.mods.p, (int32_t*)w.piv.p, n,
-                                       (int32_t*)w.flags.p, (int32_t*)w.linv.p, uinv, nit, w.st));
+        if (!diag_done) {
+          // the diagonal block alone (no row swaps)
+          ProfScope ps(c, DET_KERNEL_PANEL, 8.0 * pb * pb * nit, (double)pb * pb * pb * nit, w.st);
+          HIPCHK(detk::launch_diag_block((int32_t*)w.W.p, ldw, J.slab, j0, pb,
+                                         (const Modulus*)w.mods.p, (int32_t*)w.piv.p, n,
+                                         (int32_t*)w.flags.p, lz, uinv, nit, w.st));
+        }
       } else {
         TRY(panel_step(c, w, J, P, uinv, kc, fused ? ncols : 0, bp ? j0 + pb : 0));
+        // (the panel writes its L11^{-1} at the start of w.linv)
+        lz = (int32_t*)w.linv.p;
       }
+      diag_done = false;
       if (panels) panels->push_back(P);
       const int right = ncols - (j0 + pb);
       if (fused) {
         const int M = n - (j0 + pb);
+        // the next diagonal block inside this launch when it is 32 wide too
+        const int next_pb = bp && pbw == 32 && M > 0 && detk::panel_width_for(M) == 32
+                                ? std::min(32, M) : 0;
         ProfScope ps(c, DET_KERNEL_GEMM_F64,
                      4.0 * ((double)M * pb + (double)pb * right + 2.0 * (double)M * right) * nit,
                      2.0 * ((double)M + pb) * right * pb * nit, w.st);
-        HIPCHK(detk::launch_lu_update((int32_t*)w.W.p, J.slab, ldw, j0, pb, M, right, linv, pbw,
+        HIPCHK(detk::launch_lu_update((int32_t*)w.W.p, J.slab, ldw, j0, pb, M, right, lz, pbw,
                                       bp ? uinv : nullptr, (const Modulus*)w.mods.p, kc4,
                                       cnt ? cnt + (size_t)idx * nit * cstride : nullptr, cstride,
-                                      nit, w.st));
+                                      nit, w.st, next_pb, next_pb ? linv_of(idx + 1) : nullptr,
+                                      next_pb ? uinv_of(idx + 1) : nullptr, (int32_t*)w.piv.p, n,
+                                      (int32_t*)w.flags.p));
+        diag_done = next_pb > 0;
       } else {
         TRY(trsm_step(c, w, J, j0, pb, j0 + pb, right, linv, pbw, kc4, j0, pb));
         TRY(gemm_update(c, w, J, (int64_t)(j0 + pb) * ldw + j0 + pb,
@@ -842,6 +860,7 @@ det_status det_ctx_create(int device, size_t hbm_budget_bytes, det_ctx** out) {
       hipStreamCreateWithFlags(&c->own2, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev_cra, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreate(&c->ev_t0) != hipSuccess || hipEventCreate(&c->ev_t1) != hipSuccess ||
       detk::configure_kernels() != hipSuccess) {
     (void)hipGetLastError();
     if (c->own) (void)hipStreamDestroy(c->own);
@@ -894,6 +913,8 @@ void det_ctx_destroy(det_ctx* c) {
   if (c->q_exec) (void)hipGraphExecDestroy(c->q_exec);
   if (c->ev) (void)hipEventDestroy(c->ev);
   if (c->ev_cra) (void)hipEventDestroy(c->ev_cra);
+  if (c->ev_t0) (void)hipEventDestroy(c->ev_t0);
+  if (c->ev_t1) (void)hipEventDestroy(c->ev_t1);
   if (c->own) (void)hipStreamDestroy(c->own);
   if (c->own2) (void)hipStreamDestroy(c->own2);
   delete c;
@@ -916,6 +937,7 @@ void det_opts_default(det_opts* o) {
   o->n_rhs = 1;
   o->prime_bits = 23;
   o->path = DET_PATH_AUTO;
+  o->adaptive = 1;
 }
 
 det_status det_profile_select(det_ctx* c, det_kernel kind) {
@@ -1017,78 +1039,6 @@ det_status dixon_lift(det_ctx* c, const int64_t* A, int64_t n, int64_t lda, cons
   } catch (...) {
     return fail(c, DET_E_INVALID, "unexpected error");
   }
-}
-
-// The extended bonus (Section 3.2; Alg. 4.1 with i = m >= 2 solvings) on the
-// FP64 three-digit lifting: one inverse mod p, m random right-hand sides
-// lifted together, and m random combination vectors R_0..R_{m-1} formed on
-// the GPU with every solution digit by digit.  The host step
-// (extended_bonus_host) rebuilds every R_a . x_h by rational reconstruction,
-// takes s~ = lcm of all their denominators (so that R N = s~ R X is an
-// integer matrix), and pi~ = s~^m / gcd(det(R N), s~^m) (Section 3.2's
-// exponent: R N is m x m).  K becomes lcm(K, s~, pi~), a divisor of det(A).
-// rep.bonus_factors = m on success; -m when a reconstruction failed (then
-// only the denominators that were found enter K).  *done is false when p
-// divided det(A) twice.
-det_status extended_bonus(det_ctx* c, const int64_t* dA, int64_t dlda, int n,
-                          const dethost::Bounds& bd, int m, int grid3,
-                          dethost::PrimeSampler& dsamp, uint64_t& rng, int64_t beta, BigInt& K,
-                          det_report& rep, double& t_host, bool& done) {
-  done = false;
-  uint32_t p = 0;
-  det_status st = DET_E_SINGULAR_MOD_P;
-  for (int tries = 0; tries < 2 && st == DET_E_SINGULAR_MOD_P; tries++) {
-    p = dsamp.next();
-    st = inverse_mod_p(c, dA, dlda, n, p);
-  }
-  if (st == DET_E_SINGULAR_MOD_P) return DET_OK;     // det is probably 0: CRA alone
-  TRY(st);
-  // right-hand sides in [0, beta) (B[j*m + h]) and combination vectors in [1, 2^16)
-  const int64_t npad = lift_pad(n);
-  std::vector<int64_t> B((size_t)n * m);
-  std::vector<uint32_t> R((size_t)m * npad, 0);
-  double csum = 0, b2 = 0;
-  for (int64_t j = 0; j < n; j++)
-    for (int h = 0; h < m; h++) B[(size_t)j * m + h] = (int64_t)(dethost::splitmix64(rng) % (uint64_t)beta);
-  for (int a = 0; a < m; a++) {
-    double cs = 0;
-    for (int64_t j = 0; j < n; j++) {
-      R[(size_t)a * npad + j] = 1 + (uint32_t)(dethost::splitmix64(rng) % 65535u);
-      cs += R[(size_t)a * npad + j];
-    }
-    csum = std::max(csum, cs);
-  }
-  for (int h = 0; h < m; h++) {
-    double t = 0;
-    for (int64_t j = 0; j < n; j++) t += (double)B[(size_t)j * m + h] * (double)B[(size_t)j * m + h];
-    b2 = std::max(b2, t);
-  }
-  // numerators of R_a . x_h: |.| <= max_a sum(R_a) H_col max_h ||b_h|| /
-  // min_j ||a_j|| (Cramer); denominators d <= H
-  const double log2N = log2(csum) + bd.log2_hcol + 0.5 * log2(std::max(b2, 1.0)) -
-                       bd.log2_min_col + 1e-6;
-  const int64_t Nbits = (int64_t)ceil(log2N), Dbits = (int64_t)ceil(bd.log2_h + 1e-6);
-  const int64_t k = (int64_t)ceil((double)(Nbits + Dbits + 2) / log2((double)p)) + 1;
-  TRY(ensure(c, c->cvec, (size_t)m * npad * sizeof(uint32_t)));
-  TRY(ensure(c, c->comb, (size_t)m * m * k * sizeof(uint64_t)));
-  HIPCHK(hipMemcpyAsync(c->cvec.p, R.data(), R.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
-                        c->st));
-  TRY(lift3_multi(c, grid3, dA, dlda, n, B.data(), m, p, k, nullptr, (const uint32_t*)c->cvec.p,
-                  (uint64_t*)c->comb.p, true, m));
-  std::vector<uint64_t> comb((size_t)m * m * k);
-  HIPCHK(hipMemcpyAsync(comb.data(), c->comb.p, comb.size() * sizeof(uint64_t),
-                        hipMemcpyDeviceToHost, c->st));
-  HIPCHK(hipStreamSynchronize(c->st));
-  rep.lifting_steps += k * m;
-  const double th0 = now_ms();
-  BigInt s, pi;
-  const int64_t failed = dethost::extended_bonus_host(comb.data(), m, k, p, Nbits, Dbits, s, pi);
-  K = BigInt::div_exact(K * s, BigInt::gcd(K, s));
-  K = BigInt::div_exact(K * pi, BigInt::gcd(K, pi));
-  rep.bonus_factors = failed ? -m : m;
-  t_host += now_ms() - th0;
-  done = true;
-  return DET_OK;
 }
 
 det_status dixon_lift_multi(det_ctx* c, const int64_t* A, int64_t n, int64_t lda,
@@ -1209,8 +1159,10 @@ det_status det_introspective(det_ctx* c, const int64_t* A, int64_t n, int64_t ld
     std::thread cra_thread([&] {
       try {
         (void)hipSetDevice(c->device);
+        (void)hipEventRecord(c->ev_t0, c->own2);
         cra_st = residues_core(c, c->ws[1], dA, dlda, (int)n, ps1.data(), batch1, hres1, o.path,
                                false, &cra_def);
+        (void)hipEventRecord(c->ev_t1, c->own2);
       } catch (...) {
         cra_st = DET_E_NOMEM;
       }
@@ -1223,8 +1175,96 @@ det_status det_introspective(det_ctx* c, const int64_t* A, int64_t n, int64_t ld
       ~Joiner() { join(); }
     } cra_join{cra_thread};
 
-    // ---------------- LIF: s~_n from Dixon solvings (Section 2.2)
+    // ---------------- The CRA loop on det(A)/K (Alg. 2.1 on the quotient,
+    // Section 4): every residue computed so far is kept (d_i = det mod p_i)
+    // and re-used whenever K grows (d_i K^{-1} mod p_i; primes dividing K are
+    // skipped); new batches of primes run on ws[0] until early termination
+    // (run length of Lemma 2.1(iv) for the bound H/K), the deterministic
+    // bound prod p >= 2H/K, or, with a time budget, until the budget is spent.
     BigInt K = BigInt::from_i64(1);
+    std::vector<uint32_t> cra_p, cra_r;             // primes and residues, in draw order
+    dethost::CrtState crt;
+    bool done = false;
+    double t_lu_ms = 0, lu_primes = 0;              // device time per modular determinant
+    auto restart_crt = [&]() {
+      crt = dethost::CrtState();
+      done = false;
+    };
+    auto feed = [&](size_t from) {                  // Garner steps for primes [from, end)
+      const double log2_HK = std::max(0.0, bd.log2_h - (double)(K.bit_length() - 1));
+      const double logl_H = std::max(1.0, log2_HK / log2_l);
+      int64_t kET = dethost::et_run_length(o.log2_inv_eps, dethost::prime_set_size(bits), logl_H);
+      if (kET < 0) kET = INT64_MAX;                 // lemma not applicable: certify only
+      for (size_t i = from; i < cra_p.size() && !done; i++) {
+        const uint32_t p = cra_p[i];
+        const uint64_t km = K.mod_small(p);
+        if (km == 0) continue;                       // p | K: skip this prime
+        const uint64_t kinv = dethost::powmod64(km, p - 2, p);
+        crt.add(p, (uint32_t)dethost::mulmod64(cra_r[i], kinv, p));
+        if ((double)(crt.M.bit_length() - 1) >= 1.0 + log2_HK + 1.0) done = true;
+        else if (!o.certify && crt.same >= kET) {
+          done = true;
+          rep.early_terminated = 1;
+        }
+      }
+      return kET;
+    };
+    auto cra_run = [&](double budget_ms) -> det_status {
+      const double tb = now_ms();
+      restart_crt();
+      const double th0 = now_ms();
+      int64_t kET = feed(0);
+      t_host += now_ms() - th0;
+      while (!done && now_ms() - tb < budget_ms) {
+        const double log2_HK = std::max(0.0, bd.log2_h - (double)(K.bit_length() - 1));
+        const double need = (1.0 + log2_HK + 1.0 - (double)(crt.M.bit_length() - 1)) / log2_l;
+        int64_t batch = std::min<int64_t>(std::max<int64_t>((int64_t)ceil(need) + 1, 4), 512);
+        if (!o.certify) batch = std::min<int64_t>(batch, std::max<int64_t>(2 * std::min<int64_t>(kET, 64), 8));
+        std::vector<uint32_t> ps(batch), rs(batch);
+        for (auto& q : ps) q = samp.next();
+        const double t0 = now_ms();
+        TRY(residues_core(c, c->ws[0], dA, dlda, (int)n, ps.data(), batch, rs.data(), o.path));
+        t_lu_ms += now_ms() - t0;
+        lu_primes += (double)batch;
+        rep.et_rounds++;
+        const size_t from = cra_p.size();
+        cra_p.insert(cra_p.end(), ps.begin(), ps.end());
+        cra_r.insert(cra_r.end(), rs.begin(), rs.end());
+        const double th = now_ms();
+        kET = feed(from);
+        t_host += now_ms() - th;
+      }
+      return DET_OK;
+    };
+    auto take_batch1 = [&]() -> det_status {       // the background batch, once
+      cra_join.join();
+      TRY(cra_st);
+      HIPCHK(hipStreamSynchronize(c->own2));
+      if (cra_def.count) {
+        // a prime whose block-pivot LU met an all-zero block column: again
+        // with the full pivot search
+        bool any = false;
+        for (int64_t i = 0; i < cra_def.count; i++) any |= cra_def.flags[i] != 0;
+        if (any) {
+          c->block_pivot_retries++;
+          TRY(residues_core(c, c->ws[1], dA, dlda, (int)n, ps1.data() + cra_def.s0, cra_def.count,
+                            hres1 + cra_def.s0, o.path, true, nullptr, false));
+        }
+      }
+      float ms = 0;
+      if (hipEventElapsedTime(&ms, c->ev_t0, c->ev_t1) == hipSuccess && ms > 0) {
+        t_lu_ms += ms;
+        lu_primes += (double)batch1;
+      }
+      (void)hipGetLastError();
+      cra_p.assign(ps1.begin(), ps1.end());
+      cra_r.assign(hres1, hres1 + batch1);
+      rep.et_rounds = 1;
+      return DET_OK;
+    };
+
+    // ---------------- LIF: the solvings of Alg. 4.1 (Section 2.2; the
+    // extended bonus of Section 3.2 from the second one on)
     const double tl0 = now_ms();
     // 25-bit primes when the FP64 three-digit lifting applies, else the
     // largest below 2^26 with n ||A|| p < 2^62 (64-bit integer lifting)
@@ -1235,127 +1275,100 @@ det_status det_introspective(det_ctx* c, const int64_t* A, int64_t n, int64_t ld
     while (dixon_bits > 12 && (double)n * bd.amax * ldexp(1.0, dixon_bits) >= ldexp(1.0, 62))
       dixon_bits--;
     const int64_t beta = std::max<int64_t>(2, (int64_t)ceil(bd.log2_h));
-    const int grid3 = dixon_bits == 25 ? detk::lift3_grid(c->device, (int)n) : 0;
-    if (bd.log2_h > 0 && dixon_bits > 12 && o.n_rhs >= 2 && grid3 > 0) {
-      // several solvings at once, with the extended bonus (Section 3.2)
+    const int i_max = std::min(std::max(o.n_rhs, 1), 8);
+    bool batch1_taken = false;
+    if (bd.log2_h > 0 && dixon_bits > 12) {
       dethost::PrimeSampler dsamp(dethost::splitmix64(rng), dixon_bits);
-      cra_join.join();                               // all of the batch is on own2
-      TRY(cra_st);
-      bool done = false;
-      TRY(extended_bonus(c, dA, dlda, (int)n, bd, std::min(o.n_rhs, 8), grid3, dsamp, rng, beta,
-                         K, rep, t_host, done));
-    } else if (bd.log2_h > 0 && dixon_bits > 12) {
-      dethost::PrimeSampler dsamp(dethost::splitmix64(rng), dixon_bits);
-      for (int solve = 0; solve < o.n_rhs; solve++) {
-        uint32_t p = 0;
-        det_status st = DET_E_SINGULAR_MOD_P;
-        for (int tries = 0; tries < 2 && st == DET_E_SINGULAR_MOD_P; tries++) {
-          p = dsamp.next();
-          st = inverse_mod_p(c, dA, dlda, (int)n, p);
-        }
-        if (st == DET_E_SINGULAR_MOD_P) break;     // det is probably 0: CRA alone
-        if (st != DET_OK) return st;
-        // right-hand side b in [0, beta) and the combination vector in [1, 2^16)
-        std::vector<int64_t> b(n);
-        std::vector<uint32_t> cv(n);
-        double csum = 0, b2 = 0;
-        for (int64_t j = 0; j < n; j++) {
-          b[j] = (int64_t)(dethost::splitmix64(rng) % (uint64_t)beta);
-          cv[j] = 1 + (uint32_t)(dethost::splitmix64(rng) % 65535u);
-          csum += cv[j];
-          b2 += (double)b[j] * (double)b[j];
-        }
-        // y = c.x = (c.num)/d(x): |c.num| <= sum(c) H_col ||b|| / min_j ||a_j||, d <= H.
-        const double log2N = log2(csum) + bd.log2_hcol + 0.5 * log2(std::max(b2, 1.0)) -
+      // one prime and one inverse for every solving
+      uint32_t p = 0;
+      det_status st = DET_E_SINGULAR_MOD_P;
+      for (int tries = 0; tries < 2 && st == DET_E_SINGULAR_MOD_P; tries++) {
+        p = dsamp.next();
+        st = inverse_mod_p(c, dA, dlda, (int)n, p);
+      }
+      if (st != DET_OK && st != DET_E_SINGULAR_MOD_P) return st;
+      if (st == DET_OK) {                            // else det is probably 0: CRA alone
+        // lifting length from the bounds of every combination R_a . x_h:
+        // numerators |.| <= sum(R_a) H_col ||b|| / min_j ||a_j|| (Cramer,
+        // R entries < 2^16, b entries < beta), denominators <= H
+        const double log2N = log2(65535.0 * (double)n) + bd.log2_hcol +
+                             0.5 * log2(std::max(1.0, (double)n * (double)beta * (double)beta)) -
                              bd.log2_min_col + 1e-6;
-        const double log2D = bd.log2_h + 1e-6;
-        const int64_t Nbits = (int64_t)ceil(log2N), Dbits = (int64_t)ceil(log2D);
+        const int64_t Nbits = (int64_t)ceil(log2N), Dbits = (int64_t)ceil(bd.log2_h + 1e-6);
         const int64_t k = (int64_t)ceil((double)(Nbits + Dbits + 2) / log2((double)p)) + 1;
-        TRY(ensure(c, c->cvec, (size_t)lift_pad(n) * sizeof(uint32_t)));
-        TRY(ensure(c, c->comb, (size_t)k * sizeof(uint64_t)));
-        const Stage sl = stage_layout(n, k);
-        TRY(ensure_pin(c, c->hstage, sl.total, c->st));
-        uint32_t* hcv = (uint32_t*)((char*)c->hstage.p + sl.cvec);
-        memcpy(hcv, cv.data(), n * sizeof(uint32_t));
-        HIPCHK(hipMemsetAsync(c->cvec.p, 0, lift_pad(n) * sizeof(uint32_t), c->st));
-        HIPCHK(hipMemcpyAsync(c->cvec.p, hcv, n * sizeof(uint32_t), hipMemcpyHostToDevice, c->st));
-        cra_join.join();                               // all of the batch is on own2
+        const int64_t npad = lift_pad((int)n);
+        TRY(ensure(c, c->digits, (size_t)i_max * k * n * sizeof(uint32_t)));
+        TRY(ensure(c, c->cvec, (size_t)i_max * npad * sizeof(uint32_t)));
+        TRY(ensure(c, c->comb, (size_t)i_max * i_max * k * sizeof(uint64_t)));
+        uint32_t* dig = (uint32_t*)c->digits.p;
+        std::vector<uint32_t> R((size_t)i_max * npad, 0);
+        std::vector<uint64_t> comb;
+        BigInt K_prev = BigInt::from_i64(1);
+        // every launch of the background batch is on own2 before the first
+        // lifting waits for it (the cooperative lifting needs its workgroups
+        // resident together)
+        cra_join.join();
         TRY(cra_st);
-        TRY(lift(c, dA, dlda, (int)n, bd.amax, b.data(), p, k, nullptr, (const uint32_t*)c->cvec.p,
-                 (uint64_t*)c->comb.p, true));
-        const uint64_t* comb = (const uint64_t*)((char*)c->hstage.p + sl.comb);
-        HIPCHK(hipMemcpyAsync((void*)comb, c->comb.p, k * sizeof(uint64_t), hipMemcpyDeviceToHost,
-                              c->st));
-        HIPCHK(hipStreamSynchronize(c->st));
-        rep.lifting_steps += k;
-        const double th0 = now_ms();
-        // y = sum_i comb[i] p^i (y mod p^k is c.x mod p^k) and p^k
-        BigInt y, pk;
-        dethost::radix_value(comb, k, p, y, pk);
-        BigInt a, d;
-        if (dethost::rational_reconstruct(y, pk, BigInt::from_i64(1).shl(Nbits),
-                                          BigInt::from_i64(1).shl(Dbits), a, d, p)) {
-          BigInt g = BigInt::gcd(K, d);                // s~_n <- lcm(s~_n, d)
-          K = BigInt::div_exact(K * d, g);
+        for (int i = 1; i <= i_max; i++) {
+          const double ts0 = now_ms();
+          std::vector<int64_t> b(n);
+          for (int64_t j = 0; j < n; j++) b[j] = (int64_t)(dethost::splitmix64(rng) % (uint64_t)beta);
+          TRY(lift(c, dA, dlda, (int)n, bd.amax, b.data(), p, k, dig + (size_t)(i - 1) * k * n,
+                   nullptr, nullptr, !batch1_taken));
+          // a fresh random i x n matrix R, and the i x i combinations R_a . x_h
+          for (int a = 0; a < i; a++)
+            for (int64_t j = 0; j < n; j++)
+              R[(size_t)a * npad + j] = 1 + (uint32_t)(dethost::splitmix64(rng) % 65535u);
+          HIPCHK(hipMemcpyAsync(c->cvec.p, R.data(), (size_t)i * npad * sizeof(uint32_t),
+                                hipMemcpyHostToDevice, c->st));
+          for (int h = 0; h < i; h++)
+            for (int a = 0; a < i; a++)
+              HIPCHK(detk::launch_comb_digits(dig + (size_t)h * k * n, k, (int)n,
+                                              (const uint32_t*)c->cvec.p + (size_t)a * npad,
+                                              (uint64_t*)c->comb.p + ((size_t)h * i + a) * k, c->st));
+          comb.resize((size_t)i * i * k);
+          HIPCHK(hipMemcpyAsync(comb.data(), c->comb.p, comb.size() * sizeof(uint64_t),
+                                hipMemcpyDeviceToHost, c->st));
+          HIPCHK(hipStreamSynchronize(c->st));
+          rep.lifting_steps += k;
+          const double th0 = now_ms();
+          BigInt sv, pi;
+          const int64_t failed = dethost::extended_bonus_host(comb.data(), i, k, p, Nbits, Dbits, sv, pi);
+          K = BigInt::div_exact(K * sv, BigInt::gcd(K, sv));
+          K = BigInt::div_exact(K * pi, BigInt::gcd(K, pi));
+          if (i >= 2) rep.bonus_factors = failed ? -i : i;
+          t_host += now_ms() - th0;
+          const double t_solve = now_ms() - ts0;
+          rep.solvings = i;
+          rep.t_solve_ms = t_solve;
+          if (!batch1_taken) {
+            TRY(take_batch1());
+            batch1_taken = true;
+          }
+          if (!o.adaptive) continue;                 // exactly i_max solvings, then the CRA
+          // resume the CRA on det/K for at most the time of one solving
+          TRY(cra_run(t_solve));
+          if (done) break;
+          if (i >= 2) {
+            // Section 5.3: the factor gained by this solving against what
+            // the CRA would have gained in its time
+            const double gain = (double)(K.bit_length() - K_prev.bit_length());
+            const double ratio = lu_primes > 0 ? t_solve / (t_lu_ms / lu_primes) : 0.0;
+            if (K.cmp(K_prev) == 0 || gain <= ratio * log2_l) {
+              rep.timing_switch = K.cmp(K_prev) == 0 ? 0 : 1;
+              break;
+            }
+          }
+          K_prev = K;
         }
-        t_host += now_ms() - th0;
       }
     }
     rep.sn_bits = K.bit_length();
     rep.t_lif_ms = now_ms() - tl0;
-
-    // ---------------- CRA on det(A)/K with early termination (Alg. 2.1)
-    const double log2_HK = std::max(0.0, bd.log2_h - (double)(K.bit_length() - 1));
-    const double logl_H = std::max(1.0, log2_HK / log2_l);
-    int64_t kET = dethost::et_run_length(o.log2_inv_eps, dethost::prime_set_size(bits), logl_H);
-    if (kET < 0) kET = INT64_MAX;                    // lemma not applicable: certify only
-    dethost::CrtState crt;
-    bool done = false;
-    cra_join.join();
-    TRY(cra_st);
-    HIPCHK(hipStreamSynchronize(c->own2));
-    if (cra_def.count) {
-      // a prime whose block-pivot LU met an all-zero block column: again
-      // with the full pivot search
-      bool any = false;
-      for (int64_t i = 0; i < cra_def.count; i++) any |= cra_def.flags[i] != 0;
-      if (any) {
-        c->block_pivot_retries++;
-        TRY(residues_core(c, c->ws[1], dA, dlda, (int)n, ps1.data() + cra_def.s0, cra_def.count,
-                          hres1 + cra_def.s0, o.path, true, nullptr, false));
-      }
-    }
-    std::vector<uint32_t> ps(ps1), rs(hres1, hres1 + batch1);
-    rep.et_rounds = 1;
-    int64_t batch = batch1;
-    for (;;) {
-      const double th0 = now_ms();
-      for (int64_t i = 0; i < batch && !done; i++) {
-        const uint32_t p = ps[i];
-        const uint64_t km = K.mod_small(p);
-        if (km == 0) continue;                       // p | K: skip this prime
-        const uint64_t kinv = dethost::powmod64(km, p - 2, p);
-        const uint32_t d = (uint32_t)dethost::mulmod64(rs[i], kinv, p);
-        crt.add(p, d);
-        rep.primes_used++;
-        // deterministic stop: prod p >= 2 H / K  (log2 M >= 1 + log2 H - log2 K)
-        if ((double)(crt.M.bit_length() - 1) >= 1.0 + log2_HK + 1.0) done = true;
-        else if (!o.certify && crt.same >= kET) {
-          done = true;
-          rep.early_terminated = 1;
-        }
-      }
-      t_host += now_ms() - th0;
-      if (done) break;
-      const double need = (1.0 + log2_HK + 1.0 - (double)(crt.M.bit_length() - 1)) / log2_l;
-      batch = std::min<int64_t>(std::max<int64_t>((int64_t)ceil(need) + 1, 4), 512);
-      if (!o.certify) batch = std::min<int64_t>(batch, std::max<int64_t>(2 * kET, 8));
-      ps.resize(batch);
-      rs.resize(batch);
-      for (int64_t i = 0; i < batch; i++) ps[i] = samp.next();
-      TRY(residues_core(c, c->ws[0], dA, dlda, (int)n, ps.data(), batch, rs.data(), o.path));
-      rep.et_rounds++;
-    }
+    if (!batch1_taken) TRY(take_batch1());
+    if (!done) TRY(cra_run(INFINITY));
+    rep.primes_used = (int64_t)crt.count;
+    rep.t_lu_ms = lu_primes > 0 ? t_lu_ms / lu_primes : 0.0;
     rep.t_cra_ms = now_ms() - tc0;
     const double th1 = now_ms();
     BigInt det = crt.r * K;

@@ -20,10 +20,17 @@ hipError_t launch_panel(int32_t* W, int64_t ldw, int64_t slab, int n, int j0, in
 // L21 U12); the panel's swaps already applied (launch_panel with ncols_sw).
 // Uinv != null: the panel factored only its diagonal block, and L21 is formed
 // as A21 U11^{-1} inside the update (U11^{-1} from the panel, ldt x ldt).
+// next_pb > 0 (needs Uinv != null, ldt == 32): the launch also factors the
+// next diagonal block, at (j0 + pb, j0 + pb) with width next_pb, as
+// launch_diag_block would, into next_Linv / next_Uinv (other buffers than
+// Linv / Uinv), piv and flags.
 hipError_t launch_lu_update(int32_t* W, int64_t slab, int64_t ldw, int j0, int pb, int M, int N,
                             const int32_t* Linv, int ldt, const int32_t* Uinv,
                             const Modulus* mods, int kc4, unsigned* cnt, int cnt_stride,
-                            int nitems, hipStream_t st);
+                            int nitems, hipStream_t st, int next_pb = 0,
+                            int32_t* next_Linv = nullptr, int32_t* next_Uinv = nullptr,
+                            int32_t* piv = nullptr, int64_t piv_stride = 0,
+                            int32_t* flags = nullptr);
 int panel_width_for(int m);
 // The pb x pb diagonal block at (j0, j0) of every item (pb <= 32) factored
 // without pivot search below it: U11 into W, L11^{-1} and U11^{-1} dense

@@ -64,124 +64,22 @@ __global__ __launch_bounds__(512) void k_panel(int32_t* __restrict__ W, int64_t 
 }
 
 // ------------------------------------------------------------------ K2': diagonal block
-// One wave per item factors the pb x pb diagonal block at (j0, j0) (pb <= 32)
-// without a pivot search below it, for an LU whose update forms L21 itself
-// (k_lu_update with Uinv).  Lane c holds column c of [A11 | I] (32 + 32
-// columns; a block narrower than 32 is padded with the identity).  A
-// fraction-free elimination, row_i <- b_k row_i - r_ik row_k for i > k with
-// b_k = the pivot-column entry of row k, leaves row i scaled by
-// sigma_i = b_0 ... b_{i-1}, so [U | L^{-1}] row i = row i / sigma_i and no
-// inverse is needed inside the loop.  All 1 / sigma_i come from one Fermat
-// ladder: with prefix products P_k = b_0 ... b_k (a scan across lanes) and
-// suffix products S_k = b_k ... b_31, sigma_i = P_{i-1} and
-// 1 / sigma_i = S_i / P_31.  Then U^{-1} by a backward elimination of
-// [U' | D^{-1}] (U = D U', D = diag(u_ii), 1 / u_ii = sigma_i / b_i).
-// Outputs: U11 into the block of W (on and above the diagonal), L11^{-1} and
-// U11^{-1} dense 32 x 32 row-major (zero outside pb x pb), piv = identity on
-// the block, the item's flag raised when a pivot is 0 mod p (the caller then
-// runs the full pivot search).  Values stay |v| <= (p+1)/2 + 5 through the
-// loose reductions, so every product is below 2^52.
-__device__ __forceinline__ double shfl_up_d(double x, int d) {
-  const long long b = __builtin_bit_cast(long long, x);
-  const int lo = __shfl_up((int)b, d, 64), hi = __shfl_up((int)(b >> 32), d, 64);
-  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
-}
-__device__ __forceinline__ double shfl_down_d(double x, int d) {
-  const long long b = __builtin_bit_cast(long long, x);
-  const int lo = __shfl_down((int)b, d, 64), hi = __shfl_down((int)(b >> 32), d, 64);
-  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
-}
-
-__global__ __launch_bounds__(64) void k_diag_block(int32_t* __restrict__ W, int64_t ldw,
-                                                   int64_t slab, int j0, int pb,
-                                                   const Modulus* __restrict__ mods,
-                                                   int32_t* __restrict__ piv, int64_t piv_stride,
-                                                   int32_t* __restrict__ flags,
-                                                   int32_t* __restrict__ Linv,
-                                                   int32_t* __restrict__ Uinv) {
+// One 256-thread workgroup per item factors the pb x pb diagonal block at
+// (j0, j0) without a pivot search below it (diag_block_body, panel.hpp), for
+// an LU whose update forms L21 itself (k_lu_update with Uinv).
+__global__ __launch_bounds__(256) void k_diag_block(int32_t* __restrict__ W, int64_t ldw,
+                                                    int64_t slab, int j0, int pb,
+                                                    const Modulus* __restrict__ mods,
+                                                    int32_t* __restrict__ piv, int64_t piv_stride,
+                                                    int32_t* __restrict__ flags,
+                                                    int32_t* __restrict__ Linv,
+                                                    int32_t* __restrict__ Uinv) {
+  __shared__ double sRow[128];
+  __shared__ double sV[96];
   const int z = blockIdx.x;
-  const int c = threadIdx.x;
-  const double p = mods[z].p, pinv = mods[z].pinv;
-  const uint32_t e_inv = (uint32_t)__builtin_amdgcn_readfirstlane((int)((uint32_t)p - 2u));
-  int32_t* Wz = W + (int64_t)z * slab + (int64_t)j0 * ldw + j0;
-  double F[32];
-#pragma unroll
-  for (int i = 0; i < 32; i++) {
-    if (c < 32) F[i] = (i < pb && c < pb) ? (double)Wz[(int64_t)i * ldw + c] : (i == c ? 1.0 : 0.0);
-    else F[i] = (i == c - 32) ? 1.0 : 0.0;
-  }
-  // fraction-free elimination; lane k keeps b_k
-  double bl = 1.0;
-  bool zero = false;
-#pragma unroll
-  for (int k = 0; k < 32; k++) {
-    double bk = readlane_d(F[k], k);
-    zero |= bk == 0.0;
-    bk = bk == 0.0 ? 1.0 : bk;                      // (the result is discarded then)
-    bl = c == k ? bk : bl;
-#pragma unroll
-    for (int i = k + 1; i < 32; i++) {
-      const double r = readlane_d(F[i], k);
-      F[i] = mod_loose(fma(bk, F[i], -r * F[k]), p, pinv);
-    }
-  }
-  // prefix and suffix products of b over lanes 0..31 (lanes >= 32 hold 1)
-  const double bv = c < 32 ? bl : 1.0;
-  double P = bv, S = bv;
-#pragma unroll
-  for (int d = 1; d < 32; d <<= 1) {
-    const double u = shfl_up_d(P, d), v = shfl_down_d(S, d);
-    if ((c & 31) >= d) P = mul_mod_loose(P, u, p, pinv);
-    if ((c & 31) + d < 32) S = mul_mod_loose(S, v, p, pinv);
-  }
-  P = mod_c(P, p, pinv);
-  S = mod_c(S, p, pinv);
-  const double P31 = readlane_d(P, 31);
-  const double Q = pow_mod_fixed(P31, e_inv, p, pinv);    // 1 / (b_0 ... b_31)
-  const double sinv = mul_mod(S, Q, p, pinv);             // lane i: 1 / sigma_i
-  const double Pm1 = shfl_up_d(P, 1);
-  const double sig = (c & 31) == 0 ? 1.0 : Pm1;           // lane i: sigma_i
-  // 1 / b_i = P_{i-1} S_{i+1} / P_31, and 1 / u_ii = sigma_i / b_i
-  const double Sp1 = shfl_down_d(S, 1);
-  const double s_next = (c & 31) == 31 ? 1.0 : Sp1;
-  const double binv = mul_mod(mul_mod(sig, s_next, p, pinv), Q, p, pinv);
-  const double uinv_d = mul_mod(sig, binv, p, pinv);     // lane i: 1 / u_ii
-  // rows of [U | L^{-1}]
-#pragma unroll
-  for (int i = 0; i < 32; i++) F[i] = mul_mod(F[i], readlane_d(sinv, i), p, pinv);
-  if (c < 32 && c < pb) {
-#pragma unroll
-    for (int i = 0; i < 32; i++)
-      if (i <= c) Wz[(int64_t)i * ldw + c] = (int32_t)F[i];
-  }
-  int32_t* Lz = Linv + (int64_t)z * 32 * 32;
-  int32_t* Uz = Uinv + (int64_t)z * 32 * 32;
-  if (c >= 32) {
-    const int cc = c - 32;
-#pragma unroll
-    for (int i = 0; i < 32; i++) Lz[i * 32 + cc] = (i < pb && cc < pb) ? (int32_t)F[i] : 0;
-  }
-  // U^{-1}: [U' | D^{-1}] with U' = D^{-1} U, then backward elimination
-#pragma unroll
-  for (int i = 0; i < 32; i++) {
-    const double di = readlane_d(uinv_d, i);
-    F[i] = c < 32 ? mul_mod(F[i], di, p, pinv) : (i == c - 32 ? di : 0.0);
-  }
-#pragma unroll
-  for (int k = 31; k > 0; k--) {
-#pragma unroll
-    for (int i = 0; i < k; i++) {
-      const double r = readlane_d(F[i], k);
-      F[i] = mod_loose(fma(-r, F[k], F[i]), p, pinv);
-    }
-  }
-  if (c >= 32) {
-    const int cc = c - 32;
-#pragma unroll
-    for (int i = 0; i < 32; i++) Uz[i * 32 + cc] = (i < pb && cc < pb) ? (int32_t)mod_c(F[i], p, pinv) : 0;
-  }
-  if (c < pb) piv[(int64_t)z * piv_stride + j0 + c] = j0 + c;
-  if (zero && c == 0) flags[z] = 1;
+  diag_block_body<4>(W + (int64_t)z * slab + (int64_t)j0 * ldw + j0, ldw, pb, mods[z].p,
+                     mods[z].pinv, piv + (int64_t)z * piv_stride, j0, flags + z,
+                     Linv + (int64_t)z * 1024, Uinv + (int64_t)z * 1024, sRow, sV);
 }
 
 // ------------------------------------------------------------------ K3: row swaps
@@ -515,12 +413,27 @@ __global__ void k_place_diag(int32_t* __restrict__ W, int64_t ldw, int64_t offV,
 // forms its rows' multipliers L21 = A21 U11^{-1} first (U11^{-1} from the
 // panel, dense ldt x ldt per item); they are not stored (neither a
 // determinant nor the inverse from [A | I] reads L).
+// With next.pb > 0 the workgroup of tile (0, 0), which holds the next
+// diagonal block once its own update is stored, factors that block as
+// k_diag_block would (its L11^{-1}, U11^{-1} into next.Linv, next.Uinv, which
+// must not be the buffers this launch reads), so the next step needs no
+// launch of its own for it.
+struct NextDiag {
+  int pb;
+  int32_t* Linv;
+  int32_t* Uinv;
+  int32_t* piv;
+  int64_t piv_stride;
+  int32_t* flags;
+};
+
 __global__ __launch_bounds__(256) void k_lu_update(int32_t* __restrict__ W, int64_t slab,
                                                    int64_t ldw, int j0, int pb, int M, int N,
                                                    const int32_t* __restrict__ Linv, int ldt,
                                                    const int32_t* __restrict__ Uinv,
                                                    const Modulus* __restrict__ mods, int kc4,
-                                                   unsigned* __restrict__ cnt, int cnt_stride) {
+                                                   unsigned* __restrict__ cnt, int cnt_stride,
+                                                   NextDiag next) {
   const int z = blockIdx.z;
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
@@ -691,6 +604,13 @@ __global__ __launch_bounds__(256) void k_lu_update(int32_t* __restrict__ W, int6
           Wz[(int64_t)(r0 + gr) * ldw + r0 + gc] =
               (int32_t)mod_c((double)vc[i][j][r] - mod_c(acc[i][j][r], p, pinv), p, pinv);
       }
+  if (next.pb > 0 && blockIdx.x == 0 && blockIdx.y == 0) {
+    __syncthreads();                                    // the tile is stored; sA is free
+    double* scr = &sA[0][0];
+    diag_block_body<4>(Wz + (int64_t)r0 * ldw + r0, ldw, next.pb, p, pinv,
+                       next.piv + (int64_t)z * next.piv_stride, r0, next.flags + z,
+                       next.Linv + (int64_t)z * 1024, next.Uinv + (int64_t)z * 1024, scr, scr + 128);
+  }
 }
 
 // ------------------------------------------------------------------ K4: in-place triangular apply
@@ -1073,7 +993,7 @@ hipError_t launch_diag_block(int32_t* W, int64_t ldw, int64_t slab, int j0, int 
                              const Modulus* mods, int32_t* piv, int64_t piv_stride, int32_t* flags,
                              int32_t* Linv, int32_t* Uinv, int nitems, hipStream_t st) {
   if (pb < 1 || pb > 32 || !Linv || !Uinv) return hipErrorInvalidValue;
-  k_diag_block<<<nitems, 64, 0, st>>>(W, ldw, slab, j0, pb, mods, piv, piv_stride, flags, Linv, Uinv);
+  k_diag_block<<<nitems, 256, 0, st>>>(W, ldw, slab, j0, pb, mods, piv, piv_stride, flags, Linv, Uinv);
   LAUNCH_CHECK();
   return hipSuccess;
 }
@@ -1125,13 +1045,18 @@ hipError_t launch_gemm_f64(int32_t* W, int64_t slab, int64_t offC, int64_t offA,
 hipError_t launch_lu_update(int32_t* W, int64_t slab, int64_t ldw, int j0, int pb, int M, int N,
                             const int32_t* Linv, int ldt, const int32_t* Uinv,
                             const Modulus* mods, int kc4, unsigned* cnt, int cnt_stride,
-                            int nitems, hipStream_t st) {
+                            int nitems, hipStream_t st, int next_pb, int32_t* next_Linv,
+                            int32_t* next_Uinv, int32_t* piv, int64_t piv_stride, int32_t* flags) {
   if (M < 0 || N <= 0 || nitems <= 0) return hipSuccess;
   if (pb < 1 || pb > 32 || pb > ldt || kc4 < 1) return hipErrorInvalidValue;
   dim3 grid((N + GB_N - 1) / GB_N, std::max(1, (M + GB_M - 1) / GB_M), nitems);
   if (cnt != nullptr && (int)grid.x > cnt_stride) return hipErrorInvalidValue;
+  if (next_pb > 0 && (next_pb > 32 || next_pb > M || !next_Linv || !next_Uinv || !piv || !flags ||
+                      next_Linv == Linv || next_Uinv == Uinv))
+    return hipErrorInvalidValue;
+  const NextDiag nd{next_pb, next_Linv, next_Uinv, piv, piv_stride, flags};
   k_lu_update<<<grid, 256, 0, st>>>(W, slab, ldw, j0, pb, M, N, Linv, ldt, Uinv, mods, kc4, cnt,
-                                    cnt_stride);
+                                    cnt_stride, nd);
   LAUNCH_CHECK();
   return hipSuccess;
 }

@@ -461,4 +461,156 @@ __device__ __forceinline__ void panel_body(int32_t* __restrict__ Wr, int64_t ldw
   }
 }
 
+// ------------------------------------------------------------------ diagonal block body
+// Factors the pb x pb diagonal block (pb <= 32) whose top-left entry is Wb
+// (leading dimension ldw) without a pivot search below it, with a workgroup of
+// NW waves (row i of the block belongs to wave i % NW).  Column c of
+// [A11 | I] is lane c of every wave (32 + 32 columns; a block narrower than
+// 32 is padded with the identity).  A fraction-free elimination,
+// row_i <- b_k row_i - r_ik row_k for i > k with b_k = the pivot-column entry
+// of row k, leaves row i scaled by sigma_i = b_0 ... b_{i-1}, so
+// [U | L^{-1}] row i = row i / sigma_i and no inverse is needed inside the
+// loop.  All 1 / sigma_i come from one Fermat ladder: with prefix products
+// P_k = b_0 ... b_k and suffix products S_k = b_k ... b_31 (scans across the
+// lanes of wave 0), sigma_i = P_{i-1} and 1 / sigma_i = S_i / P_31.  Then
+// U^{-1} by a backward elimination of [U' | D^{-1}] (U = D U',
+// D = diag(u_ii), 1 / u_ii = sigma_i / b_i).  The pivot row of each step
+// reaches the other waves through LDS (sRow: 2 x 64 doubles, alternating, so
+// one barrier a step).
+// Outputs: U11 into the block (on and above the diagonal), L11^{-1} and
+// U11^{-1} dense 32 x 32 row-major at Lz, Uz (zero outside pb x pb),
+// piv_z[j0 + i] = j0 + i, *flag = 1 when a pivot is 0 mod p (the caller then
+// runs the full pivot search).  Values stay below (p + 9) / 2 in magnitude
+// through the loose reductions, so every product is below 2^52.
+__device__ __forceinline__ double shfl_up_dd(double x, int d) {
+  const long long b = __builtin_bit_cast(long long, x);
+  const int lo = __shfl_up((int)b, d, 64), hi = __shfl_up((int)(b >> 32), d, 64);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double shfl_down_dd(double x, int d) {
+  const long long b = __builtin_bit_cast(long long, x);
+  const int lo = __shfl_down((int)b, d, 64), hi = __shfl_down((int)(b >> 32), d, 64);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+
+template <int NW>
+__device__ __forceinline__ void diag_block_body(int32_t* __restrict__ Wb, int64_t ldw, int pb,
+                                                double p, double pinv, int32_t* __restrict__ piv_z,
+                                                int j0, int32_t* __restrict__ flag,
+                                                int32_t* __restrict__ Lz, int32_t* __restrict__ Uz,
+                                                double* sRow, double* sV) {
+  constexpr int RW = 32 / NW;
+  static_assert(32 % NW == 0, "waves");
+  const int t = threadIdx.x;
+  const int c = t & 63, w = t >> 6;
+  const uint32_t e_inv = (uint32_t)__builtin_amdgcn_readfirstlane((int)((uint32_t)p - 2u));
+  double F[RW];
+  if (w < NW) {
+#pragma unroll
+    for (int q = 0; q < RW; q++) {
+      const int i = w + NW * q;
+      if (c < 32) F[q] = (i < pb && c < pb) ? (double)Wb[(int64_t)i * ldw + c] : (i == c ? 1.0 : 0.0);
+      else F[q] = (i == c - 32) ? 1.0 : 0.0;
+    }
+  }
+  bool zero = false;
+  // ---- fraction-free elimination
+  for (int k = 0; k < 32; k++) {
+    double* row = sRow + (k & 1) * 64;
+    if (w == k % NW) {
+      const int oq = k / NW;
+      double v = 0.0;
+#pragma unroll
+      for (int q = 0; q < RW; q++) v = q == oq ? F[q] : v;
+      row[c] = v;
+    }
+    __syncthreads();
+    const double fk = row[c < 64 ? c : 0];
+    const double braw = row[k];
+    zero |= braw == 0.0;
+    const double bk = braw == 0.0 ? 1.0 : braw;      // (the result is discarded then)
+    if (t == 0) sV[k] = bk;
+    if (w < NW) {
+#pragma unroll
+      for (int q = 0; q < RW; q++) {
+        const int i = w + NW * q;
+        const double r = readlane_d(F[q], k);
+        if (i > k) F[q] = mod_loose(fma(bk, F[q], -r * fk), p, pinv);
+      }
+    }
+  }
+  __syncthreads();
+  // ---- 1 / sigma_i and 1 / u_ii (wave 0)
+  if (w == 0) {
+    const double bv = c < 32 ? sV[c] : 1.0;
+    double P = bv, S = bv;
+#pragma unroll
+    for (int d = 1; d < 32; d <<= 1) {
+      const double u = shfl_up_dd(P, d), v = shfl_down_dd(S, d);
+      if ((c & 31) >= d) P = mul_mod_loose(P, u, p, pinv);
+      if ((c & 31) + d < 32) S = mul_mod_loose(S, v, p, pinv);
+    }
+    P = mod_c(P, p, pinv);
+    S = mod_c(S, p, pinv);
+    const double Q = pow_mod_fixed(readlane_d(P, 31), e_inv, p, pinv);   // 1 / (b_0 ... b_31)
+    const double sinv = mul_mod(S, Q, p, pinv);                          // 1 / sigma_c
+    const double Pm1 = shfl_up_dd(P, 1), Sp1 = shfl_down_dd(S, 1);
+    const double sig = (c & 31) == 0 ? 1.0 : Pm1;                        // sigma_c
+    const double snext = (c & 31) == 31 ? 1.0 : Sp1;
+    const double binv = mul_mod(mul_mod(sig, snext, p, pinv), Q, p, pinv);   // 1 / b_c
+    if (c < 32) {
+      sV[32 + c] = sinv;
+      sV[64 + c] = mul_mod(sig, binv, p, pinv);                         // 1 / u_cc
+    }
+  }
+  __syncthreads();
+  if (w < NW) {
+    // rows of [U | L^{-1}], then [U' | D^{-1}]
+#pragma unroll
+    for (int q = 0; q < RW; q++) {
+      const int i = w + NW * q;
+      F[q] = mul_mod(F[q], sV[32 + i], p, pinv);
+      if (c < 32) {
+        if (c < pb && i <= c) Wb[(int64_t)i * ldw + c] = (int32_t)F[q];
+      } else {
+        const int cc = c - 32;
+        Lz[i * 32 + cc] = (i < pb && cc < pb) ? (int32_t)F[q] : 0;
+      }
+      const double di = sV[64 + i];
+      F[q] = c < 32 ? mul_mod(F[q], di, p, pinv) : (i == c - 32 ? di : 0.0);
+    }
+  }
+  // ---- backward elimination: U^{-1} = U'^{-1} D^{-1}
+  for (int k = 31; k > 0; k--) {
+    double* row = sRow + (k & 1) * 64;
+    if (w == k % NW) {
+      const int oq = k / NW;
+      double v = 0.0;
+#pragma unroll
+      for (int q = 0; q < RW; q++) v = q == oq ? F[q] : v;
+      row[c] = v;
+    }
+    __syncthreads();
+    const double fk = row[c];
+    if (w < NW) {
+#pragma unroll
+      for (int q = 0; q < RW; q++) {
+        const int i = w + NW * q;
+        const double r = readlane_d(F[q], k);
+        if (i < k) F[q] = mod_loose(fma(-r, fk, F[q]), p, pinv);
+      }
+    }
+  }
+  if (w < NW && c >= 32) {
+    const int cc = c - 32;
+#pragma unroll
+    for (int q = 0; q < RW; q++) {
+      const int i = w + NW * q;
+      Uz[i * 32 + cc] = (i < pb && cc < pb) ? (int32_t)mod_c(F[q], p, pinv) : 0;
+    }
+  }
+  if (t < pb) piv_z[j0 + t] = j0 + t;
+  if (zero && t == 0) *flag = 1;
+}
+
 }  // namespace detk
