@@ -635,8 +635,9 @@ det_status lift3_multi(det_ctx* c, int grid3, const int64_t* dA, int64_t dlda, i
   int* err = (int*)((char*)c->sync.p + 32);
   int* herr = (int*)c->hsmall.p;
   char* hs = (char*)c->hstage.p;
-  for (int h0 = 0; h0 < m; h0 += MR) {
-    const int mm = std::min(MR, m - h0);
+  const int mr = detk::lift3_max_rhs(n);
+  for (int h0 = 0; h0 < m; h0 += mr) {
+    const int mm = std::min(mr, m - h0);
     if (h0 > 0) HIPCHK(hipStreamSynchronize(c->st));    // the staging of the last chunk is read
     // r_0 = b and its balanced digits mod p^3 (each centring carried into the
     // next digit), one record of 25-bit fields under tag 0 (step 0) per row

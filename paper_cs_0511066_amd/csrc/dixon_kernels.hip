@@ -46,7 +46,7 @@ __device__ __forceinline__ uint32_t umod64(uint64_t v, uint32_t p, double pinv) 
 
 // v mod p in [0, p) for an integer-valued double with |v| < 2^52.
 __device__ __forceinline__ double canon_p(double v, double pd, double pinv) {
-  const double r = fma(-rint(v * pinv), pd, v);
+  const double r = fma(-quot_p(v, pinv), pd, v);
   return r < 0.0 ? r + pd : r;
 }
 
@@ -571,9 +571,11 @@ static int lift3_grid_size(int n) {
   return (n + LIFT3_RPW * LIFT3_NWAVE - 1) / (LIFT3_RPW * LIFT3_NWAVE);
 }
 
+int lift3_max_rhs(int n) { return n <= 1024 ? LIFT3_MAX_RHS : 1; }
+
 int lift3_grid(int device, int n) {
   int cus = 0, coop = 0;
-  if (n > 1024) return 0;
+  if (n > 2048) return 0;
   if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, device) != hipSuccess ||
       !coop)
     return 0;
@@ -712,7 +714,7 @@ __global__ __launch_bounds__(256) void k_hensel_f64(const void* __restrict__ Lv,
         const int64_t o = (int64_t)gr * n + gc;
         if (MODE == 0) {
           const double ein = Ein ? Ein[o] : (gr == gc ? -1.0 : 0.0);
-          ((double*)out)[o] = rint((ein + acc[i][j][r]) * pinv);
+          ((double*)out)[o] = quot_p(ein + acc[i][j][r], pinv);
         } else {
           const double v = mod_c(-acc[i][j][r], pd, pinv);
           ((uint32_t*)out)[o] = (uint32_t)(v < 0 ? v + pd : v);
@@ -790,8 +792,8 @@ __device__ __forceinline__ int32_t centred_i32(uint32_t u, uint32_t p) {
 //   r' = (((r - D0)/p - D1)/p - D2)/p,
 // every partial value an integer below 2^53 (|r| stays below n ||A|| + ||b||),
 // so the per-row steps run in FP64 too: an exact quotient by p is
-// rint(v * (1/p)), as |v / p| < 2^28 keeps the error of the reciprocal far
-// below 1/2.
+// the integer nearest to v * (1/p) (quot_p), as |v / p| < 2^28 keeps the
+// error of the reciprocal far below 1/2.
 //
 // No grid barrier: every exchanged 32-bit word holds a 25-bit digit (two's
 // complement for r, plain for x) under a 7-bit tag, the step number mod 127,
@@ -808,7 +810,7 @@ __device__ __forceinline__ int32_t centred_i32(uint32_t u, uint32_t p) {
 // longer to become visible than one contiguous write.  A wait that exceeds
 // spin_limit polls sets *err; after that every wait gives up within 64
 // polls, so all waves exit.
-template <int EPL, int RPW, int NWAVE, int NRHS>
+template <int EPL, int RPW, int NWAVE, int NRHS, bool NARROW>
 __global__ __launch_bounds__(64 * NWAVE) void k_lift_resident3(
     const uint32_t* __restrict__ C0, const uint32_t* __restrict__ C1,
     const uint32_t* __restrict__ C2, const int32_t* __restrict__ Ai, int64_t* __restrict__ r,
@@ -906,8 +908,11 @@ __global__ __launch_bounds__(64 * NWAVE) void k_lift_resident3(
     if (threadIdx.x < 4 * RG * NRHS && row0 + (int)threadIdx.x / (4 * NRHS) < n)
       st_dev(v + (size_t)row0 * NRHS * 4 + threadIdx.x, sOut[threadIdx.x]);
   };
-  // centred planes and the rows of A, FP64 in registers
-  double c0[RPW][EPL], c1[RPW][EPL], c2[RPW][EPL], av[RPW][EPL];
+  // centred planes and the rows of A in registers: c0, c1 as FP64; c2 and A
+  // as FP64, or (NARROW, for the largest orders) as int32 converted at use
+  typedef typename std::conditional<NARROW, int32_t, double>::type nar_t;
+  double c0[RPW][EPL], c1[RPW][EPL];
+  nar_t c2[RPW][EPL], av[RPW][EPL];
   double rr[RPW][NRHS];                            // r of the row (lane 0), integers
   int rows[RPW];
 #pragma unroll
@@ -921,8 +926,8 @@ __global__ __launch_bounds__(64 * NWAVE) void k_lift_resident3(
       const int64_t o = (int64_t)row * n + j;
       c0[i][e] = in ? (double)centred_i32(C0[o], p) : 0.0;
       c1[i][e] = in ? (double)centred_i32(C1[o], p) : 0.0;
-      c2[i][e] = in ? (double)centred_i32(C2[o], p) : 0.0;
-      av[i][e] = in ? (double)Ai[o] : 0.0;
+      c2[i][e] = in ? (nar_t)centred_i32(C2[o], p) : (nar_t)0;
+      av[i][e] = in ? (nar_t)Ai[o] : (nar_t)0;
     }
 #pragma unroll
     for (int h = 0; h < NRHS; h++)
@@ -955,7 +960,7 @@ __global__ __launch_bounds__(64 * NWAVE) void k_lift_resident3(
           S1b[i][h] = fma(c1[i][e], w0, S1b[i][h]);
           S2a[i][h] = fma(c0[i][e], w2, S2a[i][h]);
           S2b[i][h] = fma(c1[i][e], w1, S2b[i][h]);
-          S2c[i][h] = fma(c2[i][e], w0, S2c[i][h]);
+          S2c[i][h] = fma((double)c2[i][e], w0, S2c[i][h]);
         }
       }
     }
@@ -964,10 +969,10 @@ __global__ __launch_bounds__(64 * NWAVE) void k_lift_resident3(
     for (int i = 0; i < RPW; i++)
 #pragma unroll
       for (int h = 0; h < NRHS; h++) {
-        const double q0 = rint(S0[i][h] * pinv), m0 = fma(-q0, pd, S0[i][h]);
-        const double qa = rint(S1a[i][h] * pinv), ma = fma(-qa, pd, S1a[i][h]);
+        const double q0 = quot_p(S0[i][h], pinv), m0 = fma(-q0, pd, S0[i][h]);
+        const double qa = quot_p(S1a[i][h], pinv), ma = fma(-qa, pd, S1a[i][h]);
         const double T1 = ma + S1b[i][h] + q0;
-        const double q1 = rint(T1 * pinv), m1 = fma(-q1, pd, T1);
+        const double q1 = quot_p(T1, pinv), m1 = fma(-q1, pd, T1);
         const double T2 = mod_loose(S2a[i][h], pd, pinv) + mod_loose(S2b[i][h], pd, pinv) +
                           mod_loose(S2c[i][h], pd, pinv) + qa + q1;
         const double m2 = mod_loose(T2, pd, pinv);
@@ -977,9 +982,9 @@ __global__ __launch_bounds__(64 * NWAVE) void k_lift_resident3(
         if (rows[i] < n && lane == 0) {
           // carries (|M| < 2^31): exact quotients by p in FP64
           const double x0d = canon_p((double)M0, pd, pinv);
-          const double t1 = (double)M1 + rint(((double)M0 - x0d) * pinv);
+          const double t1 = (double)M1 + quot_p((double)M0 - x0d, pinv);
           const double x1d = canon_p(t1, pd, pinv);
-          const double t2 = (double)M2 + rint((t1 - x1d) * pinv);
+          const double t2 = (double)M2 + quot_p(t1 - x1d, pinv);
           const uint32_t x0 = (uint32_t)x0d, x1 = (uint32_t)x1d;
           const uint32_t x2 = (uint32_t)canon_p(t2, pd, pinv);
           uint32_t* o = sOut + ((wave * RPW + i) * NRHS + h) * 4;
@@ -1012,9 +1017,10 @@ __global__ __launch_bounds__(64 * NWAVE) void k_lift_resident3(
         const double x2 = (double)sV[1][h][2][lane + 64 * e];
 #pragma unroll
         for (int i = 0; i < RPW; i++) {
-          D0[i][h] = fma(av[i][e], x0, D0[i][h]);
-          D1[i][h] = fma(av[i][e], x1, D1[i][h]);
-          D2[i][h] = fma(av[i][e], x2, D2[i][h]);
+          const double ae = (double)av[i][e];
+          D0[i][h] = fma(ae, x0, D0[i][h]);
+          D1[i][h] = fma(ae, x1, D1[i][h]);
+          D2[i][h] = fma(ae, x2, D2[i][h]);
         }
       }
     }
@@ -1027,16 +1033,16 @@ __global__ __launch_bounds__(64 * NWAVE) void k_lift_resident3(
         const double d2 = dpp_sum_f64(D2[i][h]);
         if (rows[i] < n && lane == 0) {
           // exact divisions by p
-          double q = rint((rr[i][h] - d0) * pinv);
-          q = rint((q - d1) * pinv);
-          q = rint((q - d2) * pinv);
+          double q = quot_p(rr[i][h] - d0, pinv);
+          q = quot_p(q - d1, pinv);
+          q = quot_p(q - d2, pinv);
           rr[i][h] = q;
           // balanced digits of r' mod p^3, the carry of each centring taken
           // into the next digit, so that m0 + p m1 + p^2 m2 = r' (mod p^3)
           const double m0d = mod_c(q, pd, pinv);
-          const double u1 = rint((q - m0d) * pinv);
+          const double u1 = quot_p(q - m0d, pinv);
           const double m1d = mod_c(u1, pd, pinv);
-          const double u2 = rint((u1 - m1d) * pinv);
+          const double u2 = quot_p(u1 - m1d, pinv);
           const int32_t m0 = (int32_t)m0d, m1 = (int32_t)m1d;
           const int32_t m2 = (int32_t)mod_c(u2, pd, pinv);
           uint32_t* o = sOut + ((wave * RPW + i) * NRHS + h) * 4;
@@ -1106,11 +1112,16 @@ hipError_t launch_lift_resident3(int grid, const uint32_t* C0, const uint32_t* C
                   (void*)&digits, (void*)&err, (void*)&spin_limit};
   const void* f = nullptr;
 #define LIFT3_PICK(E)                                                                        \
-  f = nrhs == 1 ? (const void*)k_lift_resident3<E, LIFT3_RPW, LIFT3_NWAVE, 1>                 \
-                : (const void*)k_lift_resident3<E, LIFT3_RPW, LIFT3_NWAVE, 2>
+  f = nrhs == 1 ? (const void*)k_lift_resident3<E, LIFT3_RPW, LIFT3_NWAVE, 1, false>          \
+                : (const void*)k_lift_resident3<E, LIFT3_RPW, LIFT3_NWAVE, 2, false>
+  if (nrhs > lift3_max_rhs(n)) return hipErrorInvalidValue;
   if (n <= 256) LIFT3_PICK(4);
   else if (n <= 512) LIFT3_PICK(8);
   else if (n <= 1024) LIFT3_PICK(16);
+  // above 1024 the third plane and A stay int32 in registers, one
+  // right-hand side a launch (the registers of 8 waves a CU hold no more)
+  else if (n <= 1536) f = (const void*)k_lift_resident3<24, LIFT3_RPW, LIFT3_NWAVE, 1, true>;
+  else if (n <= 2048) f = (const void*)k_lift_resident3<32, LIFT3_RPW, LIFT3_NWAVE, 1, true>;
 #undef LIFT3_PICK
   if (!f || grid != lift3_grid_size(n)) return hipErrorInvalidValue;
   return hipLaunchCooperativeKernel(f, dim3(grid), dim3(64 * LIFT3_NWAVE), args, 0, st);

@@ -351,6 +351,11 @@ inline int64_t extended_bonus_host(const uint64_t* comb, int m, int64_t k, uint6
       s = BigInt::div_exact(s * d, BigInt::gcd(s, d));
     }
   if (failed) return failed;
+  if (m == 1) {
+    // one solving: pi~_1 = s~ (Alg. 4.1), no determinant to take
+    pi = s;
+    return 0;
+  }
   // R N (rows a, columns h): exact, as every den divides s~
   std::vector<std::vector<BigInt>> RN(m, std::vector<BigInt>(m));
   for (int a = 0; a < m; a++)

@@ -92,7 +92,7 @@ hipError_t launch_lift_persistent(int grid, const uint32_t* Cu, const int32_t* A
 // step C1 = digit plane of A^{-1} mod p^2 (E: n x n scratch), then all steps.
 hipError_t launch_hensel(const int32_t* Ai, const uint32_t* Cu, uint32_t* E, uint32_t* C1, int n,
                          uint32_t p, hipStream_t st);
-// Lifting modulo p^3 in FP64 (p < 2^25, n ||A|| p < 2^53): Hensel planes
+// Lifting modulo p^3 in FP64 (p < 2^25, n ||A|| p < 2^53, n <= 2048): Hensel planes
 // C1, C2 of A^{-1} mod p^3 from C0 = A^{-1} mod p (E: n x n FP64 scratch),
 // then all steps in one cooperative launch, three digits per step.
 int lift3_grid(int device, int n);    // 0: the three-plane form does not apply
@@ -111,6 +111,7 @@ hipError_t launch_hensel_f64(const int32_t* Ai, const uint32_t* C0, double* E, u
 // launch); r: n x nrhs (row-major); digits: nrhs x kd x n.  nrhs <= LIFT3_MAX_RHS
 // right-hand sides share one launch.
 constexpr int LIFT3_MAX_RHS = 2;
+int lift3_max_rhs(int n);             // right-hand sides one launch takes at order n
 hipError_t launch_lift_resident3(int grid, const uint32_t* C0, const uint32_t* C1,
                                  const uint32_t* C2, const int32_t* Ai, int64_t* r, uint32_t* rv,
                                  uint32_t* xv, int n, int nrhs, uint32_t p, int64_t kd,

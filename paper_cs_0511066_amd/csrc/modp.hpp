@@ -4,7 +4,7 @@
 // computed in FP64.  A product of two centred residues is below 2^50 in
 // magnitude, so it is exact in FP64; a sum of such products stays exact as
 // long as the sum of absolute values stays <= 2^53 (the chunk bound that the
-// host computes and passes as `kc`).  Reduction: q = rint(c / p) from a
+// host computes and passes as `kc`).  Reduction: q = nearest integer to c / p from a
 // precomputed 1/p, r = c - q p by one fused multiply-add (exact, since the
 // true result is a small integer), then one fold into the centred range.
 #pragma once
@@ -13,9 +13,19 @@
 
 namespace detk {
 
+// The integer nearest to c / p for an integer-valued |c| <= 2^53: the
+// product c * (1/p) is rounded to an integer inside one fused multiply-add
+// with 1.5 * 2^52 (whose unit in the last place is 1; |c / p| < 2^51), and
+// the constant is taken off again.  Within one of c / p, which is all the
+// reductions below need.
+__device__ __forceinline__ double quot_p(double c, double pinv) {
+  constexpr double RND = 6755399441055744.0;
+  return fma(c, pinv, RND) - RND;
+}
+
 // c: an integer-valued double with |c| <= 2^53.  Returns c mod p, centred.
 __device__ __forceinline__ double mod_c(double c, double p, double pinv) {
-  double q = rint(c * pinv);
+  double q = quot_p(c, pinv);
   double r = fma(-q, p, c);
   double h = 0.5 * p;                 // p odd: the centred range is |r| < p/2
   r = (r > h) ? r - p : r;
@@ -26,7 +36,7 @@ __device__ __forceinline__ double mod_c(double c, double p, double pinv) {
 // c mod p without the final fold: |c| <= 2^53 gives a result congruent to c
 // with |r| <= h + 5 (h = (p-1)/2), so r == 0 exactly when p divides c.
 __device__ __forceinline__ double mod_loose(double c, double p, double pinv) {
-  return fma(-rint(c * pinv), p, c);
+  return fma(-quot_p(c, pinv), p, c);
 }
 
 __device__ __forceinline__ double mul_mod(double a, double b, double p, double pinv) {
@@ -38,7 +48,7 @@ __device__ __forceinline__ double mul_mod(double a, double b, double p, double p
 // these stay exact and need one fold at the end.  Four dependent operations.
 __device__ __forceinline__ double mul_mod_loose(double a, double b, double p, double pinv) {
   const double c = a * b;
-  return fma(-rint(c * pinv), p, c);
+  return fma(-quot_p(c, pinv), p, c);
 }
 
 // a^e mod p by square-and-multiply (e >= 0); the squaring chain is the only

@@ -292,6 +292,27 @@ def test_dixon_lift_n1024_invariant(ctx, bits, k):
         r = t // p
 
 
+@pytest.mark.parametrize("n,lo,hi,k,seed", [(1100, -100, 100, 12, 31), (1536, -1000, 1000, 390, 32),
+                                             (2048, -1024, 1024, 30, 33)])
+def test_dixon_lift_above_1024_invariant(ctx, n, lo, hi, k, seed):
+    """Orders above 1024 (the serving and precision sizes): the inverse from
+    the factors by the blocked back substitution (16-wide panels first), and
+    the FP64 three-digit lifting with the third plane and A kept as int32 in
+    registers, over 130 steps at n = 1536 (past the step-tag wrap).  Checked
+    with exact integers on the host: A x_i = r_i (mod p), p | r_i - A x_i."""
+    A = synth.dense_uniform(n, lo, hi, seed)
+    b = synth.random_rhs(n, 20000, seed)
+    p = test_primes(1 << 23, 1 << 24, 1, seed)[0]
+    _say("dixon_lift n =", n, "k =", k)
+    X = ctx.dixon_lift(A, b, p, k).astype(np.int64)
+    r = b.astype(np.int64)
+    for i in range(k):
+        assert np.all((X[i] >= 0) & (X[i] < p))
+        t = r - A @ X[i]
+        assert np.all(t % p == 0), i
+        r = t // p
+
+
 @pytest.mark.gpu
 @pytest.mark.parametrize("n,m,k", [(1, 2, 5), (5, 3, 8), (33, 2, 6), (64, 2, 30), (150, 3, 7),
                                    (300, 2, 3)])
