@@ -46,14 +46,21 @@ def log(*a):
 # (FETCH_SIZE and WRITE_SIZE, each scaled by the reading of a plain copy of
 # known size) and recorded with a hash of the kernel source it was taken on.
 TRAFFIC = {
-    "lift": ("profiles/lift_resident3_n1024_traffic.txt", "paper_cs_0511066_amd/csrc/dixon_kernels.hip"),
-    "panel": ("profiles/panel_n1024_traffic.txt", "paper_cs_0511066_amd/csrc/lu_kernels.hip"),
+    "lift": ("profiles/lift_resident3_n1024_traffic.txt",
+             "paper_cs_0511066_amd/csrc/dixon_kernels.hip,paper_cs_0511066_amd/csrc/modp.hpp"),
+    "gemm_f64": ("profiles/lu_update_gemm_mod_n1024_traffic.txt",
+                 "paper_cs_0511066_amd/csrc/lu_kernels.hip,paper_cs_0511066_amd/csrc/modp.hpp,"
+                 "paper_cs_0511066_amd/csrc/panel.hpp"),
 }
 
 
-def source_hash(path):
-    with open(os.path.join(ROOT, path), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+def source_hash(paths):
+    """Hash of the kernel sources (comma-separated paths, in that order)."""
+    h = hashlib.sha256()
+    for path in paths.split(","):
+        with open(os.path.join(ROOT, path), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(kernel):

@@ -75,10 +75,7 @@ __global__ __launch_bounds__(256, WPE) void k_lu_queue(const LuItem* __restrict_
       int32_t* wrow = W + (int64_t)i * ldw;
       int64_t v[8];
 #pragma unroll
-      for (int u = 0; u < 8; u++) {
-        const int j = lane + 64 * u;
-        v[u] = j < n ? row[j] : 0;
-      }
+      for (int u = 0; u < 8; u++) v[u] = row[min(lane + 64 * u, n - 1)];   // clamped: no waits
 #pragma unroll
       for (int u = 0; u < 8; u++) {
         const int j = lane + 64 * u;
@@ -93,16 +90,36 @@ __global__ __launch_bounds__(256, WPE) void k_lu_queue(const LuItem* __restrict_
       __syncthreads();                           // panel written back, swaps done, L11^{-1} stored
       const int r0 = j0 + pb, M = n - r0;
       if (M <= 0) break;
-      for (int e = t; e < PB * PB; e += T) {
-        const int r = e / PB, c = e % PB;
-        sT[r][c] = (r < pb && c < pb) ? (double)linv[r * PB + c] : 0.0;
+      // Loads below are unconditional, from indices clamped into range, and
+      // the padding is selected when they are stored: a load under a
+      // condition becomes a branch that waits for its own data.
+      constexpr int NTL = (PB * PB + T - 1) / T;
+      int32_t vt[NTL];
+#pragma unroll
+      for (int u = 0; u < NTL; u++) {
+        const int e = u * T + t;
+        vt[u] = linv[min(e / PB, pb - 1) * PB + min(e % PB, pb - 1)];
       }
-      // the strip A12 = rows [j0, j0 + pb) x columns [r0, n), every load in
-      // flight at once; rows k >= pb and columns past M are zero
+#pragma unroll
+      for (int u = 0; u < NTL; u++) {
+        const int e = u * T + t, r = e / PB, c = e % PB;
+        if (e < PB * PB) sT[r][c] = (r < pb && c < pb) ? (double)vt[u] : 0.0;
+      }
+      // the strip A12 = rows [j0, j0 + pb) x columns [r0, n), eight loads in
+      // flight a thread; rows k >= pb and columns past M are zero
       const int M64 = (M + 63) / 64 * 64;
-      for (int e = t; e < PB * M64; e += T) {
-        const int k = e / M64, c = e % M64;
-        sS[k * SW + c] = (k < pb && c < M) ? W[(int64_t)(j0 + k) * ldw + r0 + c] : 0;
+      for (int e0 = 0; e0 < PB * M64; e0 += 8 * T) {
+        int32_t v[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++) {
+          const int e = e0 + u * T + t, k = e / M64, c = e % M64;
+          v[u] = W[(int64_t)(j0 + min(k, pb - 1)) * ldw + r0 + min(c, M - 1)];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; u++) {
+          const int e = e0 + u * T + t, k = e / M64, c = e % M64;
+          if (e < PB * M64) sS[k * SW + c] = (k < pb && c < M) ? v[u] : 0;
+        }
       }
       __syncthreads();
       // U12 = L11^{-1} A12 over the strip: 16-column blocks, block b of wave
@@ -151,7 +168,7 @@ __global__ __launch_bounds__(256, WPE) void k_lu_queue(const LuItem* __restrict_
             for (int r = 0; r < 4; r++) {
               const int gr = rt + wr * 32 + i * 16 + (lane >> 4) + 4 * r;
               const int gc = ct + wc * 32 + j * 16 + (lane & 15);
-              v[i][j][r] = (gr < M && gc < M) ? W[(int64_t)(r0 + gr) * ldw + r0 + gc] : 0;
+              v[i][j][r] = W[(int64_t)(r0 + min(gr, M - 1)) * ldw + r0 + min(gc, M - 1)];
             }
       };
       load_c(0, vc);

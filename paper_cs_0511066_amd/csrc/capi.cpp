@@ -510,7 +510,13 @@ uint64_t inv_mod_2_64(uint64_t p) {
 det_status ensure_pinned(det_ctx* c, size_t count);
 
 // A^{-1} mod p into c->Cu by LU of [A | I] and back substitution.
-det_status inverse_mod_p(det_ctx* c, const int64_t* dA, int64_t dlda, int n, uint32_t p) {
+// With `deferred` (and the block pivot search on) only the block search runs
+// and nothing waits for it: the flag that says a block column had no non-zero
+// entry is copied to the pinned word *deferred, valid once the caller has
+// synchronised c->st; the caller then discards what it computed from c->Cu
+// and calls again without `deferred`.
+det_status inverse_mod_p(det_ctx* c, const int64_t* dA, int64_t dlda, int n, uint32_t p,
+                         const int32_t** deferred = nullptr) {
   LuWs& w = c->ws[0];
   // with every panel 32 wide the inverse is formed from the factors in a few
   // launches (inverse_from_lu, four n-wide regions), else by the blocked back
@@ -541,6 +547,7 @@ det_status inverse_mod_p(det_ctx* c, const int64_t* dA, int64_t dlda, int n, uin
   // then take a few rows instead of all of them); if some block column has
   // no non-zero entry, again with the full pivot search, whose flag means
   // that p divides det(A)
+  if (deferred) *deferred = nullptr;
   for (int attempt = 0; attempt < 2; attempt++) {
     const bool block_pivots = attempt == 0 && c->block_pivots;
     if (attempt == 1 && !c->block_pivots) break;
@@ -549,6 +556,10 @@ det_status inverse_mod_p(det_ctx* c, const int64_t* dA, int64_t dlda, int n, uin
                                  (const Modulus*)w.mods.p, 1, w.st));
     TRY(lu_factor(c, w, J, true, &panels, block_pivots));
     HIPCHK(hipMemcpyAsync(flag, w.flags.p, sizeof(int32_t), hipMemcpyDeviceToHost, w.st));
+    if (block_pivots && deferred) {
+      *deferred = flag;
+      break;
+    }
     HIPCHK(hipStreamSynchronize(w.st));
     if (!*flag) break;
     if (!block_pivots) return fail(c, DET_E_SINGULAR_MOD_P, "p divides det(A)");
@@ -605,7 +616,7 @@ det_status pack_matrix(det_ctx* c, const int64_t* dA, int64_t dlda, int n) {
 det_status lift3_multi(det_ctx* c, int grid3, const int64_t* dA, int64_t dlda, int n,
                        const int64_t* B, int m, uint32_t p, int64_t k, uint32_t* digits_dev,
                        const uint32_t* cvec_dev, uint64_t* comb_dev, bool after_own2,
-                       int ncv = 1) {
+                       int ncv = 1, const int** err_pending = nullptr) {
   constexpr int MR = detk::LIFT3_MAX_RHS;
   const double nn = (double)n * n;
   TRY(pack_matrix(c, dA, dlda, n));
@@ -681,6 +692,11 @@ det_status lift3_multi(det_ctx* c, int grid3, const int64_t* dA, int64_t dlda, i
                                           cvec_dev + (size_t)a * lift_pad(n),
                                           comb_dev + ((size_t)(h0 + hh) * ncv + a) * k, c->st));
     HIPCHK(hipMemcpyAsync(herr, err, sizeof(int), hipMemcpyDeviceToHost, c->st));
+    if (err_pending && h0 + mm >= m) {
+      // the caller synchronises c->st later and then reads the word
+      *err_pending = herr;
+      break;
+    }
     HIPCHK(hipStreamSynchronize(c->st));
     if (*herr) return fail(c, DET_E_DEVICE, "lifting: a wait for another workgroup's digits timed out");
   }
@@ -692,14 +708,19 @@ det_status lift3_multi(det_ctx* c, int grid3, const int64_t* dA, int64_t dlda, i
 // be null).
 // The cooperative form needs all its workgroups resident at once, so when
 // other work may be running on the context's second stream (`after_own2`),
-// the launch first waits for that stream.
+// the launch first waits for that stream.  With `err_pending` the FP64
+// three-digit form does not wait for the lifting: *err_pending is then the
+// pinned word of its error flag, valid after the caller synchronises c->st
+// (null when the form used has already checked it).
 det_status lift(det_ctx* c, const int64_t* dA, int64_t dlda, int n, double amax, const int64_t* b,
                 uint32_t p, int64_t k, uint32_t* digits_dev, const uint32_t* cvec_dev,
-                uint64_t* comb_dev, bool after_own2 = false) {
+                uint64_t* comb_dev, bool after_own2 = false,
+                const int** err_pending = nullptr) {
+  if (err_pending) *err_pending = nullptr;
   const int grid3 = c->lift_mode == 0 && lift3_applies(n, amax, p) ? detk::lift3_grid(c->device, n) : 0;
   if (grid3 > 0)      // lifting modulo p^3 in FP64: Hensel planes, then three digits a step
     return lift3_multi(c, grid3, dA, dlda, n, b, 1, p, k, digits_dev, cvec_dev, comb_dev,
-                       after_own2);
+                       after_own2, 1, err_pending);
   TRY(pack_matrix(c, dA, dlda, n));
   // rp and x are padded with zeros to lift_pad(n) entries (the
   // register-resident kernel loads 64 EPL entries without bounds tests)
@@ -1278,16 +1299,22 @@ det_status det_introspective(det_ctx* c, const int64_t* A, int64_t n, int64_t ld
     const int64_t beta = std::max<int64_t>(2, (int64_t)ceil(bd.log2_h));
     const int i_max = std::min(std::max(o.n_rhs, 1), 8);
     bool batch1_taken = false;
-    if (bd.log2_h > 0 && dixon_bits > 12) {
-      dethost::PrimeSampler dsamp(dethost::splitmix64(rng), dixon_bits);
+    dethost::PrimeSampler dsamp(dethost::splitmix64(rng), dixon_bits);
+    // Pass 0 takes the inverse with the block pivot search and does not wait
+    // for its flag: the flag is read with the first solving's results, and if
+    // a block column had no non-zero entry the solving is discarded and pass
+    // 1 starts over with the full search (and a fresh prime).
+    for (int pass = 0; pass < 2 && bd.log2_h > 0 && dixon_bits > 12; pass++) {
       // one prime and one inverse for every solving
       uint32_t p = 0;
       det_status st = DET_E_SINGULAR_MOD_P;
+      const int32_t* inv_flag = nullptr;
       for (int tries = 0; tries < 2 && st == DET_E_SINGULAR_MOD_P; tries++) {
         p = dsamp.next();
-        st = inverse_mod_p(c, dA, dlda, (int)n, p);
+        st = inverse_mod_p(c, dA, dlda, (int)n, p, pass == 0 && tries == 0 ? &inv_flag : nullptr);
       }
       if (st != DET_OK && st != DET_E_SINGULAR_MOD_P) return st;
+      bool redo = false;
       if (st == DET_OK) {                            // else det is probably 0: CRA alone
         // lifting length from the bounds of every combination R_a . x_h:
         // numerators |.| <= sum(R_a) H_col ||b|| / min_j ||a_j|| (Cramer,
@@ -1314,12 +1341,13 @@ det_status det_introspective(det_ctx* c, const int64_t* A, int64_t n, int64_t ld
           const double ts0 = now_ms();
           std::vector<int64_t> b(n);
           for (int64_t j = 0; j < n; j++) b[j] = (int64_t)(dethost::splitmix64(rng) % (uint64_t)beta);
-          TRY(lift(c, dA, dlda, (int)n, bd.amax, b.data(), p, k, dig + (size_t)(i - 1) * k * n,
-                   nullptr, nullptr, !batch1_taken));
-          // a fresh random i x n matrix R, and the i x i combinations R_a . x_h
+          // a fresh random i x n matrix R for the i x i combinations R_a . x_h
           for (int a = 0; a < i; a++)
             for (int64_t j = 0; j < n; j++)
               R[(size_t)a * npad + j] = 1 + (uint32_t)(dethost::splitmix64(rng) % 65535u);
+          const int* lift_err = nullptr;
+          TRY(lift(c, dA, dlda, (int)n, bd.amax, b.data(), p, k, dig + (size_t)(i - 1) * k * n,
+                   nullptr, nullptr, !batch1_taken, &lift_err));
           HIPCHK(hipMemcpyAsync(c->cvec.p, R.data(), (size_t)i * npad * sizeof(uint32_t),
                                 hipMemcpyHostToDevice, c->st));
           for (int h = 0; h < i; h++)
@@ -1331,6 +1359,17 @@ det_status det_introspective(det_ctx* c, const int64_t* A, int64_t n, int64_t ld
           HIPCHK(hipMemcpyAsync(comb.data(), c->comb.p, comb.size() * sizeof(uint64_t),
                                 hipMemcpyDeviceToHost, c->st));
           HIPCHK(hipStreamSynchronize(c->st));
+          if (inv_flag) {
+            const bool bad = *inv_flag != 0;
+            inv_flag = nullptr;
+            if (bad) {                               // see pass above
+              c->block_pivot_retries++;
+              redo = true;
+              break;
+            }
+          }
+          if (lift_err && *lift_err)
+            return fail(c, DET_E_DEVICE, "lifting: a wait for another workgroup's digits timed out");
           rep.lifting_steps += k;
           const double th0 = now_ms();
           BigInt sv, pi;
@@ -1363,6 +1402,7 @@ det_status det_introspective(det_ctx* c, const int64_t* A, int64_t n, int64_t ld
           K_prev = K;
         }
       }
+      if (!redo) break;
     }
     rep.sn_bits = K.bit_length();
     rep.t_lif_ms = now_ms() - tl0;

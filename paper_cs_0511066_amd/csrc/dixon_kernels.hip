@@ -855,14 +855,23 @@ __global__ __launch_bounds__(64 * NWAVE) void k_lift_resident3(
     }
     unsigned spins = 0;
     for (;;) {
+      // every record is read on every poll (a load under a condition would
+      // wait for its data before the next is issued; offsets past the
+      // vectors read as zero), and only the rows still wanted take the value
+      u32x4 b[NJ][NRHS];
 #pragma unroll
       for (int q = 0; q < NJ; q++)
 #pragma unroll
         for (int h = 0; h < NRHS; h++) {
           int off = 16 * ((threadIdx.x + 64 * NWAVE * q) * NRHS + h);
           asm volatile("" : "+v"(off));      // a fresh load on every poll
-          if (want[q][h]) a[q][h] = __builtin_amdgcn_raw_buffer_load_b128(src, off, 0, BUF_SC1);
+          b[q][h] = __builtin_amdgcn_raw_buffer_load_b128(src, off, 0, BUF_SC1);
         }
+#pragma unroll
+      for (int q = 0; q < NJ; q++)
+#pragma unroll
+        for (int h = 0; h < NRHS; h++)
+          if (want[q][h]) a[q][h] = b[q][h];
       bool pending = false;
 #pragma unroll
       for (int q = 0; q < NJ; q++)
@@ -919,15 +928,31 @@ __global__ __launch_bounds__(64 * NWAVE) void k_lift_resident3(
   for (int i = 0; i < RPW; i++) {
     const int row = row0 + wave * RPW + i;
     rows[i] = row;
+    // the row's loads four entries a plane at a time, all in flight
+    // together, from clamped indices (a load under a condition waits for its
+    // own data); entries outside A are zero
+    static_assert(EPL % 4 == 0, "entries per lane");
 #pragma unroll
-    for (int e = 0; e < EPL; e++) {
-      const int j = lane + 64 * e;
-      const bool in = row < n && j < n;
-      const int64_t o = (int64_t)row * n + j;
-      c0[i][e] = in ? (double)centred_i32(C0[o], p) : 0.0;
-      c1[i][e] = in ? (double)centred_i32(C1[o], p) : 0.0;
-      c2[i][e] = in ? (nar_t)centred_i32(C2[o], p) : (nar_t)0;
-      av[i][e] = in ? (nar_t)Ai[o] : (nar_t)0;
+    for (int e0 = 0; e0 < EPL; e0 += 4) {
+      uint32_t l0[4], l1[4], l2[4];
+      int32_t la[4];
+#pragma unroll
+      for (int u = 0; u < 4; u++) {
+        const int64_t o = (int64_t)min(row, n - 1) * n + min(lane + 64 * (e0 + u), n - 1);
+        l0[u] = C0[o];
+        l1[u] = C1[o];
+        l2[u] = C2[o];
+        la[u] = Ai[o];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; u++) {
+        const int e = e0 + u;
+        const bool in = row < n && lane + 64 * e < n;
+        c0[i][e] = in ? (double)centred_i32(l0[u], p) : 0.0;
+        c1[i][e] = in ? (double)centred_i32(l1[u], p) : 0.0;
+        c2[i][e] = in ? (nar_t)centred_i32(l2[u], p) : (nar_t)0;
+        av[i][e] = in ? (nar_t)la[u] : (nar_t)0;
+      }
     }
 #pragma unroll
     for (int h = 0; h < NRHS; h++)

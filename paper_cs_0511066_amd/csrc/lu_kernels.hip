@@ -170,110 +170,11 @@ __global__ __launch_bounds__(1024) void k_tri_inv(const int32_t* __restrict__ W,
 // result element r of lane l is D[l/16 + 4r][l%16].
 constexpr int GB_M = 64, GB_N = 64, GB_K = 32;
 
-// C[z] = (C[z] - A[z] * B[z]) mod p_z over an M x N region (all int32
-// centred residues, row-major with leading dimensions).  `kc4` = number of
-// MFMA k-steps (4 products each) after which the accumulator is reduced.
-__global__ __launch_bounds__(256) void k_gemm_f64(int32_t* __restrict__ W, int64_t slab,
-                                                  int64_t offC, int64_t offA, int64_t offB,
-                                                  int64_t ldw, int M, int N, int K,
-                                                  const Modulus* __restrict__ mods, int kc4) {
-  const int z = blockIdx.z;
-  const int t = threadIdx.x;
-  const int lane = t & 63, wave = t >> 6;
-  const int wr = wave >> 1, wc = wave & 1;
-  const double p = mods[z].p, pinv = mods[z].pinv;
-  int32_t* Wz = W + (int64_t)z * slab;
-  const int32_t* Ag = Wz + offA;
-  const int32_t* Bg = Wz + offB;
-  int32_t* Cg = Wz + offC;
-  const int row0 = blockIdx.y * GB_M, col0 = blockIdx.x * GB_N;
-
-  __shared__ double sA[GB_K][GB_M + 2];
-  __shared__ double sB[GB_K][GB_N + 2];
-
-  v4d acc[2][2];
-#pragma unroll
-  for (int i = 0; i < 2; i++)
-#pragma unroll
-    for (int j = 0; j < 2; j++) acc[i][j] = (v4d){0.0, 0.0, 0.0, 0.0};
-
-  int steps = 0;
-  for (int k0 = 0; k0 < K; k0 += GB_K) {
-    // A tile 64 rows x 32 k and B tile 32 k x 64 cols (a trailing update of
-    // a 32-wide panel in one chunk): value u of thread t is element u * 256 + t
-    // of the tile, row-major, so consecutive threads read consecutive words
-    {
-      int32_t va[GB_M * GB_K / 256], vb[GB_K * GB_N / 256];
-#pragma unroll
-      for (int u = 0; u < GB_M * GB_K / 256; u++) {
-        const int f = u * 256 + t, r = f / GB_K, k = f % GB_K;
-        const int gr = row0 + r, gk = k0 + k;
-        va[u] = (gr < M && gk < K) ? Ag[(int64_t)gr * ldw + gk] : 0;
-      }
-#pragma unroll
-      for (int u = 0; u < GB_K * GB_N / 256; u++) {
-        const int f = u * 256 + t, k = f / GB_N, c = f % GB_N;
-        const int gk = k0 + k, gc = col0 + c;
-        vb[u] = (gk < K && gc < N) ? Bg[(int64_t)gk * ldw + gc] : 0;
-      }
-#pragma unroll
-      for (int u = 0; u < GB_M * GB_K / 256; u++) {
-        const int f = u * 256 + t;
-        sA[f % GB_K][f / GB_K] = (double)va[u];
-      }
-#pragma unroll
-      for (int u = 0; u < GB_K * GB_N / 256; u++) {
-        const int f = u * 256 + t;
-        sB[f / GB_N][f % GB_N] = (double)vb[u];
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int ks = 0; ks < GB_K; ks += 4) {
-      const int kr = ks + (lane >> 4);
-      double af[2], bf[2];
-#pragma unroll
-      for (int i = 0; i < 2; i++) af[i] = sA[kr][wr * 32 + i * 16 + (lane & 15)];
-#pragma unroll
-      for (int j = 0; j < 2; j++) bf[j] = sB[kr][wc * 32 + j * 16 + (lane & 15)];
-#pragma unroll
-      for (int i = 0; i < 2; i++)
-#pragma unroll
-        for (int j = 0; j < 2; j++)
-          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
-      if (++steps == kc4) {
-        steps = 0;
-#pragma unroll
-        for (int i = 0; i < 2; i++)
-#pragma unroll
-          for (int j = 0; j < 2; j++)
-#pragma unroll
-            for (int r = 0; r < 4; r++) acc[i][j][r] = mod_c(acc[i][j][r], p, pinv);
-      }
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int i = 0; i < 2; i++)
-#pragma unroll
-    for (int j = 0; j < 2; j++)
-#pragma unroll
-      for (int r = 0; r < 4; r++) {
-        const int gr = row0 + wr * 32 + i * 16 + (lane >> 4) + 4 * r;
-        const int gc = col0 + wc * 32 + j * 16 + (lane & 15);
-        if (gr < M && gc < N) {
-          int32_t* cp = Cg + (int64_t)gr * ldw + gc;
-          const double s = mod_c(acc[i][j][r], p, pinv);
-          *cp = (int32_t)mod_c((double)*cp - s, p, pinv);
-        }
-      }
-}
-
 // ------------------------------------------------------------------ general modular product
 // C <op> A B (mod p) on int32 centred residues of one slab per item, FP64
 // MFMA on 64x64 tiles, K in chunks of 32 with the next chunk's global loads
 // issued before the current chunk's MFMAs (latency hidden for long K).
-// Sums are reduced every kc4 MFMA k-steps (exact chunking as k_gemm_f64).
+// Sums are reduced every kc4 MFMA k-steps (sums of |products| stay <= 2^53).
 // op: 0 C -= AB, 1 C += AB, 2 C = AB, 3 C = -AB.  upper_a: A is upper
 // triangular (zero below the diagonal), so a row tile starts K at its row.
 // Items: z = blockIdx.z at W + z * slab with modulus mods[z].
@@ -302,19 +203,20 @@ __global__ __launch_bounds__(64 * WR * WC) void k_gemm_mod(int32_t* __restrict__
   __shared__ double sA[GM_K][TM + 2];
   __shared__ double sB[GM_K][TN + 2];
   int32_t areg[NL], breg[NR];
-  // value u of thread t: element u * T + t of the tile, row-major
+  // value u of thread t: element u * T + t of the tile, row-major.  The
+  // loads are unconditional from indices clamped into range (M, N, K >= 1;
+  // a load under a condition would wait for its data at once) and the
+  // padding is applied when the values are stored to LDS.
   auto gload = [&](int k0) {
 #pragma unroll
     for (int u = 0; u < NL; u++) {
       const int f = u * T + t, r = f / GM_K, k = f % GM_K;
-      const int gr = row0 + r, gk = k0 + k;
-      areg[u] = (gr < M && gk < K) ? Ag[(int64_t)gr * ldw + gk] : 0;
+      areg[u] = Ag[(int64_t)min(row0 + r, M - 1) * ldw + min(k0 + k, K - 1)];
     }
 #pragma unroll
     for (int u = 0; u < NR; u++) {
       const int f = u * T + t, k = f / TN, c = f % TN;
-      const int gk = k0 + k, gc = col0 + c;
-      breg[u] = (gk < K && gc < N) ? Bg[(int64_t)gk * ldw + gc] : 0;
+      breg[u] = Bg[(int64_t)min(k0 + k, K - 1) * ldw + min(col0 + c, N - 1)];
     }
   };
   v4d acc[2][2];
@@ -328,13 +230,13 @@ __global__ __launch_bounds__(64 * WR * WC) void k_gemm_mod(int32_t* __restrict__
   for (int k0 = kbeg; k0 < K; k0 += GM_K) {
 #pragma unroll
     for (int u = 0; u < NL; u++) {
-      const int f = u * T + t;
-      sA[f % GM_K][f / GM_K] = (double)areg[u];
+      const int f = u * T + t, r = f / GM_K, k = f % GM_K;
+      sA[k][r] = (row0 + r < M && k0 + k < K) ? (double)areg[u] : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < NR; u++) {
-      const int f = u * T + t;
-      sB[f / TN][f % TN] = (double)breg[u];
+      const int f = u * T + t, k = f / TN, c = f % TN;
+      sB[k][c] = (k0 + k < K && col0 + c < N) ? (double)breg[u] : 0.0;
     }
     __syncthreads();
     if (k0 + GM_K < K) gload(k0 + GM_K);
@@ -363,6 +265,18 @@ __global__ __launch_bounds__(64 * WR * WC) void k_gemm_mod(int32_t* __restrict__
     }
     __syncthreads();
   }
+  // the old values of C, all loads at once (clamped; unused for op 2, 3)
+  int32_t cold[2][2][4];
+#pragma unroll
+  for (int i = 0; i < 2; i++)
+#pragma unroll
+    for (int j = 0; j < 2; j++)
+#pragma unroll
+      for (int r = 0; r < 4; r++) {
+        const int gr = row0 + wr * 32 + i * 16 + (lane >> 4) + 4 * r;
+        const int gc = col0 + wc * 32 + j * 16 + (lane & 15);
+        cold[i][j][r] = Cg[(int64_t)min(gr, M - 1) * ldw + min(gc, N - 1)];
+      }
 #pragma unroll
   for (int i = 0; i < 2; i++)
 #pragma unroll
@@ -372,14 +286,10 @@ __global__ __launch_bounds__(64 * WR * WC) void k_gemm_mod(int32_t* __restrict__
         const int gr = row0 + wr * 32 + i * 16 + (lane >> 4) + 4 * r;
         const int gc = col0 + wc * 32 + j * 16 + (lane & 15);
         if (gr < M && gc < N) {
-          int32_t* cp = Cg + (int64_t)gr * ldw + gc;
           const double s = mod_c(acc[i][j][r], p, pinv);
-          double v;
-          if (op == 0) v = (double)*cp - s;
-          else if (op == 1) v = (double)*cp + s;
-          else if (op == 2) v = s;
-          else v = -s;
-          *cp = (int32_t)mod_c(v, p, pinv);
+          const double c0 = (double)cold[i][j][r];
+          const double v = op == 0 ? c0 - s : op == 1 ? c0 + s : op == 2 ? s : -s;
+          Cg[(int64_t)gr * ldw + gc] = (int32_t)mod_c(v, p, pinv);
         }
       }
 }
@@ -447,29 +357,29 @@ __global__ __launch_bounds__(256) void k_lu_update(int32_t* __restrict__ W, int6
   __shared__ double sT[32][33];                         // L11^{-1}
   __shared__ double sU[32][33];                         // U11^{-1} (no-pivot mode)
   __shared__ int s_last;
-  // all loads at once: L11^{-1}, A12, L21 and the old values of the tile
+  // All loads at once: L11^{-1}, U11^{-1}, A12, L21 and the old values of
+  // the tile.  Every load is unconditional, from an index clamped into the
+  // valid range (M, N, pb >= 1), and the padding is selected afterwards: a
+  // load under a condition becomes a branch that waits for its own data.
   const int32_t* Tz = Linv + (int64_t)z * ldt * ldt;
-  for (int e = t; e < 32 * 32; e += 256) {
-    const int r = e >> 5, c = e & 31;
-    sT[r][c] = (r < pb && c < pb) ? (double)Tz[r * ldt + c] : 0.0;
-  }
-  if (Uinv != nullptr) {
-    const int32_t* Uz = Uinv + (int64_t)z * ldt * ldt;
-    for (int e = t; e < 32 * 32; e += 256) {
-      const int r = e >> 5, c = e & 31;
-      sU[r][c] = (r < pb && c < pb) ? (double)Uz[r * ldt + c] : 0.0;
-    }
+  const int32_t* Uz = Uinv != nullptr ? Uinv + (int64_t)z * ldt * ldt : Tz;
+  int32_t vt[4], vu[4];
+#pragma unroll
+  for (int u = 0; u < 4; u++) {
+    const int e = u * 256 + t, r = min(e >> 5, pb - 1), c = min(e & 31, pb - 1);
+    vt[u] = Tz[r * ldt + c];
+    vu[u] = Uz[r * ldt + c];
   }
   int32_t va[GB_M * GB_K / 256], vb[GB_K * GB_N / 256], vc[2][2][4];
 #pragma unroll
   for (int u = 0; u < GB_M * GB_K / 256; u++) {
     const int f = u * 256 + t, r = f / GB_K, k = f % GB_K;
-    va[u] = (row0 + r < M && k < pb) ? Wz[(int64_t)(r0 + row0 + r) * ldw + j0 + k] : 0;
+    va[u] = Wz[(int64_t)(r0 + min(row0 + r, M - 1)) * ldw + j0 + min(k, pb - 1)];
   }
 #pragma unroll
   for (int u = 0; u < GB_K * GB_N / 256; u++) {
     const int f = u * 256 + t, k = f / GB_N, c = f % GB_N;
-    vb[u] = (k < pb && col0 + c < N) ? Wz[(int64_t)(j0 + k) * ldw + r0 + col0 + c] : 0;
+    vb[u] = Wz[(int64_t)(j0 + min(k, pb - 1)) * ldw + r0 + min(col0 + c, N - 1)];
   }
 #pragma unroll
   for (int i = 0; i < 2; i++)
@@ -479,17 +389,24 @@ __global__ __launch_bounds__(256) void k_lu_update(int32_t* __restrict__ W, int6
       for (int r = 0; r < 4; r++) {
         const int gr = row0 + wr * 32 + i * 16 + (lane >> 4) + 4 * r;
         const int gc = col0 + wc * 32 + j * 16 + (lane & 15);
-        vc[i][j][r] = (gr < M && gc < N) ? Wz[(int64_t)(r0 + gr) * ldw + r0 + gc] : 0;
+        vc[i][j][r] = Wz[(int64_t)(r0 + min(gr, M - 1)) * ldw + r0 + min(gc, N - 1)];
       }
 #pragma unroll
+  for (int u = 0; u < 4; u++) {
+    const int e = u * 256 + t, r = e >> 5, c = e & 31;
+    const bool in = r < pb && c < pb;
+    sT[r][c] = in ? (double)vt[u] : 0.0;
+    sU[r][c] = in ? (double)vu[u] : 0.0;
+  }
+#pragma unroll
   for (int u = 0; u < GB_M * GB_K / 256; u++) {
-    const int f = u * 256 + t;
-    sA[f % GB_K][f / GB_K] = (double)va[u];
+    const int f = u * 256 + t, r = f / GB_K, k = f % GB_K;
+    sA[k][r] = (row0 + r < M && k < pb) ? (double)va[u] : 0.0;
   }
 #pragma unroll
   for (int u = 0; u < GB_K * GB_N / 256; u++) {
-    const int f = u * 256 + t;
-    sB[f / GB_N][f % GB_N] = (double)vb[u];
+    const int f = u * 256 + t, k = f / GB_N, c = f % GB_N;
+    sB[k][c] = (k < pb && col0 + c < N) ? (double)vb[u] : 0.0;
   }
   __syncthreads();
   if (Uinv != nullptr) {
@@ -1036,10 +953,7 @@ hipError_t launch_gemm_f64(int32_t* W, int64_t slab, int64_t offC, int64_t offA,
                            int64_t ldw, int M, int N, int K, const Modulus* mods, int kc4,
                            int nitems, hipStream_t st) {
   if (M <= 0 || N <= 0 || K <= 0) return hipSuccess;
-  dim3 grid((N + GB_N - 1) / GB_N, (M + GB_M - 1) / GB_M, nitems);
-  k_gemm_f64<<<grid, 256, 0, st>>>(W, slab, offC, offA, offB, ldw, M, N, K, mods, kc4);
-  LAUNCH_CHECK();
-  return hipSuccess;
+  return launch_gemm_mod(W, slab, offC, offA, offB, ldw, M, N, K, mods, kc4, 0, false, nitems, st);
 }
 
 hipError_t launch_lu_update(int32_t* W, int64_t slab, int64_t ldw, int j0, int pb, int M, int N,

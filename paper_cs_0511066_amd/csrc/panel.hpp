@@ -110,18 +110,24 @@ __device__ __forceinline__ void panel_body(int32_t* __restrict__ Wr, int64_t ldw
   for (int q = 0; q < RPT; q++) {
     const int row = t + q * T;
     const int32_t* src = Wz + (int64_t)(row < m ? row : 0) * ldw;
+    // (loads unconditional from the clamped row, the padding selected after:
+    // a load under a condition would wait for its own data)
+    const bool in = row < m;
     if (pb == PB) {
 #pragma unroll
       for (int k4 = 0; k4 < PB / 4; k4++) {
-        const v4i_p v = row < m ? ((const v4i_p*)src)[k4] : v4i_p{0, 0, 0, 0};
-        a[q][4 * k4] = (double)v.x;
-        a[q][4 * k4 + 1] = (double)v.y;
-        a[q][4 * k4 + 2] = (double)v.z;
-        a[q][4 * k4 + 3] = (double)v.w;
+        const v4i_p v = ((const v4i_p*)src)[k4];
+        a[q][4 * k4] = in ? (double)v.x : 0.0;
+        a[q][4 * k4 + 1] = in ? (double)v.y : 0.0;
+        a[q][4 * k4 + 2] = in ? (double)v.z : 0.0;
+        a[q][4 * k4 + 3] = in ? (double)v.w : 0.0;
       }
     } else {
 #pragma unroll
-      for (int k = 0; k < PB; k++) a[q][k] = (row < m && k < pb) ? (double)src[k] : 0.0;
+      for (int k = 0; k < PB; k++) {
+        const int32_t v = src[min(k, pb - 1)];
+        a[q][k] = (in && k < pb) ? (double)v : 0.0;
+      }
     }
   }
   __syncthreads();
@@ -493,6 +499,19 @@ __device__ __forceinline__ double shfl_down_dd(double x, int d) {
   return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
 }
 
+// mod_loose on R independent values, one phase at a time (see modp.hpp).
+template <int R>
+__device__ __forceinline__ void mod_loose_rows(double (&x)[R], double p, double pinv) {
+  constexpr double RND = 6755399441055744.0;
+  double q[R];
+#pragma unroll
+  for (int i = 0; i < R; i++) q[i] = fma(x[i], pinv, RND);
+#pragma unroll
+  for (int i = 0; i < R; i++) q[i] = q[i] - RND;
+#pragma unroll
+  for (int i = 0; i < R; i++) x[i] = fma(-q[i], p, x[i]);
+}
+
 template <int NW>
 __device__ __forceinline__ void diag_block_body(int32_t* __restrict__ Wb, int64_t ldw, int pb,
                                                 double p, double pinv, int32_t* __restrict__ piv_z,
@@ -506,10 +525,17 @@ __device__ __forceinline__ void diag_block_body(int32_t* __restrict__ Wb, int64_
   const uint32_t e_inv = (uint32_t)__builtin_amdgcn_readfirstlane((int)((uint32_t)p - 2u));
   double F[RW];
   if (w < NW) {
+    // every load is issued before any is used (clamped indices stay inside
+    // the pb x pb block; the padding is selected afterwards), so the wave
+    // waits for memory once instead of once a row
+    int32_t v[RW];
+    const int cc = min(c & 31, pb - 1);
+#pragma unroll
+    for (int q = 0; q < RW; q++) v[q] = Wb[(int64_t)min(w + NW * q, pb - 1) * ldw + cc];
 #pragma unroll
     for (int q = 0; q < RW; q++) {
       const int i = w + NW * q;
-      if (c < 32) F[q] = (i < pb && c < pb) ? (double)Wb[(int64_t)i * ldw + c] : (i == c ? 1.0 : 0.0);
+      if (c < 32) F[q] = (i < pb && c < pb) ? (double)v[q] : (i == c ? 1.0 : 0.0);
       else F[q] = (i == c - 32) ? 1.0 : 0.0;
     }
   }
@@ -531,12 +557,17 @@ __device__ __forceinline__ void diag_block_body(int32_t* __restrict__ Wb, int64_
     const double bk = braw == 0.0 ? 1.0 : braw;      // (the result is discarded then)
     if (t == 0) sV[k] = bk;
     if (w < NW) {
+      // the rows of a wave are independent: each phase runs over all of them
+      // before the next, so that a wave (alone on its SIMD) overlaps their
+      // dependent FP64 chains instead of waiting on each
+      double x[RW];
 #pragma unroll
-      for (int q = 0; q < RW; q++) {
-        const int i = w + NW * q;
-        const double r = readlane_d(F[q], k);
-        if (i > k) F[q] = mod_loose(fma(bk, F[q], -r * fk), p, pinv);
-      }
+      for (int q = 0; q < RW; q++) x[q] = -readlane_d(F[q], k) * fk;
+#pragma unroll
+      for (int q = 0; q < RW; q++) x[q] = fma(bk, F[q], x[q]);
+      mod_loose_rows<RW>(x, p, pinv);
+#pragma unroll
+      for (int q = 0; q < RW; q++) F[q] = (w + NW * q > k) ? x[q] : F[q];
     }
   }
   __syncthreads();
@@ -593,12 +624,12 @@ __device__ __forceinline__ void diag_block_body(int32_t* __restrict__ Wb, int64_
     __syncthreads();
     const double fk = row[c];
     if (w < NW) {
+      double x[RW];
 #pragma unroll
-      for (int q = 0; q < RW; q++) {
-        const int i = w + NW * q;
-        const double r = readlane_d(F[q], k);
-        if (i < k) F[q] = mod_loose(fma(-r, fk, F[q]), p, pinv);
-      }
+      for (int q = 0; q < RW; q++) x[q] = fma(-readlane_d(F[q], k), fk, F[q]);
+      mod_loose_rows<RW>(x, p, pinv);
+#pragma unroll
+      for (int q = 0; q < RW; q++) F[q] = (w + NW * q < k) ? x[q] : F[q];
     }
   }
   if (w < NW && c >= 32) {

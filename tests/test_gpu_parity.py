@@ -110,6 +110,21 @@ def test_det_introspective_zero_pivots_mid_group(ctx):
     assert ctx.det_introspective(A) == oracle.det_bareiss(A)
 
 
+@pytest.mark.gpu
+def test_det_introspective_inverse_block_search_fails(ctx):
+    """The Dixon inverse's block pivot search meets a block column with no
+    non-zero entry (column 0 vanishes in rows 0..31): the first solving, run
+    before that flag is read, is discarded and the solve starts over with the
+    full search; the determinant is exact and the solve still yields s_n."""
+    n = 100
+    A = synth.dense_uniform(n, -100, 100, 22)
+    A[:32, 0] = 0
+    A[40, 0] = 5
+    d, rep = ctx.det_introspective(A, report=True)
+    assert d == oracle.det_bareiss(A)
+    assert rep["solvings"] == 1 and rep["sn_bits"] > 64
+
+
 def test_det_mod_primes_extreme_entries(ctx):
     n = 40
     A = synth.dense_uniform(n, -(2 ** 31) + 1, 2 ** 31 - 1, 6)
