@@ -93,18 +93,21 @@ det_status gemm_update(det_ctx* c, LuWs& w, const LuJob& J, int64_t offC, int64_
   if (M <= 0 || N <= 0 || K <= 0) return DET_OK;
   if (use_i8) {
     const int Kp = (int)((K + 63) / 64 * 64);
-    const int64_t pslabA = 3LL * M * Kp, pslabB = 3LL * N * Kp;
+    const int64_t Mp = (M + 63) / 64 * 64, Np = (N + 63) / 64 * 64;
+    const int64_t pslabA = 3 * Mp * Kp, pslabB = 3 * Np * Kp;
     TRY(ensure(c, w.limbA, (size_t)nit * pslabA, w.st));
     TRY(ensure(c, w.limbB, (size_t)nit * pslabB, w.st));
     // the timed interval covers the limb splits as well as the products
-    ProfScope ps(c, DET_KERNEL_GEMM_I8, (3.0 * Kp * ((double)M + N) + 8.0 * M * N) * nit,
+    ProfScope ps(c, DET_KERNEL_GEMM_I8,
+                 (7.0 * (double)K * ((double)M + N) + 3.0 * Kp * (double)(Mp + Np) + 8.0 * M * N) * nit,
                  18.0 * M * N * K * nit, w.st);
-    HIPCHK(detk::launch_split(W, J.slab, offA, J.ldw, M, K, Kp, 0, (int8_t*)w.limbA.p, pslabA, nit,
-                              w.st));
-    HIPCHK(detk::launch_split(W, J.slab, offB, J.ldw, N, K, Kp, 1, (int8_t*)w.limbB.p, pslabB, nit,
-                              w.st));
+    HIPCHK(detk::launch_split(W, J.slab, offA, J.ldw, M, K, Kp, Mp, 0, (int8_t*)w.limbA.p, pslabA,
+                              nit, w.st));
+    HIPCHK(detk::launch_split(W, J.slab, offB, J.ldw, N, K, Kp, Np, 1, (int8_t*)w.limbB.p, pslabB,
+                              nit, w.st));
     HIPCHK(detk::launch_gemm_i8(W, J.slab, offC, J.ldw, M, N, (const int8_t*)w.limbA.p,
-                                (const int8_t*)w.limbB.p, pslabA, pslabB, Kp, mods, nit, w.st));
+                                (const int8_t*)w.limbB.p, pslabA, pslabB, Mp, Np, Kp, mods, nit,
+                                w.st));
   } else {
     ProfScope ps(c, DET_KERNEL_GEMM_F64,
                  4.0 * ((double)M * K + (double)K * N + 2.0 * M * N) * nit, 2.0 * M * N * K * nit,

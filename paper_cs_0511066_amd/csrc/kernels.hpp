@@ -51,12 +51,16 @@ hipError_t launch_trsm_apply(int32_t* W, int64_t slab, int64_t ldw, int r0, int 
 hipError_t launch_gemm_f64(int32_t* W, int64_t slab, int64_t offC, int64_t offA, int64_t offB,
                            int64_t ldw, int M, int N, int K, const Modulus* mods, int kc4,
                            int nitems, hipStream_t st);
+// Limb planes (3 x Rp x Kp int8 per item, zero-padded) of an M x K block or
+// of a K x N block transposed; p < 2^23.
 hipError_t launch_split(const int32_t* W, int64_t slab, int64_t off, int64_t ldw, int rows, int K,
-                        int Kp, int transpose, int8_t* P, int64_t pslab, int nitems,
+                        int Kp, int64_t Rp, int transpose, int8_t* P, int64_t pslab, int nitems,
                         hipStream_t st);
+// C -= A B mod p from limb planes (K padded to Kp <= 43690).
 hipError_t launch_gemm_i8(int32_t* W, int64_t slab, int64_t offC, int64_t ldw, int M, int N,
                           const int8_t* PA, const int8_t* PB, int64_t pslabA, int64_t pslabB,
-                          int Kp, const Modulus* mods, int nitems, hipStream_t st);
+                          int64_t MpA, int64_t NpB, int Kp, const Modulus* mods, int nitems,
+                          hipStream_t st);
 hipError_t launch_det_finalize(const int32_t* W, int64_t ldw, int64_t slab, int n,
                                const int32_t* piv, int64_t piv_stride, const int32_t* flags,
                                const Modulus* mods, uint32_t* out, int nitems, hipStream_t st);

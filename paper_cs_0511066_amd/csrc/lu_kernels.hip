@@ -631,45 +631,70 @@ __global__ __launch_bounds__(256) void k_trsm_apply(int32_t* __restrict__ W, int
 }
 
 // ------------------------------------------------------------------ int8 limb path
-// A centred residue |r| < 2^22 (p < 2^23) splits into balanced signed limbs
-// r = l0 + 2^8 l1 + 2^16 l2 with l0, l1 in [-128, 127] and |l2| <= 64.
-__device__ __forceinline__ void split3(int32_t r, int8_t& l0, int8_t& l1, int8_t& l2) {
-  const int32_t a0 = ((r + 128) & 255) - 128;
-  const int32_t r1 = (r - a0) >> 8;
-  const int32_t a1 = ((r1 + 128) & 255) - 128;
-  const int32_t a2 = (r1 - a1) >> 8;
-  l0 = (int8_t)a0;
-  l1 = (int8_t)a1;
-  l2 = (int8_t)a2;
+// A centred residue |r| < 2^22 (p < 2^23) in balanced signed limbs,
+// r = l0 + 2^8 l1 + 2^16 l2 with every l in [-128, 127]: with
+// u = r + 0x808080 (0 < u < 2^24) and b_j the bytes of u, r = sum (b_j - 128)
+// 2^(8j), and b_j - 128 is the byte b_j ^ 0x80 read as a signed byte.  So the
+// three limbs are bytes 0..2 of (r + 0x808080) ^ 0x808080.
+__device__ __forceinline__ uint32_t limb_word(int32_t r) {
+  return (uint32_t)(r + 0x808080) ^ 0x808080u;
 }
 
-// Limb planes of an M x K operand (A: row-major, k contiguous) or of a K x N
-// operand stored transposed (B: column j's K values contiguous), padded to
-// Kp (a multiple of 64) with zeros.  Out: P[z][3][rows][Kp].
-__global__ void k_split(const int32_t* __restrict__ W, int64_t slab, int64_t off, int64_t ldw,
-                        int rows, int K, int Kp, int transpose, int8_t* __restrict__ P,
-                        int64_t pslab) {
-  const int z = blockIdx.z;
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  const int r = blockIdx.y;
-  if (k >= Kp || r >= rows) return;
-  int32_t v = 0;
-  if (k < K) {
-    const int32_t* Wz = W + (int64_t)z * slab + off;
-    v = transpose ? Wz[(int64_t)k * ldw + r] : Wz[(int64_t)r * ldw + k];
+// Limb planes of an M x K block (A: row-major, k contiguous) or of a K x N
+// block stored transposed (B: column j's K values contiguous), both padded
+// with zeros to Rp x Kp (multiples of 64).  Out: P[z][3][Rp][Kp].  One
+// 64 x 64 tile a workgroup: the int32 tile is read row by row into LDS, and
+// each thread packs byte j of four consecutive k values into one word of
+// plane j (v_perm_b32), so reads and writes are both contiguous.
+__global__ __launch_bounds__(256) void k_split(const int32_t* __restrict__ W, int64_t slab,
+                                               int64_t off, int64_t ldw, int rows, int K, int Kp,
+                                               int64_t Rp, int transpose, int8_t* __restrict__ P,
+                                               int64_t pslab) {
+  __shared__ uint32_t sT[64][65];
+  const int z = blockIdx.z, t = threadIdx.x;
+  const int ty = blockIdx.y * 64, tx = blockIdx.x * 64;   // tile: output rows ty.., k tx..
+  const int32_t* Wz = W + (int64_t)z * slab + off;
+  // source tile: W rows (ty.. for A, tx.. for B) x 64 columns; 16 words a thread
+  const int sr0 = transpose ? tx : ty, sc0 = transpose ? ty : tx;
+  const int srows = transpose ? K : rows, scols = transpose ? rows : K;
+  int32_t x[16];
+#pragma unroll
+  for (int u = 0; u < 16; u++) {                // every load in flight before any use
+    const int e = u * 256 + t, r = e >> 6, c = e & 63;
+    x[u] = Wz[(int64_t)min(sr0 + r, srows - 1) * ldw + min(sc0 + c, scols - 1)];
   }
-  int8_t l0, l1, l2;
-  split3(v, l0, l1, l2);
+#pragma unroll
+  for (int u = 0; u < 16; u++) {
+    const int e = u * 256 + t, r = e >> 6, c = e & 63;
+    sT[r][c] = limb_word((sr0 + r < srows && sc0 + c < scols) ? x[u] : 0);
+  }
+  __syncthreads();
+  // output: 64 rows x 16 words of four k values, per plane; 4 words a thread
   int8_t* Pz = P + (int64_t)z * pslab;
-  const int64_t plane = (int64_t)rows * Kp;
-  Pz[(int64_t)r * Kp + k] = l0;
-  Pz[plane + (int64_t)r * Kp + k] = l1;
-  Pz[2 * plane + (int64_t)r * Kp + k] = l2;
+  const int64_t plane = Rp * (int64_t)Kp;
+#pragma unroll
+  for (int u = 0; u < 4; u++) {
+    const int e = u * 256 + t, orow = e >> 4, kq = (e & 15) * 4;
+    uint32_t w[4];
+#pragma unroll
+    for (int q = 0; q < 4; q++) w[q] = transpose ? sT[kq + q][orow] : sT[orow][kq + q];
+#pragma unroll
+    for (int pl = 0; pl < 3; pl++) {
+      // bytes pl of w0, w1 (and of w2, w3), then the two halves together
+      const uint32_t sel = (uint32_t)pl | (uint32_t)(pl + 4) << 8 | 0x0c0c0000u;
+      const uint32_t lo = __builtin_amdgcn_perm(w[1], w[0], sel);
+      const uint32_t hi = __builtin_amdgcn_perm(w[3], w[2], sel);
+      const uint32_t word = __builtin_amdgcn_perm(hi, lo, 0x05040100u);
+      *(uint32_t*)(Pz + pl * plane + (int64_t)(ty + orow) * Kp + tx + kq) = word;
+    }
+  }
 }
 
-// C[z] = (C[z] - A[z] B[z]) mod p_z with A, B given as limb planes.
+// C[z] = (C[z] - A[z] B[z]) mod p_z with A, B given as limb planes (Rp x Kp,
+// zero-padded, so every load is in range and unconditional).
 // C_s = sum_{a+b=s} A_a B_b on v_mfma_i32_16x16x64_i8 (exact while
 // 3 K 2^14 < 2^31), then C -= sum_s (C_s mod p)(2^(8s) mod p) mod p in FP64.
+// The next K chunk's loads are in flight during this chunk's products.
 // Lane l supplies A[l%16][16(l/16) .. +16) and B^T[l%16][same k]; result
 // element r of lane l is D[4(l/16) + r][l%16].
 constexpr int GI_K = 64;
@@ -679,7 +704,7 @@ __global__ __launch_bounds__(256) void k_gemm_i8(int32_t* __restrict__ W, int64_
                                                  int64_t offC, int64_t ldw, int M, int N,
                                                  const int8_t* __restrict__ PA,
                                                  const int8_t* __restrict__ PB, int64_t pslabA,
-                                                 int64_t pslabB, int Kp,
+                                                 int64_t pslabB, int64_t MpA, int64_t NpB, int Kp,
                                                  const Modulus* __restrict__ mods) {
   const int z = blockIdx.z;
   const int t = threadIdx.x;
@@ -689,11 +714,22 @@ __global__ __launch_bounds__(256) void k_gemm_i8(int32_t* __restrict__ W, int64_
   const int row0 = blockIdx.y * GB_M, col0 = blockIdx.x * GB_N;
   const int8_t* Az = PA + (int64_t)z * pslabA;
   const int8_t* Bz = PB + (int64_t)z * pslabB;
-  const int64_t planeA = (int64_t)M * Kp, planeB = (int64_t)N * Kp;
+  const int64_t planeA = MpA * Kp, planeB = NpB * Kp;
 
   __shared__ __attribute__((aligned(16))) int8_t sA[3][GB_M][GI_LD];
   __shared__ __attribute__((aligned(16))) int8_t sB[3][GB_N][GI_LD];
 
+  // 3 planes x 64 rows x 64 bytes per operand = 768 chunks of 16 B; 3 a thread
+  v4i ga[3], gb[3];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < 3; u++) {
+      const int e = t + u * 256;
+      const int pl = e >> 8, rem = e & 255, r = rem >> 2, q = (rem & 3) * 16;
+      ga[u] = *(const v4i*)(Az + pl * planeA + (int64_t)(row0 + r) * Kp + k0 + q);
+      gb[u] = *(const v4i*)(Bz + pl * planeB + (int64_t)(col0 + r) * Kp + k0 + q);
+    }
+  };
   v4i acc[5][2][2];
 #pragma unroll
   for (int s = 0; s < 5; s++)
@@ -702,19 +738,17 @@ __global__ __launch_bounds__(256) void k_gemm_i8(int32_t* __restrict__ W, int64_
 #pragma unroll
       for (int j = 0; j < 2; j++) acc[s][i][j] = (v4i){0, 0, 0, 0};
 
+  gload(0);
   for (int k0 = 0; k0 < Kp; k0 += GI_K) {
-    // 3 planes x 64 rows x 64 bytes per operand = 768 chunks of 16 B; 3 per thread
 #pragma unroll
     for (int u = 0; u < 3; u++) {
       const int e = t + u * 256;
       const int pl = e >> 8, rem = e & 255, r = rem >> 2, q = (rem & 3) * 16;
-      v4i va = (v4i){0, 0, 0, 0}, vb = (v4i){0, 0, 0, 0};
-      if (row0 + r < M) va = *(const v4i*)(Az + pl * planeA + (int64_t)(row0 + r) * Kp + k0 + q);
-      if (col0 + r < N) vb = *(const v4i*)(Bz + pl * planeB + (int64_t)(col0 + r) * Kp + k0 + q);
-      *(v4i*)(&sA[pl][r][q]) = va;
-      *(v4i*)(&sB[pl][r][q]) = vb;
+      *(v4i*)(&sA[pl][r][q]) = ga[u];
+      *(v4i*)(&sB[pl][r][q]) = gb[u];
     }
     __syncthreads();
+    if (k0 + GI_K < Kp) gload(k0 + GI_K);
     v4i af[3][2], bf[3][2];
 #pragma unroll
     for (int pl = 0; pl < 3; pl++) {
@@ -744,6 +778,17 @@ __global__ __launch_bounds__(256) void k_gemm_i8(int32_t* __restrict__ W, int64_
 #pragma unroll
   for (int s = 1; s < 5; s++) wgt[s] = mod_c(wgt[s - 1] * 256.0, p, pinv);
   int32_t* Cg = W + (int64_t)z * slab + offC;
+  int32_t cold[2][2][4];
+#pragma unroll
+  for (int i = 0; i < 2; i++)
+#pragma unroll
+    for (int j = 0; j < 2; j++)
+#pragma unroll
+      for (int r = 0; r < 4; r++) {
+        const int gr = row0 + wr * 32 + i * 16 + 4 * (lane >> 4) + r;
+        const int gc = col0 + wc * 32 + j * 16 + (lane & 15);
+        cold[i][j][r] = Cg[(int64_t)min(gr, M - 1) * ldw + min(gc, N - 1)];
+      }
 #pragma unroll
   for (int i = 0; i < 2; i++)
 #pragma unroll
@@ -757,8 +802,7 @@ __global__ __launch_bounds__(256) void k_gemm_i8(int32_t* __restrict__ W, int64_
 #pragma unroll
           for (int s = 0; s < 5; s++) v += mod_c((double)acc[s][i][j][r], p, pinv) * wgt[s];
           v = mod_c(v, p, pinv);
-          int32_t* cp = Cg + (int64_t)gr * ldw + gc;
-          *cp = (int32_t)mod_c((double)*cp - v, p, pinv);
+          Cg[(int64_t)gr * ldw + gc] = (int32_t)mod_c((double)cold[i][j][r] - v, p, pinv);
         }
       }
 }
@@ -996,22 +1040,26 @@ hipError_t launch_place_diag(int32_t* W, int64_t ldw, int64_t offV, int n, const
 }
 
 hipError_t launch_split(const int32_t* W, int64_t slab, int64_t off, int64_t ldw, int rows, int K,
-                        int Kp, int transpose, int8_t* P, int64_t pslab, int nitems,
+                        int Kp, int64_t Rp, int transpose, int8_t* P, int64_t pslab, int nitems,
                         hipStream_t st) {
-  if (rows <= 0 || Kp <= 0) return hipSuccess;
-  dim3 grid((Kp + 255) / 256, rows, nitems);
-  k_split<<<grid, 256, 0, st>>>(W, slab, off, ldw, rows, K, Kp, transpose, P, pslab);
+  if (rows <= 0 || K <= 0 || nitems <= 0) return hipSuccess;
+  if (Kp % 64 || Rp % 64 || Kp < K || Rp < rows) return hipErrorInvalidValue;
+  dim3 grid(Kp / 64, (unsigned)(Rp / 64), nitems);
+  k_split<<<grid, 256, 0, st>>>(W, slab, off, ldw, rows, K, Kp, Rp, transpose, P, pslab);
   LAUNCH_CHECK();
   return hipSuccess;
 }
 
 hipError_t launch_gemm_i8(int32_t* W, int64_t slab, int64_t offC, int64_t ldw, int M, int N,
                           const int8_t* PA, const int8_t* PB, int64_t pslabA, int64_t pslabB,
-                          int Kp, const Modulus* mods, int nitems, hipStream_t st) {
-  if (M <= 0 || N <= 0 || Kp <= 0) return hipSuccess;
-  if (Kp % GI_K) return hipErrorInvalidValue;
+                          int64_t MpA, int64_t NpB, int Kp, const Modulus* mods, int nitems,
+                          hipStream_t st) {
+  if (M <= 0 || N <= 0 || Kp <= 0 || nitems <= 0) return hipSuccess;
+  if (Kp % GI_K || MpA % GB_M || NpB % GB_N || MpA < M || NpB < N || Kp > 43690)
+    return hipErrorInvalidValue;
   dim3 grid((N + GB_N - 1) / GB_N, (M + GB_M - 1) / GB_M, nitems);
-  k_gemm_i8<<<grid, 256, 0, st>>>(W, slab, offC, ldw, M, N, PA, PB, pslabA, pslabB, Kp, mods);
+  k_gemm_i8<<<grid, 256, 0, st>>>(W, slab, offC, ldw, M, N, PA, PB, pslabA, pslabB, MpA, NpB, Kp,
+                                  mods);
   LAUNCH_CHECK();
   return hipSuccess;
 }
