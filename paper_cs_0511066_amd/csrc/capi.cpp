@@ -381,17 +381,19 @@ det_status matrix_bounds(det_ctx* c, const int64_t* A, int64_t lda, bool on_devi
     *b = dethost::bounds_host(A, n, lda);
     return DET_OK;
   }
-  TRY(ensure(c, c->norms, (size_t)2 * n * sizeof(double)));
-  TRY(ensure(c, c->amax, (size_t)n * sizeof(double)));
-  HIPCHK(detk::launch_norms(dA, dlda, (int)n, (double*)c->norms.p, (double*)c->amax.p, c->st));
-  std::vector<double> h(2 * n), am(n);
-  HIPCHK(hipMemcpyAsync(h.data(), c->norms.p, 2 * n * sizeof(double), hipMemcpyDeviceToHost, c->st));
-  HIPCHK(hipMemcpyAsync(am.data(), c->amax.p, n * sizeof(double), hipMemcpyDeviceToHost, c->st));
+  // column sums, row sums and row maxima in one buffer, read back with one
+  // copy into pinned memory
+  TRY(ensure(c, c->norms, (size_t)3 * n * sizeof(double)));
+  TRY(ensure_pin(c, c->hnorms, (size_t)3 * n * sizeof(double), c->st));
+  double* dn = (double*)c->norms.p;
+  HIPCHK(detk::launch_norms(dA, dlda, (int)n, dn, dn + 2 * n, c->st));
+  const double* h = (const double*)c->hnorms.p;
+  HIPCHK(hipMemcpyAsync((void*)h, dn, 3 * n * sizeof(double), hipMemcpyDeviceToHost, c->st));
   HIPCHK(hipStreamSynchronize(c->st));
   double amax = 0;
-  for (double v : am) amax = std::max(amax, v);
+  for (int64_t i = 0; i < n; i++) amax = std::max(amax, h[2 * n + i]);
   if (amax >= 2147483648.0) return fail(c, DET_E_OVERFLOW, "matrix entry with |a_ij| >= 2^31");
-  std::vector<double> cols(h.begin(), h.begin() + n), rows(h.begin() + n, h.end());
+  std::vector<double> cols(h, h + n), rows(h + n, h + 2 * n);
   *b = dethost::bounds_from_sums(cols, rows, amax);
   return DET_OK;
 }
@@ -916,7 +918,7 @@ void det_ctx_destroy(det_ctx* c) {
   (void)hipSetDevice(c->device);
   if (c->st) (void)hipStreamSynchronize(c->st);
   if (c->own2) (void)hipStreamSynchronize(c->own2);
-  std::vector<DevBuf*> all = {&c->Adev, &c->norms, &c->amax, &c->Cu, &c->Ai, &c->r, &c->rp,
+  std::vector<DevBuf*> all = {&c->Adev, &c->norms, &c->Cu, &c->Ai, &c->r, &c->rp,
                               &c->x, &c->digits, &c->comb, &c->cvec, &c->sync, &c->C1, &c->E,
                               &c->rp1, &c->x1, &c->C2, &c->Ed, &c->rv, &c->xv, &c->q_items,
                               &c->q_next, &c->q_ws, &c->q_aux, &c->q_out, &c->q_mats};
@@ -927,8 +929,8 @@ void det_ctx_destroy(det_ctx* c) {
   for (DevBuf* b : all)
     if (b->p) (void)hipFree(b->p);
   if (c->hres) (void)hipHostFree(c->hres);
-  for (PinBuf* pb : {&c->hstage, &c->hsmall, &c->ws[0].hmods, &c->ws[1].hmods, &c->ws[0].hflags,
-                     &c->ws[1].hflags, &c->q_hitems, &c->q_hout})
+  for (PinBuf* pb : {&c->hstage, &c->hsmall, &c->hnorms, &c->ws[0].hmods, &c->ws[1].hmods,
+                     &c->ws[0].hflags, &c->ws[1].hflags, &c->q_hitems, &c->q_hout})
     if (pb->p) (void)hipHostFree(pb->p);
   for (auto& pr : c->prof_pending) {
     (void)hipEventDestroy(pr.first);

@@ -54,12 +54,13 @@ struct det_ctx {
   std::mutex mu;                 // the error text, the budget count, the kernel timing state
   std::string err;
   LuWs ws[2];
-  DevBuf Adev, norms, amax, Cu, Ai, r, rp, x, digits, comb, cvec, sync, C1, E, rp1, x1, C2, Ed,
+  DevBuf Adev, norms, Cu, Ai, r, rp, x, digits, comb, cvec, sync, C1, E, rp1, x1, C2, Ed,
       rv, xv;
   uint32_t* hres = nullptr;      // pinned host residues of the background batch
   size_t hres_cap = 0;
   PinBuf hstage;                 // pinned staging of the lifting's vectors and results
   PinBuf hsmall;                 // pinned flags and error words read back on st
+  PinBuf hnorms;                 // pinned read-back of the column and row norms
   int lift_mode = 0;             // 0: fastest cooperative form that applies; 1: one launch per
                                  // phase; 2: the 64-bit integer form modulo p^2
   bool block_pivots = true;      // the inverse's panels search their diagonal block first

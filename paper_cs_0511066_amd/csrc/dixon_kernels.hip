@@ -626,22 +626,22 @@ __global__ __launch_bounds__(256) void k_hensel_f64(const void* __restrict__ Lv,
   // thread t is element u * 256 + t of the tile in row-major order
   uint32_t lreg[NL];
   rv_t rreg[NR];
+  // (unconditional loads from clamped indices: a load under a condition
+  // waits for its own data; entries outside A are zeroed at the store)
   auto gload = [&](int k0) {
 #pragma unroll
     for (int u = 0; u < NL; u++) {
       const int f = u * 256 + t, r = f / BK, k = f % BK;
-      const int gr = row0 + r, gk = k0 + k;
-      lreg[u] = (gr < n && gk < n) ? ((const uint32_t*)Lv)[(int64_t)gr * n + gk] : 0u;
+      lreg[u] = ((const uint32_t*)Lv)[(int64_t)min(row0 + r, n - 1) * n + min(k0 + k, n - 1)];
     }
 #pragma unroll
     for (int u = 0; u < NR; u++) {
       const int f = u * 256 + t, k = f / BN, c = f % BN;
-      const int gk = k0 + k, gc = col0 + c;
-      rreg[u] = (gk < n && gc < n) ? ((const rv_t*)Rv)[(int64_t)gk * n + gc] : (rv_t)0;
+      rreg[u] = ((const rv_t*)Rv)[(int64_t)min(k0 + k, n - 1) * n + min(col0 + c, n - 1)];
     }
   };
   // to LDS as FP64: A as int32; planes centred; E reduced
-  auto lstore = [&]() {
+  auto lstore = [&](int k0) {
 #pragma unroll
     for (int u = 0; u < NL; u++) {
       const int f = u * 256 + t, r = f / BK, k = f % BK;
@@ -652,7 +652,7 @@ __global__ __launch_bounds__(256) void k_hensel_f64(const void* __restrict__ Lv,
         const double w = (double)lreg[u];
         v = w > h ? w - pd : w;
       }
-      sL[k][r] = v;
+      sL[k][r] = (row0 + r < n && k0 + k < n) ? v : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < NR; u++) {
@@ -664,7 +664,7 @@ __global__ __launch_bounds__(256) void k_hensel_f64(const void* __restrict__ Lv,
       } else {
         v = mod_c((double)rreg[u], pd, pinv);
       }
-      sR[k][c] = v;
+      sR[k][c] = (k0 + k < n && col0 + c < n) ? v : 0.0;
     }
   };
   v4d_h acc[2][2];
@@ -674,7 +674,7 @@ __global__ __launch_bounds__(256) void k_hensel_f64(const void* __restrict__ Lv,
     for (int j = 0; j < 2; j++) acc[i][j] = (v4d_h){0.0, 0.0, 0.0, 0.0};
   gload(0);
   for (int k0 = 0; k0 < n; k0 += BK) {
-    lstore();
+    lstore(k0);
     __syncthreads();
     if (k0 + BK < n) gload(k0 + BK);
 #pragma unroll

@@ -74,7 +74,7 @@ __global__ __launch_bounds__(256) void k_diag_block(int32_t* __restrict__ W, int
                                                     int32_t* __restrict__ flags,
                                                     int32_t* __restrict__ Linv,
                                                     int32_t* __restrict__ Uinv) {
-  __shared__ double sRow[128];
+  __shared__ double sRow[256];
   __shared__ double sV[96];
   const int z = blockIdx.x;
   diag_block_body<4>(W + (int64_t)z * slab + (int64_t)j0 * ldw + j0, ldw, pb, mods[z].p,
@@ -526,7 +526,7 @@ __global__ __launch_bounds__(256) void k_lu_update(int32_t* __restrict__ W, int6
     double* scr = &sA[0][0];
     diag_block_body<4>(Wz + (int64_t)r0 * ldw + r0, ldw, next.pb, p, pinv,
                        next.piv + (int64_t)z * next.piv_stride, r0, next.flags + z,
-                       next.Linv + (int64_t)z * 1024, next.Uinv + (int64_t)z * 1024, scr, scr + 128);
+                       next.Linv + (int64_t)z * 1024, next.Uinv + (int64_t)z * 1024, scr, scr + 256);
   }
 }
 

@@ -470,19 +470,23 @@ __device__ __forceinline__ void panel_body(int32_t* __restrict__ Wr, int64_t ldw
 // ------------------------------------------------------------------ diagonal block body
 // Factors the pb x pb diagonal block (pb <= 32) whose top-left entry is Wb
 // (leading dimension ldw) without a pivot search below it, with a workgroup of
-// NW waves (row i of the block belongs to wave i % NW).  Column c of
-// [A11 | I] is lane c of every wave (32 + 32 columns; a block narrower than
-// 32 is padded with the identity).  A fraction-free elimination,
-// row_i <- b_k row_i - r_ik row_k for i > k with b_k = the pivot-column entry
-// of row k, leaves row i scaled by sigma_i = b_0 ... b_{i-1}, so
-// [U | L^{-1}] row i = row i / sigma_i and no inverse is needed inside the
-// loop.  All 1 / sigma_i come from one Fermat ladder: with prefix products
+// NW waves (row i of the block belongs to wave i % NW).  Two eliminations run
+// side by side, in step: [A11 | I] and [A11^T | I] (32 + 32 columns, column c
+// of both is lane c of every wave; a block narrower than 32 is padded with the
+// identity).  A fraction-free elimination, row_i <- b_k row_i - r_ik row_k
+// for i > k with b_k = the pivot-column entry of row k, leaves row i scaled
+// by sigma_i = b_0 ... b_{i-1}, so no inverse is needed inside the loop:
+//  - [A11 | I] gives [U | L^{-1}] row by row after the scaling 1 / sigma_i;
+//  - A11^T = L_T U_T with L_T = U'^T and U_T = D L^T (U = D U', D =
+//    diag(u_ii), U' unit upper), whose pivots, and so whose sigma_i, are
+//    those of A11; [A11^T | I] gives L_T^{-1} = (U'^{-1})^T after the same
+//    scaling, and U^{-1} = U'^{-1} D^{-1}, i.e. U^{-1}[c][i] = L_T^{-1}[i][c]
+//    / u_ii.
+// All 1 / sigma_i come from one Fermat ladder: with prefix products
 // P_k = b_0 ... b_k and suffix products S_k = b_k ... b_31 (scans across the
-// lanes of wave 0), sigma_i = P_{i-1} and 1 / sigma_i = S_i / P_31.  Then
-// U^{-1} by a backward elimination of [U' | D^{-1}] (U = D U',
-// D = diag(u_ii), 1 / u_ii = sigma_i / b_i).  The pivot row of each step
-// reaches the other waves through LDS (sRow: 2 x 64 doubles, alternating, so
-// one barrier a step).
+// lanes of wave 0), sigma_i = P_{i-1} and 1 / sigma_i = S_i / P_31; 1 / u_ii =
+// sigma_i / b_i.  The pivot rows of each step reach the other waves through
+// LDS (sRow: 2 x 128 doubles, alternating, so one barrier a step).
 // Outputs: U11 into the block (on and above the diagonal), L11^{-1} and
 // U11^{-1} dense 32 x 32 row-major at Lz, Uz (zero outside pb x pb),
 // piv_z[j0 + i] = j0 + i, *flag = 1 when a pivot is 0 mod p (the caller then
@@ -499,7 +503,8 @@ __device__ __forceinline__ double shfl_down_dd(double x, int d) {
   return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
 }
 
-// mod_loose on R independent values, one phase at a time (see modp.hpp).
+// mod_loose on R independent values, one phase at a time (see modp.hpp), so
+// that a wave alone on its SIMD overlaps their dependent FP64 chains.
 template <int R>
 __device__ __forceinline__ void mod_loose_rows(double (&x)[R], double p, double pinv) {
   constexpr double RND = 6755399441055744.0;
@@ -512,6 +517,7 @@ __device__ __forceinline__ void mod_loose_rows(double (&x)[R], double p, double 
   for (int i = 0; i < R; i++) x[i] = fma(-q[i], p, x[i]);
 }
 
+// LDS: sRow 256 doubles, sV 96 doubles.
 template <int NW>
 __device__ __forceinline__ void diag_block_body(int32_t* __restrict__ Wb, int64_t ldw, int pb,
                                                 double p, double pinv, int32_t* __restrict__ piv_z,
@@ -523,51 +529,75 @@ __device__ __forceinline__ void diag_block_body(int32_t* __restrict__ Wb, int64_
   const int t = threadIdx.x;
   const int c = t & 63, w = t >> 6;
   const uint32_t e_inv = (uint32_t)__builtin_amdgcn_readfirstlane((int)((uint32_t)p - 2u));
-  double F[RW];
+  double F[RW], G[RW];                           // rows of [A11 | I] and of [A11^T | I]
   if (w < NW) {
     // every load is issued before any is used (clamped indices stay inside
-    // the pb x pb block; the padding is selected afterwards), so the wave
-    // waits for memory once instead of once a row
-    int32_t v[RW];
+    // the pb x pb block; the padding is selected afterwards)
+    int32_t v[RW], u[RW];
     const int cc = min(c & 31, pb - 1);
 #pragma unroll
-    for (int q = 0; q < RW; q++) v[q] = Wb[(int64_t)min(w + NW * q, pb - 1) * ldw + cc];
+    for (int q = 0; q < RW; q++) {
+      const int ii = min(w + NW * q, pb - 1);
+      v[q] = Wb[(int64_t)ii * ldw + cc];
+      u[q] = Wb[(int64_t)cc * ldw + ii];
+    }
 #pragma unroll
     for (int q = 0; q < RW; q++) {
       const int i = w + NW * q;
-      if (c < 32) F[q] = (i < pb && c < pb) ? (double)v[q] : (i == c ? 1.0 : 0.0);
-      else F[q] = (i == c - 32) ? 1.0 : 0.0;
+      if (c < 32) {
+        const bool in = i < pb && c < pb;
+        F[q] = in ? (double)v[q] : (i == c ? 1.0 : 0.0);
+        G[q] = in ? (double)u[q] : (i == c ? 1.0 : 0.0);
+      } else {
+        F[q] = G[q] = (i == c - 32) ? 1.0 : 0.0;
+      }
     }
   }
   bool zero = false;
-  // ---- fraction-free elimination
+  // ---- the two fraction-free eliminations
   for (int k = 0; k < 32; k++) {
-    double* row = sRow + (k & 1) * 64;
+    double* rowF = sRow + (k & 1) * 128;
+    double* rowG = rowF + 64;
     if (w == k % NW) {
       const int oq = k / NW;
-      double v = 0.0;
+      double a = 0.0, b = 0.0;
 #pragma unroll
-      for (int q = 0; q < RW; q++) v = q == oq ? F[q] : v;
-      row[c] = v;
+      for (int q = 0; q < RW; q++) {
+        a = q == oq ? F[q] : a;
+        b = q == oq ? G[q] : b;
+      }
+      rowF[c] = a;
+      rowG[c] = b;
     }
     __syncthreads();
-    const double fk = row[c < 64 ? c : 0];
-    const double braw = row[k];
+    const double fk = rowF[c], gk = rowG[c];
+    const double braw = rowF[k], graw = rowG[k];
     zero |= braw == 0.0;
     const double bk = braw == 0.0 ? 1.0 : braw;      // (the result is discarded then)
+    const double bg = graw == 0.0 ? 1.0 : graw;
     if (t == 0) sV[k] = bk;
     if (w < NW) {
       // the rows of a wave are independent: each phase runs over all of them
-      // before the next, so that a wave (alone on its SIMD) overlaps their
-      // dependent FP64 chains instead of waiting on each
-      double x[RW];
+      // before the next
+      double x[RW], y[RW];
 #pragma unroll
-      for (int q = 0; q < RW; q++) x[q] = -readlane_d(F[q], k) * fk;
+      for (int q = 0; q < RW; q++) {
+        x[q] = -readlane_d(F[q], k) * fk;
+        y[q] = -readlane_d(G[q], k) * gk;
+      }
 #pragma unroll
-      for (int q = 0; q < RW; q++) x[q] = fma(bk, F[q], x[q]);
+      for (int q = 0; q < RW; q++) {
+        x[q] = fma(bk, F[q], x[q]);
+        y[q] = fma(bg, G[q], y[q]);
+      }
       mod_loose_rows<RW>(x, p, pinv);
+      mod_loose_rows<RW>(y, p, pinv);
 #pragma unroll
-      for (int q = 0; q < RW; q++) F[q] = (w + NW * q > k) ? x[q] : F[q];
+      for (int q = 0; q < RW; q++) {
+        const bool act = w + NW * q > k;
+        F[q] = act ? x[q] : F[q];
+        G[q] = act ? y[q] : G[q];
+      }
     }
   }
   __syncthreads();
@@ -577,9 +607,9 @@ __device__ __forceinline__ void diag_block_body(int32_t* __restrict__ Wb, int64_
     double P = bv, S = bv;
 #pragma unroll
     for (int d = 1; d < 32; d <<= 1) {
-      const double u = shfl_up_dd(P, d), v = shfl_down_dd(S, d);
-      if ((c & 31) >= d) P = mul_mod_loose(P, u, p, pinv);
-      if ((c & 31) + d < 32) S = mul_mod_loose(S, v, p, pinv);
+      const double uu = shfl_up_dd(P, d), vv = shfl_down_dd(S, d);
+      if ((c & 31) >= d) P = mul_mod_loose(P, uu, p, pinv);
+      if ((c & 31) + d < 32) S = mul_mod_loose(S, vv, p, pinv);
     }
     P = mod_c(P, p, pinv);
     S = mod_c(S, p, pinv);
@@ -596,48 +626,19 @@ __device__ __forceinline__ void diag_block_body(int32_t* __restrict__ Wb, int64_
   }
   __syncthreads();
   if (w < NW) {
-    // rows of [U | L^{-1}], then [U' | D^{-1}]
 #pragma unroll
     for (int q = 0; q < RW; q++) {
       const int i = w + NW * q;
-      F[q] = mul_mod(F[q], sV[32 + i], p, pinv);
+      const double si = sV[32 + i];
+      const double f = mul_mod(F[q], si, p, pinv);                      // [U | L^{-1}] row i
       if (c < 32) {
-        if (c < pb && i <= c) Wb[(int64_t)i * ldw + c] = (int32_t)F[q];
+        if (c < pb && i <= c) Wb[(int64_t)i * ldw + c] = (int32_t)f;
       } else {
         const int cc = c - 32;
-        Lz[i * 32 + cc] = (i < pb && cc < pb) ? (int32_t)F[q] : 0;
+        Lz[i * 32 + cc] = (i < pb && cc < pb) ? (int32_t)f : 0;
+        const double g = mul_mod(mul_mod(G[q], si, p, pinv), sV[64 + i], p, pinv);
+        Uz[cc * 32 + i] = (i < pb && cc < pb) ? (int32_t)g : 0;
       }
-      const double di = sV[64 + i];
-      F[q] = c < 32 ? mul_mod(F[q], di, p, pinv) : (i == c - 32 ? di : 0.0);
-    }
-  }
-  // ---- backward elimination: U^{-1} = U'^{-1} D^{-1}
-  for (int k = 31; k > 0; k--) {
-    double* row = sRow + (k & 1) * 64;
-    if (w == k % NW) {
-      const int oq = k / NW;
-      double v = 0.0;
-#pragma unroll
-      for (int q = 0; q < RW; q++) v = q == oq ? F[q] : v;
-      row[c] = v;
-    }
-    __syncthreads();
-    const double fk = row[c];
-    if (w < NW) {
-      double x[RW];
-#pragma unroll
-      for (int q = 0; q < RW; q++) x[q] = fma(-readlane_d(F[q], k), fk, F[q]);
-      mod_loose_rows<RW>(x, p, pinv);
-#pragma unroll
-      for (int q = 0; q < RW; q++) F[q] = (w + NW * q < k) ? x[q] : F[q];
-    }
-  }
-  if (w < NW && c >= 32) {
-    const int cc = c - 32;
-#pragma unroll
-    for (int q = 0; q < RW; q++) {
-      const int i = w + NW * q;
-      Uz[i * 32 + cc] = (i < pb && cc < pb) ? (int32_t)mod_c(F[q], p, pinv) : 0;
     }
   }
   if (t < pb) piv_z[j0 + t] = j0 + t;
