@@ -608,16 +608,17 @@ int lift3_grid(int device, int n) {
 //           load; products < 2^48 (p < 2^25), reduced every 16 k-steps.
 typedef double v4d_h __attribute__((ext_vector_type(4)));
 template <int MODE>
-__global__ __launch_bounds__(256) void k_hensel_f64(const void* __restrict__ Lv,
+__global__ __launch_bounds__(512) void k_hensel_f64(const void* __restrict__ Lv,
                                                     const void* __restrict__ Rv,
                                                     const double* __restrict__ Ein, int n,
                                                     uint32_t p, double pinv, void* __restrict__ out) {
   constexpr int BM = 64, BN = 64, BK = 64;
-  constexpr int NL = BM * BK / 256, NR = BK * BN / 256;     // values a thread loads per chunk
+  constexpr int T = 512;                                    // eight waves of 32 x 16
+  constexpr int NL = BM * BK / T, NR = BK * BN / T;         // values a thread loads per chunk
   typedef typename std::conditional<MODE == 0, uint32_t, double>::type rv_t;
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
-  const int wr = wave >> 1, wc = wave & 1;
+  const int wr = wave >> 2, wc = wave & 3;
   const int row0 = blockIdx.y * BM, col0 = blockIdx.x * BN;
   const double pd = (double)p, h = 0.5 * pd;
   __shared__ double sL[BK][BM + 2];
@@ -631,12 +632,12 @@ __global__ __launch_bounds__(256) void k_hensel_f64(const void* __restrict__ Lv,
   auto gload = [&](int k0) {
 #pragma unroll
     for (int u = 0; u < NL; u++) {
-      const int f = u * 256 + t, r = f / BK, k = f % BK;
+      const int f = u * T + t, r = f / BK, k = f % BK;
       lreg[u] = ((const uint32_t*)Lv)[(int64_t)min(row0 + r, n - 1) * n + min(k0 + k, n - 1)];
     }
 #pragma unroll
     for (int u = 0; u < NR; u++) {
-      const int f = u * 256 + t, k = f / BN, c = f % BN;
+      const int f = u * T + t, k = f / BN, c = f % BN;
       rreg[u] = ((const rv_t*)Rv)[(int64_t)min(k0 + k, n - 1) * n + min(col0 + c, n - 1)];
     }
   };
@@ -644,7 +645,7 @@ __global__ __launch_bounds__(256) void k_hensel_f64(const void* __restrict__ Lv,
   auto lstore = [&](int k0) {
 #pragma unroll
     for (int u = 0; u < NL; u++) {
-      const int f = u * 256 + t, r = f / BK, k = f % BK;
+      const int f = u * T + t, r = f / BK, k = f % BK;
       double v;
       if (MODE == 0) {
         v = (double)(int32_t)lreg[u];
@@ -656,7 +657,7 @@ __global__ __launch_bounds__(256) void k_hensel_f64(const void* __restrict__ Lv,
     }
 #pragma unroll
     for (int u = 0; u < NR; u++) {
-      const int f = u * 256 + t, k = f / BN, c = f % BN;
+      const int f = u * T + t, k = f / BN, c = f % BN;
       double v;
       if (MODE == 0) {
         const double w = (double)rreg[u];
@@ -667,11 +668,9 @@ __global__ __launch_bounds__(256) void k_hensel_f64(const void* __restrict__ Lv,
       sR[k][c] = (k0 + k < n && col0 + c < n) ? v : 0.0;
     }
   };
-  v4d_h acc[2][2];
+  v4d_h acc[2][1];
 #pragma unroll
-  for (int i = 0; i < 2; i++)
-#pragma unroll
-    for (int j = 0; j < 2; j++) acc[i][j] = (v4d_h){0.0, 0.0, 0.0, 0.0};
+  for (int i = 0; i < 2; i++) acc[i][0] = (v4d_h){0.0, 0.0, 0.0, 0.0};
   gload(0);
   for (int k0 = 0; k0 < n; k0 += BK) {
     lstore(k0);
@@ -680,46 +679,48 @@ __global__ __launch_bounds__(256) void k_hensel_f64(const void* __restrict__ Lv,
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 4) {
       const int kr = ks + (lane >> 4);
-      double af[2], bf[2];
+      double af[2];
 #pragma unroll
       for (int i = 0; i < 2; i++) af[i] = sL[kr][wr * 32 + i * 16 + (lane & 15)];
-#pragma unroll
-      for (int j = 0; j < 2; j++) bf[j] = sR[kr][wc * 32 + j * 16 + (lane & 15)];
+      const double bf = sR[kr][wc * 16 + (lane & 15)];
 #pragma unroll
       for (int i = 0; i < 2; i++)
-#pragma unroll
-        for (int j = 0; j < 2; j++)
-          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+        acc[i][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf, acc[i][0], 0, 0, 0);
       if (MODE == 1 && (ks & 15) == 12) {
 #pragma unroll
         for (int i = 0; i < 2; i++)
 #pragma unroll
-          for (int j = 0; j < 2; j++)
-#pragma unroll
-            for (int r = 0; r < 4; r++) acc[i][j][r] = mod_loose(acc[i][j][r], pd, pinv);
+          for (int r = 0; r < 4; r++) acc[i][0][r] = mod_loose(acc[i][0][r], pd, pinv);
       }
     }
     __syncthreads();
   }
-  // output element (row wr*32 + i*16 + lane/16 + 4 r, col wc*32 + j*16 + lane%16)
+  // output element (row wr*32 + i*16 + lane/16 + 4 r, col wc*16 + lane%16);
+  // MODE 0 reads Ein for all of them first (clamped, unconditional)
+  const int gc = col0 + wc * 16 + (lane & 15);
+  double ein[2][4];
 #pragma unroll
   for (int i = 0; i < 2; i++)
 #pragma unroll
-    for (int j = 0; j < 2; j++)
+    for (int r = 0; r < 4; r++) {
+      const int gr = row0 + wr * 32 + i * 16 + (lane >> 4) + 4 * r;
+      ein[i][r] = (MODE == 0 && Ein) ? Ein[(int64_t)min(gr, n - 1) * n + min(gc, n - 1)]
+                                     : (gr == gc ? -1.0 : 0.0);
+    }
 #pragma unroll
-      for (int r = 0; r < 4; r++) {
-        const int gr = row0 + wr * 32 + i * 16 + (lane >> 4) + 4 * r;
-        const int gc = col0 + wc * 32 + j * 16 + (lane & 15);
-        if (gr >= n || gc >= n) continue;
-        const int64_t o = (int64_t)gr * n + gc;
-        if (MODE == 0) {
-          const double ein = Ein ? Ein[o] : (gr == gc ? -1.0 : 0.0);
-          ((double*)out)[o] = quot_p(ein + acc[i][j][r], pinv);
-        } else {
-          const double v = mod_c(-acc[i][j][r], pd, pinv);
-          ((uint32_t*)out)[o] = (uint32_t)(v < 0 ? v + pd : v);
-        }
+  for (int i = 0; i < 2; i++)
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+      const int gr = row0 + wr * 32 + i * 16 + (lane >> 4) + 4 * r;
+      if (gr >= n || gc >= n) continue;
+      const int64_t o = (int64_t)gr * n + gc;
+      if (MODE == 0) {
+        ((double*)out)[o] = quot_p(ein[i][r] + acc[i][0][r], pinv);
+      } else {
+        const double v = mod_c(-acc[i][0][r], pd, pinv);
+        ((uint32_t*)out)[o] = (uint32_t)(v < 0 ? v + pd : v);
       }
+    }
 }
 
 __device__ __forceinline__ int wave_sum_i32(int v) {
@@ -1117,10 +1118,10 @@ hipError_t launch_hensel_f64(const int32_t* Ai, const uint32_t* C0, double* E, u
   if (n <= 0) return hipSuccess;
   dim3 grid((n + 63) / 64, (n + 63) / 64);
   const double pinv = 1.0 / (double)p;
-  k_hensel_f64<0><<<grid, 256, 0, st>>>((const void*)Ai, (const void*)C0, nullptr, n, p, pinv, E);
-  k_hensel_f64<1><<<grid, 256, 0, st>>>((const void*)C0, (const void*)E, nullptr, n, p, pinv, C1);
-  k_hensel_f64<0><<<grid, 256, 0, st>>>((const void*)Ai, (const void*)C1, E, n, p, pinv, E);
-  k_hensel_f64<1><<<grid, 256, 0, st>>>((const void*)C0, (const void*)E, nullptr, n, p, pinv, C2);
+  k_hensel_f64<0><<<grid, 512, 0, st>>>((const void*)Ai, (const void*)C0, nullptr, n, p, pinv, E);
+  k_hensel_f64<1><<<grid, 512, 0, st>>>((const void*)C0, (const void*)E, nullptr, n, p, pinv, C1);
+  k_hensel_f64<0><<<grid, 512, 0, st>>>((const void*)Ai, (const void*)C1, E, n, p, pinv, E);
+  k_hensel_f64<1><<<grid, 512, 0, st>>>((const void*)C0, (const void*)E, nullptr, n, p, pinv, C2);
   return hipGetLastError();
 }
 
