@@ -635,29 +635,14 @@ det_status lift3_multi(det_ctx* c, int grid3, const int64_t* dA, int64_t dlda, i
   const Stage sl = stage_layout(n, 0);
   TRY(ensure_pin(c, c->hstage, sl.total, c->st));
   TRY(ensure_pin(c, c->hsmall, 64, c->st));
-  HIPCHK(detk::launch_hensel_f64((const int32_t*)c->Ai.p, (const uint32_t*)c->Cu.p,
-                                 (double*)c->Ed.p, (uint32_t*)c->C1.p, (uint32_t*)c->C2.p, n, p,
-                                 c->st));
-  if (after_own2) {
-    HIPCHK(hipEventRecord(c->ev, c->own2));
-    HIPCHK(hipStreamWaitEvent(c->st, c->ev, 0));
-  }
-  // the combinations are formed after the lifting, from its digits
-  uint32_t* dig = digits_dev;
-  if (!dig && comb_dev) {
-    TRY(ensure(c, c->digits, (size_t)m * k * n * sizeof(uint32_t)));
-    dig = (uint32_t*)c->digits.p;
-  }
   int* err = (int*)((char*)c->sync.p + 32);
   int* herr = (int*)c->hsmall.p;
   char* hs = (char*)c->hstage.p;
   const int mr = detk::lift3_max_rhs(n);
-  for (int h0 = 0; h0 < m; h0 += mr) {
-    const int mm = std::min(mr, m - h0);
-    if (h0 > 0) HIPCHK(hipStreamSynchronize(c->st));    // the staging of the last chunk is read
-    // r_0 = b and its balanced digits mod p^3 (each centring carried into the
-    // next digit), one record of 25-bit fields under tag 0 (step 0) per row
-    // and right-hand side
+  // r_0 = b and its balanced digits mod p^3 (each centring carried into the
+  // next digit), one record of 25-bit fields under tag 0 (step 0) per row
+  // and right-hand side, for the right-hand sides [h0, h0 + mm)
+  auto stage = [&](int h0, int mm) -> det_status {
     int64_t* hb = (int64_t*)(hs + sl.r);
     uint32_t* d3 = (uint32_t*)(hs + sl.d3);
     for (int j = 0; j < n; j++)
@@ -681,6 +666,30 @@ det_status lift3_multi(det_ctx* c, int grid3, const int64_t* dA, int64_t dlda, i
     // xv: all-ones words (tag 127, not yet written by any step)
     HIPCHK(hipMemsetAsync(c->xv.p, 0xFF, recs * 4 * sizeof(uint32_t), c->st));
     HIPCHK(hipMemsetAsync(c->sync.p, 0, 64, c->st));
+    return DET_OK;
+  };
+  // the first chunk's staging goes ahead of the Hensel products, so that the
+  // lifting follows them (or the wait for own2) at once
+  TRY(stage(0, std::min(mr, m)));
+  HIPCHK(detk::launch_hensel_f64((const int32_t*)c->Ai.p, (const uint32_t*)c->Cu.p,
+                                 (double*)c->Ed.p, (uint32_t*)c->C1.p, (uint32_t*)c->C2.p, n, p,
+                                 c->st));
+  if (after_own2) {
+    HIPCHK(hipEventRecord(c->ev, c->own2));
+    HIPCHK(hipStreamWaitEvent(c->st, c->ev, 0));
+  }
+  // the combinations are formed after the lifting, from its digits
+  uint32_t* dig = digits_dev;
+  if (!dig && comb_dev) {
+    TRY(ensure(c, c->digits, (size_t)m * k * n * sizeof(uint32_t)));
+    dig = (uint32_t*)c->digits.p;
+  }
+  for (int h0 = 0; h0 < m; h0 += mr) {
+    const int mm = std::min(mr, m - h0);
+    if (h0 > 0) {
+      HIPCHK(hipStreamSynchronize(c->st));    // the staging of the last chunk is read
+      TRY(stage(h0, mm));
+    }
     {
       // algorithmic bytes per digit and right-hand side: C and A as the
       // one-launch-per-phase form reads them (8 n^2) and four n-vectors

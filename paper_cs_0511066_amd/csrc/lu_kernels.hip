@@ -64,10 +64,10 @@ __global__ __launch_bounds__(512) void k_panel(int32_t* __restrict__ W, int64_t 
 }
 
 // ------------------------------------------------------------------ K2': diagonal block
-// One 256-thread workgroup per item factors the pb x pb diagonal block at
+// One 512-thread workgroup per item factors the pb x pb diagonal block at
 // (j0, j0) without a pivot search below it (diag_block_body, panel.hpp), for
 // an LU whose update forms L21 itself (k_lu_update with Uinv).
-__global__ __launch_bounds__(256) void k_diag_block(int32_t* __restrict__ W, int64_t ldw,
+__global__ __launch_bounds__(512) void k_diag_block(int32_t* __restrict__ W, int64_t ldw,
                                                     int64_t slab, int j0, int pb,
                                                     const Modulus* __restrict__ mods,
                                                     int32_t* __restrict__ piv, int64_t piv_stride,
@@ -77,7 +77,7 @@ __global__ __launch_bounds__(256) void k_diag_block(int32_t* __restrict__ W, int
   __shared__ double sRow[256];
   __shared__ double sV[96];
   const int z = blockIdx.x;
-  diag_block_body<4>(W + (int64_t)z * slab + (int64_t)j0 * ldw + j0, ldw, pb, mods[z].p,
+  diag_block_body<8>(W + (int64_t)z * slab + (int64_t)j0 * ldw + j0, ldw, pb, mods[z].p,
                      mods[z].pinv, piv + (int64_t)z * piv_stride, j0, flags + z,
                      Linv + (int64_t)z * 1024, Uinv + (int64_t)z * 1024, sRow, sV);
 }
@@ -163,9 +163,9 @@ __global__ __launch_bounds__(1024) void k_tri_inv(const int32_t* __restrict__ W,
 }
 
 // ------------------------------------------------------------------ FP64 MFMA tile machinery
-// A 256-thread workgroup computes a 64x64 tile; wave w owns the 32x32
-// quadrant (w>>1, w&1) as 2x2 MFMA 16x16 blocks.  Operands are staged in LDS
-// as doubles, k-major, so that a lane reads 16 consecutive doubles per row.
+// A workgroup computes a 64x64 tile, each wave a rectangle of MFMA 16x16
+// blocks.  Operands are staged in LDS as doubles, k-major, so that a lane
+// reads 16 consecutive doubles per row.
 // v_mfma_f64_16x16x4: lane l supplies A[l%16][l/16] and B[l/16][l%16];
 // result element r of lane l is D[l/16 + 4r][l%16].
 constexpr int GB_M = 64, GB_N = 64, GB_K = 32;
@@ -312,7 +312,7 @@ __global__ void k_place_diag(int32_t* __restrict__ W, int64_t ldw, int64_t offV,
 // [j0 + pb, j0 + pb + N) of every item, in one launch:
 //   U12 = L11^{-1} A12 for the workgroup's 64 columns (every workgroup of a
 //   column tile computes it from A12), then A22 -= L21 U12 on its 64 x 64
-//   tile.
+//   tile; eight waves, two a SIMD, each a 32 x 16 block of the update.
 // A12 stays in place until every workgroup of its column tile has read it:
 // with cnt != null each workgroup counts its read (after the loads have
 // completed) and the last one stores U12 over A12; without it U12 is not
@@ -338,17 +338,18 @@ struct NextDiag {
   int32_t* flags;
 };
 
-__global__ __launch_bounds__(256) void k_lu_update(int32_t* __restrict__ W, int64_t slab,
+__global__ __launch_bounds__(512) void k_lu_update(int32_t* __restrict__ W, int64_t slab,
                                                    int64_t ldw, int j0, int pb, int M, int N,
                                                    const int32_t* __restrict__ Linv, int ldt,
                                                    const int32_t* __restrict__ Uinv,
                                                    const Modulus* __restrict__ mods, int kc4,
                                                    unsigned* __restrict__ cnt, int cnt_stride,
                                                    NextDiag next) {
+  constexpr int T = 512;                                // eight waves, two a SIMD
   const int z = blockIdx.z;
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
-  const int wr = wave >> 1, wc = wave & 1;
+  const int wr = wave >> 2, wc = wave & 3;              // update: a 32 x 16 block a wave
   const double p = mods[z].p, pinv = mods[z].pinv;
   int32_t* Wz = W + (int64_t)z * slab;
   const int r0 = j0 + pb;                               // first row and column of A22
@@ -364,168 +365,138 @@ __global__ __launch_bounds__(256) void k_lu_update(int32_t* __restrict__ W, int6
   // load under a condition becomes a branch that waits for its own data.
   const int32_t* Tz = Linv + (int64_t)z * ldt * ldt;
   const int32_t* Uz = Uinv != nullptr ? Uinv + (int64_t)z * ldt * ldt : Tz;
-  int32_t vt[4], vu[4];
+  int32_t vt[1024 / T], vu[1024 / T];
 #pragma unroll
-  for (int u = 0; u < 4; u++) {
-    const int e = u * 256 + t, r = min(e >> 5, pb - 1), c = min(e & 31, pb - 1);
+  for (int u = 0; u < 1024 / T; u++) {
+    const int e = u * T + t, r = min(e >> 5, pb - 1), c = min(e & 31, pb - 1);
     vt[u] = Tz[r * ldt + c];
     vu[u] = Uz[r * ldt + c];
   }
-  int32_t va[GB_M * GB_K / 256], vb[GB_K * GB_N / 256], vc[2][2][4];
+  int32_t va[GB_M * GB_K / T], vb[GB_K * GB_N / T], vc[2][4];
 #pragma unroll
-  for (int u = 0; u < GB_M * GB_K / 256; u++) {
-    const int f = u * 256 + t, r = f / GB_K, k = f % GB_K;
+  for (int u = 0; u < GB_M * GB_K / T; u++) {
+    const int f = u * T + t, r = f / GB_K, k = f % GB_K;
     va[u] = Wz[(int64_t)(r0 + min(row0 + r, M - 1)) * ldw + j0 + min(k, pb - 1)];
   }
 #pragma unroll
-  for (int u = 0; u < GB_K * GB_N / 256; u++) {
-    const int f = u * 256 + t, k = f / GB_N, c = f % GB_N;
+  for (int u = 0; u < GB_K * GB_N / T; u++) {
+    const int f = u * T + t, k = f / GB_N, c = f % GB_N;
     vb[u] = Wz[(int64_t)(j0 + min(k, pb - 1)) * ldw + r0 + min(col0 + c, N - 1)];
   }
+  const int gc = col0 + wc * 16 + (lane & 15);
 #pragma unroll
   for (int i = 0; i < 2; i++)
 #pragma unroll
-    for (int j = 0; j < 2; j++)
+    for (int r = 0; r < 4; r++) {
+      const int gr = row0 + wr * 32 + i * 16 + (lane >> 4) + 4 * r;
+      vc[i][r] = Wz[(int64_t)(r0 + min(gr, M - 1)) * ldw + r0 + min(gc, N - 1)];
+    }
 #pragma unroll
-      for (int r = 0; r < 4; r++) {
-        const int gr = row0 + wr * 32 + i * 16 + (lane >> 4) + 4 * r;
-        const int gc = col0 + wc * 32 + j * 16 + (lane & 15);
-        vc[i][j][r] = Wz[(int64_t)(r0 + min(gr, M - 1)) * ldw + r0 + min(gc, N - 1)];
-      }
-#pragma unroll
-  for (int u = 0; u < 4; u++) {
-    const int e = u * 256 + t, r = e >> 5, c = e & 31;
+  for (int u = 0; u < 1024 / T; u++) {
+    const int e = u * T + t, r = e >> 5, c = e & 31;
     const bool in = r < pb && c < pb;
     sT[r][c] = in ? (double)vt[u] : 0.0;
     sU[r][c] = in ? (double)vu[u] : 0.0;
   }
 #pragma unroll
-  for (int u = 0; u < GB_M * GB_K / 256; u++) {
-    const int f = u * 256 + t, r = f / GB_K, k = f % GB_K;
+  for (int u = 0; u < GB_M * GB_K / T; u++) {
+    const int f = u * T + t, r = f / GB_K, k = f % GB_K;
     sA[k][r] = (row0 + r < M && k < pb) ? (double)va[u] : 0.0;
   }
 #pragma unroll
-  for (int u = 0; u < GB_K * GB_N / 256; u++) {
-    const int f = u * 256 + t, k = f / GB_N, c = f % GB_N;
+  for (int u = 0; u < GB_K * GB_N / T; u++) {
+    const int f = u * T + t, k = f / GB_N, c = f % GB_N;
     sB[k][c] = (k < pb && col0 + c < N) ? (double)vb[u] : 0.0;
   }
   __syncthreads();
   if (Uinv != nullptr) {
-    // L21 = A21 U11^{-1} (64 x 32): wave w the rows 16 w .. 16 w + 15, two
-    // 16 x 16 MFMA blocks; written back into sA (k-major) after every wave
-    // has read A21
-    v4d l2[2];
-    l2[0] = l2[1] = (v4d){0.0, 0.0, 0.0, 0.0};
+    // L21 = A21 U11^{-1} (64 x 32): one 16 x 16 MFMA block a wave (rows
+    // 16 (w >> 1), columns 16 (w & 1)); written back into sA (k-major) after
+    // every wave has read A21
+    const int lr = (wave >> 1) * 16, lc = (wave & 1) * 16;
+    v4d l2 = (v4d){0.0, 0.0, 0.0, 0.0};
     int steps = 0;
 #pragma unroll
     for (int ks = 0; ks < 32; ks += 4) {
       const int kr = ks + (lane >> 4);
-      const double af = sA[kr][wave * 16 + (lane & 15)];
-#pragma unroll
-      for (int j = 0; j < 2; j++)
-        l2[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af, sU[kr][j * 16 + (lane & 15)], l2[j], 0, 0, 0);
+      l2 = __builtin_amdgcn_mfma_f64_16x16x4f64(sA[kr][lr + (lane & 15)], sU[kr][lc + (lane & 15)],
+                                               l2, 0, 0, 0);
       if (++steps == kc4) {
         steps = 0;
 #pragma unroll
-        for (int j = 0; j < 2; j++)
-#pragma unroll
-          for (int r = 0; r < 4; r++) l2[j][r] = mod_c(l2[j][r], p, pinv);
+        for (int r = 0; r < 4; r++) l2[r] = mod_c(l2[r], p, pinv);
       }
     }
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < 2; j++)
-#pragma unroll
-      for (int r = 0; r < 4; r++)
-        sA[j * 16 + (lane & 15)][wave * 16 + (lane >> 4) + 4 * r] = mod_c(l2[j][r], p, pinv);
+    for (int r = 0; r < 4; r++) sA[lc + (lane & 15)][lr + (lane >> 4) + 4 * r] = mod_c(l2[r], p, pinv);
     __syncthreads();
   }
-  // U12 = L11^{-1} A12 (32 x 64): wave w the 16 x 32 block (rows 16 (w >> 1),
-  // columns 32 (w & 1)), two 16 x 16 MFMA blocks
-  v4d u2[2];
-  u2[0] = u2[1] = (v4d){0.0, 0.0, 0.0, 0.0};
+  // U12 = L11^{-1} A12 (32 x 64): one 16 x 16 MFMA block a wave (rows
+  // 16 (w >> 2), columns 16 (w & 3))
+  const int ur = (wave >> 2) * 16, uc = (wave & 3) * 16;
+  v4d u2 = (v4d){0.0, 0.0, 0.0, 0.0};
   {
     int steps = 0;
 #pragma unroll
     for (int ks = 0; ks < 32; ks += 4) {
       const int kr = ks + (lane >> 4);
-      const double af = sT[wr * 16 + (lane & 15)][kr];
-#pragma unroll
-      for (int j = 0; j < 2; j++)
-        u2[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af, sB[kr][wc * 32 + j * 16 + (lane & 15)],
-                                                     u2[j], 0, 0, 0);
+      u2 = __builtin_amdgcn_mfma_f64_16x16x4f64(sT[ur + (lane & 15)][kr], sB[kr][uc + (lane & 15)],
+                                               u2, 0, 0, 0);
       if (++steps == kc4) {
         steps = 0;
 #pragma unroll
-        for (int j = 0; j < 2; j++)
-#pragma unroll
-          for (int r = 0; r < 4; r++) u2[j][r] = mod_c(u2[j][r], p, pinv);
+        for (int r = 0; r < 4; r++) u2[r] = mod_c(u2[r], p, pinv);
       }
     }
   }
   __syncthreads();                                      // every wave is done with A12
 #pragma unroll
-  for (int j = 0; j < 2; j++)
-#pragma unroll
-    for (int r = 0; r < 4; r++)
-      sB[wr * 16 + (lane >> 4) + 4 * r][wc * 32 + j * 16 + (lane & 15)] = mod_c(u2[j][r], p, pinv);
+  for (int r = 0; r < 4; r++) sB[ur + (lane >> 4) + 4 * r][uc + (lane & 15)] = mod_c(u2[r], p, pinv);
   if (cnt != nullptr && t == 0) {
     const unsigned prev = atomicAdd(cnt + (int64_t)z * cnt_stride + blockIdx.x, 1u);
     s_last = prev + 1 == gridDim.y;
   }
   __syncthreads();
   if (cnt != nullptr && s_last) {                       // the last reader stores U12
-    for (int e = t; e < 32 * GB_N; e += 256) {
+    for (int e = t; e < 32 * GB_N; e += T) {
       const int k = e / GB_N, c = e % GB_N;
       if (k < pb && col0 + c < N) Wz[(int64_t)(j0 + k) * ldw + r0 + col0 + c] = (int32_t)sB[k][c];
     }
   }
-  // A22 -= L21 U12
-  v4d acc[2][2];
-#pragma unroll
-  for (int i = 0; i < 2; i++)
-#pragma unroll
-    for (int j = 0; j < 2; j++) acc[i][j] = (v4d){0.0, 0.0, 0.0, 0.0};
+  // A22 -= L21 U12: wave (wr, wc) the 32 x 16 block at rows 32 wr, columns 16 wc
+  v4d acc[2];
+  acc[0] = acc[1] = (v4d){0.0, 0.0, 0.0, 0.0};
   int steps = 0;
 #pragma unroll
   for (int ks = 0; ks < GB_K; ks += 4) {
     const int kr = ks + (lane >> 4);
-    double af[2], bf[2];
-#pragma unroll
-    for (int i = 0; i < 2; i++) af[i] = sA[kr][wr * 32 + i * 16 + (lane & 15)];
-#pragma unroll
-    for (int j = 0; j < 2; j++) bf[j] = sB[kr][wc * 32 + j * 16 + (lane & 15)];
+    const double bf = sB[kr][wc * 16 + (lane & 15)];
 #pragma unroll
     for (int i = 0; i < 2; i++)
-#pragma unroll
-      for (int j = 0; j < 2; j++)
-        acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+      acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(sA[kr][wr * 32 + i * 16 + (lane & 15)], bf,
+                                                   acc[i], 0, 0, 0);
     if (++steps == kc4) {
       steps = 0;
 #pragma unroll
       for (int i = 0; i < 2; i++)
 #pragma unroll
-        for (int j = 0; j < 2; j++)
-#pragma unroll
-          for (int r = 0; r < 4; r++) acc[i][j][r] = mod_c(acc[i][j][r], p, pinv);
+        for (int r = 0; r < 4; r++) acc[i][r] = mod_c(acc[i][r], p, pinv);
     }
   }
 #pragma unroll
   for (int i = 0; i < 2; i++)
 #pragma unroll
-    for (int j = 0; j < 2; j++)
-#pragma unroll
-      for (int r = 0; r < 4; r++) {
-        const int gr = row0 + wr * 32 + i * 16 + (lane >> 4) + 4 * r;
-        const int gc = col0 + wc * 32 + j * 16 + (lane & 15);
-        if (gr < M && gc < N)
-          Wz[(int64_t)(r0 + gr) * ldw + r0 + gc] =
-              (int32_t)mod_c((double)vc[i][j][r] - mod_c(acc[i][j][r], p, pinv), p, pinv);
-      }
+    for (int r = 0; r < 4; r++) {
+      const int gr = row0 + wr * 32 + i * 16 + (lane >> 4) + 4 * r;
+      if (gr < M && gc < N)
+        Wz[(int64_t)(r0 + gr) * ldw + r0 + gc] =
+            (int32_t)mod_c((double)vc[i][r] - mod_c(acc[i][r], p, pinv), p, pinv);
+    }
   if (next.pb > 0 && blockIdx.x == 0 && blockIdx.y == 0) {
     __syncthreads();                                    // the tile is stored; sA is free
     double* scr = &sA[0][0];
-    diag_block_body<4>(Wz + (int64_t)r0 * ldw + r0, ldw, next.pb, p, pinv,
+    diag_block_body<8>(Wz + (int64_t)r0 * ldw + r0, ldw, next.pb, p, pinv,
                        next.piv + (int64_t)z * next.piv_stride, r0, next.flags + z,
                        next.Linv + (int64_t)z * 1024, next.Uinv + (int64_t)z * 1024, scr, scr + 256);
   }
@@ -955,7 +926,7 @@ hipError_t launch_diag_block(int32_t* W, int64_t ldw, int64_t slab, int j0, int 
                              const Modulus* mods, int32_t* piv, int64_t piv_stride, int32_t* flags,
                              int32_t* Linv, int32_t* Uinv, int nitems, hipStream_t st) {
   if (pb < 1 || pb > 32 || !Linv || !Uinv) return hipErrorInvalidValue;
-  k_diag_block<<<nitems, 256, 0, st>>>(W, ldw, slab, j0, pb, mods, piv, piv_stride, flags, Linv, Uinv);
+  k_diag_block<<<nitems, 512, 0, st>>>(W, ldw, slab, j0, pb, mods, piv, piv_stride, flags, Linv, Uinv);
   LAUNCH_CHECK();
   return hipSuccess;
 }
@@ -1014,7 +985,7 @@ hipError_t launch_lu_update(int32_t* W, int64_t slab, int64_t ldw, int j0, int p
                       next_Linv == Linv || next_Uinv == Uinv))
     return hipErrorInvalidValue;
   const NextDiag nd{next_pb, next_Linv, next_Uinv, piv, piv_stride, flags};
-  k_lu_update<<<grid, 256, 0, st>>>(W, slab, ldw, j0, pb, M, N, Linv, ldt, Uinv, mods, kc4, cnt,
+  k_lu_update<<<grid, 512, 0, st>>>(W, slab, ldw, j0, pb, M, N, Linv, ldt, Uinv, mods, kc4, cnt,
                                     cnt_stride, nd);
   LAUNCH_CHECK();
   return hipSuccess;
