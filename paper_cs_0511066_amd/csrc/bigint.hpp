@@ -206,12 +206,49 @@ class BigInt {
   // words per result with 128-bit accumulation: terms of equal sign add as
   // magnitudes (below 2^128 with the carry), terms of opposite sign subtract
   // (below 2^127 in magnitude); a negative result is negated at the end.
+  // (x, y) <- (A x + B y, C x + D y) for |A|, |B|, |C|, |D| < 2^62, in place
+  // and in one pass: limb i of both results needs only limb i of x and y
+  // and the running carries (two's complement, 128-bit: |a x_i + b y_i| <
+  // 2^127), so each is written over the inputs' limb i.
   static void lincomb2(BigInt& x, BigInt& y, int64_t A, int64_t B, int64_t C, int64_t D) {
-    BigInt nx = combine(x, A, y, B), ny = combine(x, C, y, D);
-    x.mag.swap(nx.mag);
-    x.sign = nx.sign;
-    y.mag.swap(ny.mag);
-    y.sign = ny.sign;
+    const int64_t a = x.sign < 0 ? -A : A, b = y.sign < 0 ? -B : B;
+    const int64_t c = x.sign < 0 ? -C : C, d = y.sign < 0 ? -D : D;
+    const size_t n = std::max(x.mag.size(), y.mag.size());
+    x.mag.resize(n + 1, 0);
+    y.mag.resize(n + 1, 0);
+    uint64_t* xm = x.mag.data();
+    uint64_t* ym = y.mag.data();
+    __int128 c1 = 0, c2 = 0;
+    for (size_t i = 0; i < n; i++) {
+      const uint64_t xi = xm[i], yi = ym[i];
+      // signed x unsigned products, split so that each partial sum fits
+      const __int128 t1 = (__int128)a * (__int128)(u128)xi + (__int128)b * (__int128)(u128)yi + c1;
+      const __int128 t2 = (__int128)c * (__int128)(u128)xi + (__int128)d * (__int128)(u128)yi + c2;
+      xm[i] = (uint64_t)t1;
+      ym[i] = (uint64_t)t2;
+      c1 = t1 >> 64;
+      c2 = t2 >> 64;
+    }
+    // the carries are below 2^63 in magnitude: one more limb each, and the
+    // sign of the result is the sign of that limb
+    xm[n] = (uint64_t)c1;
+    ym[n] = (uint64_t)c2;
+    finish_twos(x, c1 < 0);
+    finish_twos(y, c2 < 0);
+  }
+  // x.mag holds a two's complement value (its top limb gives the sign):
+  // back to sign and magnitude
+  static void finish_twos(BigInt& x, bool neg) {
+    if (neg) {
+      uint64_t cy = 1;
+      for (auto& w : x.mag) {
+        const u128 t = (u128)(~w) + cy;
+        w = (uint64_t)t;
+        cy = (uint64_t)(t >> 64);
+      }
+    }
+    x.sign = neg ? -1 : 1;
+    x.trim();
   }
   static BigInt combine(const BigInt& x, int64_t a, const BigInt& y, int64_t b) {
     const int sa = x.sign * (a < 0 ? -1 : a > 0 ? 1 : 0);

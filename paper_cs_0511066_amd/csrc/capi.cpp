@@ -14,6 +14,7 @@
 #include <atomic>
 #include <chrono>
 #include <exception>
+#include <functional>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -312,13 +313,9 @@ det_status inverse_from_lu(det_ctx* c, LuWs& w, const LuJob& J, int64_t* col_out
   const int kc4 = std::max(1, exact_chunk(J.pmax) / 4);
   const int64_t offV = 2 * (int64_t)n, offS = 3 * (int64_t)n;
   int32_t* W = (int32_t*)w.W.p;
-  const int nrep = (n + 63) / 64;
-  TRY(ensure(c, w.modsr, (size_t)nrep * sizeof(Modulus), w.st));
-  HIPCHK(hipMemcpyAsync(w.modsr.p, w.hmods.p, (size_t)nrep * sizeof(Modulus),
-                        hipMemcpyHostToDevice, w.st));
+  // (w.modsr holds the modulus once per batched pair and the region V is
+  // zero: both were set before the factorisation)
   const Modulus* mr = (const Modulus*)w.modsr.p;
-  HIPCHK(hipMemset2DAsync(W + offV, ldw * sizeof(int32_t), 0, (size_t)n * sizeof(int32_t), n,
-                          w.st));
   HIPCHK(detk::launch_place_diag(W, ldw, offV, n, (const int32_t*)w.uinv.p, w.st));
   for (int64_t b = 32; b < n; b *= 2) {
     const int64_t npairs = ((n + b - 1) / b) / 2;
@@ -546,6 +543,14 @@ det_status inverse_mod_p(det_ctx* c, const int64_t* dA, int64_t dlda, int n, uin
   TRY(ensure(c, w.mods, sizeof(Modulus), w.st));
   TRY(ensure(c, c->Cu, (size_t)n * n * sizeof(uint32_t)));
   HIPCHK(hipMemcpyAsync(w.mods.p, hm, sizeof(Modulus), hipMemcpyHostToDevice, w.st));
+  if (fast) {
+    // for inverse_from_lu, ahead of the factorisation (the LU of [A | I]
+    // touches columns [0, 2n) only): the modulus once per batched pair of
+    // diagonal blocks, and V = columns [2n, 3n) cleared
+    TRY(ensure(c, w.modsr, (size_t)nrep * sizeof(Modulus), w.st));
+    HIPCHK(hipMemcpyAsync(w.modsr.p, hm, (size_t)nrep * sizeof(Modulus), hipMemcpyHostToDevice,
+                          w.st));
+  }
   std::vector<Panel> panels;
   int32_t* flag = (int32_t*)c->hres;
   // first with pivots searched inside each diagonal block only (the panels
@@ -559,6 +564,9 @@ det_status inverse_mod_p(det_ctx* c, const int64_t* dA, int64_t dlda, int n, uin
     HIPCHK(hipMemsetAsync(w.flags.p, 0, sizeof(int32_t), w.st));
     HIPCHK(detk::launch_residues(dA, dlda, n, 2 * n, (int32_t*)w.W.p, J.ldw, J.slab,
                                  (const Modulus*)w.mods.p, 1, w.st));
+    if (fast)
+      HIPCHK(hipMemset2DAsync((int32_t*)w.W.p + 2 * (int64_t)n, J.ldw * sizeof(int32_t), 0,
+                              (size_t)n * sizeof(int32_t), n, w.st));
     TRY(lu_factor(c, w, J, true, &panels, block_pivots));
     HIPCHK(hipMemcpyAsync(flag, w.flags.p, sizeof(int32_t), hipMemcpyDeviceToHost, w.st));
     if (block_pivots && deferred) {
@@ -598,6 +606,11 @@ Stage stage_layout(int64_t n, int64_t k) {
   return s;
 }
 
+// Called by a lifting once its preparation (Hensel planes, staging) is
+// queued and before the lifting itself is launched; setting *skip ends the
+// lifting there (nothing launched after the preparation).
+typedef std::function<det_status(bool*)> PreLaunch;
+
 // The FP64 three-digit lifting is exact for p < 2^25 and n ||A|| p < 2^53.
 bool lift3_applies(int n, double amax, uint32_t p) {
   return p < (1u << 25) && (double)n * std::max(amax, 1.0) * (double)p < ldexp(1.0, 53);
@@ -621,7 +634,8 @@ det_status pack_matrix(det_ctx* c, const int64_t* dA, int64_t dlda, int n) {
 det_status lift3_multi(det_ctx* c, int grid3, const int64_t* dA, int64_t dlda, int n,
                        const int64_t* B, int m, uint32_t p, int64_t k, uint32_t* digits_dev,
                        const uint32_t* cvec_dev, uint64_t* comb_dev, bool after_own2,
-                       int ncv = 1, const int** err_pending = nullptr) {
+                       int ncv = 1, const int** err_pending = nullptr,
+                       const PreLaunch* pre = nullptr) {
   constexpr int MR = detk::LIFT3_MAX_RHS;
   const double nn = (double)n * n;
   TRY(pack_matrix(c, dA, dlda, n));
@@ -674,6 +688,11 @@ det_status lift3_multi(det_ctx* c, int grid3, const int64_t* dA, int64_t dlda, i
   HIPCHK(detk::launch_hensel_f64((const int32_t*)c->Ai.p, (const uint32_t*)c->Cu.p,
                                  (double*)c->Ed.p, (uint32_t*)c->C1.p, (uint32_t*)c->C2.p, n, p,
                                  c->st));
+  if (pre) {
+    bool skip = false;
+    TRY((*pre)(&skip));
+    if (skip) return DET_OK;
+  }
   if (after_own2) {
     HIPCHK(hipEventRecord(c->ev, c->own2));
     HIPCHK(hipStreamWaitEvent(c->st, c->ev, 0));
@@ -729,12 +748,17 @@ det_status lift3_multi(det_ctx* c, int grid3, const int64_t* dA, int64_t dlda, i
 det_status lift(det_ctx* c, const int64_t* dA, int64_t dlda, int n, double amax, const int64_t* b,
                 uint32_t p, int64_t k, uint32_t* digits_dev, const uint32_t* cvec_dev,
                 uint64_t* comb_dev, bool after_own2 = false,
-                const int** err_pending = nullptr) {
+                const int** err_pending = nullptr, const PreLaunch* pre = nullptr) {
   if (err_pending) *err_pending = nullptr;
   const int grid3 = c->lift_mode == 0 && lift3_applies(n, amax, p) ? detk::lift3_grid(c->device, n) : 0;
   if (grid3 > 0)      // lifting modulo p^3 in FP64: Hensel planes, then three digits a step
     return lift3_multi(c, grid3, dA, dlda, n, b, 1, p, k, digits_dev, cvec_dev, comb_dev,
-                       after_own2, 1, err_pending);
+                       after_own2, 1, err_pending, pre);
+  if (pre) {
+    bool skip = false;
+    TRY((*pre)(&skip));
+    if (skip) return DET_OK;
+  }
   TRY(pack_matrix(c, dA, dlda, n));
   // rp and x are padded with zeros to lift_pad(n) entries (the
   // register-resident kernel loads 64 EPL entries without bounds tests)
@@ -1360,8 +1384,32 @@ det_status det_introspective(det_ctx* c, const int64_t* A, int64_t n, int64_t ld
             for (int64_t j = 0; j < n; j++)
               R[(size_t)a * npad + j] = 1 + (uint32_t)(dethost::splitmix64(rng) % 65535u);
           const int* lift_err = nullptr;
+          // Before the first lifting is launched (its preparation queued),
+          // the background batch is taken: with the adaptive loop, when its
+          // residues already end the CRA on det itself (K = 1: early
+          // termination, Alg. 2.1, or the bound 2H), no solving is needed
+          // and none is launched (Alg. 4.1 stops when the CRA has
+          // terminated).  The host has then waited for the batch, so the
+          // lifting need not wait for its stream.
+          bool cra_done_first = false;
+          const PreLaunch pre = [&](bool* skip) -> det_status {
+            TRY(take_batch1());
+            batch1_taken = true;
+            if (o.adaptive && K.cmp(BigInt::from_i64(1)) == 0) {
+              restart_crt();
+              const double th = now_ms();
+              feed(0);
+              t_host += now_ms() - th;
+              if (done) *skip = cra_done_first = true;
+            }
+            return DET_OK;
+          };
           TRY(lift(c, dA, dlda, (int)n, bd.amax, b.data(), p, k, dig + (size_t)(i - 1) * k * n,
-                   nullptr, nullptr, !batch1_taken, &lift_err));
+                   nullptr, nullptr, false, &lift_err, batch1_taken ? nullptr : &pre));
+          if (cra_done_first) {
+            HIPCHK(hipStreamSynchronize(c->st));    // (the queued preparation ends)
+            break;
+          }
           HIPCHK(hipMemcpyAsync(c->cvec.p, R.data(), (size_t)i * npad * sizeof(uint32_t),
                                 hipMemcpyHostToDevice, c->st));
           for (int h = 0; h < i; h++)

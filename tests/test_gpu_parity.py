@@ -475,6 +475,20 @@ def test_det_introspective_structured_serving_matrices(ctx):
         assert d == oracle.det_bareiss_c(A)
 
 
+def test_det_introspective_small_det_needs_no_solving(ctx):
+    """Alg. 4.1 stops once the CRA has terminated: for a matrix whose
+    determinant is small (U diag(s) V, |det| < 2^16), the residues of the
+    first background batch already end the CRA on det itself (K = 1), so the
+    adaptive loop launches no lifting; with the loop off the solving runs.
+    The determinant is exact either way."""
+    A, sign, s = synth.structured_serving(300, 7)
+    d, rep = ctx.det_introspective(A, report=True)
+    assert d == sign * math.prod(s) == oracle.det_bareiss_c(A)
+    assert rep["solvings"] == 0 and rep["lifting_steps"] == 0 and rep["early_terminated"] == 1, rep
+    d2, rep2 = ctx.det_introspective(A, adaptive=False, report=True)
+    assert d2 == d and rep2["solvings"] == 1 and rep2["lifting_steps"] > 0, rep2
+
+
 @pytest.mark.parametrize("n,lo,hi", [(128, -128, 127), (200, -1000, 1000), (256, 0, 255)])
 def test_det_introspective_mid_sizes(ctx, n, lo, hi):
     A = synth.dense_uniform(n, lo, hi, n)
