@@ -216,25 +216,42 @@ class BigInt {
     const size_t n = std::max(x.mag.size(), y.mag.size());
     x.mag.resize(n + 1, 0);
     y.mag.resize(n + 1, 0);
-    uint64_t* xm = x.mag.data();
-    uint64_t* ym = y.mag.data();
+    // the signs of the four coefficients select one of 16 loops, so that
+    // every product is one unsigned 64 x 64 -> 128 multiplication
+    const int sel = (a < 0) << 3 | (b < 0) << 2 | (c < 0) << 1 | (d < 0);
+    const uint64_t ma = mag64(a), mb = mag64(b), mc = mag64(c), md = mag64(d);
     __int128 c1 = 0, c2 = 0;
+    switch (sel) {
+#define LC_CASE(k) \
+      case k: lc_loop<(k >> 3) & 1, (k >> 2) & 1, (k >> 1) & 1, k & 1>(x.mag.data(), y.mag.data(), n, ma, mb, mc, md, c1, c2); break;
+      LC_CASE(0) LC_CASE(1) LC_CASE(2) LC_CASE(3) LC_CASE(4) LC_CASE(5) LC_CASE(6) LC_CASE(7)
+      LC_CASE(8) LC_CASE(9) LC_CASE(10) LC_CASE(11) LC_CASE(12) LC_CASE(13) LC_CASE(14) LC_CASE(15)
+#undef LC_CASE
+    }
+    // the carries are below 2^63 in magnitude: one more limb each, and the
+    // sign of the result is the sign of that limb
+    x.mag[n] = (uint64_t)c1;
+    y.mag[n] = (uint64_t)c2;
+    finish_twos(x, c1 < 0);
+    finish_twos(y, c2 < 0);
+  }
+  static uint64_t mag64(int64_t v) { return v < 0 ? (uint64_t)0 - (uint64_t)v : (uint64_t)v; }
+  template <bool NA, bool NB, bool NC, bool ND>
+  static void lc_loop(uint64_t* xm, uint64_t* ym, size_t n, uint64_t ma, uint64_t mb, uint64_t mc,
+                      uint64_t md, __int128& c1, __int128& c2) {
     for (size_t i = 0; i < n; i++) {
       const uint64_t xi = xm[i], yi = ym[i];
-      // signed x unsigned products, split so that each partial sum fits
-      const __int128 t1 = (__int128)a * (__int128)(u128)xi + (__int128)b * (__int128)(u128)yi + c1;
-      const __int128 t2 = (__int128)c * (__int128)(u128)xi + (__int128)d * (__int128)(u128)yi + c2;
+      // |coefficient| < 2^62: each product is below 2^126, and so is their
+      // signed sum plus the carry, which fits a signed 128-bit word
+      const __int128 pa = (__int128)((u128)xi * ma), pb = (__int128)((u128)yi * mb);
+      const __int128 pc = (__int128)((u128)xi * mc), pd = (__int128)((u128)yi * md);
+      const __int128 t1 = (NA ? -pa : pa) + (NB ? -pb : pb) + c1;
+      const __int128 t2 = (NC ? -pc : pc) + (ND ? -pd : pd) + c2;
       xm[i] = (uint64_t)t1;
       ym[i] = (uint64_t)t2;
       c1 = t1 >> 64;
       c2 = t2 >> 64;
     }
-    // the carries are below 2^63 in magnitude: one more limb each, and the
-    // sign of the result is the sign of that limb
-    xm[n] = (uint64_t)c1;
-    ym[n] = (uint64_t)c2;
-    finish_twos(x, c1 < 0);
-    finish_twos(y, c2 < 0);
   }
   // x.mag holds a two's complement value (its top limb gives the sign):
   // back to sign and magnitude

@@ -64,22 +64,20 @@ __global__ __launch_bounds__(512) void k_panel(int32_t* __restrict__ W, int64_t 
 }
 
 // ------------------------------------------------------------------ K2': diagonal block
-// One 512-thread workgroup per item factors the pb x pb diagonal block at
+// One two-wave workgroup per item factors the pb x pb diagonal block at
 // (j0, j0) without a pivot search below it (diag_block_body, panel.hpp), for
 // an LU whose update forms L21 itself (k_lu_update with Uinv).
-__global__ __launch_bounds__(512) void k_diag_block(int32_t* __restrict__ W, int64_t ldw,
+__global__ __launch_bounds__(128) void k_diag_block(int32_t* __restrict__ W, int64_t ldw,
                                                     int64_t slab, int j0, int pb,
                                                     const Modulus* __restrict__ mods,
                                                     int32_t* __restrict__ piv, int64_t piv_stride,
                                                     int32_t* __restrict__ flags,
                                                     int32_t* __restrict__ Linv,
                                                     int32_t* __restrict__ Uinv) {
-  __shared__ double sRow[256];
-  __shared__ double sV[96];
   const int z = blockIdx.x;
-  diag_block_body<8>(W + (int64_t)z * slab + (int64_t)j0 * ldw + j0, ldw, pb, mods[z].p,
-                     mods[z].pinv, piv + (int64_t)z * piv_stride, j0, flags + z,
-                     Linv + (int64_t)z * 1024, Uinv + (int64_t)z * 1024, sRow, sV);
+  diag_block_body(W + (int64_t)z * slab + (int64_t)j0 * ldw + j0, ldw, pb, mods[z].p,
+                  mods[z].pinv, piv + (int64_t)z * piv_stride, j0, flags + z,
+                  Linv + (int64_t)z * 1024, Uinv + (int64_t)z * 1024);
 }
 
 // ------------------------------------------------------------------ K3: row swaps
@@ -494,11 +492,10 @@ __global__ __launch_bounds__(512) void k_lu_update(int32_t* __restrict__ W, int6
             (int32_t)mod_c((double)vc[i][r] - mod_c(acc[i][r], p, pinv), p, pinv);
     }
   if (next.pb > 0 && blockIdx.x == 0 && blockIdx.y == 0) {
-    __syncthreads();                                    // the tile is stored; sA is free
-    double* scr = &sA[0][0];
-    diag_block_body<8>(Wz + (int64_t)r0 * ldw + r0, ldw, next.pb, p, pinv,
-                       next.piv + (int64_t)z * next.piv_stride, r0, next.flags + z,
-                       next.Linv + (int64_t)z * 1024, next.Uinv + (int64_t)z * 1024, scr, scr + 256);
+    __syncthreads();                                    // the tile is stored
+    diag_block_body(Wz + (int64_t)r0 * ldw + r0, ldw, next.pb, p, pinv,
+                    next.piv + (int64_t)z * next.piv_stride, r0, next.flags + z,
+                    next.Linv + (int64_t)z * 1024, next.Uinv + (int64_t)z * 1024);
   }
 }
 
@@ -926,7 +923,7 @@ hipError_t launch_diag_block(int32_t* W, int64_t ldw, int64_t slab, int j0, int 
                              const Modulus* mods, int32_t* piv, int64_t piv_stride, int32_t* flags,
                              int32_t* Linv, int32_t* Uinv, int nitems, hipStream_t st) {
   if (pb < 1 || pb > 32 || !Linv || !Uinv) return hipErrorInvalidValue;
-  k_diag_block<<<nitems, 512, 0, st>>>(W, ldw, slab, j0, pb, mods, piv, piv_stride, flags, Linv, Uinv);
+  k_diag_block<<<nitems, 128, 0, st>>>(W, ldw, slab, j0, pb, mods, piv, piv_stride, flags, Linv, Uinv);
   LAUNCH_CHECK();
   return hipSuccess;
 }

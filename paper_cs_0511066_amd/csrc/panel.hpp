@@ -469,177 +469,116 @@ __device__ __forceinline__ void panel_body(int32_t* __restrict__ Wr, int64_t ldw
 
 // ------------------------------------------------------------------ diagonal block body
 // Factors the pb x pb diagonal block (pb <= 32) whose top-left entry is Wb
-// (leading dimension ldw) without a pivot search below it, with a workgroup of
-// NW waves (row i of the block belongs to wave i % NW).  Two eliminations run
-// side by side, in step: [A11 | I] and [A11^T | I] (32 + 32 columns, column c
-// of both is lane c of every wave; a block narrower than 32 is padded with the
-// identity).  A fraction-free elimination, row_i <- b_k row_i - r_ik row_k
-// for i > k with b_k = the pivot-column entry of row k, leaves row i scaled
-// by sigma_i = b_0 ... b_{i-1}, so no inverse is needed inside the loop:
+// (leading dimension ldw) without a pivot search below it.  Two eliminations
+// of a 32 x 64 block run side by side, each held whole by one wave (lane c =
+// column c, X[i] = row i, so a step needs no exchange between waves and no
+// barrier): [A11 | I] in wave 0 and [A11^T | I] in wave 1 (a block narrower
+// than 32 is padded with the identity).  A fraction-free elimination, row_i
+// <- b_k row_i - r_ik row_k for i > k with b_k = the pivot-column entry of
+// row k, leaves row i scaled by sigma_i = b_0 ... b_{i-1}, so no inverse is
+// needed inside the loop:
 //  - [A11 | I] gives [U | L^{-1}] row by row after the scaling 1 / sigma_i;
 //  - A11^T = L_T U_T with L_T = U'^T and U_T = D L^T (U = D U', D =
-//    diag(u_ii), U' unit upper), whose pivots, and so whose sigma_i, are
-//    those of A11; [A11^T | I] gives L_T^{-1} = (U'^{-1})^T after the same
-//    scaling, and U^{-1} = U'^{-1} D^{-1}, i.e. U^{-1}[c][i] = L_T^{-1}[i][c]
-//    / u_ii.
-// All 1 / sigma_i come from one Fermat ladder: with prefix products
-// P_k = b_0 ... b_k and suffix products S_k = b_k ... b_31 (scans across the
-// lanes of wave 0), sigma_i = P_{i-1} and 1 / sigma_i = S_i / P_31; 1 / u_ii =
-// sigma_i / b_i.  The pivot rows of each step reach the other waves through
-// LDS (sRow: 2 x 128 doubles, alternating, so one barrier a step).
+//    diag(u_ii), U' unit upper), whose pivots, and so whose b_i, are those of
+//    A11; [A11^T | I] gives L_T^{-1} = (U'^{-1})^T after the scaling
+//    1 / sigma_i, and U^{-1} = U'^{-1} D^{-1} with u_ii = b_i / sigma_i, so
+//    U^{-1}[c][i] = (row i of the second elimination)[c] / b_i.
+// The 32 inverses a wave needs (1 / sigma_i in wave 0, 1 / b_i in wave 1)
+// come from one Fermat ladder run by the 32 lanes side by side; sigma_i is
+// the running product of the pivots, kept beside the elimination.
 // Outputs: U11 into the block (on and above the diagonal), L11^{-1} and
 // U11^{-1} dense 32 x 32 row-major at Lz, Uz (zero outside pb x pb),
 // piv_z[j0 + i] = j0 + i, *flag = 1 when a pivot is 0 mod p (the caller then
 // runs the full pivot search).  Values stay below (p + 9) / 2 in magnitude
-// through the loose reductions, so every product is below 2^52.
-__device__ __forceinline__ double shfl_up_dd(double x, int d) {
-  const long long b = __builtin_bit_cast(long long, x);
-  const int lo = __shfl_up((int)b, d, 64), hi = __shfl_up((int)(b >> 32), d, 64);
-  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
-}
-__device__ __forceinline__ double shfl_down_dd(double x, int d) {
-  const long long b = __builtin_bit_cast(long long, x);
-  const int lo = __shfl_down((int)b, d, 64), hi = __shfl_down((int)(b >> 32), d, 64);
-  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+// through the loose reductions, so every product is below 2^52.  Waves 2 and
+// up of the workgroup do nothing here, and no LDS is used.
+
+// Step K of the fraction-free elimination of the 32 x 64 block X (lane =
+// column), then the steps after it (a compile-time recursion, so that every
+// row index is a register): the rows below the pivot in groups of G, each
+// phase over the group before the next, so that independent FP64 chains fill
+// the pipeline of the one wave that runs them.
+template <int K, int G>
+__device__ __forceinline__ void diag_elim_step(double (&X)[32], double& S, double& sig,
+                                               double& bl, bool& zero, int lane, double p,
+                                               double pinv) {
+  if constexpr (K < 32) {
+    constexpr double RND = 6755399441055744.0;
+    const double braw = readlane_d(X[K], K);
+    zero |= braw == 0.0;
+    const double bk = braw == 0.0 ? 1.0 : braw;      // (the result is discarded then)
+    sig = lane == K ? S : sig;                       // sigma_K = b_0 ... b_{K-1}
+    bl = lane == K ? bk : bl;
+    S = mul_mod_loose(S, bk, p, pinv);
+    const double xk = X[K];
+#pragma unroll
+    for (int i0 = K + 1; i0 < 32; i0 += G) {
+      double x[G], q[G];
+#pragma unroll
+      for (int j = 0; j < G; j++)
+        if (i0 + j < 32) x[j] = -readlane_d(X[i0 + j], K) * xk;
+#pragma unroll
+      for (int j = 0; j < G; j++)
+        if (i0 + j < 32) x[j] = fma(bk, X[i0 + j], x[j]);
+#pragma unroll
+      for (int j = 0; j < G; j++)
+        if (i0 + j < 32) q[j] = fma(x[j], pinv, RND);
+#pragma unroll
+      for (int j = 0; j < G; j++)
+        if (i0 + j < 32) q[j] = q[j] - RND;
+#pragma unroll
+      for (int j = 0; j < G; j++)
+        if (i0 + j < 32) X[i0 + j] = fma(-q[j], p, x[j]);
+    }
+    diag_elim_step<K + 1, G>(X, S, sig, bl, zero, lane, p, pinv);
+  }
 }
 
-// mod_loose on R independent values, one phase at a time (see modp.hpp), so
-// that a wave alone on its SIMD overlaps their dependent FP64 chains.
-template <int R>
-__device__ __forceinline__ void mod_loose_rows(double (&x)[R], double p, double pinv) {
-  constexpr double RND = 6755399441055744.0;
-  double q[R];
-#pragma unroll
-  for (int i = 0; i < R; i++) q[i] = fma(x[i], pinv, RND);
-#pragma unroll
-  for (int i = 0; i < R; i++) q[i] = q[i] - RND;
-#pragma unroll
-  for (int i = 0; i < R; i++) x[i] = fma(-q[i], p, x[i]);
-}
-
-// LDS: sRow 256 doubles, sV 96 doubles.
-template <int NW>
 __device__ __forceinline__ void diag_block_body(int32_t* __restrict__ Wb, int64_t ldw, int pb,
                                                 double p, double pinv, int32_t* __restrict__ piv_z,
                                                 int j0, int32_t* __restrict__ flag,
-                                                int32_t* __restrict__ Lz, int32_t* __restrict__ Uz,
-                                                double* sRow, double* sV) {
-  constexpr int RW = 32 / NW;
-  static_assert(32 % NW == 0, "waves");
+                                                int32_t* __restrict__ Lz, int32_t* __restrict__ Uz) {
   const int t = threadIdx.x;
   const int c = t & 63, w = t >> 6;
+  if (w >= 2) return;
+  const bool tr = w == 1;                            // the transposed elimination
+  const int cl = c & 31;
   const uint32_t e_inv = (uint32_t)__builtin_amdgcn_readfirstlane((int)((uint32_t)p - 2u));
-  double F[RW], G[RW];                           // rows of [A11 | I] and of [A11^T | I]
-  if (w < NW) {
+  double X[32];
+  {
     // every load is issued before any is used (clamped indices stay inside
     // the pb x pb block; the padding is selected afterwards)
-    int32_t v[RW], u[RW];
-    const int cc = min(c & 31, pb - 1);
+    int32_t v[32];
+    const int cc = min(cl, pb - 1);
 #pragma unroll
-    for (int q = 0; q < RW; q++) {
-      const int ii = min(w + NW * q, pb - 1);
-      v[q] = Wb[(int64_t)ii * ldw + cc];
-      u[q] = Wb[(int64_t)cc * ldw + ii];
+    for (int i = 0; i < 32; i++) {
+      const int ii = min(i, pb - 1);
+      v[i] = Wb[tr ? (int64_t)cc * ldw + ii : (int64_t)ii * ldw + cc];
     }
 #pragma unroll
-    for (int q = 0; q < RW; q++) {
-      const int i = w + NW * q;
-      if (c < 32) {
-        const bool in = i < pb && c < pb;
-        F[q] = in ? (double)v[q] : (i == c ? 1.0 : 0.0);
-        G[q] = in ? (double)u[q] : (i == c ? 1.0 : 0.0);
-      } else {
-        F[q] = G[q] = (i == c - 32) ? 1.0 : 0.0;
-      }
+    for (int i = 0; i < 32; i++) {
+      const bool in = c < 32 && i < pb && c < pb;
+      const bool one = cl == i && (c >= 32 || i >= pb);
+      X[i] = in ? (double)v[i] : (one ? 1.0 : 0.0);
     }
   }
+  double S = 1.0, sig = 1.0, bl = 1.0;
   bool zero = false;
-  // ---- the two fraction-free eliminations
-  for (int k = 0; k < 32; k++) {
-    double* rowF = sRow + (k & 1) * 128;
-    double* rowG = rowF + 64;
-    if (w == k % NW) {
-      const int oq = k / NW;
-      double a = 0.0, b = 0.0;
+  diag_elim_step<0, 8>(X, S, sig, bl, zero, cl, p, pinv);
+  // lane c: 1 / sigma_c (wave 0) or 1 / b_c (wave 1)
+  const double y = pow_mod_fixed(tr ? bl : sig, e_inv, p, pinv);
 #pragma unroll
-      for (int q = 0; q < RW; q++) {
-        a = q == oq ? F[q] : a;
-        b = q == oq ? G[q] : b;
-      }
-      rowF[c] = a;
-      rowG[c] = b;
-    }
-    __syncthreads();
-    const double fk = rowF[c], gk = rowG[c];
-    const double braw = rowF[k], graw = rowG[k];
-    zero |= braw == 0.0;
-    const double bk = braw == 0.0 ? 1.0 : braw;      // (the result is discarded then)
-    const double bg = graw == 0.0 ? 1.0 : graw;
-    if (t == 0) sV[k] = bk;
-    if (w < NW) {
-      // the rows of a wave are independent: each phase runs over all of them
-      // before the next
-      double x[RW], y[RW];
+  for (int i = 0; i < 32; i++) X[i] = mul_mod(X[i], readlane_d(y, i), p, pinv);
+  // wave 0: row i of U (lanes below 32, on and above the diagonal) and of
+  // L^{-1} (lanes 32 and up); wave 1: column i of U^{-1} (lanes 32 and up)
+  const int cc = c - 32;
+  int32_t* const base = tr ? Uz + cc * 32 : (c < 32 ? Wb + c : Lz + cc);
+  const int64_t step = tr ? 1 : (c < 32 ? ldw : 32);
 #pragma unroll
-      for (int q = 0; q < RW; q++) {
-        x[q] = -readlane_d(F[q], k) * fk;
-        y[q] = -readlane_d(G[q], k) * gk;
-      }
-#pragma unroll
-      for (int q = 0; q < RW; q++) {
-        x[q] = fma(bk, F[q], x[q]);
-        y[q] = fma(bg, G[q], y[q]);
-      }
-      mod_loose_rows<RW>(x, p, pinv);
-      mod_loose_rows<RW>(y, p, pinv);
-#pragma unroll
-      for (int q = 0; q < RW; q++) {
-        const bool act = w + NW * q > k;
-        F[q] = act ? x[q] : F[q];
-        G[q] = act ? y[q] : G[q];
-      }
-    }
-  }
-  __syncthreads();
-  // ---- 1 / sigma_i and 1 / u_ii (wave 0)
-  if (w == 0) {
-    const double bv = c < 32 ? sV[c] : 1.0;
-    double P = bv, S = bv;
-#pragma unroll
-    for (int d = 1; d < 32; d <<= 1) {
-      const double uu = shfl_up_dd(P, d), vv = shfl_down_dd(S, d);
-      if ((c & 31) >= d) P = mul_mod_loose(P, uu, p, pinv);
-      if ((c & 31) + d < 32) S = mul_mod_loose(S, vv, p, pinv);
-    }
-    P = mod_c(P, p, pinv);
-    S = mod_c(S, p, pinv);
-    const double Q = pow_mod_fixed(readlane_d(P, 31), e_inv, p, pinv);   // 1 / (b_0 ... b_31)
-    const double sinv = mul_mod(S, Q, p, pinv);                          // 1 / sigma_c
-    const double Pm1 = shfl_up_dd(P, 1), Sp1 = shfl_down_dd(S, 1);
-    const double sig = (c & 31) == 0 ? 1.0 : Pm1;                        // sigma_c
-    const double snext = (c & 31) == 31 ? 1.0 : Sp1;
-    const double binv = mul_mod(mul_mod(sig, snext, p, pinv), Q, p, pinv);   // 1 / b_c
-    if (c < 32) {
-      sV[32 + c] = sinv;
-      sV[64 + c] = mul_mod(sig, binv, p, pinv);                         // 1 / u_cc
-    }
-  }
-  __syncthreads();
-  if (w < NW) {
-#pragma unroll
-    for (int q = 0; q < RW; q++) {
-      const int i = w + NW * q;
-      const double si = sV[32 + i];
-      const double f = mul_mod(F[q], si, p, pinv);                      // [U | L^{-1}] row i
-      if (c < 32) {
-        if (c < pb && i <= c) Wb[(int64_t)i * ldw + c] = (int32_t)f;
-      } else {
-        const int cc = c - 32;
-        Lz[i * 32 + cc] = (i < pb && cc < pb) ? (int32_t)f : 0;
-        const double g = mul_mod(mul_mod(G[q], si, p, pinv), sV[64 + i], p, pinv);
-        Uz[cc * 32 + i] = (i < pb && cc < pb) ? (int32_t)g : 0;
-      }
-    }
+  for (int i = 0; i < 32; i++) {
+    const bool keep = c >= 32 ? (i < pb && cc < pb) : true;
+    const bool st = c >= 32 || (!tr && c < pb && i <= c);
+    if (st) base[(int64_t)i * step] = keep ? (int32_t)X[i] : 0;
   }
   if (t < pb) piv_z[j0 + t] = j0 + t;
   if (zero && t == 0) *flag = 1;
