@@ -140,6 +140,24 @@ det_status dixon_lift(det_ctx *ctx, const int64_t *A, int64_t n, int64_t lda, co
 det_status dixon_lift_multi(det_ctx *ctx, const int64_t *A, int64_t n, int64_t lda,
                             const int64_t *B, int64_t m, uint32_t p, int64_t k, uint32_t *digits);
 
+/*
+ * Several Dixon liftings side by side (Section 6: p-adic liftings with
+ * different primes in parallel, each with fewer iterations; their results
+ * meet by Chinese remaindering, as det_introspective does):
+ * digits[(z*k + i)*n + j] = x_i[j], the i-th base-p_z digit of A^{-1} b,
+ * for each of the np distinct primes p_z -- exactly what dixon_lift returns
+ * for p_z alone.  1 <= np <= 4; primes: host array; digits: host array of
+ * np*k*n entries, owned by the caller.  When the FP64 three-digit form
+ * applies to every prime (p_z < 2^25, n ||A|| p_z < 2^53, n <= 1024) and np
+ * of its grids fit on the device, the inverses come from one batched LU and
+ * the liftings share one launch (each prime its own workgroups); otherwise
+ * the primes are lifted one after the other.  Errors as dixon_lift, plus
+ * DET_E_INVALID for repeated primes.
+ */
+det_status dixon_lift_primes(det_ctx *ctx, const int64_t *A, int64_t n, int64_t lda,
+                             const int64_t *b, const uint32_t *primes, int64_t np, int64_t k,
+                             uint32_t *digits);
+
 typedef struct {
   double log2_inv_eps;   /* early termination: failure probability < 2^-log2_inv_eps (default 64) */
   int certify;           /* 1: ignore early termination; reconstruct det/s_n up to the Hadamard bound */
@@ -157,6 +175,12 @@ typedef struct {
                             when pi~_i = pi~_{i-1} or, by Section 5.3's rule, when
                             log2(pi~_i / pi~_{i-1}) <= (time(solving) / time(LU)) log2(l).
                             0: exactly n_rhs solvings, then the CRA on det/K */
+  int lift_primes;       /* liftings side by side (Section 6: several p-adic liftings in
+                            parallel, each with fewer steps, combined by Chinese remaindering):
+                            0 (default) picks the number, 1 .. 4 asks for at most that many.
+                            Applies to the three-digit lifting (n <= 1024); each solving then
+                            lifts modulo every one of the primes, to k digits each with
+                            prod p_z^k above the reconstruction bound */
 } det_opts;
 
 typedef struct {
@@ -176,6 +200,7 @@ typedef struct {
   int timing_switch;       /* 1 when Section 5.3's time rule ended the solvings */
   double t_solve_ms;       /* time of the last solving (lifting + reconstruction) */
   double t_lu_ms;          /* measured device time per modular determinant (batched) */
+  int64_t lift_primes;     /* primes lifted side by side in each solving */
 } det_report;
 
 /* Fill *opts with the defaults above. */

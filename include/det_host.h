@@ -61,20 +61,24 @@ det_status det_host_bigint(int op, int a_sign, const uint32_t *a, int64_t alen, 
 
 /* The extended bonus of Section 3.2 (Alg. 4.1 with m solvings) from the
  * p-adic expansions of the m x m combinations y[h][a] = R_a . x_h, with
- * x_h = A^{-1} b_h:  comb[(h*m + a)*k + i] = R_a . (digit i of x_h), so
- * y[h][a] = sum_{i<k} comb[..+i] p^i mod p^k (host array, m*m*k entries,
- * each < 2^64).  Every y[h][a] is rebuilt by rational reconstruction
+ * x_h = A^{-1} b_h, lifted modulo np distinct primes p_z (np = 1: one
+ * lifting; np > 1: liftings side by side, Section 6):
+ * comb[((h*m + a)*np + z)*k + i] = R_a . (digit i of x_h modulo p_z), so
+ * y[h][a] = sum_{i<k} comb[..+i] p_z^i mod p_z^k (host array, m*m*np*k
+ * entries, each < 2^64), and y[h][a] modulo P = prod_z p_z^k by Chinese
+ * remaindering.  Every y[h][a] is rebuilt by rational reconstruction
  * (|numerator| <= 2^Nbits, 0 < denominator <= 2^Dbits; needs
- * Nbits + Dbits + 1 < k log2 p).  Outputs, as magnitudes:
+ * Nbits + Dbits + 1 < log2 P).  Outputs, as magnitudes:
  *   s~  = lcm of the denominators found (a divisor of s_n),
  *   pi~ = s~^m / gcd(det(R N), s~^m) with R N = s~ (R_a . x_h), a divisor of
  *         s_n s_{n-1} ... s_{n-m+1};
  * *failed = number of combinations whose reconstruction failed (then pi~ = 1
- * and s~ covers only the others).  1 <= m <= 64. */
-det_status det_host_extended_bonus(const uint64_t* comb, int64_t m, int64_t k, uint32_t p,
-                                   int64_t Nbits, int64_t Dbits, uint32_t* s_mag, int64_t s_cap,
-                                   int64_t* s_len, uint32_t* pi_mag, int64_t pi_cap,
-                                   int64_t* pi_len, int64_t* failed);
+ * and s~ covers only the others).  1 <= m <= 64, 1 <= np <= 4. */
+det_status det_host_extended_bonus(const uint64_t* comb, int64_t m, int64_t k,
+                                   const uint32_t* primes, int64_t np, int64_t Nbits,
+                                   int64_t Dbits, uint32_t* s_mag, int64_t s_cap, int64_t* s_len,
+                                   uint32_t* pi_mag, int64_t pi_cap, int64_t* pi_len,
+                                   int64_t* failed);
 
 #ifdef __cplusplus
 }

@@ -57,7 +57,8 @@ class DetError(RuntimeError):
 
 class det_opts(ctypes.Structure):
     _fields_ = [("log2_inv_eps", c_double), ("certify", c_int), ("seed", c_u64),
-                ("n_rhs", c_int), ("prime_bits", c_int), ("path", c_int), ("adaptive", c_int)]
+                ("n_rhs", c_int), ("prime_bits", c_int), ("path", c_int), ("adaptive", c_int),
+                ("lift_primes", c_int)]
 
 
 class det_report(ctypes.Structure):
@@ -65,7 +66,7 @@ class det_report(ctypes.Structure):
                 ("et_rounds", c_i64), ("hadamard_bits", c_i64), ("early_terminated", c_int),
                 ("bonus_factors", c_int), ("t_lif_ms", c_double), ("t_cra_ms", c_double),
                 ("t_host_ms", c_double), ("solvings", c_i64), ("timing_switch", c_int),
-                ("t_solve_ms", c_double), ("t_lu_ms", c_double)]
+                ("t_solve_ms", c_double), ("t_lu_ms", c_double), ("lift_primes", c_i64)]
 
 
 def _sig(name, res, args):
@@ -87,6 +88,8 @@ _sig("dixon_lift", c_int, [ctypes.c_void_p, ctypes.c_void_p, c_i64, c_i64, P(c_i
                            P(c_u32)])
 _sig("dixon_lift_multi", c_int, [ctypes.c_void_p, ctypes.c_void_p, c_i64, c_i64, P(c_i64), c_i64,
                                  c_u32, c_i64, P(c_u32)])
+_sig("dixon_lift_primes", c_int, [ctypes.c_void_p, ctypes.c_void_p, c_i64, c_i64, P(c_i64), P(c_u32),
+                                  c_i64, c_i64, P(c_u32)])
 _sig("det_introspective", c_int, [ctypes.c_void_p, ctypes.c_void_p, c_i64, c_i64, P(det_opts),
                                   P(c_int), P(c_u32), c_i64, P(c_i64), P(det_report)])
 _sig("det_batch", c_int, [ctypes.c_void_p, c_i64, P(ctypes.c_void_p), P(c_i64), P(c_i64),
@@ -120,11 +123,13 @@ _sig("det_host_ratrecon", c_int, [P(c_u32), c_i64, P(c_u32), c_i64, c_i64, c_i64
                                   P(c_u32), c_i64, P(c_i64), P(c_u32), c_i64, P(c_i64)])
 _sig("det_host_bigint", c_int, [c_int, c_int, P(c_u32), c_i64, c_int, P(c_u32), c_i64, P(c_int),
                                 P(c_u32), c_i64, P(c_i64)])
-_sig("det_host_extended_bonus", c_int, [P(c_u64), c_i64, c_i64, c_u32, c_i64, c_i64, P(c_u32), c_i64,
-                                        P(c_i64), P(c_u32), c_i64, P(c_i64), P(c_i64)])
+_sig("det_host_extended_bonus", c_int, [P(c_u64), c_i64, c_i64, P(c_u32), c_i64, c_i64, c_i64,
+                                        P(c_u32), c_i64, P(c_i64), P(c_u32), c_i64, P(c_i64),
+                                        P(c_i64)])
 
 EXPORTED = ["det_ctx_create", "det_ctx_destroy", "det_ctx_set_stream", "det_status_str",
             "det_last_error", "det_opts_default", "det_mod_primes", "dixon_lift", "dixon_lift_multi",
+            "dixon_lift_primes",
             "det_introspective", "det_batch", "det_autotune", "det_autotune_read",
             "det_mod_primes_noalloc", "det_server_create", "det_server_submit", "det_server_poll",
             "det_server_stats", "det_server_destroy", "det_profile_select", "det_profile_read", "det_host_is_prime", "det_host_sample_primes",
@@ -279,14 +284,31 @@ class Context:
         del keep
         return out
 
+    def dixon_lift_primes(self, A, b, primes, k: int) -> np.ndarray:
+        """Digits of A^{-1} b mod p_z^k for several primes lifted side by side
+        (dixon_lift_primes): an np x k x n array."""
+        ptr, n, lda, keep = _matrix_arg(A)
+        bb = np.ascontiguousarray(np.asarray(b, dtype=np.int64))
+        if bb.shape != (n,):
+            raise ValueError("b must have n entries")
+        ps = np.ascontiguousarray(np.asarray(primes, dtype=np.uint32))
+        out = np.zeros((len(ps), k, n), dtype=np.uint32)
+        self._check(_lib.dixon_lift_primes(self._h, ptr, n, lda, _i64p(bb), _u32p(ps), len(ps), k,
+                                           _u32p(out)))
+        del keep
+        return out
+
     def det_introspective(self, A, certify: bool = False, seed: int | None = None,
                           log2_inv_eps: float | None = None, n_rhs: int | None = None,
                           prime_bits: int | None = None, path: str | None = None,
-                          adaptive: bool | None = None, report: bool = False):
+                          adaptive: bool | None = None, report: bool = False,
+                          lift_primes: int | None = None):
         ptr, n, lda, keep = _matrix_arg(A)
         o = det_opts()
         _lib.det_opts_default(ctypes.byref(o))
         o.certify = int(bool(certify))
+        if lift_primes is not None:
+            o.lift_primes = lift_primes
         if seed is not None:
             o.seed = seed
         if log2_inv_eps is not None:
@@ -559,18 +581,26 @@ def det_host_bigint(op: str, a: int, b: int) -> int:
     return _from_limbs(so.value, out[:ln.value])
 
 
-def det_host_extended_bonus(comb, p: int, Nbits: int, Dbits: int):
-    """(s~, pi~, failed) of the extended bonus from an m x m x k array of
-    combination digits comb[h, a, i] = R_a . (digit i of x_h)."""
-    cb = np.ascontiguousarray(np.asarray(comb, dtype=np.uint64))
-    if cb.ndim != 3 or cb.shape[0] != cb.shape[1]:
-        raise ValueError("comb must be m x m x k")
-    m, _, k = cb.shape
+def det_host_extended_bonus(comb, p, Nbits: int, Dbits: int):
+    """(s~, pi~, failed) of the extended bonus from the combination digits:
+    comb[h, a, i] = R_a . (digit i of x_h) for one prime p (an m x m x k
+    array), or comb[h, a, z, i] = R_a . (digit i of x_h mod p_z) for a list
+    of primes p (m x m x np x k), the liftings combined by Chinese
+    remaindering."""
+    cb = np.asarray(comb, dtype=np.uint64)
+    primes = [int(p)] if np.isscalar(p) else [int(q) for q in p]
+    if cb.ndim == 3:
+        cb = cb[:, :, None, :]
+    if cb.ndim != 4 or cb.shape[0] != cb.shape[1] or cb.shape[2] != len(primes):
+        raise ValueError("comb must be m x m x k (one prime) or m x m x np x k")
+    cb = np.ascontiguousarray(cb)
+    m, _, npr, k = cb.shape
+    ps = np.ascontiguousarray(np.asarray(primes, dtype=np.uint32))
     cap = int((Nbits + Dbits) * m // 32 + 8)
     sm, pm = np.zeros(cap, dtype=np.uint32), np.zeros(cap, dtype=np.uint32)
     sl, pl, failed = c_i64(0), c_i64(0), c_i64(0)
-    st = _lib.det_host_extended_bonus(cb.ctypes.data_as(P(c_u64)), m, k, p, Nbits, Dbits,
-                                      _u32p(sm), cap, ctypes.byref(sl), _u32p(pm), cap,
+    st = _lib.det_host_extended_bonus(cb.ctypes.data_as(P(c_u64)), m, k, _u32p(ps), npr, Nbits,
+                                      Dbits, _u32p(sm), cap, ctypes.byref(sl), _u32p(pm), cap,
                                       ctypes.byref(pl), ctypes.byref(failed))
     if st != DET_OK:
         raise DetError(st)

@@ -39,6 +39,8 @@ constexpr int MAX_N = 4096;
 // panel's own L11^{-1} serves the triangular solve); larger batches use outer
 // blocks of NB_OUTER columns so that the trailing update contracts over 128.
 constexpr int TWO_LEVEL_MIN_ITEMS = 64;
+// liftings side by side when det_opts.lift_primes is 0
+constexpr int LIFT_PRIMES_AUTO = 2;
 
 // Largest K such that K h^2 + h <= 2^53 with h = (pmax - 1)/2: FP64 sums of
 // that many products of centred residues are exact.
@@ -301,46 +303,45 @@ det_status back_substitute(det_ctx* c, LuWs& w, const LuJob& J, const std::vecto
 }
 
 // A^{-1} = U^{-1} (L^{-1} P) from the factored [A | I] when every panel is 32
-// wide, in a few launches: V = U^{-1} by recursive doubling over the diagonal
-// blocks (for a pair of blocks of size b, V12 = -V1 U12 V2, batched over the
-// pairs of a level: the pairs lie a fixed stride 2b (ldw + 1) apart), then
-// one product V (L^{-1} P).  Regions of W (ldw >= 4n): [0, n) L\U,
-// [n, 2n) L^{-1} P, [2n, 3n) V, [3n, 4n) scratch, then the inverse.
-// w.hmods must hold (n + 63) / 64 copies of the modulus.
+// wide, in a few launches for all items of the job: V = U^{-1} by recursive
+// doubling over the diagonal blocks (for a pair of blocks of size b, V12 =
+// -V1 U12 V2, batched over the pairs of a level and the items: the pairs lie
+// a fixed stride 2b (ldw + 1) apart), then one product V (L^{-1} P) per
+// item.  Regions of each item's slab (ldw >= 4n): [0, n) L\U, [n, 2n)
+// L^{-1} P, [2n, 3n) V (cleared before the factorisation), [3n, 4n) scratch,
+// then the inverse.
 det_status inverse_from_lu(det_ctx* c, LuWs& w, const LuJob& J, int64_t* col_out) {
-  const int n = J.n;
+  const int n = J.n, nit = J.nitems;
   const int64_t ldw = J.ldw;
   const int kc4 = std::max(1, exact_chunk(J.pmax) / 4);
   const int64_t offV = 2 * (int64_t)n, offS = 3 * (int64_t)n;
   int32_t* W = (int32_t*)w.W.p;
-  // (w.modsr holds the modulus once per batched pair and the region V is
-  // zero: both were set before the factorisation)
-  const Modulus* mr = (const Modulus*)w.modsr.p;
-  HIPCHK(detk::launch_place_diag(W, ldw, offV, n, (const int32_t*)w.uinv.p, w.st));
+  const Modulus* mods = (const Modulus*)w.mods.p;
+  HIPCHK(detk::launch_place_diag(W, J.slab, ldw, offV, n, (const int32_t*)w.uinv.p, nit, w.st));
   for (int64_t b = 32; b < n; b *= 2) {
     const int64_t npairs = ((n + b - 1) / b) / 2;
     int64_t nfull = 0;
     while (nfull < npairs && (2 * nfull + 2) * b <= n) nfull++;
-    // pairs i0 .. i0+cnt-1, right blocks of size r
+    // pairs i0 .. i0+cnt-1 of every item, right blocks of size r
     auto level = [&](int64_t i0, int64_t cnt, int64_t r) -> det_status {
       const int64_t rowL = 2 * i0 * b, rowR = rowL + b, stride = 2 * b * (ldw + 1);
-      ProfScope ps(c, DET_KERNEL_GEMM_F64, 12.0 * b * (b + 2.0 * r) * cnt,
-                   2.0 * b * r * (r + b) * cnt, w.st);
+      ProfScope ps(c, DET_KERNEL_GEMM_F64, 12.0 * b * (b + 2.0 * r) * cnt * nit,
+                   2.0 * b * r * (r + b) * cnt * nit, w.st);
       HIPCHK(detk::launch_gemm_mod(W, stride, rowL * ldw + offS + rowR, rowL * ldw + rowR,
-                                   rowR * ldw + offV + rowR, ldw, (int)b, (int)r, (int)r, mr, kc4,
-                                   2, false, (int)cnt, w.st));           // S = U12 V2
+                                   rowR * ldw + offV + rowR, ldw, (int)b, (int)r, (int)r, mods, kc4,
+                                   2, false, (int)cnt, w.st, nit, J.slab, true));   // S = U12 V2
       HIPCHK(detk::launch_gemm_mod(W, stride, rowL * ldw + offV + rowR, rowL * ldw + offV + rowL,
-                                   rowL * ldw + offS + rowR, ldw, (int)b, (int)r, (int)b, mr, kc4,
-                                   3, true, (int)cnt, w.st));            // V12 = -V1 S
+                                   rowL * ldw + offS + rowR, ldw, (int)b, (int)r, (int)b, mods, kc4,
+                                   3, true, (int)cnt, w.st, nit, J.slab, true));    // V12 = -V1 S
       return DET_OK;
     };
     if (nfull > 0) TRY(level(0, nfull, b));
     if (npairs > nfull) TRY(level(nfull, 1, n - (2 * nfull + 1) * b));
   }
   {
-    ProfScope ps(c, DET_KERNEL_GEMM_F64, 12.0 * (double)n * n, (double)n * n * n, w.st);
-    HIPCHK(detk::launch_gemm_mod(W, J.slab, offS, offV, n, ldw, n, n, n,
-                                 (const Modulus*)w.mods.p, kc4, 2, true, 1, w.st));
+    ProfScope ps(c, DET_KERNEL_GEMM_F64, 12.0 * (double)n * n * nit, (double)n * n * n * nit, w.st);
+    HIPCHK(detk::launch_gemm_mod(W, J.slab, offS, offV, n, ldw, n, n, n, mods, kc4, 2, true, nit,
+                                 w.st));
   }
   *col_out = offS;
   return DET_OK;
@@ -511,46 +512,42 @@ uint64_t inv_mod_2_64(uint64_t p) {
 // on workspace ws[0].  Returns DET_E_SINGULAR_MOD_P if p | det(A).
 det_status ensure_pinned(det_ctx* c, size_t count);
 
-// A^{-1} mod p into c->Cu by LU of [A | I] and back substitution.
+// A^{-1} mod p_z into c->Cu + z n^2 (canonical, n x n) for np primes at once
+// (np > 1 needs n <= 1024; the items of one batched LU of [A | I]), on
+// workspace ws[0].  Returns DET_E_SINGULAR_MOD_P if some p_z divides det(A).
 // With `deferred` (and the block pivot search on) only the block search runs
-// and nothing waits for it: the flag that says a block column had no non-zero
-// entry is copied to the pinned word *deferred, valid once the caller has
-// synchronised c->st; the caller then discards what it computed from c->Cu
-// and calls again without `deferred`.
-det_status inverse_mod_p(det_ctx* c, const int64_t* dA, int64_t dlda, int n, uint32_t p,
-                         const int32_t** deferred = nullptr) {
+// and nothing waits for it: the np flags that say a block column had no
+// non-zero entry are copied to the pinned words (*deferred)[0 .. np), valid
+// once the caller has synchronised c->st; if one is set the caller discards
+// what it computed from c->Cu and calls again without `deferred`.
+det_status inverse_mod_primes(det_ctx* c, const int64_t* dA, int64_t dlda, int n,
+                              const uint32_t* ps, int np, const int32_t** deferred = nullptr) {
   LuWs& w = c->ws[0];
   // with every panel 32 wide the inverse is formed from the factors in a few
   // launches (inverse_from_lu, four n-wide regions), else by the blocked back
   // substitution (two)
   const bool fast = detk::panel_width_for(n) == 32;
+  if (np < 1 || np > detk::LIFT_MAX_PRIMES || (np > 1 && !fast))
+    return fail(c, DET_E_INVALID, "inverse: unsupported number of primes");
   LuJob J;
   J.n = n;
   J.ncols = 2 * n;
   J.ldw = lu_stride((fast ? 4 : 2) * (int64_t)n);
   J.slab = J.ldw * n;
-  J.nitems = 1;
-  J.pmax = p;
+  J.nitems = np;
+  J.pmax = 0;
+  for (int z = 0; z < np; z++) J.pmax = std::max(J.pmax, ps[z]);
   J.int8 = false;
-  const int nrep = (n + 63) / 64;
-  TRY(ensure_pin(c, w.hmods, (size_t)nrep * sizeof(Modulus), w.st));
+  TRY(ensure_pin(c, w.hmods, (size_t)np * sizeof(Modulus), w.st));
   TRY(ensure_pinned(c, 64));                       // c->hres[0..63]; a background CRA batch
   Modulus* hm = (Modulus*)w.hmods.p;               // writes from c->hres + 64
-  for (int i = 0; i < nrep; i++) hm[i] = modulus_of(p);
-  TRY(ensure(c, w.W, (size_t)J.slab * sizeof(int32_t), w.st));
-  TRY(ensure(c, w.piv, (size_t)n * sizeof(int32_t), w.st));
-  TRY(ensure(c, w.flags, sizeof(int32_t), w.st));
-  TRY(ensure(c, w.mods, sizeof(Modulus), w.st));
-  TRY(ensure(c, c->Cu, (size_t)n * n * sizeof(uint32_t)));
-  HIPCHK(hipMemcpyAsync(w.mods.p, hm, sizeof(Modulus), hipMemcpyHostToDevice, w.st));
-  if (fast) {
-    // for inverse_from_lu, ahead of the factorisation (the LU of [A | I]
-    // touches columns [0, 2n) only): the modulus once per batched pair of
-    // diagonal blocks, and V = columns [2n, 3n) cleared
-    TRY(ensure(c, w.modsr, (size_t)nrep * sizeof(Modulus), w.st));
-    HIPCHK(hipMemcpyAsync(w.modsr.p, hm, (size_t)nrep * sizeof(Modulus), hipMemcpyHostToDevice,
-                          w.st));
-  }
+  for (int z = 0; z < np; z++) hm[z] = modulus_of(ps[z]);
+  TRY(ensure(c, w.W, (size_t)np * J.slab * sizeof(int32_t), w.st));
+  TRY(ensure(c, w.piv, (size_t)np * n * sizeof(int32_t), w.st));
+  TRY(ensure(c, w.flags, (size_t)np * sizeof(int32_t), w.st));
+  TRY(ensure(c, w.mods, (size_t)np * sizeof(Modulus), w.st));
+  TRY(ensure(c, c->Cu, (size_t)np * n * n * sizeof(uint32_t)));
+  HIPCHK(hipMemcpyAsync(w.mods.p, hm, (size_t)np * sizeof(Modulus), hipMemcpyHostToDevice, w.st));
   std::vector<Panel> panels;
   int32_t* flag = (int32_t*)c->hres;
   // first with pivots searched inside each diagonal block only (the panels
@@ -561,35 +558,45 @@ det_status inverse_mod_p(det_ctx* c, const int64_t* dA, int64_t dlda, int n, uin
   for (int attempt = 0; attempt < 2; attempt++) {
     const bool block_pivots = attempt == 0 && c->block_pivots;
     if (attempt == 1 && !c->block_pivots) break;
-    HIPCHK(hipMemsetAsync(w.flags.p, 0, sizeof(int32_t), w.st));
+    HIPCHK(hipMemsetAsync(w.flags.p, 0, (size_t)np * sizeof(int32_t), w.st));
     HIPCHK(detk::launch_residues(dA, dlda, n, 2 * n, (int32_t*)w.W.p, J.ldw, J.slab,
-                                 (const Modulus*)w.mods.p, 1, w.st));
-    if (fast)
-      HIPCHK(hipMemset2DAsync((int32_t*)w.W.p + 2 * (int64_t)n, J.ldw * sizeof(int32_t), 0,
-                              (size_t)n * sizeof(int32_t), n, w.st));
+                                 (const Modulus*)w.mods.p, np, w.st));
+    if (fast)             // V = columns [2n, 3n), read by inverse_from_lu, cleared
+      for (int z = 0; z < np; z++)
+        HIPCHK(hipMemset2DAsync((int32_t*)w.W.p + z * J.slab + 2 * (int64_t)n,
+                                J.ldw * sizeof(int32_t), 0, (size_t)n * sizeof(int32_t), n, w.st));
     TRY(lu_factor(c, w, J, true, &panels, block_pivots));
-    HIPCHK(hipMemcpyAsync(flag, w.flags.p, sizeof(int32_t), hipMemcpyDeviceToHost, w.st));
+    HIPCHK(hipMemcpyAsync(flag, w.flags.p, (size_t)np * sizeof(int32_t), hipMemcpyDeviceToHost,
+                          w.st));
     if (block_pivots && deferred) {
       *deferred = flag;
       break;
     }
     HIPCHK(hipStreamSynchronize(w.st));
-    if (!*flag) break;
+    bool any = false;
+    for (int z = 0; z < np; z++) any |= flag[z] != 0;
+    if (!any) break;
     if (!block_pivots) return fail(c, DET_E_SINGULAR_MOD_P, "p divides det(A)");
     c->block_pivot_retries++;
   }
   int64_t col = n;
   if (fast) TRY(inverse_from_lu(c, w, J, &col));
   else TRY(back_substitute(c, w, J, panels, 1));
-  HIPCHK(detk::launch_extract_inverse((const int32_t*)w.W.p, J.ldw, col, n,
-                                      (const Modulus*)w.mods.p, (uint32_t*)c->Cu.p, w.st));
+  HIPCHK(detk::launch_extract_inverse((const int32_t*)w.W.p, J.slab, J.ldw, col, n,
+                                      (const Modulus*)w.mods.p, (uint32_t*)c->Cu.p, np, w.st));
   return DET_OK;
+}
+
+// A^{-1} mod p into c->Cu (see inverse_mod_primes).
+det_status inverse_mod_p(det_ctx* c, const int64_t* dA, int64_t dlda, int n, uint32_t p,
+                         const int32_t** deferred = nullptr) {
+  return inverse_mod_primes(c, dA, dlda, n, &p, 1, deferred);
 }
 
 // Layout of the pinned staging buffer c->hstage for a lifting of order n
 // with k digits: r (int64, up to LIFT3_MAX_RHS right-hand sides), digit 0 of
 // r, three balanced digits a record (four words, up to LIFT3_MAX_RHS records
-// a row), digit 1 of r, the combination vector, then k combination sums read
+// a row, for up to LIFT_MAX_PRIMES primes), digit 1 of r, the combination vector, then k combination sums read
 // back.
 struct Stage {
   size_t r, rp0, d3, rp1, cvec, comb, total;
@@ -599,7 +606,7 @@ Stage stage_layout(int64_t n, int64_t k) {
   s.r = 0;
   s.rp0 = s.r + 8 * (size_t)n * detk::LIFT3_MAX_RHS;
   s.d3 = s.rp0 + 4 * (size_t)n;
-  s.rp1 = s.d3 + 16 * (size_t)n * detk::LIFT3_MAX_RHS;
+  s.rp1 = s.d3 + 16 * (size_t)n * detk::LIFT3_MAX_RHS * detk::LIFT_MAX_PRIMES;
   s.cvec = s.rp1 + 4 * (size_t)n;
   s.comb = (s.cvec + 4 * (size_t)n + 63) & ~(size_t)63;
   s.total = s.comb + 8 * (size_t)k;
@@ -625,26 +632,29 @@ det_status pack_matrix(det_ctx* c, const int64_t* dA, int64_t dlda, int n) {
 }
 
 // The three-digit FP64 lifting (modulo p^3) of m right-hand sides B (n x m,
-// row-major) from C0 = A^{-1} mod p in c->Cu, on c->st: A packed into c->Ai,
-// the Hensel planes once, then one cooperative launch per LIFT3_MAX_RHS
-// right-hand sides (they share the planes, the rows of A and every exchange).
-// digits_dev: m x k x n (may be null); cvec_dev: ncv combination vectors
-// (stride lift_pad(n)); comb_dev: m x ncv x k sums cvec_a . x_i (may be null).
-// With after_own2 the launches first wait for own2.
+// row-major) for np primes side by side (Section 6: several p-adic liftings
+// in parallel, each with fewer steps), from C0 = A^{-1} mod p_z in c->Cu + z
+// n^2, on c->st: A packed into c->Ai, the Hensel planes of every prime in
+// one batch, then one cooperative launch per LIFT3_MAX_RHS right-hand sides
+// (they share the planes, the rows of A and every exchange; each prime has
+// its own workgroups).  digits_dev: m x np x k x n, digit i of x_h modulo
+// p_z at ((h np + z) k + i) n (may be null).  With after_own2 the launches
+// first wait for own2.
 det_status lift3_multi(det_ctx* c, int grid3, const int64_t* dA, int64_t dlda, int n,
-                       const int64_t* B, int m, uint32_t p, int64_t k, uint32_t* digits_dev,
-                       const uint32_t* cvec_dev, uint64_t* comb_dev, bool after_own2,
-                       int ncv = 1, const int** err_pending = nullptr,
+                       const int64_t* B, int m, const uint32_t* ps, int np, int64_t k,
+                       uint32_t* digits_dev, bool after_own2, const int** err_pending = nullptr,
                        const PreLaunch* pre = nullptr) {
   constexpr int MR = detk::LIFT3_MAX_RHS;
   const double nn = (double)n * n;
+  const size_t nz = (size_t)np;
+  if (np < 1 || np > detk::LIFT_MAX_PRIMES) return fail(c, DET_E_INVALID, "lifting: primes");
   TRY(pack_matrix(c, dA, dlda, n));
-  TRY(ensure(c, c->C1, (size_t)n * n * sizeof(uint32_t)));
-  TRY(ensure(c, c->C2, (size_t)n * n * sizeof(uint32_t)));
-  TRY(ensure(c, c->Ed, (size_t)n * n * sizeof(double)));
-  TRY(ensure(c, c->r, (size_t)n * MR * sizeof(int64_t)));
-  TRY(ensure(c, c->rv, (size_t)n * MR * 4 * sizeof(uint32_t)));
-  TRY(ensure(c, c->xv, (size_t)n * MR * 4 * sizeof(uint32_t)));
+  TRY(ensure(c, c->C1, nz * n * n * sizeof(uint32_t)));
+  TRY(ensure(c, c->C2, nz * n * n * sizeof(uint32_t)));
+  TRY(ensure(c, c->Ed, nz * n * n * sizeof(double)));
+  TRY(ensure(c, c->r, nz * n * MR * sizeof(int64_t)));
+  TRY(ensure(c, c->rv, nz * n * MR * 4 * sizeof(uint32_t)));
+  TRY(ensure(c, c->xv, nz * n * MR * 4 * sizeof(uint32_t)));
   TRY(ensure(c, c->sync, 64));
   const Stage sl = stage_layout(n, 0);
   TRY(ensure_pin(c, c->hstage, sl.total, c->st));
@@ -653,32 +663,37 @@ det_status lift3_multi(det_ctx* c, int grid3, const int64_t* dA, int64_t dlda, i
   int* herr = (int*)c->hsmall.p;
   char* hs = (char*)c->hstage.p;
   const int mr = detk::lift3_max_rhs(n);
-  // r_0 = b and its balanced digits mod p^3 (each centring carried into the
-  // next digit), one record of 25-bit fields under tag 0 (step 0) per row
-  // and right-hand side, for the right-hand sides [h0, h0 + mm)
+  // r_0 = b and its balanced digits mod p_z^3 (each centring carried into
+  // the next digit), one record of 25-bit fields under tag 0 (step 0) per
+  // row and right-hand side, for the right-hand sides [h0, h0 + mm) and
+  // every prime
   auto stage = [&](int h0, int mm) -> det_status {
     int64_t* hb = (int64_t*)(hs + sl.r);
-    uint32_t* d3 = (uint32_t*)(hs + sl.d3);
+    const size_t recs = (size_t)n * mm;
     for (int j = 0; j < n; j++)
-      for (int hh = 0; hh < mm; hh++) {
-        int64_t v = B[(size_t)j * m + h0 + hh];
-        hb[(size_t)j * mm + hh] = v;
-        uint32_t* rec = d3 + ((size_t)j * mm + hh) * 4;
+      for (int hh = 0; hh < mm; hh++) hb[(size_t)j * mm + hh] = B[(size_t)j * m + h0 + hh];
+    for (int z = 0; z < np; z++) {
+      const int64_t pz = (int64_t)ps[z];
+      uint32_t* d3 = (uint32_t*)(hs + sl.d3) + z * recs * 4;
+      for (size_t e = 0; e < recs; e++) {
+        int64_t v = hb[e];
+        uint32_t* rec = d3 + e * 4;
         for (int q = 0; q < 3; q++) {
-          int64_t md = v % (int64_t)p;
-          if (md < 0) md += p;
-          if (md > (int64_t)(p - 1) / 2) md -= p;
+          int64_t md = v % pz;
+          if (md < 0) md += pz;
+          if (md > (pz - 1) / 2) md -= pz;
           rec[q] = (uint32_t)(int32_t)md & detk::LIFT3_DIGIT_MASK;
-          v = (v - md) / (int64_t)p;                   // exact
+          v = (v - md) / pz;                           // exact
         }
         rec[3] = 0;
       }
-    const size_t recs = (size_t)n * mm;
-    HIPCHK(hipMemcpyAsync(c->r.p, hb, recs * sizeof(int64_t), hipMemcpyHostToDevice, c->st));
-    HIPCHK(hipMemcpyAsync(c->rv.p, d3, recs * 4 * sizeof(uint32_t), hipMemcpyHostToDevice,
-                          c->st));
+      HIPCHK(hipMemcpyAsync((int64_t*)c->r.p + z * recs, hb, recs * sizeof(int64_t),
+                            hipMemcpyHostToDevice, c->st));
+    }
+    HIPCHK(hipMemcpyAsync(c->rv.p, hs + sl.d3, nz * recs * 4 * sizeof(uint32_t),
+                          hipMemcpyHostToDevice, c->st));
     // xv: all-ones words (tag 127, not yet written by any step)
-    HIPCHK(hipMemsetAsync(c->xv.p, 0xFF, recs * 4 * sizeof(uint32_t), c->st));
+    HIPCHK(hipMemsetAsync(c->xv.p, 0xFF, nz * recs * 4 * sizeof(uint32_t), c->st));
     HIPCHK(hipMemsetAsync(c->sync.p, 0, 64, c->st));
     return DET_OK;
   };
@@ -686,8 +701,8 @@ det_status lift3_multi(det_ctx* c, int grid3, const int64_t* dA, int64_t dlda, i
   // lifting follows them (or the wait for own2) at once
   TRY(stage(0, std::min(mr, m)));
   HIPCHK(detk::launch_hensel_f64((const int32_t*)c->Ai.p, (const uint32_t*)c->Cu.p,
-                                 (double*)c->Ed.p, (uint32_t*)c->C1.p, (uint32_t*)c->C2.p, n, p,
-                                 c->st));
+                                 (double*)c->Ed.p, (uint32_t*)c->C1.p, (uint32_t*)c->C2.p, n, ps,
+                                 np, c->st));
   if (pre) {
     bool skip = false;
     TRY((*pre)(&skip));
@@ -697,12 +712,6 @@ det_status lift3_multi(det_ctx* c, int grid3, const int64_t* dA, int64_t dlda, i
     HIPCHK(hipEventRecord(c->ev, c->own2));
     HIPCHK(hipStreamWaitEvent(c->st, c->ev, 0));
   }
-  // the combinations are formed after the lifting, from its digits
-  uint32_t* dig = digits_dev;
-  if (!dig && comb_dev) {
-    TRY(ensure(c, c->digits, (size_t)m * k * n * sizeof(uint32_t)));
-    dig = (uint32_t*)c->digits.p;
-  }
   for (int h0 = 0; h0 < m; h0 += mr) {
     const int mm = std::min(mr, m - h0);
     if (h0 > 0) {
@@ -710,20 +719,16 @@ det_status lift3_multi(det_ctx* c, int grid3, const int64_t* dA, int64_t dlda, i
       TRY(stage(h0, mm));
     }
     {
-      // algorithmic bytes per digit and right-hand side: C and A as the
-      // one-launch-per-phase form reads them (8 n^2) and four n-vectors
-      ProfScope ps(c, DET_KERNEL_LIFT, (8.0 * nn + 40.0 * n) * k * mm, 4.0 * nn * k * mm, c->st);
+      // algorithmic bytes per digit, right-hand side and prime: C and A as
+      // the one-launch-per-phase form reads them (8 n^2) and four n-vectors
+      ProfScope ps_(c, DET_KERNEL_LIFT, (8.0 * nn + 40.0 * n) * k * mm * np,
+                    4.0 * nn * k * mm * np, c->st);
       HIPCHK(detk::launch_lift_resident3(
           grid3, (const uint32_t*)c->Cu.p, (const uint32_t*)c->C1.p, (const uint32_t*)c->C2.p,
           (const int32_t*)c->Ai.p, (int64_t*)c->r.p, (uint32_t*)c->rv.p, (uint32_t*)c->xv.p, n,
-          mm, p, k, dig ? dig + (size_t)h0 * k * n : nullptr, err, c->st));
+          mm, ps, np, k, digits_dev ? digits_dev + (size_t)h0 * np * k * n : nullptr,
+          (int64_t)np * k * n, k * (int64_t)n, err, c->st));
     }
-    if (comb_dev)
-      for (int hh = 0; hh < mm; hh++)
-        for (int a = 0; a < ncv; a++)
-          HIPCHK(detk::launch_comb_digits(dig + (size_t)(h0 + hh) * k * n, k, n,
-                                          cvec_dev + (size_t)a * lift_pad(n),
-                                          comb_dev + ((size_t)(h0 + hh) * ncv + a) * k, c->st));
     HIPCHK(hipMemcpyAsync(herr, err, sizeof(int), hipMemcpyDeviceToHost, c->st));
     if (err_pending && h0 + mm >= m) {
       // the caller synchronises c->st later and then reads the word
@@ -751,9 +756,16 @@ det_status lift(det_ctx* c, const int64_t* dA, int64_t dlda, int n, double amax,
                 const int** err_pending = nullptr, const PreLaunch* pre = nullptr) {
   if (err_pending) *err_pending = nullptr;
   const int grid3 = c->lift_mode == 0 && lift3_applies(n, amax, p) ? detk::lift3_grid(c->device, n) : 0;
-  if (grid3 > 0)      // lifting modulo p^3 in FP64: Hensel planes, then three digits a step
-    return lift3_multi(c, grid3, dA, dlda, n, b, 1, p, k, digits_dev, cvec_dev, comb_dev,
-                       after_own2, 1, err_pending, pre);
+  if (grid3 > 0) {    // lifting modulo p^3 in FP64: Hensel planes, then three digits a step
+    uint32_t* dig = digits_dev;
+    if (!dig && comb_dev) {
+      TRY(ensure(c, c->digits, (size_t)k * n * sizeof(uint32_t)));
+      dig = (uint32_t*)c->digits.p;
+    }
+    TRY(lift3_multi(c, grid3, dA, dlda, n, b, 1, &p, 1, k, dig, after_own2, err_pending, pre));
+    if (comb_dev) HIPCHK(detk::launch_comb_digits(dig, k, n, cvec_dev, comb_dev, c->st));
+    return DET_OK;
+  }
   if (pre) {
     bool skip = false;
     TRY((*pre)(&skip));
@@ -957,7 +969,7 @@ void det_ctx_destroy(det_ctx* c) {
                               &c->q_next, &c->q_ws, &c->q_aux, &c->q_out, &c->q_mats};
   for (LuWs& w : c->ws)
     for (DevBuf* b : {&w.W, &w.piv, &w.flags, &w.mods, &w.linv, &w.uinv, &w.tinv, &w.limbA,
-                      &w.limbB, &w.res, &w.modsr, &w.cnt})
+                      &w.limbB, &w.res, &w.cnt})
       all.push_back(b);
   for (DevBuf* b : all)
     if (b->p) (void)hipFree(b->p);
@@ -998,6 +1010,7 @@ void det_opts_default(det_opts* o) {
   o->prime_bits = 23;
   o->path = DET_PATH_AUTO;
   o->adaptive = 1;
+  o->lift_primes = 0;
 }
 
 det_status det_profile_select(det_ctx* c, det_kernel kind) {
@@ -1101,6 +1114,66 @@ det_status dixon_lift(det_ctx* c, const int64_t* A, int64_t n, int64_t lda, cons
   }
 }
 
+det_status dixon_lift_primes(det_ctx* c, const int64_t* A, int64_t n, int64_t lda,
+                             const int64_t* b, const uint32_t* primes, int64_t np, int64_t k,
+                             uint32_t* digits) {
+  if (!c) return DET_E_INVALID;
+  try {
+    if (n < 0 || k < 0 || np < 1 || np > detk::LIFT_MAX_PRIMES || !primes ||
+        (n > 0 && (!A || lda < n || !b)) || (n > 0 && k > 0 && !digits))
+      return fail(c, DET_E_INVALID, "invalid argument");
+    if (n > MAX_N) return fail(c, DET_E_INVALID, "n exceeds 4096");
+    for (int64_t z = 0; z < np; z++) {
+      if (primes[z] <= 256 || primes[z] >= (1u << 26))
+        return fail(c, DET_E_PRIME_RANGE, "p must lie in (2^8, 2^26)");
+      if (!dethost::is_prime_u32(primes[z])) return fail(c, DET_E_NOT_PRIME, "p is not prime");
+      for (int64_t y = 0; y < z; y++)
+        if (primes[y] == primes[z]) return fail(c, DET_E_INVALID, "primes not distinct");
+    }
+    if (n == 0 || k == 0) return DET_OK;
+    const double blim = ldexp(1.0, 62) / (double)(n + 1);
+    for (int64_t j = 0; j < n; j++)
+      if (fabs((double)b[j]) >= blim) return fail(c, DET_E_OVERFLOW, "|b_j| too large");
+    HIPCHK(hipSetDevice(c->device));
+    const int64_t* dA;
+    int64_t dlda;
+    bool on_dev;
+    TRY(stage_matrix(c, A, n, lda, &dA, &dlda, &on_dev));
+    dethost::Bounds bd;
+    TRY(matrix_bounds(c, A, lda, on_dev, dA, dlda, n, &bd));
+    uint32_t pmax = 0;
+    bool three = c->lift_mode == 0;
+    for (int64_t z = 0; z < np; z++) {
+      pmax = std::max(pmax, primes[z]);
+      three &= lift3_applies((int)n, bd.amax, primes[z]);
+    }
+    if ((double)n * bd.amax * (double)pmax >= ldexp(1.0, 62))
+      return fail(c, DET_E_OVERFLOW, "n ||A|| p >= 2^62");
+    const int grid3 = three ? detk::lift3_grid(c->device, (int)n) : 0;
+    TRY(ensure(c, c->digits, (size_t)np * k * n * sizeof(uint32_t)));
+    uint32_t* dig = (uint32_t*)c->digits.p;
+    if (grid3 > 0 && np <= detk::lift3_max_primes(c->device, (int)n)) {
+      // one batched inverse and one launch for every prime
+      TRY(inverse_mod_primes(c, dA, dlda, (int)n, primes, (int)np));
+      TRY(lift3_multi(c, grid3, dA, dlda, (int)n, b, 1, primes, (int)np, k, dig, false));
+    } else {
+      for (int64_t z = 0; z < np; z++) {
+        TRY(inverse_mod_p(c, dA, dlda, (int)n, primes[z]));
+        TRY(lift(c, dA, dlda, (int)n, bd.amax, b, primes[z], k, dig + (size_t)z * k * n, nullptr,
+                 nullptr));
+      }
+    }
+    HIPCHK(hipMemcpyAsync(digits, dig, (size_t)np * k * n * sizeof(uint32_t),
+                          hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    return DET_OK;
+  } catch (const std::exception& e) {
+    return fail(c, DET_E_NOMEM, e.what());
+  } catch (...) {
+    return fail(c, DET_E_INVALID, "unexpected error");
+  }
+}
+
 det_status dixon_lift_multi(det_ctx* c, const int64_t* A, int64_t n, int64_t lda,
                             const int64_t* B, int64_t m, uint32_t p, int64_t k, uint32_t* digits) {
   if (!c) return DET_E_INVALID;
@@ -1131,7 +1204,7 @@ det_status dixon_lift_multi(det_ctx* c, const int64_t* A, int64_t n, int64_t lda
     const int grid3 =
         c->lift_mode == 0 && lift3_applies((int)n, bd.amax, p) ? detk::lift3_grid(c->device, (int)n) : 0;
     if (grid3 > 0) {
-      TRY(lift3_multi(c, grid3, dA, dlda, (int)n, B, (int)m, p, k, dig, nullptr, nullptr, false));
+      TRY(lift3_multi(c, grid3, dA, dlda, (int)n, B, (int)m, &p, 1, k, dig, false));
     } else {
       std::vector<int64_t> bh(n);
       for (int64_t h = 0; h < m; h++) {
@@ -1342,30 +1415,55 @@ det_status det_introspective(det_ctx* c, const int64_t* A, int64_t n, int64_t ld
     // for its flag: the flag is read with the first solving's results, and if
     // a block column had no non-zero entry the solving is discarded and pass
     // 1 starts over with the full search (and a fresh prime).
+    // Liftings side by side (Section 6: several p-adic liftings in parallel,
+    // each with fewer steps, combined by Chinese remaindering): np primes,
+    // each lifted to k digits with prod p_z^k above the bound, when the
+    // three-digit form applies and np of its grids fit on the device.
+    const int grid3 = dixon_bits == 25 ? detk::lift3_grid(c->device, (int)n) : 0;
+    int np = 1;
+    if (grid3 > 0) {
+      const int cap = detk::lift3_max_primes(c->device, (int)n);
+      np = o.lift_primes > 0 ? std::min(o.lift_primes, cap) : std::min(cap, LIFT_PRIMES_AUTO);
+      np = std::max(1, np);
+    }
+    rep.lift_primes = np;
     for (int pass = 0; pass < 2 && bd.log2_h > 0 && dixon_bits > 12; pass++) {
-      // one prime and one inverse for every solving
-      uint32_t p = 0;
+      // one set of primes and inverses for every solving
+      uint32_t dps[detk::LIFT_MAX_PRIMES] = {0, 0, 0, 0};
       det_status st = DET_E_SINGULAR_MOD_P;
       const int32_t* inv_flag = nullptr;
       for (int tries = 0; tries < 2 && st == DET_E_SINGULAR_MOD_P; tries++) {
-        p = dsamp.next();
-        st = inverse_mod_p(c, dA, dlda, (int)n, p, pass == 0 && tries == 0 ? &inv_flag : nullptr);
+        for (int z = 0; z < np; z++) {
+          bool fresh;
+          do {
+            dps[z] = dsamp.next();
+            fresh = true;
+            for (int y = 0; y < z; y++) fresh &= dps[y] != dps[z];
+          } while (!fresh);
+        }
+        st = inverse_mod_primes(c, dA, dlda, (int)n, dps, np,
+                                pass == 0 && tries == 0 ? &inv_flag : nullptr);
       }
       if (st != DET_OK && st != DET_E_SINGULAR_MOD_P) return st;
       bool redo = false;
       if (st == DET_OK) {                            // else det is probably 0: CRA alone
         // lifting length from the bounds of every combination R_a . x_h:
         // numerators |.| <= sum(R_a) H_col ||b|| / min_j ||a_j|| (Cramer,
-        // R entries < 2^16, b entries < beta), denominators <= H
+        // R entries < 2^16, b entries < beta), denominators <= H; with np
+        // primes, k digits of each (prod p_z^k > 2^(Nbits + Dbits + 2))
         const double log2N = log2(65535.0 * (double)n) + bd.log2_hcol +
                              0.5 * log2(std::max(1.0, (double)n * (double)beta * (double)beta)) -
                              bd.log2_min_col + 1e-6;
         const int64_t Nbits = (int64_t)ceil(log2N), Dbits = (int64_t)ceil(bd.log2_h + 1e-6);
-        const int64_t k = (int64_t)ceil((double)(Nbits + Dbits + 2) / log2((double)p)) + 1;
+        double log2P = 0;
+        for (int z = 0; z < np; z++) log2P += log2((double)dps[z]);
+        const int64_t k = (int64_t)ceil((double)(Nbits + Dbits + 2) / log2P) + 1;
         const int64_t npad = lift_pad((int)n);
-        TRY(ensure(c, c->digits, (size_t)i_max * k * n * sizeof(uint32_t)));
+        TRY(ensure(c, c->digits, (size_t)i_max * np * k * n * sizeof(uint32_t)));
         TRY(ensure(c, c->cvec, (size_t)i_max * npad * sizeof(uint32_t)));
-        TRY(ensure(c, c->comb, (size_t)i_max * i_max * k * sizeof(uint64_t)));
+        TRY(ensure(c, c->comb, (size_t)i_max * i_max * np * k * sizeof(uint64_t)));
+        dethost::PadicCrt crt_p;
+        bool crt_ready = false;
         uint32_t* dig = (uint32_t*)c->digits.p;
         std::vector<uint32_t> R((size_t)i_max * npad, 0);
         std::vector<uint64_t> comb;
@@ -1404,8 +1502,13 @@ det_status det_introspective(det_ctx* c, const int64_t* A, int64_t n, int64_t ld
             }
             return DET_OK;
           };
-          TRY(lift(c, dA, dlda, (int)n, bd.amax, b.data(), p, k, dig + (size_t)(i - 1) * k * n,
-                   nullptr, nullptr, false, &lift_err, batch1_taken ? nullptr : &pre));
+          uint32_t* dig_i = dig + (size_t)(i - 1) * np * k * n;
+          if (np > 1)
+            TRY(lift3_multi(c, grid3, dA, dlda, (int)n, b.data(), 1, dps, np, k, dig_i, false,
+                            &lift_err, batch1_taken ? nullptr : &pre));
+          else
+            TRY(lift(c, dA, dlda, (int)n, bd.amax, b.data(), dps[0], k, dig_i, nullptr, nullptr,
+                     false, &lift_err, batch1_taken ? nullptr : &pre));
           if (cra_done_first) {
             HIPCHK(hipStreamSynchronize(c->st));    // (the queued preparation ends)
             break;
@@ -1414,15 +1517,25 @@ det_status det_introspective(det_ctx* c, const int64_t* A, int64_t n, int64_t ld
                                 hipMemcpyHostToDevice, c->st));
           for (int h = 0; h < i; h++)
             for (int a = 0; a < i; a++)
-              HIPCHK(detk::launch_comb_digits(dig + (size_t)h * k * n, k, (int)n,
-                                              (const uint32_t*)c->cvec.p + (size_t)a * npad,
-                                              (uint64_t*)c->comb.p + ((size_t)h * i + a) * k, c->st));
-          comb.resize((size_t)i * i * k);
+              for (int z = 0; z < np; z++)
+                HIPCHK(detk::launch_comb_digits(
+                    dig + ((size_t)h * np + z) * k * n, k, (int)n,
+                    (const uint32_t*)c->cvec.p + (size_t)a * npad,
+                    (uint64_t*)c->comb.p + (((size_t)h * i + a) * np + z) * k, c->st));
+          comb.resize((size_t)i * i * np * k);
           HIPCHK(hipMemcpyAsync(comb.data(), c->comb.p, comb.size() * sizeof(uint64_t),
                                 hipMemcpyDeviceToHost, c->st));
+          if (!crt_ready) {
+            // the remaindering constants of the primes, while the device lifts
+            const double th = now_ms();
+            if (!crt_p.setup(dps, np, k)) return fail(c, DET_E_INVALID, "lifting primes not distinct");
+            crt_ready = true;
+            t_host += now_ms() - th;
+          }
           HIPCHK(hipStreamSynchronize(c->st));
           if (inv_flag) {
-            const bool bad = *inv_flag != 0;
+            bool bad = false;
+            for (int z = 0; z < np; z++) bad |= inv_flag[z] != 0;
             inv_flag = nullptr;
             if (bad) {                               // see pass above
               c->block_pivot_retries++;
@@ -1435,7 +1548,8 @@ det_status det_introspective(det_ctx* c, const int64_t* A, int64_t n, int64_t ld
           rep.lifting_steps += k;
           const double th0 = now_ms();
           BigInt sv, pi;
-          const int64_t failed = dethost::extended_bonus_host(comb.data(), i, k, p, Nbits, Dbits, sv, pi);
+          const int64_t failed =
+              dethost::extended_bonus_host(comb.data(), i, k, dps, np, Nbits, Dbits, &crt_p, sv, pi);
           K = BigInt::div_exact(K * sv, BigInt::gcd(K, sv));
           K = BigInt::div_exact(K * pi, BigInt::gcd(K, pi));
           if (i >= 2) rep.bonus_factors = failed ? -i : i;

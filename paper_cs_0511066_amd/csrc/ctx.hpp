@@ -35,7 +35,7 @@ struct PinBuf {
 
 // Device workspace of one batched LU, bound to one stream.
 struct LuWs {
-  DevBuf W, piv, flags, mods, linv, uinv, tinv, limbA, limbB, res, modsr, cnt;
+  DevBuf W, piv, flags, mods, linv, uinv, tinv, limbA, limbB, res, cnt;
   PinBuf hmods;                 // pinned host copy of the moduli (async uploads)
   PinBuf hflags;                // pinned copy of the batch's flags (block-pivot check)
   hipStream_t st = nullptr;

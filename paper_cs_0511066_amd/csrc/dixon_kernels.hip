@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "kernels.hpp"
@@ -573,6 +574,20 @@ static int lift3_grid_size(int n) {
 
 int lift3_max_rhs(int n) { return n <= 1024 ? LIFT3_MAX_RHS : 1; }
 
+// Liftings side by side in one launch: the forms up to order 1024 (planes and
+// A as FP64 registers, one workgroup a CU) take LIFT_MAX_PRIMES x their grid
+// at most; the narrow forms above it take one.
+static int lift3_max_primes_of(int n) { return n <= 1024 ? LIFT_MAX_PRIMES : 1; }
+
+int lift3_max_primes(int device, int n) {
+  const int grid = lift3_grid(device, n);
+  int cus = 0;
+  if (grid <= 0 ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
+    return 0;
+  return std::max(1, std::min(lift3_max_primes_of(n), cus / grid));
+}
+
 int lift3_grid(int device, int n) {
   int cus = 0, coop = 0;
   if (n > 2048) return 0;
@@ -608,10 +623,11 @@ int lift3_grid(int device, int n) {
 //           load; products < 2^48 (p < 2^25), reduced every 16 k-steps.
 typedef double v4d_h __attribute__((ext_vector_type(4)));
 template <int MODE>
-__global__ __launch_bounds__(512) void k_hensel_f64(const void* __restrict__ Lv,
-                                                    const void* __restrict__ Rv,
-                                                    const double* __restrict__ Ein, int n,
-                                                    uint32_t p, double pinv, void* __restrict__ out) {
+__global__ __launch_bounds__(512) void k_hensel_f64(const void* __restrict__ Lv0,
+                                                    const void* __restrict__ Rv0,
+                                                    const double* __restrict__ Ein0, int n,
+                                                    PrimeSet ps, int64_t sLz, int64_t sRz,
+                                                    int64_t sEz, void* __restrict__ out0) {
   constexpr int BM = 64, BN = 64, BK = 64;
   constexpr int T = 512;                                    // eight waves of 32 x 16
   constexpr int NL = BM * BK / T, NR = BK * BN / T;         // values a thread loads per chunk
@@ -620,6 +636,17 @@ __global__ __launch_bounds__(512) void k_hensel_f64(const void* __restrict__ Lv,
   const int lane = t & 63, wave = t >> 6;
   const int wr = wave >> 2, wc = wave & 3;
   const int row0 = blockIdx.y * BM, col0 = blockIdx.x * BN;
+  // prime z of the batch: its operands at element offsets z sLz, z sRz, z sEz
+  // (an offset of 0 shares the operand), its output at z n^2
+  const int z = blockIdx.z;
+  const uint32_t p = ps.p[z];
+  const double pinv = ps.pinv[z];
+  typedef typename std::conditional<MODE == 0, uint32_t, double>::type rv0_t;
+  typedef typename std::conditional<MODE == 0, double, uint32_t>::type out_t;
+  const void* Lv = (const uint32_t*)Lv0 + (int64_t)z * sLz;
+  const void* Rv = (const rv0_t*)Rv0 + (int64_t)z * sRz;
+  const double* Ein = Ein0 ? Ein0 + (int64_t)z * sEz : nullptr;
+  void* out = (out_t*)out0 + (int64_t)z * n * n;
   const double pd = (double)p, h = 0.5 * pd;
   __shared__ double sL[BK][BM + 2];
   __shared__ double sR[BK][BN + 2];
@@ -813,19 +840,34 @@ __device__ __forceinline__ int32_t centred_i32(uint32_t u, uint32_t p) {
 // polls, so all waves exit.
 template <int EPL, int RPW, int NWAVE, int NRHS, bool NARROW>
 __global__ __launch_bounds__(64 * NWAVE) void k_lift_resident3(
-    const uint32_t* __restrict__ C0, const uint32_t* __restrict__ C1,
-    const uint32_t* __restrict__ C2, const int32_t* __restrict__ Ai, int64_t* __restrict__ r,
-    uint32_t* rv, uint32_t* xv, int n, uint32_t p, double pinv, int64_t kd,
-    uint32_t* __restrict__ digits, int* err, unsigned spin_limit) {
+    const uint32_t* __restrict__ C0g, const uint32_t* __restrict__ C1g,
+    const uint32_t* __restrict__ C2g, const int32_t* __restrict__ Ai, int64_t* __restrict__ rg,
+    uint32_t* rvg, uint32_t* xvg, int n, PrimeSet ps, int gpp, int64_t kd,
+    uint32_t* __restrict__ digitsg, int64_t dig_rhs_stride, int64_t dig_prime_stride, int* err,
+    unsigned spin_limit) {
   typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
+  // the lifting of prime z runs on workgroups [z gpp, (z + 1) gpp), on its
+  // own planes, vectors and digits (the rows of A are shared)
+  const int z = blockIdx.x / gpp;
+  const int blk = blockIdx.x - z * gpp;
+  const uint32_t p = ps.p[z];
+  const double pinv = ps.pinv[z];
+  const int64_t nn = (int64_t)n * n;
+  const uint32_t* __restrict__ C0 = C0g + z * nn;
+  const uint32_t* __restrict__ C1 = C1g + z * nn;
+  const uint32_t* __restrict__ C2 = C2g + z * nn;
+  int64_t* __restrict__ r = rg + (int64_t)z * n * NRHS;
+  uint32_t* rv = rvg + (int64_t)z * n * NRHS * 4;
+  uint32_t* xv = xvg + (int64_t)z * n * NRHS * 4;
+  uint32_t* __restrict__ digits = digitsg ? digitsg + z * dig_prime_stride : nullptr;
   const double pd = (double)p;
   constexpr uint32_t DIG = LIFT3_DIGIT_MASK;
   constexpr int RG = RPW * NWAVE;                       // rows per workgroup
   constexpr int NC = 64 * EPL;                          // columns (at least n)
   constexpr int NJ = (EPL + NWAVE - 1) / NWAVE;         // rows staged per thread
-  const int row0 = blockIdx.x * RG;
+  const int row0 = blk * RG;
   // the vectors a phase reads, staged once per workgroup as int32 (digit t of
   // row j for right-hand side h at [h][t][j]: every wave reads all of it), one
   // buffer per phase so that a phase may stage while slower waves still read
@@ -1019,7 +1061,7 @@ __global__ __launch_bounds__(64 * NWAVE) void k_lift_resident3(
           o[2] = tag << 25 | x2;
           o[3] = tag << 25;
           if (digits) {
-            uint32_t* dg = digits + (int64_t)h * kd * n;
+            uint32_t* dg = digits + (int64_t)h * dig_rhs_stride;
             dg[(3 * step) * n + rows[i]] = x0;
             if (3 * step + 1 < kd) dg[(3 * step + 1) * n + rows[i]] = x1;
             if (3 * step + 2 < kd) dg[(3 * step + 2) * n + rows[i]] = x2;
@@ -1113,29 +1155,49 @@ hipError_t launch_comb_digits(const uint32_t* digits, int64_t k, int n, const ui
   return hipGetLastError();
 }
 
+static bool prime_set(const uint32_t* primes, int np, PrimeSet* ps) {
+  if (np < 1 || np > LIFT_MAX_PRIMES || !primes) return false;
+  for (int z = 0; z < LIFT_MAX_PRIMES; z++) {
+    ps->p[z] = primes[z < np ? z : 0];
+    ps->pinv[z] = 1.0 / (double)ps->p[z];
+  }
+  return true;
+}
+
 hipError_t launch_hensel_f64(const int32_t* Ai, const uint32_t* C0, double* E, uint32_t* C1,
-                             uint32_t* C2, int n, uint32_t p, hipStream_t st) {
+                             uint32_t* C2, int n, const uint32_t* primes, int np, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  dim3 grid((n + 63) / 64, (n + 63) / 64);
-  const double pinv = 1.0 / (double)p;
-  k_hensel_f64<0><<<grid, 512, 0, st>>>((const void*)Ai, (const void*)C0, nullptr, n, p, pinv, E);
-  k_hensel_f64<1><<<grid, 512, 0, st>>>((const void*)C0, (const void*)E, nullptr, n, p, pinv, C1);
-  k_hensel_f64<0><<<grid, 512, 0, st>>>((const void*)Ai, (const void*)C1, E, n, p, pinv, E);
-  k_hensel_f64<1><<<grid, 512, 0, st>>>((const void*)C0, (const void*)E, nullptr, n, p, pinv, C2);
+  PrimeSet ps;
+  if (!prime_set(primes, np, &ps)) return hipErrorInvalidValue;
+  dim3 grid((n + 63) / 64, (n + 63) / 64, np);
+  const int64_t nn = (int64_t)n * n;
+  k_hensel_f64<0><<<grid, 512, 0, st>>>((const void*)Ai, (const void*)C0, nullptr, n, ps, 0, nn,
+                                        0, E);
+  k_hensel_f64<1><<<grid, 512, 0, st>>>((const void*)C0, (const void*)E, nullptr, n, ps, nn, nn,
+                                        0, C1);
+  k_hensel_f64<0><<<grid, 512, 0, st>>>((const void*)Ai, (const void*)C1, E, n, ps, 0, nn, nn, E);
+  k_hensel_f64<1><<<grid, 512, 0, st>>>((const void*)C0, (const void*)E, nullptr, n, ps, nn, nn,
+                                        0, C2);
   return hipGetLastError();
 }
 
 hipError_t launch_lift_resident3(int grid, const uint32_t* C0, const uint32_t* C1,
                                  const uint32_t* C2, const int32_t* Ai, int64_t* r, uint32_t* rv,
-                                 uint32_t* xv, int n, int nrhs, uint32_t p, int64_t kd,
-                                 uint32_t* digits, int* err, hipStream_t st) {
+                                 uint32_t* xv, int n, int nrhs, const uint32_t* primes, int np,
+                                 int64_t kd, uint32_t* digits, int64_t dig_rhs_stride,
+                                 int64_t dig_prime_stride, int* err, hipStream_t st) {
   if (n <= 0 || kd <= 0) return hipSuccess;
-  if (p >= (1u << 25) || nrhs < 1 || nrhs > LIFT3_MAX_RHS) return hipErrorInvalidValue;
-  double pinv = 1.0 / (double)p;
+  PrimeSet ps;
+  if (!prime_set(primes, np, &ps) || nrhs < 1 || nrhs > LIFT3_MAX_RHS) return hipErrorInvalidValue;
+  for (int z = 0; z < np; z++)
+    if (primes[z] >= (1u << 25)) return hipErrorInvalidValue;
+  if (np > 1 && np > lift3_max_primes_of(n)) return hipErrorInvalidValue;
   unsigned spin_limit = 1u << 18;     // polls of about 1 us each: ~0.3 s per wait at most
+  int gpp = grid;
   void* args[] = {(void*)&C0, (void*)&C1, (void*)&C2, (void*)&Ai, (void*)&r, (void*)&rv,
-                  (void*)&xv, (void*)&n, (void*)&p, (void*)&pinv, (void*)&kd,
-                  (void*)&digits, (void*)&err, (void*)&spin_limit};
+                  (void*)&xv, (void*)&n, (void*)&ps, (void*)&gpp, (void*)&kd, (void*)&digits,
+                  (void*)&dig_rhs_stride, (void*)&dig_prime_stride, (void*)&err,
+                  (void*)&spin_limit};
   const void* f = nullptr;
 #define LIFT3_PICK(E)                                                                        \
   f = nrhs == 1 ? (const void*)k_lift_resident3<E, LIFT3_RPW, LIFT3_NWAVE, 1, false>          \
@@ -1150,7 +1212,7 @@ hipError_t launch_lift_resident3(int grid, const uint32_t* C0, const uint32_t* C
   else if (n <= 2048) f = (const void*)k_lift_resident3<32, LIFT3_RPW, LIFT3_NWAVE, 1, true>;
 #undef LIFT3_PICK
   if (!f || grid != lift3_grid_size(n)) return hipErrorInvalidValue;
-  return hipLaunchCooperativeKernel(f, dim3(grid), dim3(64 * LIFT3_NWAVE), args, 0, st);
+  return hipLaunchCooperativeKernel(f, dim3(grid * np), dim3(64 * LIFT3_NWAVE), args, 0, st);
 }
 
 hipError_t launch_lift_persistent(int grid, const uint32_t* Cu, const int32_t* Ai, int64_t* r,

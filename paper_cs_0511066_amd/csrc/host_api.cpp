@@ -111,16 +111,20 @@ det_status det_host_bigint(int op, int a_sign, const uint32_t* a, int64_t alen, 
   }
 }
 
-det_status det_host_extended_bonus(const uint64_t* comb, int64_t m, int64_t k, uint32_t p,
-                                   int64_t Nbits, int64_t Dbits, uint32_t* s_mag, int64_t s_cap,
-                                   int64_t* s_len, uint32_t* pi_mag, int64_t pi_cap,
-                                   int64_t* pi_len, int64_t* failed) {
-  if (m < 0 || m > 64 || k < 1 || p < 3 || Nbits < 0 || Dbits < 0 || !s_len || !pi_len ||
-      !failed || (m > 0 && !comb))
+det_status det_host_extended_bonus(const uint64_t* comb, int64_t m, int64_t k,
+                                   const uint32_t* primes, int64_t np, int64_t Nbits,
+                                   int64_t Dbits, uint32_t* s_mag, int64_t s_cap, int64_t* s_len,
+                                   uint32_t* pi_mag, int64_t pi_cap, int64_t* pi_len,
+                                   int64_t* failed) {
+  if (m < 0 || m > 64 || k < 1 || np < 1 || np > 4 || !primes || Nbits < 0 || Dbits < 0 ||
+      !s_len || !pi_len || !failed || (m > 0 && !comb))
     return DET_E_INVALID;
+  for (int64_t z = 0; z < np; z++)
+    if (primes[z] < 3) return DET_E_INVALID;
   try {
     BigInt s, pi;
-    *failed = dethost::extended_bonus_host(comb, (int)m, k, p, Nbits, Dbits, s, pi);
+    *failed = dethost::extended_bonus_host(comb, (int)m, k, primes, (int)np, Nbits, Dbits, nullptr,
+                                           s, pi);
     det_status a = put(s, nullptr, s_mag, s_cap, s_len);
     det_status b = put(pi, nullptr, pi_mag, pi_cap, pi_len);
     return a != DET_OK ? a : b;

@@ -260,7 +260,7 @@ inline void radix_value(const uint64_t* c, int64_t k, uint64_t p, BigInt& y, Big
 // gcd(a, d) = 1 reduces to pbase not dividing d.
 inline bool rational_reconstruct(const BigInt& u_in, const BigInt& m, const BigInt& N,
                                  const BigInt& D, BigInt& a_out, BigInt& d_out,
-                                 uint64_t pbase = 0) {
+                                 const uint64_t* pbases, int nbases) {
   BigInt q, u;
   BigInt::divmod_floor(u_in, m, q, u);
   BigInt r0 = m, r1 = u, t0, t1 = BigInt::from_i64(1);
@@ -301,8 +301,9 @@ inline bool rational_reconstruct(const BigInt& u_in, const BigInt& m, const BigI
   if (d.is_zero()) return false;
   if (d.sign < 0) { a = -a; d = -d; }
   if (d.cmp(D) > 0) return false;
-  if (pbase) {
-    if (d.mod_small(pbase) == 0) return false;
+  if (nbases > 0) {
+    for (int z = 0; z < nbases; z++)
+      if (d.mod_small(pbases[z]) == 0) return false;
   } else if (!(BigInt::gcd(a, d).cmp(BigInt::from_i64(1)) == 0)) {
     return false;
   }
@@ -311,13 +312,86 @@ inline bool rational_reconstruct(const BigInt& u_in, const BigInt& m, const BigI
   return true;
 }
 
+inline bool rational_reconstruct(const BigInt& u_in, const BigInt& m, const BigInt& N,
+                                 const BigInt& D, BigInt& a_out, BigInt& d_out,
+                                 uint64_t pbase = 0) {
+  return rational_reconstruct(u_in, m, N, D, a_out, d_out, &pbase, pbase ? 1 : 0);
+}
+
+// u^{-1} mod m for m a power of the prime q (false when q divides u): the
+// extended Euclidean algorithm run down to the remainder 1, which is the
+// rational reconstruction with numerator bound 1 (the cofactor d of the
+// remainder +-1 satisfies +-1 = d u mod m).
+inline bool inverse_mod_prime_power(const BigInt& u, const BigInt& m, uint64_t q, BigInt& inv) {
+  BigInt a, d;
+  if (!rational_reconstruct(u, m, BigInt::from_i64(1), m, a, d, q)) return false;
+  if (a.sign < 0) d = m - d;
+  inv = d;
+  return true;
+}
+
+// Chinese remaindering of p-adic values (several liftings in parallel,
+// Section 6): P_z = p_z^k for distinct primes p_z, and y = the integer in
+// [0, P_0 ... P_{np-1}) with y = y_z mod P_z, by Garner's mixed-radix form
+// y = v_0 + P_0 (v_1 + P_1 (...)) with
+//   v_z = (y_z - (v_0 + P_0 v_1 + ... )) (P_0 ... P_{z-1})^{-1} mod P_z.
+// The inverses depend only on the primes and k, so setup() can run before
+// the digits exist.
+struct PadicCrt {
+  int np = 0;
+  std::vector<uint64_t> p;
+  std::vector<BigInt> P, inv;                   // inv[z] = (P_0 ... P_{z-1})^{-1} mod P_z
+  BigInt M;                                     // P_0 ... P_{np-1}
+  bool setup(const uint32_t* ps, int count, int64_t k) {
+    np = count;
+    p.assign(ps, ps + count);
+    P.assign(count, BigInt());
+    inv.assign(count, BigInt());
+    M = BigInt::from_i64(1);
+    for (int z = 0; z < count; z++) {
+      BigInt pk = BigInt::from_i64(1), b = BigInt::from_u64(ps[z]);
+      for (int64_t e = k; e > 0; e >>= 1) {
+        if (e & 1) pk = pk * b;
+        if (e > 1) b = b * b;
+      }
+      P[z] = pk;
+      if (z > 0) {
+        BigInt q, r;
+        BigInt::divmod_floor(M, pk, q, r);
+        if (!inverse_mod_prime_power(r, pk, ps[z], inv[z])) return false;   // (equal primes)
+      }
+      M = M * pk;
+    }
+    return true;
+  }
+  // y from the values y_z (any integers; each is reduced mod P_z first)
+  BigInt combine(const BigInt* y) const {
+    BigInt q, acc, Mz = BigInt::from_i64(1);
+    for (int z = 0; z < np; z++) {
+      BigInt v;
+      BigInt::divmod_floor(y[z], P[z], q, v);
+      if (z > 0) {
+        BigInt t;
+        BigInt::divmod_floor(v - acc, P[z], q, t);      // (y_z - acc) mod P_z
+        BigInt::divmod_floor(t * inv[z], P[z], q, v);
+        v = acc + Mz * v;
+      }
+      acc = v;
+      Mz = Mz * P[z];
+    }
+    return acc;
+  }
+};
+
 // ---------------------------------------------------------------- extended bonus
 // The extended bonus of Section 3.2 (Alg. 4.1 with m >= 2 solvings), from
 // the p-adic expansions of the m x m combinations y[h][a] = R_a . x_h,
-// x_h = A^{-1} b_h:  comb[(h m + a) k + i] = R_a . (digit i of x_h), so that
-// y[h][a] = sum_i comb[..i] p^i (mod p^k).  Each y[h][a] is rebuilt by
-// rational reconstruction (numerator <= 2^Nbits, denominator <= 2^Dbits,
-// unique when Nbits + Dbits + 1 < k log2 p).
+// x_h = A^{-1} b_h, lifted modulo np primes side by side (np = 1: one
+// lifting): comb[((h m + a) np + z) k + i] = R_a . (digit i of x_h modulo
+// p_z), so that y[h][a] = sum_i comb[..i] p_z^i (mod p_z^k) for each z, and
+// y[h][a] modulo P = prod_z p_z^k by Chinese remaindering.  Each y[h][a] is
+// rebuilt by rational reconstruction modulo P (numerator <= 2^Nbits,
+// denominator <= 2^Dbits, unique when Nbits + Dbits + 1 < log2 P).
 //   s~  = lcm of the denominators of all y[h][a]; every one divides the
 //         common denominator of X = [x_0 .. x_{m-1}] and so s_n;
 //   R N = s~ R X, the integer m x m matrix with entries num * (s~ / den);
@@ -327,22 +401,31 @@ inline bool rational_reconstruct(const BigInt& u_in, const BigInt& m, const BigI
 // divides P_m for any s~ that makes R N integral; and s~ | s_n | P_m, so
 // lcm(s~, pi~) divides det(A).  Returns the number of combinations whose
 // reconstruction failed (0 on success; then pi~ is set, else pi~ = 1 and s~
-// is the lcm of the denominators that were found).
-inline int64_t extended_bonus_host(const uint64_t* comb, int m, int64_t k, uint64_t p,
-                                   int64_t Nbits, int64_t Dbits, BigInt& s, BigInt& pi) {
+// is the lcm of the denominators that were found).  crt: the remaindering
+// set up for ps and k (built here when null).
+inline int64_t extended_bonus_host(const uint64_t* comb, int m, int64_t k, const uint32_t* ps,
+                                   int np, int64_t Nbits, int64_t Dbits, const PadicCrt* crt,
+                                   BigInt& s, BigInt& pi) {
   s = BigInt::from_i64(1);
   pi = BigInt::from_i64(1);
   if (m <= 0) return 0;
+  PadicCrt own;
+  if (!crt) {
+    if (!own.setup(ps, np, k)) return (int64_t)m * m;
+    crt = &own;
+  }
   const BigInt Nb = BigInt::from_i64(1).shl(Nbits), Db = BigInt::from_i64(1).shl(Dbits);
   std::vector<std::vector<BigInt>> num(m, std::vector<BigInt>(m)), den(m, std::vector<BigInt>(m));
   int64_t failed = 0;
+  std::vector<BigInt> yz(np);
   BigInt pk;
   for (int h = 0; h < m; h++)
     for (int a = 0; a < m; a++) {
-      BigInt y;
-      radix_value(comb + ((size_t)h * m + a) * k, k, p, y, pk);
+      for (int z = 0; z < np; z++)
+        radix_value(comb + (((size_t)h * m + a) * np + z) * k, k, ps[z], yz[z], pk);
+      const BigInt y = np == 1 ? yz[0] : crt->combine(yz.data());
       BigInt nu, d;
-      if (!rational_reconstruct(y, pk, Nb, Db, nu, d, p)) {
+      if (!rational_reconstruct(y, crt->M, Nb, Db, nu, d, crt->p.data(), np)) {
         failed++;
         continue;
       }
@@ -366,6 +449,12 @@ inline int64_t extended_bonus_host(const uint64_t* comb, int m, int64_t k, uint6
   if (dRN.sign < 0) dRN = -dRN;
   pi = BigInt::div_exact(sm, BigInt::gcd(dRN, sm));
   return 0;
+}
+
+inline int64_t extended_bonus_host(const uint64_t* comb, int m, int64_t k, uint64_t p,
+                                   int64_t Nbits, int64_t Dbits, BigInt& s, BigInt& pi) {
+  const uint32_t p32 = (uint32_t)p;
+  return extended_bonus_host(comb, m, k, &p32, 1, Nbits, Dbits, nullptr, s, pi);
 }
 
 }  // namespace dethost

@@ -64,18 +64,24 @@ hipError_t launch_gemm_i8(int32_t* W, int64_t slab, int64_t offC, int64_t ldw, i
 hipError_t launch_det_finalize(const int32_t* W, int64_t ldw, int64_t slab, int n,
                                const int32_t* piv, int64_t piv_stride, const int32_t* flags,
                                const Modulus* mods, uint32_t* out, int nitems, hipStream_t st);
-hipError_t launch_extract_inverse(const int32_t* W, int64_t ldw, int64_t col0, int n,
-                                  const Modulus* mods, uint32_t* Cu, hipStream_t st);
+// Cu[z] (n x n, canonical) = the n x n block at column col0 of item z, for
+// the nitems items at W + z * slab.
+hipError_t launch_extract_inverse(const int32_t* W, int64_t slab, int64_t ldw, int64_t col0, int n,
+                                  const Modulus* mods, uint32_t* Cu, int nitems, hipStream_t st);
 // C <op> A B (mod p) on int32 centred residues within one slab per item
 // (op 0: C -= AB, 1: C += AB, 2: C = AB, 3: C = -AB); upper_a: A is upper
-// triangular (a row tile starts K at its row).
+// triangular (a row tile starts K at its row).  Items: nitems x nouter, item
+// (zo, zi) at W + zo * slab_outer + zi * slab, with modulus mods[zo] when
+// mod_by_outer, else mods[zo * nitems + zi].
 hipError_t launch_gemm_mod(int32_t* W, int64_t slab, int64_t offC, int64_t offA, int64_t offB,
                            int64_t ldw, int M, int N, int K, const Modulus* mods, int kc4, int op,
-                           bool upper_a, int nitems, hipStream_t st);
-// The 32 x 32 diagonal-block inverses (panel-major) onto the diagonal of the
-// n x n region at offV.
-hipError_t launch_place_diag(int32_t* W, int64_t ldw, int64_t offV, int n, const int32_t* uinv,
-                             hipStream_t st);
+                           bool upper_a, int nitems, hipStream_t st, int nouter = 1,
+                           int64_t slab_outer = 0, bool mod_by_outer = false);
+// The 32 x 32 diagonal-block inverses (panel-major: panel q of item z at
+// (q * nitems + z) * 1024) onto the diagonal of the n x n region at offV of
+// each item.
+hipError_t launch_place_diag(int32_t* W, int64_t slab, int64_t ldw, int64_t offV, int n,
+                             const int32_t* uinv, int nitems, hipStream_t st);
 
 // Dixon lifting (dixon_kernels.hip).
 hipError_t launch_lift_x(const uint32_t* Cu, const uint32_t* rp, int n, uint32_t p,
@@ -100,6 +106,9 @@ hipError_t launch_hensel(const int32_t* Ai, const uint32_t* Cu, uint32_t* E, uin
 // C1, C2 of A^{-1} mod p^3 from C0 = A^{-1} mod p (E: n x n FP64 scratch),
 // then all steps in one cooperative launch, three digits per step.
 int lift3_grid(int device, int n);    // 0: the three-plane form does not apply
+// liftings of order n that one launch can run side by side (1 .. LIFT_MAX_PRIMES;
+// 0 when the three-plane form does not apply)
+int lift3_max_primes(int device, int n);
 // comb[i] = cvec . digits[i] for k digit vectors of length n (after a lifting)
 hipError_t launch_comb_digits(const uint32_t* digits, int64_t k, int n, const uint32_t* cvec,
                               uint64_t* comb, hipStream_t st);
@@ -108,18 +117,33 @@ hipError_t launch_comb_digits(const uint32_t* digits, int64_t k, int n, const ui
 // of r) under a 7-bit tag, the step number mod 127; tag 127 (an all-ones
 // word) marks a word not yet written.  r of step 0 goes in with tag 0.
 constexpr uint32_t LIFT3_DIGIT_MASK = 0x1FFFFFFu;
+// Several liftings side by side, one per prime (Section 6: p-adic liftings
+// in parallel, each with fewer steps): the primes of one launch, with their
+// reciprocals.
+constexpr int LIFT_MAX_PRIMES = 4;
+struct PrimeSet {
+  uint32_t p[LIFT_MAX_PRIMES];
+  double pinv[LIFT_MAX_PRIMES];
+};
+// The Hensel planes for np primes at once: C0, E, C1, C2 hold np n x n
+// matrices each (prime z at offset z n^2); Ai is shared.
 hipError_t launch_hensel_f64(const int32_t* Ai, const uint32_t* C0, double* E, uint32_t* C1,
-                             uint32_t* C2, int n, uint32_t p, hipStream_t st);
+                             uint32_t* C2, int n, const uint32_t* primes, int np, hipStream_t st);
 // rv, xv: n x nrhs x 4 words, the digit vectors passed between workgroups (r
 // of step 0 in rv under tag 0, xv filled with all-ones words before the
-// launch); r: n x nrhs (row-major); digits: nrhs x kd x n.  nrhs <= LIFT3_MAX_RHS
-// right-hand sides share one launch.
+// launch); r: n x nrhs (row-major); digits of right-hand side h at
+// digits + h * dig_rhs_stride (kd x n).  nrhs <= LIFT3_MAX_RHS right-hand
+// sides share one launch.  With np > 1 primes, np liftings run side by side,
+// `grid` workgroups each: prime z has its planes at C* + z n^2, its r at
+// r + z n nrhs, its vectors at rv, xv + 4 z n nrhs and its digits at digits +
+// z * dig_prime_stride; Ai and err are shared.
 constexpr int LIFT3_MAX_RHS = 2;
 int lift3_max_rhs(int n);             // right-hand sides one launch takes at order n
 hipError_t launch_lift_resident3(int grid, const uint32_t* C0, const uint32_t* C1,
                                  const uint32_t* C2, const int32_t* Ai, int64_t* r, uint32_t* rv,
-                                 uint32_t* xv, int n, int nrhs, uint32_t p, int64_t kd,
-                                 uint32_t* digits, int* err, hipStream_t st);
+                                 uint32_t* xv, int n, int nrhs, const uint32_t* primes, int np,
+                                 int64_t kd, uint32_t* digits, int64_t dig_rhs_stride,
+                                 int64_t dig_prime_stride, int* err, hipStream_t st);
 hipError_t launch_lift_resident2(int grid, const uint32_t* C0, const uint32_t* C1,
                                  const int32_t* Ai, int64_t* r, uint32_t* rp0, uint32_t* rp1,
                                  uint32_t* xb0, uint32_t* xb1, int n, uint32_t p, uint64_t pinv64,

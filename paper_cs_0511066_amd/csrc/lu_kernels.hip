@@ -175,7 +175,8 @@ constexpr int GB_M = 64, GB_N = 64, GB_K = 32;
 // Sums are reduced every kc4 MFMA k-steps (sums of |products| stay <= 2^53).
 // op: 0 C -= AB, 1 C += AB, 2 C = AB, 3 C = -AB.  upper_a: A is upper
 // triangular (zero below the diagonal), so a row tile starts K at its row.
-// Items: z = blockIdx.z at W + z * slab with modulus mods[z].
+// Items: z = blockIdx.z = zo nin + zi at W + zo slab_out + zi slab, with
+// modulus mods[zo] (mod_by_outer) or mods[z].
 constexpr int GM_K = 32;
 // WR x WC waves, each an MI x NJ grid of 16 x 16 MFMA blocks: tiles of
 // 16 MI WR x 16 NJ WC (64 x 64 with four waves of 2 x 2 blocks, or with
@@ -186,15 +187,18 @@ __global__ __launch_bounds__(64 * WR * WC) void k_gemm_mod(int32_t* __restrict__
                                                            int64_t offB, int64_t ldw, int M,
                                                            int N, int K,
                                                            const Modulus* __restrict__ mods,
-                                                           int kc4, int op, int upper_a) {
+                                                           int kc4, int op, int upper_a, int nin,
+                                                           int64_t slab_out, int mod_by_outer) {
   constexpr int T = 64 * WR * WC, TM = 16 * MI * WR, TN = 16 * NJ * WC;
   constexpr int NL = TM * GM_K / T, NR = GM_K * TN / T;
   const int z = blockIdx.z;
+  const int zo = z / nin, zi = z - zo * nin;
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
   const int wr = wave / WC, wc = wave % WC;
-  const double p = mods[z].p, pinv = mods[z].pinv;
-  int32_t* Wz = W + (int64_t)z * slab;
+  const Modulus& md = mods[mod_by_outer ? zo : z];
+  const double p = md.p, pinv = md.pinv;
+  int32_t* Wz = W + (int64_t)zo * slab_out + (int64_t)zi * slab;
   const int32_t* Ag = Wz + offA;
   const int32_t* Bg = Wz + offB;
   int32_t* Cg = Wz + offC;
@@ -295,12 +299,14 @@ __global__ __launch_bounds__(64 * WR * WC) void k_gemm_mod(int32_t* __restrict__
 
 // The 32 x 32 inverses of the diagonal blocks of U (panel-major, panel q at
 // rows and columns [32 q, 32 q + pb)) into the diagonal of an n x n region.
-__global__ void k_place_diag(int32_t* __restrict__ W, int64_t ldw, int64_t offV, int n,
-                             const int32_t* __restrict__ uinv) {
-  const int q = blockIdx.x, r = threadIdx.x >> 5, cc = threadIdx.x & 31;
+__global__ void k_place_diag(int32_t* __restrict__ W, int64_t slab, int64_t ldw, int64_t offV,
+                             int n, const int32_t* __restrict__ uinv, int nitems) {
+  const int q = blockIdx.x, z = blockIdx.y, r = threadIdx.x >> 5, cc = threadIdx.x & 31;
+  int32_t* Wz = W + (int64_t)z * slab;
+  const int32_t* u = uinv + ((int64_t)q * nitems + z) * 1024;
   for (int rr = r; rr < 32; rr += blockDim.x >> 5) {
     const int gr = 32 * q + rr, gc = 32 * q + cc;
-    if (gr < n && gc < n) W[offV + (int64_t)gr * ldw + gc] = uinv[(int64_t)q * 1024 + rr * 32 + cc];
+    if (gr < n && gc < n) Wz[offV + (int64_t)gr * ldw + gc] = u[rr * 32 + cc];
   }
 }
 
@@ -818,14 +824,15 @@ __global__ __launch_bounds__(256) void k_det_finalize(const int32_t* __restrict_
 // ------------------------------------------------------------------ inverse extraction
 // Cu[i][j] = canonical residue of W[z=0][i][n + j] (the right half of [A | I]
 // after elimination and back substitution holds A^{-1} mod p).
-__global__ void k_extract_inverse(const int32_t* __restrict__ W, int64_t ldw, int64_t col0,
-                                  int n, const Modulus* __restrict__ mods,
+__global__ void k_extract_inverse(const int32_t* __restrict__ W, int64_t slab, int64_t ldw,
+                                  int64_t col0, int n, const Modulus* __restrict__ mods,
                                   uint32_t* __restrict__ Cu) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  const int i = blockIdx.y;
+  const int i = blockIdx.y, z = blockIdx.z;
   if (j >= n || i >= n) return;
-  const double p = mods[0].p;
-  Cu[(int64_t)i * n + j] = to_canonical((double)W[(int64_t)i * ldw + col0 + j], p);
+  const double p = mods[z].p;
+  Cu[((int64_t)z * n + i) * n + j] =
+      to_canonical((double)W[(int64_t)z * slab + (int64_t)i * ldw + col0 + j], p);
 }
 
 // ------------------------------------------------------------------ A packing and norms
@@ -990,22 +997,24 @@ hipError_t launch_lu_update(int32_t* W, int64_t slab, int64_t ldw, int j0, int p
 
 hipError_t launch_gemm_mod(int32_t* W, int64_t slab, int64_t offC, int64_t offA, int64_t offB,
                            int64_t ldw, int M, int N, int K, const Modulus* mods, int kc4, int op,
-                           bool upper_a, int nitems, hipStream_t st) {
-  if (M <= 0 || N <= 0 || nitems <= 0) return hipSuccess;
-  if (op < 0 || op > 3 || kc4 < 1) return hipErrorInvalidValue;
-  dim3 grid((N + 63) / 64, (M + 63) / 64, nitems);
+                           bool upper_a, int nitems, hipStream_t st, int nouter,
+                           int64_t slab_outer, bool mod_by_outer) {
+  if (M <= 0 || N <= 0 || nitems <= 0 || nouter <= 0) return hipSuccess;
+  if (op < 0 || op > 3 || kc4 < 1 || (int64_t)nitems * nouter > 65535) return hipErrorInvalidValue;
+  dim3 grid((N + 63) / 64, (M + 63) / 64, nitems * nouter);
   // eight waves of 32 x 16 (two a SIMD hide each other's LDS and MFMA
   // latencies): 1.28x the four-wave form on the 570-prime trailing updates
   k_gemm_mod<2, 4, 2, 1><<<grid, 512, 0, st>>>(W, slab, offC, offA, offB, ldw, M, N, K, mods,
-                                               kc4, op, upper_a ? 1 : 0);
+                                               kc4, op, upper_a ? 1 : 0, nitems, slab_outer,
+                                               mod_by_outer ? 1 : 0);
   LAUNCH_CHECK();
   return hipSuccess;
 }
 
-hipError_t launch_place_diag(int32_t* W, int64_t ldw, int64_t offV, int n, const int32_t* uinv,
-                             hipStream_t st) {
-  if (n <= 0) return hipSuccess;
-  k_place_diag<<<(n + 31) / 32, 256, 0, st>>>(W, ldw, offV, n, uinv);
+hipError_t launch_place_diag(int32_t* W, int64_t slab, int64_t ldw, int64_t offV, int n,
+                             const int32_t* uinv, int nitems, hipStream_t st) {
+  if (n <= 0 || nitems <= 0) return hipSuccess;
+  k_place_diag<<<dim3((n + 31) / 32, nitems), 256, 0, st>>>(W, slab, ldw, offV, n, uinv, nitems);
   LAUNCH_CHECK();
   return hipSuccess;
 }
@@ -1043,11 +1052,11 @@ hipError_t launch_det_finalize(const int32_t* W, int64_t ldw, int64_t slab, int 
   return hipSuccess;
 }
 
-hipError_t launch_extract_inverse(const int32_t* W, int64_t ldw, int64_t col0, int n,
-                                  const Modulus* mods, uint32_t* Cu, hipStream_t st) {
-  if (n <= 0) return hipSuccess;
-  dim3 grid((n + 255) / 256, n);
-  k_extract_inverse<<<grid, 256, 0, st>>>(W, ldw, col0, n, mods, Cu);
+hipError_t launch_extract_inverse(const int32_t* W, int64_t slab, int64_t ldw, int64_t col0, int n,
+                                  const Modulus* mods, uint32_t* Cu, int nitems, hipStream_t st) {
+  if (n <= 0 || nitems <= 0) return hipSuccess;
+  dim3 grid((n + 255) / 256, n, nitems);
+  k_extract_inverse<<<grid, 256, 0, st>>>(W, slab, ldw, col0, n, mods, Cu);
   LAUNCH_CHECK();
   return hipSuccess;
 }

@@ -288,6 +288,57 @@ def test_dixon_lift_past_the_tag_wrap_matches_oracle(ctx):
     assert np.array_equal(X.astype(np.int64), oracle.dixon_digits(A, b, p, k))
 
 
+@pytest.mark.parametrize("n,k,count", [(1, 5, 2), (33, 6, 2), (64, 45, 3), (150, 20, 4),
+                                       (300, 7, 2), (64, 400, 2)])
+def test_dixon_lift_primes_matches_oracle(ctx, n, k, count):
+    """Several liftings side by side (Section 6): one batched inverse, one
+    launch in which each prime has its own workgroups.  The digits for each
+    prime equal the oracle's lifting modulo that prime; k = 400 is 134 steps,
+    past the step-tag wrap, in both liftings at once."""
+    _say("dixon_lift_primes n =", n, "k =", k, "primes =", count)
+    A = synth.dense_uniform(n, -100, 100, 700 + n)
+    b = synth.random_rhs(n, 1000, n + 1)
+    ps = test_primes(1 << 24, 1 << 25, count, n + k)
+    X = ctx.dixon_lift_primes(A, b, ps, k)
+    assert X.shape == (count, k, n)
+    for z, p in enumerate(ps):
+        assert np.array_equal(X[z].astype(np.int64), oracle.dixon_digits(A, b, p, k)), z
+
+
+def test_dixon_lift_primes_mixed_forms_and_errors(ctx):
+    """A 26-bit prime takes the 64-bit integer lifting, so the primes are
+    lifted one after another; the digits are the same as prime by prime.
+    Repeated primes are refused."""
+    import paper_cs_0511066_amd as det
+    n, k = 80, 9
+    A = synth.dense_uniform(n, -100, 100, 81)
+    b = synth.random_rhs(n, 1000, 82)
+    ps = test_primes(1 << 24, 1 << 25, 1, 83) + test_primes(1 << 25, 1 << 26, 1, 84)
+    X = ctx.dixon_lift_primes(A, b, ps, k)
+    for z, p in enumerate(ps):
+        assert np.array_equal(X[z].astype(np.int64), oracle.dixon_digits(A, b, p, k))
+    with pytest.raises(det.DetError):
+        ctx.dixon_lift_primes(A, b, [ps[0], ps[0]], k)
+
+
+def test_dixon_lift_primes_n1024_invariant(ctx):
+    """Full size, two primes side by side for 130 steps (past the step-tag
+    wrap): for each prime, A x_i = r_i (mod p) and p | r_i - A x_i at every
+    step, checked with exact integers on the host."""
+    n, k = 1024, 390
+    A = synth.dense_uniform(n, 0, 255, 1024)
+    b = synth.random_rhs(n, 12000, 3)
+    ps = test_primes(1 << 24, 1 << 25, 2, 78)
+    X = ctx.dixon_lift_primes(A, b, ps, k).astype(np.int64)
+    for z, p in enumerate(ps):
+        r = b.astype(np.int64)
+        for i in range(k):
+            assert np.all((X[z, i] >= 0) & (X[z, i] < p))
+            t = r - A @ X[z, i]
+            assert np.all(t % p == 0), (z, i)
+            r = t // p
+
+
 @pytest.mark.parametrize("bits,k", [(26, 7), (24, 420)])
 def test_dixon_lift_n1024_invariant(ctx, bits, k):
     """Full size (the 64-bit integer form for 26-bit p, the FP64 three-digit
@@ -498,6 +549,34 @@ def test_det_introspective_mid_sizes(ctx, n, lo, hi):
     _say("n", n, "report", rep)
 
 
+@pytest.mark.parametrize("n,lo,hi,lp", [(100, -100, 100, 1), (100, -100, 100, 2),
+                                        (200, 0, 255, 3), (256, -1000, 1000, 4), (64, -5, 5, 4)])
+def test_det_introspective_lift_primes(ctx, n, lo, hi, lp):
+    """The solving lifted modulo 1 to 4 primes side by side, its combination
+    rebuilt by Chinese remaindering of the p-adic values: the same exact
+    determinant, the divisor from the lifting carrying nearly all of it."""
+    A = synth.dense_uniform(n, lo, hi, 4000 + n)
+    d = oracle.det_bareiss_c(A)
+    got, rep = ctx.det_introspective(A, report=True, lift_primes=lp)
+    _say("n", n, "lift_primes", lp, "report", rep)
+    assert got == d
+    assert rep["lift_primes"] == lp
+    assert rep["solvings"] == 1
+    assert rep["sn_bits"] >= abs(d).bit_length() - 64, rep
+
+
+def test_det_introspective_extended_bonus_lift_primes(ctx):
+    """Section 3.2 with the solvings lifted modulo three primes side by side:
+    the bonus still finds the product of the two largest invariant factors."""
+    n, tail, seed = 60, [101, 101 * 103], 31
+    s = [1] * (n - len(tail)) + tail
+    A, sign = synth.smith_matrix(s, seed, None)
+    d, rep = ctx.det_introspective(A, n_rhs=2, adaptive=False, report=True, lift_primes=3)
+    assert d == sign * math.prod(s)
+    assert rep["bonus_factors"] == 2 and rep["lift_primes"] == 3, rep
+    assert rep["sn_bits"] == math.prod(tail).bit_length()
+
+
 def _golden(name):
     path = os.path.join(ROOT, "tests", "golden", name + ".json")
     if not os.path.exists(path):
@@ -519,10 +598,14 @@ def test_det_introspective_golden_n1024(ctx):
     got, rep = ctx.det_introspective(A, report=True)
     _say("n1024 report", rep)
     assert got == d
-    # the divisor from the lifting (335 three-digit steps, past the step-tag
-    # wrap) carries nearly all of det: the CRA on det / K needed few primes
+    # the divisor from the lifting (two primes side by side, 168 three-digit
+    # steps each, past the step-tag wrap) carries nearly all of det: the CRA
+    # on det / K needed few primes
+    assert rep["lift_primes"] == 2, rep
     assert rep["sn_bits"] >= abs(d).bit_length() - 64, rep
     assert rep["primes_used"] <= 16, rep
+    d1, rep1 = ctx.det_introspective(A, report=True, lift_primes=1)
+    assert d1 == d and rep1["lift_primes"] == 1 and rep1["sn_bits"] == rep["sn_bits"]
     torch = pytest.importorskip("torch")
     assert ctx.det_introspective(torch.from_numpy(A).cuda()) == d
 

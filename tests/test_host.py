@@ -231,6 +231,58 @@ def test_extended_bonus_host_matches_oracle(n, tail, seed, m):
         assert got_pi == math.prod(s[-m:])
 
 
+@pytest.mark.parametrize("n,tail,seed,m,count", [(60, [101, 101 * 103], 31, 2, 2),
+                                                 (96, [107, 107 * 109, 107 * 109 * 113], 32, 3, 3),
+                                                 (40, [1, 1], 33, 2, 4)])
+def test_extended_bonus_host_several_primes(n, tail, seed, m, count):
+    """Liftings modulo several primes side by side (Section 6), each only
+    long enough for its share of the bound: the combinations are rebuilt by
+    Chinese remaindering of the p-adic values, and s~, pi~ equal the oracle's;
+    any single prime's digits are too short on their own."""
+    ps = test_primes(1 << 24, 1 << 25, count, seed + 7)
+    A, B, R, _, Nbits, Dbits, s = _bonus_inputs(n, tail, seed, m, ps[0])
+    log2P = sum(math.log2(p) for p in ps)
+    k = int(math.ceil((Nbits + Dbits + 2) / log2P)) + 1
+    comb = np.zeros((m, m, count, k), dtype=np.uint64)
+    for h in range(m):
+        for z, p in enumerate(ps):
+            X = oracle.dixon_digits(A, B[:, h], p, k)
+            for a in range(m):
+                comb[h, a, z] = (X @ R[a]).astype(np.uint64)
+    got_s, got_pi, failed = det.det_host_extended_bonus(comb, ps, Nbits, Dbits)
+    ref_s, ref_pi = oracle.extended_bonus(A, B, R)
+    assert failed == 0
+    assert (got_s, got_pi) == (ref_s, ref_pi)
+    assert math.prod(s) % math.lcm(got_s, got_pi) == 0
+
+
+def test_padic_remaindering_rebuilds_a_fraction():
+    """Chinese remaindering of p-adic expansions: the expansions of a known
+    fraction a/d modulo p1^k and p2^k, fed as digit sums (m = 1, R = 1),
+    give back d as s~ = pi~; the digits are those of Python's exact modular
+    arithmetic, so nothing of the library enters the expected value."""
+    ps = test_primes(1 << 24, 1 << 25, 2, 91)
+    k = 40                                           # 2 x 40 x 24 bits > 2 x 900 + 2
+    a, d = -(3 ** 500) + 17, 7 ** 300 + 2
+    assert math.gcd(a, d) == 1 and all(d % p for p in ps)
+    comb = np.zeros((1, 1, 2, k), dtype=np.uint64)
+    for z, p in enumerate(ps):
+        v = a * pow(d, -1, p ** k) % p ** k
+        for i in range(k):
+            comb[0, 0, z, i] = v % p
+            v //= p
+    got_s, got_pi, failed = det.det_host_extended_bonus(comb, ps, 900, 900)
+    assert failed == 0 and got_s == d and got_pi == d
+    # either prime's 40 digits alone (960 bits) cannot determine a/d (|a| d
+    # needs 1636): the reconstruction fails or finds another fraction
+    for z in range(2):
+        one_s, _, one_failed = det.det_host_extended_bonus(comb[:, :, z:z + 1], ps[z:z + 1], 900, 900)
+        assert one_failed == 1 or one_s != d
+    # the remaindering in the other order gives the same value
+    got_s2, _, _ = det.det_host_extended_bonus(comb[:, :, ::-1], ps[::-1], 900, 900)
+    assert got_s2 == d
+
+
 def test_extended_bonus_host_reports_a_corrupted_lifting():
     """A wrong digit in one combination's expansion makes its reconstruction
     fail (the bounds leave no room for a spurious fraction), and the failure
