@@ -81,6 +81,10 @@ struct LuJob {
   int64_t ldw = 0, slab = 0;
   bool int8 = false;  // trailing update on int8 limbs
   uint32_t pmax = 0;
+  // columns [n, 2n) start as the identity ([A | I]): a step without row swaps
+  // changes only the n columns [j0 + pb, n + j0 + pb), since row i of the
+  // right half stays zero beyond column n + i until row i is a pivot row
+  bool ident_right = false;
 };
 
 // Panels of one LU: first row, width, template width (ld of its inverses).
@@ -225,7 +229,8 @@ det_status lu_factor(det_ctx* c, LuWs& w, const LuJob& J, bool keep_uinv,
       }
       diag_done = false;
       if (panels) panels->push_back(P);
-      const int right = ncols - (j0 + pb);
+      int right = ncols - (j0 + pb);
+      if (J.ident_right && bp && pbw == 32) right = std::min(right, n);   // (no row swaps)
       if (fused) {
         const int M = n - (j0 + pb);
         // the next diagonal block inside this launch when it is 32 wide too
@@ -538,6 +543,7 @@ det_status inverse_mod_primes(det_ctx* c, const int64_t* dA, int64_t dlda, int n
   J.pmax = 0;
   for (int z = 0; z < np; z++) J.pmax = std::max(J.pmax, ps[z]);
   J.int8 = false;
+  J.ident_right = true;
   TRY(ensure_pin(c, w.hmods, (size_t)np * sizeof(Modulus), w.st));
   TRY(ensure_pinned(c, 64));                       // c->hres[0..63]; a background CRA batch
   Modulus* hm = (Modulus*)w.hmods.p;               // writes from c->hres + 64
@@ -631,6 +637,63 @@ det_status pack_matrix(det_ctx* c, const int64_t* dA, int64_t dlda, int n) {
   return DET_OK;
 }
 
+// Buffers of the three-digit lifting of order n for np primes, A packed into
+// c->Ai, and the staging of the right-hand sides [h0, h0 + mm) of B (n x m,
+// row-major): r_0 = b and its balanced digits mod p_z^3 (each centring
+// carried into the next digit), one record of 25-bit fields under tag 0
+// (step 0) per row, right-hand side and prime; xv filled with all-ones words
+// (tag 127, not yet written by any step); the error word cleared.  Enqueued
+// on c->st; the staging area is reused, so a second call must wait for the
+// first one's copies.  The host computes the staging while the device still
+// runs the inverse.
+det_status lift3_stage(det_ctx* c, const int64_t* dA, int64_t dlda, int n, const int64_t* B,
+                       int m, int h0, int mm, const uint32_t* ps, int np) {
+  constexpr int MR = detk::LIFT3_MAX_RHS;
+  const size_t nz = (size_t)np;
+  if (np < 1 || np > detk::LIFT_MAX_PRIMES) return fail(c, DET_E_INVALID, "lifting: primes");
+  if (h0 == 0) {
+    TRY(pack_matrix(c, dA, dlda, n));
+    TRY(ensure(c, c->C1, nz * n * n * sizeof(uint32_t)));
+    TRY(ensure(c, c->C2, nz * n * n * sizeof(uint32_t)));
+    TRY(ensure(c, c->Ed, nz * n * n * sizeof(double)));
+    TRY(ensure(c, c->r, nz * n * MR * sizeof(int64_t)));
+    TRY(ensure(c, c->rv, nz * n * MR * 4 * sizeof(uint32_t)));
+    TRY(ensure(c, c->xv, nz * n * MR * 4 * sizeof(uint32_t)));
+    TRY(ensure(c, c->sync, 64));
+  }
+  const Stage sl = stage_layout(n, 0);
+  TRY(ensure_pin(c, c->hstage, sl.total, c->st));
+  TRY(ensure_pin(c, c->hsmall, 64, c->st));
+  char* hs = (char*)c->hstage.p;
+  int64_t* hb = (int64_t*)(hs + sl.r);
+  const size_t recs = (size_t)n * mm;
+  for (int j = 0; j < n; j++)
+    for (int hh = 0; hh < mm; hh++) hb[(size_t)j * mm + hh] = B[(size_t)j * m + h0 + hh];
+  for (int z = 0; z < np; z++) {
+    const int64_t pz = (int64_t)ps[z];
+    uint32_t* d3 = (uint32_t*)(hs + sl.d3) + z * recs * 4;
+    for (size_t e = 0; e < recs; e++) {
+      int64_t v = hb[e];
+      uint32_t* rec = d3 + e * 4;
+      for (int q = 0; q < 3; q++) {
+        int64_t md = v % pz;
+        if (md < 0) md += pz;
+        if (md > (pz - 1) / 2) md -= pz;
+        rec[q] = (uint32_t)(int32_t)md & detk::LIFT3_DIGIT_MASK;
+        v = (v - md) / pz;                             // exact
+      }
+      rec[3] = 0;
+    }
+    HIPCHK(hipMemcpyAsync((int64_t*)c->r.p + z * recs, hb, recs * sizeof(int64_t),
+                          hipMemcpyHostToDevice, c->st));
+  }
+  HIPCHK(hipMemcpyAsync(c->rv.p, hs + sl.d3, nz * recs * 4 * sizeof(uint32_t),
+                        hipMemcpyHostToDevice, c->st));
+  HIPCHK(hipMemsetAsync(c->xv.p, 0xFF, nz * recs * 4 * sizeof(uint32_t), c->st));
+  HIPCHK(hipMemsetAsync(c->sync.p, 0, 64, c->st));
+  return DET_OK;
+}
+
 // The three-digit FP64 lifting (modulo p^3) of m right-hand sides B (n x m,
 // row-major) for np primes side by side (Section 6: several p-adic liftings
 // in parallel, each with fewer steps), from C0 = A^{-1} mod p_z in c->Cu + z
@@ -644,62 +707,14 @@ det_status lift3_multi(det_ctx* c, int grid3, const int64_t* dA, int64_t dlda, i
                        const int64_t* B, int m, const uint32_t* ps, int np, int64_t k,
                        uint32_t* digits_dev, bool after_own2, const int** err_pending = nullptr,
                        const PreLaunch* pre = nullptr) {
-  constexpr int MR = detk::LIFT3_MAX_RHS;
   const double nn = (double)n * n;
-  const size_t nz = (size_t)np;
   if (np < 1 || np > detk::LIFT_MAX_PRIMES) return fail(c, DET_E_INVALID, "lifting: primes");
-  TRY(pack_matrix(c, dA, dlda, n));
-  TRY(ensure(c, c->C1, nz * n * n * sizeof(uint32_t)));
-  TRY(ensure(c, c->C2, nz * n * n * sizeof(uint32_t)));
-  TRY(ensure(c, c->Ed, nz * n * n * sizeof(double)));
-  TRY(ensure(c, c->r, nz * n * MR * sizeof(int64_t)));
-  TRY(ensure(c, c->rv, nz * n * MR * 4 * sizeof(uint32_t)));
-  TRY(ensure(c, c->xv, nz * n * MR * 4 * sizeof(uint32_t)));
-  TRY(ensure(c, c->sync, 64));
-  const Stage sl = stage_layout(n, 0);
-  TRY(ensure_pin(c, c->hstage, sl.total, c->st));
-  TRY(ensure_pin(c, c->hsmall, 64, c->st));
-  int* err = (int*)((char*)c->sync.p + 32);
-  int* herr = (int*)c->hsmall.p;
-  char* hs = (char*)c->hstage.p;
   const int mr = detk::lift3_max_rhs(n);
-  // r_0 = b and its balanced digits mod p_z^3 (each centring carried into
-  // the next digit), one record of 25-bit fields under tag 0 (step 0) per
-  // row and right-hand side, for the right-hand sides [h0, h0 + mm) and
-  // every prime
-  auto stage = [&](int h0, int mm) -> det_status {
-    int64_t* hb = (int64_t*)(hs + sl.r);
-    const size_t recs = (size_t)n * mm;
-    for (int j = 0; j < n; j++)
-      for (int hh = 0; hh < mm; hh++) hb[(size_t)j * mm + hh] = B[(size_t)j * m + h0 + hh];
-    for (int z = 0; z < np; z++) {
-      const int64_t pz = (int64_t)ps[z];
-      uint32_t* d3 = (uint32_t*)(hs + sl.d3) + z * recs * 4;
-      for (size_t e = 0; e < recs; e++) {
-        int64_t v = hb[e];
-        uint32_t* rec = d3 + e * 4;
-        for (int q = 0; q < 3; q++) {
-          int64_t md = v % pz;
-          if (md < 0) md += pz;
-          if (md > (pz - 1) / 2) md -= pz;
-          rec[q] = (uint32_t)(int32_t)md & detk::LIFT3_DIGIT_MASK;
-          v = (v - md) / pz;                           // exact
-        }
-        rec[3] = 0;
-      }
-      HIPCHK(hipMemcpyAsync((int64_t*)c->r.p + z * recs, hb, recs * sizeof(int64_t),
-                            hipMemcpyHostToDevice, c->st));
-    }
-    HIPCHK(hipMemcpyAsync(c->rv.p, hs + sl.d3, nz * recs * 4 * sizeof(uint32_t),
-                          hipMemcpyHostToDevice, c->st));
-    // xv: all-ones words (tag 127, not yet written by any step)
-    HIPCHK(hipMemsetAsync(c->xv.p, 0xFF, nz * recs * 4 * sizeof(uint32_t), c->st));
-    HIPCHK(hipMemsetAsync(c->sync.p, 0, 64, c->st));
-    return DET_OK;
-  };
   // the first chunk's staging goes ahead of the Hensel products, so that the
   // lifting follows them (or the wait for own2) at once
-  TRY(stage(0, std::min(mr, m)));
+  TRY(lift3_stage(c, dA, dlda, n, B, m, 0, std::min(mr, m), ps, np));
+  int* err = (int*)((char*)c->sync.p + 32);
+  int* herr = (int*)c->hsmall.p;
   HIPCHK(detk::launch_hensel_f64((const int32_t*)c->Ai.p, (const uint32_t*)c->Cu.p,
                                  (double*)c->Ed.p, (uint32_t*)c->C1.p, (uint32_t*)c->C2.p, n, ps,
                                  np, c->st));
@@ -716,7 +731,7 @@ det_status lift3_multi(det_ctx* c, int grid3, const int64_t* dA, int64_t dlda, i
     const int mm = std::min(mr, m - h0);
     if (h0 > 0) {
       HIPCHK(hipStreamSynchronize(c->st));    // the staging of the last chunk is read
-      TRY(stage(h0, mm));
+      TRY(lift3_stage(c, dA, dlda, n, B, m, h0, mm, ps, np));
     }
     {
       // algorithmic bytes per digit, right-hand side and prime: C and A as
@@ -1289,7 +1304,25 @@ det_status det_introspective(det_ctx* c, const int64_t* A, int64_t n, int64_t ld
     // hres1; it is joined before anything waits for own2.
     det_status cra_st = DET_OK;
     Deferred cra_def;
-    std::thread cra_thread([&] {
+    std::thread cra_thread;
+    struct Joiner {
+      std::thread& t;
+      std::function<void()> start;
+      bool started = false;
+      void run() {
+        if (!started) {
+          started = true;
+          t = std::thread(start);
+        }
+      }
+      void join() {
+        run();
+        if (t.joinable()) t.join();
+      }
+      ~Joiner() {
+        if (t.joinable()) t.join();
+      }
+    } cra_join{cra_thread, [&] {
       try {
         (void)hipSetDevice(c->device);
         (void)hipEventRecord(c->ev_t0, c->own2);
@@ -1299,14 +1332,8 @@ det_status det_introspective(det_ctx* c, const int64_t* A, int64_t n, int64_t ld
       } catch (...) {
         cra_st = DET_E_NOMEM;
       }
-    });
-    struct Joiner {
-      std::thread& t;
-      void join() {
-        if (t.joinable()) t.join();
-      }
-      ~Joiner() { join(); }
-    } cra_join{cra_thread};
+    }};
+    cra_join.run();
 
     // ---------------- The CRA loop on det(A)/K (Alg. 2.1 on the quotient,
     // Section 4): every residue computed so far is kept (d_i = det mod p_i)
@@ -1503,7 +1530,7 @@ det_status det_introspective(det_ctx* c, const int64_t* A, int64_t n, int64_t ld
             return DET_OK;
           };
           uint32_t* dig_i = dig + (size_t)(i - 1) * np * k * n;
-          if (np > 1)
+          if (grid3 > 0)
             TRY(lift3_multi(c, grid3, dA, dlda, (int)n, b.data(), 1, dps, np, k, dig_i, false,
                             &lift_err, batch1_taken ? nullptr : &pre));
           else

@@ -191,13 +191,33 @@ inline u128 top_bits126(const BigInt& v, int64_t s) {
   return lo | (hi << 63);
 }
 
-// Quotient floor(a / b) for 0 <= a, 0 < b (128-bit), by subtraction when it
-// is small (most quotients of the Euclidean algorithm are 1, 2 or 3).
+// Quotient floor(a / b) for 0 <= a < 2^126, 0 < b (128-bit): by comparison
+// when it is below 4 (most quotients of the Euclidean algorithm are 1, 2 or
+// 3), else from the operands in double precision (relative error below
+// 2^-50, so an estimate below 2^50 is within one of the quotient), corrected
+// exactly; a 128-bit division only for larger quotients.
 inline __int128 small_quot(__int128 a, __int128 b) {
   if (a < b) return 0;
   if (a < 2 * b) return 1;
   if (a < 3 * b) return 2;
   if (a < 4 * b) return 3;
+  constexpr double TWO64 = 18446744073709551616.0;
+  const double da = (double)(uint64_t)((u128)a >> 64) * TWO64 + (double)(uint64_t)a;
+  const double db = (double)(uint64_t)((u128)b >> 64) * TWO64 + (double)(uint64_t)b;
+  const double qd = da / db;
+  if (qd < 1e15) {
+    int64_t q = (int64_t)qd;
+    __int128 r = a - (__int128)q * b;
+    while (r < 0) {
+      q--;
+      r += b;
+    }
+    while (r >= b) {
+      q++;
+      r -= b;
+    }
+    return q;
+  }
   return a / b;
 }
 
@@ -288,6 +308,23 @@ inline bool rational_reconstruct(const BigInt& u_in, const BigInt& m, const BigI
         BigInt::lincomb2(t0, t1, (int64_t)A, (int64_t)B, (int64_t)C, (int64_t)Dd);
         continue;
       }
+    }
+    // one Euclidean step.  When r1 is within 31 bits of r0, the quotient q
+    // (below 2^31) is within one of qe = floor(xh / yh) from the leading 63
+    // bits: (r0, r1) <- (r1, r0 - (qe - 1) r1) in place, then r1 -= r0 while
+    // r1 >= r0 (at most twice), and the same step on the cofactors.
+    const int64_t sh = std::max<int64_t>(0, r0.bit_length() - 63);
+    const uint64_t xh = top_bits(r0, sh), yh = top_bits(r1, sh);
+    if (yh >= (1ull << 32)) {
+      int64_t q = (int64_t)(xh / yh);
+      if (q > 0) q--;
+      BigInt::lincomb2(r0, r1, 0, 1, 1, -q);
+      while (r1.cmp(r0) >= 0) {
+        BigInt::lincomb2(r0, r1, 1, 0, -1, 1);
+        q++;
+      }
+      BigInt::lincomb2(t0, t1, 0, 1, 1, -q);
+      continue;
     }
     BigInt qq, rr;
     BigInt::divmod_floor(r0, r1, qq, rr);

@@ -154,6 +154,33 @@ def test_ratrecon_lehmer_large_prime_power():
         oracle.rational_reconstruct(u, m, 1 << 601, 1 << 601)
 
 
+def test_ratrecon_random_against_oracle():
+    """The Lehmer passes, the leading-bit quotient steps and the full
+    divisions of the host reconstruction against the textbook extended
+    Euclid: random moduli (general and prime powers) from 64 to 5000 bits,
+    residues of every magnitude (tiny ones give huge first quotients), and
+    bounds on both sides of 2 N D < m; the outputs must be identical,
+    failures included."""
+    rng = random.Random(19)
+    cases = 0
+    for trial in range(300):
+        bits = rng.choice([64, 200, 700, 2000, 5000])
+        if trial % 3 == 0:
+            p = rng.choice([33554393, 16777213, 10007])
+            m = p ** max(1, bits // p.bit_length())
+        else:
+            m = rng.getrandbits(bits) | (1 << (bits - 1)) | 1
+        u = rng.randrange(1, m) >> rng.choice([0, 0, 0, 5, 60, bits // 2])
+        half = (m.bit_length() - 2) // 2
+        Nbits = max(1, half + rng.randint(-40, 40))
+        Dbits = max(1, half + rng.randint(-40, 40))
+        got = det.det_host_ratrecon(u, m, Nbits, Dbits)
+        ref = oracle.rational_reconstruct(u, m, 1 << Nbits, 1 << Dbits)
+        assert got == ref, (trial, bits, Nbits, Dbits)
+        cases += ref is not None
+    assert cases > 20
+
+
 def test_ratrecon_rejects_when_out_of_bounds():
     m = 10007 ** 2
     u = 123456 * pow(654321, -1, m) % m
