@@ -524,9 +524,13 @@ det_status ensure_pinned(det_ctx* c, size_t count);
 // and nothing waits for it: the np flags that say a block column had no
 // non-zero entry are copied to the pinned words (*deferred)[0 .. np), valid
 // once the caller has synchronised c->st; if one is set the caller discards
-// what it computed from c->Cu and calls again without `deferred`.
+// what it computed from c->Cu and calls again without `deferred`.  With
+// det_out (pinned, np words) det(A) mod p_z is read back from the same
+// factorisation, with the flags, and det_done is recorded after both (a
+// residue is valid when its flag is clear).
 det_status inverse_mod_primes(det_ctx* c, const int64_t* dA, int64_t dlda, int n,
-                              const uint32_t* ps, int np, const int32_t** deferred = nullptr) {
+                              const uint32_t* ps, int np, const int32_t** deferred = nullptr,
+                              uint32_t* det_out = nullptr, hipEvent_t det_done = nullptr) {
   LuWs& w = c->ws[0];
   // with every panel 32 wide the inverse is formed from the factors in a few
   // launches (inverse_from_lu, four n-wide regions), else by the blocked back
@@ -572,8 +576,19 @@ det_status inverse_mod_primes(det_ctx* c, const int64_t* dA, int64_t dlda, int n
         HIPCHK(hipMemset2DAsync((int32_t*)w.W.p + z * J.slab + 2 * (int64_t)n,
                                 J.ldw * sizeof(int32_t), 0, (size_t)n * sizeof(int32_t), n, w.st));
     TRY(lu_factor(c, w, J, true, &panels, block_pivots));
+    if (det_out) {
+      // det(A) mod p_z from the same factorisation (U's diagonal and the
+      // pivots of [A | I] are those of A), a free CRA residue per prime
+      TRY(ensure(c, w.res, (size_t)np * sizeof(uint32_t), w.st));
+      HIPCHK(detk::launch_det_finalize((const int32_t*)w.W.p, J.ldw, J.slab, n,
+                                       (const int32_t*)w.piv.p, n, (const int32_t*)w.flags.p,
+                                       (const Modulus*)w.mods.p, (uint32_t*)w.res.p, np, w.st));
+      HIPCHK(hipMemcpyAsync(det_out, w.res.p, (size_t)np * sizeof(uint32_t),
+                            hipMemcpyDeviceToHost, w.st));
+    }
     HIPCHK(hipMemcpyAsync(flag, w.flags.p, (size_t)np * sizeof(int32_t), hipMemcpyDeviceToHost,
                           w.st));
+    if (det_out && det_done) HIPCHK(hipEventRecord(det_done, w.st));
     if (block_pivots && deferred) {
       *deferred = flag;
       break;
@@ -947,6 +962,7 @@ det_status det_ctx_create(int device, size_t hbm_budget_bytes, det_ctx** out) {
       hipStreamCreateWithFlags(&c->own2, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev_cra, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_det, hipEventDisableTiming) != hipSuccess ||
       hipEventCreate(&c->ev_t0) != hipSuccess || hipEventCreate(&c->ev_t1) != hipSuccess ||
       detk::configure_kernels() != hipSuccess) {
     (void)hipGetLastError();
@@ -1000,6 +1016,7 @@ void det_ctx_destroy(det_ctx* c) {
   if (c->q_exec) (void)hipGraphExecDestroy(c->q_exec);
   if (c->ev) (void)hipEventDestroy(c->ev);
   if (c->ev_cra) (void)hipEventDestroy(c->ev_cra);
+  if (c->ev_det) (void)hipEventDestroy(c->ev_det);
   if (c->ev_t0) (void)hipEventDestroy(c->ev_t0);
   if (c->ev_t1) (void)hipEventDestroy(c->ev_t1);
   if (c->own) (void)hipStreamDestroy(c->own);
@@ -1285,19 +1302,73 @@ det_status det_introspective(det_ctx* c, const int64_t* A, int64_t n, int64_t ld
     const double log2_l = (double)(bits - 1);
     dethost::PrimeSampler samp(dethost::splitmix64(rng), bits);
 
+    const double tl0 = now_ms();
+    // 25-bit primes when the FP64 three-digit lifting applies, else the
+    // largest below 2^26 with n ||A|| p < 2^62 (64-bit integer lifting)
+    int dixon_bits = 26;
+    if (c->lift_mode == 0 && lift3_applies((int)n, bd.amax, (1u << 25) - 1) &&
+        detk::lift3_grid(c->device, (int)n) > 0)
+      dixon_bits = 25;
+    while (dixon_bits > 12 && (double)n * bd.amax * ldexp(1.0, dixon_bits) >= ldexp(1.0, 62))
+      dixon_bits--;
+    const int64_t beta = std::max<int64_t>(2, (int64_t)ceil(bd.log2_h));
+    const int i_max = std::min(std::max(o.n_rhs, 1), 8);
+    bool batch1_taken = false;
+    dethost::PrimeSampler dsamp(dethost::splitmix64(rng), dixon_bits);
+    // Pass 0 takes the inverse with the block pivot search and does not wait
+    // for its flag: the flag is read with the first solving's results, and if
+    // a block column had no non-zero entry the solving is discarded and pass
+    // 1 starts over with the full search (and a fresh prime).
+    // Liftings side by side (Section 6: several p-adic liftings in parallel,
+    // each with fewer steps, combined by Chinese remaindering): np primes,
+    // each lifted to k digits with prod p_z^k above the bound, when the
+    // three-digit form applies and np of its grids fit on the device.
+    const int grid3 = dixon_bits == 25 ? detk::lift3_grid(c->device, (int)n) : 0;
+    int np = 1;
+    if (grid3 > 0) {
+      const int cap = detk::lift3_max_primes(c->device, (int)n);
+      np = o.lift_primes > 0 ? std::min(o.lift_primes, cap) : std::min(cap, LIFT_PRIMES_AUTO);
+      np = std::max(1, np);
+    }
+    rep.lift_primes = np;
+    // The first inverse is the head of the critical path: it is enqueued
+    // before the CRA batch is set up (the pinned read-back words it uses are
+    // sized for the batch first, and A is marked ready for the batch's stream).
+    const double logl_H0 = std::max(1.0, bd.log2_h / log2_l);
+    const int64_t k0 = dethost::et_run_length(o.log2_inv_eps, dethost::prime_set_size(bits), logl_H0);
+    // (two more primes than the run: a determinant of up to two primes' worth
+    // of bits ends the CRA within the batch)
+    const bool solving = bd.log2_h > 0 && dixon_bits > 12;
+    const int64_t batch1 = k0 > 0 ? std::min<int64_t>(k0 + 2, 64) : 16;
+    TRY(ensure_pinned(c, (size_t)batch1 + 64));
+    HIPCHK(hipEventRecord(c->ev_cra, c->st));          // A (and its bounds) are ready on st
+    auto draw_dixon = [&](uint32_t* dps) {
+      for (int z = 0; z < np; z++) {
+        bool fresh;
+        do {
+          dps[z] = dsamp.next();
+          fresh = true;
+          for (int y = 0; y < z; y++) fresh &= dps[y] != dps[z];
+        } while (!fresh);
+      }
+    };
+    std::vector<uint32_t> ps1(batch1);
+    for (auto& q : ps1) q = samp.next();
+    uint32_t* hres1 = c->hres + 64;                  // (c->hres[0..63]: the inverse's read-backs)
+    uint32_t dps0[detk::LIFT_MAX_PRIMES] = {0, 0, 0, 0};
+    det_status st0 = DET_E_SINGULAR_MOD_P;
+    const int32_t* inv_flag0 = nullptr;
+    uint32_t* hdet0 = c->hres + 32;                  // det(A) mod the lifting primes
+    if (solving) {
+      draw_dixon(dps0);
+      st0 = inverse_mod_primes(c, dA, dlda, (int)n, dps0, np, &inv_flag0, hdet0, c->ev_det);
+    }
+
     // ---------------- CRA batch 1 on the second stream (Section 4: the
     // modular determinants run in the background while the systems are
     // solved).  Its size covers the run length of Lemma 2.1(iv) for the
     // bound H itself; once s_n is known, fewer may be needed.
     const double tc0 = now_ms();
-    const double logl_H0 = std::max(1.0, bd.log2_h / log2_l);
-    const int64_t k0 = dethost::et_run_length(o.log2_inv_eps, dethost::prime_set_size(bits), logl_H0);
-    const int64_t batch1 = k0 > 0 ? std::min<int64_t>(k0 + 3, 64) : 16;
-    std::vector<uint32_t> ps1(batch1);
-    for (auto& q : ps1) q = samp.next();
-    TRY(ensure_pinned(c, (size_t)batch1 + 64));
-    uint32_t* hres1 = c->hres + 64;                  // (c->hres[0..63]: the inverse's read-backs)
-    HIPCHK(hipEventRecord(c->ev_cra, c->st));          // A (and its bounds) are ready on st
     HIPCHK(hipStreamWaitEvent(c->own2, c->ev_cra, 0));
     // A second host thread enqueues the batch (some seventy launches), so that
     // the Dixon solve's launches start at once.  It uses only ws[1], own2 and
@@ -1359,6 +1430,7 @@ det_status det_introspective(det_ctx* c, const int64_t* A, int64_t n, int64_t ld
         const uint32_t p = cra_p[i];
         const uint64_t km = K.mod_small(p);
         if (km == 0) continue;                       // p | K: skip this prime
+        if (crt.count > 0 && crt.M.mod_small(p) == 0) continue;   // (a prime drawn twice)
         const uint64_t kinv = dethost::powmod64(km, p - 2, p);
         crt.add(p, (uint32_t)dethost::mulmod64(cra_r[i], kinv, p));
         if ((double)(crt.M.bit_length() - 1) >= 1.0 + log2_HK + 1.0) done = true;
@@ -1419,57 +1491,39 @@ det_status det_introspective(det_ctx* c, const int64_t* A, int64_t n, int64_t ld
       (void)hipGetLastError();
       cra_p.assign(ps1.begin(), ps1.end());
       cra_r.assign(hres1, hres1 + batch1);
+      // the lifting primes' residues from the inverse's LU (free extra CRA
+      // residues), when its block pivot search found every pivot
+      if (solving && st0 == DET_OK && inv_flag0) {
+        HIPCHK(hipEventSynchronize(c->ev_det));
+        bool ok = true;
+        for (int z = 0; z < np; z++) ok &= inv_flag0[z] == 0;
+        if (ok) {
+          cra_p.insert(cra_p.begin(), dps0, dps0 + np);
+          cra_r.insert(cra_r.begin(), hdet0, hdet0 + np);
+        }
+      }
       rep.et_rounds = 1;
       return DET_OK;
     };
 
     // ---------------- LIF: the solvings of Alg. 4.1 (Section 2.2; the
     // extended bonus of Section 3.2 from the second one on)
-    const double tl0 = now_ms();
-    // 25-bit primes when the FP64 three-digit lifting applies, else the
-    // largest below 2^26 with n ||A|| p < 2^62 (64-bit integer lifting)
-    int dixon_bits = 26;
-    if (c->lift_mode == 0 && lift3_applies((int)n, bd.amax, (1u << 25) - 1) &&
-        detk::lift3_grid(c->device, (int)n) > 0)
-      dixon_bits = 25;
-    while (dixon_bits > 12 && (double)n * bd.amax * ldexp(1.0, dixon_bits) >= ldexp(1.0, 62))
-      dixon_bits--;
-    const int64_t beta = std::max<int64_t>(2, (int64_t)ceil(bd.log2_h));
-    const int i_max = std::min(std::max(o.n_rhs, 1), 8);
-    bool batch1_taken = false;
-    dethost::PrimeSampler dsamp(dethost::splitmix64(rng), dixon_bits);
-    // Pass 0 takes the inverse with the block pivot search and does not wait
-    // for its flag: the flag is read with the first solving's results, and if
-    // a block column had no non-zero entry the solving is discarded and pass
-    // 1 starts over with the full search (and a fresh prime).
-    // Liftings side by side (Section 6: several p-adic liftings in parallel,
-    // each with fewer steps, combined by Chinese remaindering): np primes,
-    // each lifted to k digits with prod p_z^k above the bound, when the
-    // three-digit form applies and np of its grids fit on the device.
-    const int grid3 = dixon_bits == 25 ? detk::lift3_grid(c->device, (int)n) : 0;
-    int np = 1;
-    if (grid3 > 0) {
-      const int cap = detk::lift3_max_primes(c->device, (int)n);
-      np = o.lift_primes > 0 ? std::min(o.lift_primes, cap) : std::min(cap, LIFT_PRIMES_AUTO);
-      np = std::max(1, np);
-    }
-    rep.lift_primes = np;
-    for (int pass = 0; pass < 2 && bd.log2_h > 0 && dixon_bits > 12; pass++) {
-      // one set of primes and inverses for every solving
+    for (int pass = 0; pass < 2 && solving; pass++) {
+      // one set of primes and inverses for every solving (pass 0 starts with
+      // the inverse enqueued above)
       uint32_t dps[detk::LIFT_MAX_PRIMES] = {0, 0, 0, 0};
       det_status st = DET_E_SINGULAR_MOD_P;
       const int32_t* inv_flag = nullptr;
-      for (int tries = 0; tries < 2 && st == DET_E_SINGULAR_MOD_P; tries++) {
-        for (int z = 0; z < np; z++) {
-          bool fresh;
-          do {
-            dps[z] = dsamp.next();
-            fresh = true;
-            for (int y = 0; y < z; y++) fresh &= dps[y] != dps[z];
-          } while (!fresh);
-        }
-        st = inverse_mod_primes(c, dA, dlda, (int)n, dps, np,
-                                pass == 0 && tries == 0 ? &inv_flag : nullptr);
+      int tries = 0;
+      if (pass == 0) {
+        memcpy(dps, dps0, sizeof(dps));
+        st = st0;
+        inv_flag = inv_flag0;
+        tries = 1;
+      }
+      for (; tries < 2 && st == DET_E_SINGULAR_MOD_P; tries++) {
+        draw_dixon(dps);
+        st = inverse_mod_primes(c, dA, dlda, (int)n, dps, np, nullptr);
       }
       if (st != DET_OK && st != DET_E_SINGULAR_MOD_P) return st;
       bool redo = false;
@@ -1516,7 +1570,7 @@ det_status det_introspective(det_ctx* c, const int64_t* A, int64_t n, int64_t ld
           // and none is launched (Alg. 4.1 stops when the CRA has
           // terminated).  The host has then waited for the batch, so the
           // lifting need not wait for its stream.
-          bool cra_done_first = false;
+          bool cra_done_first = false, inverse_failed = false;
           const PreLaunch pre = [&](bool* skip) -> det_status {
             TRY(take_batch1());
             batch1_taken = true;
@@ -1526,6 +1580,14 @@ det_status det_introspective(det_ctx* c, const int64_t* A, int64_t n, int64_t ld
               feed(0);
               t_host += now_ms() - th;
               if (done) *skip = cra_done_first = true;
+            }
+            // the inverse's block pivot flags are back (take_batch1 waited
+            // for them): a block column without a non-zero entry means the
+            // inverse must be redone with the full search, so this lifting
+            // is not launched at all
+            if (!*skip && inv_flag && pass == 0) {
+              for (int z = 0; z < np; z++) inverse_failed |= inv_flag[z] != 0;
+              if (inverse_failed) *skip = true;
             }
             return DET_OK;
           };
@@ -1538,6 +1600,13 @@ det_status det_introspective(det_ctx* c, const int64_t* A, int64_t n, int64_t ld
                      false, &lift_err, batch1_taken ? nullptr : &pre));
           if (cra_done_first) {
             HIPCHK(hipStreamSynchronize(c->st));    // (the queued preparation ends)
+            break;
+          }
+          if (inverse_failed) {                     // see pass above
+            HIPCHK(hipStreamSynchronize(c->st));
+            inv_flag = nullptr;
+            c->block_pivot_retries++;
+            redo = true;
             break;
           }
           HIPCHK(hipMemcpyAsync(c->cvec.p, R.data(), (size_t)i * npad * sizeof(uint32_t),

@@ -51,6 +51,7 @@ struct det_ctx {
   hipEvent_t ev = nullptr;       // orders own2 after work queued on st
   hipEvent_t ev_cra = nullptr;   // the same for the first CRA batch (enqueued by a second thread)
   hipEvent_t ev_t0 = nullptr, ev_t1 = nullptr;   // device time of the first CRA batch
+  hipEvent_t ev_det = nullptr;   // det(A) mod the lifting primes read back (from the inverse's LU)
   std::mutex mu;                 // the error text, the budget count, the kernel timing state
   std::string err;
   LuWs ws[2];

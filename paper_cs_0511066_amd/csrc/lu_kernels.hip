@@ -350,14 +350,26 @@ __global__ __launch_bounds__(512) void k_lu_update(int32_t* __restrict__ W, int6
                                                    unsigned* __restrict__ cnt, int cnt_stride,
                                                    NextDiag next) {
   constexpr int T = 512;                                // eight waves, two a SIMD
-  const int z = blockIdx.z;
+  // Workgroup order: tile (0, 0) of every item first (the tile whose
+  // workgroup factors the next diagonal block, the head of the critical
+  // path), then the other tiles item by item.
+  const int tx = gridDim.x, ty = gridDim.y;
+  const int L = blockIdx.x + tx * (blockIdx.y + ty * blockIdx.z);
+  int z = L, bx = 0, by = 0;
+  if (L >= (int)gridDim.z) {
+    const int per = tx * ty - 1, L2 = L - gridDim.z;
+    z = L2 / per;
+    const int tt = 1 + L2 % per;
+    bx = tt % tx;
+    by = tt / tx;
+  }
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
   const int wr = wave >> 2, wc = wave & 3;              // update: a 32 x 16 block a wave
   const double p = mods[z].p, pinv = mods[z].pinv;
   int32_t* Wz = W + (int64_t)z * slab;
   const int r0 = j0 + pb;                               // first row and column of A22
-  const int row0 = blockIdx.y * GB_M, col0 = blockIdx.x * GB_N;
+  const int row0 = by * GB_M, col0 = bx * GB_N;
   __shared__ double sA[GB_K][GB_M + 2];                 // L21 tile, k-major
   __shared__ double sB[GB_K][GB_N + 2];                 // A12 tile, then U12
   __shared__ double sT[32][33];                         // L11^{-1}
@@ -458,8 +470,8 @@ __global__ __launch_bounds__(512) void k_lu_update(int32_t* __restrict__ W, int6
 #pragma unroll
   for (int r = 0; r < 4; r++) sB[ur + (lane >> 4) + 4 * r][uc + (lane & 15)] = mod_c(u2[r], p, pinv);
   if (cnt != nullptr && t == 0) {
-    const unsigned prev = atomicAdd(cnt + (int64_t)z * cnt_stride + blockIdx.x, 1u);
-    s_last = prev + 1 == gridDim.y;
+    const unsigned prev = atomicAdd(cnt + (int64_t)z * cnt_stride + bx, 1u);
+    s_last = prev + 1 == (unsigned)ty;
   }
   __syncthreads();
   if (cnt != nullptr && s_last) {                       // the last reader stores U12
@@ -497,7 +509,7 @@ __global__ __launch_bounds__(512) void k_lu_update(int32_t* __restrict__ W, int6
         Wz[(int64_t)(r0 + gr) * ldw + r0 + gc] =
             (int32_t)mod_c((double)vc[i][r] - mod_c(acc[i][r], p, pinv), p, pinv);
     }
-  if (next.pb > 0 && blockIdx.x == 0 && blockIdx.y == 0) {
+  if (next.pb > 0 && bx == 0 && by == 0) {
     __syncthreads();                                    // the tile is stored
     diag_block_body(Wz + (int64_t)r0 * ldw + r0, ldw, next.pb, p, pinv,
                     next.piv + (int64_t)z * next.piv_stride, r0, next.flags + z,

@@ -528,8 +528,9 @@ def test_det_introspective_structured_serving_matrices(ctx):
 
 def test_det_introspective_small_det_needs_no_solving(ctx):
     """Alg. 4.1 stops once the CRA has terminated: for a matrix whose
-    determinant is small (U diag(s) V, |det| < 2^16), the residues of the
-    first background batch already end the CRA on det itself (K = 1), so the
+    determinant is small (U diag(s) V, a 43-bit determinant: two primes'
+    worth), the residues of the first background batch already end the CRA
+    on det itself (K = 1), so the
     adaptive loop launches no lifting; with the loop off the solving runs.
     The determinant is exact either way."""
     A, sign, s = synth.structured_serving(300, 7)
