@@ -56,7 +56,7 @@ struct det_ctx {
   std::string err;
   LuWs ws[2];
   DevBuf Adev, norms, Cu, Ai, r, rp, x, digits, comb, cvec, sync, C1, E, rp1, x1, C2, Ed,
-      rv, xv;
+      rv, xv, Hp;
   uint32_t* hres = nullptr;      // pinned host residues of the background batch
   size_t hres_cap = 0;
   PinBuf hstage;                 // pinned staging of the lifting's vectors and results
@@ -65,6 +65,7 @@ struct det_ctx {
   int lift_mode = 0;             // 0: fastest cooperative form that applies; 1: one launch per
                                  // phase; 2: the 64-bit integer form modulo p^2
   bool block_pivots = true;      // the inverse's panels search their diagonal block first
+  bool hensel_i8 = true;         // Hensel planes on int8 MFMA where the operands allow it
   int64_t block_pivot_retries = 0;   // inverses that fell back to the full pivot search
   // kernel timing (det_profile_select / det_profile_read)
   int prof_kind = 0;

@@ -18,6 +18,7 @@
 
 #include "kernels.hpp"
 #include "modp.hpp"
+#include "i8tile.hpp"
 
 namespace detk {
 
@@ -750,6 +751,104 @@ __global__ __launch_bounds__(512) void k_hensel_f64(const void* __restrict__ Lv0
     }
 }
 
+// ------------------------------------------------------------------ Hensel products on int8 MFMA
+// The same four products as k_hensel_f64, on three signed int8 limbs of each
+// operand (i8tile.hpp) with int32 accumulation: every operand value lies in
+// [-LIMB3_MAX, LIMB3_MAX] (entries of A, and centred residues for p <=
+// 2 LIMB3_MAX + 1), so the limb products give the exact integer product.
+// k_split_h<SRC>: limb planes of prime z's n x n operand (transposed for the
+// right-hand factor), SRC 0: int32 values taken as they are (A, shared: sz =
+// 0); 1: canonical residues in [0, p), centred; 2: FP64 integers (E),
+// reduced mod p and centred.
+template <int SRC>
+__global__ __launch_bounds__(256) void k_split_h(const void* __restrict__ src, int64_t sz, int n,
+                                                 int Kp, int64_t Rp, int transpose,
+                                                 int8_t* __restrict__ P, int64_t pslab,
+                                                 PrimeSet ps) {
+  __shared__ uint32_t sT[64][65];
+  const int z = blockIdx.z;
+  const uint32_t p = ps.p[z];
+  const double pd = (double)p, pinv = ps.pinv[z];
+  auto get = [&](int r, int c) -> int32_t {
+    const int64_t o = (int64_t)z * sz + (int64_t)r * n + c;
+    if (SRC == 0) return ((const int32_t*)src)[o];
+    if (SRC == 1) {
+      const uint32_t u = ((const uint32_t*)src)[o];
+      return u > (p - 1) / 2 ? (int32_t)u - (int32_t)p : (int32_t)u;
+    }
+    return (int32_t)mod_c(((const double*)src)[o], pd, pinv);
+  };
+  limb_split_tile(get, n, n, Kp, Rp, transpose, P + (int64_t)z * pslab, sT);
+}
+
+// k_hensel_i8<MODE>: the 64 x 64 output tile of prime z from the limb planes
+// (PA: left factor, PB: right factor transposed; Rp x Kp a plane).  With v
+// the exact product (the limb sums weighted by 2^(8s), in int64):
+//   MODE 0: E = (Ein + v) / p (Ein = -I when null), exact in FP64 (|Ein + v|
+//           < 2^53 under the lifting's bound), as k_hensel_f64;
+//   MODE 1: C = -v mod p in [0, p).
+template <int MODE>
+__global__ __launch_bounds__(256) void k_hensel_i8(const int8_t* __restrict__ PA,
+                                                   const int8_t* __restrict__ PB,
+                                                   int64_t pslabA, int64_t pslabB, int64_t Rp,
+                                                   int Kp, int n, PrimeSet ps,
+                                                   const double* __restrict__ Ein, int64_t sE,
+                                                   void* __restrict__ out0) {
+  const int z = blockIdx.z;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const uint32_t p = ps.p[z];
+  const double pd = (double)p, pinv = ps.pinv[z];
+  const int row0 = blockIdx.y * I8_TILE, col0 = blockIdx.x * I8_TILE;
+  __shared__ __attribute__((aligned(16))) int8_t sA[3][I8_TILE][I8_LD];
+  __shared__ __attribute__((aligned(16))) int8_t sB[3][I8_TILE][I8_LD];
+  v4i_t acc[5][2][2];
+  i8_tile_product(PA + (int64_t)z * pslabA, PB + (int64_t)z * pslabB, Rp * Kp, Rp * Kp, Kp, row0,
+                  col0, sA, sB, acc);
+  const int64_t nn = (int64_t)n * n;
+  double wgt[5];                                    // 2^(8s) mod p, centred (MODE 1)
+  wgt[0] = 1.0;
+#pragma unroll
+  for (int s = 1; s < 5; s++) wgt[s] = mod_c(wgt[s - 1] * 256.0, pd, pinv);
+  // MODE 0 reads Ein for all its elements first (clamped, unconditional)
+  double ein[2][2][4];
+#pragma unroll
+  for (int i = 0; i < 2; i++)
+#pragma unroll
+    for (int j = 0; j < 2; j++)
+#pragma unroll
+      for (int r = 0; r < 4; r++) {
+        const int gr = row0 + wr * 32 + i * 16 + 4 * (lane >> 4) + r;
+        const int gc = col0 + wc * 32 + j * 16 + (lane & 15);
+        ein[i][j][r] = (MODE == 0 && Ein)
+                           ? Ein[(int64_t)z * sE + (int64_t)min(gr, n - 1) * n + min(gc, n - 1)]
+                           : (gr == gc ? -1.0 : 0.0);
+      }
+#pragma unroll
+  for (int i = 0; i < 2; i++)
+#pragma unroll
+    for (int j = 0; j < 2; j++)
+#pragma unroll
+      for (int r = 0; r < 4; r++) {
+        const int gr = row0 + wr * 32 + i * 16 + 4 * (lane >> 4) + r;
+        const int gc = col0 + wc * 32 + j * 16 + (lane & 15);
+        if (gr >= n || gc >= n) continue;
+        const int64_t o = (int64_t)z * nn + (int64_t)gr * n + gc;
+        if (MODE == 0) {
+          int64_t v = 0;
+#pragma unroll
+          for (int s = 4; s >= 0; s--) v = v * 256 + (int64_t)acc[s][i][j][r];
+          ((double*)out0)[o] = quot_p(ein[i][j][r] + (double)v, pinv);
+        } else {
+          double v = 0.0;
+#pragma unroll
+          for (int s = 0; s < 5; s++) v += mod_c((double)acc[s][i][j][r], pd, pinv) * wgt[s];
+          v = mod_c(-v, pd, pinv);
+          ((uint32_t*)out0)[o] = (uint32_t)(v < 0 ? v + pd : v);
+        }
+      }
+}
+
 __device__ __forceinline__ int wave_sum_i32(int v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -1178,6 +1277,44 @@ hipError_t launch_hensel_f64(const int32_t* Ai, const uint32_t* C0, double* E, u
   k_hensel_f64<0><<<grid, 512, 0, st>>>((const void*)Ai, (const void*)C1, E, n, ps, 0, nn, nn, E);
   k_hensel_f64<1><<<grid, 512, 0, st>>>((const void*)C0, (const void*)E, nullptr, n, ps, nn, nn,
                                         0, C2);
+  return hipGetLastError();
+}
+
+size_t hensel_i8_scratch(int n, int np) {
+  const size_t R = (size_t)((n + 63) / 64) * 64;
+  return (1 + 4 * (size_t)np) * 3 * R * R;
+}
+
+hipError_t launch_hensel_i8(const int32_t* Ai, const uint32_t* C0, double* E, uint32_t* C1,
+                            uint32_t* C2, int n, const uint32_t* primes, int np, int8_t* planes,
+                            hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  PrimeSet ps;
+  if (!prime_set(primes, np, &ps) || !planes) return hipErrorInvalidValue;
+  for (int z = 0; z < np; z++)
+    if (primes[z] > 2u * (uint32_t)LIMB3_MAX + 1u) return hipErrorInvalidValue;
+  const int Kp = (n + 63) / 64 * 64;
+  const int64_t Rp = Kp, set = 3 * Rp * Kp, nn = (int64_t)n * n;
+  if (Kp > 43690) return hipErrorInvalidValue;     // int32 sums: 3 Kp 2^14 < 2^31
+  // planes: A (shared), then per prime the sets c0, c0^T, E^T, c1^T
+  int8_t* pA = planes;
+  int8_t* pc0 = planes + set;
+  int8_t* pc0T = pc0 + set;
+  int8_t* pET = pc0 + 2 * set;
+  int8_t* pc1T = pc0 + 3 * set;
+  const int64_t pst = 4 * set;                     // stride between primes
+  const dim3 gs(Kp / 64, (unsigned)(Rp / 64), np), gs1(Kp / 64, (unsigned)(Rp / 64), 1);
+  const dim3 gm((n + 63) / 64, (n + 63) / 64, np);
+  k_split_h<0><<<gs1, 256, 0, st>>>(Ai, 0, n, Kp, Rp, 0, pA, 0, ps);
+  k_split_h<1><<<gs, 256, 0, st>>>(C0, nn, n, Kp, Rp, 0, pc0, pst, ps);
+  k_split_h<1><<<gs, 256, 0, st>>>(C0, nn, n, Kp, Rp, 1, pc0T, pst, ps);
+  k_hensel_i8<0><<<gm, 256, 0, st>>>(pA, pc0T, 0, pst, Rp, Kp, n, ps, nullptr, 0, E);   // E_1
+  k_split_h<2><<<gs, 256, 0, st>>>(E, nn, n, Kp, Rp, 1, pET, pst, ps);
+  k_hensel_i8<1><<<gm, 256, 0, st>>>(pc0, pET, pst, pst, Rp, Kp, n, ps, nullptr, 0, C1);   // c_1
+  k_split_h<1><<<gs, 256, 0, st>>>(C1, nn, n, Kp, Rp, 1, pc1T, pst, ps);
+  k_hensel_i8<0><<<gm, 256, 0, st>>>(pA, pc1T, 0, pst, Rp, Kp, n, ps, E, nn, E);          // E_2
+  k_split_h<2><<<gs, 256, 0, st>>>(E, nn, n, Kp, Rp, 1, pET, pst, ps);
+  k_hensel_i8<1><<<gm, 256, 0, st>>>(pc0, pET, pst, pst, Rp, Kp, n, ps, nullptr, 0, C2);   // c_2
   return hipGetLastError();
 }
 

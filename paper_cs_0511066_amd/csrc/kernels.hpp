@@ -117,6 +117,10 @@ hipError_t launch_comb_digits(const uint32_t* digits, int64_t k, int n, const ui
 // of r) under a 7-bit tag, the step number mod 127; tag 127 (an all-ones
 // word) marks a word not yet written.  r of step 0 goes in with tag 0.
 constexpr uint32_t LIFT3_DIGIT_MASK = 0x1FFFFFFu;
+// Largest magnitude that three signed int8 limbs hold on both sides
+// (limb_word): the int8 paths need every operand value within it.
+constexpr int32_t LIMB3_MAX = 0x7F7F7F;
+
 // Several liftings side by side, one per prime (Section 6: p-adic liftings
 // in parallel, each with fewer steps): the primes of one launch, with their
 // reciprocals.
@@ -129,6 +133,13 @@ struct PrimeSet {
 // matrices each (prime z at offset z n^2); Ai is shared.
 hipError_t launch_hensel_f64(const int32_t* Ai, const uint32_t* C0, double* E, uint32_t* C1,
                              uint32_t* C2, int n, const uint32_t* primes, int np, hipStream_t st);
+// The same planes from int8 MFMA on three limbs of every operand: needs
+// |a_ij| <= 0x7F7F7F and every p <= 2 * 0x7F7F7F + 1; `planes` is device
+// scratch of hensel_i8_scratch(n, np) bytes.
+size_t hensel_i8_scratch(int n, int np);
+hipError_t launch_hensel_i8(const int32_t* Ai, const uint32_t* C0, double* E, uint32_t* C1,
+                            uint32_t* C2, int n, const uint32_t* primes, int np, int8_t* planes,
+                            hipStream_t st);
 // rv, xv: n x nrhs x 4 words, the digit vectors passed between workgroups (r
 // of step 0 in rv under tag 0, xv filled with all-ones words before the
 // launch); r: n x nrhs (row-major); digits of right-hand side h at

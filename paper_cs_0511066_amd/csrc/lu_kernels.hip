@@ -22,6 +22,7 @@
 #include "modp.hpp"
 #include "kernels.hpp"
 #include "panel.hpp"
+#include "i8tile.hpp"
 
 namespace detk {
 
@@ -618,14 +619,8 @@ __global__ __launch_bounds__(256) void k_trsm_apply(int32_t* __restrict__ W, int
 }
 
 // ------------------------------------------------------------------ int8 limb path
-// A centred residue |r| < 2^22 (p < 2^23) in balanced signed limbs,
-// r = l0 + 2^8 l1 + 2^16 l2 with every l in [-128, 127]: with
-// u = r + 0x808080 (0 < u < 2^24) and b_j the bytes of u, r = sum (b_j - 128)
-// 2^(8j), and b_j - 128 is the byte b_j ^ 0x80 read as a signed byte.  So the
-// three limbs are bytes 0..2 of (r + 0x808080) ^ 0x808080.
-__device__ __forceinline__ uint32_t limb_word(int32_t r) {
-  return (uint32_t)(r + 0x808080) ^ 0x808080u;
-}
+// Centred residues |r| < 2^22 (p < 2^23) in three balanced signed limbs
+// (limb_word, i8tile.hpp).
 
 // Limb planes of an M x K block (A: row-major, k contiguous) or of a K x N
 // block stored transposed (B: column j's K values contiguous), both padded
@@ -638,43 +633,10 @@ __global__ __launch_bounds__(256) void k_split(const int32_t* __restrict__ W, in
                                                int64_t Rp, int transpose, int8_t* __restrict__ P,
                                                int64_t pslab) {
   __shared__ uint32_t sT[64][65];
-  const int z = blockIdx.z, t = threadIdx.x;
-  const int ty = blockIdx.y * 64, tx = blockIdx.x * 64;   // tile: output rows ty.., k tx..
+  const int z = blockIdx.z;
   const int32_t* Wz = W + (int64_t)z * slab + off;
-  // source tile: W rows (ty.. for A, tx.. for B) x 64 columns; 16 words a thread
-  const int sr0 = transpose ? tx : ty, sc0 = transpose ? ty : tx;
-  const int srows = transpose ? K : rows, scols = transpose ? rows : K;
-  int32_t x[16];
-#pragma unroll
-  for (int u = 0; u < 16; u++) {                // every load in flight before any use
-    const int e = u * 256 + t, r = e >> 6, c = e & 63;
-    x[u] = Wz[(int64_t)min(sr0 + r, srows - 1) * ldw + min(sc0 + c, scols - 1)];
-  }
-#pragma unroll
-  for (int u = 0; u < 16; u++) {
-    const int e = u * 256 + t, r = e >> 6, c = e & 63;
-    sT[r][c] = limb_word((sr0 + r < srows && sc0 + c < scols) ? x[u] : 0);
-  }
-  __syncthreads();
-  // output: 64 rows x 16 words of four k values, per plane; 4 words a thread
-  int8_t* Pz = P + (int64_t)z * pslab;
-  const int64_t plane = Rp * (int64_t)Kp;
-#pragma unroll
-  for (int u = 0; u < 4; u++) {
-    const int e = u * 256 + t, orow = e >> 4, kq = (e & 15) * 4;
-    uint32_t w[4];
-#pragma unroll
-    for (int q = 0; q < 4; q++) w[q] = transpose ? sT[kq + q][orow] : sT[orow][kq + q];
-#pragma unroll
-    for (int pl = 0; pl < 3; pl++) {
-      // bytes pl of w0, w1 (and of w2, w3), then the two halves together
-      const uint32_t sel = (uint32_t)pl | (uint32_t)(pl + 4) << 8 | 0x0c0c0000u;
-      const uint32_t lo = __builtin_amdgcn_perm(w[1], w[0], sel);
-      const uint32_t hi = __builtin_amdgcn_perm(w[3], w[2], sel);
-      const uint32_t word = __builtin_amdgcn_perm(hi, lo, 0x05040100u);
-      *(uint32_t*)(Pz + pl * plane + (int64_t)(ty + orow) * Kp + tx + kq) = word;
-    }
-  }
+  limb_split_tile([&](int r, int c) { return Wz[(int64_t)r * ldw + c]; }, rows, K, Kp, Rp,
+                  transpose, P + (int64_t)z * pslab, sT);
 }
 
 // C[z] = (C[z] - A[z] B[z]) mod p_z with A, B given as limb planes (Rp x Kp,
@@ -684,8 +646,6 @@ __global__ __launch_bounds__(256) void k_split(const int32_t* __restrict__ W, in
 // The next K chunk's loads are in flight during this chunk's products.
 // Lane l supplies A[l%16][16(l/16) .. +16) and B^T[l%16][same k]; result
 // element r of lane l is D[4(l/16) + r][l%16].
-constexpr int GI_K = 64;
-constexpr int GI_LD = GI_K + 16;   // row stride 80 B: 16-byte reads conflict-free
 
 __global__ __launch_bounds__(256) void k_gemm_i8(int32_t* __restrict__ W, int64_t slab,
                                                  int64_t offC, int64_t ldw, int M, int N,
@@ -701,64 +661,10 @@ __global__ __launch_bounds__(256) void k_gemm_i8(int32_t* __restrict__ W, int64_
   const int row0 = blockIdx.y * GB_M, col0 = blockIdx.x * GB_N;
   const int8_t* Az = PA + (int64_t)z * pslabA;
   const int8_t* Bz = PB + (int64_t)z * pslabB;
-  const int64_t planeA = MpA * Kp, planeB = NpB * Kp;
-
-  __shared__ __attribute__((aligned(16))) int8_t sA[3][GB_M][GI_LD];
-  __shared__ __attribute__((aligned(16))) int8_t sB[3][GB_N][GI_LD];
-
-  // 3 planes x 64 rows x 64 bytes per operand = 768 chunks of 16 B; 3 a thread
-  v4i ga[3], gb[3];
-  auto gload = [&](int k0) {
-#pragma unroll
-    for (int u = 0; u < 3; u++) {
-      const int e = t + u * 256;
-      const int pl = e >> 8, rem = e & 255, r = rem >> 2, q = (rem & 3) * 16;
-      ga[u] = *(const v4i*)(Az + pl * planeA + (int64_t)(row0 + r) * Kp + k0 + q);
-      gb[u] = *(const v4i*)(Bz + pl * planeB + (int64_t)(col0 + r) * Kp + k0 + q);
-    }
-  };
-  v4i acc[5][2][2];
-#pragma unroll
-  for (int s = 0; s < 5; s++)
-#pragma unroll
-    for (int i = 0; i < 2; i++)
-#pragma unroll
-      for (int j = 0; j < 2; j++) acc[s][i][j] = (v4i){0, 0, 0, 0};
-
-  gload(0);
-  for (int k0 = 0; k0 < Kp; k0 += GI_K) {
-#pragma unroll
-    for (int u = 0; u < 3; u++) {
-      const int e = t + u * 256;
-      const int pl = e >> 8, rem = e & 255, r = rem >> 2, q = (rem & 3) * 16;
-      *(v4i*)(&sA[pl][r][q]) = ga[u];
-      *(v4i*)(&sB[pl][r][q]) = gb[u];
-    }
-    __syncthreads();
-    if (k0 + GI_K < Kp) gload(k0 + GI_K);
-    v4i af[3][2], bf[3][2];
-#pragma unroll
-    for (int pl = 0; pl < 3; pl++) {
-#pragma unroll
-      for (int i = 0; i < 2; i++)
-        af[pl][i] = *(const v4i*)(&sA[pl][wr * 32 + i * 16 + (lane & 15)][16 * (lane >> 4)]);
-#pragma unroll
-      for (int j = 0; j < 2; j++)
-        bf[pl][j] = *(const v4i*)(&sB[pl][wc * 32 + j * 16 + (lane & 15)][16 * (lane >> 4)]);
-    }
-#pragma unroll
-    for (int i = 0; i < 2; i++)
-#pragma unroll
-      for (int j = 0; j < 2; j++) {
-#pragma unroll
-        for (int a = 0; a < 3; a++)
-#pragma unroll
-          for (int b = 0; b < 3; b++)
-            acc[a + b][i][j] =
-                __builtin_amdgcn_mfma_i32_16x16x64_i8(af[a][i], bf[b][j], acc[a + b][i][j], 0, 0, 0);
-      }
-    __syncthreads();
-  }
+  __shared__ __attribute__((aligned(16))) int8_t sA[3][I8_TILE][I8_LD];
+  __shared__ __attribute__((aligned(16))) int8_t sB[3][I8_TILE][I8_LD];
+  v4i_t acc[5][2][2];
+  i8_tile_product(Az, Bz, MpA * Kp, NpB * Kp, Kp, row0, col0, sA, sB, acc);
   // weights 2^(8s) mod p, centred
   double wgt[5];
   wgt[0] = 1.0;
@@ -1047,7 +953,7 @@ hipError_t launch_gemm_i8(int32_t* W, int64_t slab, int64_t offC, int64_t ldw, i
                           int64_t MpA, int64_t NpB, int Kp, const Modulus* mods, int nitems,
                           hipStream_t st) {
   if (M <= 0 || N <= 0 || Kp <= 0 || nitems <= 0) return hipSuccess;
-  if (Kp % GI_K || MpA % GB_M || NpB % GB_N || MpA < M || NpB < N || Kp > 43690)
+  if (Kp % I8_K || MpA % GB_M || NpB % GB_N || MpA < M || NpB < N || Kp > 43690)
     return hipErrorInvalidValue;
   dim3 grid((N + GB_N - 1) / GB_N, (M + GB_M - 1) / GB_M, nitems);
   k_gemm_i8<<<grid, 256, 0, st>>>(W, slab, offC, ldw, M, N, PA, PB, pslabA, pslabB, MpA, NpB, Kp,

@@ -276,6 +276,30 @@ def test_dixon_lift_inverse_pivot_paths(ctx, case, monkeypatch):
     assert np.array_equal(X.astype(np.int64), oracle.dixon_digits(A, b, p, k))
 
 
+@pytest.mark.parametrize("n,lo,hi", [(64, -100, 100), (40, -(1 << 22), 1 << 22), (200, 0, 255),
+                                     (129, -3000, 3000)])
+def test_dixon_lift_hensel_forms_agree(n, lo, hi, monkeypatch):
+    """The Hensel planes of A^{-1} mod p^3 from int8 MFMA on three signed
+    limbs of every operand (entries of A and centred residues within
+    0x7F7F7F, p below 2^24) and from FP64 MFMA give the same digits, the
+    oracle's; entries near 2^22 use the limbs' full range, and n = 129 and
+    200 leave ragged tiles."""
+    import paper_cs_0511066_amd as det
+    A = synth.dense_uniform(n, lo, hi, n + 5)
+    b = synth.random_rhs(n, 1000, n + 6)
+    p = test_primes(1 << 23, 16711423, 1, n)[0]
+    k = 30
+    ref = oracle.dixon_digits(A, b, p, k)
+    for mode in (None, "f64"):
+        if mode is None:
+            monkeypatch.delenv("DET_HENSEL", raising=False)
+        else:
+            monkeypatch.setenv("DET_HENSEL", mode)
+        with det.Context(0) as cx:
+            X = cx.dixon_lift(A, b, p, k)
+        assert np.array_equal(X.astype(np.int64), ref), mode
+
+
 def test_dixon_lift_past_the_tag_wrap_matches_oracle(ctx):
     """A long lifting in the FP64 three-digit form: 450 digits are 150 steps,
     past the 127 values of the step tag that the kernel's workgroups exchange
