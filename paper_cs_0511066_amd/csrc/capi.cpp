@@ -40,7 +40,7 @@ constexpr int MAX_N = 4096;
 // blocks of NB_OUTER columns so that the trailing update contracts over 128.
 constexpr int TWO_LEVEL_MIN_ITEMS = 64;
 // liftings side by side when det_opts.lift_primes is 0
-constexpr int LIFT_PRIMES_AUTO = 2;
+constexpr int LIFT_PRIMES_AUTO = 4;
 
 // Largest K such that K h^2 + h <= 2^53 with h = (pmax - 1)/2: FP64 sums of
 // that many products of centred residues are exact.
@@ -352,6 +352,29 @@ det_status inverse_from_lu(det_ctx* c, LuWs& w, const LuJob& J, int64_t* col_out
   return DET_OK;
 }
 
+// Waits for `ev` (recorded already) by polling it: the host spins instead of
+// sleeping in a blocking wait, which can leave it asleep for a few hundred
+// microseconds after the device has finished.
+det_status spin_event(det_ctx* c, hipEvent_t ev) {
+  for (;;) {
+    const hipError_t q = hipEventQuery(ev);
+    if (q == hipSuccess) return DET_OK;
+    if (q != hipErrorNotReady) return fail(c, DET_E_DEVICE, hipGetErrorString(q));
+    __builtin_ia32_pause();
+  }
+}
+
+// Waits for everything queued on st so far, by polling an event of its own.
+det_status spin_stream(det_ctx* c, hipStream_t st) {
+  hipEvent_t e = nullptr;
+  HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  det_status r = DET_OK;
+  if (hipEventRecord(e, st) != hipSuccess) r = fail(c, DET_E_DEVICE, "event record failed");
+  else r = spin_event(c, e);
+  (void)hipEventDestroy(e);
+  return r;
+}
+
 // Validates A and returns a device pointer to it (uploading host memory into
 // the context's A buffer) with its leading dimension.
 det_status stage_matrix(det_ctx* c, const int64_t* A, int64_t n, int64_t lda,
@@ -392,7 +415,7 @@ det_status matrix_bounds(det_ctx* c, const int64_t* A, int64_t lda, bool on_devi
   HIPCHK(detk::launch_norms(dA, dlda, (int)n, dn, dn + 2 * n, c->st));
   const double* h = (const double*)c->hnorms.p;
   HIPCHK(hipMemcpyAsync((void*)h, dn, 3 * n * sizeof(double), hipMemcpyDeviceToHost, c->st));
-  HIPCHK(hipStreamSynchronize(c->st));
+  TRY(spin_stream(c, c->st));
   double amax = 0;
   for (int64_t i = 0; i < n; i++) amax = std::max(amax, h[2 * n + i]);
   if (amax >= 2147483648.0) return fail(c, DET_E_OVERFLOW, "matrix entry with |a_ij| >= 2^31");
@@ -516,6 +539,7 @@ uint64_t inv_mod_2_64(uint64_t p) {
 // A^{-1} mod p into c->Cu (canonical, n x n), from a staged device matrix,
 // on workspace ws[0].  Returns DET_E_SINGULAR_MOD_P if p | det(A).
 det_status ensure_pinned(det_ctx* c, size_t count);
+
 
 // A^{-1} mod p_z into c->Cu + z n^2 (canonical, n x n) for np primes at once
 // (np > 1 needs n <= 1024; the items of one batched LU of [A | I]), on
@@ -1024,7 +1048,7 @@ void det_ctx_destroy(det_ctx* c) {
   for (DevBuf* b : all)
     if (b->p) (void)hipFree(b->p);
   if (c->hres) (void)hipHostFree(c->hres);
-  for (PinBuf* pb : {&c->hstage, &c->hsmall, &c->hnorms, &c->ws[0].hmods, &c->ws[1].hmods,
+  for (PinBuf* pb : {&c->hstage, &c->hsmall, &c->hnorms, &c->hcomb, &c->ws[0].hmods, &c->ws[1].hmods,
                      &c->ws[0].hflags, &c->ws[1].hflags, &c->q_hitems, &c->q_hout})
     if (pb->p) (void)hipHostFree(pb->p);
   for (auto& pr : c->prof_pending) {
@@ -1363,9 +1387,11 @@ det_status det_introspective(det_ctx* c, const int64_t* A, int64_t n, int64_t ld
     const double logl_H0 = std::max(1.0, bd.log2_h / log2_l);
     const int64_t k0 = dethost::et_run_length(o.log2_inv_eps, dethost::prime_set_size(bits), logl_H0);
     // (two more primes than the run: a determinant of up to two primes' worth
-    // of bits ends the CRA within the batch)
+    // of bits ends the CRA within the batch; the inverse's LU adds residues
+    // modulo the np lifting primes, so the batch is np primes shorter)
     const bool solving = bd.log2_h > 0 && dixon_bits > 12;
-    const int64_t batch1 = k0 > 0 ? std::min<int64_t>(k0 + 2, 64) : 16;
+    const int64_t batch1 =
+        k0 > 0 ? std::min<int64_t>(std::max<int64_t>(k0 + 2 - (solving ? np : 0), 4), 64) : 16;
     TRY(ensure_pinned(c, (size_t)batch1 + 64));
     HIPCHK(hipEventRecord(c->ev_cra, c->st));          // A (and its bounds) are ready on st
     auto draw_dixon = [&](uint32_t* dps) {
@@ -1497,7 +1523,7 @@ det_status det_introspective(det_ctx* c, const int64_t* A, int64_t n, int64_t ld
     auto take_batch1 = [&]() -> det_status {       // the background batch, once
       cra_join.join();
       TRY(cra_st);
-      HIPCHK(hipStreamSynchronize(c->own2));
+      TRY(spin_stream(c, c->own2));
       if (cra_def.count) {
         // a prime whose block-pivot LU met an all-zero block column: again
         // with the full pivot search
@@ -1520,7 +1546,7 @@ det_status det_introspective(det_ctx* c, const int64_t* A, int64_t n, int64_t ld
       // the lifting primes' residues from the inverse's LU (free extra CRA
       // residues), when its block pivot search found every pivot
       if (solving && st0 == DET_OK && inv_flag0) {
-        HIPCHK(hipEventSynchronize(c->ev_det));
+        TRY(spin_event(c, c->ev_det));
         bool ok = true;
         for (int z = 0; z < np; z++) ok &= inv_flag0[z] == 0;
         if (ok) {
@@ -1573,7 +1599,6 @@ det_status det_introspective(det_ctx* c, const int64_t* A, int64_t n, int64_t ld
         bool crt_ready = false;
         uint32_t* dig = (uint32_t*)c->digits.p;
         std::vector<uint32_t> R((size_t)i_max * npad, 0);
-        std::vector<uint64_t> comb;
         BigInt K_prev = BigInt::from_i64(1);
         // every launch of the background batch is on own2 before the first
         // lifting waits for it (the cooperative lifting needs its workgroups
@@ -1632,6 +1657,14 @@ det_status det_introspective(det_ctx* c, const int64_t* A, int64_t n, int64_t ld
             HIPCHK(hipStreamSynchronize(c->st));
             inv_flag = nullptr;
             c->block_pivot_retries++;
+            // before the inverse is redone (with the full search) and a
+            // solving run, the CRA on det itself resumes for about that
+            // long: a small determinant ends there (Alg. 4.1 stops when the
+            // CRA has terminated)
+            if (o.adaptive && K.cmp(BigInt::from_i64(1)) == 0) {
+              TRY(cra_run(now_ms() - tl0));
+              if (done) break;
+            }
             redo = true;
             break;
           }
@@ -1644,8 +1677,12 @@ det_status det_introspective(det_ctx* c, const int64_t* A, int64_t n, int64_t ld
                     dig + ((size_t)h * np + z) * k * n, k, (int)n,
                     (const uint32_t*)c->cvec.p + (size_t)a * npad,
                     (uint64_t*)c->comb.p + (((size_t)h * i + a) * np + z) * k, c->st));
-          comb.resize((size_t)i * i * np * k);
-          HIPCHK(hipMemcpyAsync(comb.data(), c->comb.p, comb.size() * sizeof(uint64_t),
+          // (into pinned memory: a copy into pageable memory would hold the
+          // host until the lifting has ended)
+          const size_t ncomb = (size_t)i * i * np * k;
+          TRY(ensure_pin(c, c->hcomb, ncomb * sizeof(uint64_t), c->st));
+          uint64_t* comb = (uint64_t*)c->hcomb.p;
+          HIPCHK(hipMemcpyAsync(comb, c->comb.p, ncomb * sizeof(uint64_t),
                                 hipMemcpyDeviceToHost, c->st));
           if (!crt_ready) {
             // the remaindering constants of the primes, while the device lifts
@@ -1654,7 +1691,7 @@ det_status det_introspective(det_ctx* c, const int64_t* A, int64_t n, int64_t ld
             crt_ready = true;
             t_host += now_ms() - th;
           }
-          HIPCHK(hipStreamSynchronize(c->st));
+          TRY(spin_stream(c, c->st));
           if (inv_flag) {
             bool bad = false;
             for (int z = 0; z < np; z++) bad |= inv_flag[z] != 0;
@@ -1671,7 +1708,7 @@ det_status det_introspective(det_ctx* c, const int64_t* A, int64_t n, int64_t ld
           const double th0 = now_ms();
           BigInt sv, pi;
           const int64_t failed =
-              dethost::extended_bonus_host(comb.data(), i, k, dps, np, Nbits, Dbits, &crt_p, sv, pi);
+              dethost::extended_bonus_host(comb, i, k, dps, np, Nbits, Dbits, &crt_p, sv, pi);
           K = BigInt::div_exact(K * sv, BigInt::gcd(K, sv));
           K = BigInt::div_exact(K * pi, BigInt::gcd(K, pi));
           if (i >= 2) rep.bonus_factors = failed ? -i : i;

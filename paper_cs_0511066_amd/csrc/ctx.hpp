@@ -62,6 +62,7 @@ struct det_ctx {
   PinBuf hstage;                 // pinned staging of the lifting's vectors and results
   PinBuf hsmall;                 // pinned flags and error words read back on st
   PinBuf hnorms;                 // pinned read-back of the column and row norms
+  PinBuf hcomb;                  // pinned read-back of the combination sums of the liftings
   int lift_mode = 0;             // 0: fastest cooperative form that applies; 1: one launch per
                                  // phase; 2: the 64-bit integer form modulo p^2
   bool block_pivots = true;      // the inverse's panels search their diagonal block first
