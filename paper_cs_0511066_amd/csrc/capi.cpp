@@ -409,10 +409,10 @@ det_status matrix_bounds(det_ctx* c, const int64_t* A, int64_t lda, bool on_devi
   }
   // column sums, row sums and row maxima in one buffer, read back with one
   // copy into pinned memory
-  TRY(ensure(c, c->norms, (size_t)3 * n * sizeof(double)));
+  TRY(ensure(c, c->norms, ((size_t)3 * n + detk::norms_scratch((int)n)) * sizeof(double)));
   TRY(ensure_pin(c, c->hnorms, (size_t)3 * n * sizeof(double), c->st));
   double* dn = (double*)c->norms.p;
-  HIPCHK(detk::launch_norms(dA, dlda, (int)n, dn, dn + 2 * n, c->st));
+  HIPCHK(detk::launch_norms_wide(dA, dlda, (int)n, dn, dn + 2 * n, dn + 3 * n, c->st));
   const double* h = (const double*)c->hnorms.p;
   HIPCHK(hipMemcpyAsync((void*)h, dn, 3 * n * sizeof(double), hipMemcpyDeviceToHost, c->st));
   TRY(spin_stream(c, c->st));
@@ -1381,9 +1381,11 @@ det_status det_introspective(det_ctx* c, const int64_t* A, int64_t n, int64_t ld
       np = std::max(1, np);
     }
     rep.lift_primes = np;
-    // The first inverse is the head of the critical path: it is enqueued
-    // before the CRA batch is set up (the pinned read-back words it uses are
-    // sized for the batch first, and A is marked ready for the batch's stream).
+    // The first lifting waits for both the first inverse (with its Hensel
+    // step) and the first CRA batch, which take about as long as each other:
+    // the batch's thread starts first, then the inverse is enqueued beside it
+    // (the pinned read-back words both use are sized for the batch first, and
+    // A is marked ready for the batch's stream).
     const double logl_H0 = std::max(1.0, bd.log2_h / log2_l);
     const int64_t k0 = dethost::et_run_length(o.log2_inv_eps, dethost::prime_set_size(bits), logl_H0);
     // (two more primes than the run: a determinant of up to two primes' worth
@@ -1407,24 +1409,16 @@ det_status det_introspective(det_ctx* c, const int64_t* A, int64_t n, int64_t ld
     std::vector<uint32_t> ps1(batch1);
     for (auto& q : ps1) q = samp.next();
     uint32_t* hres1 = c->hres + 64;                  // (c->hres[0..63]: the inverse's read-backs)
-    uint32_t dps0[detk::LIFT_MAX_PRIMES] = {0, 0, 0, 0};
-    det_status st0 = DET_E_SINGULAR_MOD_P;
-    const int32_t* inv_flag0 = nullptr;
-    uint32_t* hdet0 = c->hres + 32;                  // det(A) mod the lifting primes
-    if (solving) {
-      draw_dixon(dps0);
-      st0 = inverse_mod_primes(c, dA, dlda, (int)n, dps0, np, &inv_flag0, hdet0, c->ev_det);
-    }
-
     // ---------------- CRA batch 1 on the second stream (Section 4: the
     // modular determinants run in the background while the systems are
     // solved).  Its size covers the run length of Lemma 2.1(iv) for the
     // bound H itself; once s_n is known, fewer may be needed.
     const double tc0 = now_ms();
     HIPCHK(hipStreamWaitEvent(c->own2, c->ev_cra, 0));
-    // A second host thread enqueues the batch (some seventy launches), so that
-    // the Dixon solve's launches start at once.  It uses only ws[1], own2 and
-    // hres1; it is joined before anything waits for own2.
+    // A second host thread enqueues the batch (some seventy launches) while
+    // this one enqueues the inverse.  It uses only ws[1], own2 and hres1
+    // (the inverse's read-backs are c->hres[0..63], already allocated); it is
+    // joined before anything waits for own2.
     det_status cra_st = DET_OK;
     Deferred cra_def;
     std::thread cra_thread;
@@ -1457,6 +1451,15 @@ det_status det_introspective(det_ctx* c, const int64_t* A, int64_t n, int64_t ld
       }
     }};
     cra_join.run();
+
+    uint32_t dps0[detk::LIFT_MAX_PRIMES] = {0, 0, 0, 0};
+    det_status st0 = DET_E_SINGULAR_MOD_P;
+    const int32_t* inv_flag0 = nullptr;
+    uint32_t* hdet0 = c->hres + 32;                  // det(A) mod the lifting primes
+    if (solving) {
+      draw_dixon(dps0);
+      st0 = inverse_mod_primes(c, dA, dlda, (int)n, dps0, np, &inv_flag0, hdet0, c->ev_det);
+    }
 
     // ---------------- The CRA loop on det(A)/K (Alg. 2.1 on the quotient,
     // Section 4): every residue computed so far is kept (d_i = det mod p_i)

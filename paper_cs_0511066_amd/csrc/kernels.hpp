@@ -195,6 +195,11 @@ hipError_t launch_lu_queue(int variant, int grid, const LuItem* items, int nitem
 hipError_t launch_pack_i32(const int64_t* A, int64_t lda, int n, int32_t* Ai, hipStream_t st);
 hipError_t launch_norms(const int64_t* A, int64_t lda, int n, double* out2n, double* amax,
                         hipStream_t st);
+// The same over a grid of 64 x 64 blocks (one launch for the partial sums,
+// one to add them); part: norms_scratch(n) doubles of device scratch.
+size_t norms_scratch(int n);
+hipError_t launch_norms_wide(const int64_t* A, int64_t lda, int n, double* out2n, double* amax,
+                             double* part, hipStream_t st);
 
 // Configure dynamic-LDS limits once per device.
 hipError_t configure_kernels();

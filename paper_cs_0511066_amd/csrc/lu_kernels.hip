@@ -809,6 +809,69 @@ __global__ __launch_bounds__(256) void k_row_norms(const int64_t* __restrict__ A
   if (lane == 0) out[n + i] = s;
 }
 
+// The same sums over the whole chip: workgroup (x, y) takes the 64 columns
+// [64x, 64x + 64) of the 64 rows [64y, 64y + 64) (a wave 16 rows, a lane a
+// column) and writes its partial column sums and maxima (part[y][j],
+// part[Y + y][j], Y = gridDim.y) and partial row sums (part[2Y + x][i]);
+// k_norm_finish adds the partials of each column and row in a fixed order,
+// so the bounds do not depend on the schedule.
+__global__ __launch_bounds__(256) void k_norm_part(const int64_t* __restrict__ A, int64_t lda,
+                                                   int n, double* __restrict__ part) {
+  __shared__ double s_s[4][64];
+  __shared__ double s_m[4][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int j = blockIdx.x * 64 + lane;
+  const int Y = gridDim.y;
+  double* const rowp = part + (size_t)(2 * Y + blockIdx.x) * n;
+  double s = 0.0, m = 0.0;
+  const int i0 = blockIdx.y * 64 + wv * 16;
+  double a[16];
+#pragma unroll
+  for (int r = 0; r < 16; r++) {
+    const int i = i0 + r;
+    a[r] = (i < n && j < n) ? (double)A[(int64_t)i * lda + j] : 0.0;
+  }
+#pragma unroll
+  for (int r = 0; r < 16; r++) {
+    s = fma(a[r], a[r], s);
+    m = fmax(m, fabs(a[r]));
+    double rs = a[r] * a[r];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) rs += __shfl_xor(rs, off, 64);
+    if (lane == 0 && i0 + r < n) rowp[i0 + r] = rs;
+  }
+  s_s[wv][lane] = s;
+  s_m[wv][lane] = m;
+  __syncthreads();
+  if (wv == 0 && j < n) {
+    part[(size_t)blockIdx.y * n + j] = ((s_s[0][lane] + s_s[1][lane]) + s_s[2][lane]) + s_s[3][lane];
+    part[(size_t)(Y + blockIdx.y) * n + j] =
+        fmax(fmax(s_m[0][lane], s_m[1][lane]), fmax(s_m[2][lane], s_m[3][lane]));
+  }
+}
+
+// Thread t < n: column t's sum and maximum over the Y row chunks; thread
+// n + i: row i's sum over the X column strips.
+__global__ __launch_bounds__(256) void k_norm_finish(const double* __restrict__ part, int n, int X,
+                                                     int Y, double* __restrict__ out2n,
+                                                     double* __restrict__ amax) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t < n) {
+    double s = 0.0, m = 0.0;
+    for (int y = 0; y < Y; y++) {
+      s += part[(size_t)y * n + t];
+      m = fmax(m, part[(size_t)(Y + y) * n + t]);
+    }
+    out2n[t] = s;
+    amax[t] = m;
+  } else if (t < 2 * n) {
+    const int i = t - n;
+    double s = 0.0;
+    for (int x = 0; x < X; x++) s += part[(size_t)(2 * Y + x) * n + i];
+    out2n[n + i] = s;
+  }
+}
+
 // ------------------------------------------------------------------ launchers
 #define LAUNCH_CHECK() do { hipError_t e_ = hipGetLastError(); if (e_ != hipSuccess) return e_; } while (0)
 
@@ -993,6 +1056,22 @@ hipError_t launch_norms(const int64_t* A, int64_t lda, int n, double* out2n, dou
   k_col_norms<<<(n + 63) / 64, 1024, 0, st>>>(A, lda, n, out2n, amax);
   LAUNCH_CHECK();
   k_row_norms<<<(n + 3) / 4, 256, 0, st>>>(A, lda, n, out2n);
+  LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+size_t norms_scratch(int n) {
+  const size_t b = (size_t)(n + 63) / 64;
+  return 3 * b * (size_t)n;
+}
+
+hipError_t launch_norms_wide(const int64_t* A, int64_t lda, int n, double* out2n, double* amax,
+                             double* part, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int b = (n + 63) / 64;
+  k_norm_part<<<dim3(b, b), 256, 0, st>>>(A, lda, n, part);
+  LAUNCH_CHECK();
+  k_norm_finish<<<(2 * n + 255) / 256, 256, 0, st>>>(part, n, b, b, out2n, amax);
   LAUNCH_CHECK();
   return hipSuccess;
 }

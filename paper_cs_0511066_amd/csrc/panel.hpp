@@ -470,68 +470,169 @@ __device__ __forceinline__ void panel_body(int32_t* __restrict__ Wr, int64_t ldw
 // ------------------------------------------------------------------ diagonal block body
 // Factors the pb x pb diagonal block (pb <= 32) whose top-left entry is Wb
 // (leading dimension ldw) without a pivot search below it.  Two eliminations
-// of a 32 x 64 block run side by side, each held whole by one wave (lane c =
-// column c, X[i] = row i, so a step needs no exchange between waves and no
-// barrier): [A11 | I] in wave 0 and [A11^T | I] in wave 1 (a block narrower
-// than 32 is padded with the identity).  A fraction-free elimination, row_i
-// <- b_k row_i - r_ik row_k for i > k with b_k = the pivot-column entry of
-// row k, leaves row i scaled by sigma_i = b_0 ... b_{i-1}, so no inverse is
-// needed inside the loop:
+// run side by side, each held whole by one wave, so a step needs no exchange
+// between waves and no barrier: [A11 | I] in wave 0 and [A11^T | I] in wave 1
+// (a block narrower than 32 is padded with the identity).  A fraction-free
+// elimination, row_i <- b_k row_i - r_ik row_k for i > k with b_k = the
+// pivot-column entry of row k, leaves row i scaled by sigma_i = b_0 ...
+// b_{i-1}, so no inverse is needed inside the loop:
 //  - [A11 | I] gives [U | L^{-1}] row by row after the scaling 1 / sigma_i;
 //  - A11^T = L_T U_T with L_T = U'^T and U_T = D L^T (U = D U', D =
 //    diag(u_ii), U' unit upper), whose pivots, and so whose b_i, are those of
 //    A11; [A11^T | I] gives L_T^{-1} = (U'^{-1})^T after the scaling
 //    1 / sigma_i, and U^{-1} = U'^{-1} D^{-1} with u_ii = b_i / sigma_i, so
 //    U^{-1}[c][i] = (row i of the second elimination)[c] / b_i.
+// Layout.  At step k the live columns of [A11 | I] are the left columns
+// k..31 and the right columns 32..32+k: the left column k is eliminated at
+// step k (its entries below row k become 0), and the right column 32+k is
+// zero outside row k (where it holds sigma_k) until step k.  So one lane
+// holds the left column c until step c and the right column 32+c from then
+// on, and 32 lanes hold the whole block: at step c lane c updates its rows
+// below c as b' = 0, pivot-row entry sigma_c, which turns them into the
+// right column's -r_ic sigma_c.  Rows above c keep U's column c, and row c
+// keeps b_c (U's diagonal) in wave 0 or sigma_c (the right column's entry,
+// wanted for U^{-1}[c][c]) in wave 1.  The two 32-lane halves of a wave then
+// split the rows: lanes 0..31 hold rows 0..15 and lanes 32..63 rows 16..31
+// (lane = column c & 31, slot s = row s + 16 * half), and one instruction
+// updates a row of each half.  The multipliers r_ik come from lane k of the
+// same half by ds_swizzle (issued right after the row's previous update, so
+// they are in flight during the rest of the step), the pivot row of the
+// upper half reaches the lower half by ds_bpermute.  While k < 16 the upper
+// half also runs the updates of its finished rows (its slots <= k); their
+// results are discarded (each upper row is copied out when it becomes final,
+// at the start of its own step), which keeps every step one instruction
+// stream with no lane masking.  Steps 16 and later issue only the slots of
+// rows still below the pivot.
 // The 32 inverses a wave needs (1 / sigma_i in wave 0, 1 / b_i in wave 1)
-// come from one Fermat ladder run by the 32 lanes side by side; sigma_i is
-// the running product of the pivots, kept beside the elimination.
+// come from one Fermat ladder run by the lanes side by side (lane c of half
+// h for index (c + 16 h) mod 32, so that the scale of slot s is read from lane
+// s of either half); sigma_i is the running product of the pivots, kept beside
+// the elimination.
 // Outputs: U11 into the block (on and above the diagonal), L11^{-1} and
 // U11^{-1} dense 32 x 32 row-major at Lz, Uz (zero outside pb x pb),
 // piv_z[j0 + i] = j0 + i, *flag = 1 when a pivot is 0 mod p (the caller then
 // runs the full pivot search).  Values stay below (p + 9) / 2 in magnitude
 // through the loose reductions, so every product is below 2^52.  Waves 2 and
-// up of the workgroup do nothing here, and no LDS is used.
+// up of the workgroup do nothing here; no LDS memory is used (the swizzles
+// and permutes only use its crossbar).
 
-// Step K of the fraction-free elimination of the 32 x 64 block X (lane =
-// column), then the steps after it (a compile-time recursion, so that every
-// row index is a register): the rows below the pivot in groups of G, each
-// phase over the group before the next, so that independent FP64 chains fill
-// the pipeline of the one wave that runs them.
+// x from lane K of each 32-lane half (ds_swizzle, bitmask mode: and 0, or K).
+template <int K>
+__device__ __forceinline__ double bcast_half(double x) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, x);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_swizzle((int)(uint32_t)u, K << 5);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_swizzle((int)(uint32_t)(u >> 32), K << 5);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// x from the lane whose byte address is addr (ds_bpermute).
+__device__ __forceinline__ double bpermute_d(int addr, double x) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, x);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)u);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)(u >> 32));
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// State of the elimination carried from step to step.
+struct DiagElim {
+  double X[16];      // slot s: row s + 16 * half of this lane's column
+  double M[16];      // the next step's multipliers (its pivot column, per slot)
+  double F[16];      // upper half: row s as it was when it became final
+  double xkn;        // lower half: the next pivot row's entry, from the upper half
+  double bnext;      // the next pivot b_k (uniform)
+  double S;          // running product of the pivots (uniform)
+  double sig, bl;    // sigma_j and b_j for this lane's ladder index j
+  bool zero;
+};
+
+// Step K, then the steps after it (a compile-time recursion, so that every
+// slot index is a register).  Within a step the slots go in groups of G,
+// each phase over the group before the next, so that independent FP64 chains
+// fill the pipeline; a scheduling barrier between steps and between groups
+// keeps the compiler from chaining one slot through several steps (which
+// would wait on every swizzle).
 template <int K, int G>
-__device__ __forceinline__ void diag_elim_step(double (&X)[32], double& S, double& sig,
-                                               double& bl, bool& zero, int lane, double p,
-                                               double pinv) {
+__device__ __forceinline__ void diag_elim_step(DiagElim& e, int L, int h, int xaddr, bool tr,
+                                               double p, double pinv) {
   if constexpr (K < 32) {
     constexpr double RND = 6755399441055744.0;
-    const double braw = readlane_d(X[K], K);
-    zero |= braw == 0.0;
+    constexpr int hK = K >> 4, sK = K & 15;
+    constexpr int K1 = K + 1, hK1 = K1 >> 4, sK1 = K1 & 15;
+    __builtin_amdgcn_sched_barrier(0);
+    const double braw = e.bnext;
+    e.zero |= braw == 0.0;
     const double bk = braw == 0.0 ? 1.0 : braw;      // (the result is discarded then)
-    sig = lane == K ? S : sig;                       // sigma_K = b_0 ... b_{K-1}
-    bl = lane == K ? bk : bl;
-    S = mul_mod_loose(S, bk, p, pinv);
-    const double xk = X[K];
+    const bool atK = L == K;
+    const double Sk = e.S;                           // sigma_K
+    double xk;                                       // pivot row K, this lane's column
+    if constexpr (hK == 0) {
+      const double own = e.X[sK];
+      xk = h ? e.xkn : own;
+      e.F[sK] = (atK && tr) ? Sk : own;
+    } else {
+      xk = e.X[sK];
+    }
+    const bool jK = ((L + 16 * h) & 31) == K;
+    e.sig = jK ? Sk : e.sig;
+    e.bl = jK ? bk : e.bl;
+    const double bkp = atK ? 0.0 : bk;
+    const double xkp = atK ? Sk : xk;
+    e.S = mul_mod_loose(e.S, bk, p, pinv);
+    constexpr int s0 = hK == 0 ? 0 : sK + 1;
 #pragma unroll
-    for (int i0 = K + 1; i0 < 32; i0 += G) {
+    for (int i0 = s0; i0 < 16; i0 += G) {
       double x[G], q[G];
 #pragma unroll
       for (int j = 0; j < G; j++)
-        if (i0 + j < 32) x[j] = -readlane_d(X[i0 + j], K) * xk;
+        if (i0 + j < 16) x[j] = -e.M[i0 + j] * xkp;
 #pragma unroll
       for (int j = 0; j < G; j++)
-        if (i0 + j < 32) x[j] = fma(bk, X[i0 + j], x[j]);
+        if (i0 + j < 16) x[j] = fma(bkp, e.X[i0 + j], x[j]);
 #pragma unroll
       for (int j = 0; j < G; j++)
-        if (i0 + j < 32) q[j] = fma(x[j], pinv, RND);
+        if (i0 + j < 16) q[j] = fma(x[j], pinv, RND);
 #pragma unroll
       for (int j = 0; j < G; j++)
-        if (i0 + j < 32) q[j] = q[j] - RND;
+        if (i0 + j < 16) q[j] = q[j] - RND;
 #pragma unroll
       for (int j = 0; j < G; j++)
-        if (i0 + j < 32) X[i0 + j] = fma(-q[j], p, x[j]);
+        if (i0 + j < 16) {
+          e.X[i0 + j] = fma(-q[j], p, x[j]);
+          if constexpr (K1 < 32) {
+            e.M[i0 + j] = bcast_half<K1>(e.X[i0 + j]);
+            if (i0 + j == sK1) {
+              e.bnext = readlane_d(e.X[i0 + j], hK1 * 32 + K1);
+              if constexpr (K1 < 16) e.xkn = bpermute_d(xaddr, e.X[i0 + j]);
+            }
+          }
+        }
+      __builtin_amdgcn_sched_barrier(0);
     }
-    diag_elim_step<K + 1, G>(X, S, sig, bl, zero, lane, p, pinv);
+    if constexpr (hK == 1) e.X[sK] = (atK && tr) ? Sk : e.X[sK];
+    diag_elim_step<K + 1, G>(e, L, h, xaddr, tr, p, pinv);
   }
+}
+
+// a^e mod p by the right-to-left ladder over the nb low bits of e (nb uniform).
+__device__ __forceinline__ double pow_mod_nbits(double a, uint32_t e, int nb, double p,
+                                                double pinv) {
+  double r = 1.0, b = a;
+  for (int i = 0; i < nb; i++) {
+    const double rb = mul_mod_loose(r, b, p, pinv);
+    r = ((e >> i) & 1u) ? rb : r;
+    b = mul_mod_loose(b, b, p, pinv);
+  }
+  return mod_c(r, p, pinv);
+}
+
+// x from lane s of each 32-lane half, s = 0..15.
+__device__ __forceinline__ void bcast_half16(double x, double (&out)[16]) {
+  out[0] = bcast_half<0>(x);   out[1] = bcast_half<1>(x);   out[2] = bcast_half<2>(x);
+  out[3] = bcast_half<3>(x);   out[4] = bcast_half<4>(x);   out[5] = bcast_half<5>(x);
+  out[6] = bcast_half<6>(x);   out[7] = bcast_half<7>(x);   out[8] = bcast_half<8>(x);
+  out[9] = bcast_half<9>(x);   out[10] = bcast_half<10>(x); out[11] = bcast_half<11>(x);
+  out[12] = bcast_half<12>(x); out[13] = bcast_half<13>(x); out[14] = bcast_half<14>(x);
+  out[15] = bcast_half<15>(x);
 }
 
 __device__ __forceinline__ void diag_block_body(int32_t* __restrict__ Wb, int64_t ldw, int pb,
@@ -542,46 +643,65 @@ __device__ __forceinline__ void diag_block_body(int32_t* __restrict__ Wb, int64_
   const int c = t & 63, w = t >> 6;
   if (w >= 2) return;
   const bool tr = w == 1;                            // the transposed elimination
-  const int cl = c & 31;
+  const int L = c & 31, h = c >> 5;
+  const int ld = (int)ldw;                           // (the block lies in the first 2^31 entries)
   const uint32_t e_inv = (uint32_t)__builtin_amdgcn_readfirstlane((int)((uint32_t)p - 2u));
-  double X[32];
+  const int nb = 32 - __builtin_clz(e_inv | 1u);
+  DiagElim e;
   {
     // every load is issued before any is used (clamped indices stay inside
     // the pb x pb block; the padding is selected afterwards)
-    int32_t v[32];
-    const int cc = min(cl, pb - 1);
+    int32_t v[16];
+    const int cc = min(L, pb - 1);
 #pragma unroll
-    for (int i = 0; i < 32; i++) {
-      const int ii = min(i, pb - 1);
-      v[i] = Wb[tr ? (int64_t)cc * ldw + ii : (int64_t)ii * ldw + cc];
+    for (int s = 0; s < 16; s++) {
+      const int ii = min(s + 16 * h, pb - 1);
+      v[s] = Wb[tr ? cc * ld + ii : ii * ld + cc];
     }
 #pragma unroll
-    for (int i = 0; i < 32; i++) {
-      const bool in = c < 32 && i < pb && c < pb;
-      const bool one = cl == i && (c >= 32 || i >= pb);
-      X[i] = in ? (double)v[i] : (one ? 1.0 : 0.0);
+    for (int s = 0; s < 16; s++) {
+      const int r = s + 16 * h;
+      e.X[s] = (r < pb && L < pb) ? (double)v[s] : (L == r ? 1.0 : 0.0);
     }
   }
-  double S = 1.0, sig = 1.0, bl = 1.0;
-  bool zero = false;
-  diag_elim_step<0, 8>(X, S, sig, bl, zero, cl, p, pinv);
-  // lane c: 1 / sigma_c (wave 0) or 1 / b_c (wave 1)
-  const double y = pow_mod_fixed(tr ? bl : sig, e_inv, p, pinv);
+  const int xaddr = (c ^ 32) << 2;
 #pragma unroll
-  for (int i = 0; i < 32; i++) X[i] = mul_mod(X[i], readlane_d(y, i), p, pinv);
-  // wave 0: row i of U (lanes below 32, on and above the diagonal) and of
-  // L^{-1} (lanes 32 and up); wave 1: column i of U^{-1} (lanes 32 and up)
-  const int cc = c - 32;
-  int32_t* const base = tr ? Uz + cc * 32 : (c < 32 ? Wb + c : Lz + cc);
-  const int64_t step = tr ? 1 : (c < 32 ? ldw : 32);
+  for (int s = 0; s < 16; s++) e.M[s] = bcast_half<0>(e.X[s]);
+  e.xkn = bpermute_d(xaddr, e.X[0]);
+  e.bnext = readlane_d(e.X[0], 0);
+  e.S = 1.0;
+  e.sig = 1.0;
+  e.bl = 1.0;
+  e.zero = false;
+  diag_elim_step<0, 8>(e, L, h, xaddr, tr, p, pinv);
+  // lane c of half h: 1 / sigma_j (wave 0) or 1 / b_j (wave 1), j = (c + 16 h) mod 32
+  const double y = pow_mod_nbits(tr ? e.bl : e.sig, e_inv, nb, p, pinv);
+  double ys[16];
+  bcast_half16(y, ys);
+  double R[16];
 #pragma unroll
-  for (int i = 0; i < 32; i++) {
-    const bool keep = c >= 32 ? (i < pb && cc < pb) : true;
-    const bool st = c >= 32 || (!tr && c < pb && i <= c);
-    if (st) base[(int64_t)i * step] = keep ? (int32_t)X[i] : 0;
+  for (int s = 0; s < 16; s++) R[s] = mul_mod(h ? e.X[s] : e.F[s], ys[s], p, pinv);
+  const bool lin = L < pb;
+  if (!tr) {
+    // row r: U[r][L] for L >= r (into the block), L^{-1}[r][L] for L <= r
+    // (1 on the diagonal)
+#pragma unroll
+    for (int s = 0; s < 16; s++) {
+      const int r = s + 16 * h;
+      const int32_t v = (int32_t)R[s];
+      if (L >= r && lin) Wb[r * ld + L] = v;
+      Lz[r * 32 + L] = (L <= r && r < pb && lin) ? (L == r ? 1 : v) : 0;
+    }
+  } else {
+    // U^{-1}[L][r] for r >= L
+#pragma unroll
+    for (int s = 0; s < 16; s++) {
+      const int r = s + 16 * h;
+      Uz[L * 32 + r] = (r >= L && r < pb && lin) ? (int32_t)R[s] : 0;
+    }
   }
   if (t < pb) piv_z[j0 + t] = j0 + t;
-  if (zero && t == 0) *flag = 1;
+  if (e.zero && t == 0) *flag = 1;
 }
 
 }  // namespace detk
