@@ -222,6 +222,26 @@ def test_device_pointer_input(ctx):
     assert ctx.det_mod_primes(big[:, :150], ps).tolist() == ctx.det_mod_primes(A, ps).tolist()
 
 
+@pytest.mark.parametrize("n", [1, 63, 64, 65, 130, 300])
+def test_device_bounds_equal_host_bounds(ctx, n):
+    """The Hadamard bounds of a device matrix come from the norm kernels
+    (partial sums over 64 x 64 blocks of the whole matrix, added in a fixed
+    order), those of a host matrix from the host: with entries below 2^20
+    every sum is exact, so the bound, the lifting length and the determinant
+    agree, also for a strided view (leading dimension above n)."""
+    torch = pytest.importorskip("torch")
+    A = synth.dense_uniform(n, -(1 << 20), 1 << 20, 31 + n)
+    d_host, rep_host = ctx.det_introspective(A, report=True)
+    big = torch.zeros((n, n + 37), dtype=torch.int64, device="cuda")
+    big[:, 3:3 + n] = torch.from_numpy(A).cuda()
+    d_dev, rep_dev = ctx.det_introspective(big[:, 3:3 + n], report=True)
+    assert d_dev == d_host
+    assert rep_dev["hadamard_bits"] == rep_host["hadamard_bits"], (rep_dev, rep_host)
+    assert rep_dev["lifting_steps"] == rep_host["lifting_steps"], (rep_dev, rep_host)
+    if n <= 64:
+        assert d_host == oracle.det_bareiss(A)
+
+
 # ---------------------------------------------------------------- dixon_lift
 @pytest.mark.parametrize("n,k", [(1, 5), (5, 8), (33, 6), (64, 45), (150, 7), (300, 3)])
 def test_dixon_lift_matches_oracle(ctx, n, k):
