@@ -625,6 +625,24 @@ def test_det_introspective_lift_primes(ctx, n, lo, hi, lp):
     assert rep["sn_bits"] >= abs(d).bit_length() - 64, rep
 
 
+@pytest.mark.parametrize("n,amax", [(48, 1 << 22), (20, 0x7F7F7F + 1000), (40, 1 << 30)])
+def test_det_introspective_entry_size_picks_the_lifting_form(ctx, n, amax):
+    """The size of the entries decides the lifting: up to 0x7F7F7F the
+    Hensel planes come from int8 limbs with 24-bit primes; just above it from
+    FP64 products with 25-bit primes (the three-digit FP64 lifting still exact,
+    n ||A|| p < 2^53); at 2^30 the 64-bit integer form with 26-bit primes
+    (n ||A|| p < 2^62).  Each gives the exact determinant, with the divisor
+    from the lifting carrying nearly all of it."""
+    rng = np.random.default_rng(n)
+    A = rng.integers(-amax, amax + 1, size=(n, n), dtype=np.int64)
+    A[0, 0] = amax
+    d = oracle.det_bareiss_c(A)
+    got, rep = ctx.det_introspective(A, report=True)
+    _say("n", n, "amax", amax, "report", rep)
+    assert got == d
+    assert rep["solvings"] == 1 and rep["sn_bits"] >= abs(d).bit_length() - 64, rep
+
+
 def test_det_introspective_extended_bonus_lift_primes(ctx):
     """Section 3.2 with the solvings lifted modulo three primes side by side:
     the bonus still finds the product of the two largest invariant factors."""
