@@ -593,12 +593,11 @@ det_status inverse_mod_primes(det_ctx* c, const int64_t* dA, int64_t dlda, int n
     const bool block_pivots = attempt == 0 && c->block_pivots;
     if (attempt == 1 && !c->block_pivots) break;
     HIPCHK(hipMemsetAsync(w.flags.p, 0, (size_t)np * sizeof(int32_t), w.st));
-    HIPCHK(detk::launch_residues(dA, dlda, n, 2 * n, (int32_t*)w.W.p, J.ldw, J.slab,
+    // [A | I], and with the fast inverse V = columns [2n, 3n) (read by
+    // inverse_from_lu) cleared by the same launch: the identity's columns
+    // past 2n are zero
+    HIPCHK(detk::launch_residues(dA, dlda, n, (fast ? 3 : 2) * n, (int32_t*)w.W.p, J.ldw, J.slab,
                                  (const Modulus*)w.mods.p, np, w.st));
-    if (fast)             // V = columns [2n, 3n), read by inverse_from_lu, cleared
-      for (int z = 0; z < np; z++)
-        HIPCHK(hipMemset2DAsync((int32_t*)w.W.p + z * J.slab + 2 * (int64_t)n,
-                                J.ldw * sizeof(int32_t), 0, (size_t)n * sizeof(int32_t), n, w.st));
     TRY(lu_factor(c, w, J, true, &panels, block_pivots));
     if (det_out) {
       // det(A) mod p_z from the same factorisation (U's diagonal and the

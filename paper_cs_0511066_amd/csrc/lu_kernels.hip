@@ -30,8 +30,9 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 typedef int v4i __attribute__((ext_vector_type(4)));
 
 // ------------------------------------------------------------------ K1: residues
-// W[z][i][j] = A[i][j] mod p_z (centred) for j < n; when `augment` is set the
-// columns n..2n-1 hold the identity (the right half of [A | I]).
+// W[z][i][j] = A[i][j] mod p_z (centred) for j < n; columns n <= j < ncols
+// hold the identity's columns j - n (the right half of [A | I] for ncols =
+// 2n; zero from column 2n on).
 __global__ void k_residues(const int64_t* __restrict__ A, int64_t lda, int n, int ncols,
                            int32_t* __restrict__ W, int64_t ldw, int64_t slab,
                            const Modulus* __restrict__ mods, int nitems) {
