@@ -413,7 +413,9 @@ __global__ __launch_bounds__(512) void k_lu_update(int32_t* __restrict__ W, int6
   for (int u = 0; u < 1024 / T; u++) {
     const int e = u * T + t, r = e >> 5, c = e & 31;
     const bool in = r < pb && c < pb;
-    sT[r][c] = in ? (double)vt[u] : 0.0;
+    // L11^{-1} is unit lower triangular: only its entries below the
+    // diagonal are read (the diagonal block's factorisation stores no others)
+    sT[r][c] = in ? (c < r ? (double)vt[u] : (c == r ? 1.0 : 0.0)) : 0.0;
     sU[r][c] = in ? (double)vu[u] : 0.0;
   }
 #pragma unroll

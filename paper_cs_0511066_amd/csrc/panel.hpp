@@ -508,8 +508,10 @@ __device__ __forceinline__ void panel_body(int32_t* __restrict__ Wr, int64_t ldw
 // h for index (c + 16 h) mod 32, so that the scale of slot s is read from lane
 // s of either half); sigma_i is the running product of the pivots, kept beside
 // the elimination.
-// Outputs: U11 into the block (on and above the diagonal), L11^{-1} and
-// U11^{-1} dense 32 x 32 row-major at Lz, Uz (zero outside pb x pb),
+// Outputs: U11 into the block (on and above the diagonal), L11^{-1} at Lz
+// (32 x 32 row-major, only its entries below the diagonal: it is unit lower
+// triangular, and its reader takes the rest as given), U11^{-1} dense 32 x 32
+// row-major at Uz (zero outside pb x pb),
 // piv_z[j0 + i] = j0 + i, *flag = 1 when a pivot is 0 mod p (the caller then
 // runs the full pivot search).  Values stay below (p + 9) / 2 in magnitude
 // through the loose reductions, so every product is below 2^52.  Waves 2 and
@@ -683,14 +685,15 @@ __device__ __forceinline__ void diag_block_body(int32_t* __restrict__ Wb, int64_
   for (int s = 0; s < 16; s++) R[s] = mul_mod(h ? e.X[s] : e.F[s], ys[s], p, pinv);
   const bool lin = L < pb;
   if (!tr) {
-    // row r: U[r][L] for L >= r (into the block), L^{-1}[r][L] for L <= r
-    // (1 on the diagonal)
+    // row r: U[r][L] for L >= r (into the block), L^{-1}[r][L] for L < r,
+    // one store a row (each lane writes one of the two)
 #pragma unroll
     for (int s = 0; s < 16; s++) {
       const int r = s + 16 * h;
       const int32_t v = (int32_t)R[s];
-      if (L >= r && lin) Wb[r * ld + L] = v;
-      Lz[r * 32 + L] = (L <= r && r < pb && lin) ? (L == r ? 1 : v) : 0;
+      const bool up = L >= r;
+      int32_t* const dst = up ? Wb + r * ld + L : Lz + r * 32 + L;
+      if (!up || lin) *dst = v;
     }
   } else {
     // U^{-1}[L][r] for r >= L
