@@ -1365,9 +1365,10 @@ det_status det_introspective(det_ctx* c, const int64_t* A, int64_t n, int64_t ld
     bool batch1_taken = false;
     dethost::PrimeSampler dsamp(dethost::splitmix64(rng), dixon_bits);
     // Pass 0 takes the inverse with the block pivot search and does not wait
-    // for its flag: the flag is read with the first solving's results, and if
-    // a block column had no non-zero entry the solving is discarded and pass
-    // 1 starts over with the full search (and a fresh prime).
+    // for its flag: the flag is read with the first CRA batch, before the
+    // first lifting is launched, and if a block column had no non-zero entry
+    // that lifting is not launched and pass 1 starts over with the full
+    // search (and fresh primes).
     // Liftings side by side (Section 6: several p-adic liftings in parallel,
     // each with fewer steps, combined by Chinese remaindering): np primes,
     // each lifted to k digits with prod p_z^k above the bound, when the
