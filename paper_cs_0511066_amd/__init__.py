@@ -424,10 +424,12 @@ class Server:
 
     def __init__(self, ctx: Context, hbm_budget_bytes: int = 0, seed: int | None = None,
                  certify: bool = False, log2_inv_eps: float | None = None,
-                 prime_bits: int | None = None):
+                 prime_bits: int | None = None, lift_primes: int | None = None):
         o = det_opts()
         _lib.det_opts_default(ctypes.byref(o))
         o.certify = int(bool(certify))
+        if lift_primes is not None:
+            o.lift_primes = lift_primes
         if seed is not None:
             o.seed = seed
         if log2_inv_eps is not None:
